@@ -1,0 +1,166 @@
+"""Seeded synthetic input matrices (shared by the tests, the benchmark and the
+oracle runs; holds none of the decomposition's arithmetic).
+
+The paper's own inputs (partial-wave three-nucleon matrix elements, section
+"Low-rank interactions", Eq. 3) are not available, so matrices with a known
+singular spectrum stand in for them:
+
+    general   A = U diag(sigma) V^T (+ E)
+    symmetric A = U diag(sigma) U^T (+ E), mirrored so A == A^T bitwise
+
+U, V are Haar-distributed orthonormal columns: QR of a Gaussian matrix with
+the signs fixed by diag(sign(R)) (Mezzadri 2007). Only the r_eff columns with
+sigma_i >= 1e-17 sigma_0 are built, which is exact in FP64.
+
+Random draws use numpy's PCG64 with SeedSequence([tag, channel]); the large
+product U diag(sigma) V^T may run on a torch device for speed (the spectrum
+is identical; only rounding of the product differs between devices).
+
+Workloads (shapes and spectra of the benchmark configurations; sigma index
+i = 0 .. min(m, n) - 1, so sigma_0 = 1):
+  c1  512 x 512 general, sigma_i = 10^(-i/16); k = 40, p = 10, q = 2
+  c2  16384^2 symmetric, sigma_i = exp(-i/40) + E, E = 1e-8 (G + G^T)/sqrt(2);
+      k = 256, p = 16, q = 2
+  c3  131072 x 8192 general, sigma_i = 10^(-i/64) + floor E = 1e-9 G/(sqrt(m)+sqrt(n));
+      k = 512, p = 16, q = 3
+  c4  96 symmetric PSD channels, n_c ~ logU[500, 12000], sigma_i = exp(-i/d_c),
+      d_c ~ U[10, 80]; rank by relative threshold 1e-6
+  c5  2000 channels as c4 with n_c ~ logU[200, 6000]
+"""
+
+from dataclasses import dataclass
+import math
+
+import numpy as np
+
+SIGMA_FLOOR = 1e-17
+
+
+def _rng(tag, channel=0):
+    return np.random.Generator(np.random.PCG64(np.random.SeedSequence([int(tag), int(channel)])))
+
+
+def spectrum_pow10(nvals, decades_per_index):
+    """sigma_i = 10^(-i * decades_per_index)."""
+    i = np.arange(nvals, dtype=np.float64)
+    return 10.0 ** (-i * decades_per_index)
+
+
+def spectrum_exp(nvals, d):
+    """sigma_i = exp(-i / d)."""
+    i = np.arange(nvals, dtype=np.float64)
+    return np.exp(-i / d)
+
+
+def effective(sigma):
+    """Drop the trailing values below 1e-17 * sigma_0 (they are zero in FP64)."""
+    r = int(np.count_nonzero(sigma >= SIGMA_FLOOR * sigma[0]))
+    return sigma[:r]
+
+
+def haar_columns(n, r, rng):
+    """n x r matrix with Haar-distributed orthonormal columns."""
+    G = rng.standard_normal((n, r))
+    Q, R = np.linalg.qr(G, mode="reduced")
+    d = np.sign(np.diag(R))
+    d[d == 0] = 1.0
+    return Q * d[None, :]
+
+
+def _product(U, s, V, device):
+    """U diag(s) V^T in FP64, optionally on a torch device."""
+    if device is None or device == "cpu":
+        return (U * s[None, :]) @ V.T
+    import torch
+    Ut = torch.from_numpy(U * s[None, :]).to(device)
+    Vt = torch.from_numpy(np.ascontiguousarray(V.T)).to(device)
+    out = (Ut @ Vt).cpu().numpy()
+    return out
+
+
+def general(m, n, sigma, tag, channel=0, noise=0.0, device=None):
+    """A = U diag(sigma) V^T + noise * G / (sqrt(m) + sqrt(n)) (so ||E||_2 ~ noise)."""
+    sigma = effective(np.asarray(sigma, np.float64)[: min(m, n)])
+    r = len(sigma)
+    rng = _rng(tag, channel)
+    U = haar_columns(m, r, rng)
+    V = haar_columns(n, r, rng)
+    A = _product(U, sigma, V, device)
+    if noise:
+        A += (noise / (math.sqrt(m) + math.sqrt(n))) * rng.standard_normal((m, n))
+    return np.ascontiguousarray(A)
+
+
+def symmetric(n, sigma, tag, channel=0, noise=0.0, device=None):
+    """A = U diag(sigma) U^T + noise (G + G^T)/sqrt(2), mirrored from the upper triangle."""
+    sigma = effective(np.asarray(sigma, np.float64)[:n])
+    r = len(sigma)
+    rng = _rng(tag, channel)
+    U = haar_columns(n, r, rng)
+    A = _product(U, sigma, U, device)
+    if noise:
+        G = rng.standard_normal((n, n))
+        G += G.T
+        G *= noise / math.sqrt(2.0)
+        A += G
+        del G
+    iu = np.triu_indices(n, 1)
+    A[(iu[1], iu[0])] = A[iu]
+    return np.ascontiguousarray(A)
+
+
+def rank_r(m, n, r, tag, channel=0, scale=1.0):
+    """Exactly rank-r matrix with sigma_0..sigma_{r-1} = scale * 2^-i (for the low-rank pins)."""
+    rng = _rng(tag, channel)
+    s = scale * 2.0 ** -np.arange(r)
+    U = haar_columns(m, r, rng)
+    V = haar_columns(n, r, rng)
+    return np.ascontiguousarray((U * s[None, :]) @ V.T), s
+
+
+@dataclass
+class Workload:
+    name: str
+    m: int
+    n: int
+    symmetric: bool
+    k: int
+    p: int
+    q: int
+    seed: int  # Omega key
+
+
+def c1():
+    """512 x 512 general, sigma_i = 10^(-i/16); k=40, p=10, q=2."""
+    m = n = 512
+    sigma = spectrum_pow10(n, 1.0 / 16.0)
+    A = general(m, n, sigma, tag=1)
+    return A, sigma, Workload("c1_512sq_general", m, n, False, 40, 10, 2, 2001)
+
+
+def c2(n=16384, device=None):
+    """n x n symmetric, sigma_i = exp(-i/40) + 1e-8 symmetric Gaussian noise; k=256, p=16, q=2."""
+    sigma = spectrum_exp(n, 40.0)
+    A = symmetric(n, sigma, tag=2, noise=1e-8, device=device)
+    return A, sigma, Workload(f"c2_{n}sq_symmetric", n, n, True, 256, 16, 2, 2002)
+
+
+def c3(m=131072, n=8192, device=None):
+    """m x n general, sigma_i = 10^(-i/64), noise floor ||E||_2 ~ 1e-9; k=512, p=16, q=3."""
+    sigma = spectrum_pow10(min(m, n), 1.0 / 64.0)
+    A = general(m, n, sigma, tag=3, noise=1e-9, device=device)
+    return A, sigma, Workload(f"c3_{m}x{n}_general", m, n, False, 512, 16, 3, 2003)
+
+
+def channel_dims(count, lo, hi, tag):
+    """Channel sizes n_c ~ logU[lo, hi] and decay lengths d_c ~ U[10, 80]."""
+    rng = _rng(tag, 10**6)
+    dims = np.exp(rng.uniform(math.log(lo), math.log(hi), size=count)).astype(np.int64)
+    d = rng.uniform(10.0, 80.0, size=count)
+    return dims, d
+
+
+def channel(c, n, d, tag):
+    """Symmetric PSD channel matrix with sigma_i = exp(-i/d)."""
+    sigma = spectrum_exp(n, d)
+    return symmetric(n, sigma, tag=tag, channel=c), sigma
