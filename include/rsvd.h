@@ -1,0 +1,198 @@
+/*
+ * rsvd.h - C ABI of the MI355X randomized truncated SVD library (librsvd.so).
+ *
+ * The library computes the randomized SVD described in arXiv:2307.15572,
+ * section "Randomized matrix decompositions" (Fig. 1, Eq. 1, Eq. 2): for a
+ * dense real matrix V (here called A, m x n) it draws a Gaussian random
+ * projection P (n x l), forms Z = A P, an orthonormal basis Q of Z (thin
+ * QR, step 1), projects Y = Q^T A, takes the thin SVD Y = L_Y Sigma R^T
+ * (step 2) and lifts L = Q L_Y (step 3). l = R_SVD + p with oversampling p.
+ * The singular values come back sorted decreasingly (Eq. 1) and the result
+ * is truncated to a rank R_SVD chosen by one of the rank rules below.
+ * Optional q power iterations (Halko et al.'s randomized subspace iteration,
+ * a QR after every product) sit between step 1 and step 2; q = 0 is the
+ * paper's method.
+ *
+ * Conventions shared by every entry point:
+ *  - All matrices are row-major FP64 (C / torch-contiguous order). A has
+ *    leading dimension lda >= n. Device pointers unless stated otherwise.
+ *  - The caller owns every buffer (inputs, outputs, result record and
+ *    workspace). The library never allocates device memory in rsvd_run and
+ *    never writes A.
+ *  - All work is enqueued on the caller's stream (a hipStream_t passed as
+ *    void*, NULL = the null stream). Nothing synchronizes the host.
+ *  - Errors are reported by return code only; no exception crosses the ABI.
+ *    Data-dependent outcomes (non-finite input, capped rank, QR fallback,
+ *    Jacobi not converged) are flags in the device-side result record.
+ */
+#ifndef RSVD_H
+#define RSVD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum rsvd_status {
+  RSVD_OK = 0,
+  RSVD_EINVAL = 1,        /* invalid argument (sizes, modes, pointers)            */
+  RSVD_ENOMEM = 2,        /* workspace smaller than rsvd_plan reported            */
+  RSVD_EHIP = 3,          /* a HIP runtime call or kernel launch failed           */
+  RSVD_EUNSUPPORTED = 4   /* valid request this build does not implement          */
+} rsvd_status;
+
+/* Rank rules (section "Randomized matrix decompositions": R_SVD is the number
+ * of singular values kept, R% = 100 R_SVD / N). */
+enum {
+  RSVD_RANK_FIXED = 0,         /* R_SVD = k                                        */
+  RSVD_RANK_PERCENT = 1,       /* R_SVD = ceil(R% min(m,n) / 100), rank_param = R% */
+  RSVD_RANK_REL_THRESHOLD = 2, /* R_SVD = #{j : s_j >= tau s_1}, capped at l - p   */
+  RSVD_RANK_FROB_TAIL = 3      /* smallest R_SVD with discarded energy <= tau ||A||_F */
+};
+
+/* Arithmetic of the products with A (the 2q+2 streaming passes). */
+enum {
+  RSVD_PREC_FP64 = 0,          /* every product in FP64 (MFMA f64)                  */
+  RSVD_PREC_MIXED_FP32 = 1,    /* early passes FP32 MFMA, trailing passes FP64       */
+  RSVD_PREC_MIXED_BF16 = 2,    /* early passes BF16 MFMA (FP32 accumulate)           */
+  RSVD_PREC_MIXED_BF16_SPLIT = 3 /* early passes hi/lo BF16 split, 3 products       */
+};
+
+/* Flags in rsvd_result.flags */
+enum {
+  RSVD_FLAG_FULL_SVD = 1u << 0,        /* l = min(m, n): the result is an exact SVD  */
+  RSVD_FLAG_RANK_CAPPED = 1u << 1,     /* rank rule wanted more than l - p or k_cap  */
+  RSVD_FLAG_QR_FALLBACK = 1u << 2,     /* a Cholesky QR broke down; shifted pass used */
+  RSVD_FLAG_JACOBI_MAXSWEEP = 1u << 3, /* small SVD stopped at max_sweeps            */
+  RSVD_FLAG_NONFINITE_INPUT = 1u << 4, /* A holds NaN or Inf                         */
+  RSVD_FLAG_ZERO_SIGMA = 1u << 5       /* a singular value is exactly zero           */
+};
+
+typedef struct rsvd_problem {
+  int64_t m, n;          /* A is m x n                                             */
+  int64_t k;             /* target rank; l = min(k + oversample, m, n)             */
+  int64_t k_cap;         /* columns of U, V and entries of S the caller provides;
+                            0 = l                                                  */
+  int32_t symmetric;     /* caller asserts A == A^T; A is then used for A^T        */
+  int32_t rank_mode;     /* RSVD_RANK_*                                            */
+  double rank_param;     /* R% for PERCENT, tau for the threshold rules            */
+  int32_t oversample;    /* p >= 0 (the paper uses p = 5)                          */
+  int32_t power_iters;   /* q >= 0 (0 = the paper's method)                        */
+  int32_t precision;     /* RSVD_PREC_*                                            */
+  int32_t trailing_hp;   /* mixed modes: number of trailing products kept in FP64  */
+  uint64_t seed;         /* key word 0 of the Philox stream that draws P           */
+  uint64_t channel;      /* key word 1 (symmetry channel index)                    */
+  int32_t want_u;        /* write U (m x rank)                                     */
+  int32_t want_v;        /* write V (n x rank)                                     */
+  int32_t want_residual; /* stream A once more for ||A - U S V^T||_F / ||A||_F     */
+  int32_t max_sweeps;    /* Jacobi sweep limit for the small SVD; 0 = 30           */
+} rsvd_problem;
+
+/* Result record, written to DEVICE memory by rsvd_run (so runs stay
+ * capturable in a graph); copy it back after synchronizing the stream. */
+typedef struct rsvd_result {
+  int64_t rank;          /* R_SVD: number of valid entries of S / columns of U, V  */
+  int64_t l_used;        /* sketch width l                                         */
+  double residual;       /* ||A - U_k S_k V_k^T||_F / ||A||_F (NaN if not asked)   */
+  double rel_percent;    /* R% = 100 rank / min(m, n)                              */
+  double c_eq2;          /* Eq. 2 as printed: m n / ((m + n) rank + rank)          */
+  double c_sym;          /* one stored factor: m n / (max(m, n) rank + rank)       */
+  double fro2;           /* ||A||_F^2                                              */
+  int32_t sweeps;        /* Jacobi sweeps used by the small SVD                    */
+  uint32_t flags;        /* RSVD_FLAG_*                                            */
+} rsvd_result;
+
+typedef struct rsvd_plan_s* rsvd_plan_t;
+
+/*
+ * rsvd_plan - validate a problem and size its workspace.
+ *   prob            host pointer, read only.
+ *   out             receives an immutable plan (host object); free it with
+ *                   rsvd_destroy. Concurrent runs of one plan need distinct
+ *                   workspaces.
+ *   workspace_bytes receives the device workspace size rsvd_run needs.
+ * Returns RSVD_EINVAL for m, n < 1, k < 1 (fixed rule), p < 0, q < 0,
+ * R% outside (0, 100], tau outside (0, 1), an unknown mode, or k_cap < the
+ * fixed rank; RSVD_EUNSUPPORTED for a precision mode this build lacks.
+ */
+rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* workspace_bytes);
+
+/* Sketch width l of a plan (host query). */
+int64_t rsvd_plan_l(rsvd_plan_t plan);
+
+/*
+ * rsvd_run - one randomized SVD of A (Fig. 1 steps 1-3 plus truncation).
+ *   A, lda        m x n input (device, read only), lda >= n.
+ *   omega, ldo    optional caller-provided projection P (n x l, device, ldo >= l);
+ *                 NULL draws P from the Philox4x64-10 / Box-Muller stream keyed
+ *                 by (seed, channel): entry (i, j) uses counter (i, j/4, 0, 0).
+ *   S             k_cap singular values (device), decreasing; first rank valid.
+ *   U, ldu        m x k_cap left vectors (device, ldu >= k_cap) or NULL if !want_u.
+ *   V, ldv        n x k_cap right vectors (device, ldv >= k_cap) or NULL if !want_v.
+ *   res_dev       device rsvd_result record.
+ *   work          device workspace of at least the planned size (256-B aligned).
+ *   stream        hipStream_t.
+ * Signs: each pair (U_j, V_j) is flipped so the largest-magnitude entry of
+ * U_j is positive (lowest index on ties).
+ */
+rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda,
+                     const double* omega, int64_t ldo,
+                     double* S, double* U, int64_t ldu, double* V, int64_t ldv,
+                     rsvd_result* res_dev, void* work, size_t work_bytes, void* stream);
+
+/* Free a plan (NULL is ignored). */
+void rsvd_destroy(rsvd_plan_t plan);
+
+/* Static description of a status code. */
+const char* rsvd_strerror(rsvd_status s);
+
+/*
+ * Component entry points (each one step of the path, for testing and reuse).
+ */
+
+/* rsvd_gaussian_omega - the projection P: out (n x l, ldo >= l, device) gets
+ * columns col0 .. col0+l-1 of the Philox/Box-Muller stream keyed by
+ * (seed, channel) (section "Randomized matrix decompositions": a random
+ * projection matrix P drawn once per decomposition). */
+rsvd_status rsvd_gaussian_omega(int64_t n, int64_t l, int64_t col0, uint64_t seed,
+                                uint64_t channel, double* out, int64_t ldo, void* stream);
+
+/* rsvd_dgemm - C = alpha op(A) B + beta C in FP64 on the matrix cores; the
+ * kernel behind the sketch Z = A P, the power products and the projection
+ * Q^T A. op(A) = A (m x k, lda) when trans_a == 0, A^T with A stored k x m
+ * (lda) when trans_a != 0. B is k x n (ldb), C is m x n (ldc); all device.
+ * work (device, may be NULL when work_bytes is 0) holds split-K partial
+ * sums; rsvd_dgemm_work_bytes gives the size it wants. */
+size_t rsvd_dgemm_work_bytes(int64_t m, int64_t n, int64_t k, int32_t trans_a);
+rsvd_status rsvd_dgemm(int32_t trans_a, int64_t m, int64_t n, int64_t k, double alpha,
+                       const double* A, int64_t lda, const double* B, int64_t ldb,
+                       double beta, double* C, int64_t ldc, void* work, size_t work_bytes,
+                       void* stream);
+
+/* rsvd_orth - thin QR of a tall panel Y (m x l, ldy, device, m >= l), step 1's
+ * "QR decomposition Z = Q X": Y is overwritten by Q (orthonormal columns,
+ * diag(X) > 0); X (l x l upper triangular, row-major, device) receives the
+ * R factor when non-NULL. Shifted Cholesky QR (Gram, Cholesky, triangular
+ * solve, repeated). flags (device uint32) gets RSVD_FLAG_QR_FALLBACK when
+ * the unshifted factorization broke down. */
+size_t rsvd_orth_work_bytes(int64_t m, int64_t l);
+rsvd_status rsvd_orth(int64_t m, int64_t l, double* Y, int64_t ldy, double* X,
+                      uint32_t* flags, void* work, size_t work_bytes, void* stream);
+
+/* rsvd_small_svd - SVD of a square upper-triangular R (l x l, row-major,
+ * device), step 2's thin SVD applied to the triangular factor of Y^T:
+ * R^T = Us diag(s) W^T. s (l, device) decreasing; Us and W (l x l row-major,
+ * device) hold the singular vectors as columns. One-sided Jacobi on the rows
+ * of R. sweeps (device int32) receives the sweep count; flags as above. */
+size_t rsvd_small_svd_work_bytes(int64_t l);
+rsvd_status rsvd_small_svd(int64_t l, const double* R, double* s, double* Us, double* W,
+                           int32_t max_sweeps, int32_t* sweeps, uint32_t* flags,
+                           void* work, size_t work_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RSVD_H */

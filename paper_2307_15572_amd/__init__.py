@@ -1,0 +1,316 @@
+"""MI355X randomized truncated SVD (arXiv:2307.15572, section "Randomized
+matrix decompositions") behind the C ABI of include/rsvd.h.
+
+This module only marshals arguments: torch supplies device memory and the
+current stream, and every step of the decomposition runs in the HIP kernels
+of librsvd.so. There is no CPU fallback; importing works without a GPU, but
+any call fails loudly when the library or a device is missing.
+"""
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+PKG_DIR = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG_DIR, "librsvd.so")
+
+RSVD_OK, RSVD_EINVAL, RSVD_ENOMEM, RSVD_EHIP, RSVD_EUNSUPPORTED = range(5)
+RANK_MODES = {"fixed": 0, "percent": 1, "rel_threshold": 2, "frob_tail": 3}
+PRECISIONS = {"fp64": 0, "mixed_fp32": 1, "mixed_bf16": 2, "mixed_bf16_split": 3}
+FLAG_FULL_SVD = 1 << 0
+FLAG_RANK_CAPPED = 1 << 1
+FLAG_QR_FALLBACK = 1 << 2
+FLAG_JACOBI_MAXSWEEP = 1 << 3
+FLAG_NONFINITE_INPUT = 1 << 4
+FLAG_ZERO_SIGMA = 1 << 5
+
+EXPORTED = (
+    "rsvd_plan", "rsvd_plan_l", "rsvd_run", "rsvd_destroy", "rsvd_strerror",
+    "rsvd_gaussian_omega", "rsvd_dgemm_work_bytes", "rsvd_dgemm",
+    "rsvd_orth_work_bytes", "rsvd_orth", "rsvd_small_svd_work_bytes", "rsvd_small_svd",
+)
+
+
+class RsvdError(RuntimeError):
+    pass
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [
+        ("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
+        ("k_cap", ctypes.c_int64),
+        ("symmetric", ctypes.c_int32), ("rank_mode", ctypes.c_int32),
+        ("rank_param", ctypes.c_double),
+        ("oversample", ctypes.c_int32), ("power_iters", ctypes.c_int32),
+        ("precision", ctypes.c_int32), ("trailing_hp", ctypes.c_int32),
+        ("seed", ctypes.c_uint64), ("channel", ctypes.c_uint64),
+        ("want_u", ctypes.c_int32), ("want_v", ctypes.c_int32),
+        ("want_residual", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+    ]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [
+        ("rank", ctypes.c_int64), ("l_used", ctypes.c_int64),
+        ("residual", ctypes.c_double), ("rel_percent", ctypes.c_double),
+        ("c_eq2", ctypes.c_double), ("c_sym", ctypes.c_double), ("fro2", ctypes.c_double),
+        ("sweeps", ctypes.c_int32), ("flags", ctypes.c_uint32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load librsvd.so (built in-tree by __graft_entry__.build())."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RsvdError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, u64, dbl, sz = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                  ctypes.c_uint64, ctypes.c_double, ctypes.c_size_t)
+    L.rsvd_plan.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(vp), ctypes.POINTER(sz)]
+    L.rsvd_plan.restype = ctypes.c_int
+    L.rsvd_plan_l.argtypes = [vp]
+    L.rsvd_plan_l.restype = i64
+    L.rsvd_run.argtypes = [vp, vp, i64, vp, i64, vp, vp, i64, vp, i64, vp, vp, sz, vp]
+    L.rsvd_run.restype = ctypes.c_int
+    L.rsvd_destroy.argtypes = [vp]
+    L.rsvd_destroy.restype = None
+    L.rsvd_strerror.argtypes = [ctypes.c_int]
+    L.rsvd_strerror.restype = ctypes.c_char_p
+    L.rsvd_gaussian_omega.argtypes = [i64, i64, i64, u64, u64, vp, i64, vp]
+    L.rsvd_gaussian_omega.restype = ctypes.c_int
+    L.rsvd_dgemm_work_bytes.argtypes = [i64, i64, i64, i32]
+    L.rsvd_dgemm_work_bytes.restype = sz
+    L.rsvd_dgemm.argtypes = [i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, vp, sz, vp]
+    L.rsvd_dgemm.restype = ctypes.c_int
+    L.rsvd_orth_work_bytes.argtypes = [i64, i64]
+    L.rsvd_orth_work_bytes.restype = sz
+    L.rsvd_orth.argtypes = [i64, i64, vp, i64, vp, vp, vp, sz, vp]
+    L.rsvd_orth.restype = ctypes.c_int
+    L.rsvd_small_svd_work_bytes.argtypes = [i64]
+    L.rsvd_small_svd_work_bytes.restype = sz
+    L.rsvd_small_svd.argtypes = [i64, vp, vp, vp, vp, i32, vp, vp, vp, sz, vp]
+    L.rsvd_small_svd.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _check(status, what):
+    if status != RSVD_OK:
+        msg = lib().rsvd_strerror(status).decode()
+        raise RsvdError(f"{what}: {msg} (status {status})")
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RsvdError("no GPU visible: the rSVD library runs only on the device")
+    return torch
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _workspace(torch, nbytes, device):
+    """Device workspace with a 256-byte aligned start (kept alive by the caller)."""
+    buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=device)
+    off = (-buf.data_ptr()) % 256
+    return buf, ctypes.c_void_p(buf.data_ptr() + off), int(nbytes)
+
+
+def _check_matrix(torch, A, name):
+    if not (A.is_cuda and A.dtype == torch.float64 and A.dim() == 2):
+        raise RsvdError(f"{name} must be a 2-D float64 CUDA tensor")
+    if A.stride(1) != 1:
+        raise RsvdError(f"{name} must be row-major (last stride 1)")
+
+
+@dataclass
+class RsvdOutput:
+    S: object          # (rank,) decreasing
+    U: object          # (m, rank) or None
+    V: object          # (n, rank) or None
+    rank: int
+    l: int
+    residual: float
+    rel_percent: float
+    c_eq2: float
+    c_sym: float
+    fro2: float
+    sweeps: int
+    flags: int
+
+
+class Plan:
+    """An immutable plan for one problem shape (wraps rsvd_plan)."""
+
+    def __init__(self, m, n, k, p, q, *, symmetric=False, rank_mode="fixed", rank_param=None,
+                 precision="fp64", trailing_hp=1, seed=0, channel=0, want_u=True, want_v=True,
+                 want_residual=True, max_sweeps=0, k_cap=0):
+        L = lib()
+        pr = Problem()
+        pr.m, pr.n, pr.k, pr.k_cap = int(m), int(n), int(k), int(k_cap)
+        pr.symmetric = int(bool(symmetric))
+        pr.rank_mode = RANK_MODES[rank_mode]
+        pr.rank_param = float(rank_param) if rank_param is not None else float(k)
+        pr.oversample, pr.power_iters = int(p), int(q)
+        pr.precision = PRECISIONS[precision]
+        pr.trailing_hp = int(trailing_hp)
+        pr.seed, pr.channel = int(seed) & (2**64 - 1), int(channel) & (2**64 - 1)
+        pr.want_u, pr.want_v = int(bool(want_u)), int(bool(want_v))
+        pr.want_residual, pr.max_sweeps = int(bool(want_residual)), int(max_sweeps)
+        self.problem = pr
+        h = ctypes.c_void_p()
+        ws = ctypes.c_size_t()
+        _check(L.rsvd_plan(ctypes.byref(pr), ctypes.byref(h), ctypes.byref(ws)), "rsvd_plan")
+        self._h = h
+        self.workspace_bytes = ws.value
+        self.l = L.rsvd_plan_l(h)
+        self.kc = min(int(k_cap) if k_cap else self.l, self.l)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.rsvd_destroy(h)
+            self._h = None
+
+    def allocate(self, device="cuda"):
+        """Output and workspace buffers for run_into (allocated once, reused)."""
+        torch = _torch()
+        pr = self.problem
+        bufs = {
+            "S": torch.empty(self.kc, dtype=torch.float64, device=device),
+            "U": torch.empty(pr.m, self.kc, dtype=torch.float64, device=device) if pr.want_u else None,
+            "V": torch.empty(pr.n, self.kc, dtype=torch.float64, device=device) if pr.want_v else None,
+            "res": torch.zeros(ctypes.sizeof(Result), dtype=torch.uint8, device=device),
+        }
+        bufs["work_buf"], bufs["work"], bufs["work_bytes"] = _workspace(torch, self.workspace_bytes, device)
+        return bufs
+
+    def run_into(self, A, bufs, omega=None):
+        """Enqueue one decomposition on the current stream (no synchronization)."""
+        torch = _torch()
+        _check_matrix(torch, A, "A")
+        pr = self.problem
+        if tuple(A.shape) != (pr.m, pr.n):
+            raise RsvdError(f"A has shape {tuple(A.shape)}, plan expects {(pr.m, pr.n)}")
+        ldo = 0
+        if omega is not None:
+            _check_matrix(torch, omega, "omega")
+            if omega.shape[0] != pr.n or omega.shape[1] < self.l:
+                raise RsvdError("omega must be n x l")
+            ldo = omega.stride(0)
+        U, V = bufs["U"], bufs["V"]
+        st = lib().rsvd_run(self._h, _ptr(A), A.stride(0), _ptr(omega), ldo, _ptr(bufs["S"]),
+                            _ptr(U), U.stride(0) if U is not None else 0,
+                            _ptr(V), V.stride(0) if V is not None else 0,
+                            _ptr(bufs["res"]), bufs["work"], bufs["work_bytes"],
+                            _stream(torch, A.device))
+        _check(st, "rsvd_run")
+
+    def result(self, bufs):
+        """Synchronize and read the device result record."""
+        torch = _torch()
+        torch.cuda.synchronize(bufs["S"].device)
+        raw = bytes(bufs["res"].cpu().numpy().tobytes())
+        return Result.from_buffer_copy(raw)
+
+
+def run(A, k, p, q, *, omega=None, **kw):
+    """Randomized SVD of the CUDA float64 matrix A (m x n); returns RsvdOutput."""
+    torch = _torch()
+    _check_matrix(torch, A, "A")
+    m, n = A.shape
+    plan = Plan(m, n, k, p, q, **kw)
+    bufs = plan.allocate(A.device)
+    plan.run_into(A, bufs, omega=omega)
+    r = plan.result(bufs)
+    if r.flags & FLAG_NONFINITE_INPUT:
+        raise RsvdError("A holds NaN or Inf")
+    rank = int(r.rank)
+    return RsvdOutput(
+        S=bufs["S"][:rank], U=bufs["U"][:, :rank] if bufs["U"] is not None else None,
+        V=bufs["V"][:, :rank] if bufs["V"] is not None else None, rank=rank, l=int(r.l_used),
+        residual=r.residual, rel_percent=r.rel_percent, c_eq2=r.c_eq2, c_sym=r.c_sym,
+        fro2=r.fro2, sweeps=int(r.sweeps), flags=int(r.flags),
+    )
+
+
+def gaussian_omega(n, l, seed, channel=0, col0=0, device="cuda"):
+    """The projection P (n x l) drawn by the library's Philox/Box-Muller kernel."""
+    torch = _torch()
+    out = torch.empty(n, l, dtype=torch.float64, device=device)
+    _check(lib().rsvd_gaussian_omega(n, l, col0, seed & (2**64 - 1), channel & (2**64 - 1),
+                                     _ptr(out), l, _stream(torch, out.device)),
+           "rsvd_gaussian_omega")
+    return out
+
+
+def dgemm(A, B, trans_a=False, alpha=1.0, beta=0.0, C=None):
+    """C = alpha op(A) B + beta C on the FP64 matrix cores."""
+    torch = _torch()
+    _check_matrix(torch, A, "A")
+    _check_matrix(torch, B, "B")
+    m = A.shape[1] if trans_a else A.shape[0]
+    k = A.shape[0] if trans_a else A.shape[1]
+    if B.shape[0] != k:
+        raise RsvdError("inner dimensions differ")
+    n = B.shape[1]
+    if C is None:
+        C = torch.zeros(m, n, dtype=torch.float64, device=A.device)
+    L = lib()
+    wb = L.rsvd_dgemm_work_bytes(m, n, k, int(trans_a))
+    work = torch.empty(max(wb // 8, 1), dtype=torch.float64, device=A.device)
+    _check(L.rsvd_dgemm(int(trans_a), m, n, k, alpha, _ptr(A), A.stride(0), _ptr(B), B.stride(0),
+                        beta, _ptr(C), C.stride(0), _ptr(work), wb, _stream(torch, A.device)),
+           "rsvd_dgemm")
+    return C
+
+
+def orth(Y):
+    """Thin QR of a tall panel: returns (Q, X, flags) with Y = Q X."""
+    torch = _torch()
+    _check_matrix(torch, Y, "Y")
+    m, l = Y.shape
+    Q = Y.clone().contiguous()
+    X = torch.empty(l, l, dtype=torch.float64, device=Y.device)
+    flags = torch.zeros(1, dtype=torch.int32, device=Y.device)
+    L = lib()
+    wb = L.rsvd_orth_work_bytes(m, l)
+    buf, w, wbytes = _workspace(torch, wb, Y.device)
+    _check(L.rsvd_orth(m, l, _ptr(Q), l, _ptr(X), _ptr(flags), w, wbytes, _stream(torch, Y.device)),
+           "rsvd_orth")
+    torch.cuda.synchronize(Y.device)
+    del buf
+    return Q, X, int(flags.item()) & 0xFFFFFFFF
+
+
+def small_svd(R, max_sweeps=0):
+    """SVD of an upper-triangular l x l R: R^T = Us diag(s) W^T. Returns (s, Us, W, sweeps, flags)."""
+    torch = _torch()
+    _check_matrix(torch, R, "R")
+    R = R.contiguous()
+    l = R.shape[0]
+    s = torch.empty(l, dtype=torch.float64, device=R.device)
+    Us = torch.empty(l, l, dtype=torch.float64, device=R.device)
+    W = torch.empty(l, l, dtype=torch.float64, device=R.device)
+    sw = torch.zeros(1, dtype=torch.int32, device=R.device)
+    fl = torch.zeros(1, dtype=torch.int32, device=R.device)
+    L = lib()
+    wb = L.rsvd_small_svd_work_bytes(l)
+    buf, w, wbytes = _workspace(torch, wb, R.device)
+    _check(L.rsvd_small_svd(l, _ptr(R), _ptr(s), _ptr(Us), _ptr(W), max_sweeps,
+                            _ptr(sw), _ptr(fl), w, wbytes, _stream(torch, R.device)),
+           "rsvd_small_svd")
+    torch.cuda.synchronize(R.device)
+    del buf
+    return s, Us, W, int(sw.item()), int(fl.item()) & 0xFFFFFFFF

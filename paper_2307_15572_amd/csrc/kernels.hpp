@@ -1,0 +1,70 @@
+// Internal launch interface of the rSVD kernels (not part of the C ABI).
+#pragma once
+
+#include "common.hpp"
+
+namespace rsvd {
+
+// ---- FP64 matrix-core GEMM (gemm.hip) --------------------------------------
+struct GemmShape {
+  int nt = 1, tiles_m = 1, tiles_n = 1, splits = 1;
+  int64_t kchunk = 0;
+  size_t part_doubles = 0;
+};
+GemmShape dgemm_shape(int64_t M, int64_t N, int64_t K, int max_splits = 64);
+rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
+                  int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
+                  double* part, size_t part_doubles, hipStream_t st, int max_splits = 64,
+                  const uint32_t* pred = nullptr);
+// ||A - US * Vt||_F^2 and ||A||_F^2 accumulated into st->resid2 / st->fro2
+// (US: M x K, Vt: K x N, A: M x N). partial: >= resid_partials(M, N) doubles.
+size_t resid_partials(int64_t M, int64_t N);
+rsvd_status resid(int64_t M, int64_t N, int64_t K, const double* US, int64_t ldus,
+                  const double* Vt, int64_t ldvt, const double* A, int64_t lda,
+                  double* partial, DevState* st, hipStream_t s);
+
+// ---- random projection (omega.hip) -----------------------------------------
+rsvd_status gaussian_omega(int64_t n, int64_t l, int64_t col0, uint64_t seed, uint64_t channel,
+                           double* out, int64_t ldo, hipStream_t st);
+
+// ---- small dense l x l kernels (smalldense.hip) -----------------------------
+// Cholesky of the Gram G (l x l) into R (upper, R^T R = G [+ shift I]) and
+// Rinv = R^{-1}. pass 0 may switch to the shifted factorization (sets
+// st->qr_shifted); a pass with only_if_shifted != 0 does nothing unless
+// st->qr_shifted is set. m = rows of the panel (sizes the shift).
+rsvd_status chol_inv(int64_t l, const double* G, double* R, double* Rinv, int64_t m, int pass,
+                     int only_if_shifted, DevState* st, hipStream_t s);
+// Householder QR of the rows x l panel Yorig into Y (= Q) and R, run only
+// when st->qr_householder is set (tau: 2 l doubles of scratch).
+rsvd_status householder_fallback(int64_t rows, int64_t l, const double* Yorig, double* Y,
+                                 double* R, double* tau, DevState* st, hipStream_t s);
+// Copy src -> dst (rows x cols, row-major) when st->qr_shifted (or always if !cond).
+rsvd_status copy_panel(int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst,
+                       int64_t ldd, int cond_shifted, DevState* st, hipStream_t s);
+// One-sided Jacobi on the rows of M (l x l): P M0 = M with orthogonal rows.
+rsvd_status jacobi_rows(int64_t l, double* M, double* P, int max_sweeps, DevState* st,
+                        hipStream_t s);
+// From converged M, P: s (decreasing), Us (l x kc), W (l x kc).
+rsvd_status svd_finish(int64_t l, int64_t kc, const double* M, const double* P, double* s,
+                       double* Us, double* W, DevState* st, hipStream_t st_);
+rsvd_status select_rank(int64_t l, int64_t p, int64_t kc, int mode, double param,
+                        const double* s, DevState* st, hipStream_t hs);
+rsvd_status sign_fix(int64_t m, int64_t n, int64_t kc, double* U, int64_t ldu, double* V,
+                     int64_t ldv, hipStream_t s);
+rsvd_status resid_prep(int64_t m, int64_t n, int64_t kc, const double* U, int64_t ldu,
+                       const double* s_vals, const double* V, int64_t ldv, double* US,
+                       double* Vt, const DevState* st, hipStream_t s);
+rsvd_status check_finite(int64_t rows, int64_t cols, const double* Y, int64_t ldy, DevState* st,
+                         hipStream_t s);
+rsvd_status sumsq(int64_t m, int64_t n, const double* A, int64_t lda, double* partial,
+                  DevState* st, hipStream_t s);
+rsvd_status finalize(int64_t m, int64_t n, int64_t l, int want_residual, const DevState* st,
+                     rsvd_result* res, hipStream_t s);
+rsvd_status init_state(DevState* st, uint32_t flags, hipStream_t s);
+rsvd_status clear_shift(DevState* st, hipStream_t s);
+rsvd_status sum_partials_into(int64_t cnt, const double* p, double* out, hipStream_t s);
+rsvd_status set_identity(int64_t l, double* P, hipStream_t s);
+rsvd_status transpose(int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst,
+                      int64_t ldd, hipStream_t s);
+
+}  // namespace rsvd

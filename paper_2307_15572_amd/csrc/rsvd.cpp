@@ -1,0 +1,435 @@
+// Host runtime and C ABI of the randomized SVD library (include/rsvd.h).
+//
+// rsvd_run enqueues, on the caller's stream and without host synchronization,
+// the steps of the method (arXiv:2307.15572, section "Randomized matrix
+// decompositions", Fig. 1):
+//   P          Gaussian projection (Philox4x64-10 + Box-Muller), unless given
+//   step 1     Z = A P; thin QR Z = Q X
+//   (q times)  Z' = A^T Q -> QR -> Z = A Q' -> QR   (Halko et al. subspace
+//              iteration; q = 0 is the paper's method)
+//   step 2     Y^T = A^T Q (= Q^T A transposed); Y^T = Q_B X_B (QR);
+//              SVD of X_B^T by one-sided Jacobi: X_B^T = L_Y Sigma W^T, so
+//              Y = L_Y Sigma (Q_B W)^T and R = Q_B W
+//   step 3     L = Q L_Y
+//   then       rank rule (R_SVD, R%, Eq. 2), sign rule, optional residual.
+// Every decision that depends on data (QR shift, rank) is taken on the
+// device, so a run is a fixed sequence of launches.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+using namespace rsvd;
+
+struct rsvd_plan_s {
+  rsvd_problem p;
+  int64_t l = 0;        // sketch width
+  int64_t kc = 0;       // columns produced: min(k_cap, l)
+  int64_t k_fixed = 0;  // resolved fixed rank (fixed / percent rules)
+  int mode = 0;
+  double param = 0.0;
+  // workspace layout (byte offsets, 256-B aligned)
+  size_t off_state = 0, off_Y = 0, off_Z = 0, off_T = 0, off_part = 0, off_G = 0;
+  size_t off_R1 = 0, off_R1i = 0, off_R2 = 0, off_R2i = 0, off_R3 = 0, off_R3i = 0;
+  size_t off_Rt = 0, off_Rtmp = 0, off_M = 0, off_P = 0, off_sig = 0, off_Us = 0, off_W = 0;
+  size_t off_Ub = 0, off_Vb = 0, off_US = 0, off_Vt = 0, off_rpart = 0;
+  size_t off_Yorig = 0, off_tau = 0;
+  size_t part_doubles = 0;
+  size_t total = 0;
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Carver {
+  size_t at = 0;
+  size_t take(size_t bytes) {
+    const size_t o = at;
+    at = align256(at + bytes);
+    return o;
+  }
+};
+
+int64_t percent_rank(double pct, int64_t m, int64_t n) {
+  const double x = pct * (double)(m < n ? m : n) / 100.0;
+  return (int64_t)std::ceil(x * (1.0 - 1e-12));
+}
+
+// Split-K scratch needed by the products of one run.
+size_t gemm_part_need(int64_t m, int64_t n, int64_t l) {
+  size_t need = 0;
+  auto upd = [&](int64_t M, int64_t N, int64_t K) {
+    GemmShape s = dgemm_shape(M, N, K);
+    if (s.part_doubles > need) need = s.part_doubles;
+  };
+  upd(m, l, n);  // A P, A Q
+  upd(n, l, m);  // A^T Q
+  upd(l, l, m);  // Gram of an m x l panel
+  upd(l, l, n);  // Gram of an n x l panel
+  upd(m, l, l);  // panel x R^{-1}
+  upd(n, l, l);
+  upd(l, l, l);
+  return need;
+}
+
+struct Ws {
+  char* base;
+  template <class T>
+  T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
+};
+
+// Thin QR of the rows x l panel Y in place (Y <- Q). Shifted Cholesky QR:
+// pass 0 (unshifted, or shifted when the Gram is too ill-conditioned or
+// breaks down), pass 1, and pass 2 only when pass 0 took the shift.
+// If Rout is non-null it receives the R factor (upper, l x l).
+rsvd_status orth(const rsvd_plan_s& pl, const Ws& w, int64_t rows, double* Y, double* Rout,
+                 hipStream_t s) {
+  const int64_t l = pl.l;
+  DevState* st = w.at<DevState>(pl.off_state);
+  double* G = w.at<double>(pl.off_G);
+  double* T = w.at<double>(pl.off_T);
+  double* part = w.at<double>(pl.off_part);
+  double* R1 = w.at<double>(pl.off_R1);
+  double* R1i = w.at<double>(pl.off_R1i);
+  double* R2 = w.at<double>(pl.off_R2);
+  double* R2i = w.at<double>(pl.off_R2i);
+  double* R3 = w.at<double>(pl.off_R3);
+  double* R3i = w.at<double>(pl.off_R3i);
+  const uint32_t* shifted = &st->qr_shifted;
+  rsvd_status r;
+#define RSVD_TRY(x) do { r = (x); if (r != RSVD_OK) return r; } while (0)
+  double* Yorig = w.at<double>(pl.off_Yorig);
+  double* tau = w.at<double>(pl.off_tau);
+  RSVD_TRY(clear_shift(st, s));
+  RSVD_TRY(copy_panel(rows, l, Y, l, Yorig, l, 0, st, s));
+  // pass 0
+  RSVD_TRY(dgemm(true, l, l, rows, 1.0, Y, l, Y, l, 0.0, G, l, part, pl.part_doubles, s));
+  RSVD_TRY(chol_inv(l, G, R1, R1i, rows, 0, 0, st, s));
+  RSVD_TRY(dgemm(false, rows, l, l, 1.0, Y, l, R1i, l, 0.0, T, l, part, pl.part_doubles, s));
+  // pass 1
+  RSVD_TRY(dgemm(true, l, l, rows, 1.0, T, l, T, l, 0.0, G, l, part, pl.part_doubles, s));
+  RSVD_TRY(chol_inv(l, G, R2, R2i, rows, 1, 0, st, s));
+  RSVD_TRY(dgemm(false, rows, l, l, 1.0, T, l, R2i, l, 0.0, Y, l, part, pl.part_doubles, s));
+  // pass 2 (device-predicated on the shift)
+  RSVD_TRY(dgemm(true, l, l, rows, 1.0, Y, l, Y, l, 0.0, G, l, part, pl.part_doubles, s, 64, shifted));
+  RSVD_TRY(chol_inv(l, G, R3, R3i, rows, 2, 1, st, s));
+  RSVD_TRY(dgemm(false, rows, l, l, 1.0, Y, l, R3i, l, 0.0, T, l, part, pl.part_doubles, s, 64, shifted));
+  RSVD_TRY(copy_panel(rows, l, T, l, Y, l, 1, st, s));
+  if (Rout) {
+    double* Rtmp = w.at<double>(pl.off_Rtmp);
+    // R = R2 R1, then R3 R when shifted
+    RSVD_TRY(dgemm(false, l, l, l, 1.0, R2, l, R1, l, 0.0, Rout, l, part, pl.part_doubles, s));
+    RSVD_TRY(dgemm(false, l, l, l, 1.0, R3, l, Rout, l, 0.0, Rtmp, l, part, pl.part_doubles, s, 64, shifted));
+    RSVD_TRY(copy_panel(l, l, Rtmp, l, Rout, l, 1, st, s));
+  }
+  // rank-deficient panel: Householder QR of the saved original
+  RSVD_TRY(householder_fallback(rows, l, Yorig, Y, Rout, tau, st, s));
+  return RSVD_OK;
+#undef RSVD_TRY
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rsvd_strerror(rsvd_status s) {
+  switch (s) {
+    case RSVD_OK: return "ok";
+    case RSVD_EINVAL: return "invalid argument";
+    case RSVD_ENOMEM: return "workspace too small";
+    case RSVD_EHIP: return "HIP runtime error";
+    case RSVD_EUNSUPPORTED: return "unsupported request";
+  }
+  return "unknown status";
+}
+
+rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* workspace_bytes) {
+  if (!prob || !out) return RSVD_EINVAL;
+  const rsvd_problem& p = *prob;
+  if (p.m < 1 || p.n < 1 || p.oversample < 0 || p.power_iters < 0) return RSVD_EINVAL;
+  if (p.symmetric && p.m != p.n) return RSVD_EINVAL;
+  if (p.precision != RSVD_PREC_FP64) return RSVD_EUNSUPPORTED;
+  int64_t k = p.k;
+  int mode = p.rank_mode;
+  double param = p.rank_param;
+  switch (mode) {
+    case RSVD_RANK_FIXED:
+      if (k < 1) return RSVD_EINVAL;
+      param = (double)k;
+      break;
+    case RSVD_RANK_PERCENT:
+      if (!(p.rank_param > 0.0 && p.rank_param <= 100.0)) return RSVD_EINVAL;
+      k = percent_rank(p.rank_param, p.m, p.n);
+      mode = RSVD_RANK_FIXED;
+      param = (double)k;
+      break;
+    case RSVD_RANK_REL_THRESHOLD:
+    case RSVD_RANK_FROB_TAIL:
+      if (!(p.rank_param > 0.0 && p.rank_param < 1.0)) return RSVD_EINVAL;
+      if (k < 1) return RSVD_EINVAL;
+      break;
+    default:
+      return RSVD_EINVAL;
+  }
+  const int64_t mn = p.m < p.n ? p.m : p.n;
+  int64_t l = k + p.oversample;
+  if (l > mn) l = mn;
+  if (l > 4096) return RSVD_EUNSUPPORTED;
+  int64_t kcap = p.k_cap > 0 ? p.k_cap : l;
+  if (mode == RSVD_RANK_FIXED && kcap < (k < l ? k : l)) return RSVD_EINVAL;
+  rsvd_plan_s* pl = new (std::nothrow) rsvd_plan_s();
+  if (!pl) return RSVD_ENOMEM;
+  pl->p = p;
+  pl->l = l;
+  pl->kc = kcap < l ? kcap : l;
+  pl->k_fixed = k;
+  pl->mode = mode;
+  pl->param = param;
+  const int64_t m = p.m, n = p.n, kc = pl->kc;
+  const int64_t mx = m > n ? m : n;
+  const size_t D = sizeof(double);
+  Carver c;
+  pl->off_state = c.take(sizeof(DevState));
+  pl->off_Y = c.take((size_t)m * l * D);
+  pl->off_Z = c.take((size_t)n * l * D);
+  pl->off_T = c.take((size_t)mx * l * D);
+  pl->off_Yorig = c.take((size_t)mx * l * D);
+  pl->off_tau = c.take((size_t)2 * l * D);
+  pl->part_doubles = gemm_part_need(m, n, l);
+  if (pl->part_doubles < 2048) pl->part_doubles = 2048;
+  pl->off_part = c.take(pl->part_doubles * D);
+  const size_t ll = (size_t)l * l * D;
+  pl->off_G = c.take(ll);
+  pl->off_R1 = c.take(ll);
+  pl->off_R1i = c.take(ll);
+  pl->off_R2 = c.take(ll);
+  pl->off_R2i = c.take(ll);
+  pl->off_R3 = c.take(ll);
+  pl->off_R3i = c.take(ll);
+  pl->off_Rt = c.take(ll);
+  pl->off_Rtmp = c.take(ll);
+  pl->off_M = c.take(ll);
+  pl->off_P = c.take(ll);
+  pl->off_sig = c.take((size_t)l * D);
+  pl->off_Us = c.take((size_t)l * kc * D);
+  pl->off_W = c.take((size_t)l * kc * D);
+  pl->off_Ub = c.take((size_t)m * kc * D);
+  pl->off_Vb = c.take((size_t)n * kc * D);
+  if (p.want_residual) {
+    pl->off_US = c.take((size_t)m * kc * D);
+    pl->off_Vt = c.take((size_t)n * kc * D);
+    pl->off_rpart = c.take(resid_partials(m, n) * D);
+  }
+  pl->total = c.at;
+  *out = pl;
+  if (workspace_bytes) *workspace_bytes = pl->total;
+  return RSVD_OK;
+}
+
+int64_t rsvd_plan_l(rsvd_plan_t plan) { return plan ? plan->l : -1; }
+
+void rsvd_destroy(rsvd_plan_t plan) { delete plan; }
+
+rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const double* omega,
+                     int64_t ldo, double* S, double* U, int64_t ldu, double* V, int64_t ldv,
+                     rsvd_result* res_dev, void* work, size_t work_bytes, void* stream) {
+  if (!plan || !A || !S || !res_dev || !work) return RSVD_EINVAL;
+  const rsvd_plan_s& pl = *plan;
+  const rsvd_problem& p = pl.p;
+  const int64_t m = p.m, n = p.n, l = pl.l, kc = pl.kc;
+  if (lda < n) return RSVD_EINVAL;
+  if (omega && ldo < l) return RSVD_EINVAL;
+  if (p.want_u && (!U || ldu < kc)) return RSVD_EINVAL;
+  if (p.want_v && (!V || ldv < kc)) return RSVD_EINVAL;
+  if (work_bytes < pl.total) return RSVD_ENOMEM;
+  if (((uintptr_t)work & 255) != 0) return RSVD_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  Ws w{(char*)work};
+  DevState* st = w.at<DevState>(pl.off_state);
+  double* Y = w.at<double>(pl.off_Y);
+  double* Z = w.at<double>(pl.off_Z);
+  double* part = w.at<double>(pl.off_part);
+  double* Rt = w.at<double>(pl.off_Rt);
+  double* Mj = w.at<double>(pl.off_M);
+  double* Pj = w.at<double>(pl.off_P);
+  double* sig = w.at<double>(pl.off_sig);
+  double* Us = w.at<double>(pl.off_Us);
+  double* W = w.at<double>(pl.off_W);
+  double* Uo = p.want_u ? U : w.at<double>(pl.off_Ub);
+  const int64_t lduo = p.want_u ? ldu : kc;
+  double* Vo = p.want_v ? V : w.at<double>(pl.off_Vb);
+  const int64_t ldvo = p.want_v ? ldv : kc;
+  const int64_t mn = m < n ? m : n;
+  rsvd_status r;
+#define RSVD_TRY(x) do { r = (x); if (r != RSVD_OK) return r; } while (0)
+  RSVD_TRY(init_state(st, l == mn ? RSVD_FLAG_FULL_SVD : 0u, s));
+
+  // step 1: Z = A P and its orthonormal basis
+  const double* Om = omega;
+  int64_t ldom = ldo;
+  if (!Om) {
+    RSVD_TRY(gaussian_omega(n, l, 0, p.seed, p.channel, Z, l, s));
+    Om = Z;
+    ldom = l;
+  }
+  RSVD_TRY(dgemm(false, m, l, n, 1.0, A, lda, Om, ldom, 0.0, Y, l, part, pl.part_doubles, s));
+  RSVD_TRY(check_finite(m, l, Y, l, st, s));
+  RSVD_TRY(orth(pl, w, m, Y, nullptr, s));
+  // power iterations
+  for (int t = 0; t < p.power_iters; t++) {
+    RSVD_TRY(dgemm(!p.symmetric, n, l, m, 1.0, A, lda, Y, l, 0.0, Z, l, part, pl.part_doubles, s));
+    RSVD_TRY(orth(pl, w, n, Z, nullptr, s));
+    RSVD_TRY(dgemm(false, m, l, n, 1.0, A, lda, Z, l, 0.0, Y, l, part, pl.part_doubles, s));
+    RSVD_TRY(orth(pl, w, m, Y, nullptr, s));
+  }
+  // step 2: Y^T = A^T Q = Q_B X_B, small SVD of X_B^T
+  RSVD_TRY(dgemm(!p.symmetric, n, l, m, 1.0, A, lda, Y, l, 0.0, Z, l, part, pl.part_doubles, s));
+  RSVD_TRY(orth(pl, w, n, Z, Rt, s));
+  RSVD_TRY(copy_panel(l, l, Rt, l, Mj, l, 0, st, s));
+  RSVD_TRY(set_identity(l, Pj, s));
+  RSVD_TRY(jacobi_rows(l, Mj, Pj, p.max_sweeps > 0 ? p.max_sweeps : 30, st, s));
+  RSVD_TRY(svd_finish(l, kc, Mj, Pj, sig, Us, W, st, s));
+  if (pl.mode == RSVD_RANK_FROB_TAIL) {
+    RSVD_TRY(sumsq(m, n, A, lda, part, st, s));
+  }
+  RSVD_TRY(select_rank(l, p.oversample, kc, pl.mode, pl.param, sig, st, s));
+  // step 3: L = Q L_Y, R = Q_B W
+  RSVD_TRY(dgemm(false, m, kc, l, 1.0, Y, l, Us, kc, 0.0, Uo, lduo, part, pl.part_doubles, s));
+  RSVD_TRY(dgemm(false, n, kc, l, 1.0, Z, l, W, kc, 0.0, Vo, ldvo, part, pl.part_doubles, s));
+  RSVD_TRY(sign_fix(m, n, kc, Uo, lduo, Vo, ldvo, s));
+  if (hipMemcpyAsync(S, sig, (size_t)kc * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return RSVD_EHIP;
+  if (p.want_residual) {
+    double* US = w.at<double>(pl.off_US);
+    double* Vt = w.at<double>(pl.off_Vt);
+    RSVD_TRY(resid_prep(m, n, kc, Uo, lduo, sig, Vo, ldvo, US, Vt, st, s));
+    RSVD_TRY(resid(m, n, kc, US, kc, Vt, n, A, lda, w.at<double>(pl.off_rpart), st, s));
+  }
+  RSVD_TRY(finalize(m, n, l, p.want_residual, st, res_dev, s));
+  return RSVD_OK;
+#undef RSVD_TRY
+}
+
+rsvd_status rsvd_gaussian_omega(int64_t n, int64_t l, int64_t col0, uint64_t seed,
+                                uint64_t channel, double* out, int64_t ldo, void* stream) {
+  if (n < 0 || l < 0 || col0 < 0 || (n > 0 && l > 0 && (!out || ldo < l))) return RSVD_EINVAL;
+  return gaussian_omega(n, l, col0, seed, channel, out, ldo, (hipStream_t)stream);
+}
+
+size_t rsvd_dgemm_work_bytes(int64_t m, int64_t n, int64_t k, int32_t trans_a) {
+  (void)trans_a;
+  if (m <= 0 || n <= 0 || k <= 0) return 0;
+  return dgemm_shape(m, n, k).part_doubles * sizeof(double);
+}
+
+rsvd_status rsvd_dgemm(int32_t trans_a, int64_t m, int64_t n, int64_t k, double alpha,
+                       const double* A, int64_t lda, const double* B, int64_t ldb, double beta,
+                       double* C, int64_t ldc, void* work, size_t work_bytes, void* stream) {
+  if (m < 0 || n < 0 || k < 0) return RSVD_EINVAL;
+  if (m == 0 || n == 0) return RSVD_OK;
+  if (!C || ldc < n) return RSVD_EINVAL;
+  if (k > 0) {
+    if (!A || !B || ldb < n) return RSVD_EINVAL;
+    if (trans_a ? lda < m : lda < k) return RSVD_EINVAL;
+  }
+  return dgemm(trans_a != 0, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, (double*)work,
+               work_bytes / sizeof(double), (hipStream_t)stream);
+}
+
+size_t rsvd_orth_work_bytes(int64_t m, int64_t l) {
+  rsvd_plan_s pl;
+  pl.l = l;
+  Carver c;
+  pl.off_state = c.take(sizeof(DevState));
+  pl.off_T = c.take((size_t)m * l * sizeof(double));
+  pl.off_Yorig = c.take((size_t)m * l * sizeof(double));
+  pl.off_tau = c.take((size_t)2 * l * sizeof(double));
+  pl.part_doubles = gemm_part_need(m, m, l);
+  pl.off_part = c.take(pl.part_doubles * sizeof(double));
+  const size_t ll = (size_t)l * l * sizeof(double);
+  for (int i = 0; i < 9; i++) c.take(ll);
+  return c.at;
+}
+
+rsvd_status rsvd_orth(int64_t m, int64_t l, double* Y, int64_t ldy, double* X, uint32_t* flags,
+                      void* work, size_t work_bytes, void* stream) {
+  if (m < 1 || l < 1 || l > m || !Y || ldy != l || !work) return RSVD_EINVAL;
+  if (work_bytes < rsvd_orth_work_bytes(m, l)) return RSVD_ENOMEM;
+  if (((uintptr_t)work & 255) != 0) return RSVD_EINVAL;
+  rsvd_plan_s pl;
+  pl.l = l;
+  Carver c;
+  pl.off_state = c.take(sizeof(DevState));
+  pl.off_T = c.take((size_t)m * l * sizeof(double));
+  pl.off_Yorig = c.take((size_t)m * l * sizeof(double));
+  pl.off_tau = c.take((size_t)2 * l * sizeof(double));
+  pl.part_doubles = gemm_part_need(m, m, l);
+  pl.off_part = c.take(pl.part_doubles * sizeof(double));
+  const size_t ll = (size_t)l * l * sizeof(double);
+  pl.off_G = c.take(ll);
+  pl.off_R1 = c.take(ll);
+  pl.off_R1i = c.take(ll);
+  pl.off_R2 = c.take(ll);
+  pl.off_R2i = c.take(ll);
+  pl.off_R3 = c.take(ll);
+  pl.off_R3i = c.take(ll);
+  pl.off_Rtmp = c.take(ll);
+  c.take(ll);
+  hipStream_t s = (hipStream_t)stream;
+  Ws w{(char*)work};
+  DevState* st = w.at<DevState>(pl.off_state);
+  rsvd_status r = init_state(st, 0, s);
+  if (r != RSVD_OK) return r;
+  r = orth(pl, w, m, Y, X, s);
+  if (r != RSVD_OK) return r;
+  if (flags) {
+    if (hipMemcpyAsync(flags, &st->flags, sizeof(uint32_t), hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return RSVD_EHIP;
+  }
+  return RSVD_OK;
+}
+
+size_t rsvd_small_svd_work_bytes(int64_t l) {
+  Carver c;
+  c.take(sizeof(DevState));
+  c.take((size_t)l * l * sizeof(double));
+  c.take((size_t)l * l * sizeof(double));
+  return c.at;
+}
+
+rsvd_status rsvd_small_svd(int64_t l, const double* R, double* sv, double* Us, double* W,
+                           int32_t max_sweeps, int32_t* sweeps, uint32_t* flags, void* work,
+                           size_t work_bytes, void* stream) {
+  if (l < 1 || !R || !sv || !Us || !W || !work) return RSVD_EINVAL;
+  if (work_bytes < rsvd_small_svd_work_bytes(l)) return RSVD_ENOMEM;
+  if (((uintptr_t)work & 255) != 0) return RSVD_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  Carver c;
+  const size_t off_state = c.take(sizeof(DevState));
+  const size_t off_M = c.take((size_t)l * l * sizeof(double));
+  const size_t off_P = c.take((size_t)l * l * sizeof(double));
+  Ws w{(char*)work};
+  DevState* st = w.at<DevState>(off_state);
+  double* Mj = w.at<double>(off_M);
+  double* Pj = w.at<double>(off_P);
+  rsvd_status r;
+#define RSVD_TRY(x) do { r = (x); if (r != RSVD_OK) return r; } while (0)
+  RSVD_TRY(init_state(st, 0, s));
+  RSVD_TRY(copy_panel(l, l, R, l, Mj, l, 0, st, s));
+  RSVD_TRY(set_identity(l, Pj, s));
+  RSVD_TRY(jacobi_rows(l, Mj, Pj, max_sweeps > 0 ? max_sweeps : 30, st, s));
+  RSVD_TRY(svd_finish(l, l, Mj, Pj, sv, Us, W, st, s));
+  if (sweeps && hipMemcpyAsync(sweeps, &st->sweeps, sizeof(int32_t), hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return RSVD_EHIP;
+  if (flags && hipMemcpyAsync(flags, &st->flags, sizeof(uint32_t), hipMemcpyDeviceToDevice, s) != hipSuccess)
+    return RSVD_EHIP;
+  return RSVD_OK;
+#undef RSVD_TRY
+}
+
+}  // extern "C"

@@ -1,0 +1,790 @@
+// Small dense kernels of the randomized SVD: the l x l work between the
+// streaming products (Cholesky QR factors, the small SVD by one-sided
+// Jacobi, ordering, rank rule, signs, residual bookkeeping).
+//
+// Paper mapping (section "Randomized matrix decompositions", Fig. 1):
+//   chol_inv      thin QR Z = Q X of step 1 (Cholesky QR: X^T X = Z^T Z)
+//   jacobi_rows   thin SVD of the projected matrix, step 2 (applied to the
+//                 triangular factor of its transpose)
+//   svd_finish    singular values ordered decreasingly (Eq. 1)
+//   select_rank   R_SVD, R% and the compression ratio of Eq. 2
+#include "common.hpp"
+#include "kernels.hpp"
+
+#include <math.h>
+
+namespace rsvd {
+
+namespace {
+
+constexpr double kUnitRoundoff = 1.1102230246251565e-16;  // 2^-53
+constexpr int kBig = 1024;                                // threads of the l x l kernels
+
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  __syncthreads();
+  if (lane == 0) red[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  const int nw = (blockDim.x + 63) >> 6;
+  for (int i = 0; i < nw; i++) s += red[i];
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky R^T R = G (+ shift I) and the inverse of R, one workgroup.
+// The factor is built in place in R's upper triangle (row j of R is column j
+// of the lower Cholesky factor), right-looking, one pivot per step.
+// W: working storage (LDS when small, else R itself in global memory).
+// ---------------------------------------------------------------------------
+__device__ bool chol_upper(int l, double* W, int ldw, double* red, double* bcast) {
+  bool ok = true;
+  for (int j = 0; j < l; j++) {
+    if (threadIdx.x == 0) {
+      const double d = W[(int64_t)j * ldw + j];
+      const bool good = d > 0.0 && isfinite(d);
+      bcast[0] = good ? sqrt(d) : -1.0;
+    }
+    __syncthreads();
+    const double rjj = bcast[0];
+    if (rjj < 0.0) { ok = false; break; }
+    const double inv = 1.0 / rjj;
+    for (int c = j + 1 + threadIdx.x; c < l; c += blockDim.x) W[(int64_t)j * ldw + c] *= inv;
+    __syncthreads();
+    if (threadIdx.x == 0) W[(int64_t)j * ldw + j] = rjj;
+    // trailing update of the upper triangle: W[i][c] -= R[j][i] R[j][c], j < i <= c
+    const int nt = l - j - 1;
+    const int64_t cnt = (int64_t)nt * nt;
+    for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) {
+      const int i = j + 1 + (int)(e / nt);
+      const int c = j + 1 + (int)(e % nt);
+      if (c >= i) W[(int64_t)i * ldw + c] -= W[(int64_t)j * ldw + i] * W[(int64_t)j * ldw + c];
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  return ok;
+}
+
+// X = R^{-1} (upper). Thread c owns column c: R X = I by back substitution.
+__device__ void tri_inv_upper(int l, const double* R, int ldr, double* X, int ldx) {
+  for (int c = threadIdx.x; c < l; c += blockDim.x) {
+    for (int i = c + 1; i < l; i++) X[(int64_t)i * ldx + c] = 0.0;
+    X[(int64_t)c * ldx + c] = 1.0 / R[(int64_t)c * ldr + c];
+    for (int i = c - 1; i >= 0; i--) {
+      double s = 0.0;
+      for (int k = i + 1; k <= c; k++) s += R[(int64_t)i * ldr + k] * X[(int64_t)k * ldx + c];
+      X[(int64_t)i * ldx + c] = -s / R[(int64_t)i * ldr + i];
+    }
+  }
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(kBig) chol_inv_kernel(int l, const double* __restrict__ G,
+                                                        double* __restrict__ R,
+                                                        double* __restrict__ Rinv, int64_t m,
+                                                        int pass, int only_if_shifted,
+                                                        DevState* st) {
+  extern __shared__ double lds[];
+  __shared__ double red[kBig / 64];
+  __shared__ double bcast[2];
+  if (only_if_shifted && st->qr_shifted == 0) return;
+  const bool in_lds = (int64_t)l * l * 2 * sizeof(double) <= 150 * 1024;
+  double* W = in_lds ? lds : R;
+  double* X = in_lds ? lds + (int64_t)l * l : Rinv;
+  const int64_t ll = (int64_t)l * l;
+
+  // trace -> shift for the shifted factorization (Fukaya et al. 2020:
+  // s = 11 (m l + l (l + 1)) u ||Z||_2^2, with ||Z||_2^2 <= trace(Z^T Z))
+  double tr = 0.0;
+  for (int i = threadIdx.x; i < l; i += blockDim.x) tr += G[(int64_t)i * l + i];
+  tr = block_sum(tr, red);
+  const double shift = 11.0 * ((double)m * l + (double)l * (l + 1)) * kUnitRoundoff * tr;
+
+  bool use_shift = false;
+  for (int attempt = 0; attempt < 2; attempt++) {
+    for (int64_t e = threadIdx.x; e < ll; e += blockDim.x) {
+      const int i = (int)(e / l), c = (int)(e % l);
+      double v = (c >= i) ? G[e] : 0.0;
+      if (use_shift && i == c) v += shift;
+      W[e] = v;
+    }
+    __syncthreads();
+    bool ok = chol_upper(l, W, l, red, bcast);
+    if (ok && pass == 0 && !use_shift) {
+      // diag(R) bounds kappa(Z) from below; past 1e5 two unshifted passes may
+      // not restore orthogonality, so take the shifted three-pass route
+      double dmax = 0.0, dmin = INFINITY;
+      for (int i = threadIdx.x; i < l; i += blockDim.x) {
+        const double d = W[(int64_t)i * l + i];
+        dmax = fmax(dmax, d);
+        dmin = fmin(dmin, d);
+      }
+      dmax = wave_max(dmax);
+      dmin = -wave_max(-dmin);
+      __syncthreads();
+      if ((threadIdx.x & 63) == 0) { red[threadIdx.x >> 6] = dmax; }
+      __syncthreads();
+      double gmax = 0.0;
+      for (int i = 0; i < (int)(blockDim.x >> 6); i++) gmax = fmax(gmax, red[i]);
+      __syncthreads();
+      if ((threadIdx.x & 63) == 0) { red[threadIdx.x >> 6] = dmin; }
+      __syncthreads();
+      double gmin = INFINITY;
+      for (int i = 0; i < (int)(blockDim.x >> 6); i++) gmin = fmin(gmin, red[i]);
+      __syncthreads();
+      if (gmax > 1e5 * gmin) ok = false;
+    }
+    if (ok) break;
+    if (pass != 0 || use_shift) {
+      // breakdown even with the shift: the panel is numerically rank
+      // deficient. Finish with clamped pivots so every value stays finite and
+      // hand the panel to the Householder fallback.
+      if (threadIdx.x == 0) st->qr_householder = 1;
+      for (int64_t e = threadIdx.x; e < ll; e += blockDim.x) {
+        const int i = (int)(e / l), c = (int)(e % l);
+        double v = (c >= i) ? G[e] : 0.0;
+        if (i == c) v += fmax(shift, 1e-300);
+        W[e] = v;
+      }
+      __syncthreads();
+      for (int j = 0; j < l; j++) {
+        if (threadIdx.x == 0) {
+          double d = W[(int64_t)j * l + j];
+          if (!(d > shift)) d = fmax(shift, 1e-300);
+          bcast[0] = sqrt(d);
+        }
+        __syncthreads();
+        const double rjj = bcast[0];
+        for (int c = j + 1 + threadIdx.x; c < l; c += blockDim.x) W[(int64_t)j * l + c] /= rjj;
+        __syncthreads();
+        if (threadIdx.x == 0) W[(int64_t)j * l + j] = rjj;
+        const int nt = l - j - 1;
+        for (int64_t e = threadIdx.x; e < (int64_t)nt * nt; e += blockDim.x) {
+          const int i = j + 1 + (int)(e / nt), c = j + 1 + (int)(e % nt);
+          if (c >= i) W[(int64_t)i * l + c] -= W[(int64_t)j * l + i] * W[(int64_t)j * l + c];
+        }
+        __syncthreads();
+      }
+      break;
+    }
+    use_shift = true;
+    if (threadIdx.x == 0) {
+      st->qr_shifted = 1;
+    }
+    __syncthreads();
+  }
+  tri_inv_upper(l, W, l, X, l);
+  if (in_lds) {
+    for (int64_t e = threadIdx.x; e < ll; e += blockDim.x) {
+      R[e] = W[e];
+      Rinv[e] = X[e];
+    }
+  }
+}
+
+
+// ---------------------------------------------------------------------------
+// Householder QR of a rows x l panel (rows >= l), one workgroup: the fallback
+// for panels whose Cholesky QR broke down (numerically rank deficient). Y is
+// overwritten by the explicit Q (diag(R) >= 0), R (l x l upper) if non-null.
+// Runs only when st->qr_householder is set. Y holds a copy of the original
+// panel on entry (restored from Yorig).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kBig) householder_kernel(int64_t rows, int l,
+                                                           const double* __restrict__ Yorig,
+                                                           double* __restrict__ Y,
+                                                           double* __restrict__ R,
+                                                           double* __restrict__ tau_buf,
+                                                           DevState* st) {
+  if (st->qr_householder == 0) return;
+  __shared__ double red[kBig / 64];
+  __shared__ double sh[4];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
+  const int64_t tot = rows * l;
+  double* W = Y;  // factor in place
+  for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) W[e] = Yorig[e];
+  __syncthreads();
+  for (int j = 0; j < l; j++) {
+    // sigma2 = sum_{i > j} W[i][j]^2
+    double s2 = 0.0;
+    for (int64_t i = j + 1 + threadIdx.x; i < rows; i += blockDim.x) {
+      const double x = W[i * l + j];
+      s2 += x * x;
+    }
+    s2 = block_sum(s2, red);
+    if (threadIdx.x == 0) {
+      const double alpha = W[(int64_t)j * l + j];
+      const double nrm = sqrt(alpha * alpha + s2);
+      double beta, tau, scale;
+      if (s2 == 0.0) {
+        beta = alpha;
+        tau = 0.0;
+        scale = 0.0;
+      } else {
+        beta = alpha >= 0.0 ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        scale = 1.0 / (alpha - beta);
+      }
+      sh[0] = beta;
+      sh[1] = tau;
+      sh[2] = scale;
+      tau_buf[j] = tau;
+    }
+    __syncthreads();
+    const double beta = sh[0], tau = sh[1], scale = sh[2];
+    for (int64_t i = j + 1 + threadIdx.x; i < rows; i += blockDim.x) W[i * l + j] *= scale;
+    __syncthreads();
+    if (threadIdx.x == 0) W[(int64_t)j * l + j] = beta;
+    // apply H = I - tau v v^T (v_j = 1) to columns c > j, one wave per column
+    if (tau != 0.0) {
+      for (int c = j + 1 + wave; c < l; c += nw) {
+        double d = (lane == 0) ? W[(int64_t)j * l + c] : 0.0;
+        for (int64_t i = j + 1 + lane; i < rows; i += 64) d += W[i * l + j] * W[i * l + c];
+        d = wave_sum(d) * tau;
+        if (lane == 0) W[(int64_t)j * l + c] -= d;
+        for (int64_t i = j + 1 + lane; i < rows; i += 64) W[i * l + c] -= d * W[i * l + j];
+      }
+    }
+    __syncthreads();
+  }
+  // R = upper(W), sign-fixed so diag(R) >= 0 (rows of R and columns of Q flip together)
+  if (R) {
+    for (int64_t e = threadIdx.x; e < (int64_t)l * l; e += blockDim.x) {
+      const int i = (int)(e / l), c = (int)(e % l);
+      const double d = W[(int64_t)i * l + i];
+      R[e] = (c >= i) ? (d < 0.0 ? -W[(int64_t)i * l + c] : W[(int64_t)i * l + c]) : 0.0;
+    }
+  }
+  // keep the diagonal signs in tau_buf[l + j]
+  for (int j = threadIdx.x; j < l; j += blockDim.x) tau_buf[l + j] = W[(int64_t)j * l + j] < 0.0 ? -1.0 : 1.0;
+  __syncthreads();
+  // Q = H_0 ... H_{l-1} [I; 0], accumulated backwards in place. Before
+  // column j is rebuilt, rows > j of column j still hold v_j.
+  for (int j = l - 1; j >= 0; j--) {
+    const double tau = tau_buf[j];
+    // columns c > j: Q[j:, c] -= tau v (v^T Q[j:, c]); Q[j][c] is 0 for c > j before H_j
+    for (int c = j + 1 + wave; c < l; c += nw) {
+      double d = 0.0;
+      for (int64_t i = j + 1 + lane; i < rows; i += 64) d += W[i * l + j] * W[i * l + c];
+      d = wave_sum(d) * tau;
+      if (lane == 0) W[(int64_t)j * l + c] = -d;
+      for (int64_t i = j + 1 + lane; i < rows; i += 64) W[i * l + c] -= d * W[i * l + j];
+    }
+    __syncthreads();
+    // column j: H_j e_j = e_j - tau v
+    for (int64_t i = j + 1 + threadIdx.x; i < rows; i += blockDim.x) W[i * l + j] = -tau * W[i * l + j];
+    if (threadIdx.x == 0) {
+      W[(int64_t)j * l + j] = 1.0 - tau;
+      for (int i = 0; i < j; i++) W[(int64_t)i * l + j] = 0.0;
+    }
+    __syncthreads();
+  }
+  for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) W[e] *= tau_buf[l + (int)(e % l)];
+  if (threadIdx.x == 0) atomicOr(&st->flags, (uint32_t)RSVD_FLAG_QR_FALLBACK);
+}
+
+__global__ void __launch_bounds__(256) copy_panel_kernel(int64_t rows, int64_t cols,
+                                                         const double* __restrict__ src, int64_t lds,
+                                                         double* __restrict__ dst, int64_t ldd,
+                                                         int cond, const DevState* st) {
+  if (cond && st->qr_shifted == 0) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  const int64_t r = idx / cols, c = idx % cols;
+  dst[r * ldd + c] = src[r * lds + c];
+}
+
+// ---------------------------------------------------------------------------
+// One-sided Jacobi (Hestenes) on the rows of M, one workgroup.
+// Round-robin (circle) ordering: in each of the L-1 steps of a sweep the
+// L/2 disjoint row pairs are handled by different waves. A pair (a, b) with
+// |a.b| > tol sqrt(|a|^2 |b|^2) is rotated so that a.b = 0 (Rutishauser's
+// formulas); the same rotation is applied to the rows of P. Converged when
+// a sweep performs no rotation. tol = l u.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void rr_pair(int L, int step, int i, int& a, int& b) {
+  // players 0..L-1, player L-1 fixed
+  if (i == 0) {
+    a = L - 1;
+    b = step;
+  } else {
+    a = (step + i) % (L - 1);
+    b = (step - i + (L - 1)) % (L - 1);
+  }
+}
+
+__global__ void __launch_bounds__(kBig) jacobi_kernel(int l, double* __restrict__ Mg,
+                                                      double* __restrict__ Pg, int max_sweeps,
+                                                      DevState* st) {
+  extern __shared__ double lds[];
+  __shared__ int s_rot;
+  const bool in_lds = (int64_t)l * l * 2 * sizeof(double) <= 150 * 1024;
+  const int64_t ll = (int64_t)l * l;
+  double* M = in_lds ? lds : Mg;
+  double* P = in_lds ? lds + ll : Pg;
+  if (in_lds) {
+    for (int64_t e = threadIdx.x; e < ll; e += blockDim.x) {
+      M[e] = Mg[e];
+      P[e] = Pg[e];
+    }
+  }
+  __syncthreads();
+  const int L = l + (l & 1);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int nw = blockDim.x >> 6;
+  const double tol = (double)l * kUnitRoundoff;
+  int sweep = 0;
+  bool converged = (l < 2);
+  for (; sweep < max_sweeps && !converged; sweep++) {
+    if (threadIdx.x == 0) s_rot = 0;
+    __syncthreads();
+    int my_rot = 0;
+    for (int step = 0; step < L - 1; step++) {
+      for (int pi = wave; pi < L / 2; pi += nw) {
+        int a, b;
+        rr_pair(L, step, pi, a, b);
+        if (a >= l || b >= l) continue;
+        if (a > b) { const int t = a; a = b; b = t; }
+        double* ra = M + (int64_t)a * l;
+        double* rb = M + (int64_t)b * l;
+        double al = 0.0, be = 0.0, ga = 0.0;
+        for (int c = lane; c < l; c += 64) {
+          const double x = ra[c], y = rb[c];
+          al += x * x;
+          be += y * y;
+          ga += x * y;
+        }
+        al = wave_sum(al);
+        be = wave_sum(be);
+        ga = wave_sum(ga);
+        if (fabs(ga) > tol * sqrt(al) * sqrt(be) && ga != 0.0) {
+          const double zeta = (be - al) / (2.0 * ga);
+          const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = 1.0 / sqrt(1.0 + t * t);
+          const double sn = cs * t;
+          for (int c = lane; c < l; c += 64) {
+            const double x = ra[c], y = rb[c];
+            ra[c] = cs * x - sn * y;
+            rb[c] = sn * x + cs * y;
+          }
+          double* pa = P + (int64_t)a * l;
+          double* pb = P + (int64_t)b * l;
+          for (int c = lane; c < l; c += 64) {
+            const double x = pa[c], y = pb[c];
+            pa[c] = cs * x - sn * y;
+            pb[c] = sn * x + cs * y;
+          }
+          my_rot++;
+        }
+      }
+      __syncthreads();
+    }
+    if (lane == 0 && my_rot) atomicAdd(&s_rot, my_rot);
+    __syncthreads();
+    converged = (s_rot == 0);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    st->sweeps = sweep;
+    if (!converged) atomicOr(&st->flags, (uint32_t)RSVD_FLAG_JACOBI_MAXSWEEP);
+  }
+  if (in_lds) {
+    __syncthreads();
+    for (int64_t e = threadIdx.x; e < ll; e += blockDim.x) {
+      Mg[e] = M[e];
+      Pg[e] = P[e];
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) identity_kernel(int64_t l, double* P) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= l * l) return;
+  P[idx] = (idx / l == idx % l) ? 1.0 : 0.0;
+}
+
+// s_i = |row i of M|, sorted decreasingly (ties keep the lower row first);
+// Us[:, i] = row pi(i) of M / s_i, W[:, i] = row pi(i) of P.
+__global__ void __launch_bounds__(kBig) svd_finish_kernel(int l, int kc,
+                                                          const double* __restrict__ M,
+                                                          const double* __restrict__ P,
+                                                          double* __restrict__ s,
+                                                          double* __restrict__ Us,
+                                                          double* __restrict__ W, DevState* st) {
+  extern __shared__ double lds[];
+  double* nrm = lds;                       // l
+  int* perm = (int*)(lds + l);             // l
+  for (int i = threadIdx.x; i < l; i += blockDim.x) {
+    double a = 0.0;
+    for (int c = 0; c < l; c++) {
+      const double x = M[(int64_t)i * l + c];
+      a += x * x;
+    }
+    nrm[i] = sqrt(a);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < l; i += blockDim.x) {
+    const double v = nrm[i];
+    int pos = 0;
+    for (int j = 0; j < l; j++) {
+      const double u = nrm[j];
+      pos += (u > v) || (u == v && j < i);
+    }
+    perm[pos] = i;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < l; i += blockDim.x) s[i] = nrm[perm[i]];
+  for (int64_t e = threadIdx.x; e < (int64_t)l * kc; e += blockDim.x) {
+    const int r = (int)(e / kc), i = (int)(e % kc);
+    if (i < l) {
+      const int src = perm[i];
+      const double sv = nrm[src];
+      Us[e] = sv > 0.0 ? M[(int64_t)src * l + r] / sv : 0.0;
+      W[e] = P[(int64_t)src * l + r];
+    } else {
+      Us[e] = 0.0;
+      W[e] = 0.0;
+    }
+  }
+  if (threadIdx.x == 0) {
+    bool zero = false;
+    for (int i = 0; i < l; i++) zero |= !(nrm[i] > 0.0);
+    if (zero) atomicOr(&st->flags, (uint32_t)RSVD_FLAG_ZERO_SIGMA);
+  }
+}
+
+// Rank rule (a single thread; l is small).
+__global__ void select_rank_kernel(int64_t l, int64_t p, int64_t kc, int mode, double param,
+                                   const double* __restrict__ s, DevState* st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int64_t k = 0;
+  uint32_t f = 0;
+  const int64_t cap = (l - p) > 1 ? (l - p) : 1;
+  if (mode == RSVD_RANK_FIXED) {
+    k = (int64_t)param;
+  } else if (mode == RSVD_RANK_REL_THRESHOLD) {
+    for (int64_t j = 0; j < l; j++) k += (s[j] >= param * s[0]) ? 1 : 0;
+    if (k > cap) { k = cap; f |= RSVD_FLAG_RANK_CAPPED; }
+  } else if (mode == RSVD_RANK_FROB_TAIL) {
+    double tot = 0.0;
+    for (int64_t j = 0; j < l; j++) tot += s[j] * s[j];
+    double missed = st->fro2 - tot;
+    if (missed < 0.0) missed = 0.0;
+    const double lim = param * sqrt(st->fro2);
+    // tail[k] = sum_{j >= k} s_j^2, accumulated from the small end
+    k = l;
+    double tail = 0.0;
+    int64_t best = l;
+    for (int64_t kk = l; kk >= 0; kk--) {
+      if (kk < l) tail += s[kk] * s[kk];
+      if (sqrt(tail + missed) <= lim) best = kk;
+    }
+    k = best;
+    if (k > cap) { k = cap; f |= RSVD_FLAG_RANK_CAPPED; }
+  }
+  if (k < 1) k = 1;
+  if (k > l) k = l;
+  if (k > kc) { k = kc; f |= RSVD_FLAG_RANK_CAPPED; }
+  st->rank = (int32_t)k;
+  st->flags |= f;
+}
+
+// Sign rule: flip (U_j, V_j) so the largest-magnitude entry of U_j is positive
+// (lowest row on ties). One workgroup per column.
+__global__ void __launch_bounds__(256) sign_fix_kernel(int64_t m, int64_t n, double* __restrict__ U,
+                                                       int64_t ldu, double* __restrict__ V,
+                                                       int64_t ldv) {
+  __shared__ double sv[4];
+  __shared__ int64_t si[4];
+  __shared__ double sgn;
+  const int64_t j = blockIdx.x;
+  double best = -1.0;
+  int64_t bi = 0;
+  for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
+    const double a = fabs(U[i * ldu + j]);
+    if (a > best) { best = a; bi = i; }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ob = __shfl_xor(best, off, 64);
+    const int64_t oi = __shfl_xor(bi, off, 64);
+    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) { sv[w] = best; si[w] = bi; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = sv[0];
+    int64_t ii = si[0];
+    for (int k = 1; k < (int)(blockDim.x >> 6); k++) {
+      if (sv[k] > b || (sv[k] == b && si[k] < ii)) { b = sv[k]; ii = si[k]; }
+    }
+    sgn = (U[ii * ldu + j] < 0.0) ? -1.0 : 1.0;
+  }
+  __syncthreads();
+  if (sgn < 0.0) {
+    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) U[i * ldu + j] = -U[i * ldu + j];
+    if (V)
+      for (int64_t i = threadIdx.x; i < n; i += blockDim.x) V[i * ldv + j] = -V[i * ldv + j];
+  }
+}
+
+// US = U diag(s) (columns >= rank zeroed), Vt = V^T (rows >= rank zeroed).
+__global__ void __launch_bounds__(256) resid_prep_kernel(int64_t m, int64_t n, int64_t kc,
+                                                         const double* __restrict__ U, int64_t ldu,
+                                                         const double* __restrict__ s,
+                                                         const double* __restrict__ V, int64_t ldv,
+                                                         double* __restrict__ US,
+                                                         double* __restrict__ Vt,
+                                                         const DevState* st) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t rank = st->rank;
+  if (idx < m * kc) {
+    const int64_t i = idx / kc, j = idx % kc;
+    US[idx] = j < rank ? U[i * ldu + j] * s[j] : 0.0;
+  }
+  if (idx < n * kc) {
+    const int64_t j = idx / n, i = idx % n;  // Vt is kc x n
+    Vt[idx] = j < rank ? V[i * ldv + j] : 0.0;
+  }
+}
+
+__global__ void __launch_bounds__(256) check_finite_kernel(int64_t rows, int64_t cols,
+                                                           const double* __restrict__ Y, int64_t ldy,
+                                                           DevState* st) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  bool bad = false;
+  if (idx < rows * cols) bad = !isfinite(Y[(idx / cols) * ldy + idx % cols]);
+  if (__any(bad) && (threadIdx.x & 63) == 0) atomicOr(&st->flags, (uint32_t)RSVD_FLAG_NONFINITE_INPUT);
+}
+
+__global__ void __launch_bounds__(256) sumsq_kernel(int64_t m, int64_t n,
+                                                    const double* __restrict__ A, int64_t lda,
+                                                    double* __restrict__ partial) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int64_t r = blockIdx.x; r < m; r += gridDim.x) {
+    for (int64_t c = threadIdx.x; c < n; c += blockDim.x) {
+      const double x = A[r * lda + c];
+      s += x * x;
+    }
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void __launch_bounds__(256) sum_partials_kernel(int64_t cnt, const double* __restrict__ p,
+                                                           double* __restrict__ out) {
+  __shared__ double red[4];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < cnt; i += blockDim.x) s += p[i];
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ void finalize_kernel(int64_t m, int64_t n, int64_t l, int want_residual,
+                                const DevState* st, rsvd_result* res) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int64_t k = st->rank;
+  const double N = (double)(m < n ? m : n);
+  res->rank = k;
+  res->l_used = l;
+  res->residual = want_residual ? sqrt(st->resid2) / sqrt(st->fro2) : __builtin_nan("");
+  res->rel_percent = 100.0 * (double)k / N;
+  res->c_eq2 = (double)m * (double)n / ((double)(m + n) * k + k);
+  res->c_sym = (double)m * (double)n / ((double)(m > n ? m : n) * k + k);
+  res->fro2 = st->fro2;
+  res->sweeps = st->sweeps;
+  res->flags = st->flags;
+}
+
+__global__ void init_state_kernel(DevState* st, uint32_t flags) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->flags = flags;
+    st->qr_shifted = 0;
+    st->qr_householder = 0;
+    st->sweeps = 0;
+    st->rank = 0;
+    st->fro2 = 0.0;
+    st->resid2 = 0.0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x < 64) st->rot_count[threadIdx.x] = 0;
+}
+
+__global__ void clear_shift_kernel(DevState* st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st->qr_shifted = 0;
+    st->qr_householder = 0;
+  }
+}
+
+__global__ void __launch_bounds__(256) transpose_kernel(int64_t rows, int64_t cols,
+                                                        const double* __restrict__ src, int64_t lds,
+                                                        double* __restrict__ dst, int64_t ldd) {
+  __shared__ double tile[32][33];
+  const int64_t r0 = (int64_t)blockIdx.y * 32, c0 = (int64_t)blockIdx.x * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int k = 0; k < 32; k += 8) {
+    const int64_t r = r0 + ty + k, c = c0 + tx;
+    if (r < rows && c < cols) tile[ty + k][tx] = src[r * lds + c];
+  }
+  __syncthreads();
+  for (int k = 0; k < 32; k += 8) {
+    const int64_t c = c0 + ty + k, r = r0 + tx;  // dst[c][r] = src[r][c]
+    if (r < rows && c < cols) dst[c * ldd + r] = tile[tx][ty + k];
+  }
+}
+
+inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// Allow the single-workgroup kernels the full 160 KB of LDS of a gfx950 CU.
+void allow_big_lds() {
+  static bool done = false;
+  if (done) return;
+  done = true;
+  (void)hipFuncSetAttribute((const void*)chol_inv_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+  (void)hipFuncSetAttribute((const void*)jacobi_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+}
+
+}  // namespace
+
+rsvd_status chol_inv(int64_t l, const double* G, double* R, double* Rinv, int64_t m, int pass,
+                     int only_if_shifted, DevState* st, hipStream_t s) {
+  allow_big_lds();
+  const size_t need = (size_t)l * l * 2 * sizeof(double);
+  const size_t shm = need <= 150 * 1024 ? need : 0;
+  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(kBig), shm, s, (int)l, G, R, Rinv, m, pass,
+                     only_if_shifted, st);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status householder_fallback(int64_t rows, int64_t l, const double* Yorig, double* Y,
+                                 double* R, double* tau, DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(householder_kernel, dim3(1), dim3(kBig), 0, s, rows, (int)l, Yorig, Y, R,
+                     tau, st);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status copy_panel(int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst,
+                       int64_t ldd, int cond_shifted, DevState* st, hipStream_t s) {
+  if (rows * cols == 0) return RSVD_OK;
+  hipLaunchKernelGGL(copy_panel_kernel, dim3(blocks_for(rows * cols, 256)), dim3(256), 0, s, rows,
+                     cols, src, lds, dst, ldd, cond_shifted, (const DevState*)st);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status jacobi_rows(int64_t l, double* M, double* P, int max_sweeps, DevState* st,
+                        hipStream_t s) {
+  allow_big_lds();
+  const size_t need = (size_t)l * l * 2 * sizeof(double);
+  const size_t shm = need <= 150 * 1024 ? need : 0;
+  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kBig), shm, s, (int)l, M, P, max_sweeps, st);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status set_identity(int64_t l, double* P, hipStream_t s) {
+  hipLaunchKernelGGL(identity_kernel, dim3(blocks_for(l * l, 256)), dim3(256), 0, s, l, P);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status svd_finish(int64_t l, int64_t kc, const double* M, const double* P, double* sv,
+                       double* Us, double* W, DevState* st, hipStream_t s) {
+  const size_t shm = (size_t)l * (sizeof(double) + sizeof(int));
+  hipLaunchKernelGGL(svd_finish_kernel, dim3(1), dim3(kBig), shm, s, (int)l, (int)kc, M, P, sv, Us,
+                     W, st);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status select_rank(int64_t l, int64_t p, int64_t kc, int mode, double param,
+                        const double* sv, DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(select_rank_kernel, dim3(1), dim3(64), 0, s, l, p, kc, mode, param, sv, st);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status sign_fix(int64_t m, int64_t n, int64_t kc, double* U, int64_t ldu, double* V,
+                     int64_t ldv, hipStream_t s) {
+  if (kc == 0) return RSVD_OK;
+  hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)kc), dim3(256), 0, s, m, n, U, ldu, V, ldv);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status resid_prep(int64_t m, int64_t n, int64_t kc, const double* U, int64_t ldu,
+                       const double* sv, const double* V, int64_t ldv, double* US, double* Vt,
+                       const DevState* st, hipStream_t s) {
+  const int64_t tot = (m > n ? m : n) * kc;
+  hipLaunchKernelGGL(resid_prep_kernel, dim3(blocks_for(tot, 256)), dim3(256), 0, s, m, n, kc, U,
+                     ldu, sv, V, ldv, US, Vt, st);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status check_finite(int64_t rows, int64_t cols, const double* Y, int64_t ldy, DevState* st,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(check_finite_kernel, dim3(blocks_for(rows * cols, 256)), dim3(256), 0, s,
+                     rows, cols, Y, ldy, st);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status sumsq(int64_t m, int64_t n, const double* A, int64_t lda, double* partial,
+                  DevState* st, hipStream_t s) {
+  const int nb = 2048;
+  hipLaunchKernelGGL(sumsq_kernel, dim3(nb), dim3(256), 0, s, m, n, A, lda, partial);
+  RSVD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, (int64_t)nb,
+                     (const double*)partial, &st->fro2);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status sum_partials_into(int64_t cnt, const double* p, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, s, cnt, p, out);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status finalize(int64_t m, int64_t n, int64_t l, int want_residual, const DevState* st,
+                     rsvd_result* res, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, s, m, n, l, want_residual, st, res);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status init_state(DevState* st, uint32_t flags, hipStream_t s) {
+  hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, s, st, flags);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status clear_shift(DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(clear_shift_kernel, dim3(1), dim3(64), 0, s, st);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status transpose(int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst,
+                      int64_t ldd, hipStream_t s) {
+  if (rows == 0 || cols == 0) return RSVD_OK;
+  dim3 grid(blocks_for(cols, 32), blocks_for(rows, 32));
+  hipLaunchKernelGGL(transpose_kernel, grid, dim3(256), 0, s, rows, cols, src, lds, dst, ldd);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+}  // namespace rsvd

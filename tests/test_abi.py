@@ -1,0 +1,103 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and rsvd_plan validates problems (no device needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2307_15572_amd as rs
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "rsvd.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rsvd_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_header_symbols_exported():
+    L = rs.lib()
+    names = _declared()
+    assert "rsvd_run" in names and "rsvd_plan" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(rs.EXPORTED)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    # compile a C probe of the header and compare every field offset with ctypes
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc") or shutil.which("cc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', 'int main(void) {']
+    for cname, cls in (("rsvd_problem", rs.Problem), ("rsvd_result", rs.Result)):
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in cls._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run([gcc, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line:
+            a, b, c = line.split()
+            got[(a, b)] = int(c)
+    for cname, cls in (("rsvd_problem", rs.Problem), ("rsvd_result", rs.Result)):
+        assert got[(cname, "size")] == ctypes.sizeof(cls)
+        for f, _ in cls._fields_:
+            assert got[(cname, f)] == getattr(cls, f).offset, (cname, f)
+
+
+def _plan(**kw):
+    base = dict(m=100, n=80, k=10, p=5, q=1)
+    base.update(kw)
+    m, n, k, p, q = (base.pop(x) for x in ("m", "n", "k", "p", "q"))
+    return rs.Plan(m, n, k, p, q, **base)
+
+
+def test_plan_sizes_and_clamp():
+    pl = _plan()
+    assert pl.l == 15 and pl.workspace_bytes > 0
+    pl2 = _plan(m=20, n=12, k=10, p=5)  # l clamps to min(m, n)
+    assert pl2.l == 12
+    pl3 = _plan(rank_mode="percent", rank_param=10.0)  # ceil(8.0) = 8 -> l = 13
+    assert pl3.l == 13
+
+
+@pytest.mark.parametrize("kw", [
+    dict(m=0), dict(n=0), dict(k=0), dict(p=-1), dict(q=-1),
+    dict(rank_mode="percent", rank_param=0.0), dict(rank_mode="percent", rank_param=150.0),
+    dict(rank_mode="rel_threshold", rank_param=1.5), dict(rank_mode="rel_threshold", rank_param=0.0),
+    dict(symmetric=True), dict(k_cap=3),
+])
+def test_plan_rejects_invalid(kw):
+    with pytest.raises(rs.RsvdError, match="invalid"):
+        _plan(**kw)
+
+
+def test_strerror_and_unsupported():
+    L = rs.lib()
+    assert L.rsvd_strerror(0) == b"ok"
+    assert L.rsvd_strerror(2) == b"workspace too small"
+    assert L.rsvd_strerror(99) == b"unknown status"
+
+
+def test_run_rejects_null_and_small_workspace():
+    L = rs.lib()
+    pl = _plan()
+    null = ctypes.c_void_p(0)
+    st = L.rsvd_run(pl._h, null, 80, null, 0, null, null, 0, null, 0, null, null, 0, null)
+    assert st == rs.RSVD_EINVAL
+    fake = ctypes.c_void_p(256)  # never dereferenced: validation fails first
+    st = L.rsvd_run(pl._h, fake, 80, null, 0, fake, fake, 15, fake, 15, fake, fake, 10, null)
+    assert st == rs.RSVD_ENOMEM
+    st = L.rsvd_run(pl._h, fake, 79, null, 0, fake, fake, 15, fake, 15, fake, fake, 10**12, null)
+    assert st == rs.RSVD_EINVAL  # lda < n

@@ -1,0 +1,127 @@
+"""Per-kernel parity on the GPU: projection P, FP64 GEMM, QR, small SVD."""
+
+import numpy as np
+import pytest
+
+from oracle.philox import gaussian_omega as oracle_omega
+from oracle.method import orth as oracle_orth
+import synth
+
+from gpu_util import announce, to_dev
+
+pytestmark = pytest.mark.gpu
+
+U_EPS = 2.0 ** -53
+
+
+@pytest.mark.parametrize("n,l,col0,seed,ch", [(1000, 50, 0, 2001, 0), (37, 13, 5, 7, 3),
+                                                (4096, 272, 0, 2002, 0), (1, 1, 0, 0, 0)])
+def test_omega_matches_oracle(n, l, col0, seed, ch):
+    import paper_2307_15572_amd as rs
+    announce(f"omega n={n} l={l} col0={col0}")
+    g = rs.gaussian_omega(n, l, seed, ch, col0=col0).cpu().numpy()
+    ref = oracle_omega(n, l, seed, ch, col0=col0)
+    # same Philox words; transcendental functions may differ by an ulp or two
+    assert np.all(np.abs(g - ref) <= 8 * U_EPS * (np.abs(ref) + 1.0))
+
+
+GEMM_CASES = [
+    (False, 64, 16, 16), (False, 1, 1, 1), (False, 130, 50, 77), (False, 517, 272, 1000),
+    (False, 300, 528, 257), (False, 2048, 272, 8192), (False, 64, 300, 20000),
+    (True, 50, 50, 512), (True, 272, 272, 16384), (True, 1000, 33, 999), (True, 40, 7, 3),
+]
+
+
+@pytest.mark.parametrize("ta,m,n,k", GEMM_CASES)
+def test_dgemm_matches_numpy(ta, m, n, k):
+    import paper_2307_15572_amd as rs
+    announce(f"dgemm ta={ta} m={m} n={n} k={k}")
+    rng = np.random.default_rng(m * 7 + n * 3 + k)
+    A = rng.standard_normal((k, m) if ta else (m, k))
+    B = rng.standard_normal((k, n))
+    C0 = rng.standard_normal((m, n))
+    ref = (A.T if ta else A) @ B
+    got = rs.dgemm(to_dev(A), to_dev(B), trans_a=ta).cpu().numpy()
+    # componentwise FP64 error bound for a k-term dot product
+    scale = (np.abs(A.T if ta else A) @ np.abs(B))
+    assert np.all(np.abs(got - ref) <= 2 * k * U_EPS * scale + 1e-300)
+    got2 = rs.dgemm(to_dev(A), to_dev(B), trans_a=ta, alpha=-0.5, beta=2.0, C=to_dev(C0)).cpu().numpy()
+    ref2 = -0.5 * ref + 2.0 * C0
+    assert np.all(np.abs(got2 - ref2) <= 2 * k * U_EPS * (0.5 * scale + 2 * np.abs(C0)) + 1e-300)
+
+
+@pytest.mark.parametrize("m,l,decay", [(500, 50, 1 / 16), (4096, 272, 1 / 40), (3000, 100, 1 / 8),
+                                       (200, 200, 1 / 64), (20, 1, 0.1)])
+def test_orth_matches_oracle(m, l, decay):
+    import paper_2307_15572_amd as rs
+    announce(f"orth m={m} l={l} decay={decay}")
+    rng = np.random.default_rng(m + l)
+    # panel with graded columns: condition number about 10^(decay * l)
+    U = synth.haar_columns(m, l, rng)
+    V = synth.haar_columns(l, l, rng)
+    Y = (U * (10.0 ** (-decay * np.arange(l)))) @ V.T
+    Q, X, flags = rs.orth(to_dev(Y))
+    Q = Q.cpu().numpy()
+    X = X.cpu().numpy()
+    assert np.abs(Q.T @ Q - np.eye(l)).max() <= 20 * l * U_EPS
+    assert np.abs(Q @ X - Y).max() <= 50 * l * U_EPS * np.abs(Y).max()
+    assert np.all(np.diag(X) > 0) and np.allclose(np.tril(X, -1), 0)
+    # diag(R) > 0 makes Q unique: compare with the oracle's Householder Q
+    Qref = oracle_orth(Y)
+    kappa = 10.0 ** (decay * (l - 1))
+    assert np.abs(Q - Qref).max() <= 1e3 * kappa * U_EPS + 1e-12
+
+
+def test_orth_numerically_rank_deficient():
+    # rank-6 product: the shifted three-pass Cholesky QR still returns an
+    # orthonormal Q whose span contains the panel (noise directions complete it)
+    import paper_2307_15572_amd as rs
+    announce("orth numerically rank-deficient 300 x 40 (rank 6)")
+    rng = np.random.default_rng(5)
+    Y = rng.standard_normal((300, 6)) @ rng.standard_normal((6, 40))
+    Q, X, flags = rs.orth(to_dev(Y))
+    Q = Q.cpu().numpy()
+    X = X.cpu().numpy()
+    assert np.abs(Q.T @ Q - np.eye(40)).max() <= 1e-12
+    assert np.abs(Q @ X - Y).max() <= 1e-12 * np.abs(Y).max()
+
+
+def test_orth_exactly_rank_deficient_uses_householder():
+    # exactly zero columns make every Cholesky pass break down: Householder QR
+    import paper_2307_15572_amd as rs
+    announce("orth exact zero columns 300 x 40")
+    rng = np.random.default_rng(6)
+    Y = rng.standard_normal((300, 40))
+    Y[:, 25:] = 0.0
+    Q, X, flags = rs.orth(to_dev(Y))
+    Q = Q.cpu().numpy()
+    X = X.cpu().numpy()
+    assert flags & rs.FLAG_QR_FALLBACK
+    assert np.abs(Q.T @ Q - np.eye(40)).max() <= 1e-13
+    assert np.abs(Q @ X - Y).max() <= 1e-13 * np.abs(Y).max()
+    assert np.all(np.diag(X) >= 0) and np.allclose(np.tril(X, -1), 0)
+    # the first 25 columns are the unique QR of the nonzero part
+    assert np.abs(Q[:, :25] - oracle_orth(Y[:, :25])).max() <= 1e-12
+
+
+@pytest.mark.parametrize("l,decay", [(50, 1 / 16), (272, 1 / 40), (17, 0.5), (1, 0.0), (128, 1 / 20)])
+def test_small_svd_matches_lapack(l, decay):
+    import paper_2307_15572_amd as rs
+    announce(f"small_svd l={l}")
+    rng = np.random.default_rng(l)
+    U = synth.haar_columns(l, l, rng)
+    V = synth.haar_columns(l, l, rng)
+    sig = 10.0 ** (-decay * np.arange(l))
+    R = np.triu(np.linalg.qr((U * sig) @ V.T)[1])
+    s, Us, W, sweeps, flags = rs.small_svd(to_dev(R))
+    s = s.cpu().numpy()
+    Us = Us.cpu().numpy()
+    W = W.cpu().numpy()
+    assert not (flags & rs.FLAG_JACOBI_MAXSWEEP)
+    ref = np.linalg.svd(R, compute_uv=False)
+    assert np.all(np.abs(s - ref) <= 1e-13 * ref[0] + 1e-12 * ref)
+    assert np.all(np.diff(s) <= 0)
+    # R^T = Us diag(s) W^T with orthonormal Us, W
+    assert np.abs(R.T - (Us * s) @ W.T).max() <= 1e-13 * ref[0] * max(1, l / 10)
+    assert np.abs(Us.T @ Us - np.eye(l)).max() <= 1e-12
+    assert np.abs(W.T @ W - np.eye(l)).max() <= 1e-12

@@ -1,0 +1,156 @@
+"""End-to-end parity of the HIP randomized SVD with the CPU FP64 oracle
+(same projection P, same p, q and QR-after-every-product schedule).
+
+Gate (FP64): |ds_j| <= 1e-10 s_j + 1e-13 s_1 for every kept j, and
+|de| <= 1e-10 e + 1e-13 for the residual e = ||A - U S V^T||_F / ||A||_F.
+The absolute floors follow from Weyl's inequality: rounding A's products by
+u ||A||_2 poly(n) moves every singular value by at most that much.
+Singular vectors are compared up to sign where the gap to the neighbours is
+large enough for them to be determined (tolerance ~ u s_1 / gap)."""
+
+import numpy as np
+import pytest
+
+import synth
+from oracle.method import rsvd as oracle_rsvd
+
+from gpu_util import announce, sigma_gate, to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _vec_tol(s_all, j):
+    gaps = []
+    if j > 0:
+        gaps.append(s_all[j - 1] - s_all[j])
+    if j + 1 < len(s_all):
+        gaps.append(s_all[j] - s_all[j + 1])
+    gap = min(gaps) if gaps else s_all[0]
+    return 1e-12 * s_all[0] / max(gap, 1e-300) + 1e-12
+
+
+def run_both(A, k, p, q, seed, *, symmetric=False, rank_mode="fixed", rank_param=None, omega=None,
+             check_vectors=True, **kw):
+    import paper_2307_15572_amd as rs
+    ref = oracle_rsvd(A, k, p, q, seed=seed, symmetric=symmetric, rank_mode=rank_mode,
+                      rank_param=rank_param, omega=omega)
+    out = rs.run(to_dev(A), k, p, q, seed=seed, symmetric=symmetric, rank_mode=rank_mode,
+                 rank_param=rank_param, omega=to_dev(omega) if omega is not None else None, **kw)
+    s = out.S.cpu().numpy()
+    kk = min(out.rank, ref.rank)
+    ok, worst = sigma_gate(s[:kk], ref.s[:kk])
+    assert ok, f"sigma gate failed: worst ratio {worst:.3g}"
+    assert abs(out.residual - ref.residual) <= 1e-10 * ref.residual + 1e-13, (out.residual, ref.residual)
+    assert out.l == ref.l
+    assert abs(out.rel_percent - ref.rel_percent) < 1e-12 * 100 or out.rank != ref.rank
+    if check_vectors:
+        U = out.U.cpu().numpy()
+        V = out.V.cpu().numpy()
+        # the sign rule holds on the GPU output itself
+        idx = np.argmax(np.abs(U), axis=0)
+        assert np.all(U[idx, np.arange(U.shape[1])] > 0)
+        for j in range(kk):
+            tol = _vec_tol(ref.s_all, j)
+            if tol > 1e-6:
+                continue  # (nearly) degenerate: the vector is not determined
+            du = min(np.abs(U[:, j] - ref.U[:, j]).max(), np.abs(U[:, j] + ref.U[:, j]).max())
+            dv = min(np.abs(V[:, j] - ref.V[:, j]).max(), np.abs(V[:, j] + ref.V[:, j]).max())
+            assert du <= tol and dv <= tol, (j, du, dv, tol)
+    return out, ref
+
+
+def test_c1_workload():
+    A, sigma, w = synth.c1()
+    announce(f"pipeline {w.name} k={w.k} p={w.p} q={w.q}")
+    out, ref = run_both(A, w.k, w.p, w.q, w.seed)
+    assert out.rank == w.k and out.l == w.k + w.p
+    # the constructed spectrum is reached where the sketch has converged
+    assert abs(out.S.cpu().numpy()[0] - sigma[0]) <= 1e-12
+
+
+@pytest.mark.parametrize("m,n,k,p,q,decay", [
+    (300, 170, 23, 7, 1, 1 / 10),      # ragged tiles in every dimension
+    (200, 700, 30, 10, 2, 1 / 20),     # wide
+    (3000, 400, 64, 16, 3, 1 / 64),    # tall, C3-like spectrum
+    (1000, 1000, 100, 20, 0, 1 / 30),  # q = 0: the paper's method exactly
+])
+def test_general_shapes(m, n, k, p, q, decay):
+    announce(f"pipeline general {m}x{n} k={k} p={p} q={q}")
+    sig = synth.spectrum_pow10(min(m, n), decay)
+    A = synth.general(m, n, sig, tag=300 + m + n)
+    run_both(A, k, p, q, seed=m * n)
+
+
+def test_symmetric_scaled_c2():
+    n = 2048
+    announce(f"pipeline symmetric {n} (C2 spectrum and noise)")
+    A, sigma, w = synth.c2(n=n)
+    out, ref = run_both(A, 256, 16, 2, 2002, symmetric=True)
+    assert out.l == 272
+
+
+@pytest.mark.parametrize("m,n,k,p", [(60, 40, 35, 10), (1, 1, 1, 0), (2, 3, 1, 5), (5, 1, 1, 1),
+                                     (17, 17, 16, 1)])
+def test_full_and_tiny(m, n, k, p):
+    import paper_2307_15572_amd as rs
+    announce(f"pipeline tiny/full {m}x{n} k={k} p={p}")
+    sig = synth.spectrum_pow10(min(m, n), 0.2)
+    A = synth.general(m, n, sig, tag=400 + m * 7 + n)
+    out, ref = run_both(A, k, p, 1, seed=3)
+    if out.l == min(m, n):
+        assert out.flags & rs.FLAG_FULL_SVD
+
+
+def test_threshold_percent_frobtail_rules():
+    n, d = 800, 20.0
+    sig = synth.spectrum_exp(n, d)
+    A = synth.symmetric(n, sig, tag=501)
+    announce("rank rule rel_threshold")
+    out, ref = run_both(A, 300, 32, 2, 9, symmetric=True, rank_mode="rel_threshold", rank_param=1e-6,
+                        check_vectors=False)
+    # threshold ties: a value within the sigma gate of tau s_1 may fall either way
+    s = ref.s_all
+    near = np.abs(s - 1e-6 * s[0]) <= 1e-10 * s + 1e-13 * s[0]
+    assert out.rank == ref.rank or near.any()
+    announce("rank rule percent")
+    run_both(A, 0, 16, 2, 9, symmetric=True, rank_mode="percent", rank_param=5.0, check_vectors=False)
+    announce("rank rule frob_tail")
+    out, ref = run_both(A, 300, 32, 2, 9, symmetric=True, rank_mode="frob_tail", rank_param=1e-4,
+                        check_vectors=False)
+    assert out.rank == ref.rank
+
+
+def test_exact_low_rank_on_gpu():
+    import paper_2307_15572_amd as rs
+    announce("pipeline exact rank 5")
+    A, s = synth.rank_r(120, 90, 5, tag=104, scale=3.0)
+    out = rs.run(to_dev(A), 10, 5, 1, seed=3)
+    S = out.S.cpu().numpy()
+    assert np.all(np.abs(S[:5] - s) <= 1e-13 * s[0])
+    assert np.all(S[5:] <= 1e-13 * s[0])
+    assert out.residual <= 1e-13
+
+
+def test_caller_omega_and_determinism():
+    import paper_2307_15572_amd as rs
+    from oracle.philox import gaussian_omega
+    announce("caller omega / determinism")
+    sig = synth.spectrum_exp(400, 12.0)
+    A = synth.general(500, 400, sig, tag=601)
+    om = np.random.default_rng(1).standard_normal((400, 40))
+    run_both(A, 30, 10, 2, seed=0, omega=om)
+    o1 = rs.run(to_dev(A), 30, 10, 2, seed=44)
+    o2 = rs.run(to_dev(A), 30, 10, 2, seed=44)
+    assert np.array_equal(o1.S.cpu().numpy(), o2.S.cpu().numpy())
+    assert np.array_equal(o1.U.cpu().numpy(), o2.U.cpu().numpy())
+    o3 = rs.run(to_dev(A), 30, 10, 2, omega=to_dev(gaussian_omega(400, 40, 44)))
+    assert np.max(np.abs(o3.S.cpu().numpy() - o1.S.cpu().numpy())) <= 1e-13
+
+
+def test_nonfinite_input_raises():
+    import paper_2307_15572_amd as rs
+    announce("non-finite input")
+    A = np.ones((50, 40))
+    A[7, 3] = np.nan
+    with pytest.raises(rs.RsvdError, match="NaN"):
+        rs.run(to_dev(A), 5, 5, 1)
