@@ -64,7 +64,7 @@ enum {
 enum {
   RSVD_FLAG_FULL_SVD = 1u << 0,        /* l = min(m, n): the result is an exact SVD  */
   RSVD_FLAG_RANK_CAPPED = 1u << 1,     /* rank rule wanted more than l - p or k_cap  */
-  RSVD_FLAG_QR_FALLBACK = 1u << 2,     /* a Cholesky QR broke down; shifted pass used */
+  RSVD_FLAG_QR_FALLBACK = 1u << 2,     /* Cholesky QR broke down (rank-deficient panel): Householder QR used */
   RSVD_FLAG_JACOBI_MAXSWEEP = 1u << 3, /* small SVD stopped at max_sweeps            */
   RSVD_FLAG_NONFINITE_INPUT = 1u << 4, /* A holds NaN or Inf                         */
   RSVD_FLAG_ZERO_SIGMA = 1u << 5       /* a singular value is exactly zero           */
@@ -190,6 +190,22 @@ size_t rsvd_small_svd_work_bytes(int64_t l);
 rsvd_status rsvd_small_svd(int64_t l, const double* R, double* s, double* Us, double* W,
                            int32_t max_sweeps, int32_t* sweeps, uint32_t* flags,
                            void* work, size_t work_bytes, void* stream);
+
+/*
+ * Phase trace (measurement aid). When enabled, rsvd_run records a HIP event
+ * pair on its stream around every launch group of a phase; the events are
+ * kept on the host until collected. Not thread-safe: one tracing caller at a
+ * time. Phases:
+ *   0 streaming products with A (sketch, power iterations, projection)
+ *   1 QR of the panels    2 small SVD (Jacobi + ordering)   3 lift + signs
+ *   4 residual pass       5 projection P                    6 everything else
+ */
+#define RSVD_TRACE_PHASES 7
+void rsvd_trace_enable(int32_t on);
+/* Synchronize on the recorded events, add their durations per phase into
+ * ms[RSVD_TRACE_PHASES] and counts[RSVD_TRACE_PHASES] (host arrays), and
+ * clear the record. Returns RSVD_EHIP if an event query fails. */
+rsvd_status rsvd_trace_collect(double* ms, int64_t* counts);
 
 #ifdef __cplusplus
 }

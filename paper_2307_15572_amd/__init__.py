@@ -28,7 +28,9 @@ EXPORTED = (
     "rsvd_plan", "rsvd_plan_l", "rsvd_run", "rsvd_destroy", "rsvd_strerror",
     "rsvd_gaussian_omega", "rsvd_dgemm_work_bytes", "rsvd_dgemm",
     "rsvd_orth_work_bytes", "rsvd_orth", "rsvd_small_svd_work_bytes", "rsvd_small_svd",
+    "rsvd_trace_enable", "rsvd_trace_collect",
 )
+TRACE_PHASES = ("stream_gemm", "qr", "small_svd", "lift_signs", "residual", "omega", "other")
 
 
 class RsvdError(RuntimeError):
@@ -95,6 +97,10 @@ def lib():
     L.rsvd_small_svd_work_bytes.restype = sz
     L.rsvd_small_svd.argtypes = [i64, vp, vp, vp, vp, i32, vp, vp, vp, sz, vp]
     L.rsvd_small_svd.restype = ctypes.c_int
+    L.rsvd_trace_enable.argtypes = [i32]
+    L.rsvd_trace_enable.restype = None
+    L.rsvd_trace_collect.argtypes = [ctypes.POINTER(dbl), ctypes.POINTER(i64)]
+    L.rsvd_trace_collect.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -314,3 +320,17 @@ def small_svd(R, max_sweeps=0):
     torch.cuda.synchronize(R.device)
     del buf
     return s, Us, W, int(sw.item()), int(fl.item()) & 0xFFFFFFFF
+
+
+def trace_enable(on=True):
+    """Record HIP event pairs around each phase of subsequent runs."""
+    lib().rsvd_trace_enable(int(bool(on)))
+
+
+def trace_collect():
+    """Per-phase (total ms, launch groups) since the last collect."""
+    n = len(TRACE_PHASES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    _check(lib().rsvd_trace_collect(ms, cnt), "rsvd_trace_collect")
+    return {TRACE_PHASES[i]: (ms[i], cnt[i]) for i in range(n)}

@@ -19,11 +19,55 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <vector>
 
 #include "common.hpp"
 #include "kernels.hpp"
 
 using namespace rsvd;
+
+namespace {
+
+// ---- phase trace ------------------------------------------------------------
+struct TraceMark {
+  int phase;
+  hipEvent_t a, b;
+};
+bool g_trace_on = false;
+std::vector<TraceMark> g_marks;
+std::vector<hipEvent_t> g_event_pool;
+
+hipEvent_t trace_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// RAII scope: records an event pair around the launches of one phase.
+struct PhaseScope {
+  int phase;
+  hipStream_t s;
+  hipEvent_t a = nullptr;
+  PhaseScope(int ph, hipStream_t st) : phase(ph), s(st) {
+    if (!g_trace_on) return;
+    a = trace_event();
+    if (a) (void)hipEventRecord(a, s);
+  }
+  ~PhaseScope() {
+    if (!a) return;
+    hipEvent_t b = trace_event();
+    if (!b) return;
+    (void)hipEventRecord(b, s);
+    g_marks.push_back({phase, a, b});
+  }
+};
+
+}  // namespace
 
 struct rsvd_plan_s {
   rsvd_problem p;
@@ -273,38 +317,57 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
   const double* Om = omega;
   int64_t ldom = ldo;
   if (!Om) {
+    PhaseScope ph(5, s);
     RSVD_TRY(gaussian_omega(n, l, 0, p.seed, p.channel, Z, l, s));
     Om = Z;
     ldom = l;
   }
-  RSVD_TRY(dgemm(false, m, l, n, 1.0, A, lda, Om, ldom, 0.0, Y, l, part, pl.part_doubles, s));
+  auto stream_pass = [&](bool trans, const double* X, int64_t ldx, double* out, int64_t rows_out,
+                         int64_t inner) -> rsvd_status {
+    PhaseScope ph(0, s);
+    return dgemm(trans, rows_out, l, inner, 1.0, A, lda, X, ldx, 0.0, out, l, part,
+                 pl.part_doubles, s);
+  };
+  auto qr = [&](int64_t rows, double* panel, double* Rout) -> rsvd_status {
+    PhaseScope ph(1, s);
+    return orth(pl, w, rows, panel, Rout, s);
+  };
+  RSVD_TRY(stream_pass(false, Om, ldom, Y, m, n));
   RSVD_TRY(check_finite(m, l, Y, l, st, s));
-  RSVD_TRY(orth(pl, w, m, Y, nullptr, s));
+  RSVD_TRY(qr(m, Y, nullptr));
   // power iterations
   for (int t = 0; t < p.power_iters; t++) {
-    RSVD_TRY(dgemm(!p.symmetric, n, l, m, 1.0, A, lda, Y, l, 0.0, Z, l, part, pl.part_doubles, s));
-    RSVD_TRY(orth(pl, w, n, Z, nullptr, s));
-    RSVD_TRY(dgemm(false, m, l, n, 1.0, A, lda, Z, l, 0.0, Y, l, part, pl.part_doubles, s));
-    RSVD_TRY(orth(pl, w, m, Y, nullptr, s));
+    RSVD_TRY(stream_pass(!p.symmetric, Y, l, Z, n, m));
+    RSVD_TRY(qr(n, Z, nullptr));
+    RSVD_TRY(stream_pass(false, Z, l, Y, m, n));
+    RSVD_TRY(qr(m, Y, nullptr));
   }
   // step 2: Y^T = A^T Q = Q_B X_B, small SVD of X_B^T
-  RSVD_TRY(dgemm(!p.symmetric, n, l, m, 1.0, A, lda, Y, l, 0.0, Z, l, part, pl.part_doubles, s));
-  RSVD_TRY(orth(pl, w, n, Z, Rt, s));
-  RSVD_TRY(copy_panel(l, l, Rt, l, Mj, l, 0, st, s));
-  RSVD_TRY(set_identity(l, Pj, s));
-  RSVD_TRY(jacobi_rows(l, Mj, Pj, p.max_sweeps > 0 ? p.max_sweeps : 30, st, s));
-  RSVD_TRY(svd_finish(l, kc, Mj, Pj, sig, Us, W, st, s));
+  RSVD_TRY(stream_pass(!p.symmetric, Y, l, Z, n, m));
+  RSVD_TRY(qr(n, Z, Rt));
+  {
+    PhaseScope ph(2, s);
+    RSVD_TRY(copy_panel(l, l, Rt, l, Mj, l, 0, st, s));
+    RSVD_TRY(set_identity(l, Pj, s));
+    RSVD_TRY(jacobi_rows(l, Mj, Pj, p.max_sweeps > 0 ? p.max_sweeps : 30, st, s));
+    RSVD_TRY(svd_finish(l, kc, Mj, Pj, sig, Us, W, st, s));
+  }
   if (pl.mode == RSVD_RANK_FROB_TAIL) {
+    PhaseScope ph(6, s);
     RSVD_TRY(sumsq(m, n, A, lda, part, st, s));
   }
   RSVD_TRY(select_rank(l, p.oversample, kc, pl.mode, pl.param, sig, st, s));
   // step 3: L = Q L_Y, R = Q_B W
-  RSVD_TRY(dgemm(false, m, kc, l, 1.0, Y, l, Us, kc, 0.0, Uo, lduo, part, pl.part_doubles, s));
-  RSVD_TRY(dgemm(false, n, kc, l, 1.0, Z, l, W, kc, 0.0, Vo, ldvo, part, pl.part_doubles, s));
-  RSVD_TRY(sign_fix(m, n, kc, Uo, lduo, Vo, ldvo, s));
+  {
+    PhaseScope ph(3, s);
+    RSVD_TRY(dgemm(false, m, kc, l, 1.0, Y, l, Us, kc, 0.0, Uo, lduo, part, pl.part_doubles, s));
+    RSVD_TRY(dgemm(false, n, kc, l, 1.0, Z, l, W, kc, 0.0, Vo, ldvo, part, pl.part_doubles, s));
+    RSVD_TRY(sign_fix(m, n, kc, Uo, lduo, Vo, ldvo, s));
+  }
   if (hipMemcpyAsync(S, sig, (size_t)kc * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
     return RSVD_EHIP;
   if (p.want_residual) {
+    PhaseScope ph(4, s);
     double* US = w.at<double>(pl.off_US);
     double* Vt = w.at<double>(pl.off_Vt);
     RSVD_TRY(resid_prep(m, n, kc, Uo, lduo, sig, Vo, ldvo, US, Vt, st, s));
@@ -430,6 +493,25 @@ rsvd_status rsvd_small_svd(int64_t l, const double* R, double* sv, double* Us, d
     return RSVD_EHIP;
   return RSVD_OK;
 #undef RSVD_TRY
+}
+
+void rsvd_trace_enable(int32_t on) { g_trace_on = on != 0; }
+
+rsvd_status rsvd_trace_collect(double* ms, int64_t* counts) {
+  rsvd_status st = RSVD_OK;
+  for (auto& mk : g_marks) {
+    float t = 0.0f;
+    if (hipEventSynchronize(mk.b) != hipSuccess || hipEventElapsedTime(&t, mk.a, mk.b) != hipSuccess) {
+      st = RSVD_EHIP;
+    } else if (mk.phase >= 0 && mk.phase < RSVD_TRACE_PHASES) {
+      if (ms) ms[mk.phase] += t;
+      if (counts) counts[mk.phase] += 1;
+    }
+    g_event_pool.push_back(mk.a);
+    g_event_pool.push_back(mk.b);
+  }
+  g_marks.clear();
+  return st;
 }
 
 }  // extern "C"

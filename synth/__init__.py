@@ -74,8 +74,7 @@ def _product(U, s, V, device):
     import torch
     Ut = torch.from_numpy(U * s[None, :]).to(device)
     Vt = torch.from_numpy(np.ascontiguousarray(V.T)).to(device)
-    out = (Ut @ Vt).cpu().numpy()
-    return out
+    return (Ut @ Vt).cpu().numpy()
 
 
 def general(m, n, sigma, tag, channel=0, noise=0.0, device=None):
@@ -92,21 +91,37 @@ def general(m, n, sigma, tag, channel=0, noise=0.0, device=None):
 
 
 def symmetric(n, sigma, tag, channel=0, noise=0.0, device=None):
-    """A = U diag(sigma) U^T + noise (G + G^T)/sqrt(2), mirrored from the upper triangle."""
+    """A = U diag(sigma) U^T + noise (G + G^T)/sqrt(2), symmetrized from the upper
+    triangle so that A == A^T bitwise."""
     sigma = effective(np.asarray(sigma, np.float64)[:n])
     r = len(sigma)
     rng = _rng(tag, channel)
     U = haar_columns(n, r, rng)
-    A = _product(U, sigma, U, device)
+    G = rng.standard_normal((n, n)) if noise else None
+    if device is None or device == "cpu":
+        A = (U * sigma[None, :]) @ U.T
+        if noise:
+            G += G.T
+            G *= noise / math.sqrt(2.0)
+            A += G
+            del G
+        A = np.triu(A)
+        A += np.triu(A, 1).T
+        return np.ascontiguousarray(A)
+    import torch
+    Ud = torch.from_numpy(U).to(device)
+    A = (Ud * torch.from_numpy(sigma).to(device)[None, :]) @ Ud.T
+    del Ud
     if noise:
-        G = rng.standard_normal((n, n))
-        G += G.T
-        G *= noise / math.sqrt(2.0)
-        A += G
+        Gd = torch.from_numpy(G).to(device)
         del G
-    iu = np.triu_indices(n, 1)
-    A[(iu[1], iu[0])] = A[iu]
-    return np.ascontiguousarray(A)
+        A += (Gd + Gd.T) * (noise / math.sqrt(2.0))
+        del Gd
+    A = torch.triu(A)
+    A += torch.triu(A, 1).T
+    out = A.cpu().numpy()
+    del A
+    return out
 
 
 def rank_r(m, n, r, tag, channel=0, scale=1.0):
