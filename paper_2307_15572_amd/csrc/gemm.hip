@@ -245,8 +245,8 @@ GemmShape dgemm_shape(int64_t M, int64_t N, int64_t K, int max_splits) {
   s.tiles_m = (int)((M + 16 * kWM - 1) / (16 * kWM));
   const int64_t T = (int64_t)s.tiles_m * s.tiles_n;
   int S = 1;
-  // aim for >= 512 workgroups (two per CU) with at least 512 of K per split
-  while (S < max_splits && T * S < 512 && K / (2 * S) >= 512) S *= 2;
+  // aim for >= 512 workgroups (two per CU) with at least 128 of K per split
+  while (S < max_splits && T * S < 512 && K / (2 * S) >= 128) S *= 2;
   int64_t kchunk = ((K + S - 1) / S + kBK - 1) / kBK * kBK;
   if (kchunk < kBK) kchunk = kBK;
   S = (int)((K + kchunk - 1) / kchunk);

@@ -44,9 +44,15 @@ rsvd_status copy_panel(int64_t rows, int64_t cols, const double* src, int64_t ld
 // One-sided Jacobi on the rows of M (l x l): P M0 = M with orthogonal rows.
 rsvd_status jacobi_rows(int64_t l, double* M, double* P, int max_sweeps, DevState* st,
                         hipStream_t s);
+// Block one-sided Jacobi (bjacobi.hip): M, P are Lp x Lp (Lp = jacobi_padded(l))
+// workspace buffers; M <- R zero padded, P <- I, then the rows of M are
+// orthogonalized and the rotations accumulated in P.
+int64_t jacobi_padded(int64_t l);
+rsvd_status block_jacobi(int64_t l, const double* R, double* M, double* P, int max_sweeps,
+                         int inner_sweeps, DevState* st, hipStream_t s);
 // From converged M, P: s (decreasing), Us (l x kc), W (l x kc).
-rsvd_status svd_finish(int64_t l, int64_t kc, const double* M, const double* P, double* s,
-                       double* Us, double* W, DevState* st, hipStream_t st_);
+rsvd_status svd_finish(int64_t l, int64_t kc, const double* M, const double* P, int64_t ld,
+                       double* s, double* Us, double* W, DevState* st, hipStream_t st_);
 rsvd_status select_rank(int64_t l, int64_t p, int64_t kc, int mode, double param,
                         const double* s, DevState* st, hipStream_t hs);
 rsvd_status sign_fix(int64_t m, int64_t n, int64_t kc, double* U, int64_t ldu, double* V,

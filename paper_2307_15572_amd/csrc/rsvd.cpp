@@ -257,8 +257,9 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* worksp
   pl->off_R3i = c.take(ll);
   pl->off_Rt = c.take(ll);
   pl->off_Rtmp = c.take(ll);
-  pl->off_M = c.take(ll);
-  pl->off_P = c.take(ll);
+  const int64_t Lp = jacobi_padded(l);
+  pl->off_M = c.take((size_t)Lp * Lp * D);
+  pl->off_P = c.take((size_t)Lp * Lp * D);
   pl->off_sig = c.take((size_t)l * D);
   pl->off_Us = c.take((size_t)l * kc * D);
   pl->off_W = c.take((size_t)l * kc * D);
@@ -347,10 +348,8 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
   RSVD_TRY(qr(n, Z, Rt));
   {
     PhaseScope ph(2, s);
-    RSVD_TRY(copy_panel(l, l, Rt, l, Mj, l, 0, st, s));
-    RSVD_TRY(set_identity(l, Pj, s));
-    RSVD_TRY(jacobi_rows(l, Mj, Pj, p.max_sweeps > 0 ? p.max_sweeps : 30, st, s));
-    RSVD_TRY(svd_finish(l, kc, Mj, Pj, sig, Us, W, st, s));
+    RSVD_TRY(block_jacobi(l, Rt, Mj, Pj, p.max_sweeps > 0 ? p.max_sweeps : 30, 1, st, s));
+    RSVD_TRY(svd_finish(l, kc, Mj, Pj, jacobi_padded(l), sig, Us, W, st, s));
   }
   if (pl.mode == RSVD_RANK_FROB_TAIL) {
     PhaseScope ph(6, s);
@@ -458,10 +457,11 @@ rsvd_status rsvd_orth(int64_t m, int64_t l, double* Y, int64_t ldy, double* X, u
 }
 
 size_t rsvd_small_svd_work_bytes(int64_t l) {
+  const int64_t Lp = jacobi_padded(l);
   Carver c;
   c.take(sizeof(DevState));
-  c.take((size_t)l * l * sizeof(double));
-  c.take((size_t)l * l * sizeof(double));
+  c.take((size_t)Lp * Lp * sizeof(double));
+  c.take((size_t)Lp * Lp * sizeof(double));
   return c.at;
 }
 
@@ -472,10 +472,11 @@ rsvd_status rsvd_small_svd(int64_t l, const double* R, double* sv, double* Us, d
   if (work_bytes < rsvd_small_svd_work_bytes(l)) return RSVD_ENOMEM;
   if (((uintptr_t)work & 255) != 0) return RSVD_EINVAL;
   hipStream_t s = (hipStream_t)stream;
+  const int64_t Lp = jacobi_padded(l);
   Carver c;
   const size_t off_state = c.take(sizeof(DevState));
-  const size_t off_M = c.take((size_t)l * l * sizeof(double));
-  const size_t off_P = c.take((size_t)l * l * sizeof(double));
+  const size_t off_M = c.take((size_t)Lp * Lp * sizeof(double));
+  const size_t off_P = c.take((size_t)Lp * Lp * sizeof(double));
   Ws w{(char*)work};
   DevState* st = w.at<DevState>(off_state);
   double* Mj = w.at<double>(off_M);
@@ -483,10 +484,8 @@ rsvd_status rsvd_small_svd(int64_t l, const double* R, double* sv, double* Us, d
   rsvd_status r;
 #define RSVD_TRY(x) do { r = (x); if (r != RSVD_OK) return r; } while (0)
   RSVD_TRY(init_state(st, 0, s));
-  RSVD_TRY(copy_panel(l, l, R, l, Mj, l, 0, st, s));
-  RSVD_TRY(set_identity(l, Pj, s));
-  RSVD_TRY(jacobi_rows(l, Mj, Pj, max_sweeps > 0 ? max_sweeps : 30, st, s));
-  RSVD_TRY(svd_finish(l, l, Mj, Pj, sv, Us, W, st, s));
+  RSVD_TRY(block_jacobi(l, R, Mj, Pj, max_sweeps > 0 ? max_sweeps : 30, 1, st, s));
+  RSVD_TRY(svd_finish(l, l, Mj, Pj, Lp, sv, Us, W, st, s));
   if (sweeps && hipMemcpyAsync(sweeps, &st->sweeps, sizeof(int32_t), hipMemcpyDeviceToDevice, s) != hipSuccess)
     return RSVD_EHIP;
   if (flags && hipMemcpyAsync(flags, &st->flags, sizeof(uint32_t), hipMemcpyDeviceToDevice, s) != hipSuccess)

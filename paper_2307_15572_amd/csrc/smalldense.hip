@@ -285,6 +285,282 @@ __global__ void __launch_bounds__(kBig) householder_kernel(int64_t rows, int l,
   for (int64_t e = threadIdx.x; e < tot; e += blockDim.x) W[e] *= tau_buf[l + (int)(e % l)];
   if (threadIdx.x == 0) atomicOr(&st->flags, (uint32_t)RSVD_FLAG_QR_FALLBACK);
 }
+// ---------------------------------------------------------------------------
+// Blocked Cholesky + triangular inverse on 16 x 16 tiles with the FP64 matrix
+// cores, one workgroup of 16 waves. Upper form: G (+ shift I) = R^T R.
+// Right-looking over block rows k:
+//   R_kk  = chol(G_kk)            one wave, in registers (cross-lane shuffles)
+//   R_kJ  = R_kk^{-T} G_kJ        MFMA, tiles of block row k (J > k)
+//   G_IJ -= R_kI^T R_kJ           MFMA, trailing tiles (k < I <= J)
+// then X = R^{-1} by block back substitution: X_IJ = -X_II sum_{K>I} R_IK X_KJ.
+// Tiles live in global memory (L2-resident at these sizes); the current block
+// row of R is staged in LDS. Padding rows/columns beyond l act as identity.
+// Register layout of a 16 x 16 tile (the MFMA accumulator layout): lane
+// (r = lane % 16, g = lane / 16), item t holds entry (g + 4 t, r).
+// ---------------------------------------------------------------------------
+struct TileCtx {
+  int l, nb, ps;
+  __device__ __forceinline__ bool in(int i, int c) const { return i < l && c < l; }
+};
+
+__device__ __forceinline__ void load_tile(const TileCtx& cx, const double* W, int I, int J,
+                                          double t[4]) {
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int it = 0; it < 4; it++) {
+    const int i = 16 * I + g + 4 * it, c = 16 * J + r;
+    t[it] = cx.in(i, c) ? W[(int64_t)i * cx.l + c] : (i == c ? 1.0 : 0.0);
+  }
+}
+
+__device__ __forceinline__ void store_tile(const TileCtx& cx, double* W, int I, int J,
+                                           const double t[4]) {
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int it = 0; it < 4; it++) {
+    const int i = 16 * I + g + 4 * it, c = 16 * J + r;
+    if (cx.in(i, c)) W[(int64_t)i * cx.l + c] = t[it];
+  }
+}
+
+// Upper Cholesky of one 16 x 16 tile held by a wave; returns false on a
+// non-positive or non-finite pivot (unless clamping). Tracks the pivot range
+// over rows below lmax.
+__device__ bool tile_chol(double t[4], bool clamp, double clampv, int row0, int lmax,
+                          double& dmax, double& dmin) {
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < 16; j++) {
+    const int jg = j & 3, jt = j >> 2;
+    double piv = __shfl(t[jt], j + 16 * jg, 64);
+    if (clamp && !(piv > clampv)) piv = clampv;
+    if (!(piv > 0.0) || !isfinite(piv)) {
+      ok = false;
+      piv = 1.0;
+    }
+    const double rjj = sqrt(piv);
+    if (row0 + j < lmax) {
+      dmax = fmax(dmax, rjj);
+      dmin = fmin(dmin, rjj);
+    }
+    const double inv = 1.0 / rjj;
+    if (g == jg) {
+      if (r > j) t[jt] *= inv;
+      else if (r == j) t[jt] = rjj;
+    }
+    const double colv = __shfl(t[jt], r + 16 * jg, 64);
+#pragma unroll
+    for (int it = 0; it < 4; it++) {
+      const int i = g + 4 * it;
+      const double rowv = __shfl(t[jt], i + 16 * jg, 64);
+      if (i > j && r >= i) t[it] -= rowv * colv;
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < 4; it++)
+    if (g + 4 * it > r) t[it] = 0.0;
+  return ok;
+}
+
+// Inverse of an upper-triangular tile held by a wave (same layout).
+__device__ void tile_inv_upper(const double t[4], double x[4]) {
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int it = 0; it < 4; it++) x[it] = 0.0;
+#pragma unroll
+  for (int i = 15; i >= 0; i--) {
+    const int ig = i & 3, ii = i >> 2;
+    const double rii = __shfl(t[ii], i + 16 * ig, 64);
+    double part = 0.0;
+#pragma unroll
+    for (int it = 0; it < 4; it++) {
+      const int tr = g + 4 * it;
+      const double rit = __shfl(t[ii], tr + 16 * ig, 64);
+      if (tr > i) part += rit * x[it];
+    }
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    if (g == ig) x[ii] = (r == i) ? 1.0 / rii : (r > i ? -part / rii : 0.0);
+  }
+}
+
+__device__ __forceinline__ void trailing_coords(int t, int n, int& I, int& J) {
+  // t-th tile of the upper triangle (row-major) of an n x n tile grid
+  int row = 0, cnt = n;
+  while (t >= cnt) {
+    t -= cnt;
+    row++;
+    cnt--;
+  }
+  I = row;
+  J = row + t;
+}
+
+// Factor W in place (tiles). Returns false on breakdown (uniform).
+__device__ bool tiled_factor(const TileCtx& cx, double* W, double* Xg, double* panel,
+                             double* dinv, int* s_flag, bool clamp, double clampv,
+                             double* s_range) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  const int nw = blockDim.x >> 6;
+  const int nb = cx.nb, ps = cx.ps;
+  double dmax = 0.0, dmin = INFINITY;
+  if (threadIdx.x == 0) *s_flag = 0;
+  __syncthreads();
+  for (int k = 0; k < nb; k++) {
+    if (wave == 0) {
+      double t[4], x[4];
+      load_tile(cx, W, k, k, t);
+      const bool ok = tile_chol(t, clamp, clampv, 16 * k, cx.l, dmax, dmin);
+      tile_inv_upper(t, x);
+      store_tile(cx, W, k, k, t);
+      store_tile(cx, Xg, k, k, x);
+#pragma unroll
+      for (int it = 0; it < 4; it++) dinv[(g + 4 * it) * 17 + r] = x[it];
+      if (!ok && lane == 0) *s_flag = 1;
+    }
+    __syncthreads();
+    if (*s_flag) return false;
+    // block row k: R_kJ = R_kk^{-T} G_kJ
+    for (int J = k + 1 + wave; J < nb; J += nw) {
+      double b[4];
+      load_tile(cx, W, k, J, b);
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 4; s++) acc = mfma_f64_16x16x4(dinv[(4 * s + g) * 17 + r], b[s], acc);
+      double o[4] = {acc[0], acc[1], acc[2], acc[3]};
+      store_tile(cx, W, k, J, o);
+#pragma unroll
+      for (int it = 0; it < 4; it++) panel[(g + 4 * it) * ps + 16 * J + r] = o[it];
+    }
+    __syncthreads();
+    // trailing tiles
+    const int n = nb - k - 1;
+    const int T = n * (n + 1) / 2;
+    for (int tt = wave; tt < T; tt += nw) {
+      int I, J;
+      trailing_coords(tt, n, I, J);
+      I += k + 1;
+      J += k + 1;
+      double t[4];
+      load_tile(cx, W, I, J, t);
+      d4 acc = {t[0], t[1], t[2], t[3]};
+#pragma unroll
+      for (int s = 0; s < 4; s++) {
+        const double a = -panel[(4 * s + g) * ps + 16 * I + r];
+        const double bb = panel[(4 * s + g) * ps + 16 * J + r];
+        acc = mfma_f64_16x16x4(a, bb, acc);
+      }
+      double o[4] = {acc[0], acc[1], acc[2], acc[3]};
+      store_tile(cx, W, I, J, o);
+    }
+    __syncthreads();
+  }
+  if (wave == 0 && lane == 0) {
+    s_range[0] = dmax;
+    s_range[1] = dmin;
+  }
+  __syncthreads();
+  return true;
+}
+
+// X = R^{-1}: diagonal tiles already in Xg; block rows from the bottom.
+__device__ void tiled_inverse(const TileCtx& cx, const double* W, double* Xg, double* panel,
+                              double* dinv) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  const int nw = blockDim.x >> 6;
+  const int nb = cx.nb, ps = cx.ps, l = cx.l;
+  for (int I = nb - 2; I >= 0; I--) {
+    // stage block row I of R (columns >= 16 (I + 1)) and X_II
+    const int c0 = 16 * (I + 1);
+    const int width = 16 * nb - c0;
+    for (int e = threadIdx.x; e < 16 * width; e += blockDim.x) {
+      const int i = 16 * I + e / width, c = c0 + e % width;
+      panel[(e / width) * ps + c] = (i < l && c < l) ? W[(int64_t)i * l + c] : 0.0;
+    }
+    for (int e = threadIdx.x; e < 256; e += blockDim.x) {
+      const int i = 16 * I + e / 16, c = 16 * I + e % 16;
+      dinv[(e / 16) * 17 + e % 16] = (i < l && c < l) ? Xg[(int64_t)i * l + c] : (i == c ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    for (int J = I + 1 + wave; J < nb; J += nw) {
+      d4 acc = {0.0, 0.0, 0.0, 0.0};
+      for (int K = I + 1; K <= J; K++) {
+        double xb[4];
+        load_tile(cx, Xg, K, J, xb);  // rows 16K + g + 4s: B operand of step s
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+          const double a = panel[r * ps + 16 * K + 4 * s + g];  // R_IK[r][4s + g]
+          acc = mfma_f64_16x16x4(a, xb[s], acc);
+        }
+      }
+      d4 out = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < 4; s++) out = mfma_f64_16x16x4(-dinv[r * 17 + 4 * s + g], acc[s], out);
+      double o[4] = {out[0], out[1], out[2], out[3]};
+      store_tile(cx, Xg, I, J, o);
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(512) chol_tiles_kernel(int l, const double* __restrict__ G,
+                                                          double* __restrict__ R,
+                                                          double* __restrict__ Rinv, int64_t m,
+                                                          int pass, int only_if_shifted,
+                                                          DevState* st) {
+  extern __shared__ double lds[];
+  __shared__ double red[kBig / 64];
+  __shared__ int s_flag;
+  __shared__ double s_range[2];
+  if (only_if_shifted && st->qr_shifted == 0) return;
+  TileCtx cx;
+  cx.l = l;
+  cx.nb = (l + 15) / 16;
+  cx.ps = 16 * cx.nb + 1;
+  double* panel = lds;
+  double* dinv = lds + 16 * cx.ps;
+  const int64_t ll = (int64_t)l * l;
+
+  double tr = 0.0;
+  for (int i = threadIdx.x; i < l; i += blockDim.x) tr += G[(int64_t)i * l + i];
+  tr = block_sum(tr, red);
+  const double shift = 11.0 * ((double)m * l + (double)l * (l + 1)) * kUnitRoundoff * tr;
+  const double clampv = fmax(shift, 1e-300);
+
+  bool use_shift = false, clamp = false;
+  for (int attempt = 0; attempt < 3; attempt++) {
+    for (int64_t e = threadIdx.x; e < ll; e += blockDim.x) {
+      double v = G[e];
+      if (use_shift && (e / l) == (e % l)) v += shift;
+      R[e] = v;
+    }
+    __syncthreads();
+    bool ok = tiled_factor(cx, R, Rinv, panel, dinv, &s_flag, clamp, clampv, s_range);
+    if (clamp) break;
+    if (ok && pass == 0 && !use_shift && s_range[0] > 1e5 * s_range[1]) ok = false;
+    if (ok) break;
+    if (pass != 0 || use_shift) {
+      // breakdown even with the shift: numerically rank-deficient panel
+      if (threadIdx.x == 0) st->qr_householder = 1;
+      clamp = true;
+      use_shift = true;
+    } else {
+      use_shift = true;
+      if (threadIdx.x == 0) st->qr_shifted = 1;
+    }
+    __syncthreads();
+  }
+  tiled_inverse(cx, R, Rinv, panel, dinv);
+  // strictly lower parts are zero
+  for (int64_t e = threadIdx.x; e < ll; e += blockDim.x) {
+    if (e / l > e % l) {
+      R[e] = 0.0;
+      Rinv[e] = 0.0;
+    }
+  }
+}
+
 
 __global__ void __launch_bounds__(256) copy_panel_kernel(int64_t rows, int64_t cols,
                                                          const double* __restrict__ src, int64_t lds,
@@ -410,7 +686,7 @@ __global__ void __launch_bounds__(256) identity_kernel(int64_t l, double* P) {
 // Us[:, i] = row pi(i) of M / s_i, W[:, i] = row pi(i) of P.
 __global__ void __launch_bounds__(kBig) svd_finish_kernel(int l, int kc,
                                                           const double* __restrict__ M,
-                                                          const double* __restrict__ P,
+                                                          const double* __restrict__ P, int64_t ld,
                                                           double* __restrict__ s,
                                                           double* __restrict__ Us,
                                                           double* __restrict__ W, DevState* st) {
@@ -420,30 +696,32 @@ __global__ void __launch_bounds__(kBig) svd_finish_kernel(int l, int kc,
   for (int i = threadIdx.x; i < l; i += blockDim.x) {
     double a = 0.0;
     for (int c = 0; c < l; c++) {
-      const double x = M[(int64_t)i * l + c];
+      const double x = M[(int64_t)i * ld + c];
       a += x * x;
     }
     nrm[i] = sqrt(a);
   }
   __syncthreads();
+  // rank by (norm, index) with NaN ordered below every norm, so the
+  // positions always form a permutation of 0..l-1
   for (int i = threadIdx.x; i < l; i += blockDim.x) {
-    const double v = nrm[i];
+    const double v = isnan(nrm[i]) ? -1.0 : nrm[i];
     int pos = 0;
     for (int j = 0; j < l; j++) {
-      const double u = nrm[j];
+      const double u = isnan(nrm[j]) ? -1.0 : nrm[j];
       pos += (u > v) || (u == v && j < i);
     }
     perm[pos] = i;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < l; i += blockDim.x) s[i] = nrm[perm[i]];
+  for (int i = threadIdx.x; i < l; i += blockDim.x) s[i] = nrm[min(max(perm[i], 0), l - 1)];
   for (int64_t e = threadIdx.x; e < (int64_t)l * kc; e += blockDim.x) {
     const int r = (int)(e / kc), i = (int)(e % kc);
     if (i < l) {
-      const int src = perm[i];
+      const int src = min(max(perm[i], 0), l - 1);
       const double sv = nrm[src];
-      Us[e] = sv > 0.0 ? M[(int64_t)src * l + r] / sv : 0.0;
-      W[e] = P[(int64_t)src * l + r];
+      Us[e] = sv > 0.0 ? M[(int64_t)src * ld + r] / sv : 0.0;
+      W[e] = P[(int64_t)src * ld + r];
     } else {
       Us[e] = 0.0;
       W[e] = 0.0;
@@ -652,13 +930,27 @@ void allow_big_lds() {
                             hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
   (void)hipFuncSetAttribute((const void*)jacobi_kernel,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
+  (void)hipFuncSetAttribute((const void*)chol_tiles_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
 }
 
 }  // namespace
 
+size_t chol_tiles_lds(int64_t l) {
+  const int64_t nb = (l + 15) / 16;
+  return (size_t)(16 * (16 * nb + 1) + 16 * 17) * sizeof(double);
+}
+
 rsvd_status chol_inv(int64_t l, const double* G, double* R, double* Rinv, int64_t m, int pass,
                      int only_if_shifted, DevState* st, hipStream_t s) {
   allow_big_lds();
+  const size_t tl = chol_tiles_lds(l);
+  if (tl <= 150 * 1024) {
+    hipLaunchKernelGGL(chol_tiles_kernel, dim3(1), dim3(512), tl, s, (int)l, G, R, Rinv, m, pass,
+                       only_if_shifted, st);
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
+  }
   const size_t need = (size_t)l * l * 2 * sizeof(double);
   const size_t shm = need <= 150 * 1024 ? need : 0;
   hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(kBig), shm, s, (int)l, G, R, Rinv, m, pass,
@@ -700,11 +992,11 @@ rsvd_status set_identity(int64_t l, double* P, hipStream_t s) {
   return RSVD_OK;
 }
 
-rsvd_status svd_finish(int64_t l, int64_t kc, const double* M, const double* P, double* sv,
-                       double* Us, double* W, DevState* st, hipStream_t s) {
+rsvd_status svd_finish(int64_t l, int64_t kc, const double* M, const double* P, int64_t ld,
+                       double* sv, double* Us, double* W, DevState* st, hipStream_t s) {
   const size_t shm = (size_t)l * (sizeof(double) + sizeof(int));
-  hipLaunchKernelGGL(svd_finish_kernel, dim3(1), dim3(kBig), shm, s, (int)l, (int)kc, M, P, sv, Us,
-                     W, st);
+  hipLaunchKernelGGL(svd_finish_kernel, dim3(1), dim3(kBig), shm, s, (int)l, (int)kc, M, P, ld, sv,
+                     Us, W, st);
   RSVD_LAUNCH_CHECK();
   return RSVD_OK;
 }

@@ -51,7 +51,8 @@ def test_dgemm_matches_numpy(ta, m, n, k):
 
 
 @pytest.mark.parametrize("m,l,decay", [(500, 50, 1 / 16), (4096, 272, 1 / 40), (3000, 100, 1 / 8),
-                                       (200, 200, 1 / 64), (20, 1, 0.1)])
+                                       (200, 200, 1 / 64), (20, 1, 0.1), (2000, 528, 1 / 64),
+                                       (1500, 33, 0.05)])
 def test_orth_matches_oracle(m, l, decay):
     import paper_2307_15572_amd as rs
     announce(f"orth m={m} l={l} decay={decay}")
@@ -104,7 +105,8 @@ def test_orth_exactly_rank_deficient_uses_householder():
     assert np.abs(Q[:, :25] - oracle_orth(Y[:, :25])).max() <= 1e-12
 
 
-@pytest.mark.parametrize("l,decay", [(50, 1 / 16), (272, 1 / 40), (17, 0.5), (1, 0.0), (128, 1 / 20)])
+@pytest.mark.parametrize("l,decay", [(50, 1 / 16), (272, 1 / 40), (17, 0.5), (1, 0.0), (128, 1 / 20),
+                                     (528, 1 / 64), (300, 1 / 30)])
 def test_small_svd_matches_lapack(l, decay):
     import paper_2307_15572_amd as rs
     announce(f"small_svd l={l}")
