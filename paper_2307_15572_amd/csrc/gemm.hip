@@ -26,10 +26,16 @@ namespace rsvd {
 
 namespace {
 
+bool g_use_dma = true;  // LDS-DMA streaming kernel for eligible NN products
+
 constexpr int kWM = 4;      // waves per workgroup, stacked along rows
 constexpr int kBK = 16;     // K chunk per LDS stage
 constexpr int kThreads = 64 * kWM;
 constexpr int kMaxNT = 17;  // 17 x 16 = 272 columns per workgroup
+#ifndef RSVD_GEMM_APF
+#define RSVD_GEMM_APF 2     // chunks of the streamed operand A in flight ahead of use
+#endif
+constexpr int kAPF = RSVD_GEMM_APF;
 
 struct GemmArgs {
   int64_t M, N, K, kchunk;
@@ -43,6 +49,7 @@ struct GemmArgs {
   const double* Aref;      // residual mode: the matrix the product approximates
   int64_t ldref;
   double* rpart;           // residual mode: per-workgroup partial sums [2][items]
+  int vec_a, vec_b;        // 16-byte loads allowed (even leading dimension, aligned base)
 };
 
 template <bool TA, int NT, bool RES>
@@ -50,7 +57,8 @@ __global__ void __launch_bounds__(kThreads) dgemm_kernel(GemmArgs g) {
   constexpr int BN = NT * 16;
   constexpr int BEL = kBK * BN;
   constexpr int BPER = (BEL + kThreads - 1) / kThreads;
-  __shared__ double Bs[2][BEL];
+  constexpr int BPER2 = (BEL / 2 + kThreads - 1) / kThreads;
+  __shared__ __attribute__((aligned(16))) double Bs[2][BEL];
   if (g.pred != nullptr && *g.pred == 0) return;
 
   // XCD-aware item order: item = (z * tiles_m + tm) * tiles_n + tn
@@ -65,7 +73,8 @@ __global__ void __launch_bounds__(kThreads) dgemm_kernel(GemmArgs g) {
 
   const int64_t kb = (int64_t)z * g.kchunk;
   const int64_t ke = min(g.K, kb + g.kchunk);
-  const int nk = (int)((ke - kb + kBK - 1) / kBK);
+  const int nfull = (int)((ke - kb) / kBK);          // chunks entirely inside [kb, ke)
+  const bool tail = (ke - kb) % kBK != 0;
 
   const int wave = threadIdx.x >> 6;
   const int lane = threadIdx.x & 63;
@@ -73,79 +82,131 @@ __global__ void __launch_bounds__(kThreads) dgemm_kernel(GemmArgs g) {
   const int gq = lane >> 4;
   const int64_t row0 = (int64_t)tm * (16 * kWM) + wave * 16;
   const int64_t col0 = (int64_t)tn * BN;
-  const int64_t arow = row0 + r;
-  const bool arow_ok = arow < g.M;
+  // rows past M only feed output rows that are never stored: clamp the address
+  const int64_t arow = min(row0 + r, g.M - 1);
 
   const double* __restrict__ A = g.A;
   const double* __restrict__ B = g.B;
+  const bool vec_a = !TA && g.vec_a;
+  const bool vec_b = g.vec_b && (col0 + BN <= g.N);
 
   d4 acc[NT];
 #pragma unroll
   for (int t = 0; t < NT; t++) acc[t] = (d4){0.0, 0.0, 0.0, 0.0};
 
   double a_cur[4], a_nxt[4];
-  double b_stage[BPER];
+  // scalar staging uses BPER slots, the 16-byte path 2 * BPER2 (NT + 1 for odd NT)
+  constexpr int BSTAGE = BPER > 2 * BPER2 ? BPER : 2 * BPER2;
+  double b_stage[BSTAGE];
 
-  // lane (r, gq) feeds k = k0 + 4 s + gq at MFMA step s
-  auto load_a = [&](int64_t k0, double* a) {
+  // MFMA step s of a chunk uses k = k0 + 4 gq + s at lane group gq
+  auto load_a = [&](int64_t k0, double* a, bool guard) {
+    if (!guard && vec_a) {
+      const double2* p = reinterpret_cast<const double2*>(A + arow * g.lda + k0 + 4 * gq);
+      const double2 v0 = p[0], v1 = p[1];
+      a[0] = v0.x; a[1] = v0.y; a[2] = v1.x; a[3] = v1.y;
+      return;
+    }
 #pragma unroll
     for (int s = 0; s < 4; s++) {
-      const int64_t k = k0 + 4 * s + gq;
-      double v = 0.0;
-      if (arow_ok && k < ke) v = TA ? A[k * g.lda + arow] : A[arow * g.lda + k];
-      a[s] = v;
+      const int64_t k = k0 + 4 * gq + s;
+      if (guard) {
+        double v = 0.0;
+        if (k < ke) v = TA ? A[k * g.lda + arow] : A[arow * g.lda + k];
+        a[s] = v;
+      } else {
+        a[s] = TA ? A[k * g.lda + arow] : A[arow * g.lda + k];
+      }
     }
   };
-  auto load_b = [&](int64_t k0) {
+  // columns past N only feed output columns that are never stored: clamp
+  auto load_b = [&](int64_t k0, bool guard) {
+    if (!guard && vec_b) {
+#pragma unroll
+      for (int i = 0; i < BPER2; i++) {
+        const int idx = threadIdx.x + i * kThreads;  // double2 index
+        if (idx < BEL / 2) {
+          const int kk = (2 * idx) / BN, cc = (2 * idx) % BN;
+          const double2 v = *reinterpret_cast<const double2*>(B + (k0 + kk) * g.ldb + col0 + cc);
+          b_stage[2 * i] = v.x;
+          b_stage[2 * i + 1] = v.y;
+        }
+      }
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < BPER; i++) {
       const int idx = threadIdx.x + i * kThreads;
-      double v = 0.0;
       if (idx < BEL) {
         const int kk = idx / BN, cc = idx % BN;
-        const int64_t k = k0 + kk, c = col0 + cc;
-        if (k < ke && c < g.N) v = B[k * g.ldb + c];
+        const int64_t k = k0 + kk, c = min(col0 + cc, g.N - 1);
+        if (guard) {
+          double v = 0.0;
+          if (k < ke) v = B[k * g.ldb + c];
+          b_stage[i] = v;
+        } else {
+          b_stage[i] = B[k * g.ldb + c];
+        }
       }
-      b_stage[i] = v;
     }
   };
-  auto store_b = [&](int buf) {
+  auto store_b = [&](int buf, bool was_vec) {
+    if (was_vec) {
+#pragma unroll
+      for (int i = 0; i < BPER2; i++) {
+        const int idx = threadIdx.x + i * kThreads;
+        if (idx < BEL / 2)
+          reinterpret_cast<double2*>(Bs[buf])[idx] = make_double2(b_stage[2 * i], b_stage[2 * i + 1]);
+      }
+      return;
+    }
 #pragma unroll
     for (int i = 0; i < BPER; i++) {
       const int idx = threadIdx.x + i * kThreads;
       if (idx < BEL) Bs[buf][idx] = b_stage[i];
     }
   };
+  auto compute = [&](const double* bs) {
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+      double bf[NT];
+#pragma unroll
+      for (int t = 0; t < NT; t++) bf[t] = bs[(4 * gq + s) * BN + 16 * t + r];
+#pragma unroll
+      for (int t = 0; t < NT; t++) acc[t] = mfma_f64_16x16x4(a_cur[s], bf[t], acc[t]);
+    }
+  };
 
+  const int nk = nfull + (tail ? 1 : 0);
+  // A ring: a_q[j] holds chunk c + j (j = 0 .. kAPF-1); B goes one chunk ahead via LDS
+  double a_q[kAPF][4];
+#pragma unroll
+  for (int j = 0; j < kAPF; j++) {
+    if (j < nk) load_a(kb + (int64_t)j * kBK, a_q[j], j >= nfull);
+  }
   if (nk > 0) {
-    load_a(kb, a_cur);
-    load_b(kb);
-    store_b(0);
+    const bool g0 = nfull == 0;
+    load_b(kb, g0);
+    store_b(0, !g0 && vec_b);
   }
   __syncthreads();
   for (int c = 0; c < nk; c++) {
     const int buf = c & 1;
     const bool more = c + 1 < nk;
-    if (more) {
-      load_a(kb + (int64_t)(c + 1) * kBK, a_nxt);
-      load_b(kb + (int64_t)(c + 1) * kBK);
-    }
-    const double* bs = Bs[buf];
+    const bool gn = (c + 1) >= nfull;  // the next chunk is the partial tail
+    if (more) load_b(kb + (int64_t)(c + 1) * kBK, gn);
 #pragma unroll
-    for (int s = 0; s < 4; s++) {
+    for (int s = 0; s < 4; s++) a_cur[s] = a_q[0][s];
 #pragma unroll
-      for (int t = 0; t < NT; t++) {
-        const double bv = bs[(4 * s + gq) * BN + 16 * t + r];
-        acc[t] = mfma_f64_16x16x4(a_cur[s], bv, acc[t]);
-      }
-    }
-    if (more) {
-      store_b(buf ^ 1);
+    for (int j = 0; j + 1 < kAPF; j++)
 #pragma unroll
-      for (int s = 0; s < 4; s++) a_cur[s] = a_nxt[s];
-    }
+      for (int s = 0; s < 4; s++) a_q[j][s] = a_q[j + 1][s];
+    if (c + kAPF < nk) load_a(kb + (int64_t)(c + kAPF) * kBK, a_q[kAPF - 1], (c + kAPF) >= nfull);
+    compute(Bs[buf]);
+    if (more) store_b(buf ^ 1, !gn && vec_b);
     __syncthreads();
   }
+  (void)a_nxt;
 
   // D layout: lane (r, gq), item it -> row gq + 4 it, column r of the 16x16 tile
   if constexpr (RES) {
@@ -204,6 +265,171 @@ __global__ void __launch_bounds__(kThreads) dgemm_kernel(GemmArgs g) {
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Streaming variant for C = op(A) B with op(A) = A (row-major), used when
+// every K chunk is whole and both operands allow 16-byte accesses. Both
+// operands move HBM/L2 -> LDS with global_load_lds_dwordx4 (no staging
+// registers) through three LDS stages, two chunks ahead of the MFMAs. Each
+// wave waits only for its own copies of the chunk it is about to use
+// (s_waitcnt vmcnt(n) with n = copies it issued for the next chunk) and then
+// meets the other waves at a bare s_barrier, so the copies of later chunks
+// stay in flight across the barrier.
+// A stage layout: wave w, half h (k pairs 0-1 / 2-3 of a lane's 4 k values):
+// 64 lanes x 16 B, so the MFMA A fragments of a lane are one 16-byte read.
+// ---------------------------------------------------------------------------
+#define RSVD_LDS(p) ((__attribute__((address_space(3))) void*)(p))
+
+// One 16-byte-per-lane copy global -> LDS (lane i lands at lds + 16 i). Issued
+// through asm so the compiler's wait-count model does not treat the pending
+// copy as a hazard for reads of the other LDS stages; waits are explicit
+// (wait_vmcnt + barrier). No register is written by the instruction.
+__device__ __forceinline__ void copy_to_lds16(const void* src, const void* lds) {
+  const unsigned off = (unsigned)(uintptr_t)RSVD_LDS(lds);
+  asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "{m0}"(off) : "memory");
+}
+
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+template <int NT>
+__device__ __forceinline__ void wait_own_next(int wave, bool next_pending) {
+  constexpr int NBQ = 2 * NT;
+  constexpr int n0 = 2 + (NBQ + 3) / 4, n1 = 2 + (NBQ + 2) / 4, n2 = 2 + (NBQ + 1) / 4, n3 = 2 + NBQ / 4;
+  if (!next_pending) {
+    wait_vmcnt<0>();
+    return;
+  }
+  switch (wave) {
+    case 0: wait_vmcnt<n0>(); break;
+    case 1: wait_vmcnt<n1>(); break;
+    case 2: wait_vmcnt<n2>(); break;
+    default: wait_vmcnt<n3>(); break;
+  }
+}
+
+template <int NT>
+__global__ void __launch_bounds__(kThreads) dgemm_nn_dma_kernel(GemmArgs g) {
+  constexpr int BN = NT * 16;
+  constexpr int BEL = kBK * BN;
+  constexpr int NBQ = 2 * NT;            // 1 KB copies per B chunk
+  constexpr int AEL = kWM * 2 * 128;     // doubles per A stage
+  __shared__ __attribute__((aligned(16))) double B0[BEL];
+  __shared__ __attribute__((aligned(16))) double B1[BEL];
+  __shared__ __attribute__((aligned(16))) double B2[BEL];
+  __shared__ __attribute__((aligned(16))) double A0[AEL];
+  __shared__ __attribute__((aligned(16))) double A1[AEL];
+  __shared__ __attribute__((aligned(16))) double A2[AEL];
+  if (g.pred != nullptr && *g.pred == 0) return;
+
+  const int total = g.tiles_m * g.tiles_n * g.splits;
+  const int full = total & ~7;
+  int b = blockIdx.x;
+  int item = b;
+  if (b < full) item = (b & 7) * (full >> 3) + (b >> 3);
+  const int tn = item % g.tiles_n;
+  const int tm = (item / g.tiles_n) % g.tiles_m;
+  const int z = item / (g.tiles_n * g.tiles_m);
+  const int64_t kb = (int64_t)z * g.kchunk;
+  const int64_t ke = min(g.K, kb + g.kchunk);
+  const int nk = (int)((ke - kb) / kBK);
+
+  const int wave = threadIdx.x >> 6;
+  const int lane = threadIdx.x & 63;
+  const int r = lane & 15;
+  const int gq = lane >> 4;
+  const int64_t row0 = (int64_t)tm * (16 * kWM) + wave * 16;
+  const int64_t col0 = (int64_t)tn * BN;
+  const double* __restrict__ A = g.A;
+  const double* __restrict__ B = g.B;
+  // source of this lane's A copies: row (clamped), k offset 4 gq + 2 h
+  const double* asrc = A + min(row0 + r, g.M - 1) * g.lda + kb + 4 * gq;
+
+  auto issue = [&](int c, double* As, double* Bs) {
+    const int64_t k0 = (int64_t)c * kBK;
+#pragma unroll
+    for (int h = 0; h < 2; h++)
+      copy_to_lds16(asrc + k0 + 2 * h, As + (wave * 2 + h) * 128);
+#pragma unroll
+    for (int i = 0; i < (NBQ + 3) / 4; i++) {
+      const int q = wave + 4 * i;
+      if (q < NBQ) {
+        const int e = q * 128 + 2 * lane;  // element of the chunk this lane copies
+        const int kk = e / BN, cc = e % BN;
+        const int64_t col = min(col0 + cc, g.N - 2);  // columns past N are never stored
+        copy_to_lds16(B + (kb + k0 + kk) * g.ldb + col, Bs + q * 128);
+      }
+    }
+  };
+
+  d4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; t++) acc[t] = (d4){0.0, 0.0, 0.0, 0.0};
+
+  auto compute = [&](const double* As, const double* Bs) {
+    const double2 a01 = *reinterpret_cast<const double2*>(As + (wave * 2 + 0) * 128 + 2 * lane);
+    const double2 a23 = *reinterpret_cast<const double2*>(As + (wave * 2 + 1) * 128 + 2 * lane);
+    const double av[4] = {a01.x, a01.y, a23.x, a23.y};
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+      double bf[NT];
+#pragma unroll
+      for (int t = 0; t < NT; t++) bf[t] = Bs[(4 * gq + s) * BN + 16 * t + r];
+#pragma unroll
+      for (int t = 0; t < NT; t++) acc[t] = mfma_f64_16x16x4(av[s], bf[t], acc[t]);
+    }
+  };
+  auto step = [&](int c, double* As, double* Bs, double* As2, double* Bs2) {
+    wait_own_next<NT>(wave, c + 1 < nk);
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");  // no LDS access moves across the barrier
+    if (c + 2 < nk) issue(c + 2, As2, Bs2);
+    compute(As, Bs);
+  };
+
+  if (nk > 0) issue(0, A0, B0);
+  if (nk > 1) issue(1, A1, B1);
+  for (int c = 0; c < nk; c += 3) {
+    step(c, A0, B0, A2, B2);
+    if (c + 1 < nk) step(c + 1, A1, B1, A0, B0);
+    if (c + 2 < nk) step(c + 2, A2, B2, A1, B1);
+  }
+
+#pragma unroll
+  for (int t = 0; t < NT; t++) {
+#pragma unroll
+    for (int it = 0; it < 4; it++) {
+      const int64_t row = row0 + gq + 4 * it;
+      const int64_t col = col0 + 16 * t + r;
+      if (row < g.M && col < g.N) {
+        const double v = acc[t][it];
+        if (g.part) {
+          g.part[((int64_t)z * g.M + row) * g.N + col] = v;
+        } else {
+          double o = g.alpha * v;
+          if (g.beta != 0.0) o += g.beta * g.C[row * g.ldc + col];
+          g.C[row * g.ldc + col] = o;
+        }
+      }
+    }
+  }
+}
+
+hipError_t launch_dma(int nt, dim3 grid, hipStream_t st, const GemmArgs& a) {
+  switch (nt) {
+#define RSVD_DCASE(X) case X: hipLaunchKernelGGL((dgemm_nn_dma_kernel<X>), grid, dim3(kThreads), 0, st, a); break;
+    RSVD_DCASE(1) RSVD_DCASE(2) RSVD_DCASE(3) RSVD_DCASE(4) RSVD_DCASE(5) RSVD_DCASE(6)
+    RSVD_DCASE(7) RSVD_DCASE(8) RSVD_DCASE(9) RSVD_DCASE(10) RSVD_DCASE(11) RSVD_DCASE(12)
+    RSVD_DCASE(13) RSVD_DCASE(14) RSVD_DCASE(15) RSVD_DCASE(16) RSVD_DCASE(17)
+#undef RSVD_DCASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 // C = alpha * sum_z part[z] + beta * C, summed in split order.
 __global__ void __launch_bounds__(256) splitk_reduce_kernel(int64_t M, int64_t N, int S,
                                                             const double* __restrict__ part,
@@ -235,6 +461,8 @@ hipError_t launch_nt(int nt, dim3 grid, hipStream_t st, const GemmArgs& a) {
 }
 
 }  // namespace
+
+void dgemm_set_dma(bool on) { g_use_dma = on; }
 
 GemmShape dgemm_shape(int64_t M, int64_t N, int64_t K, int max_splits) {
   GemmShape s;
@@ -286,10 +514,16 @@ rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const 
   a.part = s.splits > 1 ? part : nullptr;
   a.tiles_m = s.tiles_m; a.tiles_n = s.tiles_n; a.splits = s.splits;
   a.pred = pred; a.Aref = nullptr; a.ldref = 0; a.rpart = nullptr;
+  a.vec_a = (lda % 2 == 0) && ((uintptr_t)A % 16 == 0);
+  a.vec_b = (ldb % 2 == 0) && ((uintptr_t)B % 16 == 0);
   const int64_t total = (int64_t)s.tiles_m * s.tiles_n * s.splits;
   dim3 grid((unsigned)total);
-  hipError_t e = ta ? launch_nt<true, false>(s.nt, grid, st, a)
-                    : launch_nt<false, false>(s.nt, grid, st, a);
+  // whole K chunks, even N and 16-byte aligned rows: the LDS-DMA pipeline
+  const bool dma_ok = !ta && (K % kBK == 0) && (s.kchunk % kBK == 0) && (N % 2 == 0) && N >= 2 &&
+                      a.vec_a && a.vec_b && g_use_dma;
+  hipError_t e = dma_ok ? launch_dma(s.nt, grid, st, a)
+                        : (ta ? launch_nt<true, false>(s.nt, grid, st, a)
+                              : launch_nt<false, false>(s.nt, grid, st, a));
   if (e != hipSuccess) return RSVD_EHIP;
   if (s.splits > 1) {
     const int64_t tot = M * N;
@@ -316,6 +550,8 @@ rsvd_status resid(int64_t M, int64_t N, int64_t K, const double* US, int64_t ldu
   a.part = nullptr;
   a.tiles_m = sh.tiles_m; a.tiles_n = sh.tiles_n; a.splits = 1;
   a.pred = nullptr; a.Aref = A; a.ldref = lda; a.rpart = partial;
+  a.vec_a = (ldus % 2 == 0) && ((uintptr_t)US % 16 == 0);
+  a.vec_b = (ldvt % 2 == 0) && ((uintptr_t)Vt % 16 == 0);
   const int64_t total = (int64_t)sh.tiles_m * sh.tiles_n;
   hipError_t e = launch_nt<false, true>(sh.nt, dim3((unsigned)total), s, a);
   if (e != hipSuccess) return RSVD_EHIP;

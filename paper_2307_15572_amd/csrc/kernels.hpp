@@ -12,6 +12,7 @@ struct GemmShape {
   size_t part_doubles = 0;
 };
 GemmShape dgemm_shape(int64_t M, int64_t N, int64_t K, int max_splits = 64);
+void dgemm_set_dma(bool on);  // select the LDS-DMA streaming kernel where eligible
 rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                   int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                   double* part, size_t part_doubles, hipStream_t st, int max_splits = 64,
