@@ -27,6 +27,7 @@ namespace rsvd {
 namespace {
 
 bool g_use_dma = true;  // LDS-DMA streaming kernel for eligible NN products
+int g_dma_wm = 8;       // waves per workgroup of the LDS-DMA kernel (4 or 8)
 
 constexpr int kWM = 4;      // waves per workgroup, stacked along rows
 constexpr int kBK = 16;     // K chunk per LDS stage
@@ -295,28 +296,36 @@ __device__ __forceinline__ void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
-template <int NT>
+// copies a wave issues per chunk: 2 for A plus its share of the 2 NT B copies
+template <int NT, int WM, int W>
+struct CopiesPerChunk {
+  static constexpr int value = 2 + (2 * NT - W + WM - 1) / WM;
+};
+
+template <int NT, int WM>
 __device__ __forceinline__ void wait_own_next(int wave, bool next_pending) {
-  constexpr int NBQ = 2 * NT;
-  constexpr int n0 = 2 + (NBQ + 3) / 4, n1 = 2 + (NBQ + 2) / 4, n2 = 2 + (NBQ + 1) / 4, n3 = 2 + NBQ / 4;
   if (!next_pending) {
     wait_vmcnt<0>();
     return;
   }
   switch (wave) {
-    case 0: wait_vmcnt<n0>(); break;
-    case 1: wait_vmcnt<n1>(); break;
-    case 2: wait_vmcnt<n2>(); break;
-    default: wait_vmcnt<n3>(); break;
+    case 0: wait_vmcnt<CopiesPerChunk<NT, WM, 0>::value>(); break;
+    case 1: wait_vmcnt<CopiesPerChunk<NT, WM, 1>::value>(); break;
+    case 2: wait_vmcnt<CopiesPerChunk<NT, WM, 2>::value>(); break;
+    case 3: wait_vmcnt<CopiesPerChunk<NT, WM, 3>::value>(); break;
+    case 4: wait_vmcnt<CopiesPerChunk<NT, WM, (WM > 4 ? 4 : 0)>::value>(); break;
+    case 5: wait_vmcnt<CopiesPerChunk<NT, WM, (WM > 5 ? 5 : 0)>::value>(); break;
+    case 6: wait_vmcnt<CopiesPerChunk<NT, WM, (WM > 6 ? 6 : 0)>::value>(); break;
+    default: wait_vmcnt<CopiesPerChunk<NT, WM, (WM > 7 ? 7 : 0)>::value>(); break;
   }
 }
 
-template <int NT>
-__global__ void __launch_bounds__(kThreads) dgemm_nn_dma_kernel(GemmArgs g) {
+template <int NT, int WM, bool RES>
+__global__ void __launch_bounds__(64 * WM) dgemm_nn_dma_kernel(GemmArgs g) {
   constexpr int BN = NT * 16;
   constexpr int BEL = kBK * BN;
   constexpr int NBQ = 2 * NT;            // 1 KB copies per B chunk
-  constexpr int AEL = kWM * 2 * 128;     // doubles per A stage
+  constexpr int AEL = WM * 2 * 128;      // doubles per A stage
   __shared__ __attribute__((aligned(16))) double B0[BEL];
   __shared__ __attribute__((aligned(16))) double B1[BEL];
   __shared__ __attribute__((aligned(16))) double B2[BEL];
@@ -341,27 +350,33 @@ __global__ void __launch_bounds__(kThreads) dgemm_nn_dma_kernel(GemmArgs g) {
   const int lane = threadIdx.x & 63;
   const int r = lane & 15;
   const int gq = lane >> 4;
-  const int64_t row0 = (int64_t)tm * (16 * kWM) + wave * 16;
+  const int64_t row0 = (int64_t)tm * (16 * WM) + wave * 16;
   const int64_t col0 = (int64_t)tn * BN;
   const double* __restrict__ A = g.A;
   const double* __restrict__ B = g.B;
   // source of this lane's A copies: row (clamped), k offset 4 gq + 2 h
   const double* asrc = A + min(row0 + r, g.M - 1) * g.lda + kb + 4 * gq;
 
-  auto issue = [&](int c, double* As, double* Bs) {
-    const int64_t k0 = (int64_t)c * kBK;
+  // per-lane copy sources, advanced by one chunk after every issue
+  constexpr int NQ = (NBQ + WM - 1) / WM;
+  const double* bsrc[NQ];
 #pragma unroll
-    for (int h = 0; h < 2; h++)
-      copy_to_lds16(asrc + k0 + 2 * h, As + (wave * 2 + h) * 128);
+  for (int i = 0; i < NQ; i++) {
+    const int q = min(wave + WM * i, NBQ - 1);
+    const int e = q * 128 + 2 * lane;  // element of the chunk this lane copies
+    const int kk = e / BN, cc = e % BN;
+    const int64_t col = min(col0 + cc, g.N - 2);  // columns past N are never stored
+    bsrc[i] = B + (kb + kk) * g.ldb + col;
+  }
+  const int64_t bstep = (int64_t)kBK * g.ldb;
+  auto issue = [&](double* As, double* Bs) {
 #pragma unroll
-    for (int i = 0; i < (NBQ + 3) / 4; i++) {
-      const int q = wave + 4 * i;
-      if (q < NBQ) {
-        const int e = q * 128 + 2 * lane;  // element of the chunk this lane copies
-        const int kk = e / BN, cc = e % BN;
-        const int64_t col = min(col0 + cc, g.N - 2);  // columns past N are never stored
-        copy_to_lds16(B + (kb + k0 + kk) * g.ldb + col, Bs + q * 128);
-      }
+    for (int h = 0; h < 2; h++) copy_to_lds16(asrc + 2 * h, As + (wave * 2 + h) * 128);
+    asrc += kBK;
+#pragma unroll
+    for (int i = 0; i < NQ; i++) {
+      if (wave + WM * i < NBQ) copy_to_lds16(bsrc[i], Bs + (wave + WM * i) * 128);
+      bsrc[i] += bstep;
     }
   };
 
@@ -369,7 +384,9 @@ __global__ void __launch_bounds__(kThreads) dgemm_nn_dma_kernel(GemmArgs g) {
 #pragma unroll
   for (int t = 0; t < NT; t++) acc[t] = (d4){0.0, 0.0, 0.0, 0.0};
 
-  auto compute = [&](const double* As, const double* Bs) {
+  // one MFMA step (4 k values) of a chunk; the copies of chunk c + 2 are
+  // issued after the first step so their address work overlaps the MFMAs
+  auto compute = [&](const double* As, const double* Bs, double* As2, double* Bs2, bool do_issue) {
     const double2 a01 = *reinterpret_cast<const double2*>(As + (wave * 2 + 0) * 128 + 2 * lane);
     const double2 a23 = *reinterpret_cast<const double2*>(As + (wave * 2 + 1) * 128 + 2 * lane);
     const double av[4] = {a01.x, a01.y, a23.x, a23.y};
@@ -380,22 +397,59 @@ __global__ void __launch_bounds__(kThreads) dgemm_nn_dma_kernel(GemmArgs g) {
       for (int t = 0; t < NT; t++) bf[t] = Bs[(4 * gq + s) * BN + 16 * t + r];
 #pragma unroll
       for (int t = 0; t < NT; t++) acc[t] = mfma_f64_16x16x4(av[s], bf[t], acc[t]);
+      if (s == 0 && do_issue) issue(As2, Bs2);
     }
   };
   auto step = [&](int c, double* As, double* Bs, double* As2, double* Bs2) {
-    wait_own_next<NT>(wave, c + 1 < nk);
+    wait_own_next<NT, WM>(wave, c + 1 < nk);
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");  // no LDS access moves across the barrier
-    if (c + 2 < nk) issue(c + 2, As2, Bs2);
-    compute(As, Bs);
+    compute(As, Bs, As2, Bs2, c + 2 < nk);
   };
 
-  if (nk > 0) issue(0, A0, B0);
-  if (nk > 1) issue(1, A1, B1);
+  if (nk > 0) issue(A0, B0);
+  if (nk > 1) issue(A1, B1);
   for (int c = 0; c < nk; c += 3) {
     step(c, A0, B0, A2, B2);
     if (c + 1 < nk) step(c + 1, A1, B1, A0, B0);
     if (c + 2 < nk) step(c + 2, A2, B2, A1, B1);
+  }
+  if constexpr (RES) {
+    // residual epilogue: sum (Aref - C)^2 and Aref^2 over the tile
+    double sd = 0.0, sa = 0.0;
+#pragma unroll
+    for (int t = 0; t < NT; t++) {
+#pragma unroll
+      for (int it = 0; it < 4; it++) {
+        const int64_t row = row0 + gq + 4 * it;
+        const int64_t col = col0 + 16 * t + r;
+        if (row < g.M && col < g.N) {
+          const double av = g.Aref[row * g.ldref + col];
+          const double dv = av - acc[t][it];
+          sd += dv * dv;
+          sa += av * av;
+        }
+      }
+    }
+    sd = wave_sum(sd);
+    sa = wave_sum(sa);
+    __syncthreads();
+    double* red = B0;  // the stages are no longer in use
+    if (lane == 0) {
+      red[wave] = sd;
+      red[WM + wave] = sa;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s0 = 0.0, s1 = 0.0;
+      for (int w = 0; w < WM; w++) {
+        s0 += red[w];
+        s1 += red[WM + w];
+      }
+      g.rpart[item] = s0;
+      g.rpart[total + item] = s1;
+    }
+    return;
   }
 
 #pragma unroll
@@ -418,9 +472,10 @@ __global__ void __launch_bounds__(kThreads) dgemm_nn_dma_kernel(GemmArgs g) {
   }
 }
 
+template <int WM, bool RES = false>
 hipError_t launch_dma(int nt, dim3 grid, hipStream_t st, const GemmArgs& a) {
   switch (nt) {
-#define RSVD_DCASE(X) case X: hipLaunchKernelGGL((dgemm_nn_dma_kernel<X>), grid, dim3(kThreads), 0, st, a); break;
+#define RSVD_DCASE(X) case X: hipLaunchKernelGGL((dgemm_nn_dma_kernel<X, WM, RES>), grid, dim3(64 * WM), 0, st, a); break;
     RSVD_DCASE(1) RSVD_DCASE(2) RSVD_DCASE(3) RSVD_DCASE(4) RSVD_DCASE(5) RSVD_DCASE(6)
     RSVD_DCASE(7) RSVD_DCASE(8) RSVD_DCASE(9) RSVD_DCASE(10) RSVD_DCASE(11) RSVD_DCASE(12)
     RSVD_DCASE(13) RSVD_DCASE(14) RSVD_DCASE(15) RSVD_DCASE(16) RSVD_DCASE(17)
@@ -462,7 +517,10 @@ hipError_t launch_nt(int nt, dim3 grid, hipStream_t st, const GemmArgs& a) {
 
 }  // namespace
 
-void dgemm_set_dma(bool on) { g_use_dma = on; }
+void dgemm_set_dma(bool on, int waves) {
+  g_use_dma = on;
+  if (waves == 4 || waves == 8) g_dma_wm = waves;
+}
 
 GemmShape dgemm_shape(int64_t M, int64_t N, int64_t K, int max_splits) {
   GemmShape s;
@@ -518,12 +576,37 @@ rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const 
   a.vec_b = (ldb % 2 == 0) && ((uintptr_t)B % 16 == 0);
   const int64_t total = (int64_t)s.tiles_m * s.tiles_n * s.splits;
   dim3 grid((unsigned)total);
-  // whole K chunks, even N and 16-byte aligned rows: the LDS-DMA pipeline
-  const bool dma_ok = !ta && (K % kBK == 0) && (s.kchunk % kBK == 0) && (N % 2 == 0) && N >= 2 &&
-                      a.vec_a && a.vec_b && g_use_dma;
-  hipError_t e = dma_ok ? launch_dma(s.nt, grid, st, a)
-                        : (ta ? launch_nt<true, false>(s.nt, grid, st, a)
-                              : launch_nt<false, false>(s.nt, grid, st, a));
+  // whole K chunks, even N and 16-byte aligned rows: the LDS-DMA pipeline.
+  // Its 3-stage LDS footprint allows one workgroup per CU, so it is sized to
+  // fill the 256 CUs once: split K only when the output has fewer tiles.
+  const bool dma_ok = !ta && (K % kBK == 0) && (N % 2 == 0) && N >= 2 && a.vec_a && a.vec_b &&
+                      g_use_dma;
+  hipError_t e;
+  if (dma_ok) {
+    // 8 waves need split K to fill the chip; without enough K use 4
+    int wm = g_dma_wm;
+    if (wm == 8 && (int64_t)((M + 127) / 128) * s.tiles_n < 256 && K / 2 < 256) wm = 4;
+    GemmArgs d = a;
+    d.tiles_m = (int)((M + 16 * wm - 1) / (16 * wm));
+    d.tiles_n = s.tiles_n;
+    const int64_t T = (int64_t)d.tiles_m * d.tiles_n;
+    int S = 1;
+    while (S < max_splits && T * S < 256 && K / (2 * S) >= 256) S *= 2;
+    int64_t kchunk = ((K + S - 1) / S + kBK - 1) / kBK * kBK;
+    S = (int)((K + kchunk - 1) / kchunk);
+    if (S > 1 && (part == nullptr || part_doubles < (size_t)S * M * N)) {
+      S = 1;
+      kchunk = K;
+    }
+    d.splits = S;
+    d.kchunk = kchunk;
+    d.part = S > 1 ? part : nullptr;
+    s.splits = S;
+    const dim3 g2((unsigned)(T * S));
+    e = wm == 8 ? launch_dma<8>(s.nt, g2, st, d) : launch_dma<4>(s.nt, g2, st, d);
+  } else {
+    e = ta ? launch_nt<true, false>(s.nt, grid, st, a) : launch_nt<false, false>(s.nt, grid, st, a);
+  }
   if (e != hipSuccess) return RSVD_EHIP;
   if (s.splits > 1) {
     const int64_t tot = M * N;
@@ -536,13 +619,39 @@ rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const 
 
 size_t resid_partials(int64_t M, int64_t N) {
   GemmShape s = dgemm_shape(M, N, 1, 1);
-  return (size_t)2 * s.tiles_m * s.tiles_n;
+  const size_t a = (size_t)2 * s.tiles_m * s.tiles_n;
+  const size_t b = (size_t)2 * ((M + 127) / 128) * s.tiles_n;
+  return a > b ? a : b;
+}
+
+size_t resid_partials_dma(int64_t M, int64_t N) {
+  const GemmShape sh = dgemm_shape(M, N, 1, 1);
+  return (size_t)2 * ((M + 127) / 128) * sh.tiles_n;
 }
 
 rsvd_status resid(int64_t M, int64_t N, int64_t K, const double* US, int64_t ldus,
                   const double* Vt, int64_t ldvt, const double* A, int64_t lda, double* partial,
                   DevState* st, hipStream_t s) {
   GemmShape sh = dgemm_shape(M, N, K, 1);
+  const bool dma_ok = (K % kBK == 0) && K > 0 && (N % 2 == 0) && N >= 2 && (ldus % 2 == 0) &&
+                      (ldvt % 2 == 0) && ((uintptr_t)US % 16 == 0) && ((uintptr_t)Vt % 16 == 0) &&
+                      g_use_dma;
+  if (dma_ok) {
+    GemmArgs a;
+    a.M = M; a.N = N; a.K = K; a.kchunk = K;
+    a.alpha = 1.0; a.beta = 0.0;
+    a.A = US; a.lda = ldus; a.B = Vt; a.ldb = ldvt; a.C = nullptr; a.ldc = 0;
+    a.part = nullptr;
+    a.tiles_m = (int)((M + 127) / 128); a.tiles_n = sh.tiles_n; a.splits = 1;
+    a.pred = nullptr; a.Aref = A; a.ldref = lda; a.rpart = partial;
+    a.vec_a = 1; a.vec_b = 1;
+    const int64_t total = (int64_t)a.tiles_m * a.tiles_n;
+    hipError_t e = launch_dma<8, true>(sh.nt, dim3((unsigned)total), s, a);
+    if (e != hipSuccess) return RSVD_EHIP;
+    rsvd_status r = sum_partials_into(total, partial, &st->resid2, s);
+    if (r != RSVD_OK) return r;
+    return sum_partials_into(total, partial + total, &st->fro2, s);
+  }
   GemmArgs a;
   a.M = M; a.N = N; a.K = K; a.kchunk = ((K + kBK - 1) / kBK) * kBK;
   a.alpha = 1.0; a.beta = 0.0;

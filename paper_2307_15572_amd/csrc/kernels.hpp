@@ -12,7 +12,8 @@ struct GemmShape {
   size_t part_doubles = 0;
 };
 GemmShape dgemm_shape(int64_t M, int64_t N, int64_t K, int max_splits = 64);
-void dgemm_set_dma(bool on);  // select the LDS-DMA streaming kernel where eligible
+// select the LDS-DMA streaming kernel where eligible, with 4 or 8 waves per workgroup
+void dgemm_set_dma(bool on, int waves = 4);
 rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                   int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                   double* part, size_t part_doubles, hipStream_t st, int max_splits = 64,
@@ -29,17 +30,19 @@ rsvd_status gaussian_omega(int64_t n, int64_t l, int64_t col0, uint64_t seed, ui
                            double* out, int64_t ldo, hipStream_t st);
 
 // ---- small dense l x l kernels (smalldense.hip) -----------------------------
-// Cholesky of the Gram G (l x l) into R (upper, R^T R = G [+ shift I]) and
+// Cholesky of the Gram G (l x l; overwritten, used as scratch) into R (upper,
+// R^T R = G [+ shift I]) and
 // Rinv = R^{-1}. pass 0 may switch to the shifted factorization (sets
 // st->qr_shifted); a pass with only_if_shifted != 0 does nothing unless
 // st->qr_shifted is set. m = rows of the panel (sizes the shift).
-rsvd_status chol_inv(int64_t l, const double* G, double* R, double* Rinv, int64_t m, int pass,
+rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, int64_t m, int pass,
                      int only_if_shifted, DevState* st, hipStream_t s);
 // Householder QR of the rows x l panel Yorig into Y (= Q) and R, run only
 // when st->qr_householder is set (tau: 2 l doubles of scratch).
 rsvd_status householder_fallback(int64_t rows, int64_t l, const double* Yorig, double* Y,
                                  double* R, double* tau, DevState* st, hipStream_t s);
-// Copy src -> dst (rows x cols, row-major) when st->qr_shifted (or always if !cond).
+// Copy src -> dst (rows x cols, row-major): always (cond 0), only when
+// st->qr_shifted is set (cond 1), only when it is clear (cond 2).
 rsvd_status copy_panel(int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst,
                        int64_t ldd, int cond_shifted, DevState* st, hipStream_t s);
 // One-sided Jacobi on the rows of M (l x l): P M0 = M with orthogonal rows.
@@ -58,8 +61,9 @@ rsvd_status select_rank(int64_t l, int64_t p, int64_t kc, int mode, double param
                         const double* s, DevState* st, hipStream_t hs);
 rsvd_status sign_fix(int64_t m, int64_t n, int64_t kc, double* U, int64_t ldu, double* V,
                      int64_t ldv, hipStream_t s);
-rsvd_status resid_prep(int64_t m, int64_t n, int64_t kc, const double* U, int64_t ldu,
-                       const double* s_vals, const double* V, int64_t ldv, double* US,
+// US = U diag(s) (m x kcp), Vt = V^T (kcp x n); columns / rows >= rank are zero
+rsvd_status resid_prep(int64_t m, int64_t n, int64_t kc, int64_t kcp, const double* U,
+                       int64_t ldu, const double* s_vals, const double* V, int64_t ldv, double* US,
                        double* Vt, const DevState* st, hipStream_t s);
 rsvd_status check_finite(int64_t rows, int64_t cols, const double* Y, int64_t ldy, DevState* st,
                          hipStream_t s);

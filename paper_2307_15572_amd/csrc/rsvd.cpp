@@ -127,12 +127,21 @@ struct Ws {
   T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
 };
 
-// Thin QR of the rows x l panel Y in place (Y <- Q). Shifted Cholesky QR:
-// pass 0 (unshifted, or shifted when the Gram is too ill-conditioned or
-// breaks down), pass 1, and pass 2 only when pass 0 took the shift.
+// Thin QR of the rows x l panel Y in place (Y <- Q) by Cholesky QR:
+//   pass 0  G = Y^T Y, R1 = chol(G), T = Y R1^{-1}. When the pivots of R1
+//           spread by more than 1e5 (or the factorization breaks down) the
+//           shifted factorization chol(G + s I) is used instead and the
+//           panel takes the three-pass route (shifted Cholesky QR3).
+//   pass 1  Y = T R2^{-1} with R2 = chol(T^T T)
+//   pass 2  only after a shifted pass 0: one more Cholesky QR pass.
+// full == false (an intermediate panel of the power iteration, where only
+// the span is used next): a well-conditioned panel stops after pass 0, whose
+// orthogonality error u kappa^2 <= 1e-6 does not change the span.
 // If Rout is non-null it receives the R factor (upper, l x l).
+// A panel that is rank deficient even for the shifted passes is refactored
+// by Householder QR from a saved copy.
 rsvd_status orth(const rsvd_plan_s& pl, const Ws& w, int64_t rows, double* Y, double* Rout,
-                 hipStream_t s) {
+                 hipStream_t s, bool full = true) {
   const int64_t l = pl.l;
   DevState* st = w.at<DevState>(pl.off_state);
   double* G = w.at<double>(pl.off_G);
@@ -144,11 +153,12 @@ rsvd_status orth(const rsvd_plan_s& pl, const Ws& w, int64_t rows, double* Y, do
   double* R2i = w.at<double>(pl.off_R2i);
   double* R3 = w.at<double>(pl.off_R3);
   double* R3i = w.at<double>(pl.off_R3i);
-  const uint32_t* shifted = &st->qr_shifted;
-  rsvd_status r;
-#define RSVD_TRY(x) do { r = (x); if (r != RSVD_OK) return r; } while (0)
   double* Yorig = w.at<double>(pl.off_Yorig);
   double* tau = w.at<double>(pl.off_tau);
+  const uint32_t* shifted = &st->qr_shifted;
+  const uint32_t* p1 = full ? nullptr : shifted;  // pass 1 runs always, or only after a shift
+  rsvd_status r;
+#define RSVD_TRY(x) do { r = (x); if (r != RSVD_OK) return r; } while (0)
   RSVD_TRY(clear_shift(st, s));
   RSVD_TRY(copy_panel(rows, l, Y, l, Yorig, l, 0, st, s));
   // pass 0
@@ -156,9 +166,10 @@ rsvd_status orth(const rsvd_plan_s& pl, const Ws& w, int64_t rows, double* Y, do
   RSVD_TRY(chol_inv(l, G, R1, R1i, rows, 0, 0, st, s));
   RSVD_TRY(dgemm(false, rows, l, l, 1.0, Y, l, R1i, l, 0.0, T, l, part, pl.part_doubles, s));
   // pass 1
-  RSVD_TRY(dgemm(true, l, l, rows, 1.0, T, l, T, l, 0.0, G, l, part, pl.part_doubles, s));
-  RSVD_TRY(chol_inv(l, G, R2, R2i, rows, 1, 0, st, s));
-  RSVD_TRY(dgemm(false, rows, l, l, 1.0, T, l, R2i, l, 0.0, Y, l, part, pl.part_doubles, s));
+  RSVD_TRY(dgemm(true, l, l, rows, 1.0, T, l, T, l, 0.0, G, l, part, pl.part_doubles, s, 64, p1));
+  RSVD_TRY(chol_inv(l, G, R2, R2i, rows, 1, full ? 0 : 1, st, s));
+  RSVD_TRY(dgemm(false, rows, l, l, 1.0, T, l, R2i, l, 0.0, Y, l, part, pl.part_doubles, s, 64, p1));
+  if (!full) RSVD_TRY(copy_panel(rows, l, T, l, Y, l, 2, st, s));  // unshifted: Q = T
   // pass 2 (device-predicated on the shift)
   RSVD_TRY(dgemm(true, l, l, rows, 1.0, Y, l, Y, l, 0.0, G, l, part, pl.part_doubles, s, 64, shifted));
   RSVD_TRY(chol_inv(l, G, R3, R3i, rows, 2, 1, st, s));
@@ -266,8 +277,9 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* worksp
   pl->off_Ub = c.take((size_t)m * kc * D);
   pl->off_Vb = c.take((size_t)n * kc * D);
   if (p.want_residual) {
-    pl->off_US = c.take((size_t)m * kc * D);
-    pl->off_Vt = c.take((size_t)n * kc * D);
+    const int64_t kcp = (kc + 15) / 16 * 16;
+    pl->off_US = c.take((size_t)m * kcp * D);
+    pl->off_Vt = c.take((size_t)n * kcp * D);
     pl->off_rpart = c.take(resid_partials(m, n) * D);
   }
   pl->total = c.at;
@@ -329,23 +341,25 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
     return dgemm(trans, rows_out, l, inner, 1.0, A, lda, X, ldx, 0.0, out, l, part,
                  pl.part_doubles, s);
   };
-  auto qr = [&](int64_t rows, double* panel, double* Rout) -> rsvd_status {
+  auto qr = [&](int64_t rows, double* panel, double* Rout, bool full) -> rsvd_status {
     PhaseScope ph(1, s);
-    return orth(pl, w, rows, panel, Rout, s);
+    return orth(pl, w, rows, panel, Rout, s, full);
   };
   RSVD_TRY(stream_pass(false, Om, ldom, Y, m, n));
   RSVD_TRY(check_finite(m, l, Y, l, st, s));
-  RSVD_TRY(qr(m, Y, nullptr));
+  // the basis that B = Q^T A is taken against must be orthonormal to working
+  // accuracy; bases inside the power iteration only carry the span forward
+  RSVD_TRY(qr(m, Y, nullptr, p.power_iters == 0));
   // power iterations
   for (int t = 0; t < p.power_iters; t++) {
     RSVD_TRY(stream_pass(!p.symmetric, Y, l, Z, n, m));
-    RSVD_TRY(qr(n, Z, nullptr));
+    RSVD_TRY(qr(n, Z, nullptr, false));
     RSVD_TRY(stream_pass(false, Z, l, Y, m, n));
-    RSVD_TRY(qr(m, Y, nullptr));
+    RSVD_TRY(qr(m, Y, nullptr, t + 1 == p.power_iters));
   }
   // step 2: Y^T = A^T Q = Q_B X_B, small SVD of X_B^T
   RSVD_TRY(stream_pass(!p.symmetric, Y, l, Z, n, m));
-  RSVD_TRY(qr(n, Z, Rt));
+  RSVD_TRY(qr(n, Z, Rt, true));
   {
     PhaseScope ph(2, s);
     RSVD_TRY(block_jacobi(l, Rt, Mj, Pj, p.max_sweeps > 0 ? p.max_sweeps : 30, 1, st, s));
@@ -369,8 +383,9 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
     PhaseScope ph(4, s);
     double* US = w.at<double>(pl.off_US);
     double* Vt = w.at<double>(pl.off_Vt);
-    RSVD_TRY(resid_prep(m, n, kc, Uo, lduo, sig, Vo, ldvo, US, Vt, st, s));
-    RSVD_TRY(resid(m, n, kc, US, kc, Vt, n, A, lda, w.at<double>(pl.off_rpart), st, s));
+    const int64_t kcp = (kc + 15) / 16 * 16;  // padded with zero columns / rows
+    RSVD_TRY(resid_prep(m, n, kc, kcp, Uo, lduo, sig, Vo, ldvo, US, Vt, st, s));
+    RSVD_TRY(resid(m, n, kcp, US, kcp, Vt, n, A, lda, w.at<double>(pl.off_rpart), st, s));
   }
   RSVD_TRY(finalize(m, n, l, p.want_residual, st, res_dev, s));
   return RSVD_OK;

@@ -434,25 +434,42 @@ __device__ bool tiled_factor(const TileCtx& cx, double* W, double* Xg, double* p
       for (int it = 0; it < 4; it++) panel[(g + 4 * it) * ps + 16 * J + r] = o[it];
     }
     __syncthreads();
-    // trailing tiles
+    // trailing tiles, four per wave at a time so their L2 round trips overlap
     const int n = nb - k - 1;
     const int T = n * (n + 1) / 2;
-    for (int tt = wave; tt < T; tt += nw) {
+    constexpr int TB = 4;
+    for (int t0 = wave * TB; t0 < T; t0 += nw * TB) {
+      int Is[TB], Js[TB];
+      double tl[TB][4];
       int I, J;
-      trailing_coords(tt, n, I, J);
-      I += k + 1;
-      J += k + 1;
-      double t[4];
-      load_tile(cx, W, I, J, t);
-      d4 acc = {t[0], t[1], t[2], t[3]};
+      trailing_coords(t0, n, I, J);
 #pragma unroll
-      for (int s = 0; s < 4; s++) {
-        const double a = -panel[(4 * s + g) * ps + 16 * I + r];
-        const double bb = panel[(4 * s + g) * ps + 16 * J + r];
-        acc = mfma_f64_16x16x4(a, bb, acc);
+      for (int q = 0; q < TB; q++) {
+        // consecutive tiles of the upper triangle, row-major
+        Is[q] = I + k + 1;
+        Js[q] = J + k + 1;
+        if (++J >= n) {
+          I++;
+          J = I;
+        }
       }
-      double o[4] = {acc[0], acc[1], acc[2], acc[3]};
-      store_tile(cx, W, I, J, o);
+#pragma unroll
+      for (int q = 0; q < TB; q++)
+        if (t0 + q < T) load_tile(cx, W, Is[q], Js[q], tl[q]);
+#pragma unroll
+      for (int q = 0; q < TB; q++) {
+        if (t0 + q < T) {
+          d4 acc = {tl[q][0], tl[q][1], tl[q][2], tl[q][3]};
+#pragma unroll
+          for (int s = 0; s < 4; s++) {
+            const double a = -panel[(4 * s + g) * ps + 16 * Is[q] + r];
+            const double bb = panel[(4 * s + g) * ps + 16 * Js[q] + r];
+            acc = mfma_f64_16x16x4(a, bb, acc);
+          }
+          double o[4] = {acc[0], acc[1], acc[2], acc[3]};
+          store_tile(cx, W, Is[q], Js[q], o);
+        }
+      }
     }
     __syncthreads();
   }
@@ -464,47 +481,77 @@ __device__ bool tiled_factor(const TileCtx& cx, double* W, double* Xg, double* p
   return true;
 }
 
-// X = R^{-1}: diagonal tiles already in Xg; block rows from the bottom.
-__device__ void tiled_inverse(const TileCtx& cx, const double* W, double* Xg, double* panel,
-                              double* dinv) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
-  const int nw = blockDim.x >> 6;
-  const int nb = cx.nb, ps = cx.ps, l = cx.l;
-  for (int I = nb - 2; I >= 0; I--) {
-    // stage block row I of R (columns >= 16 (I + 1)) and X_II
-    const int c0 = 16 * (I + 1);
-    const int width = 16 * nb - c0;
-    for (int e = threadIdx.x; e < 16 * width; e += blockDim.x) {
-      const int i = 16 * I + e / width, c = c0 + e % width;
-      panel[(e / width) * ps + c] = (i < l && c < l) ? W[(int64_t)i * l + c] : 0.0;
-    }
-    for (int e = threadIdx.x; e < 256; e += blockDim.x) {
-      const int i = 16 * I + e / 16, c = 16 * I + e % 16;
-      dinv[(e / 16) * 17 + e % 16] = (i < l && c < l) ? Xg[(int64_t)i * l + c] : (i == c ? 1.0 : 0.0);
-    }
-    __syncthreads();
-    for (int J = I + 1 + wave; J < nb; J += nw) {
-      d4 acc = {0.0, 0.0, 0.0, 0.0};
-      for (int K = I + 1; K <= J; K++) {
-        double xb[4];
-        load_tile(cx, Xg, K, J, xb);  // rows 16K + g + 4s: B operand of step s
+// Tile in the MFMA A-operand layout: lane (r, g), item t holds entry (r, g + 4 t).
+__device__ __forceinline__ void load_tile_a(const TileCtx& cx, const double* W, int I, int J,
+                                            double t[4]) {
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
 #pragma unroll
-        for (int s = 0; s < 4; s++) {
-          const double a = panel[r * ps + 16 * K + 4 * s + g];  // R_IK[r][4s + g]
-          acc = mfma_f64_16x16x4(a, xb[s], acc);
-        }
-      }
-      d4 out = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s = 0; s < 4; s++) out = mfma_f64_16x16x4(-dinv[r * 17 + 4 * s + g], acc[s], out);
-      double o[4] = {out[0], out[1], out[2], out[3]};
-      store_tile(cx, Xg, I, J, o);
-    }
-    __syncthreads();
+  for (int it = 0; it < 4; it++) {
+    const int i = 16 * I + r, c = 16 * J + g + 4 * it;
+    t[it] = cx.in(i, c) ? W[(int64_t)i * cx.l + c] : (i == c ? 1.0 : 0.0);
   }
 }
 
-__global__ void __launch_bounds__(512) chol_tiles_kernel(int l, const double* __restrict__ G,
+// X = R^{-1} by recursive doubling on tile blocks: with the inverses X11, X22
+// of two adjacent diagonal blocks known, the off-diagonal block of the inverse
+// of [[R11, R12], [0, R22]] is -X11 R12 X22. Block sizes 1, 2, 4, ... tiles;
+// every level runs T = R12 X22 into the scratch S, then X12 = -X11 T.
+// Diagonal tiles of X are already in Xg.
+__device__ void tiled_inverse(const TileCtx& cx, const double* W, double* Xg, double* S) {
+  const int wave = threadIdx.x >> 6;
+  const int nw = blockDim.x >> 6;
+  const int nb = cx.nb;
+  constexpr int KB = 4;
+  for (int bs = 1; bs < nb; bs *= 2) {
+    for (int phase = 0; phase < 2; phase++) {
+      // enumerate the output tiles (i, j) of all block pairs of this level
+      int count = 0;
+      for (int a = 0; a + bs < nb; a += 2 * bs) {
+        const int b1 = a + bs, b2 = min(a + 2 * bs, nb);
+        count += bs * (b2 - b1);
+      }
+      for (int t = wave; t < count; t += nw) {
+        int a = 0, rem = t, b1 = 0, b2 = 0;
+        for (;; a += 2 * bs) {
+          b1 = a + bs;
+          b2 = min(a + 2 * bs, nb);
+          const int c = bs * (b2 - b1);
+          if (rem < c) break;
+          rem -= c;
+        }
+        const int i = a + rem / (b2 - b1), j = b1 + rem % (b2 - b1);
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+        // phase 0: T_ij = sum_{k in [b1, j]} R_ik X_kj ; phase 1: X_ij = -sum_{k in [i, b1)} X_ik T_kj
+        const int k0 = phase == 0 ? b1 : i;
+        const int k1 = phase == 0 ? j + 1 : b1;
+        for (int kb = k0; kb < k1; kb += KB) {
+          double ta[KB][4], tb[KB][4];
+#pragma unroll
+          for (int q = 0; q < KB; q++) {
+            if (kb + q < k1) {
+              load_tile_a(cx, phase == 0 ? W : Xg, i, kb + q, ta[q]);
+              load_tile(cx, phase == 0 ? Xg : S, kb + q, j, tb[q]);
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < KB; q++) {
+            if (kb + q < k1) {
+#pragma unroll
+              for (int s = 0; s < 4; s++) acc = mfma_f64_16x16x4(ta[q][s], tb[q][s], acc);
+            }
+          }
+        }
+        double o[4];
+#pragma unroll
+        for (int it = 0; it < 4; it++) o[it] = phase == 0 ? acc[it] : -acc[it];
+        store_tile(cx, phase == 0 ? S : Xg, i, j, o);
+      }
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void __launch_bounds__(512) chol_tiles_kernel(int l, double* __restrict__ G,
                                                           double* __restrict__ R,
                                                           double* __restrict__ Rinv, int64_t m,
                                                           int pass, int only_if_shifted,
@@ -551,7 +598,8 @@ __global__ void __launch_bounds__(512) chol_tiles_kernel(int l, const double* __
     }
     __syncthreads();
   }
-  tiled_inverse(cx, R, Rinv, panel, dinv);
+  // G is no longer read: it serves as scratch for the inverse
+  tiled_inverse(cx, R, Rinv, G);
   // strictly lower parts are zero
   for (int64_t e = threadIdx.x; e < ll; e += blockDim.x) {
     if (e / l > e % l) {
@@ -566,7 +614,9 @@ __global__ void __launch_bounds__(256) copy_panel_kernel(int64_t rows, int64_t c
                                                          const double* __restrict__ src, int64_t lds,
                                                          double* __restrict__ dst, int64_t ldd,
                                                          int cond, const DevState* st) {
-  if (cond && st->qr_shifted == 0) return;
+  // cond 1: copy only after a shifted pass 0; cond 2: only when unshifted
+  if (cond == 1 && st->qr_shifted == 0) return;
+  if (cond == 2 && st->qr_shifted != 0) return;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= rows * cols) return;
   const int64_t r = idx / cols, c = idx % cols;
@@ -811,6 +861,7 @@ __global__ void __launch_bounds__(256) sign_fix_kernel(int64_t m, int64_t n, dou
 
 // US = U diag(s) (columns >= rank zeroed), Vt = V^T (rows >= rank zeroed).
 __global__ void __launch_bounds__(256) resid_prep_kernel(int64_t m, int64_t n, int64_t kc,
+                                                         int64_t kcp,
                                                          const double* __restrict__ U, int64_t ldu,
                                                          const double* __restrict__ s,
                                                          const double* __restrict__ V, int64_t ldv,
@@ -818,13 +869,13 @@ __global__ void __launch_bounds__(256) resid_prep_kernel(int64_t m, int64_t n, i
                                                          double* __restrict__ Vt,
                                                          const DevState* st) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t rank = st->rank;
-  if (idx < m * kc) {
-    const int64_t i = idx / kc, j = idx % kc;
+  const int64_t rank = st->rank < kc ? st->rank : kc;
+  if (idx < m * kcp) {
+    const int64_t i = idx / kcp, j = idx % kcp;  // US is m x kcp
     US[idx] = j < rank ? U[i * ldu + j] * s[j] : 0.0;
   }
-  if (idx < n * kc) {
-    const int64_t j = idx / n, i = idx % n;  // Vt is kc x n
+  if (idx < n * kcp) {
+    const int64_t j = idx / n, i = idx % n;  // Vt is kcp x n
     Vt[idx] = j < rank ? V[i * ldv + j] : 0.0;
   }
 }
@@ -941,7 +992,7 @@ size_t chol_tiles_lds(int64_t l) {
   return (size_t)(16 * (16 * nb + 1) + 16 * 17) * sizeof(double);
 }
 
-rsvd_status chol_inv(int64_t l, const double* G, double* R, double* Rinv, int64_t m, int pass,
+rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, int64_t m, int pass,
                      int only_if_shifted, DevState* st, hipStream_t s) {
   allow_big_lds();
   const size_t tl = chol_tiles_lds(l);
@@ -1016,12 +1067,12 @@ rsvd_status sign_fix(int64_t m, int64_t n, int64_t kc, double* U, int64_t ldu, d
   return RSVD_OK;
 }
 
-rsvd_status resid_prep(int64_t m, int64_t n, int64_t kc, const double* U, int64_t ldu,
-                       const double* sv, const double* V, int64_t ldv, double* US, double* Vt,
-                       const DevState* st, hipStream_t s) {
-  const int64_t tot = (m > n ? m : n) * kc;
-  hipLaunchKernelGGL(resid_prep_kernel, dim3(blocks_for(tot, 256)), dim3(256), 0, s, m, n, kc, U,
-                     ldu, sv, V, ldv, US, Vt, st);
+rsvd_status resid_prep(int64_t m, int64_t n, int64_t kc, int64_t kcp, const double* U,
+                       int64_t ldu, const double* sv, const double* V, int64_t ldv, double* US,
+                       double* Vt, const DevState* st, hipStream_t s) {
+  const int64_t tot = (m > n ? m : n) * kcp;
+  hipLaunchKernelGGL(resid_prep_kernel, dim3(blocks_for(tot, 256)), dim3(256), 0, s, m, n, kc, kcp,
+                     U, ldu, sv, V, ldv, US, Vt, st);
   RSVD_LAUNCH_CHECK();
   return RSVD_OK;
 }
