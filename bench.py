@@ -32,6 +32,15 @@ METRIC = "rSVD matrix GB/s + % HBM/MFMA roofline, mixed vs FP64 at 1e-6 rel σ e
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (vector = matrix)
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 
+# HBM bytes per launch of the streaming product, from rocprofv3 --pmc FETCH_SIZE
+# and WRITE_SIZE runs of this benchmark (profiles/rsvd_fp64_16384sq_symmetric_traffic.md).
+# FETCH_SIZE is scaled by 2.0 and WRITE_SIZE by 1.0: what the counters read
+# for a plain 1 GiB copy kernel. Valid only for the GEMM source they were
+# taken with; any other source reports traffic as null.
+TRAFFIC_SOURCE_SHA256 = "7cb1249af65a4ad1"
+TRAFFIC_FETCH_BYTES = 1122900 * 1024 * 2.0
+TRAFFIC_WRITE_BYTES = 69632 * 1024 * 1.0
+
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
@@ -123,10 +132,16 @@ def main():
     gemm_avg_s = gemm_ms / gemm_cnt * 1e-3
     flops_per_launch = 2.0 * w.m * w.n * l
     achieved = flops_per_launch / gemm_avg_s / 1e12
+    import hashlib
+    src = os.path.join(ROOT, "paper_2307_15572_amd", "csrc", "gemm.hip")
+    same = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] == TRAFFIC_SOURCE_SHA256
+    traffic = round(TRAFFIC_FETCH_BYTES + TRAFFIC_WRITE_BYTES) if same else None
     roofline = {
         "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-        "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": None,
-        "kernel": "dgemm_kernel<TA=false, NT=17> (A x 272-column panel)",
+        "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
+        "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+        "algorithmic_bytes": 8.0 * w.m * w.n + 8.0 * (w.n + w.m) * l,
+        "kernel": "dgemm_nn_dma_kernel<NT=17, 8 waves> (A x 272-column panel, LDS-DMA pipeline)",
         "flops_per_launch": flops_per_launch, "avg_ms": round(gemm_avg_s * 1e3, 4),
         "launches": int(gemm_cnt),
     }
