@@ -163,6 +163,41 @@ def main():
                    "flags": int(res.flags)},
     }
 
+    # mixed precision: FP32 matrix cores for the early products, the last
+    # product before the projection and everything after it in FP64
+    mixed = {}
+    for prec, thp in (("mixed_fp32", 1), ("mixed_bf16", 1)):
+        mplan = rs.Plan(w.m, w.n, k, p, q, symmetric=w.symmetric, seed=w.seed, want_residual=True,
+                        precision=prec, trailing_hp=thp)
+        mb = mplan.allocate(dev)
+        for _ in range(args.warmup):
+            mplan.run_into(A, mb)
+        torch.cuda.synchronize()
+        f0 = torch.cuda.Event(enable_timing=True)
+        f1 = torch.cuda.Event(enable_timing=True)
+        f0.record(stream)
+        for _ in range(args.steps):
+            mplan.run_into(A, mb)
+        f1.record(stream)
+        torch.cuda.synchronize()
+        mms = f0.elapsed_time(f1) / args.steps
+        mres = mplan.result(mb)
+        s64 = bufs["S"][: res.rank].cpu().numpy()
+        smx = mb["S"][: mres.rank].cpu().numpy()
+        kk = min(res.rank, mres.rank)
+        rel = float((np.abs(smx[:kk] - s64[:kk]) / s64[:kk]).max())
+        mixed[prec] = {
+            "value": round(passes * a_bytes / (mms * 1e-3) / 1e9, 3), "unit": "GB/s",
+            "ms_per_step": round(mms, 4), "trailing_fp64_products": thp,
+            "speedup_vs_fp64": round(ms_step / mms, 4),
+            "max_rel_sigma_err_vs_fp64": rel,
+            "meets_1e-6_gate": rel <= 1e-6,
+            "residual": mres.residual,
+        }
+        del mb, mplan
+        log(f"{prec}: {mms:.3f} ms/step, max rel sigma err vs FP64 {rel:.2e}")
+    out["mixed"] = mixed
+
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         cb, ref = cpu_baseline(A_np, w, k, p, q)

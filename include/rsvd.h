@@ -80,8 +80,9 @@ typedef struct rsvd_problem {
   double rank_param;     /* R% for PERCENT, tau for the threshold rules            */
   int32_t oversample;    /* p >= 0 (the paper uses p = 5)                          */
   int32_t power_iters;   /* q >= 0 (0 = the paper's method)                        */
-  int32_t precision;     /* RSVD_PREC_*                                            */
-  int32_t trailing_hp;   /* mixed modes: number of trailing products kept in FP64  */
+  int32_t precision;     /* RSVD_PREC_* (BF16_SPLIT: RSVD_EUNSUPPORTED)            */
+  int32_t trailing_hp;   /* mixed modes: how many of the last products before the
+                            projection stay FP64 (the projection always does)      */
   uint64_t seed;         /* key word 0 of the Philox stream that draws P           */
   uint64_t channel;      /* key word 1 (symmetry channel index)                    */
   int32_t want_u;        /* write U (m x rank)                                     */
@@ -114,8 +115,12 @@ typedef struct rsvd_plan_s* rsvd_plan_t;
  *                   workspaces.
  *   workspace_bytes receives the device workspace size rsvd_run needs.
  * Returns RSVD_EINVAL for m, n < 1, k < 1 (fixed rule), p < 0, q < 0,
- * R% outside (0, 100], tau outside (0, 1), an unknown mode, or k_cap < the
- * fixed rank; RSVD_EUNSUPPORTED for a precision mode this build lacks.
+ * R% outside (0, 100], tau outside (0, 1), an unknown mode, trailing_hp < 0,
+ * or k_cap < the fixed rank; RSVD_EUNSUPPORTED for a precision mode this
+ * build lacks. Mixed modes: of the 2q + 1 products before the projection
+ * (sketch and power products), all but the last trailing_hp run on FP32 or
+ * BF16 matrix cores with FP32 accumulation; the projection, every QR, the
+ * small SVD and the residual stay FP64.
  */
 rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* workspace_bytes);
 
@@ -170,6 +175,17 @@ rsvd_status rsvd_dgemm(int32_t trans_a, int64_t m, int64_t n, int64_t k, double 
                        const double* A, int64_t lda, const double* B, int64_t ldb,
                        double beta, double* C, int64_t ldc, void* work, size_t work_bytes,
                        void* stream);
+
+/* rsvd_gemm - the same product with the arithmetic of a precision mode:
+ * RSVD_PREC_FP64 (= rsvd_dgemm), RSVD_PREC_MIXED_FP32 (operands rounded to
+ * FP32, FP32 matrix cores, FP32 accumulation) or RSVD_PREC_MIXED_BF16
+ * (operands rounded to BF16, BF16 matrix cores, FP32 accumulation). Inputs
+ * and output stay FP64 in memory; work as for rsvd_dgemm. These are the
+ * early products of the precision schedule of the mixed modes. */
+rsvd_status rsvd_gemm(int32_t precision, int32_t trans_a, int64_t m, int64_t n, int64_t k,
+                      double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                      double beta, double* C, int64_t ldc, void* work, size_t work_bytes,
+                      void* stream);
 
 /* rsvd_orth - thin QR of a tall panel Y (m x l, ldy, device, m >= l), step 1's
  * "QR decomposition Z = Q X": Y is overwritten by Q (orthonormal columns,

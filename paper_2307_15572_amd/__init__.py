@@ -26,7 +26,7 @@ FLAG_ZERO_SIGMA = 1 << 5
 
 EXPORTED = (
     "rsvd_plan", "rsvd_plan_l", "rsvd_run", "rsvd_destroy", "rsvd_strerror",
-    "rsvd_gaussian_omega", "rsvd_dgemm_work_bytes", "rsvd_dgemm",
+    "rsvd_gaussian_omega", "rsvd_dgemm_work_bytes", "rsvd_dgemm", "rsvd_gemm",
     "rsvd_orth_work_bytes", "rsvd_orth", "rsvd_small_svd_work_bytes", "rsvd_small_svd",
     "rsvd_trace_enable", "rsvd_trace_collect",
 )
@@ -89,6 +89,8 @@ def lib():
     L.rsvd_dgemm_work_bytes.restype = sz
     L.rsvd_dgemm.argtypes = [i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, vp, sz, vp]
     L.rsvd_dgemm.restype = ctypes.c_int
+    L.rsvd_gemm.argtypes = [i32, i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, vp, sz, vp]
+    L.rsvd_gemm.restype = ctypes.c_int
     L.rsvd_orth_work_bytes.argtypes = [i64, i64]
     L.rsvd_orth_work_bytes.restype = sz
     L.rsvd_orth.argtypes = [i64, i64, vp, i64, vp, vp, vp, sz, vp]
@@ -261,8 +263,9 @@ def gaussian_omega(n, l, seed, channel=0, col0=0, device="cuda"):
     return out
 
 
-def dgemm(A, B, trans_a=False, alpha=1.0, beta=0.0, C=None):
-    """C = alpha op(A) B + beta C on the FP64 matrix cores."""
+def dgemm(A, B, trans_a=False, alpha=1.0, beta=0.0, C=None, precision="fp64"):
+    """C = alpha op(A) B + beta C on the matrix cores (FP64 unless a mixed
+    precision mode is named: "mixed_fp32" or "mixed_bf16")."""
     torch = _torch()
     _check_matrix(torch, A, "A")
     _check_matrix(torch, B, "B")
@@ -276,9 +279,10 @@ def dgemm(A, B, trans_a=False, alpha=1.0, beta=0.0, C=None):
     L = lib()
     wb = L.rsvd_dgemm_work_bytes(m, n, k, int(trans_a))
     work = torch.empty(max(wb // 8, 1), dtype=torch.float64, device=A.device)
-    _check(L.rsvd_dgemm(int(trans_a), m, n, k, alpha, _ptr(A), A.stride(0), _ptr(B), B.stride(0),
-                        beta, _ptr(C), C.stride(0), _ptr(work), wb, _stream(torch, A.device)),
-           "rsvd_dgemm")
+    _check(L.rsvd_gemm(PRECISIONS[precision], int(trans_a), m, n, k, alpha, _ptr(A), A.stride(0),
+                       _ptr(B), B.stride(0), beta, _ptr(C), C.stride(0), _ptr(work), wb,
+                       _stream(torch, A.device)),
+           "rsvd_gemm")
     return C
 
 

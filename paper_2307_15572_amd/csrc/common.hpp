@@ -22,6 +22,32 @@ __device__ __forceinline__ d4 mfma_f64_16x16x4(double a, double b, d4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// ---- FP32 / BF16 matrix-core tiles (FP32 accumulation) ---------------------
+// v_mfma_f32_16x16x4f32: A lane l holds A[l % 16][l / 16], B lane l holds
+// B[l / 16][l % 16]; D lane l, item t holds D[4 (l / 16) + t][l % 16].
+// v_mfma_f32_16x16x16bf16_1k: lane l holds 4 consecutive k values
+// 4 (l / 16) .. 4 (l / 16) + 3 of row (A) / column (B) l % 16; D as above.
+typedef short s4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ f4 mfma_f32_16x16x4(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4 mfma_bf16_16x16x16(s4 a, s4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+// FP64 -> BF16 bits: round to FP32 (nearest even), then to BF16 (nearest even).
+__device__ __forceinline__ short bf16_bits(double x) {
+  const float f = (float)x;
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (short)0x7fc0;  // NaN
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+// Arithmetic of a streaming product: FP64 MFMA, FP32 MFMA, or BF16 MFMA (both
+// with FP32 accumulation). Operands stay FP64 in memory and are rounded when
+// they enter the matrix core.
+enum Prec { kPrecF64 = 0, kPrecF32 = 1, kPrecBF16 = 2 };
+
 // ---- wave reductions --------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -38,6 +38,52 @@ constexpr int kMaxNT = 17;  // 17 x 16 = 272 columns per workgroup
 #endif
 constexpr int kAPF = RSVD_GEMM_APF;
 
+template <int PREC> struct AccType { using type = d4; };
+template <> struct AccType<kPrecF32> { using type = f4; };
+template <> struct AccType<kPrecBF16> { using type = f4; };
+
+// row of the 16 x 16 output tile held by accumulator item `it` of lane group g
+template <int PREC>
+__device__ __forceinline__ int acc_row(int g, int it) {
+  return PREC == kPrecF64 ? g + 4 * it : 4 * g + it;
+}
+
+// One chunk of 16 k values for NT tiles: av[s] = A(row r, k = 4 g + s),
+// Bs holds the chunk's 16 x BN block of B. Each precision uses its own
+// matrix-core instruction; the lane-group-to-k assignment is the same.
+template <int PREC, int NT, int BN>
+__device__ __forceinline__ void chunk_mma(typename AccType<PREC>::type (&acc)[NT], const double av[4],
+                                          const double* Bs, int g, int r) {
+  if constexpr (PREC == kPrecF64) {
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+      double bf[NT];
+#pragma unroll
+      for (int t = 0; t < NT; t++) bf[t] = Bs[(4 * g + s) * BN + 16 * t + r];
+#pragma unroll
+      for (int t = 0; t < NT; t++) acc[t] = mfma_f64_16x16x4(av[s], bf[t], acc[t]);
+    }
+  } else if constexpr (PREC == kPrecF32) {
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+      float bf[NT];
+#pragma unroll
+      for (int t = 0; t < NT; t++) bf[t] = (float)Bs[(4 * g + s) * BN + 16 * t + r];
+      const float a = (float)av[s];
+#pragma unroll
+      for (int t = 0; t < NT; t++) acc[t] = mfma_f32_16x16x4(a, bf[t], acc[t]);
+    }
+  } else {
+    const s4 a = {bf16_bits(av[0]), bf16_bits(av[1]), bf16_bits(av[2]), bf16_bits(av[3])};
+#pragma unroll
+    for (int t = 0; t < NT; t++) {
+      const double* col = Bs + 4 * g * BN + 16 * t + r;
+      const s4 b = {bf16_bits(col[0]), bf16_bits(col[BN]), bf16_bits(col[2 * BN]), bf16_bits(col[3 * BN])};
+      acc[t] = mfma_bf16_16x16x16(a, b, acc[t]);
+    }
+  }
+}
+
 struct GemmArgs {
   int64_t M, N, K, kchunk;
   double alpha, beta;
@@ -53,7 +99,7 @@ struct GemmArgs {
   int vec_a, vec_b;        // 16-byte loads allowed (even leading dimension, aligned base)
 };
 
-template <bool TA, int NT, bool RES>
+template <bool TA, int NT, bool RES, int PREC>
 __global__ void __launch_bounds__(kThreads) dgemm_kernel(GemmArgs g) {
   constexpr int BN = NT * 16;
   constexpr int BEL = kBK * BN;
@@ -91,9 +137,10 @@ __global__ void __launch_bounds__(kThreads) dgemm_kernel(GemmArgs g) {
   const bool vec_a = !TA && g.vec_a;
   const bool vec_b = g.vec_b && (col0 + BN <= g.N);
 
-  d4 acc[NT];
+  using Acc = typename AccType<PREC>::type;
+  Acc acc[NT];
 #pragma unroll
-  for (int t = 0; t < NT; t++) acc[t] = (d4){0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t < NT; t++) acc[t] = Acc{0, 0, 0, 0};
 
   double a_cur[4], a_nxt[4];
   // scalar staging uses BPER slots, the 16-byte path 2 * BPER2 (NT + 1 for odd NT)
@@ -167,16 +214,7 @@ __global__ void __launch_bounds__(kThreads) dgemm_kernel(GemmArgs g) {
       if (idx < BEL) Bs[buf][idx] = b_stage[i];
     }
   };
-  auto compute = [&](const double* bs) {
-#pragma unroll
-    for (int s = 0; s < 4; s++) {
-      double bf[NT];
-#pragma unroll
-      for (int t = 0; t < NT; t++) bf[t] = bs[(4 * gq + s) * BN + 16 * t + r];
-#pragma unroll
-      for (int t = 0; t < NT; t++) acc[t] = mfma_f64_16x16x4(a_cur[s], bf[t], acc[t]);
-    }
-  };
+  auto compute = [&](const double* bs) { chunk_mma<PREC, NT, BN>(acc, a_cur, bs, gq, r); };
 
   const int nk = nfull + (tail ? 1 : 0);
   // A ring: a_q[j] holds chunk c + j (j = 0 .. kAPF-1); B goes one chunk ahead via LDS
@@ -217,11 +255,11 @@ __global__ void __launch_bounds__(kThreads) dgemm_kernel(GemmArgs g) {
     for (int t = 0; t < NT; t++) {
 #pragma unroll
       for (int it = 0; it < 4; it++) {
-        const int64_t row = row0 + gq + 4 * it;
+        const int64_t row = row0 + acc_row<PREC>(gq, it);
         const int64_t col = col0 + 16 * t + r;
         if (row < g.M && col < g.N) {
           const double a = g.Aref[row * g.ldref + col];
-          const double d = a - acc[t][it];
+          const double d = a - (double)acc[t][it];
           sd += d * d;
           sa += a * a;
         }
@@ -250,10 +288,10 @@ __global__ void __launch_bounds__(kThreads) dgemm_kernel(GemmArgs g) {
   for (int t = 0; t < NT; t++) {
 #pragma unroll
     for (int it = 0; it < 4; it++) {
-      const int64_t row = row0 + gq + 4 * it;
+      const int64_t row = row0 + acc_row<PREC>(gq, it);
       const int64_t col = col0 + 16 * t + r;
       if (row < g.M && col < g.N) {
-        const double v = acc[t][it];
+        const double v = (double)acc[t][it];
         if (g.part) {
           g.part[((int64_t)z * g.M + row) * g.N + col] = v;
         } else {
@@ -320,7 +358,7 @@ __device__ __forceinline__ void wait_own_next(int wave, bool next_pending) {
   }
 }
 
-template <int NT, int WM, bool RES>
+template <int NT, int WM, bool RES, int PREC>
 __global__ void __launch_bounds__(64 * WM) dgemm_nn_dma_kernel(GemmArgs g) {
   constexpr int BN = NT * 16;
   constexpr int BEL = kBK * BN;
@@ -380,25 +418,19 @@ __global__ void __launch_bounds__(64 * WM) dgemm_nn_dma_kernel(GemmArgs g) {
     }
   };
 
-  d4 acc[NT];
+  using Acc = typename AccType<PREC>::type;
+  Acc acc[NT];
 #pragma unroll
-  for (int t = 0; t < NT; t++) acc[t] = (d4){0.0, 0.0, 0.0, 0.0};
+  for (int t = 0; t < NT; t++) acc[t] = Acc{0, 0, 0, 0};
 
-  // one MFMA step (4 k values) of a chunk; the copies of chunk c + 2 are
-  // issued after the first step so their address work overlaps the MFMAs
+  // one chunk; the copies of chunk c + 2 are issued first (their LDS stage
+  // was released by the barrier)
   auto compute = [&](const double* As, const double* Bs, double* As2, double* Bs2, bool do_issue) {
+    if (do_issue) issue(As2, Bs2);
     const double2 a01 = *reinterpret_cast<const double2*>(As + (wave * 2 + 0) * 128 + 2 * lane);
     const double2 a23 = *reinterpret_cast<const double2*>(As + (wave * 2 + 1) * 128 + 2 * lane);
     const double av[4] = {a01.x, a01.y, a23.x, a23.y};
-#pragma unroll
-    for (int s = 0; s < 4; s++) {
-      double bf[NT];
-#pragma unroll
-      for (int t = 0; t < NT; t++) bf[t] = Bs[(4 * gq + s) * BN + 16 * t + r];
-#pragma unroll
-      for (int t = 0; t < NT; t++) acc[t] = mfma_f64_16x16x4(av[s], bf[t], acc[t]);
-      if (s == 0 && do_issue) issue(As2, Bs2);
-    }
+    chunk_mma<PREC, NT, BN>(acc, av, Bs, gq, r);
   };
   auto step = [&](int c, double* As, double* Bs, double* As2, double* Bs2) {
     wait_own_next<NT, WM>(wave, c + 1 < nk);
@@ -421,11 +453,11 @@ __global__ void __launch_bounds__(64 * WM) dgemm_nn_dma_kernel(GemmArgs g) {
     for (int t = 0; t < NT; t++) {
 #pragma unroll
       for (int it = 0; it < 4; it++) {
-        const int64_t row = row0 + gq + 4 * it;
+        const int64_t row = row0 + acc_row<PREC>(gq, it);
         const int64_t col = col0 + 16 * t + r;
         if (row < g.M && col < g.N) {
           const double av = g.Aref[row * g.ldref + col];
-          const double dv = av - acc[t][it];
+          const double dv = av - (double)acc[t][it];
           sd += dv * dv;
           sa += av * av;
         }
@@ -456,10 +488,10 @@ __global__ void __launch_bounds__(64 * WM) dgemm_nn_dma_kernel(GemmArgs g) {
   for (int t = 0; t < NT; t++) {
 #pragma unroll
     for (int it = 0; it < 4; it++) {
-      const int64_t row = row0 + gq + 4 * it;
+      const int64_t row = row0 + acc_row<PREC>(gq, it);
       const int64_t col = col0 + 16 * t + r;
       if (row < g.M && col < g.N) {
-        const double v = acc[t][it];
+        const double v = (double)acc[t][it];
         if (g.part) {
           g.part[((int64_t)z * g.M + row) * g.N + col] = v;
         } else {
@@ -470,19 +502,6 @@ __global__ void __launch_bounds__(64 * WM) dgemm_nn_dma_kernel(GemmArgs g) {
       }
     }
   }
-}
-
-template <int WM, bool RES = false>
-hipError_t launch_dma(int nt, dim3 grid, hipStream_t st, const GemmArgs& a) {
-  switch (nt) {
-#define RSVD_DCASE(X) case X: hipLaunchKernelGGL((dgemm_nn_dma_kernel<X, WM, RES>), grid, dim3(64 * WM), 0, st, a); break;
-    RSVD_DCASE(1) RSVD_DCASE(2) RSVD_DCASE(3) RSVD_DCASE(4) RSVD_DCASE(5) RSVD_DCASE(6)
-    RSVD_DCASE(7) RSVD_DCASE(8) RSVD_DCASE(9) RSVD_DCASE(10) RSVD_DCASE(11) RSVD_DCASE(12)
-    RSVD_DCASE(13) RSVD_DCASE(14) RSVD_DCASE(15) RSVD_DCASE(16) RSVD_DCASE(17)
-#undef RSVD_DCASE
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
 }
 
 // C = alpha * sum_z part[z] + beta * C, summed in split order.
@@ -502,10 +521,10 @@ __global__ void __launch_bounds__(256) splitk_reduce_kernel(int64_t M, int64_t N
   C[row * ldc + col] = o;
 }
 
-template <bool TA, bool RES>
+template <bool TA, bool RES, int PREC>
 hipError_t launch_nt(int nt, dim3 grid, hipStream_t st, const GemmArgs& a) {
   switch (nt) {
-#define RSVD_CASE(X) case X: hipLaunchKernelGGL((dgemm_kernel<TA, X, RES>), grid, dim3(kThreads), 0, st, a); break;
+#define RSVD_CASE(X) case X: hipLaunchKernelGGL((dgemm_kernel<TA, X, RES, PREC>), grid, dim3(kThreads), 0, st, a); break;
     RSVD_CASE(1) RSVD_CASE(2) RSVD_CASE(3) RSVD_CASE(4) RSVD_CASE(5) RSVD_CASE(6)
     RSVD_CASE(7) RSVD_CASE(8) RSVD_CASE(9) RSVD_CASE(10) RSVD_CASE(11) RSVD_CASE(12)
     RSVD_CASE(13) RSVD_CASE(14) RSVD_CASE(15) RSVD_CASE(16) RSVD_CASE(17)
@@ -513,6 +532,33 @@ hipError_t launch_nt(int nt, dim3 grid, hipStream_t st, const GemmArgs& a) {
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+template <bool TA>
+hipError_t launch_nt_prec(int prec, int nt, dim3 grid, hipStream_t st, const GemmArgs& a) {
+  if (prec == kPrecF32) return launch_nt<TA, false, kPrecF32>(nt, grid, st, a);
+  if (prec == kPrecBF16) return launch_nt<TA, false, kPrecBF16>(nt, grid, st, a);
+  return launch_nt<TA, false, kPrecF64>(nt, grid, st, a);
+}
+
+template <int WM, bool RES, int PREC>
+hipError_t launch_dma(int nt, dim3 grid, hipStream_t st, const GemmArgs& a) {
+  switch (nt) {
+#define RSVD_DCASE(X) case X: hipLaunchKernelGGL((dgemm_nn_dma_kernel<X, WM, RES, PREC>), grid, dim3(64 * WM), 0, st, a); break;
+    RSVD_DCASE(1) RSVD_DCASE(2) RSVD_DCASE(3) RSVD_DCASE(4) RSVD_DCASE(5) RSVD_DCASE(6)
+    RSVD_DCASE(7) RSVD_DCASE(8) RSVD_DCASE(9) RSVD_DCASE(10) RSVD_DCASE(11) RSVD_DCASE(12)
+    RSVD_DCASE(13) RSVD_DCASE(14) RSVD_DCASE(15) RSVD_DCASE(16) RSVD_DCASE(17)
+#undef RSVD_DCASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int WM>
+hipError_t launch_dma_prec(int prec, int nt, dim3 grid, hipStream_t st, const GemmArgs& a) {
+  if (prec == kPrecF32) return launch_dma<WM, false, kPrecF32>(nt, grid, st, a);
+  if (prec == kPrecBF16) return launch_dma<WM, false, kPrecBF16>(nt, grid, st, a);
+  return launch_dma<WM, false, kPrecF64>(nt, grid, st, a);
 }
 
 }  // namespace
@@ -546,7 +592,7 @@ GemmShape dgemm_shape(int64_t M, int64_t N, int64_t K, int max_splits) {
 rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                   int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                   double* part, size_t part_doubles, hipStream_t st, int max_splits,
-                  const uint32_t* pred) {
+                  const uint32_t* pred, int prec) {
   if (M <= 0 || N <= 0) return RSVD_OK;
   if (K <= 0) {
     // C = beta * C
@@ -603,9 +649,10 @@ rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const 
     d.part = S > 1 ? part : nullptr;
     s.splits = S;
     const dim3 g2((unsigned)(T * S));
-    e = wm == 8 ? launch_dma<8>(s.nt, g2, st, d) : launch_dma<4>(s.nt, g2, st, d);
+    e = wm == 8 ? launch_dma_prec<8>(prec, s.nt, g2, st, d) : launch_dma_prec<4>(prec, s.nt, g2, st, d);
   } else {
-    e = ta ? launch_nt<true, false>(s.nt, grid, st, a) : launch_nt<false, false>(s.nt, grid, st, a);
+    e = ta ? launch_nt_prec<true>(prec, s.nt, grid, st, a)
+           : launch_nt_prec<false>(prec, s.nt, grid, st, a);
   }
   if (e != hipSuccess) return RSVD_EHIP;
   if (s.splits > 1) {
@@ -646,7 +693,7 @@ rsvd_status resid(int64_t M, int64_t N, int64_t K, const double* US, int64_t ldu
     a.pred = nullptr; a.Aref = A; a.ldref = lda; a.rpart = partial;
     a.vec_a = 1; a.vec_b = 1;
     const int64_t total = (int64_t)a.tiles_m * a.tiles_n;
-    hipError_t e = launch_dma<8, true>(sh.nt, dim3((unsigned)total), s, a);
+    hipError_t e = launch_dma<8, true, kPrecF64>(sh.nt, dim3((unsigned)total), s, a);
     if (e != hipSuccess) return RSVD_EHIP;
     rsvd_status r = sum_partials_into(total, partial, &st->resid2, s);
     if (r != RSVD_OK) return r;
@@ -662,7 +709,7 @@ rsvd_status resid(int64_t M, int64_t N, int64_t K, const double* US, int64_t ldu
   a.vec_a = (ldus % 2 == 0) && ((uintptr_t)US % 16 == 0);
   a.vec_b = (ldvt % 2 == 0) && ((uintptr_t)Vt % 16 == 0);
   const int64_t total = (int64_t)sh.tiles_m * sh.tiles_n;
-  hipError_t e = launch_nt<false, true>(sh.nt, dim3((unsigned)total), s, a);
+  hipError_t e = launch_nt<false, true, kPrecF64>(sh.nt, dim3((unsigned)total), s, a);
   if (e != hipSuccess) return RSVD_EHIP;
   rsvd_status r = sum_partials_into(total, partial, &st->resid2, s);
   if (r != RSVD_OK) return r;

@@ -17,7 +17,7 @@ void dgemm_set_dma(bool on, int waves = 4);
 rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                   int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                   double* part, size_t part_doubles, hipStream_t st, int max_splits = 64,
-                  const uint32_t* pred = nullptr);
+                  const uint32_t* pred = nullptr, int prec = kPrecF64);
 // ||A - US * Vt||_F^2 and ||A||_F^2 accumulated into st->resid2 / st->fro2
 // (US: M x K, Vt: K x N, A: M x N). partial: >= resid_partials(M, N) doubles.
 size_t resid_partials(int64_t M, int64_t N);

@@ -208,7 +208,9 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* worksp
   const rsvd_problem& p = *prob;
   if (p.m < 1 || p.n < 1 || p.oversample < 0 || p.power_iters < 0) return RSVD_EINVAL;
   if (p.symmetric && p.m != p.n) return RSVD_EINVAL;
-  if (p.precision != RSVD_PREC_FP64) return RSVD_EUNSUPPORTED;
+  if (p.precision < RSVD_PREC_FP64 || p.precision > RSVD_PREC_MIXED_BF16_SPLIT) return RSVD_EINVAL;
+  if (p.precision == RSVD_PREC_MIXED_BF16_SPLIT) return RSVD_EUNSUPPORTED;
+  if (p.trailing_hp < 0) return RSVD_EINVAL;
   int64_t k = p.k;
   int mode = p.rank_mode;
   double param = p.rank_param;
@@ -335,11 +337,21 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
     Om = Z;
     ldom = l;
   }
+  // precision schedule: of the 2q + 1 products before the projection, all but
+  // the last trailing_hp use the low-precision matrix cores in mixed modes;
+  // the projection, QR, small SVD and residual are always FP64
+  const int n_early = 2 * p.power_iters + 1;
+  const int lowp = p.precision == RSVD_PREC_MIXED_FP32   ? kPrecF32
+                   : p.precision == RSVD_PREC_MIXED_BF16 ? kPrecBF16
+                                                         : kPrecF64;
+  int product = 0;
   auto stream_pass = [&](bool trans, const double* X, int64_t ldx, double* out, int64_t rows_out,
                          int64_t inner) -> rsvd_status {
     PhaseScope ph(0, s);
+    const int prec = product < n_early - p.trailing_hp ? lowp : kPrecF64;
+    product++;
     return dgemm(trans, rows_out, l, inner, 1.0, A, lda, X, ldx, 0.0, out, l, part,
-                 pl.part_doubles, s);
+                 pl.part_doubles, s, 64, nullptr, prec);
   };
   auto qr = [&](int64_t rows, double* panel, double* Rout, bool full) -> rsvd_status {
     PhaseScope ph(1, s);
@@ -396,6 +408,25 @@ rsvd_status rsvd_gaussian_omega(int64_t n, int64_t l, int64_t col0, uint64_t see
                                 uint64_t channel, double* out, int64_t ldo, void* stream) {
   if (n < 0 || l < 0 || col0 < 0 || (n > 0 && l > 0 && (!out || ldo < l))) return RSVD_EINVAL;
   return gaussian_omega(n, l, col0, seed, channel, out, ldo, (hipStream_t)stream);
+}
+
+rsvd_status rsvd_gemm(int32_t precision, int32_t trans_a, int64_t m, int64_t n, int64_t k,
+                      double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
+                      double beta, double* C, int64_t ldc, void* work, size_t work_bytes,
+                      void* stream) {
+  if (precision < RSVD_PREC_FP64 || precision > RSVD_PREC_MIXED_BF16) return RSVD_EINVAL;
+  if (m < 0 || n < 0 || k < 0) return RSVD_EINVAL;
+  if (m == 0 || n == 0) return RSVD_OK;
+  if (!C || ldc < n) return RSVD_EINVAL;
+  if (k > 0) {
+    if (!A || !B || ldb < n) return RSVD_EINVAL;
+    if (trans_a ? lda < m : lda < k) return RSVD_EINVAL;
+  }
+  const int prec = precision == RSVD_PREC_MIXED_FP32 ? kPrecF32
+                   : precision == RSVD_PREC_MIXED_BF16 ? kPrecBF16
+                                                       : kPrecF64;
+  return dgemm(trans_a != 0, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, (double*)work,
+               work_bytes / sizeof(double), (hipStream_t)stream, 64, nullptr, prec);
 }
 
 size_t rsvd_dgemm_work_bytes(int64_t m, int64_t n, int64_t k, int32_t trans_a) {

@@ -127,3 +127,30 @@ def test_small_svd_matches_lapack(l, decay):
     assert np.abs(R.T - (Us * s) @ W.T).max() <= 1e-13 * ref[0] * max(1, l / 10)
     assert np.abs(Us.T @ Us - np.eye(l)).max() <= 1e-12
     assert np.abs(W.T @ W - np.eye(l)).max() <= 1e-12
+
+
+LOWP_CASES = [("mixed_fp32", False, 517, 272, 1000), ("mixed_fp32", False, 2048, 272, 8192),
+              ("mixed_fp32", True, 272, 272, 4096), ("mixed_fp32", False, 100, 50, 77),
+              ("mixed_bf16", False, 517, 272, 1000), ("mixed_bf16", False, 2048, 272, 8192),
+              ("mixed_bf16", True, 300, 100, 2000), ("mixed_bf16", False, 33, 18, 16)]
+
+
+@pytest.mark.parametrize("prec,ta,m,n,k", LOWP_CASES)
+def test_lowp_gemm_error_bound(prec, ta, m, n, k):
+    # operands rounded to the format (unit roundoff u_in) and products summed in
+    # FP32 (u32): |C - C_ref| <= (2 u_in + (k + 2) u32) (|A| |B|) componentwise
+    import paper_2307_15572_amd as rs
+    announce(f"gemm {prec} ta={ta} m={m} n={n} k={k}")
+    rng = np.random.default_rng(m + 3 * n + 7 * k)
+    A = rng.standard_normal((k, m) if ta else (m, k))
+    B = rng.standard_normal((k, n))
+    opA = A.T if ta else A
+    ref = opA @ B
+    got = rs.dgemm(to_dev(A), to_dev(B), trans_a=ta, precision=prec).cpu().numpy()
+    u_in = 2.0 ** -24 if prec == "mixed_fp32" else 2.0 ** -8
+    u32 = 2.0 ** -24
+    bound = (2 * u_in + (k + 2) * u32) * (np.abs(opA) @ np.abs(B))
+    assert np.all(np.abs(got - ref) <= bound)
+    # and it is not secretly FP64: the error is at the format's level
+    if prec == "mixed_bf16" and k >= 1000:
+        assert np.abs(got - ref).max() > 1e3 * 2.0 ** -53 * np.abs(ref).max()
