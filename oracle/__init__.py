@@ -39,3 +39,4 @@ from .method import (  # noqa: F401
     relative_rank_percent,
     sign_normalize,
 )
+from .adaptive import rsvd_adaptive, FLAG_ADAPT_LIMIT, POSTERIOR_FACTOR  # noqa: F401

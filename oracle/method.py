@@ -129,7 +129,8 @@ def select_rank(s_all, mode, param, l, p, k_cap, fro2_A=None):
         raise ValueError("percent rank is resolved at plan time; pass it as fixed")
     elif mode == RANK_REL_THRESHOLD:
         tau = float(param)
-        k = int(np.count_nonzero(s_all >= tau * s_all[0])) if len(s_all) else 0
+        # an all-zero projection has no value above the threshold (k = 1 below)
+        k = int(np.count_nonzero(s_all >= tau * s_all[0])) if len(s_all) and s_all[0] > 0 else 0
         cap = max(l - p, 1)
         if k > cap:
             k = cap
