@@ -67,7 +67,8 @@ enum {
   RSVD_FLAG_QR_FALLBACK = 1u << 2,     /* Cholesky QR broke down (rank-deficient panel): Householder QR used */
   RSVD_FLAG_JACOBI_MAXSWEEP = 1u << 3, /* small SVD stopped at max_sweeps            */
   RSVD_FLAG_NONFINITE_INPUT = 1u << 4, /* A holds NaN or Inf                         */
-  RSVD_FLAG_ZERO_SIGMA = 1u << 5       /* a singular value is exactly zero           */
+  RSVD_FLAG_ZERO_SIGMA = 1u << 5,      /* a singular value is exactly zero           */
+  RSVD_FLAG_ADAPT_LIMIT = 1u << 6      /* adaptive growth stopped at l_max           */
 };
 
 typedef struct rsvd_problem {
@@ -89,6 +90,10 @@ typedef struct rsvd_problem {
   int32_t want_v;        /* write V (n x rank)                                     */
   int32_t want_residual; /* stream A once more for ||A - U S V^T||_F / ||A||_F     */
   int32_t max_sweeps;    /* Jacobi sweep limit for the small SVD; 0 = 30           */
+  int32_t adaptive;      /* 1: grow l block by block (adaptive range finder, below);
+                            threshold rules only, FP64 only, k is ignored          */
+  int32_t block;         /* adaptive: columns added per growth step (1..256; 0 = 64) */
+  int64_t l_max;         /* adaptive: largest l (0 = min(m, n, 4096))              */
 } rsvd_problem;
 
 /* Result record, written to DEVICE memory by rsvd_run (so runs stay
@@ -103,6 +108,12 @@ typedef struct rsvd_result {
   double fro2;           /* ||A||_F^2                                              */
   int32_t sweeps;        /* Jacobi sweeps used by the small SVD                    */
   uint32_t flags;        /* RSVD_FLAG_*                                            */
+  double err_est;        /* adaptive: last error estimate of the basis (posterior
+                            estimate of ||(I - QQ^T) A||_2 for REL_THRESHOLD, the
+                            Frobenius indicator sqrt(||A||_F^2 - ||Q^T A||_F^2) for
+                            FROB_TAIL); NaN for a fixed-l run                      */
+  int32_t blocks;        /* adaptive: growth steps taken (0 for a fixed-l run)     */
+  int32_t reserved;
 } rsvd_result;
 
 typedef struct rsvd_plan_s* rsvd_plan_t;
@@ -116,15 +127,40 @@ typedef struct rsvd_plan_s* rsvd_plan_t;
  *   workspace_bytes receives the device workspace size rsvd_run needs.
  * Returns RSVD_EINVAL for m, n < 1, k < 1 (fixed rule), p < 0, q < 0,
  * R% outside (0, 100], tau outside (0, 1), an unknown mode, trailing_hp < 0,
- * or k_cap < the fixed rank; RSVD_EUNSUPPORTED for a precision mode this
- * build lacks. Mixed modes: of the 2q + 1 products before the projection
- * (sketch and power products), all but the last trailing_hp run on FP32 or
+ * or k_cap < the fixed rank, and for an adaptive problem with a fixed or
+ * percent rule, block outside 0..256 or l_max < 0; RSVD_EUNSUPPORTED for a
+ * precision mode this build lacks or an adaptive problem in a mixed mode.
+ * Mixed modes: of the 2q + 1 products before the projection (sketch and
+ * power products), all but the last trailing_hp run on FP32 or
  * BF16 matrix cores with FP32 accumulation; the projection, every QR, the
  * small SVD and the residual stay FP64.
  */
 rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* workspace_bytes);
 
-/* Sketch width l of a plan (host query). */
+/*
+ * Adaptive range finder (problem.adaptive = 1). The paper fixes l before the
+ * projection; with a threshold rule the rank, and so l, is not known in
+ * advance. The basis Q then grows by blocks of b columns of the same
+ * projection stream (columns l .. l+b-1, so P never depends on l), following
+ * the blocked adaptive range finder of Halko, Martinsson and Tropp (SIAM
+ * Rev. 2011, section 4.4) with the power scheme and Frobenius indicator of
+ * blocked randQB (Martinsson and Voronin 2016; Yu, Gu and Li 2018):
+ *   W = (I - QQ^T) A P_blk; est = 10 sqrt(2/pi) max_j ||W_j|| bounds
+ *   ||(I - QQ^T) A||_2 except with probability 10^-b (section 4.3 there).
+ *   REL_THRESHOLD: stop when est <= tau * (largest row norm of Q^T A) and the
+ *     small SVD of the current projection keeps at most l - p values.
+ *   otherwise Q_b = orth(W) (re-orthonormalized against Q), q power steps on
+ *     (I - QQ^T) A, Y_b = Q_b^T A, Q = [Q Q_b], l += b.
+ *   FROB_TAIL: stop when ||A||_F^2 - ||Q^T A||_F^2 <= tau^2 ||A||_F^2 and the
+ *     rule keeps at most l - p values.
+ * Steps 2 and 3 then run on the final basis. The growth decisions are taken
+ * on the host: an adaptive rsvd_run synchronizes its stream once or twice per
+ * block and cannot be captured in a graph. omega must be NULL. U, V, S
+ * receive min(k_cap, l_used) columns / values; the workspace is sized for
+ * l_max.
+ */
+
+/* Sketch width l of a plan (host query; l_max for an adaptive plan). */
 int64_t rsvd_plan_l(rsvd_plan_t plan);
 
 /*

@@ -23,6 +23,7 @@ FLAG_QR_FALLBACK = 1 << 2
 FLAG_JACOBI_MAXSWEEP = 1 << 3
 FLAG_NONFINITE_INPUT = 1 << 4
 FLAG_ZERO_SIGMA = 1 << 5
+FLAG_ADAPT_LIMIT = 1 << 6
 
 EXPORTED = (
     "rsvd_plan", "rsvd_plan_l", "rsvd_run", "rsvd_destroy", "rsvd_strerror",
@@ -48,6 +49,7 @@ class Problem(ctypes.Structure):
         ("seed", ctypes.c_uint64), ("channel", ctypes.c_uint64),
         ("want_u", ctypes.c_int32), ("want_v", ctypes.c_int32),
         ("want_residual", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+        ("adaptive", ctypes.c_int32), ("block", ctypes.c_int32), ("l_max", ctypes.c_int64),
     ]
 
 
@@ -57,6 +59,7 @@ class Result(ctypes.Structure):
         ("residual", ctypes.c_double), ("rel_percent", ctypes.c_double),
         ("c_eq2", ctypes.c_double), ("c_sym", ctypes.c_double), ("fro2", ctypes.c_double),
         ("sweeps", ctypes.c_int32), ("flags", ctypes.c_uint32),
+        ("err_est", ctypes.c_double), ("blocks", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -156,14 +159,21 @@ class RsvdOutput:
     fro2: float
     sweeps: int
     flags: int
+    err_est: float = float("nan")   # adaptive: last error estimate of the basis
+    blocks: int = 0                 # adaptive: growth steps
 
 
 class Plan:
-    """An immutable plan for one problem shape (wraps rsvd_plan)."""
+    """An immutable plan for one problem shape (wraps rsvd_plan).
+
+    adaptive=True grows l by blocks of `block` columns up to l_max (the
+    adaptive range finder of the C ABI); k is then ignored and rank_mode must
+    be "rel_threshold" or "frob_tail" with rank_param = tau.
+    """
 
     def __init__(self, m, n, k, p, q, *, symmetric=False, rank_mode="fixed", rank_param=None,
                  precision="fp64", trailing_hp=1, seed=0, channel=0, want_u=True, want_v=True,
-                 want_residual=True, max_sweeps=0, k_cap=0):
+                 want_residual=True, max_sweeps=0, k_cap=0, adaptive=False, block=0, l_max=0):
         L = lib()
         pr = Problem()
         pr.m, pr.n, pr.k, pr.k_cap = int(m), int(n), int(k), int(k_cap)
@@ -176,6 +186,7 @@ class Plan:
         pr.seed, pr.channel = int(seed) & (2**64 - 1), int(channel) & (2**64 - 1)
         pr.want_u, pr.want_v = int(bool(want_u)), int(bool(want_v))
         pr.want_residual, pr.max_sweeps = int(bool(want_residual)), int(max_sweeps)
+        pr.adaptive, pr.block, pr.l_max = int(bool(adaptive)), int(block), int(l_max)
         self.problem = pr
         h = ctypes.c_void_p()
         ws = ctypes.c_size_t()
@@ -249,7 +260,8 @@ def run(A, k, p, q, *, omega=None, **kw):
         S=bufs["S"][:rank], U=bufs["U"][:, :rank] if bufs["U"] is not None else None,
         V=bufs["V"][:, :rank] if bufs["V"] is not None else None, rank=rank, l=int(r.l_used),
         residual=r.residual, rel_percent=r.rel_percent, c_eq2=r.c_eq2, c_sym=r.c_sym,
-        fro2=r.fro2, sweeps=int(r.sweeps), flags=int(r.flags),
+        fro2=r.fro2, sweeps=int(r.sweeps), flags=int(r.flags), err_est=r.err_est,
+        blocks=int(r.blocks),
     )
 
 

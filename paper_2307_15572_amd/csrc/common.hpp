@@ -69,6 +69,12 @@ struct DevState {
   int32_t rank;          // chosen rank
   double fro2;           // ||A||_F^2
   double resid2;         // ||A - U S V^T||_F^2
+  int32_t rank_wanted;   // rank the rule asked for before the l - p / k_cap caps
+  int32_t pad_;
+  // adaptive range finder
+  double est2;           // max_j ||W_j||^2 of the latest deflated sketch block
+  double s1lb2;          // largest squared row norm of Q^T A so far (<= sigma_1^2)
+  double froY2;          // ||Q^T A||_F^2 so far
   uint32_t rot_count[64];  // rotations per Jacobi sweep (convergence test)
 };
 

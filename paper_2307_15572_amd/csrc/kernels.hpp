@@ -69,8 +69,15 @@ rsvd_status check_finite(int64_t rows, int64_t cols, const double* Y, int64_t ld
                          hipStream_t s);
 rsvd_status sumsq(int64_t m, int64_t n, const double* A, int64_t lda, double* partial,
                   DevState* st, hipStream_t s);
-rsvd_status finalize(int64_t m, int64_t n, int64_t l, int want_residual, const DevState* st,
-                     rsvd_result* res, hipStream_t s);
+rsvd_status finalize(int64_t m, int64_t n, int64_t l, int want_residual, double err_est,
+                     int blocks, const DevState* st, rsvd_result* res, hipStream_t s);
+// st->flags = (st->flags & ~clear) | set
+rsvd_status clear_flags(DevState* st, uint32_t clear, uint32_t set, hipStream_t s);
+// Column sums of squares of X (rows x cols <= 256, row-major): mode 0 sets
+// st->est2 to their maximum; mode 1 raises st->s1lb2 to their maximum and
+// adds their sum to st->froY2. partial: scratch of partial_doubles >= cols.
+rsvd_status colsumsq(int64_t rows, int cols, const double* X, int64_t ld, double* partial,
+                     size_t partial_doubles, int mode, DevState* st, hipStream_t s);
 rsvd_status init_state(DevState* st, uint32_t flags, hipStream_t s);
 rsvd_status clear_shift(DevState* st, hipStream_t s);
 rsvd_status sum_partials_into(int64_t cnt, const double* p, double* out, hipStream_t s);

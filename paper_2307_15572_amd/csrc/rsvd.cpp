@@ -82,6 +82,10 @@ struct rsvd_plan_s {
   size_t off_Rt = 0, off_Rtmp = 0, off_M = 0, off_P = 0, off_sig = 0, off_Us = 0, off_W = 0;
   size_t off_Ub = 0, off_Vb = 0, off_US = 0, off_Vt = 0, off_rpart = 0;
   size_t off_Yorig = 0, off_tau = 0;
+  // adaptive range finder: l above is l_max; blocks of blk columns
+  bool adaptive = false;
+  int64_t blk = 0;
+  size_t off_Wb = 0, off_Zb = 0, off_Ob = 0, off_Cb = 0, off_Zc = 0;
   size_t part_doubles = 0;
   size_t total = 0;
 };
@@ -127,7 +131,8 @@ struct Ws {
   T* at(size_t off) const { return reinterpret_cast<T*>(base + off); }
 };
 
-// Thin QR of the rows x l panel Y in place (Y <- Q) by Cholesky QR:
+// Thin QR of the rows x l panel Y (contiguous, ld = l) in place (Y <- Q) by
+// Cholesky QR (l <= the plan's l):
 //   pass 0  G = Y^T Y, R1 = chol(G), T = Y R1^{-1}. When the pivots of R1
 //           spread by more than 1e5 (or the factorization breaks down) the
 //           shifted factorization chol(G + s I) is used instead and the
@@ -140,9 +145,8 @@ struct Ws {
 // If Rout is non-null it receives the R factor (upper, l x l).
 // A panel that is rank deficient even for the shifted passes is refactored
 // by Householder QR from a saved copy.
-rsvd_status orth(const rsvd_plan_s& pl, const Ws& w, int64_t rows, double* Y, double* Rout,
-                 hipStream_t s, bool full = true) {
-  const int64_t l = pl.l;
+rsvd_status orth(const rsvd_plan_s& pl, const Ws& w, int64_t rows, int64_t l, double* Y,
+                 double* Rout, hipStream_t s, bool full = true) {
   DevState* st = w.at<DevState>(pl.off_state);
   double* G = w.at<double>(pl.off_G);
   double* T = w.at<double>(pl.off_T);
@@ -211,15 +215,17 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* worksp
   if (p.precision < RSVD_PREC_FP64 || p.precision > RSVD_PREC_MIXED_BF16_SPLIT) return RSVD_EINVAL;
   if (p.precision == RSVD_PREC_MIXED_BF16_SPLIT) return RSVD_EUNSUPPORTED;
   if (p.trailing_hp < 0) return RSVD_EINVAL;
+  const bool adaptive = p.adaptive != 0;
   int64_t k = p.k;
   int mode = p.rank_mode;
   double param = p.rank_param;
   switch (mode) {
     case RSVD_RANK_FIXED:
-      if (k < 1) return RSVD_EINVAL;
+      if (adaptive || k < 1) return RSVD_EINVAL;
       param = (double)k;
       break;
     case RSVD_RANK_PERCENT:
+      if (adaptive) return RSVD_EINVAL;
       if (!(p.rank_param > 0.0 && p.rank_param <= 100.0)) return RSVD_EINVAL;
       k = percent_rank(p.rank_param, p.m, p.n);
       mode = RSVD_RANK_FIXED;
@@ -228,14 +234,23 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* worksp
     case RSVD_RANK_REL_THRESHOLD:
     case RSVD_RANK_FROB_TAIL:
       if (!(p.rank_param > 0.0 && p.rank_param < 1.0)) return RSVD_EINVAL;
-      if (k < 1) return RSVD_EINVAL;
+      if (!adaptive && k < 1) return RSVD_EINVAL;
       break;
     default:
       return RSVD_EINVAL;
   }
   const int64_t mn = p.m < p.n ? p.m : p.n;
-  int64_t l = k + p.oversample;
-  if (l > mn) l = mn;
+  int64_t l = 0, blk = 0;
+  if (adaptive) {
+    if (p.block < 0 || p.block > 256 || p.l_max < 0) return RSVD_EINVAL;
+    if (p.precision != RSVD_PREC_FP64) return RSVD_EUNSUPPORTED;
+    blk = p.block > 0 ? p.block : 64;
+    l = p.l_max > 0 ? p.l_max : 4096;
+    if (l > mn) l = mn;
+  } else {
+    l = k + p.oversample;
+    if (l > mn) l = mn;
+  }
   if (l > 4096) return RSVD_EUNSUPPORTED;
   int64_t kcap = p.k_cap > 0 ? p.k_cap : l;
   if (mode == RSVD_RANK_FIXED && kcap < (k < l ? k : l)) return RSVD_EINVAL;
@@ -247,6 +262,8 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* worksp
   pl->k_fixed = k;
   pl->mode = mode;
   pl->param = param;
+  pl->adaptive = adaptive;
+  pl->blk = blk;
   const int64_t m = p.m, n = p.n, kc = pl->kc;
   const int64_t mx = m > n ? m : n;
   const size_t D = sizeof(double);
@@ -258,6 +275,21 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* worksp
   pl->off_Yorig = c.take((size_t)mx * l * D);
   pl->off_tau = c.take((size_t)2 * l * D);
   pl->part_doubles = gemm_part_need(m, n, l);
+  if (adaptive) {
+    auto upd = [&](int64_t M, int64_t N, int64_t K) {
+      const size_t need = dgemm_shape(M, N, K).part_doubles;
+      if (need > pl->part_doubles) pl->part_doubles = need;
+    };
+    upd(m, blk, n);  // A P_blk, A Q_b
+    upd(n, blk, m);  // A^T Q_b
+    upd(l, blk, m);  // Q^T W
+    upd(m, blk, l);  // Q (Q^T W)
+    upd(blk, blk, m);
+    upd(blk, blk, n);
+    upd(m, blk, blk);
+    upd(n, blk, blk);
+    if (pl->part_doubles < (size_t)512 * 256) pl->part_doubles = (size_t)512 * 256;  // column norms
+  }
   if (pl->part_doubles < 2048) pl->part_doubles = 2048;
   pl->off_part = c.take(pl->part_doubles * D);
   const size_t ll = (size_t)l * l * D;
@@ -284,6 +316,13 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* worksp
     pl->off_Vt = c.take((size_t)n * kcp * D);
     pl->off_rpart = c.take(resid_partials(m, n) * D);
   }
+  if (adaptive) {
+    pl->off_Wb = c.take((size_t)m * blk * D);
+    pl->off_Zb = c.take((size_t)n * blk * D);
+    pl->off_Ob = c.take((size_t)n * blk * D);
+    pl->off_Cb = c.take((size_t)l * blk * D);
+    pl->off_Zc = c.take((size_t)n * l * D);
+  }
   pl->total = c.at;
   *out = pl;
   if (workspace_bytes) *workspace_bytes = pl->total;
@@ -294,6 +333,219 @@ int64_t rsvd_plan_l(rsvd_plan_t plan) { return plan ? plan->l : -1; }
 
 void rsvd_destroy(rsvd_plan_t plan) { delete plan; }
 
+}  // extern "C"
+
+namespace {
+
+#define RSVD_TRY(x) do { rsvd_status r_ = (x); if (r_ != RSVD_OK) return r_; } while (0)
+
+// Output buffers of one run (caller's U / V, or workspace stand-ins).
+struct Outs {
+  double* S;
+  double* U;
+  int64_t ldu;
+  double* V;
+  int64_t ldv;
+};
+
+// Step 2 on a basis of width l whose transposed projection Y^T = A^T Q
+// (n x l, contiguous) is in Zc: Y^T = Q_B X_B (Zc <- Q_B), SVD of X_B^T by
+// one-sided Jacobi, singular values ordered decreasingly, then the rank rule.
+rsvd_status small_svd_and_rank(const rsvd_plan_s& pl, const Ws& w, int64_t l, double* Zc,
+                               hipStream_t s) {
+  const rsvd_problem& p = pl.p;
+  DevState* st = w.at<DevState>(pl.off_state);
+  double* Rt = w.at<double>(pl.off_Rt);
+  const int64_t kcl = pl.kc < l ? pl.kc : l;
+  {
+    PhaseScope ph(1, s);
+    RSVD_TRY(orth(pl, w, p.n, l, Zc, Rt, s, true));
+  }
+  {
+    PhaseScope ph(2, s);
+    RSVD_TRY(block_jacobi(l, Rt, w.at<double>(pl.off_M), w.at<double>(pl.off_P),
+                          p.max_sweeps > 0 ? p.max_sweeps : 30, 1, st, s));
+    RSVD_TRY(svd_finish(l, kcl, w.at<double>(pl.off_M), w.at<double>(pl.off_P), jacobi_padded(l),
+                        w.at<double>(pl.off_sig), w.at<double>(pl.off_Us), w.at<double>(pl.off_W),
+                        st, s));
+  }
+  return select_rank(l, p.oversample, kcl, pl.mode, pl.param, w.at<double>(pl.off_sig), st, s);
+}
+
+// Step 3 and the outputs: L = Q L_Y (Q: m x l, ldq), R = Q_B W (Q_B = Zc),
+// sign rule, S, optional residual pass, result record.
+rsvd_status lift_and_finish(const rsvd_plan_s& pl, const Ws& w, const double* A, int64_t lda,
+                            int64_t l, const double* Q, int64_t ldq, const double* Zc,
+                            const Outs& o, double err_est, int blocks, rsvd_result* res_dev,
+                            hipStream_t s) {
+  const rsvd_problem& p = pl.p;
+  const int64_t m = p.m, n = p.n;
+  const int64_t kcl = pl.kc < l ? pl.kc : l;
+  DevState* st = w.at<DevState>(pl.off_state);
+  double* part = w.at<double>(pl.off_part);
+  const double* sig = w.at<double>(pl.off_sig);
+  {
+    PhaseScope ph(3, s);
+    RSVD_TRY(dgemm(false, m, kcl, l, 1.0, Q, ldq, w.at<double>(pl.off_Us), kcl, 0.0, o.U, o.ldu,
+                   part, pl.part_doubles, s));
+    RSVD_TRY(dgemm(false, n, kcl, l, 1.0, Zc, l, w.at<double>(pl.off_W), kcl, 0.0, o.V, o.ldv,
+                   part, pl.part_doubles, s));
+    RSVD_TRY(sign_fix(m, n, kcl, o.U, o.ldu, o.V, o.ldv, s));
+  }
+  if (hipMemcpyAsync(o.S, sig, (size_t)kcl * sizeof(double), hipMemcpyDeviceToDevice, s) !=
+      hipSuccess)
+    return RSVD_EHIP;
+  if (p.want_residual) {
+    PhaseScope ph(4, s);
+    double* US = w.at<double>(pl.off_US);
+    double* Vt = w.at<double>(pl.off_Vt);
+    const int64_t kcp = (kcl + 15) / 16 * 16;  // padded with zero columns / rows
+    RSVD_TRY(resid_prep(m, n, kcl, kcp, o.U, o.ldu, sig, o.V, o.ldv, US, Vt, st, s));
+    RSVD_TRY(resid(m, n, kcp, US, kcp, Vt, n, A, lda, w.at<double>(pl.off_rpart), st, s));
+  }
+  return finalize(m, n, l, p.want_residual, err_est, blocks, st, res_dev, s);
+}
+
+// Halko et al. (2011), Eq. (4.3): ||(I - QQ^T) A|| <= 10 sqrt(2/pi) max_j ||(I - QQ^T) A w_j||
+constexpr double kPosteriorFactor = 7.978845608028654;
+
+// The adaptive range finder (header: "Adaptive range finder").
+rsvd_status run_adaptive(const rsvd_plan_s& pl, const Ws& w, const double* A, int64_t lda,
+                         const Outs& o, rsvd_result* res_dev, hipStream_t s) {
+  const rsvd_problem& p = pl.p;
+  const int64_t m = p.m, n = p.n, lmax = pl.l, b = pl.blk, mn = m < n ? m : n;
+  const int64_t over = p.oversample;
+  const double tau = pl.param;
+  const bool frob = pl.mode == RSVD_RANK_FROB_TAIL;
+  DevState* st = w.at<DevState>(pl.off_state);
+  double* Q = w.at<double>(pl.off_Y);    // m x lmax, ld lmax
+  double* Bt = w.at<double>(pl.off_Z);   // n x lmax, ld lmax: (Q^T A)^T
+  double* Wb = w.at<double>(pl.off_Wb);  // m x b
+  double* Zb = w.at<double>(pl.off_Zb);  // n x b
+  double* Ob = w.at<double>(pl.off_Ob);  // n x b
+  double* Cb = w.at<double>(pl.off_Cb);  // lmax x b
+  double* Zc = w.at<double>(pl.off_Zc);  // n x lmax contiguous
+  double* part = w.at<double>(pl.off_part);
+  const size_t pd = pl.part_doubles;
+  DevState hs;
+  auto sync_state = [&]() -> rsvd_status {
+    if (hipMemcpyAsync(&hs, st, sizeof(DevState), hipMemcpyDeviceToHost, s) != hipSuccess)
+      return RSVD_EHIP;
+    if (hipStreamSynchronize(s) != hipSuccess) return RSVD_EHIP;
+    return RSVD_OK;
+  };
+  int64_t l = 0;
+  // X (rows m, width bi, contiguous) <- (I - Q Q^T) X
+  auto deflate = [&](double* X, int64_t bi) -> rsvd_status {
+    if (l == 0) return RSVD_OK;
+    RSVD_TRY(dgemm(true, l, bi, m, 1.0, Q, lmax, X, bi, 0.0, Cb, bi, part, pd, s));
+    return dgemm(false, m, bi, l, -1.0, Q, lmax, Cb, bi, 1.0, X, bi, part, pd, s);
+  };
+  // X <- orthonormal basis of X, orthogonal to Q (orth, deflate, orth)
+  auto orth_against = [&](double* X, int64_t bi) -> rsvd_status {
+    PhaseScope ph(1, s);
+    RSVD_TRY(orth(pl, w, m, bi, X, nullptr, s, true));
+    RSVD_TRY(deflate(X, bi));
+    return orth(pl, w, m, bi, X, nullptr, s, true);
+  };
+  // steps 2: small SVD of the current projection; returns whether the rule
+  // keeps at most l - p values
+  auto try_finish = [&](bool* ok) -> rsvd_status {
+    RSVD_TRY(clear_flags(st, RSVD_FLAG_RANK_CAPPED | RSVD_FLAG_JACOBI_MAXSWEEP, 0u, s));
+    RSVD_TRY(copy_panel(n, l, Bt, lmax, Zc, l, 0, st, s));
+    RSVD_TRY(small_svd_and_rank(pl, w, l, Zc, s));
+    RSVD_TRY(sync_state());
+    *ok = hs.rank_wanted <= l - over;
+    return RSVD_OK;
+  };
+
+  RSVD_TRY(init_state(st, 0u, s));
+  if (frob) {
+    PhaseScope ph(6, s);
+    RSVD_TRY(sumsq(m, n, A, lda, part, st, s));
+  }
+  double est = __builtin_nan("");
+  int blocks = 0;
+  bool done = false;
+  while (!done) {
+    const int64_t bi = b < lmax - l ? b : lmax - l;
+    if (bi <= 0) {
+      RSVD_TRY(clear_flags(st, 0u, RSVD_FLAG_ADAPT_LIMIT, s));
+      bool ok = false;
+      RSVD_TRY(try_finish(&ok));
+      break;
+    }
+    {
+      PhaseScope ph(5, s);
+      RSVD_TRY(gaussian_omega(n, bi, l, p.seed, p.channel, Ob, bi, s));
+    }
+    {
+      PhaseScope ph(0, s);
+      RSVD_TRY(dgemm(false, m, bi, n, 1.0, A, lda, Ob, bi, 0.0, Wb, bi, part, pd, s));
+    }
+    if (l == 0) {
+      RSVD_TRY(check_finite(m, bi, Wb, bi, st, s));
+      RSVD_TRY(sync_state());
+      if (hs.flags & RSVD_FLAG_NONFINITE_INPUT) {
+        // nothing meaningful to grow: report the flag with an empty result
+        return finalize(m, n, 0, p.want_residual, est, blocks, st, res_dev, s);
+      }
+    }
+    RSVD_TRY(deflate(Wb, bi));
+    if (!frob && l > 0) {
+      RSVD_TRY(colsumsq(m, (int)bi, Wb, bi, part, pd, 0, st, s));
+      RSVD_TRY(sync_state());
+      est = kPosteriorFactor * std::sqrt(hs.est2);
+      if (est <= tau * std::sqrt(hs.s1lb2)) {
+        bool ok = false;
+        RSVD_TRY(try_finish(&ok));
+        if (ok) break;
+      }
+    }
+    RSVD_TRY(orth_against(Wb, bi));
+    for (int t = 0; t < p.power_iters; t++) {
+      {
+        PhaseScope ph(0, s);
+        RSVD_TRY(dgemm(!p.symmetric, n, bi, m, 1.0, A, lda, Wb, bi, 0.0, Zb, bi, part, pd, s));
+      }
+      {
+        PhaseScope ph(1, s);
+        RSVD_TRY(orth(pl, w, n, bi, Zb, nullptr, s, false));
+      }
+      {
+        PhaseScope ph(0, s);
+        RSVD_TRY(dgemm(false, m, bi, n, 1.0, A, lda, Zb, bi, 0.0, Wb, bi, part, pd, s));
+      }
+      RSVD_TRY(deflate(Wb, bi));
+      RSVD_TRY(orth_against(Wb, bi));
+    }
+    {
+      PhaseScope ph(0, s);
+      RSVD_TRY(dgemm(!p.symmetric, n, bi, m, 1.0, A, lda, Wb, bi, 0.0, Bt + l, lmax, part, pd, s));
+    }
+    RSVD_TRY(copy_panel(m, bi, Wb, bi, Q + l, lmax, 0, st, s));
+    RSVD_TRY(colsumsq(n, (int)bi, Bt + l, lmax, part, pd, 1, st, s));
+    l += bi;
+    blocks++;
+    if (frob) {
+      RSVD_TRY(sync_state());
+      const double miss = hs.fro2 - hs.froY2;
+      est = std::sqrt(miss > 0.0 ? miss : 0.0);
+      if (est <= tau * std::sqrt(hs.fro2)) {
+        bool ok = false;
+        RSVD_TRY(try_finish(&ok));
+        if (ok) break;
+      }
+    }
+  }
+  if (l == mn) RSVD_TRY(clear_flags(st, 0u, RSVD_FLAG_FULL_SVD, s));
+  return lift_and_finish(pl, w, A, lda, l, Q, lmax, Zc, o, est, blocks, res_dev, s);
+}
+
+}  // namespace
+
+extern "C" {
+
 rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const double* omega,
                      int64_t ldo, double* S, double* U, int64_t ldu, double* V, int64_t ldv,
                      rsvd_result* res_dev, void* work, size_t work_bytes, void* stream) {
@@ -302,31 +554,31 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
   const rsvd_problem& p = pl.p;
   const int64_t m = p.m, n = p.n, l = pl.l, kc = pl.kc;
   if (lda < n) return RSVD_EINVAL;
-  if (omega && ldo < l) return RSVD_EINVAL;
+  if (omega && (pl.adaptive || ldo < l)) return RSVD_EINVAL;
   if (p.want_u && (!U || ldu < kc)) return RSVD_EINVAL;
   if (p.want_v && (!V || ldv < kc)) return RSVD_EINVAL;
   if (work_bytes < pl.total) return RSVD_ENOMEM;
   if (((uintptr_t)work & 255) != 0) return RSVD_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   Ws w{(char*)work};
+  Outs o;
+  o.S = S;
+  o.U = p.want_u ? U : w.at<double>(pl.off_Ub);
+  o.ldu = p.want_u ? ldu : kc;
+  o.V = p.want_v ? V : w.at<double>(pl.off_Vb);
+  o.ldv = p.want_v ? ldv : kc;
+  if (pl.adaptive) return run_adaptive(pl, w, A, lda, o, res_dev, s);
+
   DevState* st = w.at<DevState>(pl.off_state);
   double* Y = w.at<double>(pl.off_Y);
   double* Z = w.at<double>(pl.off_Z);
   double* part = w.at<double>(pl.off_part);
-  double* Rt = w.at<double>(pl.off_Rt);
-  double* Mj = w.at<double>(pl.off_M);
-  double* Pj = w.at<double>(pl.off_P);
-  double* sig = w.at<double>(pl.off_sig);
-  double* Us = w.at<double>(pl.off_Us);
-  double* W = w.at<double>(pl.off_W);
-  double* Uo = p.want_u ? U : w.at<double>(pl.off_Ub);
-  const int64_t lduo = p.want_u ? ldu : kc;
-  double* Vo = p.want_v ? V : w.at<double>(pl.off_Vb);
-  const int64_t ldvo = p.want_v ? ldv : kc;
   const int64_t mn = m < n ? m : n;
-  rsvd_status r;
-#define RSVD_TRY(x) do { r = (x); if (r != RSVD_OK) return r; } while (0)
   RSVD_TRY(init_state(st, l == mn ? RSVD_FLAG_FULL_SVD : 0u, s));
+  if (pl.mode == RSVD_RANK_FROB_TAIL) {
+    PhaseScope ph(6, s);
+    RSVD_TRY(sumsq(m, n, A, lda, part, st, s));
+  }
 
   // step 1: Z = A P and its orthonormal basis
   const double* Om = omega;
@@ -353,56 +605,30 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
     return dgemm(trans, rows_out, l, inner, 1.0, A, lda, X, ldx, 0.0, out, l, part,
                  pl.part_doubles, s, 64, nullptr, prec);
   };
-  auto qr = [&](int64_t rows, double* panel, double* Rout, bool full) -> rsvd_status {
+  auto qr = [&](int64_t rows, double* panel, bool full) -> rsvd_status {
     PhaseScope ph(1, s);
-    return orth(pl, w, rows, panel, Rout, s, full);
+    return orth(pl, w, rows, l, panel, nullptr, s, full);
   };
   RSVD_TRY(stream_pass(false, Om, ldom, Y, m, n));
   RSVD_TRY(check_finite(m, l, Y, l, st, s));
   // the basis that B = Q^T A is taken against must be orthonormal to working
   // accuracy; bases inside the power iteration only carry the span forward
-  RSVD_TRY(qr(m, Y, nullptr, p.power_iters == 0));
+  RSVD_TRY(qr(m, Y, p.power_iters == 0));
   // power iterations
   for (int t = 0; t < p.power_iters; t++) {
     RSVD_TRY(stream_pass(!p.symmetric, Y, l, Z, n, m));
-    RSVD_TRY(qr(n, Z, nullptr, false));
+    RSVD_TRY(qr(n, Z, false));
     RSVD_TRY(stream_pass(false, Z, l, Y, m, n));
-    RSVD_TRY(qr(m, Y, nullptr, t + 1 == p.power_iters));
+    RSVD_TRY(qr(m, Y, t + 1 == p.power_iters));
   }
-  // step 2: Y^T = A^T Q = Q_B X_B, small SVD of X_B^T
+  // step 2: Y^T = A^T Q = Q_B X_B, small SVD of X_B^T, rank rule
   RSVD_TRY(stream_pass(!p.symmetric, Y, l, Z, n, m));
-  RSVD_TRY(qr(n, Z, Rt, true));
-  {
-    PhaseScope ph(2, s);
-    RSVD_TRY(block_jacobi(l, Rt, Mj, Pj, p.max_sweeps > 0 ? p.max_sweeps : 30, 1, st, s));
-    RSVD_TRY(svd_finish(l, kc, Mj, Pj, jacobi_padded(l), sig, Us, W, st, s));
-  }
-  if (pl.mode == RSVD_RANK_FROB_TAIL) {
-    PhaseScope ph(6, s);
-    RSVD_TRY(sumsq(m, n, A, lda, part, st, s));
-  }
-  RSVD_TRY(select_rank(l, p.oversample, kc, pl.mode, pl.param, sig, st, s));
+  RSVD_TRY(small_svd_and_rank(pl, w, l, Z, s));
   // step 3: L = Q L_Y, R = Q_B W
-  {
-    PhaseScope ph(3, s);
-    RSVD_TRY(dgemm(false, m, kc, l, 1.0, Y, l, Us, kc, 0.0, Uo, lduo, part, pl.part_doubles, s));
-    RSVD_TRY(dgemm(false, n, kc, l, 1.0, Z, l, W, kc, 0.0, Vo, ldvo, part, pl.part_doubles, s));
-    RSVD_TRY(sign_fix(m, n, kc, Uo, lduo, Vo, ldvo, s));
-  }
-  if (hipMemcpyAsync(S, sig, (size_t)kc * sizeof(double), hipMemcpyDeviceToDevice, s) != hipSuccess)
-    return RSVD_EHIP;
-  if (p.want_residual) {
-    PhaseScope ph(4, s);
-    double* US = w.at<double>(pl.off_US);
-    double* Vt = w.at<double>(pl.off_Vt);
-    const int64_t kcp = (kc + 15) / 16 * 16;  // padded with zero columns / rows
-    RSVD_TRY(resid_prep(m, n, kc, kcp, Uo, lduo, sig, Vo, ldvo, US, Vt, st, s));
-    RSVD_TRY(resid(m, n, kcp, US, kcp, Vt, n, A, lda, w.at<double>(pl.off_rpart), st, s));
-  }
-  RSVD_TRY(finalize(m, n, l, p.want_residual, st, res_dev, s));
-  return RSVD_OK;
-#undef RSVD_TRY
+  return lift_and_finish(pl, w, A, lda, l, Y, l, Z, o, __builtin_nan(""), 0, res_dev, s);
 }
+
+#undef RSVD_TRY
 
 rsvd_status rsvd_gaussian_omega(int64_t n, int64_t l, int64_t col0, uint64_t seed,
                                 uint64_t channel, double* out, int64_t ldo, void* stream) {
@@ -493,7 +719,7 @@ rsvd_status rsvd_orth(int64_t m, int64_t l, double* Y, int64_t ldy, double* X, u
   DevState* st = w.at<DevState>(pl.off_state);
   rsvd_status r = init_state(st, 0, s);
   if (r != RSVD_OK) return r;
-  r = orth(pl, w, m, Y, X, s);
+  r = orth(pl, w, m, l, Y, X, s);
   if (r != RSVD_OK) return r;
   if (flags) {
     if (hipMemcpyAsync(flags, &st->flags, sizeof(uint32_t), hipMemcpyDeviceToDevice, s) != hipSuccess)

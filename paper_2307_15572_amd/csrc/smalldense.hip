@@ -793,8 +793,12 @@ __global__ void select_rank_kernel(int64_t l, int64_t p, int64_t kc, int mode, d
   const int64_t cap = (l - p) > 1 ? (l - p) : 1;
   if (mode == RSVD_RANK_FIXED) {
     k = (int64_t)param;
+    st->rank_wanted = (int32_t)k;
   } else if (mode == RSVD_RANK_REL_THRESHOLD) {
-    for (int64_t j = 0; j < l; j++) k += (s[j] >= param * s[0]) ? 1 : 0;
+    // an all-zero projection has no value above the threshold (k = 1 below)
+    if (s[0] > 0.0)
+      for (int64_t j = 0; j < l; j++) k += (s[j] >= param * s[0]) ? 1 : 0;
+    st->rank_wanted = (int32_t)k;
     if (k > cap) { k = cap; f |= RSVD_FLAG_RANK_CAPPED; }
   } else if (mode == RSVD_RANK_FROB_TAIL) {
     double tot = 0.0;
@@ -811,6 +815,7 @@ __global__ void select_rank_kernel(int64_t l, int64_t p, int64_t kc, int mode, d
       if (sqrt(tail + missed) <= lim) best = kk;
     }
     k = best;
+    st->rank_wanted = (int32_t)k;
     if (k > cap) { k = cap; f |= RSVD_FLAG_RANK_CAPPED; }
   }
   if (k < 1) k = 1;
@@ -918,7 +923,8 @@ __global__ void __launch_bounds__(256) sum_partials_kernel(int64_t cnt, const do
 }
 
 __global__ void finalize_kernel(int64_t m, int64_t n, int64_t l, int want_residual,
-                                const DevState* st, rsvd_result* res) {
+                                double err_est, int blocks, const DevState* st,
+                                rsvd_result* res) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const int64_t k = st->rank;
   const double N = (double)(m < n ? m : n);
@@ -931,6 +937,9 @@ __global__ void finalize_kernel(int64_t m, int64_t n, int64_t l, int want_residu
   res->fro2 = st->fro2;
   res->sweeps = st->sweeps;
   res->flags = st->flags;
+  res->err_est = err_est;
+  res->blocks = blocks;
+  res->reserved = 0;
 }
 
 __global__ void init_state_kernel(DevState* st, uint32_t flags) {
@@ -942,8 +951,76 @@ __global__ void init_state_kernel(DevState* st, uint32_t flags) {
     st->rank = 0;
     st->fro2 = 0.0;
     st->resid2 = 0.0;
+    st->rank_wanted = 0;
+    st->pad_ = 0;
+    st->est2 = 0.0;
+    st->s1lb2 = 0.0;
+    st->froY2 = 0.0;
   }
   if (blockIdx.x == 0 && threadIdx.x < 64) st->rot_count[threadIdx.x] = 0;
+}
+
+__global__ void clear_flags_kernel(DevState* st, uint32_t clear, uint32_t set) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) st->flags = (st->flags & ~clear) | set;
+}
+
+// Column sums of squares of a rows x cols row-major panel (cols <= 256):
+// partial[b * cols + c] = sum over the rows of row block b of X[r][c]^2.
+// Wave w of block b takes rows 4 b + w, 4 b + w + 4 gridDim, ...; lane c
+// reads column c (+ 64 g), so each wave reads whole rows contiguously.
+__global__ void __launch_bounds__(256) colsumsq_kernel(int64_t rows, int cols,
+                                                       const double* __restrict__ X, int64_t ld,
+                                                       double* __restrict__ partial) {
+  __shared__ double red[4][256];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t r = (int64_t)blockIdx.x * 4 + w; r < rows; r += (int64_t)gridDim.x * 4) {
+    const double* row = X + r * ld;
+#pragma unroll
+    for (int g = 0; g < 4; g++) {
+      const int c = lane + 64 * g;
+      if (c < cols) {
+        const double x = row[c];
+        acc[g] += x * x;
+      }
+    }
+  }
+#pragma unroll
+  for (int g = 0; g < 4; g++) red[w][lane + 64 * g] = acc[g];
+  __syncthreads();
+  for (int c = threadIdx.x; c < cols; c += 256)
+    partial[(int64_t)blockIdx.x * cols + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+}
+
+// Reduce the partials of colsumsq_kernel over the row blocks, then
+//   mode 0: st->est2 = max_c colsum
+//   mode 1: st->s1lb2 = max(st->s1lb2, max_c colsum); st->froY2 += sum_c colsum
+__global__ void __launch_bounds__(256) colsumsq_finish_kernel(int nblk, int cols,
+                                                              const double* __restrict__ partial,
+                                                              int mode, DevState* st) {
+  __shared__ double smax[4], ssum[4];
+  const int c = threadIdx.x;
+  double v = 0.0;
+  if (c < cols)
+    for (int b = 0; b < nblk; b++) v += partial[(int64_t)b * cols + c];
+  // a NaN column must not vanish in fmax: carry it explicitly
+  const double vm = v != v ? __builtin_inf() : v;
+  const double mx = wave_max(vm), sm = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) {
+    smax[threadIdx.x >> 6] = mx;
+    ssum[threadIdx.x >> 6] = sm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double M = fmax(fmax(smax[0], smax[1]), fmax(smax[2], smax[3]));
+    const double S = (ssum[0] + ssum[1]) + (ssum[2] + ssum[3]);
+    if (mode == 0) {
+      st->est2 = M;
+    } else {
+      if (M > st->s1lb2) st->s1lb2 = M;
+      st->froY2 += S;
+    }
+  }
 }
 
 __global__ void clear_shift_kernel(DevState* st) {
@@ -1102,15 +1179,42 @@ rsvd_status sum_partials_into(int64_t cnt, const double* p, double* out, hipStre
   return RSVD_OK;
 }
 
-rsvd_status finalize(int64_t m, int64_t n, int64_t l, int want_residual, const DevState* st,
-                     rsvd_result* res, hipStream_t s) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, s, m, n, l, want_residual, st, res);
+rsvd_status finalize(int64_t m, int64_t n, int64_t l, int want_residual, double err_est,
+                     int blocks, const DevState* st, rsvd_result* res, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, s, m, n, l, want_residual, err_est,
+                     blocks, st, res);
   RSVD_LAUNCH_CHECK();
   return RSVD_OK;
 }
 
 rsvd_status init_state(DevState* st, uint32_t flags, hipStream_t s) {
   hipLaunchKernelGGL(init_state_kernel, dim3(1), dim3(64), 0, s, st, flags);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status clear_flags(DevState* st, uint32_t clear, uint32_t set, hipStream_t s) {
+  hipLaunchKernelGGL(clear_flags_kernel, dim3(1), dim3(64), 0, s, st, clear, set);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+int colsumsq_blocks(int64_t rows, int cols, size_t partial_doubles) {
+  int64_t nb = (rows + 15) / 16;
+  if (nb > 512) nb = 512;
+  const int64_t cap = (int64_t)(partial_doubles / (size_t)(cols > 0 ? cols : 1));
+  if (nb > cap) nb = cap;
+  return nb < 1 ? 1 : (int)nb;
+}
+
+rsvd_status colsumsq(int64_t rows, int cols, const double* X, int64_t ld, double* partial,
+                     size_t partial_doubles, int mode, DevState* st, hipStream_t s) {
+  if (cols < 1 || cols > 256 || partial_doubles < (size_t)cols) return RSVD_EINVAL;
+  const int nb = colsumsq_blocks(rows, cols, partial_doubles);
+  hipLaunchKernelGGL(colsumsq_kernel, dim3(nb), dim3(256), 0, s, rows, cols, X, ld, partial);
+  RSVD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(colsumsq_finish_kernel, dim3(1), dim3(256), 0, s, nb, cols,
+                     (const double*)partial, mode, st);
   RSVD_LAUNCH_CHECK();
   return RSVD_OK;
 }

@@ -101,3 +101,28 @@ def test_run_rejects_null_and_small_workspace():
     assert st == rs.RSVD_ENOMEM
     st = L.rsvd_run(pl._h, fake, 79, null, 0, fake, fake, 15, fake, 15, fake, fake, 10**12, null)
     assert st == rs.RSVD_EINVAL  # lda < n
+
+
+def test_adaptive_plan_sizes_and_validation():
+    thr = dict(k=0, rank_mode="rel_threshold", rank_param=1e-6, adaptive=True)
+    pl = _plan(**thr)
+    assert pl.l == 80  # l_max defaults to min(m, n, 4096)
+    assert _plan(l_max=48, **thr).l == 48
+    assert _plan(l_max=500, block=16, **thr).l == 80
+    for bad in (dict(block=300), dict(block=-1), dict(l_max=-5)):
+        with pytest.raises(rs.RsvdError, match="invalid"):
+            _plan(**thr, **bad)
+    with pytest.raises(rs.RsvdError, match="invalid"):
+        _plan(adaptive=True)  # fixed rule
+    with pytest.raises(rs.RsvdError, match="invalid"):
+        _plan(adaptive=True, rank_mode="percent", rank_param=10.0)
+    with pytest.raises(rs.RsvdError, match="unsupported"):
+        _plan(precision="mixed_fp32", **thr)
+
+
+def test_adaptive_run_rejects_caller_projection():
+    L = rs.lib()
+    pl = _plan(k=0, rank_mode="rel_threshold", rank_param=1e-6, adaptive=True, l_max=32)
+    fake = ctypes.c_void_p(256)  # never dereferenced: validation fails first
+    st = L.rsvd_run(pl._h, fake, 80, fake, 32, fake, fake, 32, fake, 32, fake, fake, 10**12, None)
+    assert st == rs.RSVD_EINVAL
