@@ -68,7 +68,9 @@ enum {
   RSVD_FLAG_JACOBI_MAXSWEEP = 1u << 3, /* small SVD stopped at max_sweeps            */
   RSVD_FLAG_NONFINITE_INPUT = 1u << 4, /* A holds NaN or Inf                         */
   RSVD_FLAG_ZERO_SIGMA = 1u << 5,      /* a singular value is exactly zero           */
-  RSVD_FLAG_ADAPT_LIMIT = 1u << 6      /* adaptive growth stopped at l_max           */
+  RSVD_FLAG_ADAPT_LIMIT = 1u << 6,     /* adaptive growth stopped at l_max           */
+  RSVD_FLAG_SYNC_TIMEOUT = 1u << 7     /* a device-wide barrier of the small SVD gave
+                                          up waiting (bounded wait): results invalid  */
 };
 
 typedef struct rsvd_problem {
@@ -188,6 +190,58 @@ void rsvd_destroy(rsvd_plan_t plan);
 
 /* Static description of a status code. */
 const char* rsvd_strerror(rsvd_status s);
+
+/*
+ * Batched decompositions (independent symmetry channels, section "Low-rank
+ * interactions": every partial-wave channel's matrix is decomposed on its
+ * own). A batch plan holds one plan per channel and runs them together:
+ *  - channels are ordered by cost m n l (2q + 2) (longest first) and dealt
+ *    to `lanes` HIP streams, each to the least-loaded lane (LPT schedule);
+ *  - the channels of one lane run one after another in one workspace slice
+ *    sized for the largest of them; the lanes run concurrently and join the
+ *    caller's stream at the end;
+ *  - with use_graph != 0 the whole fork / run / join sequence is captured
+ *    into a hipGraph on the first call and replayed by later calls with the
+ *    same pointers and leading dimensions (a call with other pointers
+ *    captures again). If the runtime refuses the capture, the batch runs
+ *    eagerly from then on (rsvd_batch_info reports it).
+ * Each channel computes exactly what rsvd_run computes for its problem
+ * (bitwise: the same kernels on the same data).
+ */
+typedef struct rsvd_batch_s* rsvd_batch_t;
+
+/*
+ * rsvd_batch_plan - plan count >= 1 problems (host array, read only). Every
+ * problem is validated as by rsvd_plan; adaptive problems are rejected with
+ * RSVD_EINVAL (they synchronize). lanes: 1..16 concurrent streams (0 = 4).
+ * workspace_bytes receives the device workspace rsvd_batch_run needs.
+ * Streams, events and graphs are created on the device that is current at
+ * the first rsvd_batch_run and released by rsvd_batch_destroy.
+ */
+rsvd_status rsvd_batch_plan(const rsvd_problem* probs, int64_t count, int32_t lanes,
+                            int32_t use_graph, rsvd_batch_t* out, size_t* workspace_bytes);
+
+/*
+ * rsvd_batch_run - run every channel. All pointer arrays are HOST arrays of
+ * count entries holding DEVICE pointers (A[c], S[c], U[c], V[c]) and the
+ * leading dimensions lda[c], ldu[c], ldv[c], with the meaning of rsvd_run
+ * (U / V entries may be NULL where the problem does not want them; ldu / ldv
+ * may then be NULL too). res_dev: count device result records. work: device
+ * workspace of the planned size, 256-B aligned. Ordered on `stream`: the
+ * lanes wait for the work enqueued before and the stream waits for them.
+ */
+rsvd_status rsvd_batch_run(rsvd_batch_t plan, const double* const* A, const int64_t* lda,
+                           double* const* S, double* const* U, const int64_t* ldu,
+                           double* const* V, const int64_t* ldv, rsvd_result* res_dev,
+                           void* work, size_t work_bytes, void* stream);
+
+/* rsvd_batch_info - host query: lane of channel c (lane_of, count entries,
+ * may be NULL), and whether the last run replayed a captured graph. */
+rsvd_status rsvd_batch_info(rsvd_batch_t plan, int32_t* lane_of, int32_t* graph_replayed);
+
+/* Free a batch plan with its streams, events and graph (NULL is ignored).
+ * Synchronizes the lanes first. */
+void rsvd_batch_destroy(rsvd_batch_t plan);
 
 /*
  * Component entry points (each one step of the path, for testing and reuse).

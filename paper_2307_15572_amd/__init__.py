@@ -24,12 +24,14 @@ FLAG_JACOBI_MAXSWEEP = 1 << 3
 FLAG_NONFINITE_INPUT = 1 << 4
 FLAG_ZERO_SIGMA = 1 << 5
 FLAG_ADAPT_LIMIT = 1 << 6
+FLAG_SYNC_TIMEOUT = 1 << 7
 
 EXPORTED = (
     "rsvd_plan", "rsvd_plan_l", "rsvd_run", "rsvd_destroy", "rsvd_strerror",
     "rsvd_gaussian_omega", "rsvd_dgemm_work_bytes", "rsvd_dgemm", "rsvd_gemm",
     "rsvd_orth_work_bytes", "rsvd_orth", "rsvd_small_svd_work_bytes", "rsvd_small_svd",
     "rsvd_trace_enable", "rsvd_trace_collect",
+    "rsvd_batch_plan", "rsvd_batch_run", "rsvd_batch_info", "rsvd_batch_destroy",
 )
 TRACE_PHASES = ("stream_gemm", "qr", "small_svd", "lift_signs", "residual", "omega", "other")
 
@@ -106,6 +108,16 @@ def lib():
     L.rsvd_trace_enable.restype = None
     L.rsvd_trace_collect.argtypes = [ctypes.POINTER(dbl), ctypes.POINTER(i64)]
     L.rsvd_trace_collect.restype = ctypes.c_int
+    pp = ctypes.POINTER
+    L.rsvd_batch_plan.argtypes = [pp(Problem), i64, i32, i32, pp(vp), pp(sz)]
+    L.rsvd_batch_plan.restype = ctypes.c_int
+    L.rsvd_batch_run.argtypes = [vp, pp(vp), pp(i64), pp(vp), pp(vp), pp(i64), pp(vp), pp(i64),
+                                 vp, vp, sz, vp]
+    L.rsvd_batch_run.restype = ctypes.c_int
+    L.rsvd_batch_info.argtypes = [vp, pp(i32), pp(i32)]
+    L.rsvd_batch_info.restype = ctypes.c_int
+    L.rsvd_batch_destroy.argtypes = [vp]
+    L.rsvd_batch_destroy.restype = None
     _lib = L
     return L
 
@@ -163,6 +175,25 @@ class RsvdOutput:
     blocks: int = 0                 # adaptive: growth steps
 
 
+def make_problem(m, n, k, p, q, *, symmetric=False, rank_mode="fixed", rank_param=None,
+                 precision="fp64", trailing_hp=1, seed=0, channel=0, want_u=True, want_v=True,
+                 want_residual=True, max_sweeps=0, k_cap=0, adaptive=False, block=0, l_max=0):
+    """Fill an rsvd_problem record."""
+    pr = Problem()
+    pr.m, pr.n, pr.k, pr.k_cap = int(m), int(n), int(k), int(k_cap)
+    pr.symmetric = int(bool(symmetric))
+    pr.rank_mode = RANK_MODES[rank_mode]
+    pr.rank_param = float(rank_param) if rank_param is not None else float(k)
+    pr.oversample, pr.power_iters = int(p), int(q)
+    pr.precision = PRECISIONS[precision]
+    pr.trailing_hp = int(trailing_hp)
+    pr.seed, pr.channel = int(seed) & (2**64 - 1), int(channel) & (2**64 - 1)
+    pr.want_u, pr.want_v = int(bool(want_u)), int(bool(want_v))
+    pr.want_residual, pr.max_sweeps = int(bool(want_residual)), int(max_sweeps)
+    pr.adaptive, pr.block, pr.l_max = int(bool(adaptive)), int(block), int(l_max)
+    return pr
+
+
 class Plan:
     """An immutable plan for one problem shape (wraps rsvd_plan).
 
@@ -175,18 +206,11 @@ class Plan:
                  precision="fp64", trailing_hp=1, seed=0, channel=0, want_u=True, want_v=True,
                  want_residual=True, max_sweeps=0, k_cap=0, adaptive=False, block=0, l_max=0):
         L = lib()
-        pr = Problem()
-        pr.m, pr.n, pr.k, pr.k_cap = int(m), int(n), int(k), int(k_cap)
-        pr.symmetric = int(bool(symmetric))
-        pr.rank_mode = RANK_MODES[rank_mode]
-        pr.rank_param = float(rank_param) if rank_param is not None else float(k)
-        pr.oversample, pr.power_iters = int(p), int(q)
-        pr.precision = PRECISIONS[precision]
-        pr.trailing_hp = int(trailing_hp)
-        pr.seed, pr.channel = int(seed) & (2**64 - 1), int(channel) & (2**64 - 1)
-        pr.want_u, pr.want_v = int(bool(want_u)), int(bool(want_v))
-        pr.want_residual, pr.max_sweeps = int(bool(want_residual)), int(max_sweeps)
-        pr.adaptive, pr.block, pr.l_max = int(bool(adaptive)), int(block), int(l_max)
+        pr = make_problem(m, n, k, p, q, symmetric=symmetric, rank_mode=rank_mode,
+                          rank_param=rank_param, precision=precision, trailing_hp=trailing_hp,
+                          seed=seed, channel=channel, want_u=want_u, want_v=want_v,
+                          want_residual=want_residual, max_sweeps=max_sweeps, k_cap=k_cap,
+                          adaptive=adaptive, block=block, l_max=l_max)
         self.problem = pr
         h = ctypes.c_void_p()
         ws = ctypes.c_size_t()
@@ -242,6 +266,100 @@ class Plan:
         torch.cuda.synchronize(bufs["S"].device)
         raw = bytes(bufs["res"].cpu().numpy().tobytes())
         return Result.from_buffer_copy(raw)
+
+
+class BatchPlan:
+    """Independent decompositions run together (wraps rsvd_batch_plan).
+
+    problems: list of dicts with the keyword arguments of make_problem
+    (m, n, k, p, q, ...). lanes: concurrent streams (0 = 4). use_graph:
+    capture the run into a hipGraph on first use and replay it.
+    """
+
+    def __init__(self, problems, lanes=0, use_graph=True):
+        L = lib()
+        self.count = len(problems)
+        arr = (Problem * self.count)()
+        for c, kw in enumerate(problems):
+            kw = dict(kw)
+            m, n, k, p, q = (kw.pop(x) for x in ("m", "n", "k", "p", "q"))
+            arr[c] = make_problem(m, n, k, p, q, **kw)
+        self.problems = arr
+        h = ctypes.c_void_p()
+        ws = ctypes.c_size_t()
+        _check(L.rsvd_batch_plan(arr, self.count, int(lanes), int(bool(use_graph)),
+                                 ctypes.byref(h), ctypes.byref(ws)), "rsvd_batch_plan")
+        self._h = h
+        self.workspace_bytes = ws.value
+        # per-channel sketch width and output columns (same rules as Plan)
+        self.l, self.kc = [], []
+        for pr in arr:
+            one = ctypes.c_void_p()
+            _check(L.rsvd_plan(ctypes.byref(pr), ctypes.byref(one), None), "rsvd_plan")
+            l = L.rsvd_plan_l(one)
+            L.rsvd_destroy(one)
+            self.l.append(l)
+            self.kc.append(min(pr.k_cap if pr.k_cap else l, l))
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value and _lib is not None:
+            _lib.rsvd_batch_destroy(h)
+            self._h = None
+
+    def lanes_of(self):
+        out = (ctypes.c_int32 * self.count)()
+        _check(lib().rsvd_batch_info(self._h, out, None), "rsvd_batch_info")
+        return list(out)
+
+    def graph_used(self):
+        g = ctypes.c_int32()
+        _check(lib().rsvd_batch_info(self._h, None, ctypes.byref(g)), "rsvd_batch_info")
+        return bool(g.value)
+
+    def allocate(self, device="cuda"):
+        torch = _torch()
+        S, U, V = [], [], []
+        for pr, kc in zip(self.problems, self.kc):
+            S.append(torch.empty(kc, dtype=torch.float64, device=device))
+            U.append(torch.empty(pr.m, kc, dtype=torch.float64, device=device) if pr.want_u else None)
+            V.append(torch.empty(pr.n, kc, dtype=torch.float64, device=device) if pr.want_v else None)
+        bufs = {"S": S, "U": U, "V": V,
+                "res": torch.zeros(self.count * ctypes.sizeof(Result), dtype=torch.uint8, device=device)}
+        bufs["work_buf"], bufs["work"], bufs["work_bytes"] = _workspace(torch, self.workspace_bytes, device)
+        return bufs
+
+    def run_into(self, As, bufs):
+        """Enqueue every channel on the current stream (no synchronization)."""
+        torch = _torch()
+        n = self.count
+        if len(As) != n:
+            raise RsvdError(f"expected {n} matrices")
+        vp, i64 = ctypes.c_void_p, ctypes.c_int64
+        Ap, lda = (vp * n)(), (i64 * n)()
+        Sp, Up, Vp = (vp * n)(), (vp * n)(), (vp * n)()
+        ldu, ldv = (i64 * n)(), (i64 * n)()
+        for c, (A, pr) in enumerate(zip(As, self.problems)):
+            _check_matrix(torch, A, f"A[{c}]")
+            if tuple(A.shape) != (pr.m, pr.n):
+                raise RsvdError(f"A[{c}] has shape {tuple(A.shape)}, plan expects {(pr.m, pr.n)}")
+            Ap[c], lda[c] = A.data_ptr(), A.stride(0)
+            Sp[c] = bufs["S"][c].data_ptr()
+            U, V = bufs["U"][c], bufs["V"][c]
+            Up[c], ldu[c] = (U.data_ptr(), U.stride(0)) if U is not None else (0, 0)
+            Vp[c], ldv[c] = (V.data_ptr(), V.stride(0)) if V is not None else (0, 0)
+        self._keep = (Ap, lda, Sp, Up, Vp, ldu, ldv)
+        _check(lib().rsvd_batch_run(self._h, Ap, lda, Sp, Up, ldu, Vp, ldv, _ptr(bufs["res"]),
+                                    bufs["work"], bufs["work_bytes"], _stream(torch, As[0].device)),
+               "rsvd_batch_run")
+
+    def results(self, bufs):
+        """Synchronize and read the count result records."""
+        torch = _torch()
+        torch.cuda.synchronize(bufs["res"].device)
+        raw = bytes(bufs["res"].cpu().numpy().tobytes())
+        sz = ctypes.sizeof(Result)
+        return [Result.from_buffer_copy(raw[c * sz:(c + 1) * sz]) for c in range(self.count)]
 
 
 def run(A, k, p, q, *, omega=None, **kw):

@@ -2,16 +2,18 @@
 // of the projected matrix) by block one-sided Jacobi on the rows of the
 // l x l factor M. Rows are grouped in blocks of 16; blocks are paired by a
 // round-robin (circle) tournament, nb - 1 steps per sweep, one workgroup per
-// pair, a grid-wide barrier between steps (cooperative launch, so all
-// workgroups are resident). For a pair of blocks (32 rows):
+// pair, a grid-wide barrier between steps. The grid is capped at what the
+// device holds at once (divided among runs on concurrent streams), and the
+// barrier lives in the run's workspace, so the launch is an ordinary one:
+// it can run beside other streams' work and be captured in a graph. Every
+// wait at the barrier is bounded (RSVD_FLAG_SYNC_TIMEOUT instead of a hang).
+// For a pair of blocks (32 rows):
 //   H = rows rows^T                   32 x 32 Gram, FP64 matrix cores
 //   V^T H V ~ diagonal                two-sided Jacobi on H in LDS (cyclic,
 //                                     parallel ordering, Rutishauser rotations)
 //   rows <- V^T rows, P_rows <- V^T P_rows   FP64 matrix cores
 // A pair whose scaled off-diagonal |H_ij| / sqrt(H_ii H_jj) is at most tol
 // is left alone; a sweep with no rotated pair ends the iteration.
-#include <hip/hip_cooperative_groups.h>
-
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -182,9 +184,46 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
   return true;
 }
 
+// Polls of the barrier generation before a workgroup gives up (each poll is
+// an agent-scope load after a short sleep: about two seconds in all).
+constexpr uint32_t kSpinLimit = 1u << 20;
+
+// Barrier over the gridDim.x workgroups of a launch whose whole grid fits on
+// the device at once. The last workgroup to arrive resets the counter and
+// advances the generation; the others wait for the generation to change.
+// Every thread fences at agent scope on both sides, so the rows written
+// before the barrier by any workgroup (on any XCD) are visible after it.
+// Returns false if this workgroup stopped waiting.
+__device__ bool grid_barrier(uint32_t* count, uint32_t* gen, int* s_ok) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const uint32_t g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t arrived =
+        __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    if (arrived == gridDim.x) {
+      __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      uint32_t spins = 0;
+      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (++spins > kSpinLimit) {
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(8);
+      }
+    }
+    *s_ok = ok;
+  }
+  __syncthreads();
+  __threadfence();
+  return *s_ok != 0;
+}
+
 __global__ void __launch_bounds__(256) bjacobi_kernel(JacArgs a) {
-  namespace cg = cooperative_groups;
-  cg::grid_group grid = cg::this_grid();
+  __shared__ int s_bar_ok;
   __shared__ double H[32][33];
   __shared__ double Vm[32][33];
   __shared__ double red[4 * 3 * 256];
@@ -197,16 +236,22 @@ __global__ void __launch_bounds__(256) bjacobi_kernel(JacArgs a) {
   uint32_t* counters = a.st->rot_count;
   int sweep = 0;
   bool converged = false;
-  for (; sweep < a.max_sweeps; sweep++) {
+  bool timed_out = false;
+  for (; sweep < a.max_sweeps && !timed_out; sweep++) {
     for (int step = 0; step < nb - 1; step++) {
       for (int pr = blockIdx.x; pr < npairs; pr += gridDim.x) {
         int I, J;
         rr_pair_blk(nb, step, pr, I, J);
         const bool rot = process_pair(a, I, J, tol, H, Vm, red, rot_c, rot_s, rot_p, rot_q, &s_any);
-        if (rot && threadIdx.x == 0) atomicAdd(&counters[sweep], 1u);
+        if (rot && threadIdx.x == 0)
+          __hip_atomic_fetch_add(&counters[sweep], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      grid.sync();
+      if (!grid_barrier(&a.st->bar_count, &a.st->bar_gen, &s_bar_ok)) {
+        timed_out = true;
+        break;
+      }
     }
+    if (timed_out) break;
     const uint32_t cnt = __hip_atomic_load(&counters[sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (cnt == 0) {
       converged = true;
@@ -214,16 +259,28 @@ __global__ void __launch_bounds__(256) bjacobi_kernel(JacArgs a) {
       break;
     }
   }
+  if (timed_out && threadIdx.x == 0)
+    __hip_atomic_fetch_or(&a.st->flags, (uint32_t)RSVD_FLAG_SYNC_TIMEOUT, __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_AGENT);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     a.st->sweeps = sweep;
-    if (!converged) atomicOr(&a.st->flags, (uint32_t)RSVD_FLAG_JACOBI_MAXSWEEP);
+    if (!converged)
+      __hip_atomic_fetch_or(&a.st->flags, (uint32_t)RSVD_FLAG_JACOBI_MAXSWEEP, __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
-// M (Lp x Lp) <- R (l x l) zero padded; P <- identity on the leading l x l.
+// M (Lp x Lp) <- R (l x l) zero padded; P <- identity on the leading l x l;
+// sweep counters and the grid barrier cleared.
 __global__ void __launch_bounds__(256) jac_init_kernel(int l, int Lp, const double* __restrict__ R,
-                                                       double* __restrict__ M, double* __restrict__ P) {
+                                                       double* __restrict__ M, double* __restrict__ P,
+                                                       DevState* st) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (blockIdx.x == 0 && threadIdx.x < 64) st->rot_count[threadIdx.x] = 0u;
+  if (idx == 0) {
+    st->bar_count = 0u;
+    st->bar_gen = 0u;
+  }
   if (idx >= (int64_t)Lp * Lp) return;
   const int i = (int)(idx / Lp), c = (int)(idx % Lp);
   M[idx] = (i < l && c < l) ? R[(int64_t)i * l + c] : 0.0;
@@ -240,11 +297,11 @@ int64_t jacobi_padded(int64_t l) {
 }
 
 rsvd_status block_jacobi(int64_t l, const double* R, double* M, double* P, int max_sweeps,
-                         int inner_sweeps, DevState* st, hipStream_t s) {
+                         int inner_sweeps, DevState* st, hipStream_t s, int share) {
   const int Lp = (int)jacobi_padded(l);
   const int64_t tot = (int64_t)Lp * Lp;
   hipLaunchKernelGGL(jac_init_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, (int)l,
-                     Lp, R, M, P);
+                     Lp, R, M, P, st);
   RSVD_LAUNCH_CHECK();
   JacArgs a;
   a.l = (int)l;
@@ -263,12 +320,12 @@ rsvd_status block_jacobi(int64_t l, const double* R, double* M, double* P, int m
       hipSuccess)
     return RSVD_EHIP;
   int grid = (Lp / 16) / 2;
-  const int cap = ncu * (per_cu > 0 ? per_cu : 1);
+  // grids of concurrent runs (share of them) must fit on the device together
+  int cap = ncu * (per_cu > 0 ? per_cu : 1) / (share > 1 ? share : 1);
+  if (cap < 1) cap = 1;
   if (grid > cap) grid = cap;
-  void* args[] = {&a};
-  if (hipLaunchCooperativeKernel((const void*)bjacobi_kernel, dim3(grid), dim3(256), args, 0, s) !=
-      hipSuccess)
-    return RSVD_EHIP;
+  hipLaunchKernelGGL(bjacobi_kernel, dim3(grid), dim3(256), 0, s, a);
+  RSVD_LAUNCH_CHECK();
   return RSVD_OK;
 }
 

@@ -76,6 +76,8 @@ struct DevState {
   double s1lb2;          // largest squared row norm of Q^T A so far (<= sigma_1^2)
   double froY2;          // ||Q^T A||_F^2 so far
   uint32_t rot_count[64];  // rotations per Jacobi sweep (convergence test)
+  uint32_t bar_count;    // grid barrier of the Jacobi kernel: arrivals
+  uint32_t bar_gen;      //   and generation
 };
 
 }  // namespace rsvd

@@ -52,8 +52,10 @@ rsvd_status jacobi_rows(int64_t l, double* M, double* P, int max_sweeps, DevStat
 // workspace buffers; M <- R zero padded, P <- I, then the rows of M are
 // orthogonalized and the rotations accumulated in P.
 int64_t jacobi_padded(int64_t l);
+// share > 1: at most 1/share of the device's co-resident workgroups (for
+// runs on concurrent streams, whose cooperative grids must fit together).
 rsvd_status block_jacobi(int64_t l, const double* R, double* M, double* P, int max_sweeps,
-                         int inner_sweeps, DevState* st, hipStream_t s);
+                         int inner_sweeps, DevState* st, hipStream_t s, int share = 1);
 // From converged M, P: s (decreasing), Us (l x kc), W (l x kc).
 rsvd_status svd_finish(int64_t l, int64_t kc, const double* M, const double* P, int64_t ld,
                        double* s, double* Us, double* W, DevState* st, hipStream_t st_);

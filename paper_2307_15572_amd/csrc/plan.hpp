@@ -1,0 +1,33 @@
+// Plan object behind rsvd_plan_t (internal; shared by the single and
+// batched entry points).
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/rsvd.h"
+
+struct rsvd_plan_s {
+  rsvd_problem p;
+  int64_t l = 0;        // sketch width
+  int64_t kc = 0;       // columns produced: min(k_cap, l)
+  int64_t k_fixed = 0;  // resolved fixed rank (fixed / percent rules)
+  int mode = 0;
+  double param = 0.0;
+  // workspace layout (byte offsets, 256-B aligned)
+  size_t off_state = 0, off_Y = 0, off_Z = 0, off_T = 0, off_part = 0, off_G = 0;
+  size_t off_R1 = 0, off_R1i = 0, off_R2 = 0, off_R2i = 0, off_R3 = 0, off_R3i = 0;
+  size_t off_Rt = 0, off_Rtmp = 0, off_M = 0, off_P = 0, off_sig = 0, off_Us = 0, off_W = 0;
+  size_t off_Ub = 0, off_Vb = 0, off_US = 0, off_Vt = 0, off_rpart = 0;
+  size_t off_Yorig = 0, off_tau = 0;
+  // adaptive range finder: l above is l_max; blocks of blk columns
+  bool adaptive = false;
+  int64_t blk = 0;
+  size_t off_Wb = 0, off_Zb = 0, off_Ob = 0, off_Cb = 0, off_Zc = 0;
+  // the small SVD's cooperative grid is capped at 1/coop_share of what the
+  // device holds at once (runs sharing the device concurrently set it to
+  // their number, so their grids are co-resident together)
+  int coop_share = 1;
+  size_t part_doubles = 0;
+  size_t total = 0;
+};

@@ -23,6 +23,7 @@
 
 #include "common.hpp"
 #include "kernels.hpp"
+#include "plan.hpp"
 
 using namespace rsvd;
 
@@ -68,27 +69,6 @@ struct PhaseScope {
 };
 
 }  // namespace
-
-struct rsvd_plan_s {
-  rsvd_problem p;
-  int64_t l = 0;        // sketch width
-  int64_t kc = 0;       // columns produced: min(k_cap, l)
-  int64_t k_fixed = 0;  // resolved fixed rank (fixed / percent rules)
-  int mode = 0;
-  double param = 0.0;
-  // workspace layout (byte offsets, 256-B aligned)
-  size_t off_state = 0, off_Y = 0, off_Z = 0, off_T = 0, off_part = 0, off_G = 0;
-  size_t off_R1 = 0, off_R1i = 0, off_R2 = 0, off_R2i = 0, off_R3 = 0, off_R3i = 0;
-  size_t off_Rt = 0, off_Rtmp = 0, off_M = 0, off_P = 0, off_sig = 0, off_Us = 0, off_W = 0;
-  size_t off_Ub = 0, off_Vb = 0, off_US = 0, off_Vt = 0, off_rpart = 0;
-  size_t off_Yorig = 0, off_tau = 0;
-  // adaptive range finder: l above is l_max; blocks of blk columns
-  bool adaptive = false;
-  int64_t blk = 0;
-  size_t off_Wb = 0, off_Zb = 0, off_Ob = 0, off_Cb = 0, off_Zc = 0;
-  size_t part_doubles = 0;
-  size_t total = 0;
-};
 
 namespace {
 
@@ -364,7 +344,7 @@ rsvd_status small_svd_and_rank(const rsvd_plan_s& pl, const Ws& w, int64_t l, do
   {
     PhaseScope ph(2, s);
     RSVD_TRY(block_jacobi(l, Rt, w.at<double>(pl.off_M), w.at<double>(pl.off_P),
-                          p.max_sweeps > 0 ? p.max_sweeps : 30, 1, st, s));
+                          p.max_sweeps > 0 ? p.max_sweeps : 30, 1, st, s, pl.coop_share));
     RSVD_TRY(svd_finish(l, kcl, w.at<double>(pl.off_M), w.at<double>(pl.off_P), jacobi_padded(l),
                         w.at<double>(pl.off_sig), w.at<double>(pl.off_Us), w.at<double>(pl.off_W),
                         st, s));

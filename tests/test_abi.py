@@ -126,3 +126,38 @@ def test_adaptive_run_rejects_caller_projection():
     fake = ctypes.c_void_p(256)  # never dereferenced: validation fails first
     st = L.rsvd_run(pl._h, fake, 80, fake, 32, fake, fake, 32, fake, 32, fake, fake, 10**12, None)
     assert st == rs.RSVD_EINVAL
+
+
+def _batch_problems(sizes, **kw):
+    return [dict(m=n, n=n, k=min(20, n - 4), p=4, q=1, **kw) for n in sizes]
+
+
+def test_batch_plan_lpt_and_workspace():
+    sizes = [300, 90, 500, 120, 64, 410, 250, 77, 333, 150]
+    bp = rs.BatchPlan(_batch_problems(sizes), lanes=3, use_graph=False)
+    lanes = bp.lanes_of()
+    assert sorted(set(lanes)) == [0, 1, 2]
+    # LPT by m n l (2q + 2 + residual): the costliest channel opens lane 0 and
+    # every lane's load stays within the largest single cost of the others
+    cost = [n * n * min(24, n) * 5 for n in sizes]
+    load = [sum(c for c, ln in zip(cost, lanes) if ln == i) for i in range(3)]
+    assert lanes[sizes.index(500)] == 0
+    assert max(load) - min(load) <= max(cost)
+    # workspace: one slice per lane, sized for its largest channel
+    single = [rs.Plan(n, n, min(20, n - 4), 4, 1).workspace_bytes for n in sizes]
+    want = sum(-(-max(s for s, ln in zip(single, lanes) if ln == i) // 256) * 256 for i in range(3))
+    assert bp.workspace_bytes == want
+
+
+def test_batch_plan_validation():
+    with pytest.raises(rs.RsvdError, match="invalid"):
+        rs.BatchPlan([])
+    with pytest.raises(rs.RsvdError, match="invalid"):
+        rs.BatchPlan(_batch_problems([100]), lanes=17)
+    with pytest.raises(rs.RsvdError, match="invalid"):
+        rs.BatchPlan([dict(m=100, n=80, k=0, p=4, q=1, rank_mode="rel_threshold",
+                           rank_param=1e-6, adaptive=True)])
+    with pytest.raises(rs.RsvdError, match="invalid"):
+        rs.BatchPlan(_batch_problems([100]) + [dict(m=10, n=0, k=2, p=1, q=0)])
+    bp = rs.BatchPlan(_batch_problems([100, 50]), lanes=8)
+    assert sorted(bp.lanes_of()) == [0, 1]  # lanes never exceed the channel count
