@@ -184,44 +184,6 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
   return true;
 }
 
-// Polls of the barrier generation before a workgroup gives up (each poll is
-// an agent-scope load after a short sleep: about two seconds in all).
-constexpr uint32_t kSpinLimit = 1u << 20;
-
-// Barrier over the gridDim.x workgroups of a launch whose whole grid fits on
-// the device at once. The last workgroup to arrive resets the counter and
-// advances the generation; the others wait for the generation to change.
-// Every thread fences at agent scope on both sides, so the rows written
-// before the barrier by any workgroup (on any XCD) are visible after it.
-// Returns false if this workgroup stopped waiting.
-__device__ bool grid_barrier(uint32_t* count, uint32_t* gen, int* s_ok) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int ok = 1;
-    const uint32_t g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t arrived =
-        __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-    if (arrived == gridDim.x) {
-      __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
-      uint32_t spins = 0;
-      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-        if (++spins > kSpinLimit) {
-          ok = 0;
-          break;
-        }
-        __builtin_amdgcn_s_sleep(8);
-      }
-    }
-    *s_ok = ok;
-  }
-  __syncthreads();
-  __threadfence();
-  return *s_ok != 0;
-}
-
 __global__ void __launch_bounds__(256) bjacobi_kernel(JacArgs a) {
   __shared__ int s_bar_ok;
   __shared__ double H[32][33];
@@ -246,7 +208,7 @@ __global__ void __launch_bounds__(256) bjacobi_kernel(JacArgs a) {
         if (rot && threadIdx.x == 0)
           __hip_atomic_fetch_add(&counters[sweep], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      if (!grid_barrier(&a.st->bar_count, &a.st->bar_gen, &s_bar_ok)) {
+      if (!grid_barrier(&a.st->bar_count, &a.st->bar_gen, &a.st->bar_abort, &s_bar_ok)) {
         timed_out = true;
         break;
       }
@@ -280,6 +242,7 @@ __global__ void __launch_bounds__(256) jac_init_kernel(int l, int Lp, const doub
   if (idx == 0) {
     st->bar_count = 0u;
     st->bar_gen = 0u;
+    st->bar_abort = 0u;
   }
   if (idx >= (int64_t)Lp * Lp) return;
   const int i = (int)(idx / Lp), c = (int)(idx % Lp);
@@ -320,8 +283,9 @@ rsvd_status block_jacobi(int64_t l, const double* R, double* M, double* P, int m
       hipSuccess)
     return RSVD_EHIP;
   int grid = (Lp / 16) / 2;
-  // grids of concurrent runs (share of them) must fit on the device together
-  int cap = ncu * (per_cu > 0 ? per_cu : 1) / (share > 1 ? share : 1);
+  // grids of concurrent runs (share of them) must fit on the device together:
+  // half of a fair share, so that grids of different kernels also fit
+  int cap = ncu * (per_cu > 0 ? per_cu : 1) / (share > 1 ? 2 * share : 1);
   if (cap < 1) cap = 1;
   if (grid > cap) grid = cap;
   hipLaunchKernelGGL(bjacobi_kernel, dim3(grid), dim3(256), 0, s, a);

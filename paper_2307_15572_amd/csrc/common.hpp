@@ -60,6 +60,51 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// Polls of the barrier generation before a workgroup gives up (each poll is
+// an agent-scope load after a short sleep: about two seconds in all).
+constexpr uint32_t kSpinLimit = 1u << 20;
+
+// Barrier over the gridDim.x workgroups of a launch whose whole grid fits on
+// the device at once. The last workgroup to arrive resets the counter and
+// advances the generation; the others wait for the generation to change.
+// Every thread fences at agent scope on both sides, so the data written
+// before the barrier by any workgroup (on any XCD) is visible after it.
+// A workgroup that has waited kSpinLimit polls raises *abort and leaves;
+// waiters see *abort and leave too. Returns false once the barrier has
+// been abandoned: the kernel must then return.
+__device__ inline bool grid_barrier(uint32_t* count, uint32_t* gen, uint32_t* abort, int* s_ok) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const uint32_t g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t arrived =
+        __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    if (arrived == gridDim.x) {
+      __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      uint32_t spins = 0;
+      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+          ok = 0;
+          break;
+        }
+        if (++spins > kSpinLimit) {
+          __hip_atomic_store(abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(8);
+      }
+    }
+    *s_ok = ok;
+  }
+  __syncthreads();
+  __threadfence();
+  return *s_ok != 0;
+}
+
 // Device-side scalar state of one decomposition, kept in the workspace.
 struct DevState {
   uint32_t flags;        // RSVD_FLAG_* accumulated by the kernels
@@ -76,8 +121,11 @@ struct DevState {
   double s1lb2;          // largest squared row norm of Q^T A so far (<= sigma_1^2)
   double froY2;          // ||Q^T A||_F^2 so far
   uint32_t rot_count[64];  // rotations per Jacobi sweep (convergence test)
-  uint32_t bar_count;    // grid barrier of the Jacobi kernel: arrivals
-  uint32_t bar_gen;      //   and generation
+  uint32_t bar_count;    // grid barrier of the multi-workgroup kernels
+  uint32_t bar_gen;      //   (Jacobi, Cholesky): arrivals, generation
+  uint32_t bar_abort;    //   and the abandon word
+  uint32_t chol_fail;    // multi-workgroup Cholesky: a pivot broke down
+  double piv_max, piv_min;  // and the range of its pivots
 };
 
 }  // namespace rsvd

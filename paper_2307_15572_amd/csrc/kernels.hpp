@@ -35,8 +35,14 @@ rsvd_status gaussian_omega(int64_t n, int64_t l, int64_t col0, uint64_t seed, ui
 // Rinv = R^{-1}. pass 0 may switch to the shifted factorization (sets
 // st->qr_shifted); a pass with only_if_shifted != 0 does nothing unless
 // st->qr_shifted is set. m = rows of the panel (sizes the shift).
-rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, int64_t m, int pass,
-                     int only_if_shifted, DevState* st, hipStream_t s);
+// scratch: chol_panel_doubles(l) doubles of global memory, used for the
+// current block row when it does not fit in LDS (l > 1168).
+size_t chol_panel_doubles(int64_t l);
+// From l = 320 the factorization and inverse run on a grid of workgroups
+// (at most 1/share of the device's co-resident capacity, for runs on
+// concurrent streams).
+rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, double* scratch, int64_t m,
+                     int pass, int only_if_shifted, DevState* st, hipStream_t s, int share = 1);
 // Householder QR of the rows x l panel Yorig into Y (= Q) and R, run only
 // when st->qr_householder is set (tau: 2 l doubles of scratch).
 rsvd_status householder_fallback(int64_t rows, int64_t l, const double* Yorig, double* Y,
@@ -45,9 +51,6 @@ rsvd_status householder_fallback(int64_t rows, int64_t l, const double* Yorig, d
 // st->qr_shifted is set (cond 1), only when it is clear (cond 2).
 rsvd_status copy_panel(int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst,
                        int64_t ldd, int cond_shifted, DevState* st, hipStream_t s);
-// One-sided Jacobi on the rows of M (l x l): P M0 = M with orthogonal rows.
-rsvd_status jacobi_rows(int64_t l, double* M, double* P, int max_sweeps, DevState* st,
-                        hipStream_t s);
 // Block one-sided Jacobi (bjacobi.hip): M, P are Lp x Lp (Lp = jacobi_padded(l))
 // workspace buffers; M <- R zero padded, P <- I, then the rows of M are
 // orthogonalized and the rotations accumulated in P.

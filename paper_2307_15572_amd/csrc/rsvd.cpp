@@ -139,6 +139,7 @@ rsvd_status orth(const rsvd_plan_s& pl, const Ws& w, int64_t rows, int64_t l, do
   double* R3i = w.at<double>(pl.off_R3i);
   double* Yorig = w.at<double>(pl.off_Yorig);
   double* tau = w.at<double>(pl.off_tau);
+  double* Rtmp = w.at<double>(pl.off_Rtmp);  // block-row scratch of the factorization
   const uint32_t* shifted = &st->qr_shifted;
   const uint32_t* p1 = full ? nullptr : shifted;  // pass 1 runs always, or only after a shift
   rsvd_status r;
@@ -147,20 +148,19 @@ rsvd_status orth(const rsvd_plan_s& pl, const Ws& w, int64_t rows, int64_t l, do
   RSVD_TRY(copy_panel(rows, l, Y, l, Yorig, l, 0, st, s));
   // pass 0
   RSVD_TRY(dgemm(true, l, l, rows, 1.0, Y, l, Y, l, 0.0, G, l, part, pl.part_doubles, s));
-  RSVD_TRY(chol_inv(l, G, R1, R1i, rows, 0, 0, st, s));
+  RSVD_TRY(chol_inv(l, G, R1, R1i, Rtmp, rows, 0, 0, st, s, pl.coop_share));
   RSVD_TRY(dgemm(false, rows, l, l, 1.0, Y, l, R1i, l, 0.0, T, l, part, pl.part_doubles, s));
   // pass 1
   RSVD_TRY(dgemm(true, l, l, rows, 1.0, T, l, T, l, 0.0, G, l, part, pl.part_doubles, s, 64, p1));
-  RSVD_TRY(chol_inv(l, G, R2, R2i, rows, 1, full ? 0 : 1, st, s));
+  RSVD_TRY(chol_inv(l, G, R2, R2i, Rtmp, rows, 1, full ? 0 : 1, st, s, pl.coop_share));
   RSVD_TRY(dgemm(false, rows, l, l, 1.0, T, l, R2i, l, 0.0, Y, l, part, pl.part_doubles, s, 64, p1));
   if (!full) RSVD_TRY(copy_panel(rows, l, T, l, Y, l, 2, st, s));  // unshifted: Q = T
   // pass 2 (device-predicated on the shift)
   RSVD_TRY(dgemm(true, l, l, rows, 1.0, Y, l, Y, l, 0.0, G, l, part, pl.part_doubles, s, 64, shifted));
-  RSVD_TRY(chol_inv(l, G, R3, R3i, rows, 2, 1, st, s));
+  RSVD_TRY(chol_inv(l, G, R3, R3i, Rtmp, rows, 2, 1, st, s, pl.coop_share));
   RSVD_TRY(dgemm(false, rows, l, l, 1.0, Y, l, R3i, l, 0.0, T, l, part, pl.part_doubles, s, 64, shifted));
   RSVD_TRY(copy_panel(rows, l, T, l, Y, l, 1, st, s));
   if (Rout) {
-    double* Rtmp = w.at<double>(pl.off_Rtmp);
     // R = R2 R1, then R3 R when shifted
     RSVD_TRY(dgemm(false, l, l, l, 1.0, R2, l, R1, l, 0.0, Rout, l, part, pl.part_doubles, s));
     RSVD_TRY(dgemm(false, l, l, l, 1.0, R3, l, Rout, l, 0.0, Rtmp, l, part, pl.part_doubles, s, 64, shifted));

@@ -1,11 +1,10 @@
 // Small dense kernels of the randomized SVD: the l x l work between the
-// streaming products (Cholesky QR factors, the small SVD by one-sided
-// Jacobi, ordering, rank rule, signs, residual bookkeeping).
+// streaming products (Cholesky QR factors, Householder fallback, ordering of
+// the small SVD, rank rule, signs, residual bookkeeping). The Jacobi sweeps
+// of the small SVD are in bjacobi.hip.
 //
 // Paper mapping (section "Randomized matrix decompositions", Fig. 1):
 //   chol_inv      thin QR Z = Q X of step 1 (Cholesky QR: X^T X = Z^T Z)
-//   jacobi_rows   thin SVD of the projected matrix, step 2 (applied to the
-//                 triangular factor of its transpose)
 //   svd_finish    singular values ordered decreasingly (Eq. 1)
 //   select_rank   R_SVD, R% and the compression ratio of Eq. 2
 #include "common.hpp"
@@ -19,6 +18,7 @@ namespace {
 
 constexpr double kUnitRoundoff = 1.1102230246251565e-16;  // 2^-53
 constexpr int kBig = 1024;                                // threads of the l x l kernels
+constexpr int64_t kCholGridMin = 320;  // l from which the Cholesky runs on a grid of workgroups
 
 __device__ __forceinline__ double block_sum(double v, double* red) {
   v = wave_sum(v);
@@ -31,159 +31,6 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
   for (int i = 0; i < nw; i++) s += red[i];
   return s;
 }
-
-// ---------------------------------------------------------------------------
-// Cholesky R^T R = G (+ shift I) and the inverse of R, one workgroup.
-// The factor is built in place in R's upper triangle (row j of R is column j
-// of the lower Cholesky factor), right-looking, one pivot per step.
-// W: working storage (LDS when small, else R itself in global memory).
-// ---------------------------------------------------------------------------
-__device__ bool chol_upper(int l, double* W, int ldw, double* red, double* bcast) {
-  bool ok = true;
-  for (int j = 0; j < l; j++) {
-    if (threadIdx.x == 0) {
-      const double d = W[(int64_t)j * ldw + j];
-      const bool good = d > 0.0 && isfinite(d);
-      bcast[0] = good ? sqrt(d) : -1.0;
-    }
-    __syncthreads();
-    const double rjj = bcast[0];
-    if (rjj < 0.0) { ok = false; break; }
-    const double inv = 1.0 / rjj;
-    for (int c = j + 1 + threadIdx.x; c < l; c += blockDim.x) W[(int64_t)j * ldw + c] *= inv;
-    __syncthreads();
-    if (threadIdx.x == 0) W[(int64_t)j * ldw + j] = rjj;
-    // trailing update of the upper triangle: W[i][c] -= R[j][i] R[j][c], j < i <= c
-    const int nt = l - j - 1;
-    const int64_t cnt = (int64_t)nt * nt;
-    for (int64_t e = threadIdx.x; e < cnt; e += blockDim.x) {
-      const int i = j + 1 + (int)(e / nt);
-      const int c = j + 1 + (int)(e % nt);
-      if (c >= i) W[(int64_t)i * ldw + c] -= W[(int64_t)j * ldw + i] * W[(int64_t)j * ldw + c];
-    }
-    __syncthreads();
-  }
-  __syncthreads();
-  return ok;
-}
-
-// X = R^{-1} (upper). Thread c owns column c: R X = I by back substitution.
-__device__ void tri_inv_upper(int l, const double* R, int ldr, double* X, int ldx) {
-  for (int c = threadIdx.x; c < l; c += blockDim.x) {
-    for (int i = c + 1; i < l; i++) X[(int64_t)i * ldx + c] = 0.0;
-    X[(int64_t)c * ldx + c] = 1.0 / R[(int64_t)c * ldr + c];
-    for (int i = c - 1; i >= 0; i--) {
-      double s = 0.0;
-      for (int k = i + 1; k <= c; k++) s += R[(int64_t)i * ldr + k] * X[(int64_t)k * ldx + c];
-      X[(int64_t)i * ldx + c] = -s / R[(int64_t)i * ldr + i];
-    }
-  }
-  __syncthreads();
-}
-
-__global__ void __launch_bounds__(kBig) chol_inv_kernel(int l, const double* __restrict__ G,
-                                                        double* __restrict__ R,
-                                                        double* __restrict__ Rinv, int64_t m,
-                                                        int pass, int only_if_shifted,
-                                                        DevState* st) {
-  extern __shared__ double lds[];
-  __shared__ double red[kBig / 64];
-  __shared__ double bcast[2];
-  if (only_if_shifted && st->qr_shifted == 0) return;
-  const bool in_lds = (int64_t)l * l * 2 * sizeof(double) <= 150 * 1024;
-  double* W = in_lds ? lds : R;
-  double* X = in_lds ? lds + (int64_t)l * l : Rinv;
-  const int64_t ll = (int64_t)l * l;
-
-  // trace -> shift for the shifted factorization (Fukaya et al. 2020:
-  // s = 11 (m l + l (l + 1)) u ||Z||_2^2, with ||Z||_2^2 <= trace(Z^T Z))
-  double tr = 0.0;
-  for (int i = threadIdx.x; i < l; i += blockDim.x) tr += G[(int64_t)i * l + i];
-  tr = block_sum(tr, red);
-  const double shift = 11.0 * ((double)m * l + (double)l * (l + 1)) * kUnitRoundoff * tr;
-
-  bool use_shift = false;
-  for (int attempt = 0; attempt < 2; attempt++) {
-    for (int64_t e = threadIdx.x; e < ll; e += blockDim.x) {
-      const int i = (int)(e / l), c = (int)(e % l);
-      double v = (c >= i) ? G[e] : 0.0;
-      if (use_shift && i == c) v += shift;
-      W[e] = v;
-    }
-    __syncthreads();
-    bool ok = chol_upper(l, W, l, red, bcast);
-    if (ok && pass == 0 && !use_shift) {
-      // diag(R) bounds kappa(Z) from below; past 1e5 two unshifted passes may
-      // not restore orthogonality, so take the shifted three-pass route
-      double dmax = 0.0, dmin = INFINITY;
-      for (int i = threadIdx.x; i < l; i += blockDim.x) {
-        const double d = W[(int64_t)i * l + i];
-        dmax = fmax(dmax, d);
-        dmin = fmin(dmin, d);
-      }
-      dmax = wave_max(dmax);
-      dmin = -wave_max(-dmin);
-      __syncthreads();
-      if ((threadIdx.x & 63) == 0) { red[threadIdx.x >> 6] = dmax; }
-      __syncthreads();
-      double gmax = 0.0;
-      for (int i = 0; i < (int)(blockDim.x >> 6); i++) gmax = fmax(gmax, red[i]);
-      __syncthreads();
-      if ((threadIdx.x & 63) == 0) { red[threadIdx.x >> 6] = dmin; }
-      __syncthreads();
-      double gmin = INFINITY;
-      for (int i = 0; i < (int)(blockDim.x >> 6); i++) gmin = fmin(gmin, red[i]);
-      __syncthreads();
-      if (gmax > 1e5 * gmin) ok = false;
-    }
-    if (ok) break;
-    if (pass != 0 || use_shift) {
-      // breakdown even with the shift: the panel is numerically rank
-      // deficient. Finish with clamped pivots so every value stays finite and
-      // hand the panel to the Householder fallback.
-      if (threadIdx.x == 0) st->qr_householder = 1;
-      for (int64_t e = threadIdx.x; e < ll; e += blockDim.x) {
-        const int i = (int)(e / l), c = (int)(e % l);
-        double v = (c >= i) ? G[e] : 0.0;
-        if (i == c) v += fmax(shift, 1e-300);
-        W[e] = v;
-      }
-      __syncthreads();
-      for (int j = 0; j < l; j++) {
-        if (threadIdx.x == 0) {
-          double d = W[(int64_t)j * l + j];
-          if (!(d > shift)) d = fmax(shift, 1e-300);
-          bcast[0] = sqrt(d);
-        }
-        __syncthreads();
-        const double rjj = bcast[0];
-        for (int c = j + 1 + threadIdx.x; c < l; c += blockDim.x) W[(int64_t)j * l + c] /= rjj;
-        __syncthreads();
-        if (threadIdx.x == 0) W[(int64_t)j * l + j] = rjj;
-        const int nt = l - j - 1;
-        for (int64_t e = threadIdx.x; e < (int64_t)nt * nt; e += blockDim.x) {
-          const int i = j + 1 + (int)(e / nt), c = j + 1 + (int)(e % nt);
-          if (c >= i) W[(int64_t)i * l + c] -= W[(int64_t)j * l + i] * W[(int64_t)j * l + c];
-        }
-        __syncthreads();
-      }
-      break;
-    }
-    use_shift = true;
-    if (threadIdx.x == 0) {
-      st->qr_shifted = 1;
-    }
-    __syncthreads();
-  }
-  tri_inv_upper(l, W, l, X, l);
-  if (in_lds) {
-    for (int64_t e = threadIdx.x; e < ll; e += blockDim.x) {
-      R[e] = W[e];
-      Rinv[e] = X[e];
-    }
-  }
-}
-
 
 // ---------------------------------------------------------------------------
 // Householder QR of a rows x l panel (rows >= l), one workgroup: the fallback
@@ -497,9 +344,35 @@ __device__ __forceinline__ void load_tile_a(const TileCtx& cx, const double* W, 
 // of [[R11, R12], [0, R22]] is -X11 R12 X22. Block sizes 1, 2, 4, ... tiles;
 // every level runs T = R12 X22 into the scratch S, then X12 = -X11 T.
 // Diagonal tiles of X are already in Xg.
-__device__ void tiled_inverse(const TileCtx& cx, const double* W, double* Xg, double* S) {
-  const int wave = threadIdx.x >> 6;
-  const int nw = blockDim.x >> 6;
+// Team: the waves that share the work (id in [0, size)) and their barrier
+// (a workgroup's __syncthreads, or a grid barrier across workgroups).
+struct BlockTeam {
+  __device__ int id() const { return threadIdx.x >> 6; }
+  __device__ int size() const { return blockDim.x >> 6; }
+  __device__ bool sync() const {
+    __syncthreads();
+    return true;
+  }
+};
+struct GridTeam {
+  DevState* st;
+  int* s_ok;
+  __device__ int id() const { return blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); }
+  __device__ int size() const { return gridDim.x * (blockDim.x >> 6); }
+  __device__ bool sync() const {
+    if (grid_barrier(&st->bar_count, &st->bar_gen, &st->bar_abort, s_ok)) return true;
+    if (threadIdx.x == 0)
+      __hip_atomic_fetch_or(&st->flags, (uint32_t)RSVD_FLAG_SYNC_TIMEOUT, __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT);
+    return false;
+  }
+};
+
+template <class Team>
+__device__ bool tiled_inverse(const Team& tm, const TileCtx& cx, const double* W, double* Xg,
+                              double* S) {
+  const int wave = tm.id();
+  const int nw = tm.size();
   const int nb = cx.nb;
   constexpr int KB = 4;
   for (int bs = 1; bs < nb; bs *= 2) {
@@ -546,14 +419,16 @@ __device__ void tiled_inverse(const TileCtx& cx, const double* W, double* Xg, do
         for (int it = 0; it < 4; it++) o[it] = phase == 0 ? acc[it] : -acc[it];
         store_tile(cx, phase == 0 ? S : Xg, i, j, o);
       }
-      __syncthreads();
+      if (!tm.sync()) return false;
     }
   }
+  return true;
 }
 
 __global__ void __launch_bounds__(512) chol_tiles_kernel(int l, double* __restrict__ G,
                                                           double* __restrict__ R,
-                                                          double* __restrict__ Rinv, int64_t m,
+                                                          double* __restrict__ Rinv,
+                                                          double* __restrict__ panel_g, int64_t m,
                                                           int pass, int only_if_shifted,
                                                           DevState* st) {
   extern __shared__ double lds[];
@@ -565,8 +440,10 @@ __global__ void __launch_bounds__(512) chol_tiles_kernel(int l, double* __restri
   cx.l = l;
   cx.nb = (l + 15) / 16;
   cx.ps = 16 * cx.nb + 1;
-  double* panel = lds;
-  double* dinv = lds + 16 * cx.ps;
+  // the current block row lives in LDS, or in global scratch when it does
+  // not fit (L2-resident either way)
+  double* panel = panel_g ? panel_g : lds;
+  double* dinv = panel_g ? lds : lds + 16 * cx.ps;
   const int64_t ll = (int64_t)l * l;
 
   double tr = 0.0;
@@ -599,7 +476,7 @@ __global__ void __launch_bounds__(512) chol_tiles_kernel(int l, double* __restri
     __syncthreads();
   }
   // G is no longer read: it serves as scratch for the inverse
-  tiled_inverse(cx, R, Rinv, G);
+  tiled_inverse(BlockTeam{}, cx, R, Rinv, G);
   // strictly lower parts are zero
   for (int64_t e = threadIdx.x; e < ll; e += blockDim.x) {
     if (e / l > e % l) {
@@ -609,6 +486,169 @@ __global__ void __launch_bounds__(512) chol_tiles_kernel(int l, double* __restri
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// The same Cholesky and inverse spread over a grid of workgroups (large l):
+// every wave of the grid takes tiles, the phases are separated by the grid
+// barrier, and the block row lives in global scratch. Look-ahead: the wave
+// that applies step k's update to diagonal tile k+1 factors it right away, so
+// a step has two barriers (after the block row, after the trailing update).
+// Decisions (breakdown, pivot spread, retries) are uniform across the grid.
+// ---------------------------------------------------------------------------
+
+// Factor the updated diagonal tile k held in t (one wave): R_kk, X_kk = R_kk^{-1}
+// to W / Xg; breakdown and the pivot range go to the state (one writer per step).
+__device__ void grid_diag_factor(const TileCtx& cx, double t[4], int k, double* W, double* Xg,
+                                 bool clamp, double clampv, DevState* st) {
+  double dmax = 0.0, dmin = INFINITY, x[4];
+  const bool ok = tile_chol(t, clamp, clampv, 16 * k, cx.l, dmax, dmin);
+  tile_inv_upper(t, x);
+  store_tile(cx, W, k, k, t);
+  store_tile(cx, Xg, k, k, x);
+  if ((threadIdx.x & 63) == 0) {
+    if (!ok) st->chol_fail = 1u;
+    if (dmax > st->piv_max) st->piv_max = dmax;
+    if (dmin < st->piv_min) st->piv_min = dmin;
+  }
+}
+
+// Entry (row, col) of the inverse diagonal tile k (identity beyond l).
+__device__ __forceinline__ double xdiag(const TileCtx& cx, const double* Xg, int k, int row,
+                                        int col) {
+  const int i = 16 * k + row, c = 16 * k + col;
+  return cx.in(i, c) ? Xg[(int64_t)i * cx.l + c] : (row == col ? 1.0 : 0.0);
+}
+
+__global__ void __launch_bounds__(512) chol_grid_kernel(int l, double* __restrict__ G,
+                                                         double* __restrict__ R,
+                                                         double* __restrict__ Rinv,
+                                                         double* __restrict__ panel, int64_t m,
+                                                         int pass, int only_if_shifted,
+                                                         DevState* st) {
+  __shared__ double red[512 / 64];
+  __shared__ int s_ok;
+  if (only_if_shifted && st->qr_shifted == 0) return;
+  const GridTeam tm{st, &s_ok};
+  const int gw = tm.id(), TW = tm.size();
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  TileCtx cx;
+  cx.l = l;
+  cx.nb = (l + 15) / 16;
+  cx.ps = 16 * cx.nb + 1;
+  const int nb = cx.nb, ps = cx.ps;
+  const int64_t ll = (int64_t)l * l;
+  const int64_t gthreads = (int64_t)gridDim.x * blockDim.x;
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+
+  // every workgroup forms the same trace (same entries, same order)
+  double tr = 0.0;
+  for (int i = threadIdx.x; i < l; i += blockDim.x) tr += G[(int64_t)i * l + i];
+  tr = block_sum(tr, red);
+  const double shift = 11.0 * ((double)m * l + (double)l * (l + 1)) * kUnitRoundoff * tr;
+  const double clampv = fmax(shift, 1e-300);
+
+  bool use_shift = false, clamp = false;
+  for (int attempt = 0; attempt < 3; attempt++) {
+    if (gw == 0 && lane == 0) {
+      st->chol_fail = 0u;
+      st->piv_max = 0.0;
+      st->piv_min = INFINITY;
+    }
+    for (int64_t e = gtid; e < ll; e += gthreads) {
+      double v = G[e];
+      if (use_shift && (e / l) == (e % l)) v += shift;
+      R[e] = v;
+    }
+    if (!tm.sync()) return;
+    if (gw == 0) {
+      double t[4];
+      load_tile(cx, R, 0, 0, t);
+      grid_diag_factor(cx, t, 0, R, Rinv, clamp, clampv, st);
+    }
+    if (!tm.sync()) return;
+    bool failed = __hip_atomic_load(&st->chol_fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+    for (int k = 0; k < nb && !failed; k++) {
+      // block row k: R_kJ = R_kk^{-T} G_kJ
+      for (int J = k + 1 + gw; J < nb; J += TW) {
+        double b[4];
+        load_tile(cx, R, k, J, b);
+        d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; s4++) acc = mfma_f64_16x16x4(xdiag(cx, Rinv, k, 4 * s4 + g, r), b[s4], acc);
+        double o[4] = {acc[0], acc[1], acc[2], acc[3]};
+        store_tile(cx, R, k, J, o);
+#pragma unroll
+        for (int it = 0; it < 4; it++) panel[(g + 4 * it) * ps + 16 * J + r] = o[it];
+      }
+      if (!tm.sync()) return;
+      // trailing tiles; the owner of tile (k+1, k+1) factors it after its update
+      const int n = nb - k - 1;
+      const int T = n * (n + 1) / 2;
+      constexpr int TB = 4;
+      for (int t0 = gw * TB; t0 < T; t0 += TW * TB) {
+        int Is[TB], Js[TB];
+        double tl[TB][4];
+        int I, J;
+        trailing_coords(t0, n, I, J);
+#pragma unroll
+        for (int q = 0; q < TB; q++) {
+          Is[q] = I + k + 1;
+          Js[q] = J + k + 1;
+          if (++J >= n) {
+            I++;
+            J = I;
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < TB; q++)
+          if (t0 + q < T) load_tile(cx, R, Is[q], Js[q], tl[q]);
+#pragma unroll
+        for (int q = 0; q < TB; q++) {
+          if (t0 + q < T) {
+            d4 acc = {tl[q][0], tl[q][1], tl[q][2], tl[q][3]};
+#pragma unroll
+            for (int s4 = 0; s4 < 4; s4++) {
+              const double a = -panel[(4 * s4 + g) * ps + 16 * Is[q] + r];
+              const double bb = panel[(4 * s4 + g) * ps + 16 * Js[q] + r];
+              acc = mfma_f64_16x16x4(a, bb, acc);
+            }
+            double o[4] = {acc[0], acc[1], acc[2], acc[3]};
+            if (t0 + q == 0) {
+              grid_diag_factor(cx, o, k + 1, R, Rinv, clamp, clampv, st);
+            } else {
+              store_tile(cx, R, Is[q], Js[q], o);
+            }
+          }
+        }
+      }
+      if (!tm.sync()) return;
+      failed = __hip_atomic_load(&st->chol_fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+    }
+    if (clamp) break;
+    bool ok = !failed;
+    if (ok && pass == 0 && !use_shift && st->piv_max > 1e5 * st->piv_min) ok = false;
+    if (ok) break;
+    if (pass != 0 || use_shift) {
+      // breakdown even with the shift: numerically rank-deficient panel
+      if (gw == 0 && lane == 0) st->qr_householder = 1;
+      clamp = true;
+      use_shift = true;
+    } else {
+      use_shift = true;
+      if (gw == 0 && lane == 0) st->qr_shifted = 1;
+    }
+    // every workgroup has read this attempt's outcome before the next resets it
+    if (!tm.sync()) return;
+  }
+  // G is no longer read: it serves as scratch for the inverse
+  if (!tiled_inverse(tm, cx, R, Rinv, G)) return;
+  for (int64_t e = gtid; e < ll; e += gthreads) {
+    if (e / l > e % l) {
+      R[e] = 0.0;
+      Rinv[e] = 0.0;
+    }
+  }
+}
 
 __global__ void __launch_bounds__(256) copy_panel_kernel(int64_t rows, int64_t cols,
                                                          const double* __restrict__ src, int64_t lds,
@@ -621,109 +661,6 @@ __global__ void __launch_bounds__(256) copy_panel_kernel(int64_t rows, int64_t c
   if (idx >= rows * cols) return;
   const int64_t r = idx / cols, c = idx % cols;
   dst[r * ldd + c] = src[r * lds + c];
-}
-
-// ---------------------------------------------------------------------------
-// One-sided Jacobi (Hestenes) on the rows of M, one workgroup.
-// Round-robin (circle) ordering: in each of the L-1 steps of a sweep the
-// L/2 disjoint row pairs are handled by different waves. A pair (a, b) with
-// |a.b| > tol sqrt(|a|^2 |b|^2) is rotated so that a.b = 0 (Rutishauser's
-// formulas); the same rotation is applied to the rows of P. Converged when
-// a sweep performs no rotation. tol = l u.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ void rr_pair(int L, int step, int i, int& a, int& b) {
-  // players 0..L-1, player L-1 fixed
-  if (i == 0) {
-    a = L - 1;
-    b = step;
-  } else {
-    a = (step + i) % (L - 1);
-    b = (step - i + (L - 1)) % (L - 1);
-  }
-}
-
-__global__ void __launch_bounds__(kBig) jacobi_kernel(int l, double* __restrict__ Mg,
-                                                      double* __restrict__ Pg, int max_sweeps,
-                                                      DevState* st) {
-  extern __shared__ double lds[];
-  __shared__ int s_rot;
-  const bool in_lds = (int64_t)l * l * 2 * sizeof(double) <= 150 * 1024;
-  const int64_t ll = (int64_t)l * l;
-  double* M = in_lds ? lds : Mg;
-  double* P = in_lds ? lds + ll : Pg;
-  if (in_lds) {
-    for (int64_t e = threadIdx.x; e < ll; e += blockDim.x) {
-      M[e] = Mg[e];
-      P[e] = Pg[e];
-    }
-  }
-  __syncthreads();
-  const int L = l + (l & 1);
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int nw = blockDim.x >> 6;
-  const double tol = (double)l * kUnitRoundoff;
-  int sweep = 0;
-  bool converged = (l < 2);
-  for (; sweep < max_sweeps && !converged; sweep++) {
-    if (threadIdx.x == 0) s_rot = 0;
-    __syncthreads();
-    int my_rot = 0;
-    for (int step = 0; step < L - 1; step++) {
-      for (int pi = wave; pi < L / 2; pi += nw) {
-        int a, b;
-        rr_pair(L, step, pi, a, b);
-        if (a >= l || b >= l) continue;
-        if (a > b) { const int t = a; a = b; b = t; }
-        double* ra = M + (int64_t)a * l;
-        double* rb = M + (int64_t)b * l;
-        double al = 0.0, be = 0.0, ga = 0.0;
-        for (int c = lane; c < l; c += 64) {
-          const double x = ra[c], y = rb[c];
-          al += x * x;
-          be += y * y;
-          ga += x * y;
-        }
-        al = wave_sum(al);
-        be = wave_sum(be);
-        ga = wave_sum(ga);
-        if (fabs(ga) > tol * sqrt(al) * sqrt(be) && ga != 0.0) {
-          const double zeta = (be - al) / (2.0 * ga);
-          const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = 1.0 / sqrt(1.0 + t * t);
-          const double sn = cs * t;
-          for (int c = lane; c < l; c += 64) {
-            const double x = ra[c], y = rb[c];
-            ra[c] = cs * x - sn * y;
-            rb[c] = sn * x + cs * y;
-          }
-          double* pa = P + (int64_t)a * l;
-          double* pb = P + (int64_t)b * l;
-          for (int c = lane; c < l; c += 64) {
-            const double x = pa[c], y = pb[c];
-            pa[c] = cs * x - sn * y;
-            pb[c] = sn * x + cs * y;
-          }
-          my_rot++;
-        }
-      }
-      __syncthreads();
-    }
-    if (lane == 0 && my_rot) atomicAdd(&s_rot, my_rot);
-    __syncthreads();
-    converged = (s_rot == 0);
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    st->sweeps = sweep;
-    if (!converged) atomicOr(&st->flags, (uint32_t)RSVD_FLAG_JACOBI_MAXSWEEP);
-  }
-  if (in_lds) {
-    __syncthreads();
-    for (int64_t e = threadIdx.x; e < ll; e += blockDim.x) {
-      Mg[e] = M[e];
-      Pg[e] = P[e];
-    }
-  }
 }
 
 __global__ void __launch_bounds__(256) identity_kernel(int64_t l, double* P) {
@@ -956,6 +893,9 @@ __global__ void init_state_kernel(DevState* st, uint32_t flags) {
     st->est2 = 0.0;
     st->s1lb2 = 0.0;
     st->froY2 = 0.0;
+    st->bar_count = 0u;
+    st->bar_gen = 0u;
+    st->bar_abort = 0u;
   }
   if (blockIdx.x == 0 && threadIdx.x < 64) st->rot_count[threadIdx.x] = 0;
 }
@@ -1027,6 +967,8 @@ __global__ void clear_shift_kernel(DevState* st) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     st->qr_shifted = 0;
     st->qr_householder = 0;
+    st->bar_count = 0u;
+    st->bar_abort = 0u;
   }
 }
 
@@ -1054,10 +996,6 @@ void allow_big_lds() {
   static bool done = false;
   if (done) return;
   done = true;
-  (void)hipFuncSetAttribute((const void*)chol_inv_kernel,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-  (void)hipFuncSetAttribute((const void*)jacobi_kernel,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
   (void)hipFuncSetAttribute((const void*)chol_tiles_kernel,
                             hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
 }
@@ -1069,20 +1007,46 @@ size_t chol_tiles_lds(int64_t l) {
   return (size_t)(16 * (16 * nb + 1) + 16 * 17) * sizeof(double);
 }
 
-rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, int64_t m, int pass,
-                     int only_if_shifted, DevState* st, hipStream_t s) {
+size_t chol_panel_doubles(int64_t l) { return (size_t)16 * (16 * ((l + 15) / 16) + 1); }
+
+rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, double* scratch, int64_t m,
+                     int pass, int only_if_shifted, DevState* st, hipStream_t s, int share) {
   allow_big_lds();
-  const size_t tl = chol_tiles_lds(l);
-  if (tl <= 150 * 1024) {
-    hipLaunchKernelGGL(chol_tiles_kernel, dim3(1), dim3(512), tl, s, (int)l, G, R, Rinv, m, pass,
-                       only_if_shifted, st);
+  if (l >= kCholGridMin && scratch) {
+    // one workgroup per ~32 tiles of the first trailing update, capped so the
+    // grids of concurrent runs fit on the device together
+    static int cap_all = 0;
+    if (cap_all == 0) {
+      int dev = 0, ncu = 0, per_cu = 0;
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)chol_grid_kernel, 512,
+                                                       0) != hipSuccess)
+        return RSVD_EHIP;
+      cap_all = ncu * (per_cu > 0 ? per_cu : 1);
+    }
+    const int64_t nb = (l + 15) / 16;
+    int grid = (int)((nb * (nb - 1) / 2 + 31) / 32);
+    // concurrent runs: half of a fair share, so that grids of different
+    // kernels (different per-CU footprints) also fit together
+    int cap = cap_all / (share > 1 ? 2 * share : 1);
+    if (cap > 128) cap = 128;
+    if (grid > cap) grid = cap;
+    if (grid < 1) grid = 1;
+    hipLaunchKernelGGL(chol_grid_kernel, dim3(grid), dim3(512), 0, s, (int)l, G, R, Rinv, scratch,
+                       m, pass, only_if_shifted, st);
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
   }
-  const size_t need = (size_t)l * l * 2 * sizeof(double);
-  const size_t shm = need <= 150 * 1024 ? need : 0;
-  hipLaunchKernelGGL(chol_inv_kernel, dim3(1), dim3(kBig), shm, s, (int)l, G, R, Rinv, m, pass,
-                     only_if_shifted, st);
+  size_t tl = chol_tiles_lds(l);
+  double* panel_g = nullptr;
+  if (tl > 150 * 1024) {
+    if (!scratch) return RSVD_EINVAL;
+    panel_g = scratch;
+    tl = 16 * 17 * sizeof(double);
+  }
+  hipLaunchKernelGGL(chol_tiles_kernel, dim3(1), dim3(512), tl, s, (int)l, G, R, Rinv, panel_g, m,
+                     pass, only_if_shifted, st);
   RSVD_LAUNCH_CHECK();
   return RSVD_OK;
 }
@@ -1100,16 +1064,6 @@ rsvd_status copy_panel(int64_t rows, int64_t cols, const double* src, int64_t ld
   if (rows * cols == 0) return RSVD_OK;
   hipLaunchKernelGGL(copy_panel_kernel, dim3(blocks_for(rows * cols, 256)), dim3(256), 0, s, rows,
                      cols, src, lds, dst, ldd, cond_shifted, (const DevState*)st);
-  RSVD_LAUNCH_CHECK();
-  return RSVD_OK;
-}
-
-rsvd_status jacobi_rows(int64_t l, double* M, double* P, int max_sweeps, DevState* st,
-                        hipStream_t s) {
-  allow_big_lds();
-  const size_t need = (size_t)l * l * 2 * sizeof(double);
-  const size_t shm = need <= 150 * 1024 ? need : 0;
-  hipLaunchKernelGGL(jacobi_kernel, dim3(1), dim3(kBig), shm, s, (int)l, M, P, max_sweeps, st);
   RSVD_LAUNCH_CHECK();
   return RSVD_OK;
 }

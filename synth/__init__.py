@@ -58,11 +58,18 @@ def effective(sigma):
     return sigma[:r]
 
 
-def haar_columns(n, r, rng):
-    """n x r matrix with Haar-distributed orthonormal columns."""
+def haar_columns(n, r, rng, device=None):
+    """n x r matrix with Haar-distributed orthonormal columns (a torch tensor on
+    `device` when one is given: the QR then runs there)."""
     G = rng.standard_normal((n, r))
-    Q, R = np.linalg.qr(G, mode="reduced")
-    d = np.sign(np.diag(R))
+    if device is None or device == "cpu":
+        Q, R = np.linalg.qr(G, mode="reduced")
+        d = np.sign(np.diag(R))
+        d[d == 0] = 1.0
+        return Q * d[None, :]
+    import torch
+    Q, R = torch.linalg.qr(torch.from_numpy(G).to(device), mode="reduced")
+    d = torch.sign(torch.diagonal(R))
     d[d == 0] = 1.0
     return Q * d[None, :]
 
@@ -112,6 +119,14 @@ def symmetric(n, sigma, tag, channel=0, noise=0.0, device=None):
     Ud = torch.from_numpy(U).to(device)
     A = (Ud * torch.from_numpy(sigma).to(device)[None, :]) @ Ud.T
     del Ud
+    out = _finish_symmetric_device(A, G, noise, device)
+    res = out.cpu().numpy()
+    del out
+    return res
+
+
+def _finish_symmetric_device(A, G, noise, device):
+    import torch
     if noise:
         Gd = torch.from_numpy(G).to(device)
         del G
@@ -119,9 +134,20 @@ def symmetric(n, sigma, tag, channel=0, noise=0.0, device=None):
         del Gd
     A = torch.triu(A)
     A += torch.triu(A, 1).T
-    out = A.cpu().numpy()
-    del A
-    return out
+    return A
+
+
+def symmetric_device(n, sigma, tag, channel=0, device="cuda"):
+    """As symmetric() without noise, built entirely on `device` (Haar basis by a
+    device QR); returns a contiguous torch tensor there."""
+    import torch
+    sigma = effective(np.asarray(sigma, np.float64)[:n])
+    r = len(sigma)
+    rng = _rng(tag, channel)
+    U = haar_columns(n, r, rng, device=device)
+    A = (U * torch.from_numpy(sigma).to(device)[None, :]) @ U.T
+    del U
+    return _finish_symmetric_device(A, None, 0.0, device).contiguous()
 
 
 def rank_r(m, n, r, tag, channel=0, scale=1.0):
@@ -175,7 +201,38 @@ def channel_dims(count, lo, hi, tag):
     return dims, d
 
 
-def channel(c, n, d, tag):
-    """Symmetric PSD channel matrix with sigma_i = exp(-i/d)."""
+def channel(c, n, d, tag, device=None):
+    """Symmetric PSD channel matrix with sigma_i = exp(-i/d) (numpy, or a torch
+    tensor built on `device`)."""
     sigma = spectrum_exp(n, d)
+    if device is not None and device != "cpu":
+        return symmetric_device(n, sigma, tag=tag, channel=c, device=device), sigma
     return symmetric(n, sigma, tag=tag, channel=c), sigma
+
+
+C4_TAU = 1e-6
+
+
+def c4_params(n, d, tau=C4_TAU, q=2):
+    """(k, p, q) of one c4 channel: k = the threshold rank of exp(-i/d) at tau
+    (1 + floor(d ln(1/tau))), p the smallest multiple of 16 with
+    (sigma_{k+p} / sigma_k)^(4q+2) = exp(-p (4q+2) / d) <= 1e-8, l capped at n."""
+    k = min(n, 1 + int(math.floor(d * math.log(1.0 / tau))))
+    p = 16 * int(math.ceil(d * math.log(1e8) / (4 * q + 2) / 16.0))
+    return k, p, q
+
+
+def c4(count=96, lo=500, hi=12000, device="cuda", tag=4):
+    """96 symmetric PSD channels, n_c ~ logU[500, 12000], d_c ~ U[10, 80],
+    sigma_i = exp(-i/d_c), no noise; rank by relative threshold 1e-6.
+    Returns (matrices on `device`, problem dicts for the batch planner)."""
+    dims, dec = channel_dims(count, lo, hi, tag=tag)
+    mats, probs = [], []
+    for c, (n, d) in enumerate(zip(dims, dec)):
+        n, d = int(n), float(d)
+        A, _ = channel(c, n, d, tag=tag, device=device)
+        k, p, q = c4_params(n, d)
+        mats.append(A)
+        probs.append(dict(m=n, n=n, k=k, p=p, q=q, symmetric=True, seed=2004, channel=c,
+                          rank_mode="rel_threshold", rank_param=C4_TAU, d=d))
+    return mats, probs
