@@ -208,7 +208,7 @@ __global__ void __launch_bounds__(256) bjacobi_kernel(JacArgs a) {
         if (rot && threadIdx.x == 0)
           __hip_atomic_fetch_add(&counters[sweep], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
-      if (!grid_barrier(&a.st->bar_count, &a.st->bar_gen, &a.st->bar_abort, &s_bar_ok)) {
+      if (!grid_barrier(&a.st->bar, &s_bar_ok)) {
         timed_out = true;
         break;
       }
@@ -238,11 +238,9 @@ __global__ void __launch_bounds__(256) jac_init_kernel(int l, int Lp, const doub
                                                        double* __restrict__ M, double* __restrict__ P,
                                                        DevState* st) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (blockIdx.x == 0 && threadIdx.x < 64) st->rot_count[threadIdx.x] = 0u;
-  if (idx == 0) {
-    st->bar_count = 0u;
-    st->bar_gen = 0u;
-    st->bar_abort = 0u;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x < 64) st->rot_count[threadIdx.x] = 0u;
+    grid_barrier_reset(&st->bar);
   }
   if (idx >= (int64_t)Lp * Lp) return;
   const int i = (int)(idx / Lp), c = (int)(idx % Lp);

@@ -61,48 +61,84 @@ __device__ __forceinline__ double wave_max(double v) {
 }
 
 // Polls of the barrier generation before a workgroup gives up (each poll is
-// an agent-scope load after a short sleep: about two seconds in all).
-constexpr uint32_t kSpinLimit = 1u << 20;
+// an agent-scope load after a short sleep: a few seconds in all).
+constexpr uint32_t kSpinLimit = 1u << 21;
+
+// Words of the grid barrier (in the run's workspace, zeroed before use).
+// Arrivals are counted in two levels: workgroup b arrives at group counter
+// b % 8 (each on its own 128-byte line), the last of a group at the top
+// counter, the last group advances the generation. A flat counter costs
+// ~0.13 us per workgroup of serialized atomics at the coherence point.
+struct GridBar {
+  uint32_t lo[8][32];
+  uint32_t hi[32];
+  uint32_t gen[32];
+  uint32_t abort[32];
+};
 
 // Barrier over the gridDim.x workgroups of a launch whose whole grid fits on
-// the device at once. The last workgroup to arrive resets the counter and
-// advances the generation; the others wait for the generation to change.
-// Every thread fences at agent scope on both sides, so the data written
-// before the barrier by any workgroup (on any XCD) is visible after it.
-// A workgroup that has waited kSpinLimit polls raises *abort and leaves;
-// waiters see *abort and leave too. Returns false once the barrier has
+// the device at once. The waiters poll the generation with relaxed loads (no
+// cache invalidation while they wait) and acquire once it moves.
+// Memory ordering: every wave waits until its own stores are acknowledged
+// (so they sit in its XCD's L2) before the workgroup barrier; thread 0 then
+// arrives with agent-scope acq_rel increments (an L2 write-back per arrival
+// chain), the generation is advanced with release and read back with an
+// acquire fence, and after the second workgroup barrier every wave acquires
+// at agent scope (its L1 / L2 lines are refetched).
+// A workgroup that has waited kSpinLimit polls raises the abort word and
+// leaves; waiters see it and leave too. Returns false once the barrier has
 // been abandoned: the kernel must then return.
-__device__ inline bool grid_barrier(uint32_t* count, uint32_t* gen, uint32_t* abort, int* s_ok) {
-  __threadfence();
+__device__ inline bool grid_barrier(GridBar* gb, int* s_ok) {
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
     int ok = 1;
-    const uint32_t g = __hip_atomic_load(gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t arrived =
-        __hip_atomic_fetch_add(count, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-    if (arrived == gridDim.x) {
-      __hip_atomic_store(count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_fetch_add(gen, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
+    const uint32_t g = __hip_atomic_load(&gb->gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t grp = blockIdx.x & 7u;
+    const uint32_t gsize = (gridDim.x - grp + 7u) >> 3;
+    const uint32_t ngroups = gridDim.x < 8u ? gridDim.x : 8u;
+    bool last = false;
+    const uint32_t a =
+        __hip_atomic_fetch_add(&gb->lo[grp][0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    if (a == gsize) {
+      __hip_atomic_store(&gb->lo[grp][0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t h =
+          __hip_atomic_fetch_add(&gb->hi[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+      if (h == ngroups) {
+        __hip_atomic_store(&gb->hi[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_fetch_add(&gb->gen[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        last = true;
+      }
+    }
+    if (!last) {
       uint32_t spins = 0;
-      while (__hip_atomic_load(gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-        if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+      while (__hip_atomic_load(&gb->gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (__hip_atomic_load(&gb->abort[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
           ok = 0;
           break;
         }
         if (++spins > kSpinLimit) {
-          __hip_atomic_store(abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&gb->abort[0], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
           ok = 0;
           break;
         }
-        __builtin_amdgcn_s_sleep(8);
+        __builtin_amdgcn_s_sleep(4);
       }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     }
     *s_ok = ok;
   }
   __syncthreads();
-  __threadfence();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return *s_ok != 0;
+}
+
+// Zero the barrier words (one workgroup, any size; run before the launch
+// that uses the barrier, in stream order).
+__device__ inline void grid_barrier_reset(GridBar* gb) {
+  uint32_t* w = &gb->lo[0][0];
+  constexpr int kWords = (int)(sizeof(GridBar) / sizeof(uint32_t));
+  for (int i = threadIdx.x; i < kWords; i += blockDim.x) w[i] = 0u;
 }
 
 // Device-side scalar state of one decomposition, kept in the workspace.
@@ -121,11 +157,10 @@ struct DevState {
   double s1lb2;          // largest squared row norm of Q^T A so far (<= sigma_1^2)
   double froY2;          // ||Q^T A||_F^2 so far
   uint32_t rot_count[64];  // rotations per Jacobi sweep (convergence test)
-  uint32_t bar_count;    // grid barrier of the multi-workgroup kernels
-  uint32_t bar_gen;      //   (Jacobi, Cholesky): arrivals, generation
-  uint32_t bar_abort;    //   and the abandon word
   uint32_t chol_fail;    // multi-workgroup Cholesky: a pivot broke down
+  uint32_t prefer_shift; // the last Cholesky QR of this run needed the shift
   double piv_max, piv_min;  // and the range of its pivots
+  GridBar bar;           // grid barrier of the multi-workgroup kernels
 };
 
 }  // namespace rsvd

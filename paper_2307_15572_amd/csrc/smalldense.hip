@@ -360,7 +360,7 @@ struct GridTeam {
   __device__ int id() const { return blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); }
   __device__ int size() const { return gridDim.x * (blockDim.x >> 6); }
   __device__ bool sync() const {
-    if (grid_barrier(&st->bar_count, &st->bar_gen, &st->bar_abort, s_ok)) return true;
+    if (grid_barrier(&st->bar, s_ok)) return true;
     if (threadIdx.x == 0)
       __hip_atomic_fetch_or(&st->flags, (uint32_t)RSVD_FLAG_SYNC_TIMEOUT, __ATOMIC_RELAXED,
                             __HIP_MEMORY_SCOPE_AGENT);
@@ -452,7 +452,10 @@ __global__ void __launch_bounds__(512) chol_tiles_kernel(int l, double* __restri
   const double shift = 11.0 * ((double)m * l + (double)l * (l + 1)) * kUnitRoundoff * tr;
   const double clampv = fmax(shift, 1e-300);
 
-  bool use_shift = false, clamp = false;
+  // a panel of the same run already needed the shift: start shifted (the
+  // unshifted attempt would only fail the pivot-spread test again)
+  bool use_shift = pass == 0 && st->prefer_shift != 0u, clamp = false;
+  if (use_shift && threadIdx.x == 0) st->qr_shifted = 1;
   for (int attempt = 0; attempt < 3; attempt++) {
     for (int64_t e = threadIdx.x; e < ll; e += blockDim.x) {
       double v = G[e];
@@ -475,6 +478,7 @@ __global__ void __launch_bounds__(512) chol_tiles_kernel(int l, double* __restri
     }
     __syncthreads();
   }
+  if (pass == 0 && threadIdx.x == 0) st->prefer_shift = use_shift ? 1u : 0u;
   // G is no longer read: it serves as scratch for the inverse
   tiled_inverse(BlockTeam{}, cx, R, Rinv, G);
   // strictly lower parts are zero
@@ -547,7 +551,9 @@ __global__ void __launch_bounds__(512) chol_grid_kernel(int l, double* __restric
   const double shift = 11.0 * ((double)m * l + (double)l * (l + 1)) * kUnitRoundoff * tr;
   const double clampv = fmax(shift, 1e-300);
 
-  bool use_shift = false, clamp = false;
+  // a panel of the same run already needed the shift: start shifted
+  bool use_shift = pass == 0 && st->prefer_shift != 0u, clamp = false;
+  if (use_shift && gw == 0 && lane == 0) st->qr_shifted = 1;
   for (int attempt = 0; attempt < 3; attempt++) {
     if (gw == 0 && lane == 0) {
       st->chol_fail = 0u;
@@ -640,6 +646,7 @@ __global__ void __launch_bounds__(512) chol_grid_kernel(int l, double* __restric
     // every workgroup has read this attempt's outcome before the next resets it
     if (!tm.sync()) return;
   }
+  if (pass == 0 && gw == 0 && lane == 0) st->prefer_shift = use_shift ? 1u : 0u;
   // G is no longer read: it serves as scratch for the inverse
   if (!tiled_inverse(tm, cx, R, Rinv, G)) return;
   for (int64_t e = gtid; e < ll; e += gthreads) {
@@ -893,11 +900,12 @@ __global__ void init_state_kernel(DevState* st, uint32_t flags) {
     st->est2 = 0.0;
     st->s1lb2 = 0.0;
     st->froY2 = 0.0;
-    st->bar_count = 0u;
-    st->bar_gen = 0u;
-    st->bar_abort = 0u;
+    st->prefer_shift = 0u;
   }
-  if (blockIdx.x == 0 && threadIdx.x < 64) st->rot_count[threadIdx.x] = 0;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x < 64) st->rot_count[threadIdx.x] = 0;
+    grid_barrier_reset(&st->bar);
+  }
 }
 
 __global__ void clear_flags_kernel(DevState* st, uint32_t clear, uint32_t set) {
@@ -964,12 +972,12 @@ __global__ void __launch_bounds__(256) colsumsq_finish_kernel(int nblk, int cols
 }
 
 __global__ void clear_shift_kernel(DevState* st) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
+  if (blockIdx.x != 0) return;
+  if (threadIdx.x == 0) {
     st->qr_shifted = 0;
     st->qr_householder = 0;
-    st->bar_count = 0u;
-    st->bar_abort = 0u;
   }
+  grid_barrier_reset(&st->bar);
 }
 
 __global__ void __launch_bounds__(256) transpose_kernel(int64_t rows, int64_t cols,
