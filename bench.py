@@ -15,7 +15,13 @@ dominant kernel (the streaming FP64 GEMM, MFMA-bound: intensity l/4 flop per
 byte is far above the FP64 ridge of ~9.8 flop/byte); its average duration comes
 from HIP events recorded around each streaming pass on the run's stream.
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--n 16384]
+Also reported (same JSON line): the mixed-precision schedules on the same
+matrix ("mixed": FP32 and BF16 early products, speed-up over FP64 and the
+singular-value error against the FP64 run) and a 96-channel threshold batch
+("batch": the batch planner's concurrent lanes with graph replay against the
+same channels run one after another).
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--n 16384] [--no-batch]
 """
 
 import argparse
@@ -66,6 +72,68 @@ def cpu_baseline(A_np, w, k, p, q, gpu_s=None):
     return out, ref
 
 
+def batch_leg(dev, reps=2):
+    """96 symmetric channels (n_c ~ logU[500, 12000], sigma_i = exp(-i/d_c),
+    d_c ~ U[10, 80]) decomposed together by the batch planner, rank by the
+    relative threshold 1e-6; (k, p, q) per channel from the threshold rank of
+    its spectrum (q = 2). Matrix GB/s over all channels' 2q + 2 streams."""
+    import numpy as np
+    import torch
+    import paper_2307_15572_amd as rs
+    import synth
+
+    t0 = time.perf_counter()
+    mats, probs = synth.c4(device=dev)
+    torch.cuda.synchronize()
+    log(f"batch workload: {len(mats)} channels in {time.perf_counter() - t0:.1f} s")
+    stream = torch.cuda.current_stream(dev)
+    bytes_streamed = sum(8.0 * p["m"] * p["n"] * (2 * p["q"] + 2) for p in probs)
+    legs = {}
+    for name, prec, lanes, graph in (("mixed_fp32_8lanes_graph", "mixed_fp32", 8, True),
+                                      ("fp64_8lanes_graph", "fp64", 8, True),
+                                      ("mixed_fp32_sequential", "mixed_fp32", 1, False)):
+        pp = []
+        for pr in probs:
+            d = dict(pr)
+            d.pop("d")
+            d.update(precision=prec, want_residual=False)
+            pp.append(d)
+        bp = rs.BatchPlan(pp, lanes=lanes, use_graph=graph)
+        bufs = bp.allocate(dev)
+        bp.run_into(mats, bufs)
+        bp.results(bufs)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            bp.run_into(mats, bufs)
+        e1.record(stream)
+        res = bp.results(bufs)
+        ms = e0.elapsed_time(e1) / reps
+        bad, worst = 0, 0.0
+        for c, (pr, r) in enumerate(zip(probs, res)):
+            sig = synth.spectrum_exp(pr["m"], pr["d"])
+            want = min(int(np.count_nonzero(sig >= synth.C4_TAU)), bp.l[c] - pr["p"])
+            bad += int(r.rank != want)
+            s = bufs["S"][c][: r.rank].cpu().numpy()
+            worst = max(worst, float(np.max(np.abs(s - sig[: r.rank]) / sig[: r.rank])))
+        legs[name] = {"ms": round(ms, 2), "value": round(bytes_streamed / (ms * 1e-3) / 1e9, 3),
+                      "unit": "GB/s", "graph_replayed": bp.graph_used(),
+                      "ranks_off_threshold_count": bad,
+                      "max_rel_sigma_err_vs_constructed": worst}
+        log(f"batch {name}: {ms:.1f} ms, {legs[name]['value']} GB/s")
+        del bufs, bp
+        torch.cuda.empty_cache()
+    seq = legs["mixed_fp32_sequential"]["ms"]
+    legs["mixed_fp32_8lanes_graph"]["speedup_vs_sequential"] = round(
+        seq / legs["mixed_fp32_8lanes_graph"]["ms"], 3)
+    del mats
+    torch.cuda.empty_cache()
+    return {"workload": "c4_96_channels_threshold_1e-6", "channels": len(probs),
+            "sum_n2": int(sum(p["m"] * p["n"] for p in probs)),
+            "streams_per_channel": "2q + 2 (q = 2)", "legs": legs}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -74,6 +142,8 @@ def main():
     ap.add_argument("--n", type=int, default=16384)
     ap.add_argument("--no-cpu-baseline", action="store_true",
                     help="skip the oracle timing (used for profiler runs)")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 96-channel batch leg")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -197,6 +267,10 @@ def main():
         del mb, mplan
         log(f"{prec}: {mms:.3f} ms/step, max rel sigma err vs FP64 {rel:.2e}")
     out["mixed"] = mixed
+
+    if not args.no_batch:
+        torch.cuda.empty_cache()
+        out["batch"] = batch_leg(dev)
 
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")

@@ -40,3 +40,4 @@ from .method import (  # noqa: F401
     sign_normalize,
 )
 from .adaptive import rsvd_adaptive, FLAG_ADAPT_LIMIT, POSTERIOR_FACTOR  # noqa: F401
+from . import mlp  # noqa: F401

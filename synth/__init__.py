@@ -236,3 +236,35 @@ def c4(count=96, lo=500, hi=12000, device="cuda", tag=4):
         probs.append(dict(m=n, n=n, k=k, p=p, q=q, symmetric=True, seed=2004, channel=c,
                           rank_mode="rel_threshold", rank_param=C4_TAU, d=d))
     return mats, probs
+
+
+# ---- learned (k, p, q) predictor: channels and labels ------------------------
+C5_P_GRID = (8, 16, 32, 64, 128, 192)
+C5_Q_GRID = (0, 1, 2, 3, 4)
+C5_CONVERGED = 1e-8
+
+
+def c5_dims(count=2000, lo=200, hi=6000, tag=5):
+    """Channel sizes n_c ~ logU[200, 6000] and decay lengths d_c ~ U[10, 80]
+    of the 2000-channel training / evaluation set (first 1500 train)."""
+    return channel_dims(count, lo, hi, tag=tag)
+
+
+def kpq_label(n, d, tau=C4_TAU):
+    """Training label of a channel with sigma_i = exp(-i/d) (generator metadata):
+    k* = its threshold rank at tau (capped at n); (p*, q*) = the cheapest
+    (cost (2q + 2)(k* + p)) grid point whose kept values are converged,
+    (sigma_{k+p} / sigma_k)^(4q+2) = exp(-p (4q + 2) / d) <= 1e-8, or whose
+    l = k + p reaches n (then the method is an exact SVD)."""
+    k = min(n, 1 + int(math.floor(d * math.log(1.0 / tau))))
+    best = None
+    for q in C5_Q_GRID:
+        for p in C5_P_GRID:
+            if k + p < n and math.exp(-p * (4 * q + 2) / d) > C5_CONVERGED:
+                continue
+            cost = (2 * q + 2) * min(k + p, n)
+            if best is None or cost < best[0]:
+                best = (cost, p, q)
+    if best is None:  # nothing on the grid converges: the largest p, q
+        best = (0, C5_P_GRID[-1], C5_Q_GRID[-1])
+    return k, best[1], best[2]

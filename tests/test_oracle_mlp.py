@@ -1,0 +1,102 @@
+"""Pins of the MLP oracle (oracle/mlp.py): finite-difference gradients, the
+closed form of an Adam step, He-init moments, properties of the pilot
+features on matrices with known spectra, and learning a known relation."""
+
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import mlp
+
+
+def test_parameter_count():
+    # 16*64+64 + 64*64+64 + 64*3+3
+    assert mlp.N_PARAMS == 5443
+
+
+def _data(B, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.uniform(-4.0, 0.0, size=(B, mlp.N_IN))
+    T = rng.standard_normal((B, mlp.N_OUT))
+    return X, T
+
+
+def test_gradient_matches_central_differences():
+    theta = mlp.he_init(7)
+    X, T = _data(40, 1)
+    L, g = mlp.grad(theta, X, T)
+    assert L == pytest.approx(mlp.loss(theta, X, T), rel=1e-15)
+    rng = np.random.default_rng(2)
+    idx = rng.choice(mlp.N_PARAMS, size=300, replace=False)
+    # fourth-order central differences: truncation ~h^4, rounding ~u/h
+    h = 1e-4
+    worst = 0.0
+    for i in idx:
+        e = np.zeros_like(theta)
+        e[i] = h
+        f = lambda s: mlp.loss(theta + s * e, X, T)  # noqa: E731
+        fd = (-f(2) + 8 * f(1) - 8 * f(-1) + f(-2)) / (12 * h)
+        worst = max(worst, abs(fd - g[i]) / max(abs(g[i]), 1e-3 * np.abs(g).max()))
+    assert worst <= 1e-7
+
+
+def test_adam_first_steps_closed_form():
+    theta = np.array([1.0, -2.0, 0.5])
+    g = np.array([0.3, -0.01, 0.0])
+    m = np.zeros(3)
+    v = np.zeros(3)
+    th1, m1, v1 = mlp.adam_step(theta, m, v, g, 1, lr=0.1)
+    # t = 1: mhat = g, vhat = g^2, so the step is lr g / (|g| + eps)
+    assert np.allclose(th1, theta - 0.1 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    assert np.allclose(m1, 0.1 * g) and np.allclose(v1, 0.001 * g * g)
+    # t = 2 with the same gradient: still mhat = g, vhat = g^2
+    th2, _, _ = mlp.adam_step(th1, m1, v1, g, 2, lr=0.1)
+    assert np.allclose(th2, th1 - 0.1 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=1e-15)
+
+
+def test_he_init_moments_and_determinism():
+    theta = mlp.he_init(11)
+    p = mlp.unpack(theta)
+    for name, fan_in in (("W1", 16), ("W2", 64), ("W3", 64)):
+        w = p[name]
+        assert abs(w.mean()) < 4 * math.sqrt(2.0 / fan_in) / math.sqrt(w.size)
+        assert w.var() == pytest.approx(2.0 / fan_in, rel=0.35 if w.size < 500 else 0.1)
+    assert np.all(p["b1"] == 0) and np.all(p["b2"] == 0) and np.all(p["b3"] == 0)
+    assert np.array_equal(theta, mlp.he_init(11))
+    assert not np.array_equal(theta, mlp.he_init(12))
+
+
+def test_pilot_features_properties():
+    n = 300
+    sigma = 10.0 ** (-np.arange(n) / 4.0)
+    A = synth.general(350, n, sigma, tag=700)
+    f = mlp.pilot_features(A, seed=3)
+    assert f[0] == 0.0
+    assert np.all(np.diff(f) <= 0)
+    # power-of-two scaling leaves every rounded operand's ratios unchanged
+    assert np.array_equal(f, mlp.pilot_features(8.0 * A, seed=3))
+    # the sketch tracks the spectrum's slope (-1/4 decade per index) within
+    # Gaussian factors: a wrong log base or squared values would fail this
+    slope = np.polyfit(np.arange(12), f[:12], 1)[0]
+    assert -0.3 < slope < -0.2
+    assert np.all(np.abs(f[:12] - np.log10(sigma[:12])) <= 1.5)
+
+
+def test_pilot_features_floor_on_rank_one():
+    A, _ = synth.rank_r(200, 150, 1, tag=701)
+    f = mlp.pilot_features(A, seed=4)
+    # beyond rank 1 only FP32 rounding remains (~1e-7 relative)
+    assert f[0] == 0.0 and np.all(f[1:] <= -6.0) and np.all(f >= mlp.FEATURE_FLOOR)
+
+
+def test_training_learns_a_linear_relation():
+    rng = np.random.default_rng(5)
+    X = rng.uniform(-3.0, 0.0, size=(512, mlp.N_IN))
+    Wt = rng.standard_normal((mlp.N_OUT, mlp.N_IN)) / 4
+    T = X @ Wt.T
+    theta = mlp.he_init(9)
+    L0 = mlp.loss(theta, X, T)
+    theta, hist = mlp.train(theta, X, T, epochs=60, batch=128, lr=3e-3)
+    assert mlp.loss(theta, X, T) < 0.02 * L0
