@@ -113,7 +113,8 @@ def batch_leg(dev, reps=2):
         bad, worst = 0, 0.0
         for c, (pr, r) in enumerate(zip(probs, res)):
             sig = synth.spectrum_exp(pr["m"], pr["d"])
-            want = min(int(np.count_nonzero(sig >= synth.C4_TAU)), bp.l[c] - pr["p"])
+            count = int(np.count_nonzero(sig >= synth.C4_TAU))
+            want = count if bp.l[c] == pr["m"] else min(count, bp.l[c] - pr["p"])
             bad += int(r.rank != want)
             s = bufs["S"][c][: r.rank].cpu().numpy()
             worst = max(worst, float(np.max(np.abs(s - sig[: r.rank]) / sig[: r.rank])))

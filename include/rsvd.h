@@ -48,7 +48,8 @@ typedef enum rsvd_status {
 enum {
   RSVD_RANK_FIXED = 0,         /* R_SVD = k                                        */
   RSVD_RANK_PERCENT = 1,       /* R_SVD = ceil(R% min(m,n) / 100), rank_param = R% */
-  RSVD_RANK_REL_THRESHOLD = 2, /* R_SVD = #{j : s_j >= tau s_1}, capped at l - p   */
+  RSVD_RANK_REL_THRESHOLD = 2, /* R_SVD = #{j : s_j >= tau s_1}, capped at l - p
+                                  unless l = min(m, n) (exact SVD)                 */
   RSVD_RANK_FROB_TAIL = 3      /* smallest R_SVD with discarded energy <= tau ||A||_F */
 };
 
@@ -242,6 +243,58 @@ rsvd_status rsvd_batch_info(rsvd_batch_t plan, int32_t* lane_of, int32_t* graph_
 /* Free a batch plan with its streams, events and graph (NULL is ignored).
  * Synchronizes the lanes first. */
 void rsvd_batch_destroy(rsvd_batch_t plan);
+
+/*
+ * Learned (k, p, q) predictor. The paper fixes R_SVD and the oversampling by
+ * hand; here a small MLP maps 16 features of a cheap pilot sketch of a
+ * channel to (log10 k, p, q) in standardized units, so the decomposition can
+ * be sized without adaptive growth (the caller checks the result and falls
+ * back to the adaptive range finder where it fails).
+ *
+ * Features (rsvd_pilot_features): Y0 = A P0 with P0 the first 32 columns of
+ * the Philox / Box-Muller projection keyed by (seed, channel), computed on
+ * FP32 matrix cores (operands rounded to FP32, FP32 accumulation); s_i the
+ * singular values of Y0 (FP64 QR + Jacobi); f_i = max(log10(s_i / s_1), -16)
+ * for i = 1..16 (-16 beyond min(32, m, n) values).
+ *
+ * Model: h1 = relu(W1 f + b1), h2 = relu(W2 h1 + b2), y = W3 h2 + b3 with
+ * W1 64 x 16, W2 64 x 64, W3 3 x 64; parameters are one flat FP32 device
+ * array of RSVD_MLP_PARAMS values in the order W1 (row-major), b1, W2, b2,
+ * W3, b3, owned by the caller (save / load it as plain floats). Training
+ * minimizes the mean of (y - t)^2 over the batch and the 3 outputs with Adam
+ * (Kingma and Ba 2015; beta1 0.9, beta2 0.999, eps 1e-8).
+ * All arrays are device FP32, row-major: X is B x 16, T and Y are B x 3.
+ */
+#define RSVD_MLP_PARAMS 5443
+#define RSVD_MLP_IN 16
+#define RSVD_MLP_OUT 3
+#define RSVD_MLP_MAX_BATCH 128
+#define RSVD_PILOT_COLS 32
+
+/* He-normal initialization: W ~ N(0, 2 / fan_in) with entry (i, j) of layer
+ * L (0, 1, 2) the Philox / Box-Muller draw at counter (i, j / 4, 0, 0), key
+ * (seed, L); biases 0. */
+rsvd_status rsvd_mlp_init(float* params, uint64_t seed, void* stream);
+/* Y = MLP(X) for B >= 0 samples. */
+rsvd_status rsvd_mlp_forward(const float* params, const float* X, int64_t B, float* Y,
+                             void* stream);
+/* Loss (device float, may be NULL) and its gradient (RSVD_MLP_PARAMS device
+ * floats, same layout as params) for one batch, 1 <= B <= 128. */
+rsvd_status rsvd_mlp_grad(const float* params, const float* X, const float* T, int64_t B,
+                          float* grad, float* loss, void* stream);
+/* One Adam step (step >= 1 counts the steps taken, for the bias corrections)
+ * on one batch, 1 <= B <= 128: params, adam_m and adam_v (RSVD_MLP_PARAMS
+ * device floats each, zero before the first step) are updated in place; loss
+ * (device float, may be NULL) receives the batch loss before the step. */
+rsvd_status rsvd_mlp_train_step(float* params, float* adam_m, float* adam_v, int64_t step,
+                                const float* X, const float* T, int64_t B, float lr,
+                                float* loss, void* stream);
+/* Pilot features of A (m x n, lda, device): feat = 16 device floats. work:
+ * device workspace of rsvd_pilot_work_bytes(m, n) bytes, 256-B aligned. */
+size_t rsvd_pilot_work_bytes(int64_t m, int64_t n);
+rsvd_status rsvd_pilot_features(const double* A, int64_t lda, int64_t m, int64_t n, uint64_t seed,
+                                uint64_t channel, float* feat, void* work, size_t work_bytes,
+                                void* stream);
 
 /*
  * Component entry points (each one step of the path, for testing and reuse).

@@ -161,7 +161,7 @@ def rsvd_adaptive(A, tau, p, q, block=64, seed=0, channel=0, symmetric=False, l_
     L = Q @ L_Y
     R = Rt.T
     L, R = sign_normalize(L, R)
-    rank, f2 = select_rank(s_all, rank_mode, tau, l, p, k_cap, fro2_A=fro2)
+    rank, f2 = select_rank(s_all, rank_mode, tau, l, 0 if l == mn else p, k_cap, fro2_A=fro2)
     flags |= f2
     U_k, s_k, V_k = L[:, :rank], s_all[:rank], R[:, :rank]
     e = residual(A, U_k, s_k, V_k) if want_residual else float("nan")

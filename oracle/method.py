@@ -22,7 +22,8 @@ Readings where the paper is silent (all listed in the design notes):
   * Signs: each pair (L_j, R_j) is flipped so that the entry of largest
     magnitude of L_j is positive (the lowest index wins ties).
   * Rank rules: fixed R_SVD; percent (R_SVD = ceil(R% * min(m, n) / 100));
-    relative threshold (R_SVD = #{j : s_j >= tau * s_1}, at most l - p);
+    relative threshold (R_SVD = #{j : s_j >= tau * s_1}, at most l - p
+    unless l = min(m, n), where every value is exact);
     Frobenius tail (smallest R_SVD whose discarded energy, including what
     the sketch missed, is at most tau * ||V||_F).
   * Eq. 2 is reported as printed, C = m n / ((m + n) R_SVD + R_SVD), which is
@@ -203,7 +204,9 @@ def rsvd(A, k, p, q, seed=0, channel=0, symmetric=False, omega=None,
     L, R = sign_normalize(L, R)
 
     fro2 = float(np.sum(A * A))
-    rank, f2 = select_rank(s_all, rank_mode, rank_param, l, p, k_cap, fro2_A=fro2)
+    # the l - p cap protects unconverged trailing values; an exact SVD has none
+    p_cap = 0 if l == min(m, n) else p
+    rank, f2 = select_rank(s_all, rank_mode, rank_param, l, p_cap, k_cap, fro2_A=fro2)
     flags |= f2
     U_k, s_k, V_k = L[:, :rank], s_all[:rank], R[:, :rank]
     e = residual(A, U_k, s_k, V_k) if want_residual else float("nan")

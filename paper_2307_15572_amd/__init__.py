@@ -32,7 +32,10 @@ EXPORTED = (
     "rsvd_orth_work_bytes", "rsvd_orth", "rsvd_small_svd_work_bytes", "rsvd_small_svd",
     "rsvd_trace_enable", "rsvd_trace_collect",
     "rsvd_batch_plan", "rsvd_batch_run", "rsvd_batch_info", "rsvd_batch_destroy",
+    "rsvd_mlp_init", "rsvd_mlp_forward", "rsvd_mlp_grad", "rsvd_mlp_train_step",
+    "rsvd_pilot_work_bytes", "rsvd_pilot_features",
 )
+MLP_PARAMS, MLP_IN, MLP_OUT, MLP_MAX_BATCH, PILOT_COLS = 5443, 16, 3, 128, 32
 TRACE_PHASES = ("stream_gemm", "qr", "small_svd", "lift_signs", "residual", "omega", "other")
 
 
@@ -118,6 +121,19 @@ def lib():
     L.rsvd_batch_info.restype = ctypes.c_int
     L.rsvd_batch_destroy.argtypes = [vp]
     L.rsvd_batch_destroy.restype = None
+    fp = ctypes.c_void_p
+    L.rsvd_mlp_init.argtypes = [fp, u64, vp]
+    L.rsvd_mlp_init.restype = ctypes.c_int
+    L.rsvd_mlp_forward.argtypes = [fp, fp, i64, fp, vp]
+    L.rsvd_mlp_forward.restype = ctypes.c_int
+    L.rsvd_mlp_grad.argtypes = [fp, fp, fp, i64, fp, fp, vp]
+    L.rsvd_mlp_grad.restype = ctypes.c_int
+    L.rsvd_mlp_train_step.argtypes = [fp, fp, fp, i64, fp, fp, i64, ctypes.c_float, fp, vp]
+    L.rsvd_mlp_train_step.restype = ctypes.c_int
+    L.rsvd_pilot_work_bytes.argtypes = [i64, i64]
+    L.rsvd_pilot_work_bytes.restype = sz
+    L.rsvd_pilot_features.argtypes = [vp, i64, i64, i64, u64, u64, fp, vp, sz, vp]
+    L.rsvd_pilot_features.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -173,6 +189,7 @@ class RsvdOutput:
     flags: int
     err_est: float = float("nan")   # adaptive: last error estimate of the basis
     blocks: int = 0                 # adaptive: growth steps
+    S_all: object = None            # every computed value (min(k_cap, l) of them)
 
 
 def make_problem(m, n, k, p, q, *, symmetric=False, rank_mode="fixed", rank_param=None,
@@ -379,7 +396,7 @@ def run(A, k, p, q, *, omega=None, **kw):
         V=bufs["V"][:, :rank] if bufs["V"] is not None else None, rank=rank, l=int(r.l_used),
         residual=r.residual, rel_percent=r.rel_percent, c_eq2=r.c_eq2, c_sym=r.c_sym,
         fro2=r.fro2, sweeps=int(r.sweeps), flags=int(r.flags), err_est=r.err_est,
-        blocks=int(r.blocks),
+        blocks=int(r.blocks), S_all=bufs["S"][: min(plan.kc, int(r.l_used))],
     )
 
 
@@ -454,6 +471,75 @@ def small_svd(R, max_sweeps=0):
     torch.cuda.synchronize(R.device)
     del buf
     return s, Us, W, int(sw.item()), int(fl.item()) & 0xFFFFFFFF
+
+
+def pilot_features(A, seed, channel=0, work=None):
+    """16 FP32 features of the pilot sketch of A (see include/rsvd.h)."""
+    torch = _torch()
+    _check_matrix(torch, A, "A")
+    m, n = A.shape
+    feat = torch.empty(MLP_IN, dtype=torch.float32, device=A.device)
+    L = lib()
+    wb = L.rsvd_pilot_work_bytes(m, n)
+    if work is None or work[2] < wb:
+        work = _workspace(torch, wb, A.device)
+    _check(L.rsvd_pilot_features(_ptr(A), A.stride(0), m, n, seed & (2**64 - 1),
+                                 channel & (2**64 - 1), _ptr(feat), work[1], work[2],
+                                 _stream(torch, A.device)), "rsvd_pilot_features")
+    return feat, work
+
+
+class Mlp:
+    """The 16-64-64-3 predictor: flat FP32 parameters and Adam moments on the
+    device; every computation runs in the library's kernels."""
+
+    def __init__(self, seed=0, device="cuda"):
+        torch = _torch()
+        self.device = torch.device(device)
+        self.params = torch.empty(MLP_PARAMS, dtype=torch.float32, device=self.device)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+        self._loss = torch.zeros(1, dtype=torch.float32, device=self.device)
+        _check(lib().rsvd_mlp_init(_ptr(self.params), seed & (2**64 - 1),
+                                   _stream(torch, self.device)), "rsvd_mlp_init")
+
+    @staticmethod
+    def _f32(torch, X, cols, name):
+        if not (X.is_cuda and X.dtype == torch.float32 and X.dim() == 2 and X.shape[1] == cols
+                and X.is_contiguous()):
+            raise RsvdError(f"{name} must be a contiguous float32 CUDA tensor with {cols} columns")
+
+    def forward(self, X):
+        torch = _torch()
+        self._f32(torch, X, MLP_IN, "X")
+        Y = torch.empty(X.shape[0], MLP_OUT, dtype=torch.float32, device=X.device)
+        _check(lib().rsvd_mlp_forward(_ptr(self.params), _ptr(X), X.shape[0], _ptr(Y),
+                                      _stream(torch, X.device)), "rsvd_mlp_forward")
+        return Y
+
+    def grad(self, X, T):
+        """(loss, gradient) of one batch (B <= 128) without updating."""
+        torch = _torch()
+        self._f32(torch, X, MLP_IN, "X")
+        self._f32(torch, T, MLP_OUT, "T")
+        g = torch.empty_like(self.params)
+        _check(lib().rsvd_mlp_grad(_ptr(self.params), _ptr(X), _ptr(T), X.shape[0], _ptr(g),
+                                   _ptr(self._loss), _stream(torch, X.device)), "rsvd_mlp_grad")
+        return float(self._loss.item()), g
+
+    def train_step(self, X, T, lr=1e-3):
+        """One Adam step on a batch (B <= 128); returns a device scalar with the
+        batch loss before the step (read it without forcing a sync each step)."""
+        torch = _torch()
+        self._f32(torch, X, MLP_IN, "X")
+        self._f32(torch, T, MLP_OUT, "T")
+        self.step += 1
+        loss = torch.empty(1, dtype=torch.float32, device=X.device)
+        _check(lib().rsvd_mlp_train_step(_ptr(self.params), _ptr(self.m), _ptr(self.v), self.step,
+                                         _ptr(X), _ptr(T), X.shape[0], float(lr), _ptr(loss),
+                                         _stream(torch, X.device)), "rsvd_mlp_train_step")
+        return loss
 
 
 def trace_enable(on=True):

@@ -90,4 +90,14 @@ rsvd_status set_identity(int64_t l, double* P, hipStream_t s);
 rsvd_status transpose(int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst,
                       int64_t ldd, hipStream_t s);
 
+// ---- learned (k, p, q) predictor (mlp.hip) ---------------------------------
+rsvd_status mlp_init(float* p, uint64_t seed, hipStream_t s);
+rsvd_status mlp_forward(const float* p, const float* X, int64_t B, float* Y, hipStream_t s);
+// One batch (B <= 128): loss into *loss (may be null); adam: Adam step
+// number `step` (>= 1) applied to p, m, v; else the gradient into G.
+rsvd_status mlp_grad(float* p, const float* X, const float* T, int64_t B, bool adam, float* m,
+                     float* v, int64_t step, float lr, float* G, float* loss, hipStream_t s);
+// f_i = max(log10(sig_i / sig_0), -16) for i < 16 (sig: l decreasing values)
+rsvd_status pilot_features(int l, const double* sig, float* feat, hipStream_t s);
+
 }  // namespace rsvd

@@ -13,42 +13,11 @@
 // take consecutive groups of the same row, so stores are contiguous.
 #include "common.hpp"
 #include "kernels.hpp"
+#include "philox.hpp"
 
 namespace rsvd {
 
 namespace {
-
-constexpr uint64_t kPhiloxM0 = 0xD2E7470EE14C6C93ull;
-constexpr uint64_t kPhiloxM1 = 0xCA5A826395121157ull;
-constexpr uint64_t kPhiloxW0 = 0x9E3779B97F4A7C15ull;
-constexpr uint64_t kPhiloxW1 = 0xBB67AE8584CAA73Bull;
-
-__device__ __forceinline__ void philox4x64_10(uint64_t& c0, uint64_t& c1, uint64_t& c2,
-                                              uint64_t& c3, uint64_t k0, uint64_t k1) {
-#pragma unroll
-  for (int r = 0; r < 10; r++) {
-    if (r > 0) {
-      k0 += kPhiloxW0;
-      k1 += kPhiloxW1;
-    }
-    const uint64_t lo0 = kPhiloxM0 * c0, hi0 = __umul64hi(kPhiloxM0, c0);
-    const uint64_t lo1 = kPhiloxM1 * c2, hi1 = __umul64hi(kPhiloxM1, c2);
-    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
-    c0 = n0;
-    c1 = lo1;
-    c2 = n2;
-    c3 = lo0;
-  }
-}
-
-__device__ __forceinline__ void box_muller(uint64_t ra, uint64_t rb, double& z0, double& z1) {
-  const double u1 = ((double)(ra >> 11) + 1.0) * 0x1p-53;
-  const double u2 = (double)(rb >> 11) * 0x1p-53;
-  const double rad = sqrt(-2.0 * log(u1));
-  const double ang = (2.0 * 3.141592653589793) * u2;
-  z0 = rad * cos(ang);
-  z1 = rad * sin(ang);
-}
 
 __global__ void __launch_bounds__(256) omega_kernel(int64_t n, int64_t l, int64_t col0,
                                                     uint64_t seed, uint64_t channel,

@@ -349,7 +349,10 @@ rsvd_status small_svd_and_rank(const rsvd_plan_s& pl, const Ws& w, int64_t l, do
                         w.at<double>(pl.off_sig), w.at<double>(pl.off_Us), w.at<double>(pl.off_W),
                         st, s));
   }
-  return select_rank(l, p.oversample, kcl, pl.mode, pl.param, w.at<double>(pl.off_sig), st, s);
+  // the l - p cap protects unconverged trailing values; an exact SVD
+  // (l = min(m, n)) has none
+  const int64_t p_cap = l == (p.m < p.n ? p.m : p.n) ? 0 : p.oversample;
+  return select_rank(l, p_cap, kcl, pl.mode, pl.param, w.at<double>(pl.off_sig), st, s);
 }
 
 // Step 3 and the outputs: L = Q L_Y (Q: m x l, ldq), R = Q_B W (Q_B = Zc),
@@ -744,6 +747,99 @@ rsvd_status rsvd_small_svd(int64_t l, const double* R, double* sv, double* Us, d
     return RSVD_EHIP;
   return RSVD_OK;
 #undef RSVD_TRY
+}
+
+// ---- learned (k, p, q) predictor ---------------------------------------------
+
+rsvd_status rsvd_mlp_init(float* params, uint64_t seed, void* stream) {
+  if (!params) return RSVD_EINVAL;
+  return mlp_init(params, seed, (hipStream_t)stream);
+}
+
+rsvd_status rsvd_mlp_forward(const float* params, const float* X, int64_t B, float* Y,
+                             void* stream) {
+  if (B < 0 || (B > 0 && (!params || !X || !Y))) return RSVD_EINVAL;
+  return mlp_forward(params, X, B, Y, (hipStream_t)stream);
+}
+
+rsvd_status rsvd_mlp_grad(const float* params, const float* X, const float* T, int64_t B,
+                          float* grad, float* loss, void* stream) {
+  if (!params || !X || !T || !grad || B < 1 || B > RSVD_MLP_MAX_BATCH) return RSVD_EINVAL;
+  return mlp_grad(const_cast<float*>(params), X, T, B, false, nullptr, nullptr, 1, 0.0f, grad,
+                  loss, (hipStream_t)stream);
+}
+
+rsvd_status rsvd_mlp_train_step(float* params, float* adam_m, float* adam_v, int64_t step,
+                                const float* X, const float* T, int64_t B, float lr,
+                                float* loss, void* stream) {
+  if (!params || !adam_m || !adam_v || !X || !T || step < 1 || B < 1 ||
+      B > RSVD_MLP_MAX_BATCH || !(lr > 0.0f))
+    return RSVD_EINVAL;
+  return mlp_grad(params, X, T, B, true, adam_m, adam_v, step, lr, nullptr, loss,
+                  (hipStream_t)stream);
+}
+
+namespace {
+// Layout of the pilot: a plan for l = min(32, m, n) columns in the FP32
+// schedule with no power step (the sketch is the only product with A).
+rsvd_status pilot_plan(int64_t m, int64_t n, rsvd_plan_t* pl, size_t* bytes) {
+  rsvd_problem p{};
+  p.m = m;
+  p.n = n;
+  p.k = RSVD_PILOT_COLS;
+  p.rank_mode = RSVD_RANK_FIXED;
+  p.precision = RSVD_PREC_MIXED_FP32;
+  return rsvd_plan(&p, pl, bytes);
+}
+}  // namespace
+
+size_t rsvd_pilot_work_bytes(int64_t m, int64_t n) {
+  rsvd_plan_t pl = nullptr;
+  size_t bytes = 0;
+  if (m < 1 || n < 1 || pilot_plan(m, n, &pl, &bytes) != RSVD_OK) return 0;
+  rsvd_destroy(pl);
+  return bytes;
+}
+
+rsvd_status rsvd_pilot_features(const double* A, int64_t lda, int64_t m, int64_t n, uint64_t seed,
+                                uint64_t channel, float* feat, void* work, size_t work_bytes,
+                                void* stream) {
+  if (!A || !feat || !work || m < 1 || n < 1 || lda < n) return RSVD_EINVAL;
+  if (((uintptr_t)work & 255) != 0) return RSVD_EINVAL;
+  rsvd_plan_t plh = nullptr;
+  size_t need = 0;
+  rsvd_status r = pilot_plan(m, n, &plh, &need);
+  if (r != RSVD_OK) return r;
+  struct Guard {
+    rsvd_plan_t p;
+    ~Guard() { rsvd_destroy(p); }
+  } guard{plh};
+  if (work_bytes < need) return RSVD_ENOMEM;
+  const rsvd_plan_s& pl = *plh;
+  const int64_t l = pl.l;
+  hipStream_t s = (hipStream_t)stream;
+  Ws w{(char*)work};
+  DevState* st = w.at<DevState>(pl.off_state);
+  double* Y = w.at<double>(pl.off_Y);
+  double* P0 = w.at<double>(pl.off_Z);
+  double* Rt = w.at<double>(pl.off_Rt);
+  double* part = w.at<double>(pl.off_part);
+  if ((r = init_state(st, 0u, s)) != RSVD_OK) return r;
+  if ((r = gaussian_omega(n, l, 0, seed, channel, P0, l, s)) != RSVD_OK) return r;
+  // Y0 = A P0 on the FP32 matrix cores
+  if ((r = dgemm(false, m, l, n, 1.0, A, lda, P0, l, 0.0, Y, l, part, pl.part_doubles, s, 64,
+                 nullptr, kPrecF32)) != RSVD_OK)
+    return r;
+  // singular values of Y0 = those of its triangular factor
+  if ((r = orth(pl, w, m, l, Y, Rt, s, true)) != RSVD_OK) return r;
+  if ((r = block_jacobi(l, Rt, w.at<double>(pl.off_M), w.at<double>(pl.off_P), 30, 1, st, s)) !=
+      RSVD_OK)
+    return r;
+  if ((r = svd_finish(l, pl.kc, w.at<double>(pl.off_M), w.at<double>(pl.off_P), jacobi_padded(l),
+                      w.at<double>(pl.off_sig), w.at<double>(pl.off_Us), w.at<double>(pl.off_W),
+                      st, s)) != RSVD_OK)
+    return r;
+  return pilot_features((int)l, w.at<double>(pl.off_sig), feat, s);
 }
 
 void rsvd_trace_enable(int32_t on) { g_trace_on = on != 0; }

@@ -162,6 +162,18 @@ def test_threshold_rank_rule():
     assert r2.rank == 100 and r2.flags & orsvd.FLAG_RANK_CAPPED
 
 
+def test_threshold_rank_uncapped_for_exact_svd():
+    # l = min(m, n): every value is exact, so the rule keeps all values above
+    # the threshold even beyond l - p
+    n = 60
+    sig = synth.spectrum_exp(n, 5.0)
+    A = synth.symmetric(n, sig, tag=114)
+    r = rsvd(A, k=50, p=20, q=0, seed=12, symmetric=True, rank_mode="rel_threshold", rank_param=1e-5)
+    expect = int(math.floor(5.0 * math.log(1e5))) + 1  # 58 > l - p = 40
+    assert r.l == n and r.rank == expect
+    assert r.flags == orsvd.FLAG_FULL_SVD
+
+
 def test_percent_rank_and_eq2_values():
     gold = json.load(open(GOLDEN))
     N = gold["channel_dims"][1]["N"]
