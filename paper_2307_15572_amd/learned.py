@@ -23,6 +23,9 @@ from dataclasses import dataclass
 P_GRID = (8, 16, 32, 64, 128, 192)
 Q_MAX = 4
 CONVERGED = 1e-8
+# predicted ranks are inflated by 10 %: an under-predicted k fails the check
+# (rank capped) and costs a fallback, an over-predicted one a few columns
+K_MARGIN = 1.1
 
 
 def standardize(T):
@@ -42,10 +45,11 @@ def targets_from_labels(labels):
 
 
 def kpq_from_output(y, mu, sd, n):
-    """Standardized network output -> (k, p, q): k rounded up and capped at n,
-    p rounded up to the grid, q rounded up into 0..4."""
+    """Standardized network output -> (k, p, q): k with the K_MARGIN safety
+    factor, rounded up and capped at n; p rounded up to the grid; q rounded
+    up into 0..4."""
     raw = [float(y[i]) * sd[i] + mu[i] for i in range(3)]
-    k = int(min(max(math.ceil(10.0 ** raw[0]), 1), n))
+    k = int(min(max(math.ceil(K_MARGIN * 10.0 ** raw[0]), 1), n))
     p = next((g for g in P_GRID if g >= raw[1]), P_GRID[-1])
     q = int(min(max(math.ceil(raw[2] - 1e-9), 0), Q_MAX))
     return k, p, q
@@ -104,3 +108,32 @@ def adaptive_passes(blocks, q, l, mn):
     products + 1 projection, plus the stopping sketch unless the growth hit
     min(m, n)."""
     return blocks * (2 * q + 2) + (0 if l >= mn else 1)
+
+
+def train_predictor(features, labels, epochs=300, batch=128, lr=3e-3, seed=0, device="cuda"):
+    """Fit the MLP on (features N x 16, labels [(k, p, q)]) with Adam on the
+    device. Labels should describe the spectrum alone (no cap at the channel
+    size, which the features cannot see). Returns (net, mu, sd, final mean
+    loss in standardized units)."""
+    import numpy as np
+    import torch
+    from . import Mlp
+    T = targets_from_labels(labels)
+    mu, sd = standardize(T)
+    Xd = torch.as_tensor(np.asarray(features, dtype=np.float32), device=device).contiguous()
+    Td = torch.as_tensor(((T - mu) / sd).astype(np.float32), device=device).contiguous()
+    net = Mlp(seed=seed, device=device)
+    N = Xd.shape[0]
+    last = []
+    for ep in range(epochs):
+        for b0 in range(0, N, batch):
+            loss = net.train_step(Xd[b0:b0 + batch], Td[b0:b0 + batch], lr=lr)
+            if ep == epochs - 1:
+                last.append(loss)
+    final = float(torch.cat(last).mean().item()) if last else float("nan")
+    return net, mu, sd, final
+
+
+def threshold_rank(n, d, tau):
+    """Exact threshold rank of the constructed spectrum exp(-i/d) (capped at n)."""
+    return min(n, 1 + int(math.floor(d * math.log(1.0 / tau))))

@@ -250,12 +250,16 @@ def c5_dims(count=2000, lo=200, hi=6000, tag=5):
     return channel_dims(count, lo, hi, tag=tag)
 
 
-def kpq_label(n, d, tau=C4_TAU):
+def kpq_label(n, d, tau=C4_TAU, cap=True):
     """Training label of a channel with sigma_i = exp(-i/d) (generator metadata):
     k* = its threshold rank at tau (capped at n); (p*, q*) = the cheapest
     (cost (2q + 2)(k* + p)) grid point whose kept values are converged,
     (sigma_{k+p} / sigma_k)^(4q+2) = exp(-p (4q + 2) / d) <= 1e-8, or whose
-    l = k + p reaches n (then the method is an exact SVD)."""
+    l = k + p reaches n (then the method is an exact SVD). cap=False labels
+    the spectrum alone, as if n were unbounded (what the pilot features can
+    see; the cap at n is applied when a prediction is used)."""
+    if not cap:
+        n = 1 << 40
     k = min(n, 1 + int(math.floor(d * math.log(1.0 / tau))))
     best = None
     for q in C5_Q_GRID:
@@ -268,3 +272,24 @@ def kpq_label(n, d, tau=C4_TAU):
     if best is None:  # nothing on the grid converges: the largest p, q
         best = (0, C5_P_GRID[-1], C5_Q_GRID[-1])
     return k, best[1], best[2]
+
+
+def channel_device_rng(c, n, d, tag, device="cuda"):
+    """Symmetric PSD channel with sigma_i = exp(-i/d) drawn entirely on the
+    device (torch generator seeded by (tag, c)): the fast path for the large
+    learned-predictor sets. Same construction as channel(); only the random
+    stream differs."""
+    import torch
+    sigma = effective(spectrum_exp(n, d))
+    r = len(sigma)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(tag) * 1_000_003 + int(c))
+    G = torch.randn(n, r, dtype=torch.float64, device=device, generator=g)
+    Q, R = torch.linalg.qr(G, mode="reduced")
+    del G
+    dd = torch.sign(torch.diagonal(R))
+    dd[dd == 0] = 1.0
+    Q = Q * dd[None, :]
+    A = (Q * torch.from_numpy(sigma).to(device)[None, :]) @ Q.T
+    del Q
+    return _finish_symmetric_device(A, None, 0.0, device).contiguous(), spectrum_exp(n, d)
