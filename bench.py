@@ -43,8 +43,8 @@ PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 # FETCH_SIZE is scaled by 2.0 and WRITE_SIZE by 1.0: what the counters read
 # for a plain 1 GiB copy kernel. Valid only for the GEMM source they were
 # taken with; any other source reports traffic as null.
-TRAFFIC_SOURCE_SHA256 = "7cb1249af65a4ad1"
-TRAFFIC_FETCH_BYTES = 1122900 * 1024 * 2.0
+TRAFFIC_SOURCE_SHA256 = "81546d6e767f017d"
+TRAFFIC_FETCH_BYTES = 1134085 * 1024 * 2.0
 TRAFFIC_WRITE_BYTES = 69632 * 1024 * 1.0
 
 
@@ -212,7 +212,7 @@ def main():
         "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
         "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
         "algorithmic_bytes": 8.0 * w.m * w.n + 8.0 * (w.n + w.m) * l,
-        "kernel": "dgemm_nn_dma_kernel<NT=17, 8 waves> (A x 272-column panel, LDS-DMA pipeline)",
+        "kernel": "dgemm_nn_dma_kernel<NT=17, 8 waves, FP64> (A x 272-column panel, LDS-DMA pipeline)",
         "flops_per_launch": flops_per_launch, "avg_ms": round(gemm_avg_s * 1e3, 4),
         "launches": int(gemm_cnt),
     }
