@@ -492,28 +492,67 @@ __global__ void __launch_bounds__(512) chol_tiles_kernel(int l, double* __restri
 
 
 // ---------------------------------------------------------------------------
-// The same Cholesky and inverse spread over a grid of workgroups (large l):
-// every wave of the grid takes tiles, the phases are separated by the grid
-// barrier, and the block row lives in global scratch. Look-ahead: the wave
-// that applies step k's update to diagonal tile k+1 factors it right away, so
-// a step has two barriers (after the block row, after the trailing update).
+// The same Cholesky and inverse spread over a grid of workgroups (large l),
+// in super-steps of 32 rows (two tile rows, 2K and 2K+1):
+//   row      R_{2K,J} = X_00^T G_{2K,J};  R_{2K+1,J} = X_11^T (G_{2K+1,J} -
+//            R_01^T R_{2K,J}) for every tile column J beyond the block
+//            (forward substitution with the diagonal block [R_00 R_01; 0 R_11]
+//            and the inverses X_00, X_11 of its diagonal tiles)
+//   trailing G_IJ -= R_{2K,I}^T R_{2K,J} + R_{2K+1,I}^T R_{2K+1,J}
+// with the next diagonal block updated and factored by one wave as soon as
+// its three tiles are done (look-ahead), so a super-step has two grid
+// barriers. Every wave of the grid takes tiles; the 32-row panel lives in
+// global scratch. A tile count that is odd is padded with an identity tile.
 // Decisions (breakdown, pivot spread, retries) are uniform across the grid.
 // ---------------------------------------------------------------------------
 
-// Factor the updated diagonal tile k held in t (one wave): R_kk, X_kk = R_kk^{-1}
-// to W / Xg; breakdown and the pivot range go to the state (one writer per step).
-__device__ void grid_diag_factor(const TileCtx& cx, double t[4], int k, double* W, double* Xg,
-                                 bool clamp, double clampv, DevState* st) {
-  double dmax = 0.0, dmin = INFINITY, x[4];
-  const bool ok = tile_chol(t, clamp, clampv, 16 * k, cx.l, dmax, dmin);
-  tile_inv_upper(t, x);
-  store_tile(cx, W, k, k, t);
-  store_tile(cx, Xg, k, k, x);
+// Pivot bookkeeping of one factored diagonal tile (lane 0 of the wave; one
+// writer per super-step).
+__device__ __forceinline__ void note_pivots(bool ok, double dmax, double dmin, DevState* st) {
   if ((threadIdx.x & 63) == 0) {
     if (!ok) st->chol_fail = 1u;
     if (dmax > st->piv_max) st->piv_max = dmax;
     if (dmin < st->piv_min) st->piv_min = dmin;
   }
+}
+
+// Factor the updated 32 x 32 diagonal block of super-step K held by one wave
+// (t00, t01, t11 in the accumulator layout): R_00, R_01, R_11 to W and the
+// inverses X_00, X_11 to Xg. The accumulator layout of each product is the
+// operand layout the next one needs (item s of lane (r, g) is entry
+// (g + 4 s, r)), so no transposition is required:
+//   R_01 = X_00^T t01;  t11 -= R_01^T R_01;  R_11 = chol(t11).
+struct Tiles3 {
+  double t00[4], t01[4], t11[4];
+};
+
+// Not inlined: its unrolled shuffles would otherwise share the register
+// budget of the grid kernel's trailing loop (and spill it).
+__device__ __noinline__ void grid_block_factor(TileCtx cx, Tiles3 tb, int K, double* W, double* Xg,
+                                               bool clamp, double clampv, DevState* st) {
+  double* t00 = tb.t00;
+  double* t01 = tb.t01;
+  double* t11 = tb.t11;
+  const int i0 = 2 * K, i1 = 2 * K + 1;
+  double dmax = 0.0, dmin = INFINITY, x00[4], x11[4];
+  bool ok = tile_chol(t00, clamp, clampv, 16 * i0, cx.l, dmax, dmin);
+  tile_inv_upper(t00, x00);
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s4 = 0; s4 < 4; s4++) acc = mfma_f64_16x16x4(x00[s4], t01[s4], acc);
+  double r01[4] = {acc[0], acc[1], acc[2], acc[3]};
+  d4 upd = {t11[0], t11[1], t11[2], t11[3]};
+#pragma unroll
+  for (int s4 = 0; s4 < 4; s4++) upd = mfma_f64_16x16x4(-r01[s4], r01[s4], upd);
+  double u11[4] = {upd[0], upd[1], upd[2], upd[3]};
+  ok = tile_chol(u11, clamp, clampv, 16 * i1, cx.l, dmax, dmin) && ok;
+  tile_inv_upper(u11, x11);
+  store_tile(cx, W, i0, i0, t00);
+  store_tile(cx, W, i0, i1, r01);
+  store_tile(cx, W, i1, i1, u11);
+  store_tile(cx, Xg, i0, i0, x00);
+  store_tile(cx, Xg, i1, i1, x11);
+  note_pivots(ok, dmax, dmin, st);
 }
 
 // Entry (row, col) of the inverse diagonal tile k (identity beyond l).
@@ -523,13 +562,22 @@ __device__ __forceinline__ double xdiag(const TileCtx& cx, const double* Xg, int
   return cx.in(i, c) ? Xg[(int64_t)i * cx.l + c] : (row == col ? 1.0 : 0.0);
 }
 
-__global__ void __launch_bounds__(512) chol_grid_kernel(int l, double* __restrict__ G,
+// Scratch (doubles) of the grid Cholesky's 32-row panel.
+__host__ __device__ __forceinline__ int64_t grid_panel_ld(int64_t l) {
+  const int64_t nb = (l + 15) / 16;
+  return 16 * (nb + (nb & 1)) + 1;
+}
+
+// 256 threads: one wave per SIMD, so each wave may use the whole register
+// file (the 32-row trailing batch needs ~330 registers; at 512 threads a
+// wave is limited to 256 and the kernel spills).
+__global__ void __launch_bounds__(256) chol_grid_kernel(int l, double* __restrict__ G,
                                                          double* __restrict__ R,
                                                          double* __restrict__ Rinv,
                                                          double* __restrict__ panel, int64_t m,
                                                          int pass, int only_if_shifted,
                                                          DevState* st) {
-  __shared__ double red[512 / 64];
+  __shared__ double red[256 / 64];
   __shared__ int s_ok;
   if (only_if_shifted && st->qr_shifted == 0) return;
   const GridTeam tm{st, &s_ok};
@@ -538,8 +586,10 @@ __global__ void __launch_bounds__(512) chol_grid_kernel(int l, double* __restric
   TileCtx cx;
   cx.l = l;
   cx.nb = (l + 15) / 16;
-  cx.ps = 16 * cx.nb + 1;
-  const int nb = cx.nb, ps = cx.ps;
+  cx.ps = (int)grid_panel_ld(l);
+  const int nbe = cx.nb + (cx.nb & 1);  // tiles, padded to an even count
+  const int nsup = nbe / 2;
+  const int ps = cx.ps;
   const int64_t ll = (int64_t)l * l;
   const int64_t gthreads = (int64_t)gridDim.x * blockDim.x;
   const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -567,62 +617,111 @@ __global__ void __launch_bounds__(512) chol_grid_kernel(int l, double* __restric
     }
     if (!tm.sync()) return;
     if (gw == 0) {
-      double t[4];
-      load_tile(cx, R, 0, 0, t);
-      grid_diag_factor(cx, t, 0, R, Rinv, clamp, clampv, st);
+      Tiles3 tb;
+      load_tile(cx, R, 0, 0, tb.t00);
+      load_tile(cx, R, 0, 1, tb.t01);
+      load_tile(cx, R, 1, 1, tb.t11);
+      grid_block_factor(cx, tb, 0, R, Rinv, clamp, clampv, st);
     }
     if (!tm.sync()) return;
     bool failed = __hip_atomic_load(&st->chol_fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
-    for (int k = 0; k < nb && !failed; k++) {
-      // block row k: R_kJ = R_kk^{-T} G_kJ
-      for (int J = k + 1 + gw; J < nb; J += TW) {
-        double b[4];
-        load_tile(cx, R, k, J, b);
-        d4 acc = {0.0, 0.0, 0.0, 0.0};
+    for (int K = 0; K < nsup && !failed; K++) {
+      const int i0 = 2 * K, i1 = 2 * K + 1;
+      // block row: the two tile rows of the block against every later column
+      for (int J = i1 + 1 + gw; J < nbe; J += TW) {
+        double g0[4], g1[4], w01[4];
+        load_tile(cx, R, i0, J, g0);
+        load_tile(cx, R, i1, J, g1);
+        load_tile(cx, R, i0, i1, w01);
+        d4 a0 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-        for (int s4 = 0; s4 < 4; s4++) acc = mfma_f64_16x16x4(xdiag(cx, Rinv, k, 4 * s4 + g, r), b[s4], acc);
-        double o[4] = {acc[0], acc[1], acc[2], acc[3]};
-        store_tile(cx, R, k, J, o);
+        for (int s4 = 0; s4 < 4; s4++) a0 = mfma_f64_16x16x4(xdiag(cx, Rinv, i0, 4 * s4 + g, r), g0[s4], a0);
+        double r0[4] = {a0[0], a0[1], a0[2], a0[3]};
+        d4 a1 = {g1[0], g1[1], g1[2], g1[3]};
 #pragma unroll
-        for (int it = 0; it < 4; it++) panel[(g + 4 * it) * ps + 16 * J + r] = o[it];
+        for (int s4 = 0; s4 < 4; s4++) a1 = mfma_f64_16x16x4(-w01[s4], r0[s4], a1);
+        double h1[4] = {a1[0], a1[1], a1[2], a1[3]};
+        d4 a2 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s4 = 0; s4 < 4; s4++) a2 = mfma_f64_16x16x4(xdiag(cx, Rinv, i1, 4 * s4 + g, r), h1[s4], a2);
+        double r1[4] = {a2[0], a2[1], a2[2], a2[3]};
+        store_tile(cx, R, i0, J, r0);
+        store_tile(cx, R, i1, J, r1);
+#pragma unroll
+        for (int it = 0; it < 4; it++) {
+          panel[(g + 4 * it) * ps + 16 * J + r] = r0[it];
+          panel[(16 + g + 4 * it) * ps + 16 * J + r] = r1[it];
+        }
       }
       if (!tm.sync()) return;
-      // trailing tiles; the owner of tile (k+1, k+1) factors it after its update
-      const int n = nb - k - 1;
-      const int T = n * (n + 1) / 2;
-      constexpr int TB = 4;
-      for (int t0 = gw * TB; t0 < T; t0 += TW * TB) {
-        int Is[TB], Js[TB];
-        double tl[TB][4];
-        int I, J;
-        trailing_coords(t0, n, I, J);
+      // trailing update of the tiles beyond the block (upper triangle)
+      const int n = nbe - i1 - 1;
+      if (n > 0) {
+        const int first = i1 + 1;
+        // wave 0 of the grid: the next diagonal block, then its factorization
+        if (gw == 0) {
+          Tiles3 tb;
+          double* dst[3] = {tb.t00, tb.t01, tb.t11};
+          const int bi[3] = {first, first, first + 1}, bj[3] = {first, first + 1, first + 1};
 #pragma unroll
-        for (int q = 0; q < TB; q++) {
-          Is[q] = I + k + 1;
-          Js[q] = J + k + 1;
-          if (++J >= n) {
-            I++;
-            J = I;
+          for (int q = 0; q < 3; q++) {
+            double t[4];
+            load_tile(cx, R, bi[q], bj[q], t);
+            d4 acc = {t[0], t[1], t[2], t[3]};
+#pragma unroll
+            for (int h = 0; h < 2; h++)
+#pragma unroll
+              for (int s4 = 0; s4 < 4; s4++) {
+                const double a = -panel[(16 * h + 4 * s4 + g) * ps + 16 * bi[q] + r];
+                const double bb = panel[(16 * h + 4 * s4 + g) * ps + 16 * bj[q] + r];
+                acc = mfma_f64_16x16x4(a, bb, acc);
+              }
+#pragma unroll
+            for (int it = 0; it < 4; it++) dst[q][it] = acc[it];
           }
+          grid_block_factor(cx, tb, K + 1, R, Rinv, clamp, clampv, st);
         }
+        // every other wave: the remaining tiles, TB at a time so their L2
+        // round trips overlap
+        const int T = n * (n + 1) / 2;
+        constexpr int TB = 4;
+        if (gw > 0) {
+          for (int t0 = (gw - 1) * TB; t0 < T; t0 += (TW - 1) * TB) {
+            int Is[TB], Js[TB];
+            double tl[TB][4];
+            int I, J;
+            trailing_coords(t0, n, I, J);
 #pragma unroll
-        for (int q = 0; q < TB; q++)
-          if (t0 + q < T) load_tile(cx, R, Is[q], Js[q], tl[q]);
-#pragma unroll
-        for (int q = 0; q < TB; q++) {
-          if (t0 + q < T) {
-            d4 acc = {tl[q][0], tl[q][1], tl[q][2], tl[q][3]};
-#pragma unroll
-            for (int s4 = 0; s4 < 4; s4++) {
-              const double a = -panel[(4 * s4 + g) * ps + 16 * Is[q] + r];
-              const double bb = panel[(4 * s4 + g) * ps + 16 * Js[q] + r];
-              acc = mfma_f64_16x16x4(a, bb, acc);
+            for (int q = 0; q < TB; q++) {
+              Is[q] = I + first;
+              Js[q] = J + first;
+              if (++J >= n) {
+                I++;
+                J = I;
+              }
             }
-            double o[4] = {acc[0], acc[1], acc[2], acc[3]};
-            if (t0 + q == 0) {
-              grid_diag_factor(cx, o, k + 1, R, Rinv, clamp, clampv, st);
-            } else {
-              store_tile(cx, R, Is[q], Js[q], o);
+#pragma unroll
+            for (int q = 0; q < TB; q++) {
+              // the next diagonal block belongs to wave 0
+              const bool mine = t0 + q < T && !(Is[q] <= first + 1 && Js[q] <= first + 1);
+              if (mine) load_tile(cx, R, Is[q], Js[q], tl[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < TB; q++) {
+              const bool mine = t0 + q < T && !(Is[q] <= first + 1 && Js[q] <= first + 1);
+              if (mine) {
+                d4 acc = {tl[q][0], tl[q][1], tl[q][2], tl[q][3]};
+#pragma unroll
+                for (int h = 0; h < 2; h++)
+#pragma unroll
+                  for (int s4 = 0; s4 < 4; s4++) {
+                    const double a = -panel[(16 * h + 4 * s4 + g) * ps + 16 * Is[q] + r];
+                    const double bb = panel[(16 * h + 4 * s4 + g) * ps + 16 * Js[q] + r];
+                    acc = mfma_f64_16x16x4(a, bb, acc);
+                  }
+                double o[4] = {acc[0], acc[1], acc[2], acc[3]};
+                store_tile(cx, R, Is[q], Js[q], o);
+              }
             }
           }
         }
@@ -1015,20 +1114,25 @@ size_t chol_tiles_lds(int64_t l) {
   return (size_t)(16 * (16 * nb + 1) + 16 * 17) * sizeof(double);
 }
 
-size_t chol_panel_doubles(int64_t l) { return (size_t)16 * (16 * ((l + 15) / 16) + 1); }
+size_t chol_panel_doubles(int64_t l) {
+  // the single-workgroup kernel's 16-row panel, or the grid kernel's 32 rows
+  const size_t one = (size_t)16 * (16 * ((l + 15) / 16) + 1);
+  const size_t grid = (size_t)32 * (size_t)grid_panel_ld(l);
+  return one > grid ? one : grid;
+}
 
 rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, double* scratch, int64_t m,
                      int pass, int only_if_shifted, DevState* st, hipStream_t s, int share) {
   allow_big_lds();
   if (l >= kCholGridMin && scratch) {
-    // one workgroup per ~32 tiles of the first trailing update, capped so the
-    // grids of concurrent runs fit on the device together
+    // one 4-wave workgroup per ~32 tiles of the first trailing update, capped
+    // so the grids of concurrent runs fit on the device together
     static int cap_all = 0;
     if (cap_all == 0) {
       int dev = 0, ncu = 0, per_cu = 0;
       if (hipGetDevice(&dev) != hipSuccess ||
           hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)chol_grid_kernel, 512,
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)chol_grid_kernel, 256,
                                                        0) != hipSuccess)
         return RSVD_EHIP;
       cap_all = ncu * (per_cu > 0 ? per_cu : 1);
@@ -1041,7 +1145,7 @@ rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, double* scra
     if (cap > 128) cap = 128;
     if (grid > cap) grid = cap;
     if (grid < 1) grid = 1;
-    hipLaunchKernelGGL(chol_grid_kernel, dim3(grid), dim3(512), 0, s, (int)l, G, R, Rinv, scratch,
+    hipLaunchKernelGGL(chol_grid_kernel, dim3(grid), dim3(256), 0, s, (int)l, G, R, Rinv, scratch,
                        m, pass, only_if_shifted, st);
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
