@@ -41,10 +41,25 @@ struct JacArgs {
 };
 
 // returns true if the pair needed rotating
-__device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double (*H)[33],
-                             double (*Vm)[33], double* red, double* rot_c, double* rot_s,
-                             int* rot_p, int* rot_q, int* s_any) {
+// Rotation that annihilates h_pq of the symmetric 2 x 2 [h_pp h_pq; h_pq h_qq]
+// (Rutishauser's formulas); identity when |h_pq| <= tol sqrt(h_pp h_qq).
+__device__ __forceinline__ void jac_rot(double hpp, double hqq, double hpq, double tol, double& c,
+                                        double& s) {
+  c = 1.0;
+  s = 0.0;
+  if (fabs(hpq) > tol * sqrt(hpp) * sqrt(hqq) && hpq != 0.0) {
+    const double zeta = (hqq - hpp) / (2.0 * hpq);
+    const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+    c = 1.0 / sqrt(1.0 + t * t);
+    s = c * t;
+  }
+}
+
+// Hb, Vb: two 32 x 33 buffers each (the Gram H is built in Hb[0]).
+__device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double (*Hb)[32][33],
+                             double (*Vb)[32][33], double* red, int* s_any) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  double (*H)[33] = Hb[0];
   const int Lp = a.Lp;
   const int nct = Lp / 16;
   const double* rI = a.M + (int64_t)16 * I * Lp;
@@ -101,82 +116,99 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
   __syncthreads();
   if (*s_any == 0) return false;
 
-  // ---- two-sided Jacobi on H, V accumulates the rotations
-  for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) Vm[e / 32][e % 32] = (e / 32 == e % 32) ? 1.0 : 0.0;
+  // ---- two-sided Jacobi on H, V accumulates the rotations. A round applies
+  // 16 disjoint plane rotations J_k on both sides, H <- J^T H J, V <- V J.
+  // Thread (k, m) owns the 2 x 2 block of H at rows {p_k, q_k} and columns
+  // {p_m, q_m} (and the same entries of V): it forms rotations k and m from
+  // the old H, applies J_k^T then J_m to its block (the arithmetic, in the
+  // same order, of a row pass followed by a column pass) and writes the other
+  // buffer, so a round needs one barrier.
+  for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x)
+    Vb[0][e / 32][e % 32] = (e / 32 == e % 32) ? 1.0 : 0.0;
   __syncthreads();
-  for (int isw = 0; isw < a.inner_sweeps; isw++) {
-    for (int round = 0; round < 31; round++) {
-      if (threadIdx.x < 16) {
-        int p, q;
-        rr_pair_blk(32, round, threadIdx.x, p, q);
-        if (p > q) { const int t = p; p = q; q = t; }
-        const double hpp = H[p][p], hqq = H[q][q], hpq = H[p][q];
-        double c = 1.0, s = 0.0;
-        if (fabs(hpq) > tol * sqrt(hpp) * sqrt(hqq) && hpq != 0.0) {
-          const double zeta = (hqq - hpp) / (2.0 * hpq);
-          const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          c = 1.0 / sqrt(1.0 + t * t);
-          s = c * t;
+  int cur = 0;
+  {
+    const int k = threadIdx.x >> 4, mm = threadIdx.x & 15;
+    for (int isw = 0; isw < a.inner_sweeps; isw++) {
+      for (int round = 0; round < 31; round++) {
+        double (*Hc)[33] = Hb[cur];
+        double (*Hn)[33] = Hb[cur ^ 1];
+        double (*Vc)[33] = Vb[cur];
+        double (*Vn)[33] = Vb[cur ^ 1];
+        int pk, qk, pm, qm;
+        rr_pair_blk(32, round, k, pk, qk);
+        if (pk > qk) { const int t = pk; pk = qk; qk = t; }
+        rr_pair_blk(32, round, mm, pm, qm);
+        if (pm > qm) { const int t = pm; pm = qm; qm = t; }
+        double ck, sk, cm, sm;
+        jac_rot(Hc[pk][pk], Hc[qk][qk], Hc[pk][qk], tol, ck, sk);
+        jac_rot(Hc[pm][pm], Hc[qm][qm], Hc[pm][qm], tol, cm, sm);
+        // rows: J_k^T
+        double hpp = Hc[pk][pm], hpq = Hc[pk][qm], hqp = Hc[qk][pm], hqq = Hc[qk][qm];
+        if (sk != 0.0) {
+          const double a0 = ck * hpp - sk * hqp, a1 = sk * hpp + ck * hqp;
+          const double b0 = ck * hpq - sk * hqq, b1 = sk * hpq + ck * hqq;
+          hpp = a0; hqp = a1; hpq = b0; hqq = b1;
         }
-        rot_c[threadIdx.x] = c;
-        rot_s[threadIdx.x] = s;
-        rot_p[threadIdx.x] = p;
-        rot_q[threadIdx.x] = q;
-      }
-      __syncthreads();
-      // rows: H <- J^T H
-      for (int e = threadIdx.x; e < 16 * 32; e += blockDim.x) {
-        const int k = e / 32, x = e % 32;
-        const double c = rot_c[k], s = rot_s[k];
-        if (s != 0.0) {
-          const int p = rot_p[k], q = rot_q[k];
-          const double hp = H[p][x], hq = H[q][x];
-          H[p][x] = c * hp - s * hq;
-          H[q][x] = s * hp + c * hq;
+        // columns: J_m
+        if (sm != 0.0) {
+          const double a0 = cm * hpp - sm * hpq, a1 = sm * hpp + cm * hpq;
+          const double b0 = cm * hqp - sm * hqq, b1 = sm * hqp + cm * hqq;
+          hpp = a0; hpq = a1; hqp = b0; hqq = b1;
         }
-      }
-      __syncthreads();
-      // columns: H <- H J, V <- V J
-      for (int e = threadIdx.x; e < 16 * 32; e += blockDim.x) {
-        const int k = e / 32, x = e % 32;
-        const double c = rot_c[k], s = rot_s[k];
-        if (s != 0.0) {
-          const int p = rot_p[k], q = rot_q[k];
-          const double hp = H[x][p], hq = H[x][q];
-          H[x][p] = c * hp - s * hq;
-          H[x][q] = s * hp + c * hq;
-          const double vp = Vm[x][p], vq = Vm[x][q];
-          Vm[x][p] = c * vp - s * vq;
-          Vm[x][q] = s * vp + c * vq;
+        Hn[pk][pm] = hpp;
+        Hn[pk][qm] = hpq;
+        Hn[qk][pm] = hqp;
+        Hn[qk][qm] = hqq;
+        double vpp = Vc[pk][pm], vpq = Vc[pk][qm], vqp = Vc[qk][pm], vqq = Vc[qk][qm];
+        if (sm != 0.0) {
+          const double a0 = cm * vpp - sm * vpq, a1 = sm * vpp + cm * vpq;
+          const double b0 = cm * vqp - sm * vqq, b1 = sm * vqp + cm * vqq;
+          vpp = a0; vpq = a1; vqp = b0; vqq = b1;
         }
+        Vn[pk][pm] = vpp;
+        Vn[pk][qm] = vpq;
+        Vn[qk][pm] = vqp;
+        Vn[qk][qm] = vqq;
+        cur ^= 1;
+        __syncthreads();
       }
-      __syncthreads();
     }
   }
+  double (*Vm)[33] = Vb[cur];
 
   // ---- apply: rows <- V^T rows for M and P; each wave owns whole column tiles
   for (int mat = 0; mat < 2; mat++) {
     double* base = mat == 0 ? a.M : a.P;
     double* bI = base + (int64_t)16 * I * Lp;
     double* bJ = base + (int64_t)16 * J * Lp;
-    for (int ct = wave; ct < nct; ct += 4) {
-      double b[8];
+    // two column tiles per iteration (their loads in flight together)
+    for (int ct = wave; ct < nct; ct += 8) {
+      const bool two = ct + 4 < nct;
+      double b[2][8];
 #pragma unroll
-      for (int s = 0; s < 8; s++) {
-        const int row = 4 * s + g;  // 0..31
-        const double* src = row < 16 ? bI : bJ;
-        b[s] = src[(int64_t)(row & 15) * Lp + 16 * ct + r];
-      }
-      d4 o0 = {0, 0, 0, 0}, o1 = {0, 0, 0, 0};
+      for (int u = 0; u < 2; u++)
 #pragma unroll
-      for (int s = 0; s < 8; s++) {
-        o0 = mfma_f64_16x16x4(Vm[4 * s + g][r], b[s], o0);
-        o1 = mfma_f64_16x16x4(Vm[4 * s + g][16 + r], b[s], o1);
-      }
+        for (int s = 0; s < 8; s++) {
+          const int row = 4 * s + g;  // 0..31
+          const double* src = row < 16 ? bI : bJ;
+          b[u][s] = (u == 0 || two) ? src[(int64_t)(row & 15) * Lp + 16 * (ct + 4 * u) + r] : 0.0;
+        }
 #pragma unroll
-      for (int it = 0; it < 4; it++) {
-        bI[(int64_t)(g + 4 * it) * Lp + 16 * ct + r] = o0[it];
-        bJ[(int64_t)(g + 4 * it) * Lp + 16 * ct + r] = o1[it];
+      for (int u = 0; u < 2; u++) {
+        if (u == 1 && !two) break;
+        const int c = 16 * (ct + 4 * u) + r;
+        d4 o0 = {0, 0, 0, 0}, o1 = {0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < 8; s++) {
+          o0 = mfma_f64_16x16x4(Vm[4 * s + g][r], b[u][s], o0);
+          o1 = mfma_f64_16x16x4(Vm[4 * s + g][16 + r], b[u][s], o1);
+        }
+#pragma unroll
+        for (int it = 0; it < 4; it++) {
+          bI[(int64_t)(g + 4 * it) * Lp + c] = o0[it];
+          bJ[(int64_t)(g + 4 * it) * Lp + c] = o1[it];
+        }
       }
     }
   }
@@ -186,11 +218,9 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
 
 __global__ void __launch_bounds__(256) bjacobi_kernel(JacArgs a) {
   __shared__ int s_bar_ok;
-  __shared__ double H[32][33];
-  __shared__ double Vm[32][33];
+  __shared__ double Hb[2][32][33];
+  __shared__ double Vb[2][32][33];
   __shared__ double red[4 * 3 * 256];
-  __shared__ double rot_c[16], rot_s[16];
-  __shared__ int rot_p[16], rot_q[16];
   __shared__ int s_any;
   const int nb = a.Lp / 16;  // even
   const int npairs = nb / 2;
@@ -204,7 +234,7 @@ __global__ void __launch_bounds__(256) bjacobi_kernel(JacArgs a) {
       for (int pr = blockIdx.x; pr < npairs; pr += gridDim.x) {
         int I, J;
         rr_pair_blk(nb, step, pr, I, J);
-        const bool rot = process_pair(a, I, J, tol, H, Vm, red, rot_c, rot_s, rot_p, rot_q, &s_any);
+        const bool rot = process_pair(a, I, J, tol, Hb, Vb, red, &s_any);
         if (rot && threadIdx.x == 0)
           __hip_atomic_fetch_add(&counters[sweep], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
