@@ -58,7 +58,9 @@ enum {
   RSVD_PREC_FP64 = 0,          /* every product in FP64 (MFMA f64)                  */
   RSVD_PREC_MIXED_FP32 = 1,    /* early passes FP32 MFMA, trailing passes FP64       */
   RSVD_PREC_MIXED_BF16 = 2,    /* early passes BF16 MFMA (FP32 accumulate)           */
-  RSVD_PREC_MIXED_BF16_SPLIT = 3 /* early passes hi/lo BF16 split, 3 products       */
+  RSVD_PREC_MIXED_BF16_SPLIT = 3 /* early passes on BF16 matrix cores with each operand
+                                    split x = hi + lo (hi = bf16(x), lo = bf16(x - hi)):
+                                    hi*lo + lo*hi + hi*hi, FP32 accumulation          */
 };
 
 /* Flags in rsvd_result.flags */
@@ -84,7 +86,7 @@ typedef struct rsvd_problem {
   double rank_param;     /* R% for PERCENT, tau for the threshold rules            */
   int32_t oversample;    /* p >= 0 (the paper uses p = 5)                          */
   int32_t power_iters;   /* q >= 0 (0 = the paper's method)                        */
-  int32_t precision;     /* RSVD_PREC_* (BF16_SPLIT: RSVD_EUNSUPPORTED)            */
+  int32_t precision;     /* RSVD_PREC_*                                            */
   int32_t trailing_hp;   /* mixed modes: how many of the last products before the
                             projection stay FP64 (the projection always does)      */
   uint64_t seed;         /* key word 0 of the Philox stream that draws P           */
@@ -131,12 +133,12 @@ typedef struct rsvd_plan_s* rsvd_plan_t;
  * Returns RSVD_EINVAL for m, n < 1, k < 1 (fixed rule), p < 0, q < 0,
  * R% outside (0, 100], tau outside (0, 1), an unknown mode, trailing_hp < 0,
  * or k_cap < the fixed rank, and for an adaptive problem with a fixed or
- * percent rule, block outside 0..256 or l_max < 0; RSVD_EUNSUPPORTED for a
- * precision mode this build lacks or an adaptive problem in a mixed mode.
+ * percent rule, block outside 0..256 or l_max < 0; RSVD_EUNSUPPORTED for
+ * an adaptive problem in a mixed mode or l > 4096.
  * Mixed modes: of the 2q + 1 products before the projection (sketch and
- * power products), all but the last trailing_hp run on FP32 or
- * BF16 matrix cores with FP32 accumulation; the projection, every QR, the
- * small SVD and the residual stay FP64.
+ * power products), all but the last trailing_hp run on FP32 or BF16 (plain
+ * or split) matrix cores with FP32 accumulation; the projection, every QR,
+ * the small SVD and the residual stay FP64.
  */
 rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* workspace_bytes);
 
@@ -322,7 +324,9 @@ rsvd_status rsvd_dgemm(int32_t trans_a, int64_t m, int64_t n, int64_t k, double 
 /* rsvd_gemm - the same product with the arithmetic of a precision mode:
  * RSVD_PREC_FP64 (= rsvd_dgemm), RSVD_PREC_MIXED_FP32 (operands rounded to
  * FP32, FP32 matrix cores, FP32 accumulation) or RSVD_PREC_MIXED_BF16
- * (operands rounded to BF16, BF16 matrix cores, FP32 accumulation). Inputs
+ * (operands rounded to BF16, BF16 matrix cores, FP32 accumulation) or
+ * RSVD_PREC_MIXED_BF16_SPLIT (operands split into BF16 hi + lo, three BF16
+ * products, FP32 accumulation). Inputs
  * and output stay FP64 in memory; work as for rsvd_dgemm. These are the
  * early products of the precision schedule of the mixed modes. */
 rsvd_status rsvd_gemm(int32_t precision, int32_t trans_a, int64_t m, int64_t n, int64_t k,

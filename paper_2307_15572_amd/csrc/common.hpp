@@ -43,10 +43,17 @@ __device__ __forceinline__ short bf16_bits(double x) {
   return (short)(u >> 16);
 }
 
-// Arithmetic of a streaming product: FP64 MFMA, FP32 MFMA, or BF16 MFMA (both
-// with FP32 accumulation). Operands stay FP64 in memory and are rounded when
-// they enter the matrix core.
-enum Prec { kPrecF64 = 0, kPrecF32 = 1, kPrecBF16 = 2 };
+// BF16 bits back to a value.
+__device__ __forceinline__ double bf16_value(short b) {
+  return (double)__uint_as_float(((uint32_t)(uint16_t)b) << 16);
+}
+
+// Arithmetic of a streaming product: FP64 MFMA, FP32 MFMA, BF16 MFMA, or the
+// BF16 split (x = hi + lo with hi = bf16(x), lo = bf16(x - hi); the product
+// as hi*lo + lo*hi + hi*hi on BF16 matrix cores). The low-precision ones
+// accumulate in FP32. Operands stay FP64 in memory and are rounded (split)
+// when they enter the matrix core.
+enum Prec { kPrecF64 = 0, kPrecF32 = 1, kPrecBF16 = 2, kPrecBF16S = 3 };
 
 // ---- wave reductions --------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {

@@ -41,6 +41,7 @@ constexpr int kAPF = RSVD_GEMM_APF;
 template <int PREC> struct AccType { using type = d4; };
 template <> struct AccType<kPrecF32> { using type = f4; };
 template <> struct AccType<kPrecBF16> { using type = f4; };
+template <> struct AccType<kPrecBF16S> { using type = f4; };
 
 // row of the 16 x 16 output tile held by accumulator item `it` of lane group g
 template <int PREC>
@@ -73,13 +74,37 @@ __device__ __forceinline__ void chunk_mma(typename AccType<PREC>::type (&acc)[NT
 #pragma unroll
       for (int t = 0; t < NT; t++) acc[t] = mfma_f32_16x16x4(a, bf[t], acc[t]);
     }
-  } else {
+  } else if constexpr (PREC == kPrecBF16) {
     const s4 a = {bf16_bits(av[0]), bf16_bits(av[1]), bf16_bits(av[2]), bf16_bits(av[3])};
 #pragma unroll
     for (int t = 0; t < NT; t++) {
       const double* col = Bs + 4 * g * BN + 16 * t + r;
       const s4 b = {bf16_bits(col[0]), bf16_bits(col[BN]), bf16_bits(col[2 * BN]), bf16_bits(col[3 * BN])};
       acc[t] = mfma_bf16_16x16x16(a, b, acc[t]);
+    }
+  } else {
+    s4 ahi, alo;
+#pragma unroll
+    for (int s = 0; s < 4; s++) {
+      const short h = bf16_bits(av[s]);
+      ahi[s] = h;
+      alo[s] = bf16_bits(av[s] - bf16_value(h));
+    }
+#pragma unroll
+    for (int t = 0; t < NT; t++) {
+      const double* col = Bs + 4 * g * BN + 16 * t + r;
+      s4 bhi, blo;
+#pragma unroll
+      for (int s = 0; s < 4; s++) {
+        const double x = col[s * BN];
+        const short h = bf16_bits(x);
+        bhi[s] = h;
+        blo[s] = bf16_bits(x - bf16_value(h));
+      }
+      // the small cross terms first, then the leading product
+      acc[t] = mfma_bf16_16x16x16(ahi, blo, acc[t]);
+      acc[t] = mfma_bf16_16x16x16(alo, bhi, acc[t]);
+      acc[t] = mfma_bf16_16x16x16(ahi, bhi, acc[t]);
     }
   }
 }
@@ -538,6 +563,7 @@ template <bool TA>
 hipError_t launch_nt_prec(int prec, int nt, dim3 grid, hipStream_t st, const GemmArgs& a) {
   if (prec == kPrecF32) return launch_nt<TA, false, kPrecF32>(nt, grid, st, a);
   if (prec == kPrecBF16) return launch_nt<TA, false, kPrecBF16>(nt, grid, st, a);
+  if (prec == kPrecBF16S) return launch_nt<TA, false, kPrecBF16S>(nt, grid, st, a);
   return launch_nt<TA, false, kPrecF64>(nt, grid, st, a);
 }
 
@@ -558,6 +584,7 @@ template <int WM>
 hipError_t launch_dma_prec(int prec, int nt, dim3 grid, hipStream_t st, const GemmArgs& a) {
   if (prec == kPrecF32) return launch_dma<WM, false, kPrecF32>(nt, grid, st, a);
   if (prec == kPrecBF16) return launch_dma<WM, false, kPrecBF16>(nt, grid, st, a);
+  if (prec == kPrecBF16S) return launch_dma<WM, false, kPrecBF16S>(nt, grid, st, a);
   return launch_dma<WM, false, kPrecF64>(nt, grid, st, a);
 }
 

@@ -193,7 +193,6 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* worksp
   if (p.m < 1 || p.n < 1 || p.oversample < 0 || p.power_iters < 0) return RSVD_EINVAL;
   if (p.symmetric && p.m != p.n) return RSVD_EINVAL;
   if (p.precision < RSVD_PREC_FP64 || p.precision > RSVD_PREC_MIXED_BF16_SPLIT) return RSVD_EINVAL;
-  if (p.precision == RSVD_PREC_MIXED_BF16_SPLIT) return RSVD_EUNSUPPORTED;
   if (p.trailing_hp < 0) return RSVD_EINVAL;
   const bool adaptive = p.adaptive != 0;
   int64_t k = p.k;
@@ -576,9 +575,10 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
   // the last trailing_hp use the low-precision matrix cores in mixed modes;
   // the projection, QR, small SVD and residual are always FP64
   const int n_early = 2 * p.power_iters + 1;
-  const int lowp = p.precision == RSVD_PREC_MIXED_FP32   ? kPrecF32
-                   : p.precision == RSVD_PREC_MIXED_BF16 ? kPrecBF16
-                                                         : kPrecF64;
+  const int lowp = p.precision == RSVD_PREC_MIXED_FP32         ? kPrecF32
+                   : p.precision == RSVD_PREC_MIXED_BF16       ? kPrecBF16
+                   : p.precision == RSVD_PREC_MIXED_BF16_SPLIT ? kPrecBF16S
+                                                               : kPrecF64;
   int product = 0;
   auto stream_pass = [&](bool trans, const double* X, int64_t ldx, double* out, int64_t rows_out,
                          int64_t inner) -> rsvd_status {
@@ -623,7 +623,7 @@ rsvd_status rsvd_gemm(int32_t precision, int32_t trans_a, int64_t m, int64_t n, 
                       double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
                       double beta, double* C, int64_t ldc, void* work, size_t work_bytes,
                       void* stream) {
-  if (precision < RSVD_PREC_FP64 || precision > RSVD_PREC_MIXED_BF16) return RSVD_EINVAL;
+  if (precision < RSVD_PREC_FP64 || precision > RSVD_PREC_MIXED_BF16_SPLIT) return RSVD_EINVAL;
   if (m < 0 || n < 0 || k < 0) return RSVD_EINVAL;
   if (m == 0 || n == 0) return RSVD_OK;
   if (!C || ldc < n) return RSVD_EINVAL;
@@ -631,9 +631,10 @@ rsvd_status rsvd_gemm(int32_t precision, int32_t trans_a, int64_t m, int64_t n, 
     if (!A || !B || ldb < n) return RSVD_EINVAL;
     if (trans_a ? lda < m : lda < k) return RSVD_EINVAL;
   }
-  const int prec = precision == RSVD_PREC_MIXED_FP32 ? kPrecF32
-                   : precision == RSVD_PREC_MIXED_BF16 ? kPrecBF16
-                                                       : kPrecF64;
+  const int prec = precision == RSVD_PREC_MIXED_FP32         ? kPrecF32
+                   : precision == RSVD_PREC_MIXED_BF16       ? kPrecBF16
+                   : precision == RSVD_PREC_MIXED_BF16_SPLIT ? kPrecBF16S
+                                                             : kPrecF64;
   return dgemm(trans_a != 0, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, (double*)work,
                work_bytes / sizeof(double), (hipStream_t)stream, 64, nullptr, prec);
 }

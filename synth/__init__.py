@@ -293,3 +293,39 @@ def channel_device_rng(c, n, d, tag, device="cuda"):
     A = (Q * torch.from_numpy(sigma).to(device)[None, :]) @ Q.T
     del Q
     return _finish_symmetric_device(A, None, 0.0, device).contiguous(), spectrum_exp(n, d)
+
+
+def general_device_rng(m, n, sigma, tag, noise=0.0, device="cuda"):
+    """As general(), drawn entirely on `device` (torch generator seeded by
+    tag): A = U diag(sigma) V^T + noise G / (sqrt(m) + sqrt(n)), Haar U, V by
+    a device QR. Returns a contiguous torch tensor there (the fast path for
+    the 131072 x 8192 workload)."""
+    import torch
+    sigma = effective(np.asarray(sigma, np.float64)[: min(m, n)])
+    r = len(sigma)
+    g = torch.Generator(device=device)
+    g.manual_seed(int(tag) * 7_919 + 17)
+
+    def haar(rows):
+        G = torch.randn(rows, r, dtype=torch.float64, device=device, generator=g)
+        Q, R = torch.linalg.qr(G, mode="reduced")
+        del G
+        d = torch.sign(torch.diagonal(R))
+        d[d == 0] = 1.0
+        return Q * d[None, :]
+
+    U = haar(m)
+    V = haar(n)
+    A = (U * torch.from_numpy(sigma).to(device)[None, :]) @ V.T
+    del U, V
+    if noise:
+        A += (noise / (math.sqrt(m) + math.sqrt(n))) * torch.randn(m, n, dtype=torch.float64,
+                                                                  device=device, generator=g)
+    return A.contiguous()
+
+
+def c3_device(m=131072, n=8192, device="cuda"):
+    """The tall workload built on the device (see c3)."""
+    sigma = spectrum_pow10(min(m, n), 1.0 / 64.0)
+    A = general_device_rng(m, n, sigma, tag=3, noise=1e-9, device=device)
+    return A, sigma, Workload(f"c3_{m}x{n}_general", m, n, False, 512, 16, 3, 2003)

@@ -134,7 +134,9 @@ def test_small_svd_matches_lapack(l, decay):
 LOWP_CASES = [("mixed_fp32", False, 517, 272, 1000), ("mixed_fp32", False, 2048, 272, 8192),
               ("mixed_fp32", True, 272, 272, 4096), ("mixed_fp32", False, 100, 50, 77),
               ("mixed_bf16", False, 517, 272, 1000), ("mixed_bf16", False, 2048, 272, 8192),
-              ("mixed_bf16", True, 300, 100, 2000), ("mixed_bf16", False, 33, 18, 16)]
+              ("mixed_bf16", True, 300, 100, 2000), ("mixed_bf16", False, 33, 18, 16),
+              ("mixed_bf16_split", False, 517, 272, 1000), ("mixed_bf16_split", False, 2048, 272, 8192),
+              ("mixed_bf16_split", True, 300, 100, 2000), ("mixed_bf16_split", False, 33, 18, 16)]
 
 
 @pytest.mark.parametrize("prec,ta,m,n,k", LOWP_CASES)
@@ -149,9 +151,14 @@ def test_lowp_gemm_error_bound(prec, ta, m, n, k):
     opA = A.T if ta else A
     ref = opA @ B
     got = rs.dgemm(to_dev(A), to_dev(B), trans_a=ta, precision=prec).cpu().numpy()
-    u_in = 2.0 ** -24 if prec == "mixed_fp32" else 2.0 ** -8
     u32 = 2.0 ** -24
-    bound = (2 * u_in + (k + 2) * u32) * (np.abs(opA) @ np.abs(B))
+    if prec == "mixed_bf16_split":
+        # x = hi + lo to 2^-17 |x|, the dropped lo*lo term 2^-16 |a b|, and three
+        # products summed in FP32 per term
+        bound = (2.0 ** -15 + (3 * k + 2) * u32) * (np.abs(opA) @ np.abs(B))
+    else:
+        u_in = 2.0 ** -24 if prec == "mixed_fp32" else 2.0 ** -8
+        bound = (2 * u_in + (k + 2) * u32) * (np.abs(opA) @ np.abs(B))
     assert np.all(np.abs(got - ref) <= bound)
     # and it is not secretly FP64: the error is at the format's level
     if prec == "mixed_bf16" and k >= 1000:

@@ -198,3 +198,33 @@ def test_mixed_bf16_error_level():
     assert nrm <= 1e-5
     assert rel <= 1e-2
     assert abs(out.residual - ref.residual) <= 1e-3 * ref.residual
+
+
+def test_tall_full_size_properties():
+    # the 131072 x 8192 workload at full size, where the oracle cannot run:
+    # (i) the leading values (converged: (sigma_528/sigma_255)^7 ~ 1e-19) equal
+    #     the constructed spectrum up to the noise floor (Weyl: |ds| <= ||E||_2
+    #     ~ 1e-9) and FP64 rounding;
+    # (ii) no value exceeds the constructed one by more than that bound
+    #     (interlacing: s_j(Q^T A) <= s_j(A) <= sigma_j + ||E||_2);
+    # (iii) U and V orthonormal; the residual matches sqrt(1 - sum s^2 / ||A||^2)
+    #     to the noise floor's share (Pythagoras with U S V^T = Q Q^T A P_k)
+    import torch
+    import paper_2307_15572_amd as rs
+    announce("tall 131072 x 8192 full size, FP64, properties")
+    A, sigma, w = synth.c3_device(device="cuda:0")
+    out = rs.run(A, w.k, w.p, w.q, seed=w.seed, want_residual=True)
+    s = out.S.cpu().numpy()
+    assert out.rank == 512 and out.l == 528
+    lead = 256
+    assert np.all(np.abs(s[:lead] - sigma[:lead]) <= 2e-9 + 1e-10 * sigma[:lead])
+    assert np.all(s <= sigma[: len(s)] + 2e-9 + 1e-13)
+    U, V = out.U, out.V
+    eye = torch.eye(512, dtype=torch.float64, device=A.device)
+    assert (U.T @ U - eye).abs().max().item() <= 1e-12
+    assert (V.T @ V - eye).abs().max().item() <= 1e-12
+    fro2 = out.fro2
+    pyth = np.sqrt(max(1.0 - np.sum(s ** 2) / fro2, 0.0))
+    assert abs(out.residual - pyth) <= 1e-6
+    del A
+    torch.cuda.empty_cache()
