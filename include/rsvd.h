@@ -334,6 +334,20 @@ rsvd_status rsvd_gemm(int32_t precision, int32_t trans_a, int64_t m, int64_t n, 
                       double beta, double* C, int64_t ldc, void* work, size_t work_bytes,
                       void* stream);
 
+/* rsvd_bf16_gemm - C = op(A) B (m x n, FP64, overwritten) as rsvd_run
+ * computes the early products of the BF16 schedules: op(A) (m x k) and B
+ * (k x n) are rounded into BF16 planes in the workspace (split != 0: hi =
+ * bf16(x) and lo = bf16(x - hi), three products hi*lo + lo*hi + hi*hi per
+ * term), multiplied on the BF16 matrix cores with FP32 accumulation, and
+ * split-K partial sums are added in FP64. A is m x k (lda), or k x m when
+ * trans_a != 0; B is k x n (ldb); C is m x n (ldc); all device, row-major.
+ * work: device, 256-byte aligned, at least rsvd_bf16_gemm_work_bytes bytes
+ * (RSVD_ENOMEM otherwise). Same error bounds as rsvd_gemm's BF16 modes. */
+size_t rsvd_bf16_gemm_work_bytes(int64_t m, int64_t n, int64_t k, int32_t split);
+rsvd_status rsvd_bf16_gemm(int32_t split, int32_t trans_a, int64_t m, int64_t n, int64_t k,
+                           const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
+                           int64_t ldc, void* work, size_t work_bytes, void* stream);
+
 /* rsvd_orth - thin QR of a tall panel Y (m x l, ldy, device, m >= l), step 1's
  * "QR decomposition Z = Q X": Y is overwritten by Q (orthonormal columns,
  * diag(X) > 0); X (l x l upper triangular, row-major, device) receives the
@@ -355,6 +369,53 @@ rsvd_status rsvd_small_svd(int64_t l, const double* R, double* s, double* Us, do
                            void* work, size_t work_bytes, void* stream);
 
 /*
+ * Autotuning of the tile shapes of the matrix-core products (the
+ * "autotuned tiles" of the batched mode; the paper fixes no tiling).
+ *
+ * Every product launch (FP64 streaming and small products, the residual
+ * pass, the BF16 plane products) picks its tiling from a process-wide table
+ * keyed by kernel kind, arithmetic, transposition and (M, N, K), and falls
+ * back to a built-in heuristic for keys not in the table. rsvd_tune fills
+ * the table for the products of one decomposition: it runs the decomposition
+ * once (arguments exactly as rsvd_run) while each launch records itself,
+ * replays every recorded key not yet in the table once per candidate tiling
+ * (FP64 kernel: 4 or 8 waves per workgroup x K-split counts whose partial
+ * sums fit the plan's workspace; residual pass: 4 or 8 waves; BF16 plane
+ * kernel: 16 or 32 rows per wave x one or two times the fewest column
+ * groups x K-split counts), timed with HIP events over `reps` (1..100)
+ * launches after one warm-up, keeps the fastest, and runs the
+ * decomposition once more, so that S, U, V and *res_dev hold the result of
+ * the tuned shapes. Synchronizes `stream`; device-predicated launches (the
+ * third Cholesky QR pass) are not timed. Tuned shapes change summation
+ * orders only: results stay within the same error bounds. n_tuned (host,
+ * may be NULL) receives the number of keys added. One tuning caller at a
+ * time; runs on other host threads during tuning see the forced candidate
+ * of the key being timed.
+ *
+ * rsvd_batch_tune does the same for every channel of a batch (arguments as
+ * rsvd_batch_run), channel by channel on `stream` in the channel's lane
+ * workspace (shapes timed with the device to themselves); the next
+ * rsvd_batch_run captures a new graph with the tuned shapes.
+ *
+ * rsvd_tune_entries copies up to `max` entries of the table (kind[i] =
+ * 100 kind + 10 arithmetic + transposed; mnk[3i..3i+2] = M, N, K; cfg[3i..]
+ * = the tiling: waves / rows per wave, K splits, column groups) into host
+ * arrays (each may be NULL) and returns the number of entries;
+ * rsvd_tune_clear empties the table.
+ */
+rsvd_status rsvd_tune(rsvd_plan_t plan, const double* A, int64_t lda, const double* omega,
+                      int64_t ldo, double* S, double* U, int64_t ldu, double* V, int64_t ldv,
+                      rsvd_result* res_dev, void* work, size_t work_bytes, int32_t reps,
+                      int32_t* n_tuned, void* stream);
+rsvd_status rsvd_batch_tune(rsvd_batch_t plan, const double* const* A, const int64_t* lda,
+                            double* const* S, double* const* U, const int64_t* ldu,
+                            double* const* V, const int64_t* ldv, rsvd_result* res_dev,
+                            void* work, size_t work_bytes, int32_t reps, int32_t* n_tuned,
+                            void* stream);
+int64_t rsvd_tune_entries(int64_t max, int32_t* kind, int64_t* mnk, int32_t* cfg);
+void rsvd_tune_clear(void);
+
+/*
  * Phase trace (measurement aid). When enabled, rsvd_run records a HIP event
  * pair on its stream around every launch group of a phase; the events are
  * kept on the host until collected. Not thread-safe: one tracing caller at a
@@ -362,8 +423,9 @@ rsvd_status rsvd_small_svd(int64_t l, const double* R, double* s, double* Us, do
  *   0 streaming products with A (sketch, power iterations, projection)
  *   1 QR of the panels    2 small SVD (Jacobi + ordering)   3 lift + signs
  *   4 residual pass       5 projection P                    6 everything else
+ *   7 rounding A into the BF16 planes of the BF16 schedules
  */
-#define RSVD_TRACE_PHASES 7
+#define RSVD_TRACE_PHASES 8
 void rsvd_trace_enable(int32_t on);
 /* Synchronize on the recorded events, add their durations per phase into
  * ms[RSVD_TRACE_PHASES] and counts[RSVD_TRACE_PHASES] (host arrays), and

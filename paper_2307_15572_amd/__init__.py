@@ -29,14 +29,17 @@ FLAG_SYNC_TIMEOUT = 1 << 7
 EXPORTED = (
     "rsvd_plan", "rsvd_plan_l", "rsvd_run", "rsvd_destroy", "rsvd_strerror",
     "rsvd_gaussian_omega", "rsvd_dgemm_work_bytes", "rsvd_dgemm", "rsvd_gemm",
+    "rsvd_bf16_gemm_work_bytes", "rsvd_bf16_gemm",
     "rsvd_orth_work_bytes", "rsvd_orth", "rsvd_small_svd_work_bytes", "rsvd_small_svd",
     "rsvd_trace_enable", "rsvd_trace_collect",
     "rsvd_batch_plan", "rsvd_batch_run", "rsvd_batch_info", "rsvd_batch_destroy",
     "rsvd_mlp_init", "rsvd_mlp_forward", "rsvd_mlp_grad", "rsvd_mlp_train_step",
     "rsvd_pilot_work_bytes", "rsvd_pilot_features",
+    "rsvd_tune", "rsvd_batch_tune", "rsvd_tune_entries", "rsvd_tune_clear",
 )
 MLP_PARAMS, MLP_IN, MLP_OUT, MLP_MAX_BATCH, PILOT_COLS = 5443, 16, 3, 128, 32
-TRACE_PHASES = ("stream_gemm", "qr", "small_svd", "lift_signs", "residual", "omega", "other")
+TRACE_PHASES = ("stream_gemm", "qr", "small_svd", "lift_signs", "residual", "omega", "other",
+                "bf16_planes")
 
 
 class RsvdError(RuntimeError):
@@ -99,6 +102,10 @@ def lib():
     L.rsvd_dgemm.restype = ctypes.c_int
     L.rsvd_gemm.argtypes = [i32, i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, vp, sz, vp]
     L.rsvd_gemm.restype = ctypes.c_int
+    L.rsvd_bf16_gemm_work_bytes.argtypes = [i64, i64, i64, i32]
+    L.rsvd_bf16_gemm_work_bytes.restype = sz
+    L.rsvd_bf16_gemm.argtypes = [i32, i32, i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, sz, vp]
+    L.rsvd_bf16_gemm.restype = ctypes.c_int
     L.rsvd_orth_work_bytes.argtypes = [i64, i64]
     L.rsvd_orth_work_bytes.restype = sz
     L.rsvd_orth.argtypes = [i64, i64, vp, i64, vp, vp, vp, sz, vp]
@@ -117,6 +124,15 @@ def lib():
     L.rsvd_batch_run.argtypes = [vp, pp(vp), pp(i64), pp(vp), pp(vp), pp(i64), pp(vp), pp(i64),
                                  vp, vp, sz, vp]
     L.rsvd_batch_run.restype = ctypes.c_int
+    L.rsvd_tune.argtypes = [vp, vp, i64, vp, i64, vp, vp, i64, vp, i64, vp, vp, sz, i32, pp(i32), vp]
+    L.rsvd_tune.restype = ctypes.c_int
+    L.rsvd_batch_tune.argtypes = [vp, pp(vp), pp(i64), pp(vp), pp(vp), pp(i64), pp(vp), pp(i64),
+                                  vp, vp, sz, i32, pp(i32), vp]
+    L.rsvd_batch_tune.restype = ctypes.c_int
+    L.rsvd_tune_entries.argtypes = [i64, pp(i32), pp(i64), pp(i32)]
+    L.rsvd_tune_entries.restype = i64
+    L.rsvd_tune_clear.argtypes = []
+    L.rsvd_tune_clear.restype = None
     L.rsvd_batch_info.argtypes = [vp, pp(i32), pp(i32)]
     L.rsvd_batch_info.restype = ctypes.c_int
     L.rsvd_batch_destroy.argtypes = [vp]
@@ -277,6 +293,25 @@ class Plan:
                             _stream(torch, A.device))
         _check(st, "rsvd_run")
 
+    def tune(self, A, bufs, reps=3, omega=None):
+        """Autotune the tile shapes of this decomposition's products (see
+        rsvd_tune); synchronizes. bufs then hold the tuned run's result.
+        Returns the number of shapes added to the process-wide table."""
+        torch = _torch()
+        _check_matrix(torch, A, "A")
+        pr = self.problem
+        if tuple(A.shape) != (pr.m, pr.n):
+            raise RsvdError(f"A has shape {tuple(A.shape)}, plan expects {(pr.m, pr.n)}")
+        ldo = omega.stride(0) if omega is not None else 0
+        U, V = bufs["U"], bufs["V"]
+        n = ctypes.c_int32(0)
+        _check(lib().rsvd_tune(self._h, _ptr(A), A.stride(0), _ptr(omega), ldo, _ptr(bufs["S"]),
+                               _ptr(U), U.stride(0) if U is not None else 0,
+                               _ptr(V), V.stride(0) if V is not None else 0,
+                               _ptr(bufs["res"]), bufs["work"], bufs["work_bytes"], int(reps),
+                               ctypes.byref(n), _stream(torch, A.device)), "rsvd_tune")
+        return n.value
+
     def result(self, bufs):
         """Synchronize and read the device result record."""
         torch = _torch()
@@ -346,9 +381,7 @@ class BatchPlan:
         bufs["work_buf"], bufs["work"], bufs["work_bytes"] = _workspace(torch, self.workspace_bytes, device)
         return bufs
 
-    def run_into(self, As, bufs):
-        """Enqueue every channel on the current stream (no synchronization)."""
-        torch = _torch()
+    def _pointers(self, torch, As, bufs):
         n = self.count
         if len(As) != n:
             raise RsvdError(f"expected {n} matrices")
@@ -366,9 +399,26 @@ class BatchPlan:
             Up[c], ldu[c] = (U.data_ptr(), U.stride(0)) if U is not None else (0, 0)
             Vp[c], ldv[c] = (V.data_ptr(), V.stride(0)) if V is not None else (0, 0)
         self._keep = (Ap, lda, Sp, Up, Vp, ldu, ldv)
+        return self._keep
+
+    def run_into(self, As, bufs):
+        """Enqueue every channel on the current stream (no synchronization)."""
+        torch = _torch()
+        Ap, lda, Sp, Up, Vp, ldu, ldv = self._pointers(torch, As, bufs)
         _check(lib().rsvd_batch_run(self._h, Ap, lda, Sp, Up, ldu, Vp, ldv, _ptr(bufs["res"]),
                                     bufs["work"], bufs["work_bytes"], _stream(torch, As[0].device)),
                "rsvd_batch_run")
+
+    def tune(self, As, bufs, reps=3):
+        """Autotune the tile shapes of every channel's products (see
+        rsvd_batch_tune); synchronizes. Returns the number of shapes added."""
+        torch = _torch()
+        Ap, lda, Sp, Up, Vp, ldu, ldv = self._pointers(torch, As, bufs)
+        n = ctypes.c_int32(0)
+        _check(lib().rsvd_batch_tune(self._h, Ap, lda, Sp, Up, ldu, Vp, ldv, _ptr(bufs["res"]),
+                                     bufs["work"], bufs["work_bytes"], int(reps), ctypes.byref(n),
+                                     _stream(torch, As[0].device)), "rsvd_batch_tune")
+        return n.value
 
     def results(self, bufs):
         """Synchronize and read the count result records."""
@@ -431,6 +481,67 @@ def dgemm(A, B, trans_a=False, alpha=1.0, beta=0.0, C=None, precision="fp64"):
                        _stream(torch, A.device)),
            "rsvd_gemm")
     return C
+
+
+def bf16_gemm(A, B, trans_a=False, split=False):
+    """op(A) B from BF16 planes, as the BF16 schedules of run() compute their
+    early products (split: hi + lo planes, three products per term)."""
+    torch = _torch()
+    _check_matrix(torch, A, "A")
+    _check_matrix(torch, B, "B")
+    m = A.shape[1] if trans_a else A.shape[0]
+    k = A.shape[0] if trans_a else A.shape[1]
+    if B.shape[0] != k:
+        raise RsvdError("inner dimensions differ")
+    n = B.shape[1]
+    C = torch.empty(m, n, dtype=torch.float64, device=A.device)
+    L = lib()
+    wb = L.rsvd_bf16_gemm_work_bytes(m, n, k, int(split))
+    buf, w, wbytes = _workspace(torch, wb, A.device)
+    _check(L.rsvd_bf16_gemm(int(split), int(trans_a), m, n, k, _ptr(A), A.stride(0), _ptr(B),
+                            B.stride(0), _ptr(C), C.stride(0), w, wbytes, _stream(torch, A.device)),
+           "rsvd_bf16_gemm")
+    torch.cuda.synchronize(A.device)
+    del buf
+    return C
+
+
+TUNE_KINDS = {0: "fp64_stream", 1: "generic", 2: "residual", 3: "bf16_planes"}
+
+
+def tune_table():
+    """The autotuner's table: list of dicts (kind, arithmetic, transposed,
+    M, N, K, and the chosen tiling)."""
+    L = lib()
+    n = L.rsvd_tune_entries(0, None, None, None)
+    if n == 0:
+        return []
+    kind = (ctypes.c_int32 * n)()
+    mnk = (ctypes.c_int64 * (3 * n))()
+    cfg = (ctypes.c_int32 * (3 * n))()
+    L.rsvd_tune_entries(n, kind, mnk, cfg)
+    out = []
+    for i in range(n):
+        kd = kind[i]
+        k0 = TUNE_KINDS.get(kd // 100, str(kd // 100))
+        ent = {"kind": k0, "arith": (kd // 10) % 10, "trans": kd % 10,
+               "M": mnk[3 * i], "N": mnk[3 * i + 1], "K": mnk[3 * i + 2]}
+        a, b, c = cfg[3 * i], cfg[3 * i + 1], cfg[3 * i + 2]
+        if k0 == "bf16_planes":
+            ent.update(rows_per_wave=16 * a, splits=b, column_groups=c)
+        elif k0 == "residual":
+            ent.update(waves=a)
+        elif k0 == "generic":
+            ent.update(splits=b)
+        else:
+            ent.update(waves=a, splits=b)
+        out.append(ent)
+    return out
+
+
+def tune_clear():
+    """Empty the autotuner's table (later products use the heuristics)."""
+    lib().rsvd_tune_clear()
 
 
 def orth(Y):

@@ -14,6 +14,7 @@
 
 #include "common.hpp"
 #include "plan.hpp"
+#include "tune.hpp"
 
 struct rsvd_batch_s {
   int64_t count = 0;
@@ -141,6 +142,8 @@ std::vector<uintptr_t> make_key(const rsvd_batch_s* b, const BatchArgs& a) {
   }
   k.push_back((uintptr_t)a.res);
   k.push_back((uintptr_t)a.work);
+  // captured launches hold the tile shapes in force when they were captured
+  k.push_back((uintptr_t)rsvd::tune_generation());
   return k;
 }
 
@@ -268,6 +271,37 @@ rsvd_status rsvd_batch_run(rsvd_batch_t plan, const double* const* A, const int6
     }
   }
   return enqueue_all(b, a, s);
+}
+
+rsvd_status rsvd_batch_tune(rsvd_batch_t plan, const double* const* A, const int64_t* lda,
+                            double* const* S, double* const* U, const int64_t* ldu,
+                            double* const* V, const int64_t* ldv, rsvd_result* res_dev,
+                            void* work, size_t work_bytes, int32_t reps, int32_t* n_tuned,
+                            void* stream) {
+  if (!plan || !A || !lda || !S || !res_dev || !work) return RSVD_EINVAL;
+  rsvd_batch_s* b = plan;
+  if (work_bytes < b->total) return RSVD_ENOMEM;
+  if (((uintptr_t)work & 255) != 0) return RSVD_EINVAL;
+  BatchArgs a{A, lda, S, U, ldu, V, ldv, res_dev, (char*)work};
+  for (int64_t c = 0; c < b->count; c++) {
+    const rsvd_status r = check_channel(*b->plans[c], a, c);
+    if (r != RSVD_OK) return r;
+  }
+  // channel by channel on the caller's stream, each in its lane's workspace;
+  // shapes already in the table are not timed again
+  int tuned = 0;
+  rsvd_status r = RSVD_OK;
+  for (int64_t c = 0; c < b->count && r == RSVD_OK; c++) {
+    const rsvd_plan_s& pl = *b->plans[c];
+    const int i = b->lane_of[c];
+    const rsvd::TuneRun run{a.A[c], a.lda[c], nullptr, 0, a.S[c],
+                            pl.p.want_u ? a.U[c] : nullptr, pl.p.want_u ? a.ldu[c] : 0,
+                            pl.p.want_v ? a.V[c] : nullptr, pl.p.want_v ? a.ldv[c] : 0,
+                            a.res + c, a.work + b->lane_off[i], b->lane_bytes[i]};
+    r = rsvd::tune_plan(b->plans[c], run, reps, (hipStream_t)stream, &tuned);
+  }
+  if (n_tuned) *n_tuned = tuned;
+  return r;
 }
 
 rsvd_status rsvd_batch_info(rsvd_batch_t plan, int32_t* lane_of, int32_t* graph_replayed) {

@@ -55,6 +55,25 @@ __device__ __forceinline__ double bf16_value(short b) {
 // when they enter the matrix core.
 enum Prec { kPrecF64 = 0, kPrecF32 = 1, kPrecBF16 = 2, kPrecBF16S = 3 };
 
+// ---- LDS-DMA copies ---------------------------------------------------------
+#define RSVD_LDS(p) ((__attribute__((address_space(3))) void*)(p))
+
+// One 16-byte-per-lane copy global -> LDS (lane i lands at lds + 16 i). Issued
+// through asm so the compiler's wait-count model does not treat the pending
+// copy as a hazard for reads of the other LDS stages; waits are explicit
+// (wait_vmcnt + barrier). No register is written by the instruction.
+__device__ __forceinline__ void copy_to_lds16(const void* src, const void* lds) {
+  const unsigned off = (unsigned)(uintptr_t)RSVD_LDS(lds);
+  asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "{m0}"(off) : "memory");
+}
+
+template <int N>
+__device__ __forceinline__ void wait_vmcnt() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
+}
+
+
 // ---- wave reductions --------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

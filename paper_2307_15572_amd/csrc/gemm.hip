@@ -21,6 +21,7 @@
 // order (deterministic; no floating-point atomics).
 #include "common.hpp"
 #include "kernels.hpp"
+#include "tune.hpp"
 
 namespace rsvd {
 
@@ -342,23 +343,6 @@ __global__ void __launch_bounds__(kThreads) dgemm_kernel(GemmArgs g) {
 // A stage layout: wave w, half h (k pairs 0-1 / 2-3 of a lane's 4 k values):
 // 64 lanes x 16 B, so the MFMA A fragments of a lane are one 16-byte read.
 // ---------------------------------------------------------------------------
-#define RSVD_LDS(p) ((__attribute__((address_space(3))) void*)(p))
-
-// One 16-byte-per-lane copy global -> LDS (lane i lands at lds + 16 i). Issued
-// through asm so the compiler's wait-count model does not treat the pending
-// copy as a hazard for reads of the other LDS stages; waits are explicit
-// (wait_vmcnt + barrier). No register is written by the instruction.
-__device__ __forceinline__ void copy_to_lds16(const void* src, const void* lds) {
-  const unsigned off = (unsigned)(uintptr_t)RSVD_LDS(lds);
-  asm volatile("s_nop 0\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(src), "{m0}"(off) : "memory");
-}
-
-template <int N>
-__device__ __forceinline__ void wait_vmcnt() {
-  static_assert(N >= 0 && N < 64, "vmcnt range");
-  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
-}
-
 // copies a wave issues per chunk: 2 for A plus its share of the 2 NT B copies
 template <int NT, int WM, int W>
 struct CopiesPerChunk {
@@ -631,7 +615,34 @@ rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const 
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
   }
+  const bool vec_a = (lda % 2 == 0) && ((uintptr_t)A % 16 == 0);
+  const bool vec_b = (ldb % 2 == 0) && ((uintptr_t)B % 16 == 0);
+  // whole K chunks, even N and 16-byte aligned rows: the LDS-DMA pipeline
+  const bool dma_ok = !ta && (K % kBK == 0) && (N % 2 == 0) && N >= 2 && vec_a && vec_b && g_use_dma;
+  const TuneKey tkey{dma_ok ? kTuneDma : kTuneGeneric, prec, ta ? 1 : 0, M, N, K};
+  if (pred == nullptr && tune_recording()) {
+    // candidates: waves (LDS-DMA kernel) x split counts whose partials fit
+    std::vector<TuneCfg> cands;
+    for (int w = dma_ok ? 4 : 0; w <= (dma_ok ? 8 : 0); w += 4) {
+      for (int S = 1; S <= max_splits && S <= 64; S *= 2) {
+        if (S > 1 && (K / S < 2 * kBK || !part || part_doubles < (size_t)S * M * N)) break;
+        cands.push_back({w, S, 0});
+      }
+    }
+    tune_record(tkey, std::move(cands), [=](hipStream_t s2) {
+      return dgemm(ta, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, part_doubles, s2,
+                   max_splits, pred, prec);
+    });
+  }
+  TuneCfg tcfg;
+  const bool tuned = tune_get(tkey, &tcfg) && tcfg.b >= 1;
   GemmShape s = dgemm_shape(M, N, K, max_splits);
+  if (tuned && !dma_ok) {
+    int S = tcfg.b < max_splits ? tcfg.b : max_splits;
+    s.kchunk = ((K + S - 1) / S + kBK - 1) / kBK * kBK;
+    s.splits = (int)((K + s.kchunk - 1) / s.kchunk);
+    s.part_doubles = s.splits > 1 ? (size_t)s.splits * M * N : 0;
+  }
   if (s.splits > 1 && (part == nullptr || part_doubles < s.part_doubles)) {
     // not enough scratch for split-K: run unsplit
     s.splits = 1;
@@ -645,26 +656,28 @@ rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const 
   a.part = s.splits > 1 ? part : nullptr;
   a.tiles_m = s.tiles_m; a.tiles_n = s.tiles_n; a.splits = s.splits;
   a.pred = pred; a.Aref = nullptr; a.ldref = 0; a.rpart = nullptr;
-  a.vec_a = (lda % 2 == 0) && ((uintptr_t)A % 16 == 0);
-  a.vec_b = (ldb % 2 == 0) && ((uintptr_t)B % 16 == 0);
+  a.vec_a = vec_a;
+  a.vec_b = vec_b;
   const int64_t total = (int64_t)s.tiles_m * s.tiles_n * s.splits;
   dim3 grid((unsigned)total);
-  // whole K chunks, even N and 16-byte aligned rows: the LDS-DMA pipeline.
-  // Its 3-stage LDS footprint allows one workgroup per CU, so it is sized to
-  // fill the 256 CUs once: split K only when the output has fewer tiles.
-  const bool dma_ok = !ta && (K % kBK == 0) && (N % 2 == 0) && N >= 2 && a.vec_a && a.vec_b &&
-                      g_use_dma;
   hipError_t e;
   if (dma_ok) {
-    // 8 waves need split K to fill the chip; without enough K use 4
+    // The LDS-DMA kernel's 3-stage LDS footprint allows one workgroup per
+    // CU, so by default it is sized to fill the 256 CUs once: split K only
+    // when the output has fewer tiles; 8 waves need split K to fill the
+    // chip, without enough K use 4. A tuned shape replaces both choices.
     int wm = g_dma_wm;
     if (wm == 8 && (int64_t)((M + 127) / 128) * s.tiles_n < 256 && K / 2 < 256) wm = 4;
+    if (tuned && (tcfg.a == 4 || tcfg.a == 8)) wm = tcfg.a;
     GemmArgs d = a;
     d.tiles_m = (int)((M + 16 * wm - 1) / (16 * wm));
     d.tiles_n = s.tiles_n;
     const int64_t T = (int64_t)d.tiles_m * d.tiles_n;
     int S = 1;
-    while (S < max_splits && T * S < 256 && K / (2 * S) >= 256) S *= 2;
+    if (tuned)
+      S = tcfg.b < max_splits ? tcfg.b : max_splits;
+    else
+      while (S < max_splits && T * S < 256 && K / (2 * S) >= 256) S *= 2;
     int64_t kchunk = ((K + S - 1) / S + kBK - 1) / kBK * kBK;
     S = (int)((K + kchunk - 1) / kchunk);
     if (S > 1 && (part == nullptr || part_doubles < (size_t)S * M * N)) {
@@ -711,16 +724,25 @@ rsvd_status resid(int64_t M, int64_t N, int64_t K, const double* US, int64_t ldu
                       (ldvt % 2 == 0) && ((uintptr_t)US % 16 == 0) && ((uintptr_t)Vt % 16 == 0) &&
                       g_use_dma;
   if (dma_ok) {
+    // 8 waves per workgroup unless tuned to 4 (partial holds the 4-wave count)
+    const TuneKey tkey{kTuneResid, kPrecF64, 0, M, N, K};
+    if (tune_recording())
+      tune_record(tkey, {{4, 0, 0}, {8, 0, 0}}, [=](hipStream_t s2) {
+        return resid(M, N, K, US, ldus, Vt, ldvt, A, lda, partial, st, s2);
+      });
+    TuneCfg tcfg;
+    const int wm = tune_get(tkey, &tcfg) && tcfg.a == 4 ? 4 : 8;
     GemmArgs a;
     a.M = M; a.N = N; a.K = K; a.kchunk = K;
     a.alpha = 1.0; a.beta = 0.0;
     a.A = US; a.lda = ldus; a.B = Vt; a.ldb = ldvt; a.C = nullptr; a.ldc = 0;
     a.part = nullptr;
-    a.tiles_m = (int)((M + 127) / 128); a.tiles_n = sh.tiles_n; a.splits = 1;
+    a.tiles_m = (int)((M + 16 * wm - 1) / (16 * wm)); a.tiles_n = sh.tiles_n; a.splits = 1;
     a.pred = nullptr; a.Aref = A; a.ldref = lda; a.rpart = partial;
     a.vec_a = 1; a.vec_b = 1;
     const int64_t total = (int64_t)a.tiles_m * a.tiles_n;
-    hipError_t e = launch_dma<8, true, kPrecF64>(sh.nt, dim3((unsigned)total), s, a);
+    hipError_t e = wm == 4 ? launch_dma<4, true, kPrecF64>(sh.nt, dim3((unsigned)total), s, a)
+                           : launch_dma<8, true, kPrecF64>(sh.nt, dim3((unsigned)total), s, a);
     if (e != hipSuccess) return RSVD_EHIP;
     rsvd_status r = sum_partials_into(total, partial, &st->resid2, s);
     if (r != RSVD_OK) return r;

@@ -25,6 +25,41 @@ rsvd_status resid(int64_t M, int64_t N, int64_t K, const double* US, int64_t ldu
                   const double* Vt, int64_t ldvt, const double* A, int64_t lda,
                   double* partial, DevState* st, hipStream_t s);
 
+// ---- BF16 early products from BF16 planes (bf16gemm.hip) ------------------
+// Plane layout: row-major uint16 BF16 bits, leading dimension a multiple of
+// 64, zero padded. Split schedule: a lo plane beside each hi plane.
+struct Bf16Shape {
+  int nt = 1, rw = 1, tiles_m = 1, tiles_n = 1, splits = 1;
+  int64_t Kp = 0, kchunk = 0, xt_rows = 0;
+  size_t part_floats = 0;
+};
+int64_t bf16_pad(int64_t k);
+// largest split count bf16_shape uses for M x N, and the partials it needs
+int bf16_split_cap(int64_t M, int64_t N);
+size_t bf16_part_floats_max(int64_t M, int64_t N);
+// rw: 16-row fragments per wave (1 or 2; 0 picks), splits: K ranges (0
+// picks, at most 16), groups: column groups (0 picks the fewest; at most
+// twice the fewest)
+Bf16Shape bf16_shape(int64_t M, int64_t N, int64_t K, bool split, int rw = 0, int splits = 0,
+                     int groups = 0);
+// the tuned shape of this product if the autotuner has one, else bf16_shape's
+Bf16Shape bf16_tuned_shape(int64_t M, int64_t N, int64_t K, bool split);
+// rows of XT any shape for N columns may use
+int64_t bf16_xt_rows_max(int64_t N);
+// Planes of X (R x C, FP64): same orientation into n_hi / n_lo (R x ld_n)
+// and / or transposed into t_hi / t_lo (rows_t x ld_t, t(c, r) = X(r, c)),
+// zero padded. Null hi pointers skip an orientation, null lo pointers the lo plane.
+rsvd_status bf16_planes(int64_t R, int64_t C, const double* X, int64_t ldx, uint16_t* n_hi,
+                        uint16_t* n_lo, int64_t ld_n, uint16_t* t_hi, uint16_t* t_lo, int64_t ld_t,
+                        int64_t rows_t, hipStream_t s);
+// C (M x N) = P X with P the A planes (M x sh.Kp, lda) and X given as XT
+// planes (sh.xt_rows x sh.Kp); split: hi*lo + lo*hi + hi*hi per term.
+// part: >= sh.part_floats floats when sh.splits > 1.
+rsvd_status bf16_gemm(const Bf16Shape& sh, int64_t M, int64_t N, const uint16_t* A_hi,
+                      const uint16_t* A_lo, int64_t lda, const uint16_t* XT_hi,
+                      const uint16_t* XT_lo, double* C, int64_t ldc, float* part,
+                      size_t part_floats, bool split, hipStream_t st);
+
 // ---- random projection (omega.hip) -----------------------------------------
 rsvd_status gaussian_omega(int64_t n, int64_t l, int64_t col0, uint64_t seed, uint64_t channel,
                            double* out, int64_t ldo, hipStream_t st);

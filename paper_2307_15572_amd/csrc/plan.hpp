@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "../../include/rsvd.h"
+#include "kernels.hpp"
 
 struct rsvd_plan_s {
   rsvd_problem p;
@@ -28,6 +29,14 @@ struct rsvd_plan_s {
   // device holds at once (runs sharing the device concurrently set it to
   // their number, so their grids are co-resident together)
   int coop_share = 1;
+  // BF16 schedules: planes of A (m x ld_an) and, for a non-symmetric A with
+  // a low-precision A^T product, of A^T (n x ld_at); XT planes of the panel
+  // (xt_rows x xt_ld); FP32 split-K partials of the BF16 products
+  bool bf16 = false, bf16_t = false, bf16_split = false;
+  int64_t ld_an = 0, ld_at = 0, xt_rows = 0, xt_ld = 0;
+  rsvd::Bf16Shape sh_n, sh_t;
+  size_t off_Ah = 0, off_Al = 0, off_Ath = 0, off_Atl = 0, off_XTh = 0, off_XTl = 0;
+  size_t off_fpart = 0, fpart_floats = 0;
   size_t part_doubles = 0;
   size_t total = 0;
 };

@@ -295,6 +295,36 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* worksp
     pl->off_Vt = c.take((size_t)n * kcp * D);
     pl->off_rpart = c.take(resid_partials(m, n) * D);
   }
+  // BF16 schedules: planes for the low-precision products
+  const int n_low = 2 * p.power_iters + 1 - p.trailing_hp;
+  if (!adaptive && n_low > 0 &&
+      (p.precision == RSVD_PREC_MIXED_BF16 || p.precision == RSVD_PREC_MIXED_BF16_SPLIT)) {
+    const size_t H = sizeof(uint16_t);
+    const int planes = p.precision == RSVD_PREC_MIXED_BF16_SPLIT ? 2 : 1;
+    pl->bf16 = true;
+    pl->bf16_split = planes == 2;
+    pl->bf16_t = !p.symmetric && n_low >= 2;  // products 1, 3, .. are A^T ones
+    pl->ld_an = bf16_pad(n);
+    pl->sh_n = bf16_shape(m, l, n, planes == 2);
+    size_t fpart = bf16_part_floats_max(m, l);
+    pl->xt_ld = pl->ld_an;
+    pl->off_Ah = c.take((size_t)m * pl->ld_an * H);
+    if (planes == 2) pl->off_Al = c.take((size_t)m * pl->ld_an * H);
+    if (pl->bf16_t) {
+      pl->ld_at = bf16_pad(m);
+      pl->sh_t = bf16_shape(n, l, m, planes == 2);
+      const size_t f2 = bf16_part_floats_max(n, l);
+      if (f2 > fpart) fpart = f2;
+      if (pl->ld_at > pl->xt_ld) pl->xt_ld = pl->ld_at;
+      pl->off_Ath = c.take((size_t)n * pl->ld_at * H);
+      if (planes == 2) pl->off_Atl = c.take((size_t)n * pl->ld_at * H);
+    }
+    pl->xt_rows = bf16_xt_rows_max(l);
+    pl->off_XTh = c.take((size_t)pl->xt_rows * pl->xt_ld * H);
+    if (planes == 2) pl->off_XTl = c.take((size_t)pl->xt_rows * pl->xt_ld * H);
+    pl->fpart_floats = fpart;
+    if (fpart) pl->off_fpart = c.take(fpart * sizeof(float));
+  }
   if (adaptive) {
     pl->off_Wb = c.take((size_t)m * blk * D);
     pl->off_Zb = c.take((size_t)n * blk * D);
@@ -580,11 +610,32 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
                    : p.precision == RSVD_PREC_MIXED_BF16_SPLIT ? kPrecBF16S
                                                                : kPrecF64;
   int product = 0;
+  uint16_t* Ah = pl.bf16 ? w.at<uint16_t>(pl.off_Ah) : nullptr;
+  uint16_t* Al = pl.bf16_split ? w.at<uint16_t>(pl.off_Al) : nullptr;
+  uint16_t* Ath = pl.bf16_t ? w.at<uint16_t>(pl.off_Ath) : nullptr;
+  uint16_t* Atl = pl.bf16_t && pl.bf16_split ? w.at<uint16_t>(pl.off_Atl) : nullptr;
+  uint16_t* XTh = pl.bf16 ? w.at<uint16_t>(pl.off_XTh) : nullptr;
+  uint16_t* XTl = pl.bf16_split ? w.at<uint16_t>(pl.off_XTl) : nullptr;
+  float* fpart = pl.fpart_floats ? w.at<float>(pl.off_fpart) : nullptr;
+  if (pl.bf16) {
+    // BF16 schedules: A rounded once into the planes its low-precision
+    // products stream (A for A X, and A^T for A^T X when A is not symmetric)
+    PhaseScope ph(7, s);
+    RSVD_TRY(bf16_planes(m, n, A, lda, Ah, Al, pl.ld_an, Ath, Atl, pl.ld_at, n, s));
+  }
   auto stream_pass = [&](bool trans, const double* X, int64_t ldx, double* out, int64_t rows_out,
                          int64_t inner) -> rsvd_status {
     PhaseScope ph(0, s);
     const int prec = product < n_early - p.trailing_hp ? lowp : kPrecF64;
     product++;
+    if (pl.bf16 && prec != kPrecF64) {
+      // X (inner x l) -> XT planes, then the product from the planes
+      const Bf16Shape sh = bf16_tuned_shape(rows_out, l, inner, pl.bf16_split);
+      RSVD_TRY(bf16_planes(inner, l, X, ldx, nullptr, nullptr, 0, XTh, XTl, sh.Kp, sh.xt_rows, s));
+      return bf16_gemm(sh, rows_out, l, trans ? Ath : Ah, trans ? Atl : Al,
+                       trans ? pl.ld_at : pl.ld_an, XTh, XTl, out, l, fpart, pl.fpart_floats,
+                       pl.bf16_split, s);
+    }
     return dgemm(trans, rows_out, l, inner, 1.0, A, lda, X, ldx, 0.0, out, l, part,
                  pl.part_doubles, s, 64, nullptr, prec);
   };
@@ -637,6 +688,65 @@ rsvd_status rsvd_gemm(int32_t precision, int32_t trans_a, int64_t m, int64_t n, 
                                                              : kPrecF64;
   return dgemm(trans_a != 0, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, (double*)work,
                work_bytes / sizeof(double), (hipStream_t)stream, 64, nullptr, prec);
+}
+
+namespace {
+// workspace of rsvd_bf16_gemm: A planes (m x Kp), XT planes, FP32 partials
+struct Bf16GemmLayout {
+  size_t off_a = 0, off_al = 0, off_x = 0, off_xl = 0, off_part = 0, total = 0;
+  int64_t Kp = 0, xt_rows = 0;
+  size_t part_floats = 0;
+  Bf16GemmLayout(int64_t m, int64_t n, int64_t k, bool split) {
+    Carver c;
+    Kp = bf16_pad(k);
+    xt_rows = bf16_xt_rows_max(n);
+    part_floats = bf16_part_floats_max(m, n);
+    const size_t H = sizeof(uint16_t);
+    off_a = c.take((size_t)m * Kp * H);
+    if (split) off_al = c.take((size_t)m * Kp * H);
+    off_x = c.take((size_t)xt_rows * Kp * H);
+    if (split) off_xl = c.take((size_t)xt_rows * Kp * H);
+    if (part_floats) off_part = c.take(part_floats * sizeof(float));
+    total = c.at;
+  }
+};
+}  // namespace
+
+size_t rsvd_bf16_gemm_work_bytes(int64_t m, int64_t n, int64_t k, int32_t split) {
+  if (m <= 0 || n <= 0 || k <= 0) return 0;
+  return Bf16GemmLayout(m, n, k, split != 0).total;
+}
+
+rsvd_status rsvd_bf16_gemm(int32_t split, int32_t trans_a, int64_t m, int64_t n, int64_t k,
+                           const double* A, int64_t lda, const double* B, int64_t ldb, double* C,
+                           int64_t ldc, void* work, size_t work_bytes, void* stream) {
+  if (m < 0 || n < 0 || k < 0) return RSVD_EINVAL;
+  if (m == 0 || n == 0) return RSVD_OK;
+  if (!C || ldc < n) return RSVD_EINVAL;
+  if (k == 0) return dgemm(false, m, n, 0, 1.0, nullptr, 1, nullptr, n, 0.0, C, ldc, nullptr, 0,
+                           (hipStream_t)stream);
+  if (!A || !B || ldb < n || (trans_a ? lda < m : lda < k)) return RSVD_EINVAL;
+  const Bf16GemmLayout lay(m, n, k, split != 0);
+  if (!work || work_bytes < lay.total) return RSVD_ENOMEM;
+  if (((uintptr_t)work & 255) != 0) return RSVD_EINVAL;
+  char* wb = (char*)work;
+  uint16_t* ah = (uint16_t*)(wb + lay.off_a);
+  uint16_t* al = split ? (uint16_t*)(wb + lay.off_al) : nullptr;
+  uint16_t* xh = (uint16_t*)(wb + lay.off_x);
+  uint16_t* xl = split ? (uint16_t*)(wb + lay.off_xl) : nullptr;
+  float* part = lay.part_floats ? (float*)(wb + lay.off_part) : nullptr;
+  hipStream_t s = (hipStream_t)stream;
+  const Bf16Shape sh = bf16_tuned_shape(m, n, k, split != 0);
+  rsvd_status r;
+  // op(A) planes (m x Kp): A itself, or the transpose of the k x m A
+  if (trans_a)
+    r = bf16_planes(k, m, A, lda, nullptr, nullptr, 0, ah, al, lay.Kp, m, s);
+  else
+    r = bf16_planes(m, k, A, lda, ah, al, lay.Kp, nullptr, nullptr, 0, 0, s);
+  if (r != RSVD_OK) return r;
+  if ((r = bf16_planes(k, n, B, ldb, nullptr, nullptr, 0, xh, xl, lay.Kp, sh.xt_rows, s)) != RSVD_OK)
+    return r;
+  return bf16_gemm(sh, m, n, ah, al, lay.Kp, xh, xl, C, ldc, part, lay.part_floats, split != 0, s);
 }
 
 size_t rsvd_dgemm_work_bytes(int64_t m, int64_t n, int64_t k, int32_t trans_a) {

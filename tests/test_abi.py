@@ -161,3 +161,21 @@ def test_batch_plan_validation():
         rs.BatchPlan(_batch_problems([100]) + [dict(m=10, n=0, k=2, p=1, q=0)])
     bp = rs.BatchPlan(_batch_problems([100, 50]), lanes=8)
     assert sorted(bp.lanes_of()) == [0, 1]  # lanes never exceed the channel count
+
+
+def test_tune_entry_points_without_device():
+    import ctypes
+    import paper_2307_15572_amd as rs
+    L = rs.lib()
+    rs.tune_clear()
+    assert L.rsvd_tune_entries(0, None, None, None) == 0
+    assert rs.tune_table() == []
+    n = ctypes.c_int32(-1)
+    # null plan / reps out of range: rejected before any device work
+    assert L.rsvd_tune(None, None, 0, None, 0, None, None, 0, None, 0, None, None, 0, 3,
+                       ctypes.byref(n), None) == 1
+    plan = rs.Plan(100, 80, 10, 5, 1)
+    assert L.rsvd_tune(plan._h, None, 0, None, 0, None, None, 0, None, 0, None, None, 0, 0,
+                       ctypes.byref(n), None) == 1
+    assert L.rsvd_batch_tune(None, None, None, None, None, None, None, None, None, None, 0, 3,
+                             ctypes.byref(n), None) == 1

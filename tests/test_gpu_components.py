@@ -163,3 +163,52 @@ def test_lowp_gemm_error_bound(prec, ta, m, n, k):
     # and it is not secretly FP64: the error is at the format's level
     if prec == "mixed_bf16" and k >= 1000:
         assert np.abs(got - ref).max() > 1e3 * 2.0 ** -53 * np.abs(ref).max()
+
+
+def _bf16(x):
+    """Round to BF16 as the planes do: FP64 -> FP32 (nearest even), then the
+    upper 16 bits of the FP32 word, nearest even on the dropped half."""
+    f = np.ascontiguousarray(x, dtype=np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+# (trans_a, m, n, k): row tiles of 128 and 256 rows with ragged tails, one and
+# several column groups, k padded to 64, split K with FP32 partials
+BF16_PLANE_CASES = [
+    (False, 517, 272, 1000), (False, 2048, 272, 8192), (True, 300, 100, 2000), (False, 33, 18, 16),
+    (False, 1, 1, 1), (False, 129, 17, 65), (False, 5000, 528, 3000), (True, 2048, 8, 20000),
+    (False, 2600, 300, 700), (True, 1000, 33, 999),
+]
+
+
+@pytest.mark.parametrize("split", [False, True])
+@pytest.mark.parametrize("ta,m,n,k", BF16_PLANE_CASES)
+def test_bf16_planes_gemm(split, ta, m, n, k):
+    # the rounded operands multiply exactly in FP32; the only error left is
+    # the FP32 accumulation: |C - P X| <= (k + 2) u32 (|P| |X|) per entry,
+    # P, X the BF16 operands (split: hi hi + hi lo + lo hi, lo lo dropped)
+    import paper_2307_15572_amd as rs
+    announce(f"bf16 planes gemm split={split} ta={ta} m={m} n={n} k={k}")
+    rng = np.random.default_rng(11 * m + 5 * n + k + split)
+    A = rng.standard_normal((k, m) if ta else (m, k))
+    B = rng.standard_normal((k, n))
+    opA = A.T if ta else A
+    got = rs.bf16_gemm(to_dev(A), to_dev(B), trans_a=ta, split=split).cpu().numpy()
+    ah, bh = _bf16(opA), _bf16(B)
+    if split:
+        al, bl = _bf16(opA - ah), _bf16(B - bh)
+        ref = ah @ bh + ah @ bl + al @ bh
+        mag = np.abs(ah) @ np.abs(bh) + np.abs(ah) @ np.abs(bl) + np.abs(al) @ np.abs(bh)
+        terms = 3 * k
+    else:
+        ref = ah @ bh
+        mag = np.abs(ah) @ np.abs(bh)
+        terms = k
+    u32 = 2.0 ** -24
+    assert np.all(np.abs(got - ref) <= (terms + 2) * u32 * mag)
+    # and the operand rounding is the format's: against the FP64 product
+    exact = opA @ B
+    u_in = 2.0 ** -15 if split else 2.0 ** -8
+    assert np.all(np.abs(got - exact) <= (2 * u_in + (terms + 2) * u32) * (np.abs(opA) @ np.abs(B)))
