@@ -15,9 +15,13 @@ dominant kernel (the streaming FP64 GEMM, MFMA-bound: intensity l/4 flop per
 byte is far above the FP64 ridge of ~9.8 flop/byte); its average duration comes
 from HIP events recorded around each streaming pass on the run's stream.
 
+Every plan's product tilings come from the autotuner (rsvd_tune /
+rsvd_batch_tune), run before its timed region; the tuned table is reported.
+
 Also reported (same JSON line): the mixed-precision schedules on the same
-matrix ("mixed": FP32 and BF16 early products, speed-up over FP64 and the
-singular-value error against the FP64 run) and a 96-channel threshold batch
+matrix ("mixed": FP32 and BF16 early products, speed-up over FP64, the
+singular-value error against the FP64 run, and the rate of the BF16 plane
+products against HBM and BF16 matrix-core peaks) and a 96-channel threshold batch
 ("batch": the batch planner's concurrent lanes with graph replay against the
 same channels run one after another) and the 131072 x 8192 tall matrix
 ("tall": FP64, FP32 and BF16 schedules with each result's error against the
@@ -39,6 +43,7 @@ if ROOT not in sys.path:
 METRIC = "rSVD matrix GB/s + % HBM/MFMA roofline, mixed vs FP64 at 1e-6 rel σ error"
 PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (vector = matrix)
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
+PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 matrix
 
 # HBM bytes per launch of the streaming product, from rocprofv3 --pmc FETCH_SIZE
 # and WRITE_SIZE runs of this benchmark (profiles/rsvd_fp64_16384sq_symmetric_traffic.md).
@@ -102,6 +107,9 @@ def batch_leg(dev, reps=2):
             pp.append(d)
         bp = rs.BatchPlan(pp, lanes=lanes, use_graph=graph)
         bufs = bp.allocate(dev)
+        tt = time.perf_counter()
+        ntuned = bp.tune(mats, bufs, reps=1)
+        tune_s = time.perf_counter() - tt
         bp.run_into(mats, bufs)
         bp.results(bufs)
         e0 = torch.cuda.Event(enable_timing=True)
@@ -123,6 +131,7 @@ def batch_leg(dev, reps=2):
         legs[name] = {"ms": round(ms, 2), "value": round(bytes_streamed / (ms * 1e-3) / 1e9, 3),
                       "unit": "GB/s", "graph_replayed": bp.graph_used(),
                       "ranks_off_threshold_count": bad,
+                      "autotune": {"shapes_added": int(ntuned), "seconds": round(tune_s, 2)},
                       "max_rel_sigma_err_vs_constructed": worst}
         log(f"batch {name}: {ms:.1f} ms, {legs[name]['value']} GB/s")
         del bufs, bp
@@ -170,6 +179,7 @@ def tall_leg(dev, reps=2):
         bufs = plan.allocate(dev)
         plan.run_into(A, bufs)
         plan.result(bufs)
+        plan.tune(A, bufs, reps=1)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
@@ -251,7 +261,11 @@ def main():
     for _ in range(args.warmup):
         plan.run_into(A, bufs)
     torch.cuda.synchronize()
-    log("warmup done")
+    # tile shapes of every product from the autotuner (outside the timed region)
+    t0 = time.perf_counter()
+    tuned = plan.tune(A, bufs, reps=3)
+    tune_s = time.perf_counter() - t0
+    log(f"warmup done; autotuner added {tuned} shapes in {tune_s:.2f} s")
 
     rs.trace_enable(True)
     rs.trace_collect()  # clear
@@ -285,12 +299,15 @@ def main():
     src = os.path.join(ROOT, "paper_2307_15572_amd", "csrc", "gemm.hip")
     same = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] == TRAFFIC_SOURCE_SHA256
     traffic = round(TRAFFIC_FETCH_BYTES + TRAFFIC_WRITE_BYTES) if same else None
+    main_shape = next((e for e in rs.tune_table() if e["kind"] == "fp64_stream" and e["M"] == w.m
+                       and e["N"] == l and e["K"] == w.n), None)
     roofline = {
         "bound": "mfma", "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
         "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "traffic": traffic,
         "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
         "algorithmic_bytes": 8.0 * w.m * w.n + 8.0 * (w.n + w.m) * l,
-        "kernel": "dgemm_nn_dma_kernel<NT=17, 8 waves, FP64> (A x 272-column panel, LDS-DMA pipeline)",
+        "kernel": "dgemm_nn_dma_kernel<NT=17, FP64> (A x 272-column panel, LDS-DMA pipeline)",
+        "tuned_shape": main_shape,
         "flops_per_launch": flops_per_launch, "avg_ms": round(gemm_avg_s * 1e3, 4),
         "launches": int(gemm_cnt),
     }
@@ -308,6 +325,7 @@ def main():
         "roofline": roofline,
         "step_fraction_of_mfma_floor": round(step_roof_ms / ms_step, 4),
         "phases_ms_per_step": {kk: round(v[0] / args.steps, 4) for kk, v in phases.items()},
+        "autotune": {"shapes_added": int(tuned), "seconds": round(tune_s, 3)},
         "result": {"rank": int(res.rank), "residual": res.residual, "sweeps": int(res.sweeps),
                    "flags": int(res.flags)},
     }
@@ -319,13 +337,16 @@ def main():
     sig_c2 = sigma
     jc2 = int(np.max(np.nonzero((sig_c2[l_c2] / sig_c2[: w.k]) ** (2 * w.q + 1) <= 1e-8)))
     for prec, thp in (("mixed_fp32", 1), ("mixed_bf16", 1), ("mixed_bf16", 2),
-                      ("mixed_bf16_split", 1)):
+                      ("mixed_bf16_split", 1), ("mixed_bf16_split", 2)):
         mplan = rs.Plan(w.m, w.n, k, p, q, symmetric=w.symmetric, seed=w.seed, want_residual=True,
                         precision=prec, trailing_hp=thp)
         mb = mplan.allocate(dev)
         for _ in range(args.warmup):
             mplan.run_into(A, mb)
+        mplan.tune(A, mb, reps=3)
         torch.cuda.synchronize()
+        rs.trace_enable(True)
+        rs.trace_collect()
         f0 = torch.cuda.Event(enable_timing=True)
         f1 = torch.cuda.Event(enable_timing=True)
         f0.record(stream)
@@ -333,6 +354,8 @@ def main():
             mplan.run_into(A, mb)
         f1.record(stream)
         torch.cuda.synchronize()
+        rs.trace_enable(False)
+        mph = rs.trace_collect()
         mms = f0.elapsed_time(f1) / args.steps
         mres = mplan.result(mb)
         s64 = bufs["S"][: res.rank].cpu().numpy()
@@ -349,10 +372,27 @@ def main():
             "max_rel_sigma_err_vs_fp64_converged": float(relv[: jc2 + 1].max()),
             "fp64_converged_indices": f"0..{jc2}",
             "residual": mres.residual,
+            "phases_ms_per_step": {kk: round(v[0] / args.steps, 4) for kk, v in mph.items() if v[1]},
         }
+        bms, bcnt = mph["bf16_gemm"]
+        if bcnt:
+            # BF16 plane product (panel planes + product + split-K sum), per launch:
+            # algorithmic bytes = A planes (2 bytes per plane and entry) + the
+            # FP64 panel in + the FP64 result out; flops = 2 m n l per BF16 product
+            planes = 2 if prec == "mixed_bf16_split" else 1
+            avg_s = bms / bcnt * 1e-3
+            byts = 2.0 * planes * w.m * w.n + 8.0 * (w.n + w.m) * l
+            fl = 2.0 * w.m * w.n * l * (3 if planes == 2 else 1)
+            mixed[f"{prec}_thp{thp}"]["bf16_product"] = {
+                "launches_per_step": bcnt // args.steps, "avg_ms": round(avg_s * 1e3, 4),
+                "algorithmic_bytes": byts, "GBs": round(byts / avg_s / 1e9, 1),
+                "frac_hbm": round(byts / avg_s / 1e9 / PEAK_HBM_GBS, 4),
+                "TFLOPs": round(fl / avg_s / 1e12, 1),
+                "frac_mfma_bf16": round(fl / avg_s / 1e12 / PEAK_BF16_TFLOPS, 4)}
         del mb, mplan
         log(f"{prec} thp={thp}: {mms:.3f} ms/step, max rel sigma err vs FP64 {rel:.2e}")
     out["mixed"] = mixed
+    out["autotune"]["table"] = rs.tune_table()
 
     if not args.no_batch:
         torch.cuda.empty_cache()

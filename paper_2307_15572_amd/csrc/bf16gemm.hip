@@ -15,15 +15,14 @@
 //
 // Kernel (8 waves per workgroup, wave64): a wave owns RW fragments of 16
 // rows; the workgroup covers 128 RW rows and NT column tiles of 16. K goes in
-// chunks of 64. Per chunk each lane loads the 32 bytes A[row][k + 16 g ..
-// k + 16 g + 15] (g = lane / 16) of each of its rows straight into registers,
-// one chunk ahead; the chunk of XT for all column tiles is copied HBM/L2 ->
-// LDS with global_load_lds_dwordx4 (no staging registers, two LDS stages,
-// one chunk ahead) and shared by the 8 waves. The 16 k values of a lane feed
-// two v_mfma_f32_16x16x32_bf16: the k values a lane contributes to one MFMA
-// need not be adjacent, only the same for both operands. XT rows are stored
-// in LDS with the 16-byte pieces of row c permuted by c & 7 (conflict-free
-// reads of 8 rows at a time). Accumulation in FP32; split K writes FP32
+// chunks of 64, two v_mfma_f32_16x16x32_bf16 k-steps: for step h each lane
+// loads A[row][k + 32 h + 8 g .. + 7] (g = lane / 16; 64 contiguous bytes of
+// a row per load instruction) straight into a register ring, 1 to 3 chunks
+// ahead (as registers allow); the chunk of XT for all column tiles is copied
+// HBM/L2 -> LDS with global_load_lds_dwordx4 (no staging registers, two LDS
+// stages, one chunk ahead) and shared by the 8 waves. XT rows are stored in LDS with the
+// 16-byte pieces of row c permuted by c & 7 (conflict-free reads of 8 rows
+// at a time). Accumulation in FP32; split K writes FP32
 // partials (exact copies of the accumulators) that a second kernel sums in
 // split order in FP64. Split schedule per term: hi*lo + lo*hi + hi*hi.
 #include "common.hpp"
@@ -39,9 +38,12 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 constexpr int kKC = 64;      // k per chunk (two MFMA k-steps per lane)
 constexpr int kWavesB = 8;   // waves per workgroup
 constexpr int kMaxNT = 17;   // column tiles per workgroup
-// split schedule with two fragments per wave: beyond 14 tiles the
-// accumulators and operands exceed 256 VGPRs
-constexpr int kMaxNTSplit2 = 14;
+// column tiles with two fragments per wave: beyond these the accumulators,
+// the A ring and the operands exceed 256 VGPRs
+constexpr int kMaxNT2 = 16;
+constexpr int kMaxNTSplit2 = 11;
+
+inline int max_nt(int rw, bool split) { return rw == 1 ? kMaxNT : (split ? kMaxNTSplit2 : kMaxNT2); }
 
 __device__ __forceinline__ f4 mfma_bf16_32(bf8 a, bf8 b, f4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
@@ -105,6 +107,42 @@ __global__ void __launch_bounds__(256) bf16_planes_kernel(
   }
 }
 
+// Same-orientation planes only (no transpose): each thread rounds 8
+// consecutive entries of a row, 64 bytes in (four 16-byte loads when the row
+// allows) and 16 bytes out per plane.
+__global__ void __launch_bounds__(256) bf16_planes_n_kernel(int64_t R, int64_t C,
+                                                            const double* __restrict__ X,
+                                                            int64_t ldx, bool vec,
+                                                            uint16_t* __restrict__ n_hi,
+                                                            uint16_t* __restrict__ n_lo,
+                                                            int64_t ld_n) {
+  const int64_t per_row = ld_n / 8;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= R * per_row) return;
+  const int64_t r = idx / per_row, c = (idx % per_row) * 8;
+  const double* src = X + r * ldx + c;
+  double x[8];
+  if (vec && c + 8 <= C) {
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const double2 v = reinterpret_cast<const double2*>(src)[j];
+      x[2 * j] = v.x;
+      x[2 * j + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < 8; j++) x[j] = c + j < C ? src[j] : 0.0;
+  }
+  uint16_t h[8], w[8];
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    h[j] = to_bf16(x[j]);
+    w[j] = to_bf16(x[j] - bf16_value((short)h[j]));
+  }
+  *reinterpret_cast<uint4*>(n_hi + r * ld_n + c) = *reinterpret_cast<const uint4*>(h);
+  if (n_lo) *reinterpret_cast<uint4*>(n_lo + r * ld_n + c) = *reinterpret_cast<const uint4*>(w);
+}
+
 struct Bf16Args {
   int64_t M, N, Kp, kchunk;
   const uint16_t* A;   // hi plane of the left operand (M x Kp, lda)
@@ -149,9 +187,9 @@ __global__ void __launch_bounds__(64 * kWavesB) bf16_stream_kernel(Bf16Args g) {
   const int64_t col0 = (int64_t)tn * (NT * 16);
 
   // A: rows past M read row M - 1 (never stored)
-  const uint16_t* asrc[RW];
+  const uint16_t* abase[RW];
 #pragma unroll
-  for (int f = 0; f < RW; f++) asrc[f] = g.A + min(row0 + 16 * f + r, g.M - 1) * g.lda + kb + 16 * gq;
+  for (int f = 0; f < RW; f++) abase[f] = g.A + min(row0 + 16 * f + r, g.M - 1) * g.lda + kb + 8 * gq;
   // XT copy q = wave + 8 i: lane -> slot 64 q + lane, i.e. row c = 8 q + lane / 8
   // (c & 7 = lane / 8), slot position lane & 7 holding piece (lane & 7) ^ (lane / 8)
   const uint16_t* bsrc = g.B + (col0 + 8 * wave + (lane >> 3)) * g.ldb + kb +
@@ -170,16 +208,18 @@ __global__ void __launch_bounds__(64 * kWavesB) bf16_stream_kernel(Bf16Args g) {
     }
     bsrc += kKC;
   };
-  auto load_a = [&](bf8 (&a)[RW][PL][2]) {
+  // chunk indices past the last are clamped to it: the loads stay
+  // unconditional (their count is what the wait counts below rely on)
+  auto load_a = [&](bf8 (&a)[RW][PL][2], int chunk) {
+    const int64_t off = (int64_t)min(chunk, nk - 1) * kKC;
 #pragma unroll
     for (int f = 0; f < RW; f++) {
 #pragma unroll
       for (int pl = 0; pl < PL; pl++) {
-        const bf8* p = reinterpret_cast<const bf8*>(asrc[f] + pl * g.a_lo);
-        a[f][pl][0] = p[0];
-        a[f][pl][1] = p[1];
+        const uint16_t* p = abase[f] + pl * g.a_lo + off;
+        a[f][pl][0] = *reinterpret_cast<const bf8*>(p);
+        a[f][pl][1] = *reinterpret_cast<const bf8*>(p + 32);
       }
-      asrc[f] += kKC;
     }
   };
 
@@ -194,7 +234,7 @@ __global__ void __launch_bounds__(64 * kWavesB) bf16_stream_kernel(Bf16Args g) {
     for (int h = 0; h < 2; h++) {
 #pragma unroll
       for (int t = 0; t < NT; t++) {
-        const int slot = (16 * t + r) * 8 + ((2 * gq + h) ^ (r & 7));
+        const int slot = (16 * t + r) * 8 + ((4 * h + gq) ^ (r & 7));
         const bf8 bh = Bs[stage][0][slot];
         if constexpr (SPLIT) {
           const bf8 bl = Bs[stage][PL - 1][slot];
@@ -211,33 +251,47 @@ __global__ void __launch_bounds__(64 * kWavesB) bf16_stream_kernel(Bf16Args g) {
       }
     }
   };
-  // all copies of the chunk landed (own: vmcnt 0; others: the barrier), and
-  // every wave is done with the stage the next copies overwrite
-  auto sync = [&]() {
-    wait_vmcnt<0>();
+  // A runs DA chunks ahead in a register ring, XT one chunk ahead in two LDS
+  // stages. Issue order: A(0 .. DA-2), XT(0), A(DA-1), then per chunk c
+  // XT(c+1), A(c+DA); so when chunk c starts only A(c+DA-1) was issued after
+  // XT(c), and waiting for all but those NA loads (in-order counter) lands
+  // XT(c) and A(c) (DA >= 2; with DA = 1 everything). Compiler barriers on
+  // both sides of the wait keep the loads where this count assumes them; the
+  // wait also drains this wave's LDS reads, so after the barrier no wave
+  // still reads the stage the next copies overwrite. Whole groups of DA + 1
+  // chunks run with unconditional loads; the last partial group issues no A
+  // loads (they would be past the end, and dead) and waits for everything.
+  constexpr int DA = RW == 1 ? (SPLIT ? 2 : 3) : (SPLIT ? 1 : 2);
+  constexpr int NA = RW * PL * 2;  // A load instructions per chunk
+  bf8 ring[DA + 1][RW][PL][2];
+  auto begin_chunk = [&](int c, bool tail) {
+    asm volatile("" ::: "memory");
+    if (DA >= 2 && !tail)
+      wait_vm_lgkm<NA, 0>();
+    else
+      wait_vm_lgkm<0, 0>();
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
+    if (c + 1 < nk) issue_b((c + 1) & 1);
   };
-
-  bf8 a0[RW][PL][2], a1[RW][PL][2];
-  if (nk > 0) {
-    issue_b(0);
-    load_a(a0);
-  }
-  for (int c = 0; c < nk; c += 2) {
-    sync();
-    if (c + 1 < nk) {
-      issue_b(1);
-      load_a(a1);
+#pragma unroll
+  for (int i = 0; i + 1 < DA; i++) load_a(ring[i], i);
+  issue_b(0);
+  load_a(ring[DA - 1], DA - 1);
+  int c0 = 0;
+  for (; c0 + DA + 1 <= nk; c0 += DA + 1) {
+#pragma unroll
+    for (int i = 0; i <= DA; i++) {
+      begin_chunk(c0 + i, false);
+      load_a(ring[(i + DA) % (DA + 1)], c0 + i + DA);
+      compute((c0 + i) & 1, ring[i]);
     }
-    compute(0, a0);
-    if (c + 1 < nk) {
-      sync();
-      if (c + 2 < nk) {
-        issue_b(0);
-        load_a(a0);
-      }
-      compute(1, a1);
+  }
+#pragma unroll
+  for (int i = 0; i < DA; i++) {
+    if (c0 + i < nk) {
+      begin_chunk(c0 + i, true);
+      compute((c0 + i) & 1, ring[i]);
     }
   }
 
@@ -316,10 +370,11 @@ Bf16Shape bf16_shape(int64_t M, int64_t N, int64_t K, bool split, int rw, int sp
   s.tiles_n = (int)tn;
   s.nt = (int)((ntiles + tn - 1) / tn);  // balanced column groups
   s.rw = rw == 1 || rw == 2 ? rw : (M >= 2048 ? 2 : 1);
-  if (split && s.rw == 2 && s.nt > kMaxNTSplit2) {
+  const int cap_nt = max_nt(s.rw, split);
+  if (s.nt > cap_nt) {
     if (rw == 2) {
       // keep two fragments per wave: more column groups
-      tn = (ntiles + kMaxNTSplit2 - 1) / kMaxNTSplit2;
+      tn = (ntiles + cap_nt - 1) / cap_nt;
       s.tiles_n = (int)tn;
       s.nt = (int)((ntiles + tn - 1) / tn);
     } else {
@@ -368,7 +423,14 @@ rsvd_status bf16_planes(int64_t R, int64_t C, const double* X, int64_t ldx, uint
   if (R <= 0 || C <= 0 || (!n_hi && !t_hi)) return RSVD_OK;
   if ((n_hi && (ld_n % 64 != 0 || ld_n < C)) || (t_hi && (ld_t % 64 != 0 || ld_t < R || rows_t < C)))
     return RSVD_EINVAL;
-  const int64_t cx = n_hi ? (t_hi ? (ld_n > rows_t ? ld_n : rows_t) : ld_n) : rows_t;
+  if (!t_hi) {
+    const bool vec = (ldx % 2 == 0) && ((uintptr_t)X % 16 == 0);
+    hipLaunchKernelGGL(bf16_planes_n_kernel, dim3(blocks_of(R * (ld_n / 8), 256)), dim3(256), 0, s,
+                       R, C, X, ldx, vec, n_hi, n_lo, ld_n);
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
+  }
+  const int64_t cx = n_hi ? (ld_n > rows_t ? ld_n : rows_t) : rows_t;
   const int64_t rx = t_hi ? (ld_t > R ? ld_t : R) : R;
   const dim3 grid(blocks_of(cx, 64), blocks_of(rx, 64));
   if (grid.y > 65535) return RSVD_EUNSUPPORTED;
@@ -408,7 +470,7 @@ rsvd_status bf16_gemm(const Bf16Shape& sh, int64_t M, int64_t N, const uint16_t*
     });
   }
   if (sh.nt < 1 || sh.nt > kMaxNT || (sh.rw != 1 && sh.rw != 2)) return RSVD_EINVAL;
-  if (split && sh.rw == 2 && sh.nt > kMaxNTSplit2) return RSVD_EINVAL;
+  if (sh.nt > max_nt(sh.rw, split)) return RSVD_EINVAL;
   if (lda < sh.Kp || lda % 8 != 0 || (int64_t)sh.nt * sh.tiles_n * 16 < N) return RSVD_EINVAL;
   if (split && (!A_lo || !XT_lo)) return RSVD_EINVAL;
   if (sh.splits > 1 && (!part || part_floats < sh.part_floats)) return RSVD_EINVAL;

@@ -73,6 +73,13 @@ __device__ __forceinline__ void wait_vmcnt() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (15 << 8));
 }
 
+// s_waitcnt vmcnt(N) lgkmcnt(L)
+template <int N, int L>
+__device__ __forceinline__ void wait_vm_lgkm() {
+  static_assert(N >= 0 && N < 64 && L >= 0 && L < 16, "counter range");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | (7 << 4) | (L << 8));
+}
+
 
 // ---- wave reductions --------------------------------------------------------
 __device__ __forceinline__ double wave_sum(double v) {

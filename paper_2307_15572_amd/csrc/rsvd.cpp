@@ -625,9 +625,9 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
   }
   auto stream_pass = [&](bool trans, const double* X, int64_t ldx, double* out, int64_t rows_out,
                          int64_t inner) -> rsvd_status {
-    PhaseScope ph(0, s);
     const int prec = product < n_early - p.trailing_hp ? lowp : kPrecF64;
     product++;
+    PhaseScope ph(pl.bf16 && prec != kPrecF64 ? 8 : 0, s);
     if (pl.bf16 && prec != kPrecF64) {
       // X (inner x l) -> XT planes, then the product from the planes
       const Bf16Shape sh = bf16_tuned_shape(rows_out, l, inner, pl.bf16_split);
