@@ -386,9 +386,22 @@ __global__ void __launch_bounds__(64 * WM) dgemm_nn_dma_kernel(GemmArgs g) {
   int b = blockIdx.x;
   int item = b;
   if (b < full) item = (b & 7) * (full >> 3) + (b >> 3);
-  const int tn = item % g.tiles_n;
-  const int tm = (item / g.tiles_n) % g.tiles_m;
+  int tn = item % g.tiles_n;
+  int tm = (item / g.tiles_n) % g.tiles_m;
   const int z = item / (g.tiles_n * g.tiles_m);
+  if constexpr (RES) {
+    // the residual pass has many column tiles, each with its own slice of
+    // B = V^T: consecutive items walk the row tiles of a group of kResCols
+    // column tiles, so the workgroups running together on an XCD share a few
+    // slices of both operands in its L2 (one row tile across all column
+    // tiles would fetch every B slice again per row tile)
+    constexpr int kResCols = 4;
+    const int grp = item / (kResCols * g.tiles_m);
+    const int cols = min(kResCols, g.tiles_n - grp * kResCols);
+    const int idx = item - grp * kResCols * g.tiles_m;
+    tm = idx / cols;
+    tn = grp * kResCols + idx % cols;
+  }
   const int64_t kb = (int64_t)z * g.kchunk;
   const int64_t ke = min(g.K, kb + g.kchunk);
   const int nk = (int)((ke - kb) / kBK);
