@@ -401,7 +401,11 @@ rsvd_status rsvd_small_svd(int64_t l, const double* R, double* s, double* Us, do
  * 100 kind + 10 arithmetic + transposed; mnk[3i..3i+2] = M, N, K; cfg[3i..]
  * = the tiling: waves / rows per wave, K splits, column groups) into host
  * arrays (each may be NULL) and returns the number of entries;
- * rsvd_tune_clear empties the table.
+ * rsvd_tune_clear empties the table. rsvd_tune_set pins the tiling of one
+ * key (kind 0 FP64 streaming, 1 register-staged, 2 residual, 3 BF16 plane
+ * product; arith 0 FP64, 1 FP32, 2 BF16, 3 split BF16; a, b, c as in
+ * rsvd_tune_entries): RSVD_EINVAL for values out of range; a launch falls
+ * back to its heuristic when the pinned tiling does not fit its scratch.
  */
 rsvd_status rsvd_tune(rsvd_plan_t plan, const double* A, int64_t lda, const double* omega,
                       int64_t ldo, double* S, double* U, int64_t ldu, double* V, int64_t ldv,
@@ -414,6 +418,8 @@ rsvd_status rsvd_batch_tune(rsvd_batch_t plan, const double* const* A, const int
                             void* stream);
 int64_t rsvd_tune_entries(int64_t max, int32_t* kind, int64_t* mnk, int32_t* cfg);
 void rsvd_tune_clear(void);
+rsvd_status rsvd_tune_set(int32_t kind, int32_t arith, int32_t trans, int64_t M, int64_t N,
+                          int64_t K, int32_t a, int32_t b, int32_t c);
 
 /*
  * Phase trace (measurement aid). When enabled, rsvd_run records a HIP event

@@ -35,7 +35,7 @@ EXPORTED = (
     "rsvd_batch_plan", "rsvd_batch_run", "rsvd_batch_info", "rsvd_batch_destroy",
     "rsvd_mlp_init", "rsvd_mlp_forward", "rsvd_mlp_grad", "rsvd_mlp_train_step",
     "rsvd_pilot_work_bytes", "rsvd_pilot_features",
-    "rsvd_tune", "rsvd_batch_tune", "rsvd_tune_entries", "rsvd_tune_clear",
+    "rsvd_tune", "rsvd_batch_tune", "rsvd_tune_entries", "rsvd_tune_clear", "rsvd_tune_set",
 )
 MLP_PARAMS, MLP_IN, MLP_OUT, MLP_MAX_BATCH, PILOT_COLS = 5443, 16, 3, 128, 32
 TRACE_PHASES = ("stream_gemm", "qr", "small_svd", "lift_signs", "residual", "omega", "other",
@@ -133,6 +133,8 @@ def lib():
     L.rsvd_tune_entries.restype = i64
     L.rsvd_tune_clear.argtypes = []
     L.rsvd_tune_clear.restype = None
+    L.rsvd_tune_set.argtypes = [i32, i32, i32, i64, i64, i64, i32, i32, i32]
+    L.rsvd_tune_set.restype = ctypes.c_int
     L.rsvd_batch_info.argtypes = [vp, pp(i32), pp(i32)]
     L.rsvd_batch_info.restype = ctypes.c_int
     L.rsvd_batch_destroy.argtypes = [vp]
@@ -542,6 +544,23 @@ def tune_table():
 def tune_clear():
     """Empty the autotuner's table (later products use the heuristics)."""
     lib().rsvd_tune_clear()
+
+
+def tune_set(kind, M, N, K, arith=0, trans=0, **tiling):
+    """Pin the tiling of one product key. kind: "fp64_stream", "generic",
+    "residual" or "bf16_planes"; tiling keywords as tune_table() reports them
+    (waves, splits, rows_per_wave, column_groups)."""
+    kinds = {v: k for k, v in TUNE_KINDS.items()}
+    kd = kinds[kind]
+    if kind == "bf16_planes":
+        a, b, c = tiling["rows_per_wave"] // 16, tiling.get("splits", 1), tiling.get("column_groups", 0)
+    elif kind == "generic":
+        a, b, c = 0, tiling["splits"], 0
+    elif kind == "residual":
+        a, b, c = tiling["waves"], 0, 0
+    else:
+        a, b, c = tiling["waves"], tiling.get("splits", 1), 0
+    _check(lib().rsvd_tune_set(kd, int(arith), int(trans), M, N, K, a, b, c), "rsvd_tune_set")
 
 
 def orth(Y):

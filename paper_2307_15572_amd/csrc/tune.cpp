@@ -215,6 +215,33 @@ int64_t rsvd_tune_entries(int64_t max, int32_t* kind, int64_t* mnk, int32_t* cfg
   return i;
 }
 
+rsvd_status rsvd_tune_set(int32_t kind, int32_t arith, int32_t trans, int64_t M, int64_t N,
+                          int64_t K, int32_t a, int32_t b, int32_t c) {
+  if (kind < kTuneDma || kind > kTuneBf16 || arith < 0 || arith > 3 || (trans != 0 && trans != 1) ||
+      M < 1 || N < 1 || K < 1)
+    return RSVD_EINVAL;
+  // the launch sites validate a tiling against the call's scratch and fall
+  // back to their heuristic when it does not fit; here only the ranges
+  if ((kind == kTuneDma && (a != 4 && a != 8)) || (kind == kTuneResid && (a != 4 && a != 8)) ||
+      (kind == kTuneBf16 && (a != 1 && a != 2)) || b < 0 || b > 64 || c < 0 || c > 1024)
+    return RSVD_EINVAL;
+  TuneKey k;
+  k.kind = kind;
+  k.prec = arith;
+  k.ta = trans;
+  k.M = M;
+  k.N = N;
+  k.K = kind == kTuneBf16 ? bf16_pad(K) : K;
+  TuneCfg cfg;
+  cfg.a = a;
+  cfg.b = b;
+  cfg.c = c;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_table[k] = cfg;
+  g_gen++;
+  return RSVD_OK;
+}
+
 void rsvd_tune_clear(void) {
   std::lock_guard<std::mutex> lk(g_mu);
   g_table.clear();

@@ -32,3 +32,12 @@ def match_columns_up_to_sign(X, Xref, tol):
         d2 = np.abs(X[:, j] + Xref[:, j]).max()
         worst = max(worst, min(d1, d2))
     return worst <= tol, worst
+
+
+def bf16_round(x):
+    """Round to BF16 as the planes do: FP64 -> FP32 (nearest even), then the
+    upper 16 bits of the FP32 word, nearest even on the dropped half."""
+    f = np.ascontiguousarray(x, dtype=np.float64).astype(np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)

@@ -179,3 +179,39 @@ def test_tune_entry_points_without_device():
                        ctypes.byref(n), None) == 1
     assert L.rsvd_batch_tune(None, None, None, None, None, None, None, None, None, None, 0, 3,
                              ctypes.byref(n), None) == 1
+
+
+def test_tune_set_pins_and_rejects_without_device():
+    import paper_2307_15572_amd as rs
+    L = rs.lib()
+    rs.tune_clear()
+    try:
+        # out of range: kind, arithmetic, transposition, sizes, tiling
+        assert L.rsvd_tune_set(4, 0, 0, 10, 10, 10, 4, 1, 0) == 1
+        assert L.rsvd_tune_set(0, 4, 0, 10, 10, 10, 4, 1, 0) == 1
+        assert L.rsvd_tune_set(0, 0, 2, 10, 10, 10, 4, 1, 0) == 1
+        assert L.rsvd_tune_set(0, 0, 0, 0, 10, 10, 4, 1, 0) == 1
+        assert L.rsvd_tune_set(0, 0, 0, 10, 10, 10, 6, 1, 0) == 1
+        assert L.rsvd_tune_set(2, 0, 0, 10, 10, 10, 2, 0, 0) == 1
+        assert L.rsvd_tune_set(3, 2, 0, 10, 10, 10, 3, 1, 0) == 1
+        assert L.rsvd_tune_set(3, 2, 0, 10, 10, 10, 1, 65, 0) == 1
+        assert rs.tune_table() == []
+        rs.tune_set("fp64_stream", 1000, 272, 5000, waves=4, splits=2)
+        rs.tune_set("residual", 1000, 272, 5000, waves=8)
+        # the BF16 key holds K padded to the 64-wide plane rows
+        rs.tune_set("bf16_planes", 1000, 272, 4000, arith=3, rows_per_wave=16, splits=4,
+                    column_groups=2)
+        tab = {e["kind"]: e for e in rs.tune_table()}
+        assert tab["fp64_stream"] == dict(kind="fp64_stream", arith=0, trans=0, M=1000, N=272,
+                                          K=5000, waves=4, splits=2)
+        assert tab["residual"]["waves"] == 8
+        assert tab["bf16_planes"] == dict(kind="bf16_planes", arith=3, trans=0, M=1000, N=272,
+                                          K=4032, rows_per_wave=16, splits=4, column_groups=2)
+        # pinning a key again replaces its tiling
+        rs.tune_set("residual", 1000, 272, 5000, waves=4)
+        assert len(rs.tune_table()) == 3
+        assert {e["kind"]: e for e in rs.tune_table()}["residual"]["waves"] == 4
+        with pytest.raises(rs.RsvdError):
+            rs.tune_set("bf16_planes", 10, 10, 10, rows_per_wave=48)
+    finally:
+        rs.tune_clear()

@@ -7,7 +7,7 @@ from oracle.philox import gaussian_omega as oracle_omega
 from oracle.method import orth as oracle_orth
 import synth
 
-from gpu_util import announce, to_dev
+from gpu_util import announce, bf16_round, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -165,15 +165,6 @@ def test_lowp_gemm_error_bound(prec, ta, m, n, k):
         assert np.abs(got - ref).max() > 1e3 * 2.0 ** -53 * np.abs(ref).max()
 
 
-def _bf16(x):
-    """Round to BF16 as the planes do: FP64 -> FP32 (nearest even), then the
-    upper 16 bits of the FP32 word, nearest even on the dropped half."""
-    f = np.ascontiguousarray(x, dtype=np.float64).astype(np.float32)
-    u = f.view(np.uint32).astype(np.uint64)
-    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
-    return u.astype(np.uint32).view(np.float32).astype(np.float64)
-
-
 # (trans_a, m, n, k): row tiles of 128 and 256 rows with ragged tails, one and
 # several column groups, k padded to 64, split K with FP32 partials
 BF16_PLANE_CASES = [
@@ -196,9 +187,9 @@ def test_bf16_planes_gemm(split, ta, m, n, k):
     B = rng.standard_normal((k, n))
     opA = A.T if ta else A
     got = rs.bf16_gemm(to_dev(A), to_dev(B), trans_a=ta, split=split).cpu().numpy()
-    ah, bh = _bf16(opA), _bf16(B)
+    ah, bh = bf16_round(opA), bf16_round(B)
     if split:
-        al, bl = _bf16(opA - ah), _bf16(B - bh)
+        al, bl = bf16_round(opA - ah), bf16_round(B - bh)
         ref = ah @ bh + ah @ bl + al @ bh
         mag = np.abs(ah) @ np.abs(bh) + np.abs(ah) @ np.abs(bl) + np.abs(al) @ np.abs(bh)
         terms = 3 * k

@@ -8,7 +8,7 @@ import pytest
 import synth
 from oracle.method import rsvd as oracle_rsvd
 
-from gpu_util import announce, sigma_gate, to_dev
+from gpu_util import announce, bf16_round, sigma_gate, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -115,3 +115,45 @@ def test_batch_tune_then_graph_matches_single_runs():
             one = rs.run(A, k, p, q, **kw)
             assert res[c].rank == one.rank and res[c].residual == one.residual
             assert np.array_equal(bufs["S"][c][: one.rank].cpu().numpy(), one.S.cpu().numpy())
+
+
+# (split, rows per wave, K splits, column groups) pinned for one product key
+PINNED_BF16 = [(False, 16, 1, 1), (False, 32, 1, 2), (False, 32, 4, 1), (True, 16, 1, 2),
+               (True, 32, 2, 1), (True, 16, 8, 1)]
+
+
+@pytest.mark.parametrize("split,rows,splits,groups", PINNED_BF16)
+def test_pinned_bf16_tiling(split, rows, splits, groups):
+    # a pinned tiling is what the table holds, and the product under it keeps
+    # the FP32-accumulation bound of the BF16 operands; without K splits every
+    # tiling sums each entry in the same order, so those results agree bitwise
+    import paper_2307_15572_amd as rs
+    m, n, k = 1100, 272, 5000
+    announce(f"pinned bf16 tiling split={split} rows={rows} splits={splits} groups={groups}")
+    rng = np.random.default_rng(17 + splits + 3 * rows + split)
+    A = rng.standard_normal((m, k))
+    B = rng.standard_normal((k, n))
+    Ad, Bd = to_dev(A), to_dev(B)
+    base = rs.bf16_gemm(Ad, Bd, split=split).cpu().numpy()
+    rs.tune_set("bf16_planes", m, n, k, arith=3 if split else 2, rows_per_wave=rows,
+                splits=splits, column_groups=groups)
+    tab = rs.tune_table()
+    assert len(tab) == 1 and tab[0]["rows_per_wave"] == rows and tab[0]["splits"] == splits
+    got = rs.bf16_gemm(Ad, Bd, split=split).cpu().numpy()
+    ah, bh = bf16_round(A), bf16_round(B)
+    if split:
+        al, bl = bf16_round(A - ah), bf16_round(B - bh)
+        ref = ah @ bh + ah @ bl + al @ bh
+        mag = np.abs(ah) @ np.abs(bh) + np.abs(ah) @ np.abs(bl) + np.abs(al) @ np.abs(bh)
+        terms = 3 * k
+    else:
+        ref, mag, terms = ah @ bh, np.abs(ah) @ np.abs(bh), k
+    assert np.all(np.abs(got - ref) <= (terms + 2) * 2.0 ** -24 * mag)
+    # the default tiling of this key splits K when the chip is not yet full;
+    # compare bitwise with an unsplit pinned run instead
+    if splits == 1:
+        rs.tune_set("bf16_planes", m, n, k, arith=3 if split else 2, rows_per_wave=48 - rows,
+                    splits=1, column_groups=3 - groups)
+        other = rs.bf16_gemm(Ad, Bd, split=split).cpu().numpy()
+        assert np.array_equal(other, got)
+    assert np.abs(got - base).max() <= (terms + 2) * 2.0 ** -23 * mag.max()
