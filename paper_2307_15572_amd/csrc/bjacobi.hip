@@ -23,14 +23,32 @@ namespace {
 
 constexpr double kU = 1.1102230246251565e-16;
 
+// x mod m for 0 <= x < 2 m
+__device__ __forceinline__ int mod_once(int x, int m) { return x >= m ? x - m : x; }
+
+// Pair i of step `step` (0 <= step, i < L - 1) of the circle tournament on L
+// players: player L - 1 is fixed, the others rotate.
 __device__ __forceinline__ void rr_pair_blk(int L, int step, int i, int& a, int& b) {
-  if (i == 0) {
-    a = L - 1;
-    b = step;
-  } else {
-    a = (step + i) % (L - 1);
-    b = (step - i + (L - 1)) % (L - 1);
-  }
+  a = i == 0 ? L - 1 : mod_once(step + i, L - 1);
+  b = i == 0 ? step : mod_once(step - i + (L - 1), L - 1);
+}
+
+// 1/x and 1/sqrt(x) from the hardware estimates and two Newton steps each
+// (the estimates carry about half the FP64 mantissa; each step doubles it).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  double e = fma(-h * y, y, 0.5);
+  y = fma(y, e, y);
+  e = fma(-h * y, y, 0.5);
+  return fma(y, e, y);
 }
 
 struct JacArgs {
@@ -40,24 +58,39 @@ struct JacArgs {
   DevState* st;
 };
 
-// returns true if the pair needed rotating
 // Rotation that annihilates h_pq of the symmetric 2 x 2 [h_pp h_pq; h_pq h_qq]
-// (Rutishauser's formulas); identity when |h_pq| <= tol sqrt(h_pp h_qq).
+// (Rutishauser's formulas: zeta = (h_qq - h_pp) / (2 h_pq), t = sign(zeta) /
+// (|zeta| + sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2), s = c t); identity when
+// |h_pq| <= tol sqrt(h_pp h_qq). The reciprocals and square roots come from
+// rcp_nr / rsq_nr: c is 1 / sqrt(1 + t^2) to about an ulp and s = c t, so
+// c^2 + s^2 = 1 to a few ulps whatever the rounding of t (an inexact t only
+// leaves a slightly larger h_pq for a later round). Straight-line code: the
+// rare cases (subnormal h_pq, |zeta| beyond 1e150) are computed beside the
+// common one and selected, so the compiler can interleave the two rotations a
+// thread forms in a round.
 __device__ __forceinline__ void jac_rot(double hpp, double hqq, double hpq, double tol, double& c,
                                         double& s) {
-  c = 1.0;
-  s = 0.0;
-  if (fabs(hpq) > tol * sqrt(hpp) * sqrt(hqq) && hpq != 0.0) {
-    const double zeta = (hqq - hpp) / (2.0 * hpq);
-    const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-    c = 1.0 / sqrt(1.0 + t * t);
-    s = c * t;
-  }
+  const bool rot = fabs(hpq) > tol * sqrt(hpp) * sqrt(hqq) && hpq != 0.0;
+  const double e = 2.0 * hpq, d = hqq - hpp;
+  const bool normal_e = fabs(e) >= 1e-290;
+  const double zeta_fast = d * rcp_nr(normal_e ? e : 1.0);
+  const double zeta_slow = d / (e != 0.0 ? e : 1.0);  // the estimate would overflow
+  const double zeta = normal_e ? zeta_fast : zeta_slow;
+  const double az = fabs(zeta);
+  const bool huge = !(az < 1e150);  // sqrt(1 + zeta^2) = |zeta| to working precision
+  const double zc = huge ? 1.0 : az;
+  const double w = fma(zc, zc, 1.0);
+  const double t_common = rcp_nr(zc + w * rsq_nr(w));  // 1 / (|zeta| + sqrt(1 + zeta^2))
+  const double t_huge = 0.5 * rcp_nr(huge ? az : 1.0);
+  const double t = copysign(huge ? t_huge : t_common, zeta);
+  const double cc = rsq_nr(fma(t, t, 1.0));
+  c = rot ? cc : 1.0;
+  s = rot ? cc * t : 0.0;
 }
 
-// Hb, Vb: two 32 x 33 buffers each (the Gram H is built in Hb[0]).
+// Returns true if the pair needed rotating. dsq: 32 doubles of LDS.
 __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double (*Hb)[32][33],
-                             double (*Vb)[32][33], double* red, int* s_any) {
+                             double (*Vb)[32][33], double* red, double* dsq, int* s_any) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
   double (*H)[33] = Hb[0];
   const int Lp = a.Lp;
@@ -65,21 +98,33 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
   const double* rI = a.M + (int64_t)16 * I * Lp;
   const double* rJ = a.M + (int64_t)16 * J * Lp;
 
-  // ---- Gram of the 32 rows (tiles 00, 01, 11), K split over the 4 waves
+  // ---- Gram of the 32 rows (tiles 00, 01, 11), K split over the 4 waves;
+  // GB column tiles of a wave in flight together
+  constexpr int GB = 4;
   d4 h00 = {0, 0, 0, 0}, h01 = {0, 0, 0, 0}, h11 = {0, 0, 0, 0};
-  for (int ct = wave; ct < nct; ct += 4) {
-    const int c0 = 16 * ct + 4 * g;
-    double xi[4], xj[4];
+  for (int ct0 = wave; ct0 < nct; ct0 += 4 * GB) {
+    double xi[GB][4], xj[GB][4];
 #pragma unroll
-    for (int s = 0; s < 4; s++) {
-      xi[s] = rI[(int64_t)r * Lp + c0 + s];
-      xj[s] = rJ[(int64_t)r * Lp + c0 + s];
+    for (int u = 0; u < GB; u++) {
+      const int c0 = 16 * (ct0 + 4 * u) + 4 * g;
+      if (ct0 + 4 * u < nct) {
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+          xi[u][s] = rI[(int64_t)r * Lp + c0 + s];
+          xj[u][s] = rJ[(int64_t)r * Lp + c0 + s];
+        }
+      }
     }
 #pragma unroll
-    for (int s = 0; s < 4; s++) {
-      h00 = mfma_f64_16x16x4(xi[s], xi[s], h00);
-      h01 = mfma_f64_16x16x4(xi[s], xj[s], h01);
-      h11 = mfma_f64_16x16x4(xj[s], xj[s], h11);
+    for (int u = 0; u < GB; u++) {
+      if (ct0 + 4 * u < nct) {
+#pragma unroll
+        for (int s = 0; s < 4; s++) {
+          h00 = mfma_f64_16x16x4(xi[u][s], xi[u][s], h00);
+          h01 = mfma_f64_16x16x4(xi[u][s], xj[u][s], h01);
+          h11 = mfma_f64_16x16x4(xj[u][s], xj[u][s], h11);
+        }
+      }
     }
   }
 #pragma unroll
@@ -103,14 +148,18 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
     H[i][16 + j] = v1;
     H[16 + j][i] = v1;
     H[16 + i][16 + j] = v2;
+    if (i == j) {
+      dsq[i] = sqrt(v0);
+      dsq[16 + i] = sqrt(v2);
+    }
   }
   __syncthreads();
-  // ---- any pair above tolerance?
+  // ---- any pair above tolerance? (|h_ij| > tol sqrt(h_ii) sqrt(h_jj))
   for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x) {
     const int i = e / 32, j = e % 32;
     if (i < j) {
       const double hij = H[i][j];
-      if (fabs(hij) > tol * sqrt(H[i][i]) * sqrt(H[j][j]) && hij != 0.0) *s_any = 1;
+      if (fabs(hij) > tol * dsq[i] * dsq[j] && hij != 0.0) *s_any = 1;
     }
   }
   __syncthreads();
@@ -143,15 +192,15 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
         double ck, sk, cm, sm;
         jac_rot(Hc[pk][pk], Hc[qk][qk], Hc[pk][qk], tol, ck, sk);
         jac_rot(Hc[pm][pm], Hc[qm][qm], Hc[pm][qm], tol, cm, sm);
-        // rows: J_k^T
+        // rows: J_k^T, then columns: J_m (an identity rotation, c = 1 and
+        // s = 0, leaves finite entries exactly as they are)
         double hpp = Hc[pk][pm], hpq = Hc[pk][qm], hqp = Hc[qk][pm], hqq = Hc[qk][qm];
-        if (sk != 0.0) {
+        {
           const double a0 = ck * hpp - sk * hqp, a1 = sk * hpp + ck * hqp;
           const double b0 = ck * hpq - sk * hqq, b1 = sk * hpq + ck * hqq;
           hpp = a0; hqp = a1; hpq = b0; hqq = b1;
         }
-        // columns: J_m
-        if (sm != 0.0) {
+        {
           const double a0 = cm * hpp - sm * hpq, a1 = sm * hpp + cm * hpq;
           const double b0 = cm * hqp - sm * hqq, b1 = sm * hqp + cm * hqq;
           hpp = a0; hpq = a1; hqp = b0; hqq = b1;
@@ -161,7 +210,7 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
         Hn[qk][pm] = hqp;
         Hn[qk][qm] = hqq;
         double vpp = Vc[pk][pm], vpq = Vc[pk][qm], vqp = Vc[qk][pm], vqq = Vc[qk][qm];
-        if (sm != 0.0) {
+        {
           const double a0 = cm * vpp - sm * vpq, a1 = sm * vpp + cm * vpq;
           const double b0 = cm * vqp - sm * vqq, b1 = sm * vqp + cm * vqq;
           vpp = a0; vpq = a1; vqp = b0; vqq = b1;
@@ -182,21 +231,21 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
     double* base = mat == 0 ? a.M : a.P;
     double* bI = base + (int64_t)16 * I * Lp;
     double* bJ = base + (int64_t)16 * J * Lp;
-    // two column tiles per iteration (their loads in flight together)
-    for (int ct = wave; ct < nct; ct += 8) {
-      const bool two = ct + 4 < nct;
-      double b[2][8];
+    // AB column tiles per iteration (their loads in flight together)
+    constexpr int AB = 4;
+    for (int ct = wave; ct < nct; ct += 4 * AB) {
+      double b[AB][8];
 #pragma unroll
-      for (int u = 0; u < 2; u++)
+      for (int u = 0; u < AB; u++)
 #pragma unroll
         for (int s = 0; s < 8; s++) {
           const int row = 4 * s + g;  // 0..31
           const double* src = row < 16 ? bI : bJ;
-          b[u][s] = (u == 0 || two) ? src[(int64_t)(row & 15) * Lp + 16 * (ct + 4 * u) + r] : 0.0;
+          b[u][s] = ct + 4 * u < nct ? src[(int64_t)(row & 15) * Lp + 16 * (ct + 4 * u) + r] : 0.0;
         }
 #pragma unroll
-      for (int u = 0; u < 2; u++) {
-        if (u == 1 && !two) break;
+      for (int u = 0; u < AB; u++) {
+        if (ct + 4 * u >= nct) break;
         const int c = 16 * (ct + 4 * u) + r;
         d4 o0 = {0, 0, 0, 0}, o1 = {0, 0, 0, 0};
 #pragma unroll
@@ -221,6 +270,7 @@ __global__ void __launch_bounds__(256) bjacobi_kernel(JacArgs a) {
   __shared__ double Hb[2][32][33];
   __shared__ double Vb[2][32][33];
   __shared__ double red[4 * 3 * 256];
+  __shared__ double dsq[32];
   __shared__ int s_any;
   const int nb = a.Lp / 16;  // even
   const int npairs = nb / 2;
@@ -234,7 +284,7 @@ __global__ void __launch_bounds__(256) bjacobi_kernel(JacArgs a) {
       for (int pr = blockIdx.x; pr < npairs; pr += gridDim.x) {
         int I, J;
         rr_pair_blk(nb, step, pr, I, J);
-        const bool rot = process_pair(a, I, J, tol, Hb, Vb, red, &s_any);
+        const bool rot = process_pair(a, I, J, tol, Hb, Vb, red, dsq, &s_any);
         if (rot && threadIdx.x == 0)
           __hip_atomic_fetch_add(&counters[sweep], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }

@@ -18,7 +18,7 @@ namespace {
 
 constexpr double kUnitRoundoff = 1.1102230246251565e-16;  // 2^-53
 constexpr int kBig = 1024;                                // threads of the l x l kernels
-constexpr int64_t kCholGridMin = 320;  // l from which the Cholesky runs on a grid of workgroups
+constexpr int64_t kCholGridMin = 256;  // l from which the Cholesky runs on a grid of workgroups
 
 __device__ __forceinline__ double block_sum(double v, double* red) {
   v = wave_sum(v);
