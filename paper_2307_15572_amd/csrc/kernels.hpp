@@ -99,8 +99,10 @@ rsvd_status svd_finish(int64_t l, int64_t kc, const double* M, const double* P, 
                        double* s, double* Us, double* W, DevState* st, hipStream_t st_);
 rsvd_status select_rank(int64_t l, int64_t p, int64_t kc, int mode, double param,
                         const double* s, DevState* st, hipStream_t hs);
+// Sign rule on the first kc columns of U (m x kc) and V (n x kc, may be null);
+// scratch: 2 kc doubles.
 rsvd_status sign_fix(int64_t m, int64_t n, int64_t kc, double* U, int64_t ldu, double* V,
-                     int64_t ldv, hipStream_t s);
+                     int64_t ldv, double* scratch, hipStream_t s);
 // US = U diag(s) (m x kcp), Vt = V^T (kcp x n); columns / rows >= rank are zero
 rsvd_status resid_prep(int64_t m, int64_t n, int64_t kc, int64_t kcp, const double* U,
                        int64_t ldu, const double* s_vals, const double* V, int64_t ldv, double* US,

@@ -402,7 +402,8 @@ rsvd_status lift_and_finish(const rsvd_plan_s& pl, const Ws& w, const double* A,
                    part, pl.part_doubles, s));
     RSVD_TRY(dgemm(false, n, kcl, l, 1.0, Zc, l, w.at<double>(pl.off_W), kcl, 0.0, o.V, o.ldv,
                    part, pl.part_doubles, s));
-    RSVD_TRY(sign_fix(m, n, kcl, o.U, o.ldu, o.V, o.ldv, s));
+    // the Householder fallback's tau (2 l doubles) is free by now
+    RSVD_TRY(sign_fix(m, n, kcl, o.U, o.ldu, o.V, o.ldv, w.at<double>(pl.off_tau), s));
   }
   if (hipMemcpyAsync(o.S, sig, (size_t)kcl * sizeof(double), hipMemcpyDeviceToDevice, s) !=
       hipSuccess)

@@ -869,41 +869,78 @@ __global__ void select_rank_kernel(int64_t l, int64_t p, int64_t kc, int mode, d
 }
 
 // Sign rule: flip (U_j, V_j) so the largest-magnitude entry of U_j is positive
-// (lowest row on ties). One workgroup per column.
-__global__ void __launch_bounds__(256) sign_fix_kernel(int64_t m, int64_t n, double* __restrict__ U,
-                                                       int64_t ldu, double* __restrict__ V,
-                                                       int64_t ldv) {
-  __shared__ double sv[4];
-  __shared__ int64_t si[4];
-  __shared__ double sgn;
-  const int64_t j = blockIdx.x;
-  double best = -1.0;
-  int64_t bi = 0;
-  for (int64_t i = threadIdx.x; i < m; i += blockDim.x) {
+// (lowest row on ties; NaN entries never win). Four coalesced passes over the
+// row-major factors, threads along the columns of a row:
+//   colmax  key_j = max_i |U_ij| as the bit pattern of a non-negative double
+//           (ordered like the value), a workgroup per block of rows, one
+//           atomic max per column and workgroup;
+//   colarg  idx_j = the lowest row whose |U_ij| has that pattern (atomic min);
+//   colsign sign_j = -1 where U[idx_j][j] < 0, else +1 (into key_j);
+//   flip    U_ij, V_ij negated in the columns with sign_j = -1.
+constexpr int64_t kSignRows = 64;  // rows per workgroup of colmax / colarg
+
+__global__ void __launch_bounds__(256) colmax_init_kernel(int64_t kc, unsigned long long* key,
+                                                          unsigned long long* idx) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < kc) {
+    key[j] = 0ull;
+    idx[j] = ~0ull;
+  }
+}
+
+__global__ void __launch_bounds__(256) colmax_kernel(int64_t m, int64_t kc,
+                                                     const double* __restrict__ U, int64_t ldu,
+                                                     unsigned long long* key) {
+  const int64_t j = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+  if (j >= kc) return;
+  const int64_t r0 = (int64_t)blockIdx.x * kSignRows;
+  const int64_t r1 = r0 + kSignRows < m ? r0 + kSignRows : m;
+  double best = 0.0;
+  for (int64_t i = r0; i < r1; i++) {
     const double a = fabs(U[i * ldu + j]);
-    if (a > best) { best = a; bi = i; }
+    if (a > best) best = a;
   }
-  for (int off = 32; off > 0; off >>= 1) {
-    const double ob = __shfl_xor(best, off, 64);
-    const int64_t oi = __shfl_xor(bi, off, 64);
-    if (ob > best || (ob == best && oi < bi)) { best = ob; bi = oi; }
-  }
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) { sv[w] = best; si[w] = bi; }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double b = sv[0];
-    int64_t ii = si[0];
-    for (int k = 1; k < (int)(blockDim.x >> 6); k++) {
-      if (sv[k] > b || (sv[k] == b && si[k] < ii)) { b = sv[k]; ii = si[k]; }
+  if (best > 0.0) atomicMax(&key[j], (unsigned long long)__double_as_longlong(best));
+}
+
+__global__ void __launch_bounds__(256) colarg_kernel(int64_t m, int64_t kc,
+                                                     const double* __restrict__ U, int64_t ldu,
+                                                     const unsigned long long* key,
+                                                     unsigned long long* idx) {
+  const int64_t j = (int64_t)blockIdx.y * blockDim.x + threadIdx.x;
+  if (j >= kc) return;
+  const int64_t r0 = (int64_t)blockIdx.x * kSignRows;
+  const int64_t r1 = r0 + kSignRows < m ? r0 + kSignRows : m;
+  const unsigned long long k = key[j];
+  for (int64_t i = r0; i < r1; i++) {
+    if ((unsigned long long)__double_as_longlong(fabs(U[i * ldu + j])) == k) {
+      atomicMin(&idx[j], (unsigned long long)i);
+      break;
     }
-    sgn = (U[ii * ldu + j] < 0.0) ? -1.0 : 1.0;
   }
-  __syncthreads();
-  if (sgn < 0.0) {
-    for (int64_t i = threadIdx.x; i < m; i += blockDim.x) U[i * ldu + j] = -U[i * ldu + j];
-    if (V)
-      for (int64_t i = threadIdx.x; i < n; i += blockDim.x) V[i * ldv + j] = -V[i * ldv + j];
+}
+
+__global__ void __launch_bounds__(256) colsign_kernel(int64_t m, int64_t kc,
+                                                      const double* __restrict__ U, int64_t ldu,
+                                                      const unsigned long long* idx,
+                                                      double* sign) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= kc) return;
+  const unsigned long long i = idx[j];
+  sign[j] = (i < (unsigned long long)m && U[(int64_t)i * ldu + j] < 0.0) ? -1.0 : 1.0;
+}
+
+__global__ void __launch_bounds__(256) flip_kernel(int64_t m, int64_t n, int64_t kc,
+                                                   double* __restrict__ U, int64_t ldu,
+                                                   double* __restrict__ V, int64_t ldv,
+                                                   const double* __restrict__ sign) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t rows = m + (V ? n : 0);
+  if (e >= rows * kc) return;
+  const int64_t i = e / kc, j = e % kc;
+  if (sign[j] < 0.0) {
+    double* p = i < m ? &U[i * ldu + j] : &V[(i - m) * ldv + j];
+    *p = -*p;
   }
 }
 
@@ -1203,9 +1240,25 @@ rsvd_status select_rank(int64_t l, int64_t p, int64_t kc, int mode, double param
 }
 
 rsvd_status sign_fix(int64_t m, int64_t n, int64_t kc, double* U, int64_t ldu, double* V,
-                     int64_t ldv, hipStream_t s) {
-  if (kc == 0) return RSVD_OK;
-  hipLaunchKernelGGL(sign_fix_kernel, dim3((unsigned)kc), dim3(256), 0, s, m, n, U, ldu, V, ldv);
+                     int64_t ldv, double* scratch, hipStream_t s) {
+  if (kc == 0 || m == 0) return RSVD_OK;
+  unsigned long long* key = reinterpret_cast<unsigned long long*>(scratch);
+  unsigned long long* idx = key + kc;
+  const unsigned cb = blocks_for(kc, 256);
+  const dim3 grid(blocks_for(m, kSignRows), cb);
+  if (grid.y > 65535) return RSVD_EUNSUPPORTED;
+  hipLaunchKernelGGL(colmax_init_kernel, dim3(cb), dim3(256), 0, s, kc, key, idx);
+  RSVD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(colmax_kernel, grid, dim3(256), 0, s, m, kc, U, ldu, key);
+  RSVD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(colarg_kernel, grid, dim3(256), 0, s, m, kc, U, ldu, key, idx);
+  RSVD_LAUNCH_CHECK();
+  // the sign overwrites the key of its column (read by this thread only)
+  hipLaunchKernelGGL(colsign_kernel, dim3(cb), dim3(256), 0, s, m, kc, U, ldu, idx, scratch);
+  RSVD_LAUNCH_CHECK();
+  const int64_t tot = (m + (V ? n : 0)) * kc;
+  hipLaunchKernelGGL(flip_kernel, dim3(blocks_for(tot, 256)), dim3(256), 0, s, m, n, kc, U, ldu,
+                     V, ldv, scratch);
   RSVD_LAUNCH_CHECK();
   return RSVD_OK;
 }
