@@ -399,8 +399,9 @@ rsvd_status rsvd_small_svd(int64_t l, const double* R, double* s, double* Us, do
  *
  * rsvd_tune_entries copies up to `max` entries of the table (kind[i] =
  * 100 kind + 10 arithmetic + transposed; mnk[3i..3i+2] = M, N, K; cfg[3i..]
- * = the tiling: waves / rows per wave, K splits, column groups) into host
- * arrays (each may be NULL) and returns the number of entries;
+ * = the tiling: waves / rows per wave, K splits (residual: column tiles per
+ * workgroup, 0 for the widest), column groups) into host arrays (each may be
+ * NULL) and returns the number of entries;
  * rsvd_tune_clear empties the table. rsvd_tune_set pins the tiling of one
  * key (kind 0 FP64 streaming, 1 register-staged, 2 residual, 3 BF16 plane
  * product; arith 0 FP64, 1 FP32, 2 BF16, 3 split BF16; a, b, c as in

@@ -717,10 +717,17 @@ rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const 
   return RSVD_OK;
 }
 
+// Column tiles per workgroup of the residual pass's narrow candidate: two
+// 4-wave workgroups of it fit on a CU (72 KB of LDS each), so one's epilogue
+// (the read of A) overlaps the other's products.
+constexpr int kResNarrowNT = 8;
+
 size_t resid_partials(int64_t M, int64_t N) {
   GemmShape s = dgemm_shape(M, N, 1, 1);
   const size_t a = (size_t)2 * s.tiles_m * s.tiles_n;
-  const size_t b = (size_t)2 * ((M + 127) / 128) * s.tiles_n;
+  // every DMA candidate: 4 or 8 waves, the default or the narrow column tile
+  const int64_t ntiles = (N + 15) / 16;
+  const size_t b = (size_t)2 * ((M + 63) / 64) * ((ntiles + kResNarrowNT - 1) / kResNarrowNT);
   return a > b ? a : b;
 }
 
@@ -737,25 +744,40 @@ rsvd_status resid(int64_t M, int64_t N, int64_t K, const double* US, int64_t ldu
                       (ldvt % 2 == 0) && ((uintptr_t)US % 16 == 0) && ((uintptr_t)Vt % 16 == 0) &&
                       g_use_dma;
   if (dma_ok) {
-    // 8 waves per workgroup unless tuned to 4 (partial holds the 4-wave count)
+    // 8 waves and the widest column tile unless tuned otherwise (a = waves,
+    // b = column tiles per workgroup; partial holds every candidate's count)
     const TuneKey tkey{kTuneResid, kPrecF64, 0, M, N, K};
-    if (tune_recording())
-      tune_record(tkey, {{4, 0, 0}, {8, 0, 0}}, [=](hipStream_t s2) {
+    if (tune_recording()) {
+      std::vector<TuneCfg> cands = {{4, 0, 0}, {8, 0, 0}};
+      if (sh.nt > kResNarrowNT) {
+        cands.push_back({4, kResNarrowNT, 0});
+        cands.push_back({8, kResNarrowNT, 0});
+      }
+      tune_record(tkey, cands, [=](hipStream_t s2) {
         return resid(M, N, K, US, ldus, Vt, ldvt, A, lda, partial, st, s2);
       });
+    }
     TuneCfg tcfg;
-    const int wm = tune_get(tkey, &tcfg) && tcfg.a == 4 ? 4 : 8;
+    const bool tuned = tune_get(tkey, &tcfg);
+    const int wm = tuned && tcfg.a == 4 ? 4 : 8;
+    int nt = sh.nt;
+    int tiles_n = sh.tiles_n;
+    if (tuned && tcfg.b >= 1 && tcfg.b < sh.nt) {
+      nt = tcfg.b;
+      tiles_n = (int)(((N + 15) / 16 + nt - 1) / nt);
+    }
     GemmArgs a;
     a.M = M; a.N = N; a.K = K; a.kchunk = K;
     a.alpha = 1.0; a.beta = 0.0;
     a.A = US; a.lda = ldus; a.B = Vt; a.ldb = ldvt; a.C = nullptr; a.ldc = 0;
     a.part = nullptr;
-    a.tiles_m = (int)((M + 16 * wm - 1) / (16 * wm)); a.tiles_n = sh.tiles_n; a.splits = 1;
+    a.tiles_m = (int)((M + 16 * wm - 1) / (16 * wm)); a.tiles_n = tiles_n; a.splits = 1;
     a.pred = nullptr; a.Aref = A; a.ldref = lda; a.rpart = partial;
     a.vec_a = 1; a.vec_b = 1;
     const int64_t total = (int64_t)a.tiles_m * a.tiles_n;
-    hipError_t e = wm == 4 ? launch_dma<4, true, kPrecF64>(sh.nt, dim3((unsigned)total), s, a)
-                           : launch_dma<8, true, kPrecF64>(sh.nt, dim3((unsigned)total), s, a);
+    if ((size_t)2 * total > resid_partials(M, N)) return RSVD_EINVAL;
+    hipError_t e = wm == 4 ? launch_dma<4, true, kPrecF64>(nt, dim3((unsigned)total), s, a)
+                           : launch_dma<8, true, kPrecF64>(nt, dim3((unsigned)total), s, a);
     if (e != hipSuccess) return RSVD_EHIP;
     rsvd_status r = sum_partials_into(total, partial, &st->resid2, s);
     if (r != RSVD_OK) return r;

@@ -34,7 +34,7 @@ struct TuneKey {
 
 // kTuneDma: a = waves per workgroup (4 | 8), b = K splits
 // kTuneGeneric: b = K splits
-// kTuneResid: a = waves per workgroup (4 | 8)
+// kTuneResid: a = waves per workgroup (4 | 8), b = column tiles per workgroup (0: widest)
 // kTuneBf16: a = 16-row fragments per wave (1 | 2), b = K splits, c = column groups
 struct TuneCfg {
   int a = 0, b = 0, c = 0;

@@ -193,6 +193,7 @@ def test_tune_set_pins_and_rejects_without_device():
         assert L.rsvd_tune_set(0, 0, 0, 0, 10, 10, 4, 1, 0) == 1
         assert L.rsvd_tune_set(0, 0, 0, 10, 10, 10, 6, 1, 0) == 1
         assert L.rsvd_tune_set(2, 0, 0, 10, 10, 10, 2, 0, 0) == 1
+        assert L.rsvd_tune_set(2, 0, 0, 10, 10, 10, 4, 18, 0) == 1
         assert L.rsvd_tune_set(3, 2, 0, 10, 10, 10, 3, 1, 0) == 1
         assert L.rsvd_tune_set(3, 2, 0, 10, 10, 10, 1, 65, 0) == 1
         assert rs.tune_table() == []
@@ -204,7 +205,7 @@ def test_tune_set_pins_and_rejects_without_device():
         tab = {e["kind"]: e for e in rs.tune_table()}
         assert tab["fp64_stream"] == dict(kind="fp64_stream", arith=0, trans=0, M=1000, N=272,
                                           K=5000, waves=4, splits=2)
-        assert tab["residual"]["waves"] == 8
+        assert tab["residual"]["waves"] == 8 and tab["residual"]["column_tiles"] == 0
         assert tab["bf16_planes"] == dict(kind="bf16_planes", arith=3, trans=0, M=1000, N=272,
                                           K=4032, rows_per_wave=16, splits=4, column_groups=2)
         # pinning a key again replaces its tiling

@@ -157,3 +157,23 @@ def test_pinned_bf16_tiling(split, rows, splits, groups):
         other = rs.bf16_gemm(Ad, Bd, split=split).cpu().numpy()
         assert np.array_equal(other, got)
     assert np.abs(got - base).max() <= (terms + 2) * 2.0 ** -23 * mag.max()
+
+
+@pytest.mark.parametrize("waves,column_tiles", [(8, 0), (4, 0), (4, 8), (8, 8)])
+def test_pinned_residual_tiling(waves, column_tiles):
+    # every residual tiling the tuner may choose gives the oracle's residual
+    # (the tiling changes only the order of the FP64 sums)
+    import paper_2307_15572_amd as rs
+    m, n, k, p, q = 3000, 2000, 100, 16, 1
+    announce(f"pinned residual tiling waves={waves} column_tiles={column_tiles}")
+    sig = synth.spectrum_pow10(n, 1 / 50)
+    A = synth.general(m, n, sig, tag=811, noise=1e-9)
+    ref = oracle_rsvd(A, k, p, q, seed=811)
+    kcp = (k + 15) // 16 * 16  # the residual product's inner size: k padded to 16
+    rs.tune_set("residual", m, n, kcp, waves=waves, column_tiles=column_tiles)
+    out = rs.run(to_dev(A), k, p, q, seed=811)
+    assert out.rank == ref.rank
+    assert abs(out.residual - ref.residual) <= 1e-10 * ref.residual
+    tab = rs.tune_table()
+    assert tab == [dict(kind="residual", arith=0, trans=0, M=m, N=n, K=kcp, waves=waves,
+                        column_tiles=column_tiles)]
