@@ -79,9 +79,12 @@ size_t chol_panel_doubles(int64_t l);
 rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, double* scratch, int64_t m,
                      int pass, int only_if_shifted, DevState* st, hipStream_t s, int share = 1);
 // Householder QR of the rows x l panel Yorig into Y (= Q) and R, run only
-// when st->qr_householder is set (tau: 2 l doubles of scratch).
+// when st->qr_householder is set (tau: 2 l doubles of scratch; scratch: l x l
+// doubles for the grid variant of large panels, may be null; share: runs on
+// concurrent streams, as for chol_inv).
 rsvd_status householder_fallback(int64_t rows, int64_t l, const double* Yorig, double* Y,
-                                 double* R, double* tau, DevState* st, hipStream_t s);
+                                 double* R, double* tau, double* scratch, DevState* st,
+                                 hipStream_t s, int share = 1);
 // Copy src -> dst (rows x cols, row-major): always (cond 0), only when
 // st->qr_shifted is set (cond 1), only when it is clear (cond 2).
 rsvd_status copy_panel(int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst,

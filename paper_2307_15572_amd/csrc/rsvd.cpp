@@ -167,7 +167,8 @@ rsvd_status orth(const rsvd_plan_s& pl, const Ws& w, int64_t rows, int64_t l, do
     RSVD_TRY(copy_panel(l, l, Rtmp, l, Rout, l, 1, st, s));
   }
   // rank-deficient panel: Householder QR of the saved original
-  RSVD_TRY(householder_fallback(rows, l, Yorig, Y, Rout, tau, st, s));
+  // (Rtmp is free again: its last use, the product R3 R, is done)
+  RSVD_TRY(householder_fallback(rows, l, Yorig, Y, Rout, tau, Rtmp, st, s, pl.coop_share));
   return RSVD_OK;
 #undef RSVD_TRY
 }

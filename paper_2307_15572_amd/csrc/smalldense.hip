@@ -19,6 +19,7 @@ namespace {
 constexpr double kUnitRoundoff = 1.1102230246251565e-16;  // 2^-53
 constexpr int kBig = 1024;                                // threads of the l x l kernels
 constexpr int64_t kCholGridMin = 256;  // l from which the Cholesky runs on a grid of workgroups
+constexpr int64_t kHouseGridMin = 1 << 16;  // rows x l from which the Householder fallback runs on a grid
 
 __device__ __forceinline__ double block_sum(double v, double* red) {
   v = wave_sum(v);
@@ -756,6 +757,136 @@ __global__ void __launch_bounds__(256) chol_grid_kernel(int l, double* __restric
   }
 }
 
+// ---------------------------------------------------------------------------
+// The Householder fallback spread over a grid of workgroups (panels too large
+// for one workgroup). Workgroup w owns a contiguous range of rows. Column j of
+// the factorization:
+//   partial  part[w][c] = sum over its rows i > j of W[i][j] W[i][c], c >= j
+//            (c = j: the squared norm below the diagonal)
+//   reduce   every workgroup forms the same reflector (beta, tau, scale) from
+//            the same sum; workgroup c mod G finishes column c > j:
+//            d_c = tau (W[j][c] + scale u_c) into dfin[c], W[j][c] -= d_c
+//   update   its rows i > j: W[i][c] -= d_c scale W[i][j], then v_i = scale W[i][j]
+// with a grid barrier after the partial and after the reduce; the explicit Q
+// is accumulated backwards the same way. The arithmetic is that of
+// householder_kernel with the row sums split by workgroup. part: G l + l
+// doubles of scratch; tau_buf[j] = tau_j, tau_buf[l + j] = beta_j.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) householder_grid_kernel(int64_t rows, int l,
+                                                                const double* __restrict__ Yorig,
+                                                                double* __restrict__ Y,
+                                                                double* __restrict__ R,
+                                                                double* __restrict__ tau_buf,
+                                                                double* __restrict__ part,
+                                                                DevState* st) {
+  __shared__ int s_ok;
+  if (st->qr_householder == 0) return;
+  const GridTeam tm{st, &s_ok};
+  const int G = (int)gridDim.x, w = (int)blockIdx.x;
+  const int64_t per = (rows + G - 1) / G;
+  const int64_t r0 = min(rows, (int64_t)w * per), r1 = min(rows, r0 + per);
+  double* dfin = part + (int64_t)G * l;
+  double* W = Y;
+  const int64_t tot = rows * l;
+  const int64_t gtid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t gthreads = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = gtid; e < tot; e += gthreads) W[e] = Yorig[e];
+  if (!tm.sync()) return;
+  for (int j = 0; j < l; j++) {
+    const int64_t i0 = max(r0, (int64_t)j + 1);
+    for (int c = j + threadIdx.x; c < l; c += blockDim.x) {
+      double acc = 0.0;
+      for (int64_t i = i0; i < r1; i++) acc += W[i * l + j] * W[i * l + c];
+      part[(int64_t)w * l + c] = acc;
+    }
+    if (!tm.sync()) return;
+    double s2 = 0.0;
+    for (int v = 0; v < G; v++) s2 += part[(int64_t)v * l + j];
+    const double alpha = W[(int64_t)j * l + j];
+    double beta, tau, scale;
+    if (s2 == 0.0) {
+      beta = alpha;
+      tau = 0.0;
+      scale = 0.0;
+    } else {
+      const double nrm = sqrt(alpha * alpha + s2);
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      scale = 1.0 / (alpha - beta);
+    }
+    {
+      const int first = j + 1 + ((w - (j + 1)) % G + G) % G;  // smallest c > j with c = w (mod G)
+      for (int c = first + G * (int)threadIdx.x; c < l; c += G * (int)blockDim.x) {
+        double u = 0.0;
+        for (int v = 0; v < G; v++) u += part[(int64_t)v * l + c];
+        const double d = tau * (W[(int64_t)j * l + c] + scale * u);
+        dfin[c] = d;
+        W[(int64_t)j * l + c] -= d;
+      }
+    }
+    if (w == j % G && threadIdx.x == 0) {
+      tau_buf[j] = tau;
+      tau_buf[l + j] = beta;
+    }
+    if (!tm.sync()) return;
+    for (int c = j + 1 + threadIdx.x; c < l; c += blockDim.x) {
+      const double d = dfin[c] * scale;
+      for (int64_t i = i0; i < r1; i++) W[i * l + c] -= d * W[i * l + j];
+    }
+    __syncthreads();
+    for (int64_t i = i0 + threadIdx.x; i < r1; i += blockDim.x) W[i * l + j] *= scale;
+    if (threadIdx.x == 0 && j >= r0 && j < r1) W[(int64_t)j * l + j] = beta;
+    __syncthreads();
+  }
+  if (!tm.sync()) return;
+  // R = upper(W) with diag(R) >= 0 (rows of R and columns of Q flip together)
+  if (R) {
+    for (int64_t e = gtid; e < (int64_t)l * l; e += gthreads) {
+      const int i = (int)(e / l), c = (int)(e % l);
+      const double v = W[(int64_t)i * l + c];
+      R[e] = (c >= i) ? (tau_buf[l + i] < 0.0 ? -v : v) : 0.0;
+    }
+  }
+  if (!tm.sync()) return;
+  // Q = H_0 ... H_{l-1} [I; 0], backwards; rows > j of column j hold v_j
+  for (int j = l - 1; j >= 0; j--) {
+    const double tau = tau_buf[j];
+    const int64_t i0 = max(r0, (int64_t)j + 1);
+    for (int c = j + 1 + threadIdx.x; c < l; c += blockDim.x) {
+      double acc = 0.0;
+      for (int64_t i = i0; i < r1; i++) acc += W[i * l + j] * W[i * l + c];
+      part[(int64_t)w * l + c] = acc;
+    }
+    if (!tm.sync()) return;
+    {
+      const int first = j + 1 + ((w - (j + 1)) % G + G) % G;
+      for (int c = first + G * (int)threadIdx.x; c < l; c += G * (int)blockDim.x) {
+        double u = 0.0;
+        for (int v = 0; v < G; v++) u += part[(int64_t)v * l + c];
+        const double d = tau * u;
+        dfin[c] = d;
+        W[(int64_t)j * l + c] = -d;  // Q[j][c] is 0 before H_j
+      }
+    }
+    if (!tm.sync()) return;
+    for (int c = j + 1 + threadIdx.x; c < l; c += blockDim.x) {
+      const double d = dfin[c];
+      for (int64_t i = i0; i < r1; i++) W[i * l + c] -= d * W[i * l + j];
+    }
+    __syncthreads();
+    // column j: H_j e_j = e_j - tau v
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += blockDim.x) {
+      const double x = W[i * l + j];
+      W[i * l + j] = i > j ? -tau * x : (i == j ? 1.0 - tau : 0.0);
+    }
+    __syncthreads();
+  }
+  if (!tm.sync()) return;
+  for (int64_t e = gtid; e < tot; e += gthreads)
+    if (tau_buf[l + (int)(e % l)] < 0.0) W[e] = -W[e];
+  if (gtid == 0) atomicOr(&st->flags, (uint32_t)RSVD_FLAG_QR_FALLBACK);
+}
+
 __global__ void __launch_bounds__(256) copy_panel_kernel(int64_t rows, int64_t cols,
                                                          const double* __restrict__ src, int64_t lds,
                                                          double* __restrict__ dst, int64_t ldd,
@@ -1201,7 +1332,34 @@ rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, double* scra
 }
 
 rsvd_status householder_fallback(int64_t rows, int64_t l, const double* Yorig, double* Y,
-                                 double* R, double* tau, DevState* st, hipStream_t s) {
+                                 double* R, double* tau, double* scratch, DevState* st,
+                                 hipStream_t s, int share) {
+  // a grid of workgroups (64 rows or more each) for panels that would keep one
+  // workgroup busy for long; its scratch (G l + l doubles) fits in l x l
+  int grid = (int)((rows + 63) / 64);
+  if (grid > (int)l - 1) grid = (int)l - 1;
+  if (grid > 128) grid = 128;
+  if (scratch && rows * l >= kHouseGridMin && grid >= 2) {
+    static int cap_all = 0;
+    if (cap_all == 0) {
+      int dev = 0, ncu = 0, per_cu = 0;
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)householder_grid_kernel,
+                                                       256, 0) != hipSuccess)
+        return RSVD_EHIP;
+      cap_all = ncu * (per_cu > 0 ? per_cu : 1);
+    }
+    // concurrent runs: half of a fair share (as the other grid kernels)
+    const int cap = cap_all / (share > 1 ? 2 * share : 1);
+    if (grid > cap) grid = cap;
+    if (grid >= 2) {
+      hipLaunchKernelGGL(householder_grid_kernel, dim3(grid), dim3(256), 0, s, rows, (int)l, Yorig,
+                         Y, R, tau, scratch, st);
+      RSVD_LAUNCH_CHECK();
+      return RSVD_OK;
+    }
+  }
   hipLaunchKernelGGL(householder_kernel, dim3(1), dim3(kBig), 0, s, rows, (int)l, Yorig, Y, R,
                      tau, st);
   RSVD_LAUNCH_CHECK();

@@ -105,6 +105,28 @@ def test_orth_exactly_rank_deficient_uses_householder():
     assert np.abs(Q[:, :25] - oracle_orth(Y[:, :25])).max() <= 1e-12
 
 
+@pytest.mark.parametrize("rows,l,rank", [(3000, 300, 8), (1500, 96, 40), (700, 128, 0)])
+def test_orth_rank_deficient_large_panel_grid_householder(rows, l, rank):
+    # panels past the one-workgroup size take the fallback on a grid of
+    # workgroups: same contract (orthonormal Q, Q X = Y, diag(X) >= 0)
+    import paper_2307_15572_amd as rs
+    announce(f"orth rank-deficient {rows} x {l} (rank {rank}), grid Householder")
+    rng = np.random.default_rng(rows + l)
+    if rank:
+        Y = rng.standard_normal((rows, rank)) @ rng.standard_normal((rank, l))
+        Y[:, l - 5:] = 0.0
+    else:
+        Y = np.zeros((rows, l))
+        Y[:, 3] = rng.standard_normal(rows)
+    Q, X, flags = rs.orth(to_dev(Y))
+    Q = Q.cpu().numpy()
+    X = X.cpu().numpy()
+    assert flags & rs.FLAG_QR_FALLBACK
+    assert np.abs(Q.T @ Q - np.eye(l)).max() <= 1e-12
+    assert np.abs(Q @ X - Y).max() <= 1e-12 * max(np.abs(Y).max(), 1.0)
+    assert np.all(np.diag(X) >= 0) and np.allclose(np.tril(X, -1), 0)
+
+
 @pytest.mark.parametrize("l,decay", [(50, 1 / 16), (272, 1 / 40), (17, 0.5), (1, 0.0), (128, 1 / 20),
                                      (528, 1 / 64), (300, 1 / 30), (1250, 1 / 200)])
 def test_small_svd_matches_lapack(l, decay):
