@@ -468,8 +468,9 @@ __global__ void __launch_bounds__(512) chol_tiles_kernel(int l, double* __restri
     if (clamp) break;
     if (ok && pass == 0 && !use_shift && s_range[0] > 1e5 * s_range[1]) ok = false;
     if (ok) break;
-    if (pass != 0 || use_shift) {
-      // breakdown even with the shift: numerically rank-deficient panel
+    if (use_shift || pass == 2) {
+      // breakdown even with the shift (or in the last pass): numerically
+      // rank-deficient panel
       if (threadIdx.x == 0) st->qr_householder = 1;
       clamp = true;
       use_shift = true;
@@ -734,8 +735,9 @@ __global__ void __launch_bounds__(256) chol_grid_kernel(int l, double* __restric
     bool ok = !failed;
     if (ok && pass == 0 && !use_shift && st->piv_max > 1e5 * st->piv_min) ok = false;
     if (ok) break;
-    if (pass != 0 || use_shift) {
-      // breakdown even with the shift: numerically rank-deficient panel
+    if (use_shift || pass == 2) {
+      // breakdown even with the shift (or in the last pass): numerically
+      // rank-deficient panel
       if (gw == 0 && lane == 0) st->qr_householder = 1;
       clamp = true;
       use_shift = true;
