@@ -592,6 +592,14 @@ void dgemm_set_dma(bool on, int waves) {
   if (waves == 4 || waves == 8) g_dma_wm = waves;
 }
 
+bool dgemm_dma_eligible(int64_t K, int64_t N, const double* A, int64_t lda, const double* B,
+                        int64_t ldb) {
+  // whole K chunks, even N and 16-byte aligned rows: the LDS-DMA pipeline
+  const bool vec_a = (lda % 2 == 0) && ((uintptr_t)A % 16 == 0);
+  const bool vec_b = (ldb % 2 == 0) && ((uintptr_t)B % 16 == 0);
+  return (K % kBK == 0) && K > 0 && (N % 2 == 0) && N >= 2 && vec_a && vec_b && g_use_dma;
+}
+
 GemmShape dgemm_shape(int64_t M, int64_t N, int64_t K, int max_splits) {
   GemmShape s;
   const int64_t ntiles = (N + 15) / 16;
@@ -630,8 +638,7 @@ rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const 
   }
   const bool vec_a = (lda % 2 == 0) && ((uintptr_t)A % 16 == 0);
   const bool vec_b = (ldb % 2 == 0) && ((uintptr_t)B % 16 == 0);
-  // whole K chunks, even N and 16-byte aligned rows: the LDS-DMA pipeline
-  const bool dma_ok = !ta && (K % kBK == 0) && (N % 2 == 0) && N >= 2 && vec_a && vec_b && g_use_dma;
+  const bool dma_ok = !ta && dgemm_dma_eligible(K, N, A, lda, B, ldb);
   const TuneKey tkey{dma_ok ? kTuneDma : kTuneGeneric, prec, ta ? 1 : 0, M, N, K};
   if (pred == nullptr && tune_recording()) {
     // candidates: waves (LDS-DMA kernel) x split counts whose partials fit

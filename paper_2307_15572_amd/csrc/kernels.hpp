@@ -14,6 +14,10 @@ struct GemmShape {
 GemmShape dgemm_shape(int64_t M, int64_t N, int64_t K, int max_splits = 64);
 // select the LDS-DMA streaming kernel where eligible, with 4 or 8 waves per workgroup
 void dgemm_set_dma(bool on, int waves = 4);
+// whether an untransposed product of inner size K with N columns, A and B as
+// given, streams through the LDS-DMA kernel
+bool dgemm_dma_eligible(int64_t K, int64_t N, const double* A, int64_t lda, const double* B,
+                        int64_t ldb);
 rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                   int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                   double* part, size_t part_doubles, hipStream_t st, int max_splits = 64,

@@ -88,6 +88,11 @@ int64_t percent_rank(double pct, int64_t m, int64_t n) {
   return (int64_t)std::ceil(x * (1.0 - 1e-12));
 }
 
+// m n from which a transposed streaming product A^T X runs as (X^T A)^T on the
+// LDS-DMA kernel (below it the two extra transposes and launches do not pay)
+constexpr int64_t kTransStreamMin = (int64_t)1 << 24;
+constexpr int kTransSplits = 8;
+
 // Split-K scratch needed by the products of one run.
 size_t gemm_part_need(int64_t m, int64_t n, int64_t l) {
   size_t need = 0;
@@ -255,6 +260,12 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* worksp
   pl->off_Yorig = c.take((size_t)mx * l * D);
   pl->off_tau = c.take((size_t)2 * l * D);
   pl->part_doubles = gemm_part_need(m, n, l);
+  if (!p.symmetric && !adaptive && m * n >= kTransStreamMin) {
+    // A^T X as (X^T A)^T: its l output rows make few tiles; room for up to
+    // kTransSplits K splits so that the tuner can fill the device
+    const size_t need = (size_t)kTransSplits * l * n;
+    if (need > pl->part_doubles) pl->part_doubles = need;
+  }
   if (adaptive) {
     auto upd = [&](int64_t M, int64_t N, int64_t K) {
       const size_t need = dgemm_shape(M, N, K).part_doubles;
@@ -637,6 +648,20 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
       return bf16_gemm(sh, rows_out, l, trans ? Ath : Ah, trans ? Atl : Al,
                        trans ? pl.ld_at : pl.ld_an, XTh, XTl, out, l, fpart, pl.fpart_floats,
                        pl.bf16_split, s);
+    }
+    if (trans && rows_out * inner >= kTransStreamMin && l >= 16) {
+      // A^T X = (X^T A)^T: the LDS-DMA streaming kernel takes X^T A with A
+      // in its stored orientation, between two transposes of the skinny
+      // panels (X^T into T, the l x n product into Yorig; both are free
+      // between QRs)
+      double* Xt = w.at<double>(pl.off_T);
+      double* Ct = w.at<double>(pl.off_Yorig);
+      if (dgemm_dma_eligible(inner, rows_out, Xt, inner, A, lda)) {
+        RSVD_TRY(transpose(inner, l, X, ldx, Xt, inner, s));
+        RSVD_TRY(dgemm(false, l, rows_out, inner, 1.0, Xt, inner, A, lda, 0.0, Ct, rows_out, part,
+                       pl.part_doubles, s, 64, nullptr, prec));
+        return transpose(l, rows_out, Ct, rows_out, out, l, s);
+      }
     }
     return dgemm(trans, rows_out, l, inner, 1.0, A, lda, X, ldx, 0.0, out, l, part,
                  pl.part_doubles, s, 64, nullptr, prec);

@@ -73,6 +73,7 @@ def test_c1_workload():
     (200, 700, 30, 10, 2, 1 / 20),     # wide
     (3000, 400, 64, 16, 3, 1 / 64),    # tall, C3-like spectrum
     (1000, 1000, 100, 20, 0, 1 / 30),  # q = 0: the paper's method exactly
+    (8192, 2048, 128, 16, 2, 1 / 40),  # A^T X as (X^T A)^T on the streaming kernel
 ])
 def test_general_shapes(m, n, k, p, q, decay):
     announce(f"pipeline general {m}x{n} k={k} p={p} q={q}")
@@ -197,6 +198,15 @@ def test_mixed_fp32_general_tall():
     sig = synth.spectrum_pow10(400, 1 / 64)
     A = synth.general(3000, 400, sig, tag=701, noise=1e-9)
     rel, nrm, out, ref = _mixed_errors(A, 64, 16, 3, 5, False, "mixed_fp32", 1)
+    assert rel <= 1e-6, rel
+
+
+def test_mixed_fp32_general_transposed_stream():
+    # FP32 early products, A^T X taken as (X^T A)^T on the streaming kernel
+    announce("mixed fp32 general 8192 x 2048")
+    sig = synth.spectrum_pow10(2048, 1 / 20)
+    A = synth.general(8192, 2048, sig, tag=703, noise=1e-9)
+    rel, nrm, out, ref = _mixed_errors(A, 128, 16, 3, 5, False, "mixed_fp32", 1)
     assert rel <= 1e-6, rel
 
 
