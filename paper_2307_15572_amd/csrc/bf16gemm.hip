@@ -41,7 +41,7 @@ constexpr int kMaxNT = 17;   // column tiles per workgroup
 // column tiles with two fragments per wave: beyond these the accumulators,
 // the A ring and the operands exceed 256 VGPRs
 constexpr int kMaxNT2 = 16;
-constexpr int kMaxNTSplit2 = 11;
+constexpr int kMaxNTSplit2 = 10;
 
 inline int max_nt(int rw, bool split) { return rw == 1 ? kMaxNT : (split ? kMaxNTSplit2 : kMaxNT2); }
 
@@ -249,6 +249,19 @@ __global__ void __launch_bounds__(64 * kWavesB) bf16_stream_kernel(Bf16Args g) {
           for (int f = 0; f < RW; f++) acc[f][t] = mfma_bf16_32(a[f][0][h], bh, acc[f][t]);
         }
       }
+    }
+    // Software pipeline of the LDS reads: unit u = (h, t) is PL fragment
+    // reads and MPU products; the reads run kPF units ahead of the products
+    // that use them (left to itself the scheduler issues each read just
+    // before its product and waits for it, so every product waits the LDS
+    // latency). Scheduling-group masks: 0x100 LDS reads, 0x008 matrix ops.
+    constexpr int kU = NT * 2, kMPU = RW * (SPLIT ? 3 : 1), kPF = 4;
+#pragma unroll
+    for (int u = 0; u < kPF && u < kU; u++) __builtin_amdgcn_sched_group_barrier(0x100, PL, 0);
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      __builtin_amdgcn_sched_group_barrier(0x008, kMPU, 0);
+      if (u + kPF < kU) __builtin_amdgcn_sched_group_barrier(0x100, PL, 0);
     }
   };
   // A runs DA chunks ahead in a register ring, XT one chunk ahead in two LDS
