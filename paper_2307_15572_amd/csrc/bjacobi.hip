@@ -33,23 +33,7 @@ __device__ __forceinline__ void rr_pair_blk(int L, int step, int i, int& a, int&
   b = i == 0 ? step : mod_once(step - i + (L - 1), L - 1);
 }
 
-// 1/x and 1/sqrt(x) from the hardware estimates and two Newton steps each
-// (the estimates carry about half the FP64 mantissa; each step doubles it).
-__device__ __forceinline__ double rcp_nr(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  double e = fma(-x, y, 1.0);
-  y = fma(y, e, y);
-  e = fma(-x, y, 1.0);
-  return fma(y, e, y);
-}
-__device__ __forceinline__ double rsq_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  const double h = 0.5 * x;
-  double e = fma(-h * y, y, 0.5);
-  y = fma(y, e, y);
-  e = fma(-h * y, y, 0.5);
-  return fma(y, e, y);
-}
+
 
 struct JacArgs {
   int l, Lp, max_sweeps, inner_sweeps;

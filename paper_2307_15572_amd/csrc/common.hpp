@@ -82,6 +82,25 @@ __device__ __forceinline__ void wait_vm_lgkm() {
 
 
 // ---- wave reductions --------------------------------------------------------
+// 1/x and 1/sqrt(x) from the hardware estimates and two Newton steps each
+// (the estimates carry about half the FP64 mantissa; each step doubles it).
+// For normal x of moderate range (the callers keep x >= 1e-290).
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, y, 1.0);
+  y = fma(y, e, y);
+  e = fma(-x, y, 1.0);
+  return fma(y, e, y);
+}
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double h = 0.5 * x;
+  double e = fma(-h * y, y, 0.5);
+  y = fma(y, e, y);
+  e = fma(-h * y, y, 0.5);
+  return fma(y, e, y);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);

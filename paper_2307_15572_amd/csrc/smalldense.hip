@@ -187,12 +187,20 @@ __device__ bool tile_chol(double t[4], bool clamp, double clampv, int row0, int 
       ok = false;
       piv = 1.0;
     }
-    const double rjj = sqrt(piv);
+    // 1 / sqrt(piv) from the estimate and Newton steps (piv is the same in
+    // every lane, so the exact path for tiny pivots is a uniform branch)
+    double inv, rjj;
+    if (piv >= 1e-290) {
+      inv = rsq_nr(piv);
+      rjj = piv * inv;
+    } else {
+      rjj = sqrt(piv);
+      inv = 1.0 / rjj;
+    }
     if (row0 + j < lmax) {
       dmax = fmax(dmax, rjj);
       dmin = fmin(dmin, rjj);
     }
-    const double inv = 1.0 / rjj;
     if (g == jg) {
       if (r > j) t[jt] *= inv;
       else if (r == j) t[jt] = rjj;
@@ -229,7 +237,10 @@ __device__ void tile_inv_upper(const double t[4], double x[4]) {
     }
     part += __shfl_xor(part, 16, 64);
     part += __shfl_xor(part, 32, 64);
-    if (g == ig) x[ii] = (r == i) ? 1.0 / rii : (r > i ? -part / rii : 0.0);
+    // rii >= 2e-162: the square root of a positive double, or 1 for a
+    // failed pivot, so the reciprocal estimate is in range
+    const double ri = rcp_nr(rii);
+    if (g == ig) x[ii] = (r == i) ? ri : (r > i ? -part * ri : 0.0);
   }
 }
 
