@@ -81,7 +81,16 @@ size_t chol_panel_doubles(int64_t l);
 // (at most 1/share of the device's co-resident capacity, for runs on
 // concurrent streams).
 rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, double* scratch, int64_t m,
-                     int pass, int only_if_shifted, DevState* st, hipStream_t s, int share = 1);
+                     int pass, int only_if_shifted, DevState* st, hipStream_t s, int share = 1,
+                     bool full_inverse = true);
+// Q = Y R^{-1} (rows x l) by block forward substitution with R upper
+// triangular and Xd holding the inverses of R's 16 x 16 diagonal tiles (as
+// chol_inv writes them, with or without the full inverse); skipped when pred
+// is non-null and *pred == 0. Supported for l <= 320 (trsm_supported).
+bool trsm_supported(int64_t l);
+rsvd_status trsm_upper(int64_t rows, int64_t l, const double* Y, int64_t ldy, const double* R,
+                       const double* Xd, double* Q, int64_t ldq, const uint32_t* pred,
+                       hipStream_t s);
 // Householder QR of the rows x l panel Yorig into Y (= Q) and R, run only
 // when st->qr_householder is set (tau: 2 l doubles of scratch; scratch: l x l
 // doubles for the grid variant of large panels, may be null; share: runs on

@@ -151,19 +151,29 @@ rsvd_status orth(const rsvd_plan_s& pl, const Ws& w, int64_t rows, int64_t l, do
 #define RSVD_TRY(x) do { r = (x); if (r != RSVD_OK) return r; } while (0)
   RSVD_TRY(clear_shift(st, s));
   RSVD_TRY(copy_panel(rows, l, Y, l, Yorig, l, 0, st, s));
+  // Q = Y R^{-1}: block forward substitution with the diagonal tiles'
+  // inverses (the factorization then skips the full inverse), or a product
+  // with the full inverse beyond the substitution kernel's width
+  const bool tri = trsm_supported(l);
+  auto apply = [&](const double* src, const double* Rf, const double* Ri, double* dst,
+                   const uint32_t* pred) -> rsvd_status {
+    if (tri) return trsm_upper(rows, l, src, l, Rf, Ri, dst, l, pred, s);
+    return dgemm(false, rows, l, l, 1.0, src, l, Ri, l, 0.0, dst, l, part, pl.part_doubles, s, 64,
+                 pred);
+  };
   // pass 0
   RSVD_TRY(dgemm(true, l, l, rows, 1.0, Y, l, Y, l, 0.0, G, l, part, pl.part_doubles, s));
-  RSVD_TRY(chol_inv(l, G, R1, R1i, Rtmp, rows, 0, 0, st, s, pl.coop_share));
-  RSVD_TRY(dgemm(false, rows, l, l, 1.0, Y, l, R1i, l, 0.0, T, l, part, pl.part_doubles, s));
+  RSVD_TRY(chol_inv(l, G, R1, R1i, Rtmp, rows, 0, 0, st, s, pl.coop_share, !tri));
+  RSVD_TRY(apply(Y, R1, R1i, T, nullptr));
   // pass 1
   RSVD_TRY(dgemm(true, l, l, rows, 1.0, T, l, T, l, 0.0, G, l, part, pl.part_doubles, s, 64, p1));
-  RSVD_TRY(chol_inv(l, G, R2, R2i, Rtmp, rows, 1, full ? 0 : 1, st, s, pl.coop_share));
-  RSVD_TRY(dgemm(false, rows, l, l, 1.0, T, l, R2i, l, 0.0, Y, l, part, pl.part_doubles, s, 64, p1));
+  RSVD_TRY(chol_inv(l, G, R2, R2i, Rtmp, rows, 1, full ? 0 : 1, st, s, pl.coop_share, !tri));
+  RSVD_TRY(apply(T, R2, R2i, Y, p1));
   if (!full) RSVD_TRY(copy_panel(rows, l, T, l, Y, l, 2, st, s));  // unshifted: Q = T
   // pass 2 (device-predicated on the shift)
   RSVD_TRY(dgemm(true, l, l, rows, 1.0, Y, l, Y, l, 0.0, G, l, part, pl.part_doubles, s, 64, shifted));
-  RSVD_TRY(chol_inv(l, G, R3, R3i, Rtmp, rows, 2, 1, st, s, pl.coop_share));
-  RSVD_TRY(dgemm(false, rows, l, l, 1.0, Y, l, R3i, l, 0.0, T, l, part, pl.part_doubles, s, 64, shifted));
+  RSVD_TRY(chol_inv(l, G, R3, R3i, Rtmp, rows, 2, 1, st, s, pl.coop_share, !tri));
+  RSVD_TRY(apply(Y, R3, R3i, T, shifted));
   RSVD_TRY(copy_panel(rows, l, T, l, Y, l, 1, st, s));
   if (Rout) {
     // R = R2 R1, then R3 R when shifted

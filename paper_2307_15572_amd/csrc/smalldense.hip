@@ -7,6 +7,8 @@
 //   chol_inv      thin QR Z = Q X of step 1 (Cholesky QR: X^T X = Z^T Z)
 //   svd_finish    singular values ordered decreasingly (Eq. 1)
 //   select_rank   R_SVD, R% and the compression ratio of Eq. 2
+#include <utility>
+
 #include "common.hpp"
 #include "kernels.hpp"
 
@@ -442,7 +444,7 @@ __global__ void __launch_bounds__(512) chol_tiles_kernel(int l, double* __restri
                                                           double* __restrict__ Rinv,
                                                           double* __restrict__ panel_g, int64_t m,
                                                           int pass, int only_if_shifted,
-                                                          DevState* st) {
+                                                          int full_inverse, DevState* st) {
   extern __shared__ double lds[];
   __shared__ double red[kBig / 64];
   __shared__ int s_flag;
@@ -492,8 +494,9 @@ __global__ void __launch_bounds__(512) chol_tiles_kernel(int l, double* __restri
     __syncthreads();
   }
   if (pass == 0 && threadIdx.x == 0) st->prefer_shift = use_shift ? 1u : 0u;
-  // G is no longer read: it serves as scratch for the inverse
-  tiled_inverse(BlockTeam{}, cx, R, Rinv, G);
+  // G is no longer read: it serves as scratch for the inverse (without
+  // full_inverse only the diagonal tiles of Rinv, written above, are valid)
+  if (full_inverse) tiled_inverse(BlockTeam{}, cx, R, Rinv, G);
   // strictly lower parts are zero
   for (int64_t e = threadIdx.x; e < ll; e += blockDim.x) {
     if (e / l > e % l) {
@@ -589,7 +592,7 @@ __global__ void __launch_bounds__(256) chol_grid_kernel(int l, double* __restric
                                                          double* __restrict__ Rinv,
                                                          double* __restrict__ panel, int64_t m,
                                                          int pass, int only_if_shifted,
-                                                         DevState* st) {
+                                                         int full_inverse, DevState* st) {
   __shared__ double red[256 / 64];
   __shared__ int s_ok;
   if (only_if_shifted && st->qr_shifted == 0) return;
@@ -760,8 +763,9 @@ __global__ void __launch_bounds__(256) chol_grid_kernel(int l, double* __restric
     if (!tm.sync()) return;
   }
   if (pass == 0 && gw == 0 && lane == 0) st->prefer_shift = use_shift ? 1u : 0u;
-  // G is no longer read: it serves as scratch for the inverse
-  if (!tiled_inverse(tm, cx, R, Rinv, G)) return;
+  // G is no longer read: it serves as scratch for the inverse (without
+  // full_inverse only the diagonal tiles of Rinv are valid)
+  if (full_inverse && !tiled_inverse(tm, cx, R, Rinv, G)) return;
   for (int64_t e = gtid; e < ll; e += gthreads) {
     if (e / l > e % l) {
       R[e] = 0.0;
@@ -898,6 +902,132 @@ __global__ void __launch_bounds__(256) householder_grid_kernel(int64_t rows, int
   for (int64_t e = gtid; e < tot; e += gthreads)
     if (tau_buf[l + (int)(e % l)] < 0.0) W[e] = -W[e];
   if (gtid == 0) atomicOr(&st->flags, (uint32_t)RSVD_FLAG_QR_FALLBACK);
+}
+
+// ---------------------------------------------------------------------------
+// Q = Y R^{-1} for the upper-triangular factor R (l x l, row-major) by block
+// forward substitution over 16-column tiles, in transposed form
+//   Q_J^T = X_JJ^T (Y_J^T - sum_{K<J} R_KJ^T Q_K^T),   X_JJ = R_JJ^{-1}
+// (X_JJ: the diagonal tiles of Xd, written by the factorization). In this
+// form the FP64 accumulator layout of a result tile (lane (r, g), item t:
+// entry (g + 4 t, r)) is the B-operand layout the later tiles read, so a wave
+// keeps the Q^T tiles of its 16 rows in registers (l <= 16 kTrsmMaxNB). The
+// workgroup stages R's column block J (rows 0 .. 16 J - 1, 16 columns) in
+// LDS, double buffered. Rows past `rows` read as zero and are not stored;
+// columns past l act as identity.
+// ---------------------------------------------------------------------------
+constexpr int kTrsmMaxNB = 20;
+constexpr int kTrsmWaves = 4;
+
+struct TrsmCtx {
+  int64_t rows, ldy, ldq, row;
+  int l, nb, r, g;
+  bool row_ok;
+  const double* Y;
+  const double* R;
+  const double* Xd;
+  double* Q;
+  double* lds;
+};
+
+// Column tile J of the substitution (J a constant, so the register arrays
+// are indexed statically).
+template <int J>
+__device__ __forceinline__ void trsm_tile(const TrsmCtx& c, double (&qt)[kTrsmMaxNB][4]) {
+  constexpr int kT = 64 * kTrsmWaves;
+  constexpr int kU = (256 * (J + 1) + kT - 1) / kT;
+  if (J >= c.nb) return;
+  const int r = c.r, g = c.g, l = c.l;
+  // this thread's share of block J + 1 (rows 0 .. 16 J + 15 of columns
+  // 16 (J + 1) ..), loaded now and written to LDS after this block's
+  // products, so the loads overlap them
+  const bool more = J + 1 < c.nb;
+  double nxt[kU];
+#pragma unroll
+  for (int u = 0; u < kU; u++) {
+    const int e = (int)threadIdx.x + kT * u;
+    const int i = e >> 4, cc = 16 * (J + 1) + (e & 15);
+    nxt[u] = (more && e < 256 * (J + 1) && cc < l) ? c.R[(int64_t)i * l + cc] : 0.0;
+  }
+  d4 acc;
+  double xa[4];
+#pragma unroll
+  for (int t = 0; t < 4; t++) {
+    const int cc = 16 * J + g + 4 * t;
+    acc[t] = (c.row_ok && cc < l) ? c.Y[c.row * c.ldy + cc] : 0.0;
+    const int i = 16 * J + g + 4 * t, cd = 16 * J + r;
+    xa[t] = (i < l && cd < l) ? c.Xd[(int64_t)i * l + cd] : (i == cd ? 1.0 : 0.0);
+  }
+  if constexpr (J > 0) {
+    __syncthreads();  // block J written, block J - 1 no longer read
+    const double* Rb = c.lds + (size_t)(J & 1) * c.nb * 256;
+#pragma unroll
+    for (int K = 0; K < J; K++) {
+#pragma unroll
+      for (int s4 = 0; s4 < 4; s4++)
+        acc = mfma_f64_16x16x4(-Rb[(16 * K + g + 4 * s4) * 16 + r], qt[K][s4], acc);
+    }
+    // LDS reads of the R fragments run six products ahead of their use
+    // (masks: 0x100 LDS reads, 0x008 matrix ops)
+    constexpr int kPF = 6, kN = 4 * J;
+#pragma unroll
+    for (int u = 0; u < kPF && u < kN; u++) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+#pragma unroll
+    for (int u = 0; u < kN; u++) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      if (u + kPF < kN) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+  }
+  d4 out = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s4 = 0; s4 < 4; s4++) out = mfma_f64_16x16x4(xa[s4], acc[s4], out);
+#pragma unroll
+  for (int t = 0; t < 4; t++) {
+    qt[J][t] = out[t];
+    const int cc = 16 * J + g + 4 * t;
+    if (c.row_ok && cc < l) c.Q[c.row * c.ldq + cc] = out[t];
+  }
+  // block J + 1 into the other buffer (its last reader, block J - 1,
+  // finished before this block's barrier)
+  if (more) {
+    double* dst = c.lds + (size_t)((J + 1) & 1) * c.nb * 256;
+#pragma unroll
+    for (int u = 0; u < kU; u++) {
+      const int e = (int)threadIdx.x + kT * u;
+      if (e < 256 * (J + 1)) dst[e] = nxt[u];
+    }
+  }
+}
+
+template <int... Js>
+__device__ __forceinline__ void trsm_tiles(const TrsmCtx& c, double (&qt)[kTrsmMaxNB][4],
+                                           std::integer_sequence<int, Js...>) {
+  (trsm_tile<Js>(c, qt), ...);
+}
+
+__global__ void __launch_bounds__(64 * kTrsmWaves) trsm_upper_kernel(
+    int64_t rows, int l, const double* __restrict__ Y, int64_t ldy, const double* __restrict__ R,
+    const double* __restrict__ Xd, double* __restrict__ Q, int64_t ldq, const uint32_t* pred) {
+  extern __shared__ double lds[];
+  if (pred != nullptr && *pred == 0) return;
+  TrsmCtx c;
+  c.rows = rows;
+  c.ldy = ldy;
+  c.ldq = ldq;
+  c.l = l;
+  c.nb = (l + 15) / 16;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  c.r = lane & 15;
+  c.g = lane >> 4;
+  c.row = (int64_t)blockIdx.x * (16 * kTrsmWaves) + wave * 16 + c.r;
+  c.row_ok = c.row < rows;
+  c.Y = Y;
+  c.R = R;
+  c.Xd = Xd;
+  c.Q = Q;
+  c.lds = lds;
+  double qt[kTrsmMaxNB][4];
+  trsm_tiles(c, qt, std::make_integer_sequence<int, kTrsmMaxNB>{});
 }
 
 __global__ void __launch_bounds__(256) copy_panel_kernel(int64_t rows, int64_t cols,
@@ -1303,7 +1433,8 @@ size_t chol_panel_doubles(int64_t l) {
 }
 
 rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, double* scratch, int64_t m,
-                     int pass, int only_if_shifted, DevState* st, hipStream_t s, int share) {
+                     int pass, int only_if_shifted, DevState* st, hipStream_t s, int share,
+                     bool full_inverse) {
   allow_big_lds();
   if (l >= kCholGridMin && scratch) {
     // one 4-wave workgroup per ~32 tiles of the first trailing update, capped
@@ -1327,7 +1458,7 @@ rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, double* scra
     if (grid > cap) grid = cap;
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(chol_grid_kernel, dim3(grid), dim3(256), 0, s, (int)l, G, R, Rinv, scratch,
-                       m, pass, only_if_shifted, st);
+                       m, pass, only_if_shifted, full_inverse ? 1 : 0, st);
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
   }
@@ -1339,7 +1470,30 @@ rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, double* scra
     tl = 16 * 17 * sizeof(double);
   }
   hipLaunchKernelGGL(chol_tiles_kernel, dim3(1), dim3(512), tl, s, (int)l, G, R, Rinv, panel_g, m,
-                     pass, only_if_shifted, st);
+                     pass, only_if_shifted, full_inverse ? 1 : 0, st);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+bool trsm_supported(int64_t l) { return l >= 1 && (l + 15) / 16 <= kTrsmMaxNB; }
+
+rsvd_status trsm_upper(int64_t rows, int64_t l, const double* Y, int64_t ldy, const double* R,
+                       const double* Xd, double* Q, int64_t ldq, const uint32_t* pred,
+                       hipStream_t s) {
+  if (rows <= 0 || l <= 0) return RSVD_OK;
+  if (!trsm_supported(l) || ldy < l || ldq < l) return RSVD_EINVAL;
+  static bool attr = false;
+  if (!attr) {
+    attr = true;
+    (void)hipFuncSetAttribute((const void*)trsm_upper_kernel,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              2 * kTrsmMaxNB * 256 * (int)sizeof(double));
+  }
+  const int nb = (int)((l + 15) / 16);
+  const size_t lds = (size_t)2 * nb * 256 * sizeof(double);
+  const int64_t per = 16 * kTrsmWaves;
+  hipLaunchKernelGGL(trsm_upper_kernel, dim3((unsigned)((rows + per - 1) / per)),
+                     dim3(64 * kTrsmWaves), lds, s, rows, (int)l, Y, ldy, R, Xd, Q, ldq, pred);
   RSVD_LAUNCH_CHECK();
   return RSVD_OK;
 }
