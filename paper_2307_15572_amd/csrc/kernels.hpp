@@ -88,6 +88,12 @@ rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, double* scra
 // chol_inv writes them, with or without the full inverse); skipped when pred
 // is non-null and *pred == 0. Supported for l <= 320 (trsm_supported).
 bool trsm_supported(int64_t l);
+// G = Y^T Y (l x l, both triangles) of a rows x l panel by slabs of rows on
+// the matrix cores (upper tiles, per-slab partials in part, summed in a fixed
+// order) for l <= 272; the general product for wider panels or when part has
+// too little room; skipped when pred is non-null and *pred == 0.
+rsvd_status gram(int64_t rows, int64_t l, const double* Y, int64_t ldy, double* G, double* part,
+                 size_t part_doubles, const uint32_t* pred, hipStream_t s);
 rsvd_status trsm_upper(int64_t rows, int64_t l, const double* Y, int64_t ldy, const double* R,
                        const double* Xd, double* Q, int64_t ldq, const uint32_t* pred,
                        hipStream_t s);

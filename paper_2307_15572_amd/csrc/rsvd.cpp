@@ -162,16 +162,16 @@ rsvd_status orth(const rsvd_plan_s& pl, const Ws& w, int64_t rows, int64_t l, do
                  pred);
   };
   // pass 0
-  RSVD_TRY(dgemm(true, l, l, rows, 1.0, Y, l, Y, l, 0.0, G, l, part, pl.part_doubles, s));
+  RSVD_TRY(gram(rows, l, Y, l, G, part, pl.part_doubles, nullptr, s));
   RSVD_TRY(chol_inv(l, G, R1, R1i, Rtmp, rows, 0, 0, st, s, pl.coop_share, !tri));
   RSVD_TRY(apply(Y, R1, R1i, T, nullptr));
   // pass 1
-  RSVD_TRY(dgemm(true, l, l, rows, 1.0, T, l, T, l, 0.0, G, l, part, pl.part_doubles, s, 64, p1));
+  RSVD_TRY(gram(rows, l, T, l, G, part, pl.part_doubles, p1, s));
   RSVD_TRY(chol_inv(l, G, R2, R2i, Rtmp, rows, 1, full ? 0 : 1, st, s, pl.coop_share, !tri));
   RSVD_TRY(apply(T, R2, R2i, Y, p1));
   if (!full) RSVD_TRY(copy_panel(rows, l, T, l, Y, l, 2, st, s));  // unshifted: Q = T
   // pass 2 (device-predicated on the shift)
-  RSVD_TRY(dgemm(true, l, l, rows, 1.0, Y, l, Y, l, 0.0, G, l, part, pl.part_doubles, s, 64, shifted));
+  RSVD_TRY(gram(rows, l, Y, l, G, part, pl.part_doubles, shifted, s));
   RSVD_TRY(chol_inv(l, G, R3, R3i, Rtmp, rows, 2, 1, st, s, pl.coop_share, !tri));
   RSVD_TRY(apply(Y, R3, R3i, T, shifted));
   RSVD_TRY(copy_panel(rows, l, T, l, Y, l, 1, st, s));

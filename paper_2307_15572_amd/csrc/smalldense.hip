@@ -1030,6 +1030,139 @@ __global__ void __launch_bounds__(64 * kTrsmWaves) trsm_upper_kernel(
   trsm_tiles(c, qt, std::make_integer_sequence<int, kTrsmMaxNB>{});
 }
 
+// ---------------------------------------------------------------------------
+// Gram matrix G = Y^T Y of a rows x l panel on the FP64 matrix cores, upper
+// 16 x 16 tiles only. Workgroup (slab, group) sums the rows of its slab for
+// up to kGramWaves x kGramSlots upper tiles (tile t of the upper triangle,
+// row-major, goes to wave t mod kGramWaves, slot t / kGramWaves of its
+// group). Both MFMA operands of tile (I, J) are 4-row fragments of the same
+// rows (lane (r, g): Y[k + g][16 I + r] and Y[k + g][16 J + r]), read from
+// 32-row chunks staged in LDS (double buffered, the next chunk's loads in
+// registers while the current one is consumed). Each slab writes its tiles
+// to part[slab][t][256]; gram_reduce_kernel sums the slabs in order and
+// mirrors the lower triangle.
+// ---------------------------------------------------------------------------
+constexpr int kGramWaves = 16;
+constexpr int kGramSlots = 5;
+constexpr int kGramRows = 32;  // rows per LDS chunk (eight 4-row k-steps)
+constexpr int kGramMaxNB = 17;  // column tiles (l <= 272): chunk and prefetch sizes
+
+__global__ void __launch_bounds__(64 * kGramWaves) gram_kernel(int64_t rows, int l,
+                                                                const double* __restrict__ Y,
+                                                                int64_t ldy, int64_t per_slab,
+                                                                double* __restrict__ part,
+                                                                const uint32_t* pred) {
+  extern __shared__ double lds[];
+  if (pred != nullptr && *pred == 0) return;
+  constexpr int kT = 64 * kGramWaves;
+  const int nb = (l + 15) / 16, lp = 16 * nb;
+  const int ntiles = nb * (nb + 1) / 2;
+  const int slab = blockIdx.x;
+  // the wave index as a wave-uniform value: the tile coordinates below stay in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  const int64_t r0 = (int64_t)slab * per_slab;
+  const int64_t r1 = min(rows, r0 + per_slab);
+  const int nch = r1 > r0 ? (int)((r1 - r0 + kGramRows - 1) / kGramRows) : 0;
+  // this wave's tiles: the LDS column offsets of tile (I, J), 16 I and 16 J,
+  // packed in one word (0xffffffff: no tile)
+  uint32_t toff[kGramSlots];
+  const int t0 = (int)blockIdx.y * kGramWaves * kGramSlots + wave;
+#pragma unroll
+  for (int q = 0; q < kGramSlots; q++) {
+    const int t = t0 + q * kGramWaves;
+    int I = 0, J = 0;
+    if (t < ntiles) trailing_coords(t, nb, I, J);
+    toff[q] = t < ntiles ? (uint32_t)(16 * I) | ((uint32_t)(16 * J) << 16) : 0xffffffffu;
+  }
+  d4 acc[kGramSlots];
+#pragma unroll
+  for (int q = 0; q < kGramSlots; q++) acc[q] = d4{0.0, 0.0, 0.0, 0.0};
+  // a chunk is kGramRows x lp doubles: nu <= kMaxU per thread (registers)
+  constexpr int kMaxU = (kGramRows * 16 * kGramMaxNB + kT - 1) / kT;
+  const int nu = (kGramRows * lp + kT - 1) / kT;
+  double nxt[kMaxU];
+  auto load_chunk = [&](int c) {
+#pragma unroll
+    for (int u = 0; u < kMaxU; u++) {
+      if (u < nu) {
+        const int e = (int)threadIdx.x + kT * u;
+        const int i = e / lp, col = e % lp;
+        const int64_t row = r0 + (int64_t)kGramRows * c + i;
+        nxt[u] = (e < kGramRows * lp && row < r1 && col < l) ? Y[row * ldy + col] : 0.0;
+      }
+    }
+  };
+  auto store_chunk = [&](int b) {
+    double* dst = lds + (size_t)b * kGramRows * lp;
+#pragma unroll
+    for (int u = 0; u < kMaxU; u++) {
+      const int e = (int)threadIdx.x + kT * u;
+      if (u < nu && e < kGramRows * lp) dst[e] = nxt[u];
+    }
+  };
+  if (nch > 0) {
+    load_chunk(0);
+    store_chunk(0);
+  }
+  for (int c = 0; c < nch; c++) {
+    if (c + 1 < nch) load_chunk(c + 1);
+    __syncthreads();  // chunk c stored, chunk c - 1 no longer read
+    const double* buf = lds + (size_t)(c & 1) * kGramRows * lp;
+#pragma unroll
+    for (int s4 = 0; s4 < kGramRows / 4; s4++) {
+      const double* rowp = buf + (4 * s4 + g) * lp + r;
+#pragma unroll
+      for (int q = 0; q < kGramSlots; q++) {
+        if (toff[q] != 0xffffffffu)
+          acc[q] = mfma_f64_16x16x4(rowp[toff[q] & 0xffffu], rowp[toff[q] >> 16], acc[q]);
+      }
+    }
+    if (c + 1 < nch) store_chunk((c + 1) & 1);
+  }
+#pragma unroll
+  for (int q = 0; q < kGramSlots; q++) {
+    if (toff[q] != 0xffffffffu) {
+      double* dst = part + ((int64_t)slab * ntiles + (t0 + q * kGramWaves)) * 256;
+#pragma unroll
+      for (int t = 0; t < 4; t++) dst[(g + 4 * t) * 16 + r] = acc[q][t];
+    }
+  }
+}
+
+// G (l x l) = sum over the slabs of part, in slab order; the lower triangle
+// mirrored from the upper tiles.
+__global__ void __launch_bounds__(256) gram_reduce_kernel(int l, int slabs,
+                                                          const double* __restrict__ part,
+                                                          double* __restrict__ G,
+                                                          const uint32_t* pred) {
+  if (pred != nullptr && *pred == 0) return;
+  const int nb = (l + 15) / 16;
+  const int ntiles = nb * (nb + 1) / 2;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)ntiles * 256) return;
+  const int t = (int)(idx / 256), e = (int)(idx % 256);
+  // eight independent running sums (loads in flight together), combined in a
+  // fixed order: deterministic
+  const double* p = part + (int64_t)t * 256 + e;
+  const int64_t stride = (int64_t)ntiles * 256;
+  double v8[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  int sl = 0;
+  for (; sl + 8 <= slabs; sl += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; u++) v8[u] += p[(int64_t)(sl + u) * stride];
+  }
+  for (int u = 0; sl < slabs; sl++, u++) v8[u] += p[(int64_t)sl * stride];
+  const double v = ((v8[0] + v8[1]) + (v8[2] + v8[3])) + ((v8[4] + v8[5]) + (v8[6] + v8[7]));
+  int I, J;
+  trailing_coords(t, nb, I, J);
+  const int i = 16 * I + e / 16, j = 16 * J + e % 16;
+  if (i < l && j < l) {
+    G[(int64_t)i * l + j] = v;
+    if (I != J) G[(int64_t)j * l + i] = v;
+  }
+}
+
 __global__ void __launch_bounds__(256) copy_panel_kernel(int64_t rows, int64_t cols,
                                                          const double* __restrict__ src, int64_t lds,
                                                          double* __restrict__ dst, int64_t ldd,
@@ -1471,6 +1604,40 @@ rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, double* scra
   }
   hipLaunchKernelGGL(chol_tiles_kernel, dim3(1), dim3(512), tl, s, (int)l, G, R, Rinv, panel_g, m,
                      pass, only_if_shifted, full_inverse ? 1 : 0, st);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status gram(int64_t rows, int64_t l, const double* Y, int64_t ldy, double* G, double* part,
+                 size_t part_doubles, const uint32_t* pred, hipStream_t s) {
+  if (rows <= 0 || l <= 0) return RSVD_OK;
+  const int64_t nb = (l + 15) / 16;
+  const int64_t ntiles = nb * (nb + 1) / 2;
+  // enough (slab, tile group) workgroups for the device: slabs of at least
+  // 64 rows, as many as the partials' room allows
+  const int64_t groups = (ntiles + kGramWaves * kGramSlots - 1) / (kGramWaves * kGramSlots);
+  int64_t slabs = (rows + 63) / 64;
+  if (slabs > 256 / groups) slabs = 256 / groups;
+  const int64_t room = part ? (int64_t)(part_doubles / ((size_t)ntiles * 256)) : 0;
+  if (slabs > room) slabs = room;
+  if (nb > kGramMaxNB || slabs < 16 || ldy < l) {
+    // too little room or too wide: the general product
+    return dgemm(true, l, l, rows, 1.0, Y, ldy, Y, ldy, 0.0, G, l, part, part_doubles, s, 64, pred);
+  }
+  static bool attr = false;
+  if (!attr) {
+    attr = true;
+    (void)hipFuncSetAttribute((const void*)gram_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              2 * kGramRows * 16 * kGramMaxNB * (int)sizeof(double));
+  }
+  const int64_t per = ((rows + slabs - 1) / slabs + kGramRows - 1) / kGramRows * kGramRows;
+  slabs = (rows + per - 1) / per;
+  const size_t lds = (size_t)2 * kGramRows * 16 * nb * sizeof(double);
+  hipLaunchKernelGGL(gram_kernel, dim3((unsigned)slabs, (unsigned)groups), dim3(64 * kGramWaves),
+                     lds, s, rows, (int)l, Y, ldy, per, part, pred);
+  RSVD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3((unsigned)((ntiles * 256 + 255) / 256)), dim3(256),
+                     0, s, (int)l, (int)slabs, (const double*)part, G, pred);
   RSVD_LAUNCH_CHECK();
   return RSVD_OK;
 }
