@@ -724,10 +724,11 @@ rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const 
   return RSVD_OK;
 }
 
-// Column tiles per workgroup of the residual pass's narrow candidate: two
-// 4-wave workgroups of it fit on a CU (72 KB of LDS each), so one's epilogue
-// (the read of A) overlaps the other's products.
-constexpr int kResNarrowNT = 8;
+// Column tiles per workgroup of the residual pass's narrow candidates: two
+// workgroups of them fit on a CU, so one's epilogue (the read of A)
+// overlaps the other's products. kResNarrowNT is the narrowest.
+constexpr int kResNarrowNT = 4;
+constexpr int kResNarrow[] = {4, 6, 8, 12};
 
 size_t resid_partials(int64_t M, int64_t N) {
   GemmShape s = dgemm_shape(M, N, 1, 1);
@@ -756,9 +757,11 @@ rsvd_status resid(int64_t M, int64_t N, int64_t K, const double* US, int64_t ldu
     const TuneKey tkey{kTuneResid, kPrecF64, 0, M, N, K};
     if (tune_recording()) {
       std::vector<TuneCfg> cands = {{4, 0, 0}, {8, 0, 0}};
-      if (sh.nt > kResNarrowNT) {
-        cands.push_back({4, kResNarrowNT, 0});
-        cands.push_back({8, kResNarrowNT, 0});
+      for (int nt : kResNarrow) {
+        if (nt < sh.nt) {
+          cands.push_back({4, nt, 0});
+          cands.push_back({8, nt, 0});
+        }
       }
       tune_record(tkey, cands, [=](hipStream_t s2) {
         return resid(M, N, K, US, ldus, Vt, ldvt, A, lda, partial, st, s2);

@@ -159,7 +159,7 @@ def test_pinned_bf16_tiling(split, rows, splits, groups):
     assert np.abs(got - base).max() <= (terms + 2) * 2.0 ** -23 * mag.max()
 
 
-@pytest.mark.parametrize("waves,column_tiles", [(8, 0), (4, 0), (4, 8), (8, 8)])
+@pytest.mark.parametrize("waves,column_tiles", [(8, 0), (4, 0), (4, 8), (8, 8), (4, 4), (8, 6), (4, 12)])
 def test_pinned_residual_tiling(waves, column_tiles):
     # every residual tiling the tuner may choose gives the oracle's residual
     # (the tiling changes only the order of the FP64 sums)
