@@ -50,8 +50,8 @@ PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 matrix
 # FETCH_SIZE is scaled by 2.0 and WRITE_SIZE by 1.0: what the counters read
 # for a plain 1 GiB copy kernel. Valid only for the GEMM source they were
 # taken with; any other source reports traffic as null.
-TRAFFIC_SOURCE_SHA256 = "3560c8646b5e4108"
-TRAFFIC_FETCH_BYTES = 1135329 * 1024 * 2.0
+TRAFFIC_SOURCE_SHA256 = "22708e6b1645ad24"
+TRAFFIC_FETCH_BYTES = 1135019 * 1024 * 2.0
 TRAFFIC_WRITE_BYTES = 69632 * 1024 * 1.0
 
 
