@@ -246,6 +246,92 @@ __device__ void tile_inv_upper(const double t[4], double x[4]) {
   }
 }
 
+// Upper Cholesky of one tile held by a wave together with Z = R^{-T} (lower,
+// same layout): the row operations of the factorization (row j scaled by
+// 1 / r_jj, then row i > j less r_ji times row j) are L^{-1} for G = L L^T,
+// L = R^T, so applied to the identity beside G they leave L^{-1} = R^{-T}.
+// Row j of Z is final after step j, so the inverse costs one more shuffle
+// and four FMAs per step instead of a second 16-step substitution. Same
+// pivot handling and return value as tile_chol. The loop over the item
+// holding row j (j / 4) is not unrolled: its body selects that item, which
+// keeps the code and its live lane masks small inside a caller that holds
+// many tiles in registers.
+__device__ bool tile_chol_inv(d4& t, d4& z, bool clamp, double clampv, int row0,
+                              int lmax, double& dmax, double& dmin) {
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  bool ok = true;
+#pragma unroll
+  for (int it = 0; it < 4; it++) z[it] = (g + 4 * it == r) ? 1.0 : 0.0;
+#pragma unroll 1
+  for (int jt = 0; jt < 4; jt++) {
+#pragma unroll
+    for (int jg = 0; jg < 4; jg++) {
+      const int j = 4 * jt + jg;
+      double tj = t[0], zj = z[0];
+#pragma unroll
+      for (int it = 1; it < 4; it++) {
+        if (it == jt) {
+          tj = t[it];
+          zj = z[it];
+        }
+      }
+      double piv = __shfl(tj, j + 16 * jg, 64);
+      if (clamp && !(piv > clampv)) piv = clampv;
+      if (!(piv > 0.0) || !isfinite(piv)) {
+        ok = false;
+        piv = 1.0;
+      }
+      double inv, rjj;
+      if (piv >= 1e-290) {
+        inv = rsq_nr(piv);
+        rjj = piv * inv;
+      } else {
+        rjj = sqrt(piv);
+        inv = 1.0 / rjj;
+      }
+      if (row0 + j < lmax) {
+        dmax = fmax(dmax, rjj);
+        dmin = fmin(dmin, rjj);
+      }
+      if (g == jg) {
+        if (r > j) tj *= inv;
+        else if (r == j) tj = rjj;
+        zj *= inv;
+      }
+      const double colv = __shfl(tj, r + 16 * jg, 64);  // r_j,r
+      const double colz = __shfl(zj, r + 16 * jg, 64);  // z_j,r
+#pragma unroll
+      for (int it = 0; it < 4; it++) {
+        const int i = g + 4 * it;
+        const double rowv = __shfl(tj, i + 16 * jg, 64);  // r_j,i
+        double tv = t[it], zv = z[it];
+        if (it == jt && g == jg) {  // row j itself: scaled above
+          tv = tj;
+          zv = zj;
+        }
+        if (i > j) {
+          if (r >= i) tv -= rowv * colv;
+          zv -= rowv * colz;
+        }
+        t[it] = tv;
+        z[it] = zv;
+      }
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < 4; it++) {
+    if (g + 4 * it > r) t[it] = 0.0;
+    if (g + 4 * it < r) z[it] = 0.0;
+  }
+  return ok;
+}
+
+// x mod m in [0, m) for any int x (m > 0)
+__device__ __forceinline__ int mod_pos(int x, int m) {
+  const int q = x % m;
+  return q < 0 ? q + m : q;
+}
+
 __device__ __forceinline__ void trailing_coords(int t, int n, int& I, int& J) {
   // t-th tile of the upper triangle (row-major) of an n x n tile grid
   int row = 0, cnt = n;
@@ -506,6 +592,233 @@ __global__ void __launch_bounds__(512) chol_tiles_kernel(int l, double* __restri
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// The Cholesky for l <= 272 by one workgroup with the off-diagonal tiles of
+// the upper triangle resident in registers (tile t of the row-major strict
+// upper triangle in slot t / 8 of wave t % 8) and the diagonal tiles in LDS.
+// Block row k:
+//   every wave factors the (updated) diagonal tile k itself: R_kk and
+//     Z_kk = R_kk^{-T} together (tile_chol_inv), Z_kk through a private LDS
+//     tile into the operand layout
+//   its tiles of row k: R_kJ = Z_kk G_kJ, into the LDS panel and to R
+//   barrier
+//   its tiles with I > k: G_IJ -= R_kI^T R_kJ; diagonal tiles d > k (d mod 8
+//     = wave): G_dd -= R_kd^T R_kd in LDS
+//   barrier
+// The factorization is computed redundantly by every wave (identical inputs
+// and instructions, so identical results and decisions), which avoids a
+// third barrier and a broadcast per block row; its 16-column chain is the
+// only serial part. Only the diagonal tiles of Rinv are formed (what the
+// triangular solve of the QR uses); the strictly lower tiles of R and Rinv
+// are cleared. Pivot checks, shift and retries as in chol_tiles_kernel.
+// ---------------------------------------------------------------------------
+constexpr int kCholRegMaxNB = 17;
+constexpr int kCholRegWaves = 8;
+constexpr int kCholRegSlots =
+    (kCholRegMaxNB * (kCholRegMaxNB - 1) / 2 + kCholRegWaves - 1) / kCholRegWaves;  // 17
+
+__global__ void __launch_bounds__(64 * kCholRegWaves) chol_reg_kernel(
+    int l, const double* __restrict__ G, double* __restrict__ R, double* __restrict__ Rinv,
+    int64_t m, int pass, int only_if_shifted, DevState* st) {
+  constexpr int kPs = 16 * kCholRegMaxNB + 1;
+  __shared__ double panel[16 * kPs];
+  // diagonal tiles: item it of lane x of tile d at [256 d + 64 it + x]
+  __shared__ double diag[kCholRegMaxNB * 256];
+  __shared__ double zl[kCholRegWaves][16 * 17];  // each wave's Z_kk, row-major
+  __shared__ double red[kCholRegWaves];
+  __shared__ int s_flag;
+  __shared__ double s_range[2];
+  if (only_if_shifted && st->qr_shifted == 0) return;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  TileCtx cx;
+  cx.l = l;
+  cx.nb = (l + 15) / 16;
+  cx.ps = kPs;
+  const int nb = cx.nb;
+  const int noff = nb * (nb - 1) / 2;
+
+  // slot coordinates (I << 8 | J), -1 for an empty slot; wave-uniform
+  int crd[kCholRegSlots];
+  {
+    int t = wave, I = 0, J = 1, cur = 0;  // (I, J): tile `cur` of the strict upper triangle
+#pragma unroll
+    for (int s = 0; s < kCholRegSlots; s++) {
+      if (t < noff) {
+        while (cur < t) {
+          cur++;
+          if (++J >= nb) {
+            I++;
+            J = I + 1;
+          }
+        }
+        crd[s] = I << 8 | J;
+      } else {
+        crd[s] = -1;
+      }
+      t += kCholRegWaves;
+    }
+  }
+
+  double tr = 0.0;
+  for (int i = threadIdx.x; i < l; i += blockDim.x) tr += G[(int64_t)i * l + i];
+  tr = block_sum(tr, red);
+  const double shift = 11.0 * ((double)m * l + (double)l * (l + 1)) * kUnitRoundoff * tr;
+  const double clampv = fmax(shift, 1e-300);
+
+  bool use_shift = pass == 0 && st->prefer_shift != 0u, clamp = false;
+  if (use_shift && threadIdx.x == 0) st->qr_shifted = 1;
+  d4 tl[kCholRegSlots];  // one MFMA accumulator per slot
+  for (int attempt = 0; attempt < 3; attempt++) {
+    double dmax = 0.0, dmin = INFINITY;
+    if (threadIdx.x == 0) s_flag = 0;
+    // off-diagonal tiles of G (zero beyond l): a uniform base per tile and
+    // one lane offset for all
+#pragma unroll
+    for (int s = 0; s < kCholRegSlots; s++) {
+      crd[s] = __builtin_amdgcn_readfirstlane(crd[s]);
+      asm volatile("" : "+s"(crd[s]));
+      if (crd[s] >= 0) {
+        const int I = crd[s] >> 8, J = crd[s] & 255;
+        const double* base = G + (int64_t)16 * I * l + 16 * J;
+        if (16 * I + 16 <= l && 16 * J + 16 <= l) {
+#pragma unroll
+          for (int it = 0; it < 4; it++) tl[s][it] = base[(g + 4 * it) * l + r];
+        } else {
+#pragma unroll
+          for (int it = 0; it < 4; it++) {
+            const int i = 16 * I + g + 4 * it, c = 16 * J + r;
+            tl[s][it] = cx.in(i, c) ? base[(g + 4 * it) * l + r] : 0.0;
+          }
+        }
+      }
+    }
+    // diagonal tiles of G (+ shift; identity beyond l)
+    for (int d = wave; d < nb; d += kCholRegWaves) {
+#pragma unroll
+      for (int it = 0; it < 4; it++) {
+        const int i = 16 * d + g + 4 * it, c = 16 * d + r;
+        double v = cx.in(i, c) ? G[(int64_t)i * l + c] : (i == c ? 1.0 : 0.0);
+        if (use_shift && i == c && i < l) v += shift;
+        diag[256 * d + 64 * it + lane] = v;
+      }
+    }
+    __syncthreads();
+    bool failed = false;
+    for (int k = 0; k < nb; k++) {
+      // opaque per-step copies of the slot coordinates, the lane and l: keeps
+      // the compiler from hoisting per-slot addresses and lane masks out of
+      // this loop (hundreds of them would stay live beside the tiles)
+      int ln = lane, lk = l;
+      asm volatile("" : "+v"(ln));
+      asm volatile("" : "+s"(lk));
+      const int rr = ln & 15, gg = ln >> 4;
+      TileCtx ck = cx;
+      ck.l = lk;
+#pragma unroll
+      for (int s = 0; s < kCholRegSlots; s++) {
+        crd[s] = __builtin_amdgcn_readfirstlane(crd[s]);
+        asm volatile("" : "+s"(crd[s]));
+      }
+      // ---- diagonal tile k (every wave)
+      {
+        d4 t, z;
+#pragma unroll
+        for (int it = 0; it < 4; it++) t[it] = diag[256 * k + 64 * it + ln];
+        const bool ok = tile_chol_inv(t, z, clamp, clampv, 16 * k, lk, dmax, dmin);
+        if (wave == 0) {
+          double o[4] = {t[0], t[1], t[2], t[3]};
+          store_tile(ck, R, k, k, o);
+#pragma unroll
+          for (int it = 0; it < 4; it++) {
+            // X = Z^T: lane (r, g) item it holds x_{r, g + 4 it}
+            const int i = 16 * k + rr, c = 16 * k + gg + 4 * it;
+            if (ck.in(i, c)) Rinv[(int64_t)i * lk + c] = z[it];
+          }
+          if (!ok && ln == 0) s_flag = 1;
+        }
+        // Z_kk into the operand layout through this wave's LDS tile
+#pragma unroll
+        for (int it = 0; it < 4; it++) zl[wave][(gg + 4 * it) * 17 + rr] = z[it];
+      }
+      // ---- this wave's tiles of block row k: R_kJ = Z_kk G_kJ
+#pragma unroll
+      for (int s = 0; s < kCholRegSlots; s++) {
+        if (crd[s] >= 0 && (crd[s] >> 8) == k) {
+          const int J = crd[s] & 255;
+          d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+          for (int s4 = 0; s4 < 4; s4++)
+            acc = mfma_f64_16x16x4(zl[wave][rr * 17 + 4 * s4 + gg], tl[s][s4], acc);
+          tl[s] = acc;
+          double o[4];
+#pragma unroll
+          for (int it = 0; it < 4; it++) {
+            o[it] = acc[it];
+            panel[(gg + 4 * it) * kPs + 16 * J + rr] = acc[it];
+          }
+          store_tile(ck, R, k, J, o);
+        }
+      }
+      __syncthreads();
+      failed = s_flag != 0;
+      if (failed) break;
+      // ---- trailing tiles
+#pragma unroll
+      for (int s = 0; s < kCholRegSlots; s++) {
+        if (crd[s] >= 0 && (crd[s] >> 8) > k) {
+          const int I = crd[s] >> 8, J = crd[s] & 255;
+#pragma unroll
+          for (int s4 = 0; s4 < 4; s4++) {
+            const double a = -panel[(4 * s4 + gg) * kPs + 16 * I + rr];
+            const double b = panel[(4 * s4 + gg) * kPs + 16 * J + rr];
+            tl[s] = mfma_f64_16x16x4(a, b, tl[s]);
+          }
+        }
+      }
+      for (int d = k + 1 + mod_pos(wave - k - 1, kCholRegWaves); d < nb; d += kCholRegWaves) {
+        d4 acc;
+#pragma unroll
+        for (int it = 0; it < 4; it++) acc[it] = diag[256 * d + 64 * it + ln];
+#pragma unroll
+        for (int s4 = 0; s4 < 4; s4++) {
+          const double b = panel[(4 * s4 + gg) * kPs + 16 * d + rr];
+          acc = mfma_f64_16x16x4(-b, b, acc);
+        }
+#pragma unroll
+        for (int it = 0; it < 4; it++) diag[256 * d + 64 * it + ln] = acc[it];
+      }
+      // strictly lower tiles of tile row k of R and Rinv (16 rows, 16 k columns)
+      const int rows = min(16, lk - 16 * k), cols = 16 * k;
+      for (int e = threadIdx.x; e < rows * cols; e += 64 * kCholRegWaves) {
+        const int64_t o = (int64_t)(16 * k + e / cols) * lk + e % cols;
+        R[o] = 0.0;
+        Rinv[o] = 0.0;
+      }
+      __syncthreads();
+    }
+    if (wave == 0 && lane == 0) {
+      s_range[0] = dmax;
+      s_range[1] = dmin;
+    }
+    __syncthreads();
+    if (clamp) break;
+    bool ok = !failed;
+    if (ok && pass == 0 && !use_shift && s_range[0] > 1e5 * s_range[1]) ok = false;
+    if (ok) break;
+    if (use_shift || pass == 2) {
+      if (threadIdx.x == 0) st->qr_householder = 1;
+      clamp = true;
+      use_shift = true;
+    } else {
+      use_shift = true;
+      if (threadIdx.x == 0) st->qr_shifted = 1;
+    }
+    __syncthreads();
+  }
+  if (pass == 0 && threadIdx.x == 0) st->prefer_shift = use_shift ? 1u : 0u;
+}
 
 // ---------------------------------------------------------------------------
 // The same Cholesky and inverse spread over a grid of workgroups (large l),
@@ -1569,6 +1882,12 @@ rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, double* scra
                      int pass, int only_if_shifted, DevState* st, hipStream_t s, int share,
                      bool full_inverse) {
   allow_big_lds();
+  if (!full_inverse && l <= 16 * kCholRegMaxNB) {
+    hipLaunchKernelGGL(chol_reg_kernel, dim3(1), dim3(64 * kCholRegWaves), 0, s, (int)l, G, R,
+                       Rinv, m, pass, only_if_shifted, st);
+    RSVD_LAUNCH_CHECK();
+    return RSVD_OK;
+  }
   if (l >= kCholGridMin && scratch) {
     // one 4-wave workgroup per ~32 tiles of the first trailing update, capped
     // so the grids of concurrent runs fit on the device together

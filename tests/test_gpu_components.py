@@ -52,7 +52,8 @@ def test_dgemm_matches_numpy(ta, m, n, k):
 
 @pytest.mark.parametrize("m,l,decay", [(500, 50, 1 / 16), (4096, 272, 1 / 40), (3000, 100, 1 / 8),
                                        (200, 200, 1 / 64), (20, 1, 0.1), (2000, 528, 1 / 64),
-                                       (1500, 33, 0.05), (2600, 1250, 1 / 200)])
+                                       (1500, 33, 0.05), (2600, 1250, 1 / 200), (3000, 257, 1 / 40),
+                                       (700, 16, 0.1), (900, 17, 0.05), (5000, 271, 1 / 50)])
 def test_orth_matches_oracle(m, l, decay):
     import paper_2307_15572_amd as rs
     announce(f"orth m={m} l={l} decay={decay}")
