@@ -151,40 +151,41 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
 
   // ---- two-sided Jacobi on H, V accumulates the rotations. A round applies
   // 16 disjoint plane rotations J_k on both sides, H <- J^T H J, V <- V J:
-  // 16 lanes form the round's rotations from H into LDS (each once), then
   // thread (k, m) applies J_k^T and J_m to the 2 x 2 block of H at rows
   // {p_k, q_k} and columns {p_m, q_m} (the arithmetic, in the same order, of
   // a row pass followed by a column pass) and J_m to the same entries of V.
-  // The blocks partition H and V, so both are updated in place.
+  // Every lane forms the rotation of its column pair m itself (each wave
+  // holds all 16) and takes J_k from lane k of its wave by a shuffle, so a
+  // round needs no exchange through LDS; H is double buffered (a round reads
+  // one buffer and writes the other, since other threads read the diagonal
+  // entries of a block its owner rewrites), which leaves one barrier per
+  // round. The blocks partition V, so V is updated in place.
   double (*V)[33] = Vb[0];
-  double* rc = &Hb[1][0][0];  // rotation cosines and sines of the round (Hb[1] is free)
-  double* rs = rc + 16;
   for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x)
     V[e / 32][e % 32] = (e / 32 == e % 32) ? 1.0 : 0.0;
   __syncthreads();
   {
     const int k = threadIdx.x >> 4, mm = threadIdx.x & 15;
+    int cur = 0;
     for (int isw = 0; isw < a.inner_sweeps; isw++) {
       for (int round = 0; round < 31; round++) {
-        if (threadIdx.x < 16) {
-          int p0, q0;
-          rr_pair_blk(32, round, (int)threadIdx.x, p0, q0);
-          if (p0 > q0) { const int t = p0; p0 = q0; q0 = t; }
-          double c, sn;
-          jac_rot(H[p0][p0], H[q0][q0], H[p0][q0], tol, c, sn);
-          rc[threadIdx.x] = c;
-          rs[threadIdx.x] = sn;
-        }
-        __syncthreads();
+        double (*Hc)[33] = Hb[cur];
+        double (*Hn)[33] = Hb[cur ^ 1];
         int pk, qk, pm, qm;
         rr_pair_blk(32, round, k, pk, qk);
         if (pk > qk) { const int t = pk; pk = qk; qk = t; }
         rr_pair_blk(32, round, mm, pm, qm);
         if (pm > qm) { const int t = pm; pm = qm; qm = t; }
-        const double ck = rc[k], sk = rs[k], cm = rc[mm], sm = rs[mm];
+        // all reads of the round first: the rotation's three entries and
+        // this thread's blocks of H and V
+        const double dpp = Hc[pm][pm], dqq = Hc[qm][qm], dpq = Hc[pm][qm];
+        double hpp = Hc[pk][pm], hpq = Hc[pk][qm], hqp = Hc[qk][pm], hqq = Hc[qk][qm];
+        double vpp = V[pk][pm], vpq = V[pk][qm], vqp = V[qk][pm], vqq = V[qk][qm];
+        double cm, sm;
+        jac_rot(dpp, dqq, dpq, tol, cm, sm);
+        const double ck = __shfl(cm, k & 15, 64), sk = __shfl(sm, k & 15, 64);
         // rows: J_k^T, then columns: J_m (an identity rotation, c = 1 and
         // s = 0, leaves finite entries exactly as they are)
-        double hpp = H[pk][pm], hpq = H[pk][qm], hqp = H[qk][pm], hqq = H[qk][qm];
         {
           const double a0 = ck * hpp - sk * hqp, a1 = sk * hpp + ck * hqp;
           const double b0 = ck * hpq - sk * hqq, b1 = sk * hpq + ck * hqq;
@@ -195,11 +196,10 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
           const double b0 = cm * hqp - sm * hqq, b1 = sm * hqp + cm * hqq;
           hpp = a0; hpq = a1; hqp = b0; hqq = b1;
         }
-        H[pk][pm] = hpp;
-        H[pk][qm] = hpq;
-        H[qk][pm] = hqp;
-        H[qk][qm] = hqq;
-        double vpp = V[pk][pm], vpq = V[pk][qm], vqp = V[qk][pm], vqq = V[qk][qm];
+        Hn[pk][pm] = hpp;
+        Hn[pk][qm] = hpq;
+        Hn[qk][pm] = hqp;
+        Hn[qk][qm] = hqq;
         {
           const double a0 = cm * vpp - sm * vpq, a1 = sm * vpp + cm * vpq;
           const double b0 = cm * vqp - sm * vqq, b1 = sm * vqp + cm * vqq;
@@ -209,6 +209,7 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
         V[pk][qm] = vpq;
         V[qk][pm] = vqp;
         V[qk][qm] = vqq;
+        cur ^= 1;
         __syncthreads();
       }
     }

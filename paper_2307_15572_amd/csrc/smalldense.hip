@@ -250,73 +250,73 @@ __device__ void tile_inv_upper(const double t[4], double x[4]) {
 // same layout): the row operations of the factorization (row j scaled by
 // 1 / r_jj, then row i > j less r_ji times row j) are L^{-1} for G = L L^T,
 // L = R^T, so applied to the identity beside G they leave L^{-1} = R^{-T}.
-// Row j of Z is final after step j, so the inverse costs one more shuffle
-// and four FMAs per step instead of a second 16-step substitution. Same
-// pivot handling and return value as tile_chol. The loop over the item
-// holding row j (j / 4) is not unrolled: its body selects that item, which
-// keeps the code and its live lane masks small inside a caller that holds
-// many tiles in registers.
-__device__ bool tile_chol_inv(d4& t, d4& z, bool clamp, double clampv, int row0,
+// Row j of Z is final after step j, so the inverse costs a few more FMAs per
+// step instead of a second 16-step substitution. The pivot is read from its
+// lane into scalar registers; row j of R and Z goes through the wave's own
+// 32 doubles of LDS (rowbuf), which every lane then reads by broadcast
+// (LDS operations of one wave complete in order, so no barrier is needed).
+// Same pivot handling and return value as tile_chol.
+__device__ bool tile_chol_inv(d4& t, d4& z, double* rowbuf, bool clamp, double clampv, int row0,
                               int lmax, double& dmax, double& dmin) {
-  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  // an opaque lane index: the lane masks below are formed here, not hoisted
+  // into the caller's loops (where they would stay live beside its tiles)
+  int lane = threadIdx.x & 63;
+  asm volatile("" : "+v"(lane));
+  const int r = lane & 15, g = lane >> 4;
   bool ok = true;
 #pragma unroll
   for (int it = 0; it < 4; it++) z[it] = (g + 4 * it == r) ? 1.0 : 0.0;
-#pragma unroll 1
-  for (int jt = 0; jt < 4; jt++) {
 #pragma unroll
-    for (int jg = 0; jg < 4; jg++) {
-      const int j = 4 * jt + jg;
-      double tj = t[0], zj = z[0];
-#pragma unroll
-      for (int it = 1; it < 4; it++) {
-        if (it == jt) {
-          tj = t[it];
-          zj = z[it];
-        }
-      }
-      double piv = __shfl(tj, j + 16 * jg, 64);
-      if (clamp && !(piv > clampv)) piv = clampv;
-      if (!(piv > 0.0) || !isfinite(piv)) {
-        ok = false;
-        piv = 1.0;
-      }
-      double inv, rjj;
-      if (piv >= 1e-290) {
-        inv = rsq_nr(piv);
-        rjj = piv * inv;
-      } else {
-        rjj = sqrt(piv);
-        inv = 1.0 / rjj;
-      }
-      if (row0 + j < lmax) {
-        dmax = fmax(dmax, rjj);
-        dmin = fmin(dmin, rjj);
-      }
-      if (g == jg) {
-        if (r > j) tj *= inv;
-        else if (r == j) tj = rjj;
-        zj *= inv;
-      }
-      const double colv = __shfl(tj, r + 16 * jg, 64);  // r_j,r
-      const double colz = __shfl(zj, r + 16 * jg, 64);  // z_j,r
-#pragma unroll
-      for (int it = 0; it < 4; it++) {
-        const int i = g + 4 * it;
-        const double rowv = __shfl(tj, i + 16 * jg, 64);  // r_j,i
-        double tv = t[it], zv = z[it];
-        if (it == jt && g == jg) {  // row j itself: scaled above
-          tv = tj;
-          zv = zj;
-        }
-        if (i > j) {
-          if (r >= i) tv -= rowv * colv;
-          zv -= rowv * colz;
-        }
-        t[it] = tv;
-        z[it] = zv;
-      }
+  for (int j = 0; j < 16; j++) {
+    const int jg = j & 3, jt = j >> 2;
+    // entry (j, j): item jt of lane j + 16 jg
+    const int src = j + 16 * jg;
+    const double tv = t[jt];
+    const uint64_t bits = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(
+                               (int)(__double_as_longlong(tv) >> 32), src)
+                           << 32) |
+                          (uint32_t)__builtin_amdgcn_readlane((int)__double_as_longlong(tv), src);
+    double piv = __longlong_as_double((long long)bits);
+    if (clamp && !(piv > clampv)) piv = clampv;
+    if (!(piv > 0.0) || !isfinite(piv)) {
+      ok = false;
+      piv = 1.0;
     }
+    double inv, rjj;
+    if (piv >= 1e-290) {
+      inv = rsq_nr(piv);
+      rjj = piv * inv;
+    } else {
+      rjj = sqrt(piv);
+      inv = 1.0 / rjj;
+    }
+    if (row0 + j < lmax) {
+      dmax = fmax(dmax, rjj);
+      dmin = fmin(dmin, rjj);
+    }
+    if (g == jg) {
+      if (r > j) t[jt] *= inv;
+      else if (r == j) t[jt] = rjj;
+      z[jt] *= inv;
+      rowbuf[r] = t[jt];       // r_j,r
+      rowbuf[16 + r] = z[jt];  // z_j,r
+    }
+    __builtin_amdgcn_wave_barrier();
+    // all six reads in flight together, then a branch-free update
+    const double colv = rowbuf[r];
+    const double colz = rowbuf[16 + r];
+    double rowv[4];
+#pragma unroll
+    for (int it = 0; it < 4; it++) rowv[it] = rowbuf[g + 4 * it];  // r_j,i
+#pragma unroll
+    for (int it = 0; it < 4; it++) {
+      const int i = g + 4 * it;
+      const double tn = fma(-rowv[it], colv, t[it]);
+      const double zn = fma(-rowv[it], colz, z[it]);
+      t[it] = (i > j && r >= i) ? tn : t[it];
+      z[it] = i > j ? zn : z[it];
+    }
+    __builtin_amdgcn_wave_barrier();
   }
 #pragma unroll
   for (int it = 0; it < 4; it++) {
@@ -625,7 +625,8 @@ __global__ void __launch_bounds__(64 * kCholRegWaves) chol_reg_kernel(
   __shared__ double panel[16 * kPs];
   // diagonal tiles: item it of lane x of tile d at [256 d + 64 it + x]
   __shared__ double diag[kCholRegMaxNB * 256];
-  __shared__ double zl[kCholRegWaves][16 * 17];  // each wave's Z_kk, row-major
+  __shared__ double zl[4][16 * 17];  // Z_kk of waves 0..3, row-major
+  __shared__ double rowbuf[4][32];  // current row of R_kk and Z_kk, waves 0..3
   __shared__ double red[kCholRegWaves];
   __shared__ int s_flag;
   __shared__ double s_range[2];
@@ -670,6 +671,14 @@ __global__ void __launch_bounds__(64 * kCholRegWaves) chol_reg_kernel(
   bool use_shift = pass == 0 && st->prefer_shift != 0u, clamp = false;
   if (use_shift && threadIdx.x == 0) st->qr_shifted = 1;
   d4 tl[kCholRegSlots];  // one MFMA accumulator per slot
+  // barrier for LDS traffic only: the stores of R and Rinv are not read in
+  // this kernel, so the waves do not wait for them at every block row
+  auto lds_barrier = [] {
+    asm volatile("" ::: "memory");
+    wait_vm_lgkm<63, 0>();
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+  };
   for (int attempt = 0; attempt < 3; attempt++) {
     double dmax = 0.0, dmin = INFINITY;
     if (threadIdx.x == 0) s_flag = 0;
@@ -704,7 +713,7 @@ __global__ void __launch_bounds__(64 * kCholRegWaves) chol_reg_kernel(
         diag[256 * d + 64 * it + lane] = v;
       }
     }
-    __syncthreads();
+    lds_barrier();
     bool failed = false;
     for (int k = 0; k < nb; k++) {
       // opaque per-step copies of the slot coordinates, the lane and l: keeps
@@ -721,12 +730,14 @@ __global__ void __launch_bounds__(64 * kCholRegWaves) chol_reg_kernel(
         crd[s] = __builtin_amdgcn_readfirstlane(crd[s]);
         asm volatile("" : "+s"(crd[s]));
       }
-      // ---- diagonal tile k (every wave)
-      {
+      // ---- diagonal tile k: waves 0..3 (one per SIMD) factor it, each into
+      // its own LDS copy of Z_kk (identical), which the waves sharing its
+      // SIMD read after the barrier
+      if (wave < 4) {
         d4 t, z;
 #pragma unroll
         for (int it = 0; it < 4; it++) t[it] = diag[256 * k + 64 * it + ln];
-        const bool ok = tile_chol_inv(t, z, clamp, clampv, 16 * k, lk, dmax, dmin);
+        const bool ok = tile_chol_inv(t, z, rowbuf[wave], clamp, clampv, 16 * k, lk, dmax, dmin);
         if (wave == 0) {
           double o[4] = {t[0], t[1], t[2], t[3]};
           store_tile(ck, R, k, k, o);
@@ -742,6 +753,7 @@ __global__ void __launch_bounds__(64 * kCholRegWaves) chol_reg_kernel(
 #pragma unroll
         for (int it = 0; it < 4; it++) zl[wave][(gg + 4 * it) * 17 + rr] = z[it];
       }
+      lds_barrier();
       // ---- this wave's tiles of block row k: R_kJ = Z_kk G_kJ
 #pragma unroll
       for (int s = 0; s < kCholRegSlots; s++) {
@@ -750,7 +762,7 @@ __global__ void __launch_bounds__(64 * kCholRegWaves) chol_reg_kernel(
           d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
           for (int s4 = 0; s4 < 4; s4++)
-            acc = mfma_f64_16x16x4(zl[wave][rr * 17 + 4 * s4 + gg], tl[s][s4], acc);
+            acc = mfma_f64_16x16x4(zl[wave & 3][rr * 17 + 4 * s4 + gg], tl[s][s4], acc);
           tl[s] = acc;
           double o[4];
 #pragma unroll
@@ -761,7 +773,7 @@ __global__ void __launch_bounds__(64 * kCholRegWaves) chol_reg_kernel(
           store_tile(ck, R, k, J, o);
         }
       }
-      __syncthreads();
+      lds_barrier();
       failed = s_flag != 0;
       if (failed) break;
       // ---- trailing tiles
@@ -791,12 +803,15 @@ __global__ void __launch_bounds__(64 * kCholRegWaves) chol_reg_kernel(
       }
       // strictly lower tiles of tile row k of R and Rinv (16 rows, 16 k columns)
       const int rows = min(16, lk - 16 * k), cols = 16 * k;
-      for (int e = threadIdx.x; e < rows * cols; e += 64 * kCholRegWaves) {
-        const int64_t o = (int64_t)(16 * k + e / cols) * lk + e % cols;
-        R[o] = 0.0;
-        Rinv[o] = 0.0;
+      for (int i = wave; i < rows; i += kCholRegWaves) {
+        double* rR = R + (int64_t)(16 * k + i) * lk;
+        double* rX = Rinv + (int64_t)(16 * k + i) * lk;
+        for (int c = ln; c < cols; c += 64) {
+          rR[c] = 0.0;
+          rX[c] = 0.0;
+        }
       }
-      __syncthreads();
+      lds_barrier();
     }
     if (wave == 0 && lane == 0) {
       s_range[0] = dmax;
