@@ -42,34 +42,27 @@ struct JacArgs {
   DevState* st;
 };
 
-// Rotation that annihilates h_pq of the symmetric 2 x 2 [h_pp h_pq; h_pq h_qq]
-// (Rutishauser's formulas: zeta = (h_qq - h_pp) / (2 h_pq), t = sign(zeta) /
-// (|zeta| + sqrt(1 + zeta^2)), c = 1 / sqrt(1 + t^2), s = c t); identity when
-// |h_pq| <= tol sqrt(h_pp h_qq). The reciprocals and square roots come from
-// rcp_nr / rsq_nr: c is 1 / sqrt(1 + t^2) to about an ulp and s = c t, so
-// c^2 + s^2 = 1 to a few ulps whatever the rounding of t (an inexact t only
-// leaves a slightly larger h_pq for a later round). Straight-line code: the
-// rare cases (subnormal h_pq, |zeta| beyond 1e150) are computed beside the
-// common one and selected, so the compiler can interleave the two rotations a
-// thread forms in a round.
+// Rotation that annihilates h_pq of the symmetric 2 x 2 [h_pp h_pq; h_pq h_qq]:
+// with d = h_qq - h_pp and e = 2 h_pq, Rutishauser's t = sign(zeta) / (|zeta| +
+// sqrt(1 + zeta^2)), zeta = d / e, is t = sign(d) e / D with D = |d| +
+// sqrt(d^2 + e^2), and c = 1 / sqrt(1 + t^2) = D / sqrt(D^2 + e^2), s = c t =
+// sign(d) e / sqrt(D^2 + e^2). d and e are first scaled by the same power of
+// two (exact) to a largest magnitude in [0.5, 1), so no square over- or
+// underflows; c and s come from one inverse square root (rsq_nr, to about an
+// ulp), so c^2 + s^2 = 1 to a few ulps. Identity when |h_pq| <= tol
+// sqrt(h_pp h_qq). Two refined inverse square roots in sequence, no
+// reciprocal and no special cases.
 __device__ __forceinline__ void jac_rot(double hpp, double hqq, double hpq, double tol, double& c,
                                         double& s) {
   const bool rot = fabs(hpq) > tol * sqrt(hpp) * sqrt(hqq) && hpq != 0.0;
   const double e = 2.0 * hpq, d = hqq - hpp;
-  const bool normal_e = fabs(e) >= 1e-290;
-  const double zeta_fast = d * rcp_nr(normal_e ? e : 1.0);
-  const double zeta_slow = d / (e != 0.0 ? e : 1.0);  // the estimate would overflow
-  const double zeta = normal_e ? zeta_fast : zeta_slow;
-  const double az = fabs(zeta);
-  const bool huge = !(az < 1e150);  // sqrt(1 + zeta^2) = |zeta| to working precision
-  const double zc = huge ? 1.0 : az;
-  const double w = fma(zc, zc, 1.0);
-  const double t_common = rcp_nr(zc + w * rsq_nr(w));  // 1 / (|zeta| + sqrt(1 + zeta^2))
-  const double t_huge = 0.5 * rcp_nr(huge ? az : 1.0);
-  const double t = copysign(huge ? t_huge : t_common, zeta);
-  const double cc = rsq_nr(fma(t, t, 1.0));
-  c = rot ? cc : 1.0;
-  s = rot ? cc * t : 0.0;
+  const int ex = __builtin_amdgcn_frexp_exp(fmax(fabs(d), fabs(e)));
+  const double ds = __builtin_amdgcn_ldexp(d, -ex), es = __builtin_amdgcn_ldexp(e, -ex);
+  const double q = fma(ds, ds, es * es);          // [0.25, 2)
+  const double D = fabs(ds) + q * rsq_nr(q);      // [0.5, 1 + sqrt 2)
+  const double rho = rsq_nr(fma(D, D, es * es));  // 1 / sqrt(D^2 + e^2)
+  c = rot ? D * rho : 1.0;
+  s = rot ? copysign(1.0, d) * es * rho : 0.0;
 }
 
 // Returns true if the pair needed rotating. dsq: 32 doubles of LDS.
