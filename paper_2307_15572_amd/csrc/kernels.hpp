@@ -70,16 +70,16 @@ rsvd_status gaussian_omega(int64_t n, int64_t l, int64_t col0, uint64_t seed, ui
 
 // ---- small dense l x l kernels (smalldense.hip) -----------------------------
 // Cholesky of the Gram G (l x l; overwritten, used as scratch) into R (upper,
-// R^T R = G [+ shift I]) and
-// Rinv = R^{-1}. pass 0 may switch to the shifted factorization (sets
-// st->qr_shifted); a pass with only_if_shifted != 0 does nothing unless
-// st->qr_shifted is set. m = rows of the panel (sizes the shift).
-// scratch: chol_panel_doubles(l) doubles of global memory, used for the
-// current block row when it does not fit in LDS (l > 1168).
+// R^T R = G [+ shift I]) and Rinv = R^{-1} (full_inverse), or only the
+// inverses of R's 16 x 16 diagonal tiles in Rinv (what trsm_upper uses).
+// pass 0 may switch to the shifted factorization (sets st->qr_shifted); a
+// pass with only_if_shifted != 0 does nothing unless st->qr_shifted is set.
+// m = rows of the panel (sizes the shift). Without the full inverse and for
+// l <= 272 one workgroup factors with the tiles in registers; otherwise a
+// grid of workgroups (at most 1/share of the device's co-resident capacity,
+// for runs on concurrent streams) with the current 32-row block row in
+// scratch: chol_panel_doubles(l) doubles of global memory (required).
 size_t chol_panel_doubles(int64_t l);
-// From l = 320 the factorization and inverse run on a grid of workgroups
-// (at most 1/share of the device's co-resident capacity, for runs on
-// concurrent streams).
 rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, double* scratch, int64_t m,
                      int pass, int only_if_shifted, DevState* st, hipStream_t s, int share = 1,
                      bool full_inverse = true);

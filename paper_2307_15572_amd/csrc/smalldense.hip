@@ -20,7 +20,6 @@ namespace {
 
 constexpr double kUnitRoundoff = 1.1102230246251565e-16;  // 2^-53
 constexpr int kBig = 1024;                                // threads of the l x l kernels
-constexpr int64_t kCholGridMin = 256;  // l from which the Cholesky runs on a grid of workgroups
 constexpr int64_t kHouseGridMin = 1 << 16;  // rows x l from which the Householder fallback runs on a grid
 
 __device__ __forceinline__ double block_sum(double v, double* red) {
@@ -344,90 +343,6 @@ __device__ __forceinline__ void trailing_coords(int t, int n, int& I, int& J) {
   J = row + t;
 }
 
-// Factor W in place (tiles). Returns false on breakdown (uniform).
-__device__ bool tiled_factor(const TileCtx& cx, double* W, double* Xg, double* panel,
-                             double* dinv, int* s_flag, bool clamp, double clampv,
-                             double* s_range) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
-  const int nw = blockDim.x >> 6;
-  const int nb = cx.nb, ps = cx.ps;
-  double dmax = 0.0, dmin = INFINITY;
-  if (threadIdx.x == 0) *s_flag = 0;
-  __syncthreads();
-  for (int k = 0; k < nb; k++) {
-    if (wave == 0) {
-      double t[4], x[4];
-      load_tile(cx, W, k, k, t);
-      const bool ok = tile_chol(t, clamp, clampv, 16 * k, cx.l, dmax, dmin);
-      tile_inv_upper(t, x);
-      store_tile(cx, W, k, k, t);
-      store_tile(cx, Xg, k, k, x);
-#pragma unroll
-      for (int it = 0; it < 4; it++) dinv[(g + 4 * it) * 17 + r] = x[it];
-      if (!ok && lane == 0) *s_flag = 1;
-    }
-    __syncthreads();
-    if (*s_flag) return false;
-    // block row k: R_kJ = R_kk^{-T} G_kJ
-    for (int J = k + 1 + wave; J < nb; J += nw) {
-      double b[4];
-      load_tile(cx, W, k, J, b);
-      d4 acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s = 0; s < 4; s++) acc = mfma_f64_16x16x4(dinv[(4 * s + g) * 17 + r], b[s], acc);
-      double o[4] = {acc[0], acc[1], acc[2], acc[3]};
-      store_tile(cx, W, k, J, o);
-#pragma unroll
-      for (int it = 0; it < 4; it++) panel[(g + 4 * it) * ps + 16 * J + r] = o[it];
-    }
-    __syncthreads();
-    // trailing tiles, four per wave at a time so their L2 round trips overlap
-    const int n = nb - k - 1;
-    const int T = n * (n + 1) / 2;
-    constexpr int TB = 4;
-    for (int t0 = wave * TB; t0 < T; t0 += nw * TB) {
-      int Is[TB], Js[TB];
-      double tl[TB][4];
-      int I, J;
-      trailing_coords(t0, n, I, J);
-#pragma unroll
-      for (int q = 0; q < TB; q++) {
-        // consecutive tiles of the upper triangle, row-major
-        Is[q] = I + k + 1;
-        Js[q] = J + k + 1;
-        if (++J >= n) {
-          I++;
-          J = I;
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < TB; q++)
-        if (t0 + q < T) load_tile(cx, W, Is[q], Js[q], tl[q]);
-#pragma unroll
-      for (int q = 0; q < TB; q++) {
-        if (t0 + q < T) {
-          d4 acc = {tl[q][0], tl[q][1], tl[q][2], tl[q][3]};
-#pragma unroll
-          for (int s = 0; s < 4; s++) {
-            const double a = -panel[(4 * s + g) * ps + 16 * Is[q] + r];
-            const double bb = panel[(4 * s + g) * ps + 16 * Js[q] + r];
-            acc = mfma_f64_16x16x4(a, bb, acc);
-          }
-          double o[4] = {acc[0], acc[1], acc[2], acc[3]};
-          store_tile(cx, W, Is[q], Js[q], o);
-        }
-      }
-    }
-    __syncthreads();
-  }
-  if (wave == 0 && lane == 0) {
-    s_range[0] = dmax;
-    s_range[1] = dmin;
-  }
-  __syncthreads();
-  return true;
-}
-
 // Tile in the MFMA A-operand layout: lane (r, g), item t holds entry (r, g + 4 t).
 __device__ __forceinline__ void load_tile_a(const TileCtx& cx, const double* W, int I, int J,
                                             double t[4]) {
@@ -446,14 +361,6 @@ __device__ __forceinline__ void load_tile_a(const TileCtx& cx, const double* W, 
 // Diagonal tiles of X are already in Xg.
 // Team: the waves that share the work (id in [0, size)) and their barrier
 // (a workgroup's __syncthreads, or a grid barrier across workgroups).
-struct BlockTeam {
-  __device__ int id() const { return threadIdx.x >> 6; }
-  __device__ int size() const { return blockDim.x >> 6; }
-  __device__ bool sync() const {
-    __syncthreads();
-    return true;
-  }
-};
 struct GridTeam {
   DevState* st;
   int* s_ok;
@@ -525,74 +432,6 @@ __device__ bool tiled_inverse(const Team& tm, const TileCtx& cx, const double* W
   return true;
 }
 
-__global__ void __launch_bounds__(512) chol_tiles_kernel(int l, double* __restrict__ G,
-                                                          double* __restrict__ R,
-                                                          double* __restrict__ Rinv,
-                                                          double* __restrict__ panel_g, int64_t m,
-                                                          int pass, int only_if_shifted,
-                                                          int full_inverse, DevState* st) {
-  extern __shared__ double lds[];
-  __shared__ double red[kBig / 64];
-  __shared__ int s_flag;
-  __shared__ double s_range[2];
-  if (only_if_shifted && st->qr_shifted == 0) return;
-  TileCtx cx;
-  cx.l = l;
-  cx.nb = (l + 15) / 16;
-  cx.ps = 16 * cx.nb + 1;
-  // the current block row lives in LDS, or in global scratch when it does
-  // not fit (L2-resident either way)
-  double* panel = panel_g ? panel_g : lds;
-  double* dinv = panel_g ? lds : lds + 16 * cx.ps;
-  const int64_t ll = (int64_t)l * l;
-
-  double tr = 0.0;
-  for (int i = threadIdx.x; i < l; i += blockDim.x) tr += G[(int64_t)i * l + i];
-  tr = block_sum(tr, red);
-  const double shift = 11.0 * ((double)m * l + (double)l * (l + 1)) * kUnitRoundoff * tr;
-  const double clampv = fmax(shift, 1e-300);
-
-  // a panel of the same run already needed the shift: start shifted (the
-  // unshifted attempt would only fail the pivot-spread test again)
-  bool use_shift = pass == 0 && st->prefer_shift != 0u, clamp = false;
-  if (use_shift && threadIdx.x == 0) st->qr_shifted = 1;
-  for (int attempt = 0; attempt < 3; attempt++) {
-    for (int64_t e = threadIdx.x; e < ll; e += blockDim.x) {
-      double v = G[e];
-      if (use_shift && (e / l) == (e % l)) v += shift;
-      R[e] = v;
-    }
-    __syncthreads();
-    bool ok = tiled_factor(cx, R, Rinv, panel, dinv, &s_flag, clamp, clampv, s_range);
-    if (clamp) break;
-    if (ok && pass == 0 && !use_shift && s_range[0] > 1e5 * s_range[1]) ok = false;
-    if (ok) break;
-    if (use_shift || pass == 2) {
-      // breakdown even with the shift (or in the last pass): numerically
-      // rank-deficient panel
-      if (threadIdx.x == 0) st->qr_householder = 1;
-      clamp = true;
-      use_shift = true;
-    } else {
-      use_shift = true;
-      if (threadIdx.x == 0) st->qr_shifted = 1;
-    }
-    __syncthreads();
-  }
-  if (pass == 0 && threadIdx.x == 0) st->prefer_shift = use_shift ? 1u : 0u;
-  // G is no longer read: it serves as scratch for the inverse (without
-  // full_inverse only the diagonal tiles of Rinv, written above, are valid)
-  if (full_inverse) tiled_inverse(BlockTeam{}, cx, R, Rinv, G);
-  // strictly lower parts are zero
-  for (int64_t e = threadIdx.x; e < ll; e += blockDim.x) {
-    if (e / l > e % l) {
-      R[e] = 0.0;
-      Rinv[e] = 0.0;
-    }
-  }
-}
-
-
 // ---------------------------------------------------------------------------
 // The Cholesky for l <= 272 by one workgroup with the off-diagonal tiles of
 // the upper triangle resident in registers (tile t of the row-major strict
@@ -611,7 +450,7 @@ __global__ void __launch_bounds__(512) chol_tiles_kernel(int l, double* __restri
 // third barrier and a broadcast per block row; its 16-column chain is the
 // only serial part. Only the diagonal tiles of Rinv are formed (what the
 // triangular solve of the QR uses); the strictly lower tiles of R and Rinv
-// are cleared. Pivot checks, shift and retries as in chol_tiles_kernel.
+// are cleared. Pivot checks, shift and retries as in chol_grid_kernel.
 // ---------------------------------------------------------------------------
 constexpr int kCholRegMaxNB = 17;
 constexpr int kCholRegWaves = 8;
@@ -1870,40 +1709,24 @@ __global__ void __launch_bounds__(256) transpose_kernel(int64_t rows, int64_t co
 
 inline unsigned blocks_for(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
-// Allow the single-workgroup kernels the full 160 KB of LDS of a gfx950 CU.
-void allow_big_lds() {
-  static bool done = false;
-  if (done) return;
-  done = true;
-  (void)hipFuncSetAttribute((const void*)chol_tiles_kernel,
-                            hipFuncAttributeMaxDynamicSharedMemorySize, 150 * 1024);
-}
-
 }  // namespace
 
-size_t chol_tiles_lds(int64_t l) {
-  const int64_t nb = (l + 15) / 16;
-  return (size_t)(16 * (16 * nb + 1) + 16 * 17) * sizeof(double);
-}
-
 size_t chol_panel_doubles(int64_t l) {
-  // the single-workgroup kernel's 16-row panel, or the grid kernel's 32 rows
-  const size_t one = (size_t)16 * (16 * ((l + 15) / 16) + 1);
-  const size_t grid = (size_t)32 * (size_t)grid_panel_ld(l);
-  return one > grid ? one : grid;
+  // the grid kernel's 32-row panel
+  return (size_t)32 * (size_t)grid_panel_ld(l);
 }
 
 rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, double* scratch, int64_t m,
                      int pass, int only_if_shifted, DevState* st, hipStream_t s, int share,
                      bool full_inverse) {
-  allow_big_lds();
   if (!full_inverse && l <= 16 * kCholRegMaxNB) {
     hipLaunchKernelGGL(chol_reg_kernel, dim3(1), dim3(64 * kCholRegWaves), 0, s, (int)l, G, R,
                        Rinv, m, pass, only_if_shifted, st);
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
   }
-  if (l >= kCholGridMin && scratch) {
+  if (!scratch) return RSVD_EINVAL;
+  {
     // one 4-wave workgroup per ~32 tiles of the first trailing update, capped
     // so the grids of concurrent runs fit on the device together
     static int cap_all = 0;
@@ -1929,17 +1752,6 @@ rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, double* scra
     RSVD_LAUNCH_CHECK();
     return RSVD_OK;
   }
-  size_t tl = chol_tiles_lds(l);
-  double* panel_g = nullptr;
-  if (tl > 150 * 1024) {
-    if (!scratch) return RSVD_EINVAL;
-    panel_g = scratch;
-    tl = 16 * 17 * sizeof(double);
-  }
-  hipLaunchKernelGGL(chol_tiles_kernel, dim3(1), dim3(512), tl, s, (int)l, G, R, Rinv, panel_g, m,
-                     pass, only_if_shifted, full_inverse ? 1 : 0, st);
-  RSVD_LAUNCH_CHECK();
-  return RSVD_OK;
 }
 
 rsvd_status gram(int64_t rows, int64_t l, const double* Y, int64_t ldy, double* G, double* part,
