@@ -77,7 +77,7 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
 
   // ---- Gram of the 32 rows (tiles 00, 01, 11), K split over the 4 waves;
   // GB column tiles of a wave in flight together
-  constexpr int GB = 4;
+  constexpr int GB = 5;
   d4 h00 = {0, 0, 0, 0}, h01 = {0, 0, 0, 0}, h11 = {0, 0, 0, 0};
   for (int ct0 = wave; ct0 < nct; ct0 += 4 * GB) {
     double xi[GB][4], xj[GB][4];
@@ -215,7 +215,7 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
     double* bI = base + (int64_t)16 * I * Lp;
     double* bJ = base + (int64_t)16 * J * Lp;
     // AB column tiles per iteration (their loads in flight together)
-    constexpr int AB = 4;
+    constexpr int AB = 5;
     for (int ct = wave; ct < nct; ct += 4 * AB) {
       double b[AB][8];
 #pragma unroll

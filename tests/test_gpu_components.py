@@ -154,6 +154,46 @@ def test_small_svd_matches_lapack(l, decay):
     assert np.abs(W.T @ W - np.eye(l)).max() <= orth_tol
 
 
+@pytest.mark.parametrize("scale", [1e150, 1e-140])
+def test_small_svd_extreme_scale(scale):
+    # Gram entries from 1e300 down to 1e-290: the rotations are formed from
+    # (d, e) scaled by a power of two, so no square or product over- or
+    # underflows (the row Grams themselves must stay in the normal range: the
+    # smallest singular value here is 1e-5 of the largest)
+    import paper_2307_15572_amd as rs
+    announce(f"small_svd extreme scale {scale:g}")
+    l = 100
+    rng = np.random.default_rng(7)
+    U = synth.haar_columns(l, l, rng)
+    V = synth.haar_columns(l, l, rng)
+    R = np.triu(np.linalg.qr((U * 10.0 ** (-np.arange(l) / 20)) @ V.T)[1]) * scale
+    s, Us, W, sweeps, flags = rs.small_svd(to_dev(R))
+    s = s.cpu().numpy()
+    assert not (flags & rs.FLAG_JACOBI_MAXSWEEP)
+    ref = np.linalg.svd(R, compute_uv=False)
+    assert np.all(np.isfinite(s))
+    assert np.all(np.abs(s - ref) <= 1e-13 * ref[0] + 1e-12 * ref)
+
+
+def test_small_svd_equal_row_norms():
+    # blocks [[3, 4], [0, 5]]: rows of equal norm, so h_qq - h_pp is exactly
+    # zero for those pairs (a 45-degree rotation); singular values sqrt(45),
+    # sqrt(5) per block, times the block's scale
+    import paper_2307_15572_amd as rs
+    announce("small_svd equal row norms")
+    nb = 17
+    l = 2 * nb
+    R = np.zeros((l, l))
+    scales = 2.0 ** np.arange(nb)
+    for i in range(nb):
+        R[2 * i:2 * i + 2, 2 * i:2 * i + 2] = scales[i] * np.array([[3.0, 4.0], [0.0, 5.0]])
+    s, Us, W, sweeps, flags = rs.small_svd(to_dev(R))
+    s = s.cpu().numpy()
+    assert not (flags & rs.FLAG_JACOBI_MAXSWEEP)
+    ref = np.sort(np.concatenate([scales * np.sqrt(45.0), scales * np.sqrt(5.0)]))[::-1]
+    assert np.all(np.abs(s - ref) <= 1e-14 * ref)
+
+
 LOWP_CASES = [("mixed_fp32", False, 517, 272, 1000), ("mixed_fp32", False, 2048, 272, 8192),
               ("mixed_fp32", True, 272, 272, 4096), ("mixed_fp32", False, 100, 50, 77),
               ("mixed_bf16", False, 517, 272, 1000), ("mixed_bf16", False, 2048, 272, 8192),
