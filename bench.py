@@ -13,7 +13,10 @@ metric value: matrix GB/s = (A streams per step) x 8 m n bytes / (time per step)
 with A resident in HBM before the timed region. The roofline object covers the
 dominant kernel (the streaming FP64 GEMM, MFMA-bound: intensity l/4 flop per
 byte is far above the FP64 ridge of ~9.8 flop/byte); its average duration comes
-from HIP events recorded around each streaming pass on the run's stream.
+from HIP events recorded around each streaming pass on the run's stream. The
+step time is timed over K steps without those per-phase events; the same K
+steps are then run again with them (phase times, the streaming product's
+launch durations, and that run's own step time, reported beside the first).
 
 Every plan's product tilings come from the autotuner (rsvd_tune /
 rsvd_batch_tune), run before its timed region; the tuned table is reported.
@@ -269,25 +272,38 @@ def main():
     tune_s = time.perf_counter() - t0
     log(f"warmup done; autotuner added {tuned} shapes in {tune_s:.2f} s")
 
-    rs.trace_enable(True)
-    rs.trace_collect()  # clear
     stream = torch.cuda.current_stream(dev)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    e0.record(stream)
-    for _ in range(args.steps):
-        plan.run_into(A, bufs)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t_start
-    rs.trace_enable(False)
-    phases = rs.trace_collect()
-    ms_total = e0.elapsed_time(e1)
-    ms_step = ms_total / args.steps
+
+    def timed(pl, bb, traced):
+        """K steps between HIP events on the run's stream; with traced, the
+        per-phase HIP events of the library (phase times, streaming-product
+        launch durations) are recorded as well."""
+        if traced:
+            rs.trace_enable(True)
+            rs.trace_collect()  # clear
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t_start = time.perf_counter()
+        e0.record(stream)
+        for _ in range(args.steps):
+            pl.run_into(A, bb)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        wall_s = time.perf_counter() - t_start
+        ph = None
+        if traced:
+            rs.trace_enable(False)
+            ph = rs.trace_collect()
+        return e0.elapsed_time(e1) / args.steps, wall_s, ph
+
+    # the step time without the phase events, then the same K steps with them
+    # (phases and the streaming product's live launch durations)
+    ms_step, wall, _ = timed(plan, bufs, False)
+    ms_traced, _, phases = timed(plan, bufs, True)
     res = plan.result(bufs)
-    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step (host wall {wall / args.steps * 1e3:.3f})")
+    log(f"timed {args.steps} steps: {ms_step:.3f} ms/step (host wall {wall / args.steps * 1e3:.3f}); "
+        f"with phase events {ms_traced:.3f}")
 
     passes = 2 * q + 3  # sketch + 2q power products + projection + residual
     a_bytes = 8.0 * w.m * w.n
@@ -327,6 +343,7 @@ def main():
         "roofline": roofline,
         "step_fraction_of_mfma_floor": round(step_roof_ms / ms_step, 4),
         "phases_ms_per_step": {kk: round(v[0] / args.steps, 4) for kk, v in phases.items()},
+        "ms_per_step_with_phase_events": round(ms_traced, 4),
         "autotune": {"shapes_added": int(tuned), "seconds": round(tune_s, 3)},
         "result": {"rank": int(res.rank), "residual": res.residual, "sweeps": int(res.sweeps),
                    "flags": int(res.flags)},
@@ -346,19 +363,8 @@ def main():
         for _ in range(args.warmup):
             mplan.run_into(A, mb)
         mplan.tune(A, mb, reps=3)
-        torch.cuda.synchronize()
-        rs.trace_enable(True)
-        rs.trace_collect()
-        f0 = torch.cuda.Event(enable_timing=True)
-        f1 = torch.cuda.Event(enable_timing=True)
-        f0.record(stream)
-        for _ in range(args.steps):
-            mplan.run_into(A, mb)
-        f1.record(stream)
-        torch.cuda.synchronize()
-        rs.trace_enable(False)
-        mph = rs.trace_collect()
-        mms = f0.elapsed_time(f1) / args.steps
+        mms, _, _ = timed(mplan, mb, False)
+        _, _, mph = timed(mplan, mb, True)
         mres = mplan.result(mb)
         s64 = bufs["S"][: res.rank].cpu().numpy()
         smx = mb["S"][: mres.rank].cpu().numpy()
