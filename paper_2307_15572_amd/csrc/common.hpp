@@ -140,24 +140,29 @@ struct GridBar {
 // A workgroup that has waited kSpinLimit polls raises the abort word and
 // leaves; waiters see it and leave too. Returns false once the barrier has
 // been abandoned: the kernel must then return.
+constexpr uint32_t kFlatBarrier = 32;
+
 __device__ inline bool grid_barrier(GridBar* gb, int* s_ok) {
   asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0) {
     int ok = 1;
     const uint32_t g = __hip_atomic_load(&gb->gen[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const uint32_t grp = blockIdx.x & 7u;
-    const uint32_t gsize = (gridDim.x - grp + 7u) >> 3;
-    const uint32_t ngroups = gridDim.x < 8u ? gridDim.x : 8u;
+    // up to kFlatBarrier workgroups arrive on one counter (one atomic fewer
+    // on the critical path); larger grids in 8 groups, then across groups
+    const bool flat = gridDim.x <= kFlatBarrier;
+    const uint32_t grp = flat ? 0u : (blockIdx.x & 7u);
+    const uint32_t gsize = flat ? gridDim.x : ((gridDim.x - grp + 7u) >> 3);
     bool last = false;
     const uint32_t a =
         __hip_atomic_fetch_add(&gb->lo[grp][0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
     if (a == gsize) {
       __hip_atomic_store(&gb->lo[grp][0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       const uint32_t h =
-          __hip_atomic_fetch_add(&gb->hi[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
-      if (h == ngroups) {
-        __hip_atomic_store(&gb->hi[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          flat ? 1u
+               : __hip_atomic_fetch_add(&gb->hi[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+      if (flat || h == 8u) {
+        if (!flat) __hip_atomic_store(&gb->hi[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         __hip_atomic_fetch_add(&gb->gen[0], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         last = true;
       }
