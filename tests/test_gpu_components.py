@@ -106,7 +106,7 @@ def test_orth_exactly_rank_deficient_uses_householder():
     assert np.abs(Q[:, :25] - oracle_orth(Y[:, :25])).max() <= 1e-12
 
 
-@pytest.mark.parametrize("rows,l,rank", [(3000, 300, 8), (1500, 96, 40), (700, 128, 0)])
+@pytest.mark.parametrize("rows,l,rank", [(3000, 300, 8), (1500, 96, 40), (700, 128, 0), (16384, 272, 100)])
 def test_orth_rank_deficient_large_panel_grid_householder(rows, l, rank):
     # panels past the one-workgroup size take the fallback on a grid of
     # workgroups: same contract (orthonormal Q, Q X = Y, diag(X) >= 0)
