@@ -72,8 +72,9 @@ enum {
   RSVD_FLAG_NONFINITE_INPUT = 1u << 4, /* A holds NaN or Inf                         */
   RSVD_FLAG_ZERO_SIGMA = 1u << 5,      /* a singular value is exactly zero           */
   RSVD_FLAG_ADAPT_LIMIT = 1u << 6,     /* adaptive growth stopped at l_max           */
-  RSVD_FLAG_SYNC_TIMEOUT = 1u << 7     /* a device-wide barrier of the small SVD gave
-                                          up waiting (bounded wait): results invalid  */
+  RSVD_FLAG_SYNC_TIMEOUT = 1u << 7     /* a grid-wide barrier (multi-workgroup Cholesky,
+                                          Householder fallback or small SVD) gave up
+                                          waiting (bounded wait): results invalid     */
 };
 
 typedef struct rsvd_problem {
@@ -129,6 +130,15 @@ typedef struct rsvd_plan_s* rsvd_plan_t;
  *   out             receives an immutable plan (host object); free it with
  *                   rsvd_destroy. Concurrent runs of one plan need distinct
  *                   workspaces.
+ * Concurrency: the multi-workgroup Cholesky, Householder and Jacobi kernels
+ * synchronize their workgroups with grid-wide barriers and size their grids
+ * to what the whole device holds at once. Two rsvd_run calls whose kernels
+ * overlap on one device (different streams) may therefore not all be
+ * co-resident: their barriers then time out and the results carry
+ * RSVD_FLAG_SYNC_TIMEOUT. Independent decompositions that should run side
+ * by side go through rsvd_batch_run, which divides the device among its
+ * lanes; rsvd_run calls on one device are meant to be ordered (one stream,
+ * or streams joined by events).
  *   workspace_bytes receives the device workspace size rsvd_run needs.
  * Returns RSVD_EINVAL for m, n < 1, k < 1 (fixed rule), p < 0, q < 0,
  * R% outside (0, 100], tau outside (0, 1), an unknown mode, trailing_hp < 0,

@@ -162,6 +162,15 @@ def _check(status, what):
         raise RsvdError(f"{what}: {msg} (status {status})")
 
 
+def check_flags(flags, what):
+    """Raise on the result flags that make a result invalid: non-finite input
+    and a grid-wide barrier that gave up waiting (SYNC_TIMEOUT)."""
+    if flags & FLAG_NONFINITE_INPUT:
+        raise RsvdError(f"{what}: A holds NaN or Inf")
+    if flags & FLAG_SYNC_TIMEOUT:
+        raise RsvdError(f"{what}: a grid-wide barrier timed out (results invalid)")
+
+
 def _torch():
     import torch
     if not torch.cuda.is_available():
@@ -422,13 +431,18 @@ class BatchPlan:
                                      _stream(torch, As[0].device)), "rsvd_batch_tune")
         return n.value
 
-    def results(self, bufs):
-        """Synchronize and read the count result records."""
+    def results(self, bufs, check=True):
+        """Synchronize and read the count result records. check: raise when a
+        channel's flags mark its result invalid (see check_flags)."""
         torch = _torch()
         torch.cuda.synchronize(bufs["res"].device)
         raw = bytes(bufs["res"].cpu().numpy().tobytes())
         sz = ctypes.sizeof(Result)
-        return [Result.from_buffer_copy(raw[c * sz:(c + 1) * sz]) for c in range(self.count)]
+        out = [Result.from_buffer_copy(raw[c * sz:(c + 1) * sz]) for c in range(self.count)]
+        if check:
+            for c, r in enumerate(out):
+                check_flags(r.flags, f"batch channel {c}")
+        return out
 
 
 def run(A, k, p, q, *, omega=None, **kw):
@@ -440,8 +454,7 @@ def run(A, k, p, q, *, omega=None, **kw):
     bufs = plan.allocate(A.device)
     plan.run_into(A, bufs, omega=omega)
     r = plan.result(bufs)
-    if r.flags & FLAG_NONFINITE_INPUT:
-        raise RsvdError("A holds NaN or Inf")
+    check_flags(r.flags, "rsvd_run")
     rank = int(r.rank)
     return RsvdOutput(
         S=bufs["S"][:rank], U=bufs["U"][:, :rank] if bufs["U"] is not None else None,
@@ -578,7 +591,9 @@ def orth(Y):
            "rsvd_orth")
     torch.cuda.synchronize(Y.device)
     del buf
-    return Q, X, int(flags.item()) & 0xFFFFFFFF
+    fl = int(flags.item()) & 0xFFFFFFFF
+    check_flags(fl, "rsvd_orth")
+    return Q, X, fl
 
 
 def small_svd(R, max_sweeps=0):
@@ -600,7 +615,9 @@ def small_svd(R, max_sweeps=0):
            "rsvd_small_svd")
     torch.cuda.synchronize(R.device)
     del buf
-    return s, Us, W, int(sw.item()), int(fl.item()) & 0xFFFFFFFF
+    flags = int(fl.item()) & 0xFFFFFFFF
+    check_flags(flags, "rsvd_small_svd")
+    return s, Us, W, int(sw.item()), flags
 
 
 def pilot_features(A, seed, channel=0, work=None):

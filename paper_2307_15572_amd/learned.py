@@ -67,7 +67,11 @@ class ChannelOutcome:
 
 def accept(S, rank, l, p, q, flags):
     """A-posteriori check of a threshold run sized by (k, p, q)."""
-    from . import FLAG_RANK_CAPPED
+    from . import FLAG_JACOBI_MAXSWEEP, FLAG_RANK_CAPPED, FLAG_SYNC_TIMEOUT
+    if flags & FLAG_SYNC_TIMEOUT:
+        return False, "grid barrier timed out"
+    if flags & FLAG_JACOBI_MAXSWEEP:
+        return False, "small SVD not converged"
     if flags & FLAG_RANK_CAPPED:
         return False, "rank capped at l - p"
     if rank >= l:

@@ -53,7 +53,10 @@ def test_dgemm_matches_numpy(ta, m, n, k):
 @pytest.mark.parametrize("m,l,decay", [(500, 50, 1 / 16), (4096, 272, 1 / 40), (3000, 100, 1 / 8),
                                        (200, 200, 1 / 64), (20, 1, 0.1), (2000, 528, 1 / 64),
                                        (1500, 33, 0.05), (2600, 1250, 1 / 200), (3000, 257, 1 / 40),
-                                       (700, 16, 0.1), (900, 17, 0.05), (5000, 271, 1 / 50)])
+                                       (700, 16, 0.1), (900, 17, 0.05), (5000, 271, 1 / 50),
+                                       # 273..320: grid Cholesky with diagonal-tile inverses
+                                       # only, then the block triangular solve
+                                       (4096, 288, 1 / 40), (6000, 320, 1 / 50)])
 def test_orth_matches_oracle(m, l, decay):
     import paper_2307_15572_amd as rs
     announce(f"orth m={m} l={l} decay={decay}")
@@ -106,7 +109,8 @@ def test_orth_exactly_rank_deficient_uses_householder():
     assert np.abs(Q[:, :25] - oracle_orth(Y[:, :25])).max() <= 1e-12
 
 
-@pytest.mark.parametrize("rows,l,rank", [(3000, 300, 8), (1500, 96, 40), (700, 128, 0), (16384, 272, 100)])
+@pytest.mark.parametrize("rows,l,rank", [(3000, 300, 8), (1500, 96, 40), (700, 128, 0), (16384, 272, 100),
+                                         (5000, 304, 50)])
 def test_orth_rank_deficient_large_panel_grid_householder(rows, l, rank):
     # panels past the one-workgroup size take the fallback on a grid of
     # workgroups: same contract (orthonormal Q, Q X = Y, diag(X) >= 0)

@@ -36,6 +36,18 @@ def test_init_matches_oracle():
     assert np.all(np.abs(got - ref) <= 1e-6 * np.abs(ref) + 1e-12)
 
 
+def test_forward_hand_computed():
+    # the hand-worked parameters and outputs of the oracle pin: every value
+    # in them is exact in FP32
+    import paper_2307_15572_amd as rs
+    from test_oracle_mlp import HAND_X, HAND_Y, _hand_params
+    announce("mlp forward, hand-computed parameters")
+    net = rs.Mlp(seed=0)
+    net.params.copy_(_f32(_hand_params()))
+    y = net.forward(_f32(HAND_X)).cpu().numpy().astype(np.float64)
+    assert np.allclose(y, HAND_Y, rtol=0, atol=1e-6)
+
+
 def _batch(B, seed):
     rng = np.random.default_rng(seed)
     X = rng.uniform(-3.0, 0.0, size=(B, 16))

@@ -100,3 +100,35 @@ def test_training_learns_a_linear_relation():
     L0 = mlp.loss(theta, X, T)
     theta, hist = mlp.train(theta, X, T, epochs=60, batch=128, lr=3e-3)
     assert mlp.loss(theta, X, T) < 0.02 * L0
+
+
+def _hand_params():
+    """A sparse parameter vector set through the documented flat layout
+    (W1 at 0, b1 at 1024, W2 at 1088, b2 at 5184, W3 at 5248, b3 at 5440)."""
+    t = np.zeros(5443)
+    w1 = lambda i, j: i * 16 + j          # noqa: E731
+    w2 = lambda i, j: 1088 + i * 64 + j   # noqa: E731
+    w3 = lambda i, j: 5248 + i * 64 + j   # noqa: E731
+    t[w1(0, 0)], t[w1(1, 1)], t[w1(2, 0)], t[w1(2, 1)] = 1.0, -2.0, 0.5, 0.5
+    t[1024 + 0], t[1024 + 1], t[1024 + 2] = 0.25, 1.0, -0.5
+    t[w2(0, 0)], t[w2(0, 1)], t[w2(1, 2)], t[w2(1, 0)] = 2.0, 1.0, -1.0, 1.0
+    t[5184 + 1] = 3.0
+    t[w3(0, 0)], t[w3(1, 1)], t[w3(2, 0)], t[w3(2, 1)] = 1.0, 0.5, -1.0, 1.0
+    t[5440:5443] = [0.1, -0.2, 0.3]
+    return t
+
+
+# worked by hand: sample 1 x = (1, -1, 0, ...): z1 = (1.25, 3, -0.5) -> h1 = (1.25, 3, 0);
+# z2 = (2*1.25 + 3, 1.25 - 0 + 3) = (5.5, 4.25); y = (5.5 + 0.1, 0.5*4.25 - 0.2, -5.5 + 4.25 + 0.3).
+# sample 2 x = (-2, 0.5, 0, ...): z1 = (-1.75, 0, -1.25) -> h1 = 0; h2 = (0, 3); y = (0.1, 1.3, 3.3)
+HAND_X = np.zeros((2, 16))
+HAND_X[0, :2] = [1.0, -1.0]
+HAND_X[1, :2] = [-2.0, 0.5]
+HAND_Y = np.array([[5.6, 1.925, -0.95], [0.1, 1.3, 3.3]])
+
+
+def test_forward_hand_computed_two_samples():
+    # pins the architecture independently of backprop: layer order, the
+    # orientation of each weight matrix, the biases and where ReLU applies
+    y, _ = mlp.forward(_hand_params(), HAND_X)
+    assert np.allclose(y, HAND_Y, rtol=0, atol=1e-14)

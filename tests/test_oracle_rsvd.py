@@ -120,6 +120,22 @@ def test_orthonormality_and_signs():
     assert np.all(r.U[idx, np.arange(r.rank)] > 0)
 
 
+def test_sign_rule_ties_lowest_index_wins():
+    # constructed ties: column 0 has |entry| 0.5 at rows 0 (negative), 1 and 2;
+    # column 1 has 0.6 at row 0 (positive) and -0.6 at row 1. The entry of
+    # largest magnitude with the lowest index decides: column 0 flips,
+    # column 1 stays; V's columns follow their U column
+    from oracle.method import sign_normalize
+    U = np.array([[-0.5, 0.6], [0.5, -0.6], [0.5, 0.1], [0.1, 0.2]])
+    V = np.array([[1.0, 2.0], [3.0, -4.0], [-5.0, 6.0]])
+    U2, V2 = sign_normalize(U, V)
+    assert np.array_equal(U2, [[0.5, 0.6], [-0.5, -0.6], [-0.5, 0.1], [-0.1, 0.2]])
+    assert np.array_equal(V2, [[-1.0, 2.0], [-3.0, -4.0], [5.0, 6.0]])
+    # a zero column keeps its sign
+    Z, W = sign_normalize(np.zeros((3, 1)), np.ones((2, 1)))
+    assert np.array_equal(Z, np.zeros((3, 1))) and np.array_equal(W, np.ones((2, 1)))
+
+
 def test_halko_average_error_bound_q0():
     # Halko, Martinsson, Tropp (2011), Thm 10.5: for q = 0 and p >= 2,
     # E ||(I - QQ^T) A||_F <= (1 + k/(p-1))^(1/2) (sum_{j>k} sigma_j^2)^(1/2)
