@@ -198,6 +198,27 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda,
                      double* S, double* U, int64_t ldu, double* V, int64_t ldv,
                      rsvd_result* res_dev, void* work, size_t work_bytes, void* stream);
 
+/*
+ * rsvd_run_noalloc - rsvd_run for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc). Arguments as rsvd_run, without work / work_bytes: the workspace
+ * is a static device array of RSVD_NOALLOC_MAX_BYTES (64 MiB) inside the
+ * library, one copy per device, held until the process ends. Its device
+ * address is looked up on the first call on each device (with that device
+ * current; the call runs on the device current at the call). Nothing is
+ * allocated, and the run clears what must start at zero itself.
+ * Returns RSVD_ENOMEM, before enqueueing anything, when the plan's workspace
+ * (rsvd_plan's workspace_bytes) exceeds RSVD_NOALLOC_MAX_BYTES; otherwise
+ * what rsvd_run returns. Calls that overlap on one device (other streams,
+ * other host threads) share the array and race: order them.
+ */
+#define RSVD_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+size_t rsvd_noalloc_max_bytes(void);
+rsvd_status rsvd_run_noalloc(rsvd_plan_t plan, const double* A, int64_t lda,
+                             const double* omega, int64_t ldo,
+                             double* S, double* U, int64_t ldu, double* V, int64_t ldv,
+                             rsvd_result* res_dev, void* stream);
+
 /* Free a plan (NULL is ignored). */
 void rsvd_destroy(rsvd_plan_t plan);
 

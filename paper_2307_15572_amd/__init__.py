@@ -36,6 +36,7 @@ EXPORTED = (
     "rsvd_mlp_init", "rsvd_mlp_forward", "rsvd_mlp_grad", "rsvd_mlp_train_step",
     "rsvd_pilot_work_bytes", "rsvd_pilot_features",
     "rsvd_tune", "rsvd_batch_tune", "rsvd_tune_entries", "rsvd_tune_clear", "rsvd_tune_set",
+    "rsvd_run_noalloc", "rsvd_noalloc_max_bytes",
 )
 MLP_PARAMS, MLP_IN, MLP_OUT, MLP_MAX_BATCH, PILOT_COLS = 5443, 16, 3, 128, 32
 TRACE_PHASES = ("stream_gemm", "qr", "small_svd", "lift_signs", "residual", "omega", "other",
@@ -90,6 +91,10 @@ def lib():
     L.rsvd_plan_l.restype = i64
     L.rsvd_run.argtypes = [vp, vp, i64, vp, i64, vp, vp, i64, vp, i64, vp, vp, sz, vp]
     L.rsvd_run.restype = ctypes.c_int
+    L.rsvd_run_noalloc.argtypes = [vp, vp, i64, vp, i64, vp, vp, i64, vp, i64, vp, vp]
+    L.rsvd_run_noalloc.restype = ctypes.c_int
+    L.rsvd_noalloc_max_bytes.argtypes = []
+    L.rsvd_noalloc_max_bytes.restype = sz
     L.rsvd_destroy.argtypes = [vp]
     L.rsvd_destroy.restype = None
     L.rsvd_strerror.argtypes = [ctypes.c_int]
@@ -303,6 +308,27 @@ class Plan:
                             _ptr(bufs["res"]), bufs["work"], bufs["work_bytes"],
                             _stream(torch, A.device))
         _check(st, "rsvd_run")
+
+    def run_into_noalloc(self, A, bufs, omega=None):
+        """Enqueue one decomposition through rsvd_run_noalloc: the library's
+        static workspace instead of bufs' (which needs no "work" entry)."""
+        torch = _torch()
+        _check_matrix(torch, A, "A")
+        pr = self.problem
+        if tuple(A.shape) != (pr.m, pr.n):
+            raise RsvdError(f"A has shape {tuple(A.shape)}, plan expects {(pr.m, pr.n)}")
+        ldo = 0
+        if omega is not None:
+            _check_matrix(torch, omega, "omega")
+            if omega.shape[0] != pr.n or omega.shape[1] < self.l:
+                raise RsvdError("omega must be n x l")
+            ldo = omega.stride(0)
+        U, V = bufs["U"], bufs["V"]
+        st = lib().rsvd_run_noalloc(self._h, _ptr(A), A.stride(0), _ptr(omega), ldo,
+                                    _ptr(bufs["S"]), _ptr(U), U.stride(0) if U is not None else 0,
+                                    _ptr(V), V.stride(0) if V is not None else 0,
+                                    _ptr(bufs["res"]), _stream(torch, A.device))
+        _check(st, "rsvd_run_noalloc")
 
     def tune(self, A, bufs, reps=3, omega=None):
         """Autotune the tile shapes of this decomposition's products (see

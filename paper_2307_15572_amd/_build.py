@@ -15,7 +15,8 @@ ROOT = os.path.dirname(PKG)
 OUT = os.path.join(PKG, "librsvd.so")
 BUILD = os.path.join(ROOT, "_build")
 
-SOURCES = ["gemm.hip", "bf16gemm.hip", "omega.hip", "smalldense.hip", "bjacobi.hip", "rsvd.cpp", "batch.cpp", "tune.cpp", "mlp.hip"]
+SOURCES = ["gemm.hip", "bf16gemm.hip", "omega.hip", "smalldense.hip", "bjacobi.hip", "rsvd.cpp", "batch.cpp", "tune.cpp", "mlp.hip",
+           "noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
