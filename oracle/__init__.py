@@ -23,6 +23,9 @@ Additions beyond the paper, each stated where it is implemented:
   * Rank rules by relative threshold and by Frobenius tail, the adaptive
     range finder and the a-posteriori error estimate, and a small MLP that
     predicts (rank, oversampling, q).
+  * The symmetric-channel form A ~ Q (Q^T A Q) Q^T (symmetric.py), the basis
+    transform on thin factors and the report of one decomposition truncated
+    at several R% (transform.py).
 
 Parity status per function is listed in each module's header.
 """
@@ -41,3 +44,5 @@ from .method import (  # noqa: F401
 )
 from .adaptive import rsvd_adaptive, FLAG_ADAPT_LIMIT, POSTERIOR_FACTOR  # noqa: F401
 from . import mlp  # noqa: F401
+from .symmetric import rsvd_sym  # noqa: F401
+from .transform import factor_transform, truncation_report  # noqa: F401

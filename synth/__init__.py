@@ -26,6 +26,8 @@ i = 0 .. min(m, n) - 1, so sigma_0 = 1):
   c4  96 symmetric PSD channels, n_c ~ logU[500, 12000], sigma_i = exp(-i/d_c),
       d_c ~ U[10, 80]; rank by relative threshold 1e-6
   c5  2000 channels as c4 with n_c ~ logU[200, 6000]
+  paper_channel  N x N symmetric channel at the paper's sizes (N = 225 x the
+      number of partial-wave states: 7650 and 40050), two-regime spectrum
 """
 
 from dataclasses import dataclass
@@ -329,3 +331,52 @@ def c3_device(m=131072, n=8192, device="cuda"):
     sigma = spectrum_pow10(min(m, n), 1.0 / 64.0)
     A = general_device_rng(m, n, sigma, tag=3, noise=1e-9, device=device)
     return A, sigma, Workload(f"c3_{m}x{n}_general", m, n, False, 512, 16, 3, 2003)
+
+
+# ---- channels at the paper's sizes -------------------------------------------
+MESH = 225  # N_p x N_q momentum mesh points per partial-wave state
+
+
+def spectrum_two_regime(N, lead=10.0, knee_frac=0.0025, knee=2e-3, tail=2e-6):
+    """Two-regime spectrum shaped like the paper's channel matrices (section
+    "Low-rank interactions", Fig. 2): a steep drop over the leading 0.25 % of
+    the indices, then a slowly declining plateau below 2e-3. Log-linear from
+    `lead` at i = 0 to `knee` at i0 = ceil(knee_frac N), then log-linear from
+    `knee` to `tail` at i = N - 1. Every value is nonzero: the matrix has full
+    rank, as the interaction matrices do."""
+    i0 = max(1, int(math.ceil(knee_frac * N)))
+    i = np.arange(N, dtype=np.float64)
+    head = math.log10(lead) + (math.log10(knee) - math.log10(lead)) * i / i0
+    plateau = math.log10(knee) + (math.log10(tail) - math.log10(knee)) * (i - i0) / max(N - 1 - i0, 1)
+    return 10.0 ** np.where(i <= i0, head, plateau)
+
+
+def paper_channel(N, tag=6, device=None):
+    """N x N symmetric channel matrix A = U diag(sigma) U^T with the two-regime
+    spectrum, N a multiple of 225. The basis is the Kronecker product
+    U = U_mesh (225 x 225) x U_states (N/225 x N/225) of two Haar matrices
+    (one per factor of the product basis of mesh points and partial-wave
+    states): exactly orthogonal up to rounding and cheap to draw at
+    N = 40050, where a Haar basis would need an N x N QR. A Gaussian
+    projection is rotation invariant, so the randomized decomposition sees
+    the same distribution of sketches as for a Haar basis. Mirrored from the
+    upper triangle (A == A^T bitwise). Returns (A, sigma): A a numpy array,
+    or a torch tensor built on `device`."""
+    if N % MESH:
+        raise ValueError("N must be a multiple of 225")
+    sigma = spectrum_two_regime(N)
+    rng = _rng(tag, N)
+    U1 = haar_columns(MESH, MESH, rng)
+    U2 = haar_columns(N // MESH, N // MESH, rng)
+    if device is None or device == "cpu":
+        U = np.kron(U1, U2)
+        A = (U * sigma[None, :]) @ U.T
+        del U
+        A = np.triu(A)
+        A += np.triu(A, 1).T
+        return np.ascontiguousarray(A), sigma
+    import torch
+    U = torch.kron(torch.from_numpy(U1).to(device), torch.from_numpy(U2).to(device))
+    A = (U * torch.from_numpy(sigma).to(device)[None, :]) @ U.T
+    del U
+    return _finish_symmetric_device(A, None, 0.0, device).contiguous(), sigma
