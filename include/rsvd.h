@@ -63,6 +63,18 @@ enum {
                                     hi*lo + lo*hi + hi*hi, FP32 accumulation          */
 };
 
+/* How step 2 projects A (rsvd_problem.form). */
+enum {
+  RSVD_FORM_SVD = 0,           /* the paper's form: Y = Q^T A (l x n), thin SVD of Y   */
+  RSVD_FORM_SYMMETRIC = 1      /* symmetric channels (section "Low-rank interactions":
+                                  the interaction is Hermitian, each channel block
+                                  symmetric): A ~ Q B Q^T with B = Q^T A Q (l x l),
+                                  B symmetrized, SVD of B = L_B Sigma R_B^T, then
+                                  L = Q L_B and R = Q R_B (Halko, Martinsson and
+                                  Tropp 2011, section 5.3). Needs symmetric = 1;
+                                  fixed-l runs only (not adaptive)                   */
+};
+
 /* Flags in rsvd_result.flags */
 enum {
   RSVD_FLAG_FULL_SVD = 1u << 0,        /* l = min(m, n): the result is an exact SVD  */
@@ -100,6 +112,8 @@ typedef struct rsvd_problem {
                             threshold rules only, FP64 only, k is ignored          */
   int32_t block;         /* adaptive: columns added per growth step (1..256; 0 = 64) */
   int64_t l_max;         /* adaptive: largest l (0 = min(m, n, 4096))              */
+  int32_t form;          /* RSVD_FORM_* (0 = the paper's one-sided projection)     */
+  int32_t reserved;      /* must be 0                                              */
 } rsvd_problem;
 
 /* Result record, written to DEVICE memory by rsvd_run (so runs stay
@@ -142,9 +156,10 @@ typedef struct rsvd_plan_s* rsvd_plan_t;
  *   workspace_bytes receives the device workspace size rsvd_run needs.
  * Returns RSVD_EINVAL for m, n < 1, k < 1 (fixed rule), p < 0, q < 0,
  * R% outside (0, 100], tau outside (0, 1), an unknown mode, trailing_hp < 0,
- * or k_cap < the fixed rank, and for an adaptive problem with a fixed or
+ * or k_cap < the fixed rank, an unknown form, the symmetric form without
+ * symmetric = 1, reserved != 0, and for an adaptive problem with a fixed or
  * percent rule, block outside 0..256 or l_max < 0; RSVD_EUNSUPPORTED for
- * an adaptive problem in a mixed mode or l > 4096.
+ * an adaptive problem in a mixed mode or in the symmetric form, or l > 4096.
  * Mixed modes: of the 2q + 1 products before the projection (sketch and
  * power products), all but the last trailing_hp run on FP32 or BF16 (plain
  * or split) matrix cores with FP32 accumulation; the projection, every QR,
@@ -276,6 +291,52 @@ rsvd_status rsvd_batch_info(rsvd_batch_t plan, int32_t* lane_of, int32_t* graph_
 /* Free a batch plan with its streams, events and graph (NULL is ignored).
  * Synchronizes the lanes first. */
 void rsvd_batch_destroy(rsvd_batch_t plan);
+
+/*
+ * rsvd_residual - one decomposition truncated at rank k (section "Randomized
+ * matrix decompositions": R_SVD is the number of kept singular values, R%
+ * = 100 R_SVD / N, Eq. 2 the compression ratio; the results sweep R% and a
+ * decomposition computed at the largest R% serves every smaller one).
+ *   A, lda        m x n input (device, read only, lda >= n).
+ *   S             at least k singular values (device), U (m x >= k, ldu) and
+ *                 V (n x >= k, ldv): a decomposition of A, e.g. rsvd_run's.
+ *   k             1 <= k <= min(m, n): the leading k triplets are kept.
+ *   res_dev       device rsvd_result: rank = l_used = k, residual =
+ *                 ||A - U_k diag(S_k) V_k^T||_F / ||A||_F (one FP64 stream of
+ *                 A), rel_percent, c_eq2, c_sym and fro2 as rsvd_run reports
+ *                 them for rank k; sweeps, flags and blocks 0, err_est NaN.
+ *   work          device workspace of rsvd_residual_work_bytes(m, n, k)
+ *                 bytes, 256-byte aligned (RSVD_ENOMEM if smaller).
+ * RSVD_EINVAL for k outside 1..min(m, n), lda < n, ldu or ldv < k, null
+ * pointers. Enqueued on stream; no host synchronization.
+ */
+size_t rsvd_residual_work_bytes(int64_t m, int64_t n, int64_t k);
+rsvd_status rsvd_residual(int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
+                          const double* S, const double* U, int64_t ldu, const double* V,
+                          int64_t ldv, rsvd_result* res_dev, void* work, size_t work_bytes,
+                          void* stream);
+
+/*
+ * rsvd_factor_transform - basis transformation of a decomposed matrix on its
+ * thin factors (section "Low-rank interactions": Vbar = U^dagger V U acts on
+ * the thin L and R^dagger alone). For real U: Vbar = (U^T L) Sigma (U^T R)^T,
+ * so Lout = U^T L and Rout = U^T R; Sigma is unchanged. Both factors are
+ * multiplied in one stream of U (side by side as one N x 2k panel).
+ *   Ub, ldub      the basis, N x Nb (device, row-major, ldub >= Nb, Nb <= N);
+ *                 orthonormal columns keep Lout, Rout orthonormal (not checked).
+ *   L, ldl        N x k (device, ldl >= k); R, ldr N x k or R = NULL (then
+ *                 only L is transformed and Rout is not written).
+ *   Lout, ldlo    Nb x k output (device, ldlo >= k); Rout, ldro likewise.
+ *   work          device workspace of rsvd_factor_transform_work_bytes(N, Nb,
+ *                 k, R != NULL) bytes, 256-byte aligned (RSVD_ENOMEM if less).
+ * RSVD_EINVAL for N, Nb, k < 1, Nb > N, bad leading dimensions or null
+ * pointers. FP64 on the matrix cores; enqueued on stream.
+ */
+size_t rsvd_factor_transform_work_bytes(int64_t N, int64_t Nb, int64_t k, int32_t with_r);
+rsvd_status rsvd_factor_transform(int64_t N, int64_t Nb, int64_t k, const double* Ub, int64_t ldub,
+                                  const double* L, int64_t ldl, const double* R, int64_t ldr,
+                                  double* Lout, int64_t ldlo, double* Rout, int64_t ldro,
+                                  void* work, size_t work_bytes, void* stream);
 
 /*
  * Learned (k, p, q) predictor. The paper fixes R_SVD and the oversampling by

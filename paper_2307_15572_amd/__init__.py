@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(PKG_DIR, "librsvd.so")
 RSVD_OK, RSVD_EINVAL, RSVD_ENOMEM, RSVD_EHIP, RSVD_EUNSUPPORTED = range(5)
 RANK_MODES = {"fixed": 0, "percent": 1, "rel_threshold": 2, "frob_tail": 3}
 PRECISIONS = {"fp64": 0, "mixed_fp32": 1, "mixed_bf16": 2, "mixed_bf16_split": 3}
+FORMS = {"svd": 0, "symmetric": 1}
 FLAG_FULL_SVD = 1 << 0
 FLAG_RANK_CAPPED = 1 << 1
 FLAG_QR_FALLBACK = 1 << 2
@@ -37,6 +38,8 @@ EXPORTED = (
     "rsvd_pilot_work_bytes", "rsvd_pilot_features",
     "rsvd_tune", "rsvd_batch_tune", "rsvd_tune_entries", "rsvd_tune_clear", "rsvd_tune_set",
     "rsvd_run_noalloc", "rsvd_noalloc_max_bytes",
+    "rsvd_residual_work_bytes", "rsvd_residual",
+    "rsvd_factor_transform_work_bytes", "rsvd_factor_transform",
 )
 MLP_PARAMS, MLP_IN, MLP_OUT, MLP_MAX_BATCH, PILOT_COLS = 5443, 16, 3, 128, 32
 TRACE_PHASES = ("stream_gemm", "qr", "small_svd", "lift_signs", "residual", "omega", "other",
@@ -59,6 +62,7 @@ class Problem(ctypes.Structure):
         ("want_u", ctypes.c_int32), ("want_v", ctypes.c_int32),
         ("want_residual", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
         ("adaptive", ctypes.c_int32), ("block", ctypes.c_int32), ("l_max", ctypes.c_int64),
+        ("form", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -95,6 +99,15 @@ def lib():
     L.rsvd_run_noalloc.restype = ctypes.c_int
     L.rsvd_noalloc_max_bytes.argtypes = []
     L.rsvd_noalloc_max_bytes.restype = sz
+    L.rsvd_residual_work_bytes.argtypes = [i64, i64, i64]
+    L.rsvd_residual_work_bytes.restype = sz
+    L.rsvd_residual.argtypes = [i64, i64, i64, vp, i64, vp, vp, i64, vp, i64, vp, vp, sz, vp]
+    L.rsvd_residual.restype = ctypes.c_int
+    L.rsvd_factor_transform_work_bytes.argtypes = [i64, i64, i64, i32]
+    L.rsvd_factor_transform_work_bytes.restype = sz
+    L.rsvd_factor_transform.argtypes = [i64, i64, i64, vp, i64, vp, i64, vp, i64, vp, i64, vp, i64,
+                                        vp, sz, vp]
+    L.rsvd_factor_transform.restype = ctypes.c_int
     L.rsvd_destroy.argtypes = [vp]
     L.rsvd_destroy.restype = None
     L.rsvd_strerror.argtypes = [ctypes.c_int]
@@ -226,7 +239,8 @@ class RsvdOutput:
 
 def make_problem(m, n, k, p, q, *, symmetric=False, rank_mode="fixed", rank_param=None,
                  precision="fp64", trailing_hp=1, seed=0, channel=0, want_u=True, want_v=True,
-                 want_residual=True, max_sweeps=0, k_cap=0, adaptive=False, block=0, l_max=0):
+                 want_residual=True, max_sweeps=0, k_cap=0, adaptive=False, block=0, l_max=0,
+                 form="svd"):
     """Fill an rsvd_problem record."""
     pr = Problem()
     pr.m, pr.n, pr.k, pr.k_cap = int(m), int(n), int(k), int(k_cap)
@@ -240,6 +254,7 @@ def make_problem(m, n, k, p, q, *, symmetric=False, rank_mode="fixed", rank_para
     pr.want_u, pr.want_v = int(bool(want_u)), int(bool(want_v))
     pr.want_residual, pr.max_sweeps = int(bool(want_residual)), int(max_sweeps)
     pr.adaptive, pr.block, pr.l_max = int(bool(adaptive)), int(block), int(l_max)
+    pr.form = FORMS[form]
     return pr
 
 
@@ -248,18 +263,20 @@ class Plan:
 
     adaptive=True grows l by blocks of `block` columns up to l_max (the
     adaptive range finder of the C ABI); k is then ignored and rank_mode must
-    be "rel_threshold" or "frob_tail" with rank_param = tau.
+    be "rel_threshold" or "frob_tail" with rank_param = tau. form="symmetric"
+    (with symmetric=True) takes the l x l core Q^T A Q instead of Q^T A.
     """
 
     def __init__(self, m, n, k, p, q, *, symmetric=False, rank_mode="fixed", rank_param=None,
                  precision="fp64", trailing_hp=1, seed=0, channel=0, want_u=True, want_v=True,
-                 want_residual=True, max_sweeps=0, k_cap=0, adaptive=False, block=0, l_max=0):
+                 want_residual=True, max_sweeps=0, k_cap=0, adaptive=False, block=0, l_max=0,
+                 form="svd"):
         L = lib()
         pr = make_problem(m, n, k, p, q, symmetric=symmetric, rank_mode=rank_mode,
                           rank_param=rank_param, precision=precision, trailing_hp=trailing_hp,
                           seed=seed, channel=channel, want_u=want_u, want_v=want_v,
                           want_residual=want_residual, max_sweeps=max_sweeps, k_cap=k_cap,
-                          adaptive=adaptive, block=block, l_max=l_max)
+                          adaptive=adaptive, block=block, l_max=l_max, form=form)
         self.problem = pr
         h = ctypes.c_void_p()
         ws = ctypes.c_size_t()
@@ -489,6 +506,52 @@ def run(A, k, p, q, *, omega=None, **kw):
         fro2=r.fro2, sweeps=int(r.sweeps), flags=int(r.flags), err_est=r.err_est,
         blocks=int(r.blocks), S_all=bufs["S"][: min(plan.kc, int(r.l_used))],
     )
+
+
+def residual(A, S, U, V, k):
+    """Truncate a decomposition (S, U, V) of A at rank k: the Result record
+    with the residual ||A - U_k S_k V_k^T||_F / ||A||_F, R% and both
+    compression ratios for R_SVD = k (rsvd_residual)."""
+    torch = _torch()
+    _check_matrix(torch, A, "A")
+    _check_matrix(torch, U, "U")
+    _check_matrix(torch, V, "V")
+    m, n = A.shape
+    if U.shape[0] != m or V.shape[0] != n or min(U.shape[1], V.shape[1], S.numel()) < k:
+        raise RsvdError("factors do not match A or hold fewer than k columns")
+    S = S.contiguous()
+    res = torch.zeros(ctypes.sizeof(Result), dtype=torch.uint8, device=A.device)
+    L = lib()
+    buf, w, wb = _workspace(torch, L.rsvd_residual_work_bytes(m, n, k), A.device)
+    _check(L.rsvd_residual(m, n, k, _ptr(A), A.stride(0), _ptr(S), _ptr(U), U.stride(0), _ptr(V),
+                           V.stride(0), _ptr(res), w, wb, _stream(torch, A.device)), "rsvd_residual")
+    torch.cuda.synchronize(A.device)
+    del buf
+    return Result.from_buffer_copy(bytes(res.cpu().numpy().tobytes()))
+
+
+def factor_transform(Ub, L, R=None):
+    """Basis change on thin factors: (U^T L, U^T R) with U = Ub (N x Nb)
+    streamed once for both (rsvd_factor_transform)."""
+    torch = _torch()
+    for t, name in ((Ub, "U"), (L, "L")) + (((R, "R"),) if R is not None else ()):
+        _check_matrix(torch, t, name)
+    N, Nb = Ub.shape
+    k = L.shape[1]
+    if L.shape[0] != N or (R is not None and tuple(R.shape) != (N, k)):
+        raise RsvdError("factors must be N x k with N the rows of U")
+    Lo = torch.empty(Nb, k, dtype=torch.float64, device=Ub.device)
+    Ro = torch.empty(Nb, k, dtype=torch.float64, device=Ub.device) if R is not None else None
+    lb = lib()
+    buf, w, wb = _workspace(torch, lb.rsvd_factor_transform_work_bytes(N, Nb, k, int(R is not None)),
+                            Ub.device)
+    _check(lb.rsvd_factor_transform(N, Nb, k, _ptr(Ub), Ub.stride(0), _ptr(L), L.stride(0), _ptr(R),
+                                    R.stride(0) if R is not None else 0, _ptr(Lo), k, _ptr(Ro),
+                                    k if R is not None else 0, w, wb, _stream(torch, Ub.device)),
+           "rsvd_factor_transform")
+    torch.cuda.synchronize(Ub.device)
+    del buf
+    return Lo, Ro
 
 
 def gaussian_omega(n, l, seed, channel=0, col0=0, device="cuda"):

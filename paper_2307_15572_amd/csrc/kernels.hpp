@@ -146,6 +146,8 @@ rsvd_status init_state(DevState* st, uint32_t flags, hipStream_t s);
 rsvd_status clear_shift(DevState* st, hipStream_t s);
 rsvd_status sum_partials_into(int64_t cnt, const double* p, double* out, hipStream_t s);
 rsvd_status set_identity(int64_t l, double* P, hipStream_t s);
+// B <- (B + B^T) / 2 (l x l, in place)
+rsvd_status symmetrize(int64_t l, double* B, int64_t ldb, hipStream_t s);
 rsvd_status transpose(int64_t rows, int64_t cols, const double* src, int64_t lds, double* dst,
                       int64_t ldd, hipStream_t s);
 

@@ -21,6 +21,9 @@ struct rsvd_plan_s {
   size_t off_Rt = 0, off_Rtmp = 0, off_M = 0, off_P = 0, off_sig = 0, off_Us = 0, off_W = 0;
   size_t off_Ub = 0, off_Vb = 0, off_US = 0, off_Vt = 0, off_rpart = 0;
   size_t off_Yorig = 0, off_tau = 0;
+  // symmetric form: the l x l core B = Q^T A Q (then Q_B of its QR)
+  int form = 0;
+  size_t off_Bs = 0;
   // adaptive range finder: l above is l_max; blocks of blk columns
   bool adaptive = false;
   int64_t blk = 0;

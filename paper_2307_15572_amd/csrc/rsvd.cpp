@@ -210,7 +210,11 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* worksp
   if (p.symmetric && p.m != p.n) return RSVD_EINVAL;
   if (p.precision < RSVD_PREC_FP64 || p.precision > RSVD_PREC_MIXED_BF16_SPLIT) return RSVD_EINVAL;
   if (p.trailing_hp < 0) return RSVD_EINVAL;
+  if (p.reserved != 0) return RSVD_EINVAL;
+  if (p.form != RSVD_FORM_SVD && p.form != RSVD_FORM_SYMMETRIC) return RSVD_EINVAL;
+  if (p.form == RSVD_FORM_SYMMETRIC && !p.symmetric) return RSVD_EINVAL;
   const bool adaptive = p.adaptive != 0;
+  if (adaptive && p.form == RSVD_FORM_SYMMETRIC) return RSVD_EUNSUPPORTED;
   int64_t k = p.k;
   int mode = p.rank_mode;
   double param = p.rank_param;
@@ -259,6 +263,7 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* worksp
   pl->param = param;
   pl->adaptive = adaptive;
   pl->blk = blk;
+  pl->form = p.form;
   const int64_t m = p.m, n = p.n, kc = pl->kc;
   const int64_t mx = m > n ? m : n;
   const size_t D = sizeof(double);
@@ -307,6 +312,7 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* worksp
   pl->off_M = c.take((size_t)Lp * Lp * D);
   pl->off_P = c.take((size_t)Lp * Lp * D);
   pl->off_sig = c.take((size_t)l * D);
+  if (p.form == RSVD_FORM_SYMMETRIC) pl->off_Bs = c.take(ll);
   pl->off_Us = c.take((size_t)l * kc * D);
   pl->off_W = c.take((size_t)l * kc * D);
   pl->off_Ub = c.take((size_t)m * kc * D);
@@ -382,15 +388,16 @@ struct Outs {
 // Step 2 on a basis of width l whose transposed projection Y^T = A^T Q
 // (n x l, contiguous) is in Zc: Y^T = Q_B X_B (Zc <- Q_B), SVD of X_B^T by
 // one-sided Jacobi, singular values ordered decreasingly, then the rank rule.
+// rows: the rows of the panel Zc (n, or l for the symmetric form's l x l core).
 rsvd_status small_svd_and_rank(const rsvd_plan_s& pl, const Ws& w, int64_t l, double* Zc,
-                               hipStream_t s) {
+                               hipStream_t s, int64_t rows = -1) {
   const rsvd_problem& p = pl.p;
   DevState* st = w.at<DevState>(pl.off_state);
   double* Rt = w.at<double>(pl.off_Rt);
   const int64_t kcl = pl.kc < l ? pl.kc : l;
   {
     PhaseScope ph(1, s);
-    RSVD_TRY(orth(pl, w, p.n, l, Zc, Rt, s, true));
+    RSVD_TRY(orth(pl, w, rows < 0 ? p.n : rows, l, Zc, Rt, s, true));
   }
   {
     PhaseScope ph(2, s);
@@ -692,6 +699,30 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
     RSVD_TRY(stream_pass(false, Z, l, Y, m, n));
     RSVD_TRY(qr(m, Y, t + 1 == p.power_iters));
   }
+  if (pl.form == RSVD_FORM_SYMMETRIC) {
+    // symmetric form: C = A Q (the projection's stream of A), B = Q^T C
+    // (l x l) symmetrized; B = Q_b X_b (QR of B = B^T), SVD of X_b^T =
+    // L_b Sigma W^T by Jacobi, so B = L_b Sigma (Q_b W)^T; then L = Q L_b and
+    // R = Q (Q_b W)
+    RSVD_TRY(stream_pass(false, Y, l, Z, n, m));
+    double* Bs = w.at<double>(pl.off_Bs);
+    {
+      PhaseScope ph(2, s);
+      RSVD_TRY(dgemm(true, l, l, m, 1.0, Y, l, Z, l, 0.0, Bs, l, part, pl.part_doubles, s));
+      RSVD_TRY(symmetrize(l, Bs, l, s));
+    }
+    RSVD_TRY(small_svd_and_rank(pl, w, l, Bs, s, l));
+    const int64_t kcl = pl.kc < l ? pl.kc : l;
+    double* Wv = w.at<double>(pl.off_W);
+    double* Rtmp = w.at<double>(pl.off_Rtmp);
+    {
+      PhaseScope ph(3, s);
+      RSVD_TRY(dgemm(false, l, kcl, l, 1.0, Bs, l, Wv, kcl, 0.0, Rtmp, kcl, part, pl.part_doubles,
+                     s));
+      RSVD_TRY(copy_panel(l, kcl, Rtmp, kcl, Wv, kcl, 0, st, s));
+    }
+    return lift_and_finish(pl, w, A, lda, l, Y, l, Y, o, __builtin_nan(""), 0, res_dev, s);
+  }
   // step 2: Y^T = A^T Q = Q_B X_B, small SVD of X_B^T, rank rule
   RSVD_TRY(stream_pass(!p.symmetric, Y, l, Z, n, m));
   RSVD_TRY(small_svd_and_rank(pl, w, l, Z, s));
@@ -896,6 +927,123 @@ rsvd_status rsvd_small_svd(int64_t l, const double* R, double* sv, double* Us, d
   return RSVD_OK;
 #undef RSVD_TRY
 }
+
+// ---- truncation of a computed decomposition ---------------------------------
+
+#define RSVD_TRY(x) do { rsvd_status r_ = (x); if (r_ != RSVD_OK) return r_; } while (0)
+
+namespace {
+struct ResidualLayout {
+  size_t off_state = 0, off_US = 0, off_Vt = 0, off_part = 0, total = 0;
+  int64_t kcp = 0;
+  ResidualLayout(int64_t m, int64_t n, int64_t k) {
+    kcp = (k + 15) / 16 * 16;
+    Carver c;
+    off_state = c.take(sizeof(DevState));
+    off_US = c.take((size_t)m * kcp * sizeof(double));
+    off_Vt = c.take((size_t)kcp * n * sizeof(double));
+    off_part = c.take(resid_partials(m, n) * sizeof(double));
+    total = c.at;
+  }
+};
+}  // namespace
+
+size_t rsvd_residual_work_bytes(int64_t m, int64_t n, int64_t k) {
+  if (m < 1 || n < 1 || k < 1) return 0;
+  return ResidualLayout(m, n, k).total;
+}
+
+rsvd_status rsvd_residual(int64_t m, int64_t n, int64_t k, const double* A, int64_t lda,
+                          const double* S, const double* U, int64_t ldu, const double* V,
+                          int64_t ldv, rsvd_result* res_dev, void* work, size_t work_bytes,
+                          void* stream) {
+  if (m < 1 || n < 1 || k < 1 || k > (m < n ? m : n)) return RSVD_EINVAL;
+  if (!A || !S || !U || !V || !res_dev || !work || lda < n || ldu < k || ldv < k)
+    return RSVD_EINVAL;
+  const ResidualLayout lay(m, n, k);
+  if (work_bytes < lay.total) return RSVD_ENOMEM;
+  if (((uintptr_t)work & 255) != 0) return RSVD_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  Ws w{(char*)work};
+  DevState* st = w.at<DevState>(lay.off_state);
+  double* US = w.at<double>(lay.off_US);
+  double* Vt = w.at<double>(lay.off_Vt);
+  RSVD_TRY(init_state(st, 0u, s));
+  // the fixed rule at k sets the rank the padded factors keep
+  RSVD_TRY(select_rank(k, 0, k, RSVD_RANK_FIXED, (double)k, S, st, s));
+  RSVD_TRY(resid_prep(m, n, k, lay.kcp, U, ldu, S, V, ldv, US, Vt, st, s));
+  RSVD_TRY(resid(m, n, lay.kcp, US, lay.kcp, Vt, n, A, lda, w.at<double>(lay.off_part), st, s));
+  return finalize(m, n, k, 1, __builtin_nan(""), 0, st, res_dev, s);
+}
+
+// ---- basis transformation on thin factors -------------------------------------
+
+namespace {
+struct TransformLayout {
+  size_t off_X = 0, off_Xt = 0, off_Ct = 0, off_O = 0, off_part = 0, total = 0;
+  int64_t K2 = 0;
+  size_t part_doubles = 0;
+  TransformLayout(int64_t N, int64_t Nb, int64_t k, bool with_r) {
+    K2 = with_r ? 2 * k : k;
+    part_doubles = dgemm_shape(Nb, K2, N).part_doubles;
+    const size_t t1 = dgemm_shape(K2, Nb, N).part_doubles;
+    if (t1 > part_doubles) part_doubles = t1;
+    const size_t t2 = (size_t)kTransSplits * K2 * Nb;
+    if (t2 > part_doubles) part_doubles = t2;
+    if (part_doubles < 2048) part_doubles = 2048;
+    const size_t D = sizeof(double);
+    Carver c;
+    off_X = c.take((size_t)N * K2 * D);
+    off_Xt = c.take((size_t)K2 * N * D);
+    off_Ct = c.take((size_t)K2 * Nb * D);
+    off_O = c.take((size_t)Nb * K2 * D);
+    off_part = c.take(part_doubles * D);
+    total = c.at;
+  }
+};
+}  // namespace
+
+size_t rsvd_factor_transform_work_bytes(int64_t N, int64_t Nb, int64_t k, int32_t with_r) {
+  if (N < 1 || Nb < 1 || k < 1 || Nb > N) return 0;
+  return TransformLayout(N, Nb, k, with_r != 0).total;
+}
+
+rsvd_status rsvd_factor_transform(int64_t N, int64_t Nb, int64_t k, const double* Ub, int64_t ldub,
+                                  const double* L, int64_t ldl, const double* R, int64_t ldr,
+                                  double* Lout, int64_t ldlo, double* Rout, int64_t ldro,
+                                  void* work, size_t work_bytes, void* stream) {
+  if (N < 1 || Nb < 1 || k < 1 || Nb > N) return RSVD_EINVAL;
+  if (!Ub || !L || !Lout || !work || ldub < Nb || ldl < k || ldlo < k) return RSVD_EINVAL;
+  if (R && (!Rout || ldr < k || ldro < k)) return RSVD_EINVAL;
+  const TransformLayout lay(N, Nb, k, R != nullptr);
+  if (work_bytes < lay.total) return RSVD_ENOMEM;
+  if (((uintptr_t)work & 255) != 0) return RSVD_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  Ws w{(char*)work};
+  const int64_t K2 = lay.K2;
+  double* X = w.at<double>(lay.off_X);
+  double* O = w.at<double>(lay.off_O);
+  double* part = w.at<double>(lay.off_part);
+  // [L R] side by side: one stream of U serves both factors
+  RSVD_TRY(copy_panel(N, k, L, ldl, X, K2, 0, nullptr, s));
+  if (R) RSVD_TRY(copy_panel(N, k, R, ldr, X + k, K2, 0, nullptr, s));
+  double* Xt = w.at<double>(lay.off_Xt);
+  double* Ct = w.at<double>(lay.off_Ct);
+  if (N * Nb >= kTransStreamMin && K2 >= 16 && dgemm_dma_eligible(N, Nb, Xt, N, Ub, ldub)) {
+    // U^T X = (X^T U)^T: U streams in its stored orientation through the
+    // LDS-DMA kernel between two transposes of the skinny panels
+    RSVD_TRY(transpose(N, K2, X, K2, Xt, N, s));
+    RSVD_TRY(dgemm(false, K2, Nb, N, 1.0, Xt, N, Ub, ldub, 0.0, Ct, Nb, part, lay.part_doubles, s));
+    RSVD_TRY(transpose(K2, Nb, Ct, Nb, O, K2, s));
+  } else {
+    RSVD_TRY(dgemm(true, Nb, K2, N, 1.0, Ub, ldub, X, K2, 0.0, O, K2, part, lay.part_doubles, s));
+  }
+  RSVD_TRY(copy_panel(Nb, k, O, K2, Lout, ldlo, 0, nullptr, s));
+  if (R) RSVD_TRY(copy_panel(Nb, k, O + k, K2, Rout, ldro, 0, nullptr, s));
+  return RSVD_OK;
+}
+
+#undef RSVD_TRY
 
 // ---- learned (k, p, q) predictor ---------------------------------------------
 

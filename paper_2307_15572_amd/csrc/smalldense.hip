@@ -1343,6 +1343,20 @@ __global__ void __launch_bounds__(256) copy_panel_kernel(int64_t rows, int64_t c
   dst[r * ldd + c] = src[r * lds + c];
 }
 
+// B <- (B + B^T) / 2 in place (l x l): the thread of each pair i < j reads
+// both entries and writes their average to both, so no entry is read after
+// another thread wrote it.
+__global__ void __launch_bounds__(256) symmetrize_kernel(int64_t l, double* __restrict__ B,
+                                                         int64_t ldb) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= l * l) return;
+  const int64_t i = idx / l, j = idx % l;
+  if (i >= j) return;
+  const double a = 0.5 * (B[i * ldb + j] + B[j * ldb + i]);
+  B[i * ldb + j] = a;
+  B[j * ldb + i] = a;
+}
+
 __global__ void __launch_bounds__(256) identity_kernel(int64_t l, double* P) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= l * l) return;
@@ -1851,6 +1865,13 @@ rsvd_status copy_panel(int64_t rows, int64_t cols, const double* src, int64_t ld
   if (rows * cols == 0) return RSVD_OK;
   hipLaunchKernelGGL(copy_panel_kernel, dim3(blocks_for(rows * cols, 256)), dim3(256), 0, s, rows,
                      cols, src, lds, dst, ldd, cond_shifted, (const DevState*)st);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status symmetrize(int64_t l, double* B, int64_t ldb, hipStream_t s) {
+  if (l <= 1) return RSVD_OK;
+  hipLaunchKernelGGL(symmetrize_kernel, dim3(blocks_for(l * l, 256)), dim3(256), 0, s, l, B, ldb);
   RSVD_LAUNCH_CHECK();
   return RSVD_OK;
 }
