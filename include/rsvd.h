@@ -84,9 +84,16 @@ enum {
   RSVD_FLAG_NONFINITE_INPUT = 1u << 4, /* A holds NaN or Inf                         */
   RSVD_FLAG_ZERO_SIGMA = 1u << 5,      /* a singular value is exactly zero           */
   RSVD_FLAG_ADAPT_LIMIT = 1u << 6,     /* adaptive growth stopped at l_max           */
-  RSVD_FLAG_SYNC_TIMEOUT = 1u << 7     /* a grid-wide barrier (multi-workgroup Cholesky,
+  RSVD_FLAG_SYNC_TIMEOUT = 1u << 7,    /* a grid-wide barrier (multi-workgroup Cholesky,
                                           Householder fallback or small SVD) gave up
                                           waiting (bounded wait): results invalid     */
+  /* set only by runs with posterior > 0 (the a-posteriori judge, below):       */
+  RSVD_FLAG_POSTERIOR_FAIL = 1u << 8,  /* REL_THRESHOLD: the posterior estimate of
+                                          ||(I - QQ^T) A||_2 exceeds tau s_1: the basis
+                                          may miss values above the threshold        */
+  RSVD_FLAG_UNCONVERGED = 1u << 9      /* threshold rules: (s_l / s_k)^(4q + 2) > 1e-8
+                                          for the kept rank k (Halko et al.'s subspace-
+                                          iteration factor): kept values not converged */
 };
 
 typedef struct rsvd_problem {
@@ -113,7 +120,15 @@ typedef struct rsvd_problem {
   int32_t block;         /* adaptive: columns added per growth step (1..256; 0 = 64) */
   int64_t l_max;         /* adaptive: largest l (0 = min(m, n, 4096))              */
   int32_t form;          /* RSVD_FORM_* (0 = the paper's one-sided projection)     */
-  int32_t reserved;      /* must be 0                                              */
+  int32_t posterior;     /* fixed-l runs: r probe columns (0 = none, 1..64) for the
+                            a-posteriori judge: columns l .. l+r-1 of the same
+                            Philox stream, W = (I - QQ^T) A P_r on the final basis
+                            Q (one more FP64 stream of A with r columns), err_est =
+                            10 sqrt(2/pi) max_j ||W_j|| (Halko et al. 2011, section
+                            4.3: bounds ||(I - QQ^T) A||_2 except with probability
+                            10^-r); threshold rules then also set POSTERIOR_FAIL /
+                            UNCONVERGED. Adaptive runs: must be 0 (they judge
+                            every block themselves)                              */
 } rsvd_problem;
 
 /* Result record, written to DEVICE memory by rsvd_run (so runs stay
@@ -131,7 +146,8 @@ typedef struct rsvd_result {
   double err_est;        /* adaptive: last error estimate of the basis (posterior
                             estimate of ||(I - QQ^T) A||_2 for REL_THRESHOLD, the
                             Frobenius indicator sqrt(||A||_F^2 - ||Q^T A||_F^2) for
-                            FROB_TAIL); NaN for a fixed-l run                      */
+                            FROB_TAIL); fixed-l run: the posterior estimate when
+                            posterior > 0, else NaN                                */
   int32_t blocks;        /* adaptive: growth steps taken (0 for a fixed-l run)     */
   int32_t reserved;
 } rsvd_result;
@@ -157,7 +173,8 @@ typedef struct rsvd_plan_s* rsvd_plan_t;
  * Returns RSVD_EINVAL for m, n < 1, k < 1 (fixed rule), p < 0, q < 0,
  * R% outside (0, 100], tau outside (0, 1), an unknown mode, trailing_hp < 0,
  * or k_cap < the fixed rank, an unknown form, the symmetric form without
- * symmetric = 1, reserved != 0, and for an adaptive problem with a fixed or
+ * symmetric = 1, posterior outside 0..64 (or != 0 when adaptive), and for
+ * an adaptive problem with a fixed or
  * percent rule, block outside 0..256 or l_max < 0; RSVD_EUNSUPPORTED for
  * an adaptive problem in a mixed mode or in the symmetric form, or l > 4096.
  * Mixed modes: of the 2q + 1 products before the projection (sketch and
@@ -383,6 +400,44 @@ rsvd_status rsvd_mlp_grad(const float* params, const float* X, const float* T, i
 rsvd_status rsvd_mlp_train_step(float* params, float* adam_m, float* adam_v, int64_t step,
                                 const float* X, const float* T, int64_t B, float lr,
                                 float* loss, void* stream);
+/* Training targets: labels (B x 3 device int64: k, p, q per sample, k >= 1)
+ * -> raw targets (log10 k, p, q) -> per-column mean and standard deviation
+ * (population; a zero deviation counts as 1) into stats (6 device floats:
+ * mean[3], sd[3]) -> standardized targets T (B x 3 device floats). B >= 1. */
+rsvd_status rsvd_mlp_targets(const int64_t* labels, int64_t B, float* stats, float* T,
+                             void* stream);
+/* Sizing from the network: y = MLP(X) (B x 16 features), raw = y sd + mean
+ * (stats as rsvd_mlp_targets writes them), then per sample
+ *   k = min(max(ceil(1.1 * 10^raw0), 1), n_cap[b])   (10 % rank margin)
+ *   p = the smallest of {8, 16, 32, 64, 128, 192, 256, 384} >= raw1 (else 384)
+ *   q = min(max(ceil(raw2), 0), 4)
+ * into kpq (B x 3 device int64). n_cap: B device int64 (min(m, n) of each
+ * channel). B >= 0. */
+rsvd_status rsvd_mlp_predict(const float* params, const float* stats, const float* X, int64_t B,
+                             const int64_t* n_cap, int64_t* kpq, void* stream);
+/* Label of one channel from a spectrum the method computed (e.g. the
+ * adaptive finder's singular values s, count of them, decreasing, device)
+ * with threshold rank k (>= 1) of an n x n channel: the cheapest (p, q) on
+ * the grid p in {8, 16, 32, 64, 128, 192, 256, 384}, q in 0..4 whose l = k + p reaches
+ * n (an exact SVD), or whose l is at least l_min (the width at which the
+ * adaptive finder's posterior estimate passed: the basis covers the tail)
+ * and whose kept values are converged, (s[k+p-1] / s[k-1])^(4q+2) <= 1e-8
+ * (for k + p > count the last computed value stands in: the ratio only
+ * falls beyond it). Cost of a decomposition of
+ * width l: (2q+2) n^2 l (products with A) + 11.4 (2q+1) n l^2 (panel QRs)
+ * + 5000 l^3 (the small SVD), the weights being measured times of a QR and
+ * of the small SVD in units of products with A (16384^2, l = 272).
+ * kpq (3 device int64) = (k, p, q); p = q = -1 when no grid point
+ * qualifies. */
+rsvd_status rsvd_size_label(const double* s, int64_t count, int64_t k, int64_t n, int64_t l_min,
+                            int64_t* kpq, void* stream);
+/* Save / load the network: a binary file holding the 8-byte tag
+ * "RSVDMLP1", the counts 5443 and 6 (uint32 each), the parameters and the
+ * stats (FP32). Both synchronize the stream; RSVD_EINVAL for a file that
+ * cannot be opened or holds anything else. */
+rsvd_status rsvd_mlp_save(const char* path, const float* params, const float* stats,
+                          void* stream);
+rsvd_status rsvd_mlp_load(const char* path, float* params, float* stats, void* stream);
 /* Pilot features of A (m x n, lda, device): feat = 16 device floats. work:
  * device workspace of rsvd_pilot_work_bytes(m, n) bytes, 256-B aligned. */
 size_t rsvd_pilot_work_bytes(int64_t m, int64_t n);

@@ -173,3 +173,37 @@ def rsvd_adaptive(A, tau, p, q, block=64, seed=0, channel=0, symmetric=False, l_
         extra={"fro2": fro2, "est": est, "blocks": blocks, "fro2_Y": fro2_Y,
                "history": history, "Y": Y},
     )
+
+
+FLAG_POSTERIOR_FAIL = 256
+FLAG_UNCONVERGED = 512
+CONVERGED_RATIO = 1e-8
+
+
+def posterior_judge(A, Q, s_all, rank, q, tau, r, seed=0, channel=0, rel_threshold=True):
+    """A-posteriori judge of a fixed-l run with final basis Q (m x l) and
+    computed values s_all (l, decreasing), kept rank `rank`:
+
+      est = 10 sqrt(2/pi) max_j ||(I - Q Q^T) A P_r e_j||, P_r = columns
+            l .. l + r - 1 of the projection stream (Halko et al., section 4.3)
+      UNCONVERGED     when (s_l / s_k)^(4q + 2) > 1e-8 (k = rank), the
+                      subspace-iteration factor of the kept values
+      POSTERIOR_FAIL  (relative threshold) when est > tau s_1
+
+    An exact decomposition (l = min(m, n)) is never flagged. Returns
+    (est, flags)."""
+    A = np.asarray(A, dtype=np.float64)
+    m, n = A.shape
+    l = Q.shape[1]
+    P = gaussian_omega(n, l + r, seed, channel)[:, l:]
+    W = _deflate(Q, A @ P)
+    est = POSTERIOR_FACTOR * float(np.sqrt(np.max(np.sum(W * W, axis=0))))
+    flags = 0
+    if l < min(m, n):
+        k = rank
+        if 1 <= k < l and s_all[k - 1] > 0:
+            if not (s_all[l - 1] / s_all[k - 1]) ** (4 * q + 2) <= CONVERGED_RATIO:
+                flags |= FLAG_UNCONVERGED
+        if rel_threshold and not est <= tau * s_all[0]:
+            flags |= FLAG_POSTERIOR_FAIL
+    return est, flags

@@ -26,7 +26,16 @@ channel from a cheap pilot sketch, so most channels need no adaptive growth:
 Parameter layout (one flat FP32 vector on the device, the same order here):
 W1 (64 x 16, row-major), b1 (64), W2 (64 x 64), b2 (64), W3 (3 x 64), b3 (3).
 
-Pins (tests/test_oracle_mlp.py): fourth-order finite-difference gradients
+Sizing (the same rules as the device): targets() standardizes integer labels
+(log10 k, p, q) by their column means and population deviations; decode()
+turns a network output back into (k, p, q) with a 10 % rank margin and the
+grids p in {8, 16, 32, 64, 128, 192, 256, 384}, q in 0..4; size_label() picks a label
+from a spectrum the method computed: the cheapest grid point whose kept
+values are converged, (s_{k+p}/s_k)^(4q+2) <= 1e-8, by the cost of the
+products with A, the panel QRs and the small SVD.
+
+Pins (tests/test_oracle_mlp.py): hand-worked standardization, decoding and
+labels; fourth-order finite-difference gradients
 of the loss, Adam against its closed form for the first steps, the He
 moments, the feature map on matrices with known spectra (slope of a
 10^(-i/4) spectrum, the rounding floor of a rank-1 matrix, exact invariance
@@ -149,3 +158,64 @@ def pilot_features(A, seed, channel=0):
         with np.errstate(divide="ignore"):
             f[: len(r)] = np.maximum(np.log10(r), FEATURE_FLOOR)
     return f
+
+
+# ---- sizing from the network and labels from computed spectra ---------------
+P_GRID = (8, 16, 32, 64, 128, 192, 256, 384)
+Q_MAX = 4
+RANK_MARGIN = 1.1
+# cost of a decomposition of width l in units of multiply-adds with A:
+# (2q+2) n^2 l products, QR_WEIGHT (2q+1) n l^2 panel QRs, SVD_WEIGHT l^3 the
+# small SVD (measured times of one QR and of the small SVD relative to one
+# product with A at 16384^2, l = 272)
+QR_WEIGHT = 11.4
+SVD_WEIGHT = 5000.0
+
+
+def targets(labels):
+    """Raw targets (log10 k, p, q) of integer labels, their column means and
+    population standard deviations (0 -> 1), and the standardized targets."""
+    L = np.asarray(labels, dtype=np.float64).reshape(-1, 3)
+    raw = np.stack([np.log10(np.maximum(L[:, 0], 1.0)), L[:, 1], L[:, 2]], axis=1)
+    mean = raw.mean(axis=0)
+    sd = raw.std(axis=0)
+    sd[sd == 0] = 1.0
+    return (raw - mean) / sd, mean, sd
+
+
+def decode(y, mean, sd, n_cap):
+    """Network output y (3 values, standardized) -> (k, p, q): k with a 10 %
+    margin rounded up into 1..n_cap, p rounded up to the grid (384 beyond it),
+    q rounded up into 0..4."""
+    raw = [float(y[i]) * float(sd[i]) + float(mean[i]) for i in range(3)]
+    kk = math.ceil(RANK_MARGIN * 10.0 ** raw[0]) if raw[0] < 300 else math.inf
+    k = int(min(max(kk, 1), n_cap))
+    p = next((g for g in P_GRID if g >= raw[1]), P_GRID[-1])
+    q = int(min(max(math.ceil(raw[2] - 1e-9), 0), Q_MAX))
+    return k, p, q
+
+
+def size_label(s, k, n, l_min=0):
+    """Cheapest (p, q) on the grid whose l = k + p reaches n, or whose l is at
+    least l_min (the width at which the labelling run's posterior estimate
+    passed) and whose kept values are converged on the computed spectrum s
+    (decreasing): (s[k+p-1] / s[k-1])^(4q+2) <= 1e-8, the last computed value
+    standing in beyond len(s) (the ratio only falls further). Returns
+    (k, p, q), with p = q = -1 when no grid point qualifies."""
+    best = None
+    for q in range(Q_MAX + 1):
+        for p in P_GRID:
+            if k + p < n:
+                if k + p < l_min:
+                    continue
+                j = min(k + p, len(s))
+                if j <= k:
+                    continue
+                r = s[j - 1] / s[k - 1] if s[k - 1] > 0 else 0.0
+                if not r ** (4 * q + 2) <= 1e-8:
+                    continue
+            L = min(k + p, n)
+            cost = (2 * q + 2) * n * n * L + QR_WEIGHT * (2 * q + 1) * n * L * L + SVD_WEIGHT * L ** 3
+            if best is None or cost < best[0]:
+                best = (cost, p, q)
+    return (k, best[1], best[2]) if best else (k, -1, -1)

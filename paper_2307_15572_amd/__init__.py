@@ -26,6 +26,8 @@ FLAG_NONFINITE_INPUT = 1 << 4
 FLAG_ZERO_SIGMA = 1 << 5
 FLAG_ADAPT_LIMIT = 1 << 6
 FLAG_SYNC_TIMEOUT = 1 << 7
+FLAG_POSTERIOR_FAIL = 1 << 8
+FLAG_UNCONVERGED = 1 << 9
 
 EXPORTED = (
     "rsvd_plan", "rsvd_plan_l", "rsvd_run", "rsvd_destroy", "rsvd_strerror",
@@ -40,6 +42,7 @@ EXPORTED = (
     "rsvd_run_noalloc", "rsvd_noalloc_max_bytes",
     "rsvd_residual_work_bytes", "rsvd_residual",
     "rsvd_factor_transform_work_bytes", "rsvd_factor_transform",
+    "rsvd_mlp_targets", "rsvd_mlp_predict", "rsvd_size_label", "rsvd_mlp_save", "rsvd_mlp_load",
 )
 MLP_PARAMS, MLP_IN, MLP_OUT, MLP_MAX_BATCH, PILOT_COLS = 5443, 16, 3, 128, 32
 TRACE_PHASES = ("stream_gemm", "qr", "small_svd", "lift_signs", "residual", "omega", "other",
@@ -62,7 +65,7 @@ class Problem(ctypes.Structure):
         ("want_u", ctypes.c_int32), ("want_v", ctypes.c_int32),
         ("want_residual", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
         ("adaptive", ctypes.c_int32), ("block", ctypes.c_int32), ("l_max", ctypes.c_int64),
-        ("form", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("form", ctypes.c_int32), ("posterior", ctypes.c_int32),
     ]
 
 
@@ -166,6 +169,16 @@ def lib():
     L.rsvd_mlp_grad.restype = ctypes.c_int
     L.rsvd_mlp_train_step.argtypes = [fp, fp, fp, i64, fp, fp, i64, ctypes.c_float, fp, vp]
     L.rsvd_mlp_train_step.restype = ctypes.c_int
+    L.rsvd_mlp_targets.argtypes = [vp, i64, fp, fp, vp]
+    L.rsvd_mlp_targets.restype = ctypes.c_int
+    L.rsvd_mlp_predict.argtypes = [fp, fp, fp, i64, vp, vp, vp]
+    L.rsvd_mlp_predict.restype = ctypes.c_int
+    L.rsvd_size_label.argtypes = [vp, i64, i64, i64, i64, vp, vp]
+    L.rsvd_size_label.restype = ctypes.c_int
+    L.rsvd_mlp_save.argtypes = [ctypes.c_char_p, fp, fp, vp]
+    L.rsvd_mlp_save.restype = ctypes.c_int
+    L.rsvd_mlp_load.argtypes = [ctypes.c_char_p, fp, fp, vp]
+    L.rsvd_mlp_load.restype = ctypes.c_int
     L.rsvd_pilot_work_bytes.argtypes = [i64, i64]
     L.rsvd_pilot_work_bytes.restype = sz
     L.rsvd_pilot_features.argtypes = [vp, i64, i64, i64, u64, u64, fp, vp, sz, vp]
@@ -240,7 +253,7 @@ class RsvdOutput:
 def make_problem(m, n, k, p, q, *, symmetric=False, rank_mode="fixed", rank_param=None,
                  precision="fp64", trailing_hp=1, seed=0, channel=0, want_u=True, want_v=True,
                  want_residual=True, max_sweeps=0, k_cap=0, adaptive=False, block=0, l_max=0,
-                 form="svd"):
+                 form="svd", posterior=0):
     """Fill an rsvd_problem record."""
     pr = Problem()
     pr.m, pr.n, pr.k, pr.k_cap = int(m), int(n), int(k), int(k_cap)
@@ -255,6 +268,7 @@ def make_problem(m, n, k, p, q, *, symmetric=False, rank_mode="fixed", rank_para
     pr.want_residual, pr.max_sweeps = int(bool(want_residual)), int(max_sweeps)
     pr.adaptive, pr.block, pr.l_max = int(bool(adaptive)), int(block), int(l_max)
     pr.form = FORMS[form]
+    pr.posterior = int(posterior)
     return pr
 
 
@@ -270,13 +284,14 @@ class Plan:
     def __init__(self, m, n, k, p, q, *, symmetric=False, rank_mode="fixed", rank_param=None,
                  precision="fp64", trailing_hp=1, seed=0, channel=0, want_u=True, want_v=True,
                  want_residual=True, max_sweeps=0, k_cap=0, adaptive=False, block=0, l_max=0,
-                 form="svd"):
+                 form="svd", posterior=0):
         L = lib()
         pr = make_problem(m, n, k, p, q, symmetric=symmetric, rank_mode=rank_mode,
                           rank_param=rank_param, precision=precision, trailing_hp=trailing_hp,
                           seed=seed, channel=channel, want_u=want_u, want_v=want_v,
                           want_residual=want_residual, max_sweeps=max_sweeps, k_cap=k_cap,
-                          adaptive=adaptive, block=block, l_max=l_max, form=form)
+                          adaptive=adaptive, block=block, l_max=l_max, form=form,
+                          posterior=posterior)
         self.problem = pr
         h = ctypes.c_void_p()
         ws = ctypes.c_size_t()
@@ -725,13 +740,29 @@ def pilot_features(A, seed, channel=0, work=None):
     return feat, work
 
 
+def size_label(S, k, n, l_min=0):
+    """(k, p, q) label of a channel from a spectrum the method computed (S:
+    device FP64 values, decreasing), its threshold rank k and the width l_min
+    the labelling run needed for its posterior estimate (rsvd_size_label);
+    p = q = -1 when no grid point qualifies."""
+    torch = _torch()
+    S = S.contiguous()
+    out = torch.empty(3, dtype=torch.int64, device=S.device)
+    _check(lib().rsvd_size_label(_ptr(S), S.numel(), int(k), int(n), int(l_min), _ptr(out),
+                                 _stream(torch, S.device)), "rsvd_size_label")
+    return tuple(int(x) for x in out.cpu().tolist())
+
+
 class Mlp:
-    """The 16-64-64-3 predictor: flat FP32 parameters and Adam moments on the
-    device; every computation runs in the library's kernels."""
+    """The 16-64-64-3 predictor: flat FP32 parameters, Adam moments and the
+    target statistics (mean[3], sd[3]) on the device; every computation runs
+    in the library's kernels."""
 
     def __init__(self, seed=0, device="cuda"):
         torch = _torch()
         self.device = torch.device(device)
+        self.stats = torch.zeros(6, dtype=torch.float32, device=self.device)
+        self.stats[3:] = 1.0
         self.params = torch.empty(MLP_PARAMS, dtype=torch.float32, device=self.device)
         self.m = torch.zeros_like(self.params)
         self.v = torch.zeros_like(self.params)
@@ -763,6 +794,41 @@ class Mlp:
         _check(lib().rsvd_mlp_grad(_ptr(self.params), _ptr(X), _ptr(T), X.shape[0], _ptr(g),
                                    _ptr(self._loss), _stream(torch, X.device)), "rsvd_mlp_grad")
         return float(self._loss.item()), g
+
+    def targets(self, labels):
+        """Standardized training targets (device B x 3 FP32) from integer
+        (k, p, q) labels (B x 3); sets the target statistics (rsvd_mlp_targets)."""
+        torch = _torch()
+        lab = torch.as_tensor(labels, dtype=torch.int64).reshape(-1, 3).to(self.device).contiguous()
+        T = torch.empty(lab.shape[0], MLP_OUT, dtype=torch.float32, device=self.device)
+        _check(lib().rsvd_mlp_targets(_ptr(lab), lab.shape[0], _ptr(self.stats), _ptr(T),
+                                      _stream(torch, self.device)), "rsvd_mlp_targets")
+        return T
+
+    def predict(self, X, n_cap):
+        """Sizing (k, p, q) per sample (rsvd_mlp_predict): X device B x 16
+        features, n_cap the min(m, n) of each channel. Returns a host list of
+        (k, p, q) tuples (one synchronization)."""
+        torch = _torch()
+        self._f32(torch, X, MLP_IN, "X")
+        nc = torch.as_tensor(list(n_cap), dtype=torch.int64).to(X.device).contiguous()
+        if nc.numel() != X.shape[0]:
+            raise RsvdError("one n_cap per sample")
+        kpq = torch.empty(X.shape[0], 3, dtype=torch.int64, device=X.device)
+        _check(lib().rsvd_mlp_predict(_ptr(self.params), _ptr(self.stats), _ptr(X), X.shape[0],
+                                      _ptr(nc), _ptr(kpq), _stream(torch, X.device)),
+               "rsvd_mlp_predict")
+        return [tuple(int(v) for v in row) for row in kpq.cpu().tolist()]
+
+    def save(self, path):
+        torch = _torch()
+        _check(lib().rsvd_mlp_save(os.fsencode(path), _ptr(self.params), _ptr(self.stats),
+                                   _stream(torch, self.device)), "rsvd_mlp_save")
+
+    def load(self, path):
+        torch = _torch()
+        _check(lib().rsvd_mlp_load(os.fsencode(path), _ptr(self.params), _ptr(self.stats),
+                                   _stream(torch, self.device)), "rsvd_mlp_load")
 
     def train_step(self, X, T, lr=1e-3):
         """One Adam step on a batch (B <= 128); returns a device scalar with the

@@ -199,6 +199,13 @@ __device__ inline void grid_barrier_reset(GridBar* gb) {
 }
 
 // Device-side scalar state of one decomposition, kept in the workspace.
+// Halko, Martinsson and Tropp (2011), Eq. (4.3): ||(I - QQ^T) A||_2 <=
+// 10 sqrt(2/pi) max_j ||(I - QQ^T) A w_j|| for r Gaussian w_j, except with
+// probability 10^-r.
+constexpr double kPosteriorFactor = 7.978845608028654;
+// converged kept values: (s_l / s_k)^(4q + 2) <= kConvergedRatio
+constexpr double kConvergedRatio = 1e-8;
+
 struct DevState {
   uint32_t flags;        // RSVD_FLAG_* accumulated by the kernels
   uint32_t qr_shifted;   // the current orthonormalization needs a third pass

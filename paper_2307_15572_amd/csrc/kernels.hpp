@@ -133,8 +133,13 @@ rsvd_status check_finite(int64_t rows, int64_t cols, const double* Y, int64_t ld
                          hipStream_t s);
 rsvd_status sumsq(int64_t m, int64_t n, const double* A, int64_t lda, double* partial,
                   DevState* st, hipStream_t s);
+// dev_est: err_est = kPosteriorFactor sqrt(st->est2) instead of the argument
 rsvd_status finalize(int64_t m, int64_t n, int64_t l, int want_residual, double err_est,
-                     int blocks, const DevState* st, rsvd_result* res, hipStream_t s);
+                     int blocks, const DevState* st, rsvd_result* res, hipStream_t s,
+                     bool dev_est = false);
+// UNCONVERGED / POSTERIOR_FAIL flags of a judged fixed-l run (after the rank rule)
+rsvd_status judge(int64_t l, int64_t mn, int q, int mode, double tau, const double* sv,
+                  DevState* st, hipStream_t s);
 // st->flags = (st->flags & ~clear) | set
 rsvd_status clear_flags(DevState* st, uint32_t clear, uint32_t set, hipStream_t s);
 // Column sums of squares of X (rows x cols <= 256, row-major): mode 0 sets
@@ -158,6 +163,14 @@ rsvd_status mlp_forward(const float* p, const float* X, int64_t B, float* Y, hip
 // number `step` (>= 1) applied to p, m, v; else the gradient into G.
 rsvd_status mlp_grad(float* p, const float* X, const float* T, int64_t B, bool adam, float* m,
                      float* v, int64_t step, float lr, float* G, float* loss, hipStream_t s);
+// sizing (k, p, q) per sample from the network (rsvd_mlp_predict)
+rsvd_status mlp_predict(const float* p, const float* stats, const float* X, int64_t B,
+                        const int64_t* n_cap, int64_t* kpq, hipStream_t s);
+// standardized training targets and their stats (rsvd_mlp_targets)
+rsvd_status mlp_targets(const int64_t* labels, int64_t B, float* stats, float* T, hipStream_t s);
+// label of one channel from a computed spectrum (rsvd_size_label)
+rsvd_status size_label(const double* sv, int64_t count, int64_t k, int64_t n, int64_t l_min,
+                       int64_t* kpq, hipStream_t s);
 // f_i = max(log10(sig_i / sig_0), -16) for i < 16 (sig: l decreasing values)
 rsvd_status pilot_features(int l, const double* sig, float* feat, hipStream_t s);
 

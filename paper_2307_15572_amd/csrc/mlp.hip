@@ -51,10 +51,21 @@ __global__ void __launch_bounds__(256) mlp_init_kernel(float* __restrict__ p, ui
   p[e] = v;
 }
 
-// Forward pass of up to 64 samples per workgroup.
+// Sizing rules applied to a prediction (documented with rsvd_mlp_predict).
+constexpr int kPGrid[8] = {8, 16, 32, 64, 128, 192, 256, 384};
+constexpr int kNGrid = 8;
+constexpr int kQMax = 4;
+constexpr double kRankMargin = 1.1;
+
+// Forward pass of up to 64 samples per workgroup. DECODE: instead of the
+// outputs y, write the sizing (k, p, q) decoded from raw = y sd + mean.
+template <bool DECODE>
 __global__ void __launch_bounds__(256) mlp_forward_kernel(const float* __restrict__ p,
                                                           const float* __restrict__ X, int64_t B,
-                                                          float* __restrict__ Y) {
+                                                          float* __restrict__ Y,
+                                                          const float* __restrict__ stats,
+                                                          const int64_t* __restrict__ n_cap,
+                                                          int64_t* __restrict__ kpq) {
   __shared__ float xs[64][kIn];
   __shared__ float h1[64][kLd];
   __shared__ float h2[64][kLd];
@@ -76,12 +87,115 @@ __global__ void __launch_bounds__(256) mlp_forward_kernel(const float* __restric
     h2[b][j] = z > 0.0f ? z : 0.0f;
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < nb * kOut; e += blockDim.x) {
-    const int b = e / kOut, o = e % kOut;
-    float y = p[kB3 + o];
-    for (int i = 0; i < kHid; i++) y += h2[b][i] * p[kW3 + o * kHid + i];
-    Y[(s0 + b) * kOut + o] = y;
+  if (!DECODE) {
+    for (int e = threadIdx.x; e < nb * kOut; e += blockDim.x) {
+      const int b = e / kOut, o = e % kOut;
+      float y = p[kB3 + o];
+      for (int i = 0; i < kHid; i++) y += h2[b][i] * p[kW3 + o * kHid + i];
+      Y[(s0 + b) * kOut + o] = y;
+    }
+    return;
   }
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    double raw[kOut];
+    for (int o = 0; o < kOut; o++) {
+      float y = p[kB3 + o];
+      for (int i = 0; i < kHid; i++) y += h2[b][i] * p[kW3 + o * kHid + i];
+      raw[o] = (double)y * (double)stats[kOut + o] + (double)stats[o];
+    }
+    const int64_t cap = n_cap[s0 + b] > 0 ? n_cap[s0 + b] : 1;
+    // k: margin, rounded up, within 1 .. cap (NaN or overflow -> cap)
+    const double kk = ceil(kRankMargin * exp10(raw[0]));
+    const int64_t k = kk < (double)cap ? (kk >= 1.0 ? (int64_t)kk : 1) : cap;
+    int pp = kPGrid[kNGrid - 1];
+    for (int g = 0; g < kNGrid; g++)
+      if ((double)kPGrid[g] >= raw[1]) { pp = kPGrid[g]; break; }
+    const double qq = ceil(raw[2] - 1e-9);
+    const int q = qq >= 0.0 ? (qq <= (double)kQMax ? (int)qq : kQMax) : (qq < 0.0 ? 0 : kQMax);
+    kpq[(s0 + b) * 3 + 0] = k;
+    kpq[(s0 + b) * 3 + 1] = pp;
+    kpq[(s0 + b) * 3 + 2] = q;
+  }
+}
+
+// Raw targets (log10 k, p, q) of B labels, their column means and population
+// standard deviations (two passes, each thread summing its samples in order,
+// then a fixed-order tree; FP64), and the standardized targets.
+__global__ void __launch_bounds__(256) mlp_targets_kernel(const int64_t* __restrict__ labels,
+                                                          int64_t B, float* __restrict__ stats,
+                                                          float* __restrict__ T) {
+  __shared__ double red[kOut][256];
+  __shared__ double mean[kOut], sd[kOut];
+  const int t = threadIdx.x;
+  auto raw = [&](int64_t b, int o) -> double {
+    const double v = (double)labels[b * 3 + o];
+    return o == 0 ? log10(v > 1.0 ? v : 1.0) : v;
+  };
+  for (int pass = 0; pass < 2; pass++) {
+    double acc[kOut] = {0.0, 0.0, 0.0};
+    for (int64_t b = t; b < B; b += blockDim.x)
+      for (int o = 0; o < kOut; o++) {
+        const double x = raw(b, o);
+        acc[o] += pass == 0 ? x : (x - mean[o]) * (x - mean[o]);
+      }
+    for (int o = 0; o < kOut; o++) red[o][t] = acc[o];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (t < w)
+        for (int o = 0; o < kOut; o++) red[o][t] += red[o][t + w];
+      __syncthreads();
+    }
+    if (t < kOut) {
+      if (pass == 0) {
+        mean[t] = red[t][0] / (double)B;
+      } else {
+        const double v = sqrt(red[t][0] / (double)B);
+        sd[t] = v > 0.0 ? v : 1.0;
+      }
+    }
+    __syncthreads();
+  }
+  if (t < kOut) {
+    stats[t] = (float)mean[t];
+    stats[kOut + t] = (float)sd[t];
+  }
+  for (int64_t e = t; e < B * kOut; e += blockDim.x) {
+    const int o = (int)(e % kOut);
+    T[e] = (float)((raw(e / kOut, o) - mean[o]) / sd[o]);
+  }
+}
+
+// Label of one channel from a computed spectrum (rsvd_size_label).
+__global__ void size_label_kernel(const double* __restrict__ s, int64_t count, int64_t k,
+                                  int64_t n, int64_t l_min, int64_t* __restrict__ kpq) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double best = 0.0;
+  int bp = -1, bq = -1;
+  const double nn = (double)n;
+  for (int q = 0; q <= kQMax; q++) {
+    for (int g = 0; g < kNGrid; g++) {
+      const int64_t pv = kPGrid[g];
+      if (k + pv < n) {
+        if (k + pv < l_min) continue;
+        // beyond the computed values the ratio only falls: the last one decides
+        const int64_t j = k + pv < count ? k + pv : count;
+        const double sk = s[k - 1];
+        const double r = sk > 0.0 ? s[j - 1] / sk : 0.0;
+        if (j <= k || !(pow(r, (double)(4 * q + 2)) <= 1e-8)) continue;
+      }
+      const double L = (double)(k + pv < n ? k + pv : n);
+      const double cost = (2.0 * q + 2.0) * nn * nn * L + 11.4 * (2.0 * q + 1.0) * nn * L * L +
+                          5000.0 * L * L * L;
+      if (bp < 0 || cost < best) {
+        best = cost;
+        bp = (int)pv;
+        bq = q;
+      }
+    }
+  }
+  kpq[0] = k;
+  kpq[1] = bp;
+  kpq[2] = bq;
 }
 
 struct AdamArgs {
@@ -263,8 +377,30 @@ rsvd_status mlp_init(float* p, uint64_t seed, hipStream_t s) {
 
 rsvd_status mlp_forward(const float* p, const float* X, int64_t B, float* Y, hipStream_t s) {
   if (B <= 0) return RSVD_OK;
-  hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)((B + 63) / 64)), dim3(256), 0, s, p, X, B,
-                     Y);
+  hipLaunchKernelGGL(mlp_forward_kernel<false>, dim3((unsigned)((B + 63) / 64)), dim3(256), 0, s,
+                     p, X, B, Y, (const float*)nullptr, (const int64_t*)nullptr, (int64_t*)nullptr);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status mlp_predict(const float* p, const float* stats, const float* X, int64_t B,
+                        const int64_t* n_cap, int64_t* kpq, hipStream_t s) {
+  if (B <= 0) return RSVD_OK;
+  hipLaunchKernelGGL(mlp_forward_kernel<true>, dim3((unsigned)((B + 63) / 64)), dim3(256), 0, s,
+                     p, X, B, (float*)nullptr, stats, n_cap, kpq);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status mlp_targets(const int64_t* labels, int64_t B, float* stats, float* T, hipStream_t s) {
+  hipLaunchKernelGGL(mlp_targets_kernel, dim3(1), dim3(256), 0, s, labels, B, stats, T);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status size_label(const double* sv, int64_t count, int64_t k, int64_t n, int64_t l_min,
+                       int64_t* kpq, hipStream_t s) {
+  hipLaunchKernelGGL(size_label_kernel, dim3(1), dim3(64), 0, s, sv, count, k, n, l_min, kpq);
   RSVD_LAUNCH_CHECK();
   return RSVD_OK;
 }

@@ -24,6 +24,9 @@ struct rsvd_plan_s {
   // symmetric form: the l x l core B = Q^T A Q (then Q_B of its QR)
   int form = 0;
   size_t off_Bs = 0;
+  // a-posteriori judge: r probe columns (P_r, A P_r deflated, Q^T A P_r)
+  int post_r = 0;
+  size_t off_Op = 0, off_Wp = 0, off_Cp = 0;
   // adaptive range finder: l above is l_max; blocks of blk columns
   bool adaptive = false;
   int64_t blk = 0;

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -210,7 +211,8 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* worksp
   if (p.symmetric && p.m != p.n) return RSVD_EINVAL;
   if (p.precision < RSVD_PREC_FP64 || p.precision > RSVD_PREC_MIXED_BF16_SPLIT) return RSVD_EINVAL;
   if (p.trailing_hp < 0) return RSVD_EINVAL;
-  if (p.reserved != 0) return RSVD_EINVAL;
+  if (p.posterior < 0 || p.posterior > 64) return RSVD_EINVAL;
+  if (p.posterior != 0 && p.adaptive) return RSVD_EINVAL;
   if (p.form != RSVD_FORM_SVD && p.form != RSVD_FORM_SYMMETRIC) return RSVD_EINVAL;
   if (p.form == RSVD_FORM_SYMMETRIC && !p.symmetric) return RSVD_EINVAL;
   const bool adaptive = p.adaptive != 0;
@@ -264,6 +266,7 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* worksp
   pl->adaptive = adaptive;
   pl->blk = blk;
   pl->form = p.form;
+  pl->post_r = p.posterior;
   const int64_t m = p.m, n = p.n, kc = pl->kc;
   const int64_t mx = m > n ? m : n;
   const size_t D = sizeof(double);
@@ -295,6 +298,19 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* worksp
     upd(m, blk, blk);
     upd(n, blk, blk);
     if (pl->part_doubles < (size_t)512 * 256) pl->part_doubles = (size_t)512 * 256;  // column norms
+  }
+  if (pl->post_r) {
+    const int64_t r = pl->post_r;
+    auto upd = [&](int64_t M, int64_t N, int64_t K) {
+      const size_t need = dgemm_shape(M, N, K).part_doubles;
+      if (need > pl->part_doubles) pl->part_doubles = need;
+    };
+    upd(m, r, n);  // A P_r
+    upd(l, r, m);  // Q^T W
+    upd(m, r, l);  // Q (Q^T W)
+    pl->off_Op = c.take((size_t)n * r * D);
+    pl->off_Wp = c.take((size_t)m * r * D);
+    pl->off_Cp = c.take((size_t)l * r * D);
   }
   if (pl->part_doubles < 2048) pl->part_doubles = 2048;
   pl->off_part = c.take(pl->part_doubles * D);
@@ -445,11 +461,12 @@ rsvd_status lift_and_finish(const rsvd_plan_s& pl, const Ws& w, const double* A,
     RSVD_TRY(resid_prep(m, n, kcl, kcp, o.U, o.ldu, sig, o.V, o.ldv, US, Vt, st, s));
     RSVD_TRY(resid(m, n, kcp, US, kcp, Vt, n, A, lda, w.at<double>(pl.off_rpart), st, s));
   }
+  if (pl.post_r) {
+    RSVD_TRY(judge(l, m < n ? m : n, p.power_iters, pl.mode, pl.param, sig, st, s));
+    return finalize(m, n, l, p.want_residual, err_est, blocks, st, res_dev, s, true);
+  }
   return finalize(m, n, l, p.want_residual, err_est, blocks, st, res_dev, s);
 }
-
-// Halko et al. (2011), Eq. (4.3): ||(I - QQ^T) A|| <= 10 sqrt(2/pi) max_j ||(I - QQ^T) A w_j||
-constexpr double kPosteriorFactor = 7.978845608028654;
 
 // The adaptive range finder (header: "Adaptive range finder").
 rsvd_status run_adaptive(const rsvd_plan_s& pl, const Ws& w, const double* A, int64_t lda,
@@ -698,6 +715,20 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
     RSVD_TRY(qr(n, Z, false));
     RSVD_TRY(stream_pass(false, Z, l, Y, m, n));
     RSVD_TRY(qr(m, Y, t + 1 == p.power_iters));
+  }
+  if (pl.post_r) {
+    // a-posteriori judge: r fresh columns of the same stream (l .. l + r - 1),
+    // W = (I - QQ^T) A P_r in FP64, est2 = max_j ||W_j||^2
+    const int64_t r = pl.post_r;
+    double* Op = w.at<double>(pl.off_Op);
+    double* Wp = w.at<double>(pl.off_Wp);
+    double* Cp = w.at<double>(pl.off_Cp);
+    PhaseScope ph(6, s);
+    RSVD_TRY(gaussian_omega(n, r, l, p.seed, p.channel, Op, r, s));
+    RSVD_TRY(dgemm(false, m, r, n, 1.0, A, lda, Op, r, 0.0, Wp, r, part, pl.part_doubles, s));
+    RSVD_TRY(dgemm(true, l, r, m, 1.0, Y, l, Wp, r, 0.0, Cp, r, part, pl.part_doubles, s));
+    RSVD_TRY(dgemm(false, m, r, l, -1.0, Y, l, Cp, r, 1.0, Wp, r, part, pl.part_doubles, s));
+    RSVD_TRY(colsumsq(m, (int)r, Wp, r, part, pl.part_doubles, 0, st, s));
   }
   if (pl.form == RSVD_FORM_SYMMETRIC) {
     // symmetric form: C = A Q (the projection's stream of A), B = Q^T C
@@ -1073,6 +1104,74 @@ rsvd_status rsvd_mlp_train_step(float* params, float* adam_m, float* adam_v, int
     return RSVD_EINVAL;
   return mlp_grad(params, X, T, B, true, adam_m, adam_v, step, lr, nullptr, loss,
                   (hipStream_t)stream);
+}
+
+rsvd_status rsvd_mlp_targets(const int64_t* labels, int64_t B, float* stats, float* T,
+                             void* stream) {
+  if (!labels || !stats || !T || B < 1) return RSVD_EINVAL;
+  return mlp_targets(labels, B, stats, T, (hipStream_t)stream);
+}
+
+rsvd_status rsvd_mlp_predict(const float* params, const float* stats, const float* X, int64_t B,
+                             const int64_t* n_cap, int64_t* kpq, void* stream) {
+  if (B < 0 || (B > 0 && (!params || !stats || !X || !n_cap || !kpq))) return RSVD_EINVAL;
+  return mlp_predict(params, stats, X, B, n_cap, kpq, (hipStream_t)stream);
+}
+
+rsvd_status rsvd_size_label(const double* sv, int64_t count, int64_t k, int64_t n, int64_t l_min,
+                            int64_t* kpq, void* stream) {
+  if (!sv || !kpq || k < 1 || count < k || n < k || l_min < 0) return RSVD_EINVAL;
+  return size_label(sv, count, k, n, l_min, kpq, (hipStream_t)stream);
+}
+
+namespace {
+constexpr char kMlpTag[8] = {'R', 'S', 'V', 'D', 'M', 'L', 'P', '1'};
+constexpr uint32_t kMlpStats = 6;
+}  // namespace
+
+rsvd_status rsvd_mlp_save(const char* path, const float* params, const float* stats,
+                          void* stream) {
+  if (!path || !params || !stats) return RSVD_EINVAL;
+  std::vector<float> buf(RSVD_MLP_PARAMS + kMlpStats);
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(buf.data(), params, RSVD_MLP_PARAMS * sizeof(float), hipMemcpyDeviceToHost,
+                     s) != hipSuccess ||
+      hipMemcpyAsync(buf.data() + RSVD_MLP_PARAMS, stats, kMlpStats * sizeof(float),
+                     hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return RSVD_EHIP;
+  FILE* f = std::fopen(path, "wb");
+  if (!f) return RSVD_EINVAL;
+  const uint32_t counts[2] = {RSVD_MLP_PARAMS, kMlpStats};
+  const bool ok = std::fwrite(kMlpTag, 1, 8, f) == 8 && std::fwrite(counts, 4, 2, f) == 2 &&
+                  std::fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+  const bool closed = std::fclose(f) == 0;
+  return ok && closed ? RSVD_OK : RSVD_EINVAL;
+}
+
+rsvd_status rsvd_mlp_load(const char* path, float* params, float* stats, void* stream) {
+  if (!path || !params || !stats) return RSVD_EINVAL;
+  FILE* f = std::fopen(path, "rb");
+  if (!f) return RSVD_EINVAL;
+  char tag[8];
+  uint32_t counts[2];
+  std::vector<float> buf(RSVD_MLP_PARAMS + kMlpStats);
+  bool ok = std::fread(tag, 1, 8, f) == 8 && std::memcmp(tag, kMlpTag, 8) == 0 &&
+            std::fread(counts, 4, 2, f) == 2 && counts[0] == RSVD_MLP_PARAMS &&
+            counts[1] == kMlpStats &&
+            std::fread(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+  char extra;
+  ok = ok && std::fread(&extra, 1, 1, f) == 0;  // nothing after the stats
+  std::fclose(f);
+  if (!ok) return RSVD_EINVAL;
+  hipStream_t s = (hipStream_t)stream;
+  if (hipMemcpyAsync(params, buf.data(), RSVD_MLP_PARAMS * sizeof(float), hipMemcpyHostToDevice,
+                     s) != hipSuccess ||
+      hipMemcpyAsync(stats, buf.data() + RSVD_MLP_PARAMS, kMlpStats * sizeof(float),
+                     hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return RSVD_EHIP;
+  return RSVD_OK;
 }
 
 namespace {

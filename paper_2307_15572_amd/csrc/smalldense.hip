@@ -1590,8 +1590,29 @@ __global__ void __launch_bounds__(256) sum_partials_kernel(int64_t cnt, const do
   if (threadIdx.x == 0) *out = red[0] + red[1] + red[2] + red[3];
 }
 
+// The a-posteriori judge of a fixed-l run (posterior > 0), after the rank
+// rule: UNCONVERGED when (s_l / s_k)^(4q + 2) > 1e-8 for the kept rank k
+// (threshold rules), POSTERIOR_FAIL when the posterior estimate exceeds
+// tau s_1 (relative threshold). An exact decomposition (l = min(m, n)) passes.
+__global__ void judge_kernel(int64_t l, int64_t mn, int q, int mode, double tau,
+                             const double* __restrict__ s, DevState* st) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  if (l >= mn || (mode != RSVD_RANK_REL_THRESHOLD && mode != RSVD_RANK_FROB_TAIL)) return;
+  const int64_t k = st->rank;
+  uint32_t f = 0;
+  if (k >= 1 && k < l && s[k - 1] > 0.0) {
+    const double r = s[l - 1] / s[k - 1];
+    if (!(pow(r, (double)(4 * q + 2)) <= kConvergedRatio)) f |= RSVD_FLAG_UNCONVERGED;
+  }
+  if (mode == RSVD_RANK_REL_THRESHOLD) {
+    const double est = kPosteriorFactor * sqrt(st->est2);
+    if (!(est <= tau * s[0])) f |= RSVD_FLAG_POSTERIOR_FAIL;
+  }
+  st->flags |= f;
+}
+
 __global__ void finalize_kernel(int64_t m, int64_t n, int64_t l, int want_residual,
-                                double err_est, int blocks, const DevState* st,
+                                double err_est, int blocks, int dev_est, const DevState* st,
                                 rsvd_result* res) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const int64_t k = st->rank;
@@ -1605,7 +1626,7 @@ __global__ void finalize_kernel(int64_t m, int64_t n, int64_t l, int want_residu
   res->fro2 = st->fro2;
   res->sweeps = st->sweeps;
   res->flags = st->flags;
-  res->err_est = err_est;
+  res->err_est = dev_est ? kPosteriorFactor * sqrt(st->est2) : err_est;
   res->blocks = blocks;
   res->reserved = 0;
 }
@@ -1958,9 +1979,17 @@ rsvd_status sum_partials_into(int64_t cnt, const double* p, double* out, hipStre
 }
 
 rsvd_status finalize(int64_t m, int64_t n, int64_t l, int want_residual, double err_est,
-                     int blocks, const DevState* st, rsvd_result* res, hipStream_t s) {
+                     int blocks, const DevState* st, rsvd_result* res, hipStream_t s,
+                     bool dev_est) {
   hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(64), 0, s, m, n, l, want_residual, err_est,
-                     blocks, st, res);
+                     blocks, (int)dev_est, st, res);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status judge(int64_t l, int64_t mn, int q, int mode, double tau, const double* sv,
+                  DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(judge_kernel, dim3(1), dim3(64), 0, s, l, mn, q, mode, tau, sv, st);
   RSVD_LAUNCH_CHECK();
   return RSVD_OK;
 }

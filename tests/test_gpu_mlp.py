@@ -146,46 +146,149 @@ def test_pilot_features_match_oracle(n, d):
     assert np.abs(f - ref).max() <= 1e-3
 
 
+def test_targets_match_oracle():
+    import paper_2307_15572_amd as rs
+    announce("mlp targets (standardization)")
+    rng = np.random.default_rng(31)
+    labels = np.stack([rng.integers(5, 3000, 700), rng.choice([8, 16, 32, 64, 128, 192], 700),
+                       rng.integers(0, 5, 700)], axis=1)
+    net = rs.Mlp(seed=1)
+    T = net.targets(labels).cpu().numpy().astype(np.float64)
+    Tr, mean, sd = omlp.targets(labels)
+    st = net.stats.cpu().numpy().astype(np.float64)
+    assert np.allclose(st[:3], mean, rtol=1e-6) and np.allclose(st[3:], sd, rtol=1e-6)
+    assert np.abs(T - Tr).max() <= 1e-5
+
+
+def test_predict_matches_oracle_decode():
+    # the decode step on both sides takes the device's FP32 network outputs
+    import paper_2307_15572_amd as rs
+    announce("mlp predict (forward + sizing rules)")
+    rng = np.random.default_rng(32)
+    net = rs.Mlp(seed=5)
+    net.targets(np.stack([rng.integers(20, 1500, 300), rng.choice([8, 32, 128, 192], 300),
+                          rng.integers(0, 5, 300)], axis=1))
+    X = rng.uniform(-6.0, 0.0, size=(300, 16))
+    n_cap = rng.integers(100, 5000, 300)
+    got = net.predict(_f32(X), n_cap)
+    y = net.forward(_f32(X)).cpu().numpy().astype(np.float64)
+    st = net.stats.cpu().numpy().astype(np.float64)
+    want = [omlp.decode(y[b], st[:3], st[3:], int(n_cap[b])) for b in range(300)]
+    assert got == want
+
+
+def test_size_label_matches_oracle():
+    import paper_2307_15572_amd as rs
+    announce("size label from computed spectra")
+    rng = np.random.default_rng(33)
+    for t in range(40):
+        n = int(rng.integers(300, 6000))
+        d = float(rng.uniform(5.0, 90.0))
+        count = int(rng.integers(50, 600))
+        s = np.exp(-np.arange(count) / d - 0.01 * rng.random(count).cumsum())
+        k = int(rng.integers(1, count))
+        l_min = int(rng.integers(0, count + 100))
+        got = rs.size_label(to_dev(s), k, n, l_min)
+        assert got == omlp.size_label(s, k, n, l_min), (t, n, d, count, k, l_min)
+
+
+def test_save_load_roundtrip(tmp_path):
+    import paper_2307_15572_amd as rs
+    announce("mlp save / load")
+    net = rs.Mlp(seed=8)
+    net.targets(np.array([[10, 8, 0], [300, 64, 2], [90, 16, 1]]))
+    path = str(tmp_path / "net.bin")
+    net.save(path)
+    other = rs.Mlp(seed=9)
+    other.load(path)
+    assert bool((other.params == net.params).all()) and bool((other.stats == net.stats).all())
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(open(path, "rb").read()[:-4])
+    with pytest.raises(rs.RsvdError):
+        other.load(str(bad))
+
+
+def test_posterior_judge_matches_oracle():
+    import paper_2307_15572_amd as rs
+    from oracle.adaptive import posterior_judge
+    from oracle.method import rsvd as oracle_rsvd
+    announce("a-posteriori judge of fixed-l threshold runs")
+    m, n = 1000, 800
+    A = synth.general(m, n, synth.spectrum_exp(n, 30.0), tag=134)
+    for k, p, q, tau in ((60, 20, 1, 1e-2), (230, 60, 2, 1e-3), (100, 8, 0, 1e-6)):
+        ref = oracle_rsvd(A, k, p, q, seed=4, rank_mode="rel_threshold", rank_param=tau)
+        est, flags = posterior_judge(A, ref.Q, ref.s_all, ref.rank, q, tau, 16, seed=4)
+        out = rs.run(to_dev(A), k, p, q, seed=4, rank_mode="rel_threshold", rank_param=tau,
+                     posterior=16)
+        assert out.rank == ref.rank
+        assert abs(out.err_est - est) <= 1e-8 * est + 1e-13, (out.err_est, est)
+        judged = rs.FLAG_POSTERIOR_FAIL | rs.FLAG_UNCONVERGED
+        assert out.flags & judged == flags, (k, p, q, out.flags, flags)
+
+
+def _timed(fn):
+    import time
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
 def test_learned_sizing_beats_adaptive_only():
-    # train on 200 channels, evaluate on 60: every evaluated channel must end
-    # with its exact threshold rank and converged kept values, using fewer
-    # streams of A than the adaptive finder alone
+    # train on channels labelled by the method itself (the adaptive FP64
+    # finder's rank and spectrum), evaluate on others: every evaluated channel
+    # ends with its exact threshold rank and accurate kept values, with fewer
+    # streams of A and less wall time than the adaptive finder alone
     import paper_2307_15572_amd as rs
     from paper_2307_15572_amd import learned
-    announce("learned sizing: 200 train / 60 eval channels, n ~ logU[200, 1200]")
+    announce("learned sizing: 240 train channels (n ~ logU[1500, 4000]) / 60 eval (n ~ logU[600, 2500])")
     tau, seed = 1e-6, 5
-    dims, dec = synth.channel_dims(260, 200, 1200, tag=77)
+    dims, dec = synth.channel_dims(300, 600, 2500, tag=77)
+    # training channels large enough that no label's l = k + p reaches n (the
+    # features see the spectrum, not the size); evaluation keeps small ones
+    tdims, _ = synth.channel_dims(300, 1500, 4000, tag=78)
+    dims[:240] = tdims[:240]
     feats, labels, evals = [], [], []
     work = None
     for c, (n, d) in enumerate(zip(dims, dec)):
         n, d = int(n), float(d)
         A, _ = synth.channel_device_rng(c, n, d, tag=77)
+        if c >= 240:
+            evals.append((c, n, d, A))
+            continue
+        lab, _ = learned.label_channel(A, tau, seed, c, symmetric=True)
+        if lab is None:
+            continue
         f, work = rs.pilot_features(A, seed=seed, channel=c, work=work)
         feats.append(f.cpu().numpy())
-        labels.append(synth.kpq_label(n, d, tau, cap=False))
-        if c >= 200:
-            evals.append((c, n, d, A))
-        else:
-            del A
-    net, mu, sd, loss = learned.train_predictor(np.array(feats[:200]), labels[:200], epochs=300)
-    # the targets are grid choices of a noisy spectrum estimate: ~0.2-0.3 is
-    # what this set supports (FP64 oracle training reaches 0.28 after 300 epochs)
-    assert loss < 0.45
+        labels.append(lab)
+        del A
+    print(f"[learned] {len(labels)} of 240 training channels labelled")
+    assert len(labels) >= 120
+    net, loss = learned.train_predictor(np.array(feats), labels, epochs=300)
+    assert loss < 0.6
     passes_l = passes_a = fell = 0
+    t_l = t_a = 0.0
     for c, n, d, A in evals:
-        k_true = learned.threshold_rank(n, d, tau)
+        k_true = min(n, 1 + int(np.floor(d * np.log(1.0 / tau))))
         sig = synth.spectrum_exp(n, d)
-        out, _ = learned.decompose(A, net, mu, sd, tau, seed=seed, channel=c, symmetric=True)
+        (out, work), dt = _timed(lambda: learned.decompose(A, net, tau, seed=seed, channel=c,
+                                                            symmetric=True, pilot_work=work))
+        t_l += dt
+        if out.fell_back:
+            print(f"[learned] channel {c} n={n} d={d:.1f} predicted {out.predicted}: {out.reason}")
         assert out.rank == k_true, (c, n, d, out.predicted, out.reason)
         s = out.S.cpu().numpy()
         assert np.max(np.abs(s - sig[: out.rank]) / sig[: out.rank]) <= 1e-6
         passes_l += out.passes
         fell += int(out.fell_back)
-        ad = rs.run(A, 0, 16, 1, seed=seed, channel=c, symmetric=True, rank_mode="rel_threshold",
-                    rank_param=tau, adaptive=True, block=64, want_u=False, want_v=False,
-                    want_residual=False)
+        ad, dt = _timed(lambda: learned.run_adaptive(A, tau, seed, c, symmetric=True))
+        t_a += dt
         assert ad.rank == k_true
         passes_a += learned.adaptive_passes(ad.blocks, 1, ad.l, n)
-    print(f"[learned] passes {passes_l} vs adaptive {passes_a}, fallbacks {fell}/{len(evals)}")
+    print(f"[learned] passes {passes_l} vs adaptive {passes_a}, time {t_l:.3f} s vs {t_a:.3f} s, "
+          f"fallbacks {fell}/{len(evals)}")
     assert passes_l < passes_a
-    assert fell <= len(evals) // 2
+    assert fell <= len(evals) // 3

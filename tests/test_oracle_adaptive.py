@@ -137,3 +137,29 @@ def test_zero_matrix():
     assert r.l == 16
     assert r.rank == 1
     assert r.s[0] == 0.0
+
+
+def test_fixed_run_posterior_judge_bounds_the_basis_error():
+    # est = 10 sqrt(2/pi) max_j ||(I - QQ^T) A p_j|| over r = 10 fresh columns
+    # bounds ||(I - QQ^T) A||_2 (failure probability 1e-10) and stays within
+    # a modest factor of it
+    from oracle.adaptive import FLAG_POSTERIOR_FAIL, FLAG_UNCONVERGED, posterior_judge
+    from oracle.method import rsvd
+    m, n = 300, 200
+    sig = synth.spectrum_exp(n, 12.0)
+    A = synth.general(m, n, sig, tag=131)
+    for seed in range(20):
+        r = rsvd(A, 30, 10, 1, seed=seed)
+        est, flags = posterior_judge(A, r.Q, r.s_all, r.rank, 1, 1e-6, 10, seed=seed)
+        true = np.linalg.norm(A - r.Q @ (r.Q.T @ A), 2)
+        assert true <= est <= 200 * true
+    # flags against their definitions: threshold rank of exp(-i/12) at 1e-3
+    # is 83 (> l - p = 30 + 10 - 10 -> capped at 30; s_40/s_30 = e^(-10/12):
+    # (0.43)^6 = 6e-3 > 1e-8 -> UNCONVERGED; est ~ s_41 > 1e-3 s_1 -> FAIL)
+    r = rsvd(A, 30, 10, 1, seed=1, rank_mode="rel_threshold", rank_param=1e-3)
+    est, flags = posterior_judge(A, r.Q, r.s_all, r.rank, 1, 1e-3, 10, seed=1)
+    assert flags == FLAG_UNCONVERGED | FLAG_POSTERIOR_FAIL
+    # a wide, converged basis passes: l = 150, q = 2, k = 83 (s_150/s_83 = e^(-67/12))
+    r = rsvd(A, 100, 50, 2, seed=1, rank_mode="rel_threshold", rank_param=1e-3)
+    est, flags = posterior_judge(A, r.Q, r.s_all, r.rank, 2, 1e-3, 10, seed=1)
+    assert r.rank == 1 + int(12.0 * math.log(1e3)) and flags == 0

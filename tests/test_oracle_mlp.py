@@ -132,3 +132,49 @@ def test_forward_hand_computed_two_samples():
     # orientation of each weight matrix, the biases and where ReLU applies
     y, _ = mlp.forward(_hand_params(), HAND_X)
     assert np.allclose(y, HAND_Y, rtol=0, atol=1e-14)
+
+
+# ---- sizing rules: standardization, decoding, labels ------------------------
+
+def test_targets_standardize_by_hand():
+    labels = [(10, 16, 1), (100, 32, 1), (1000, 64, 1)]
+    T, mean, sd = mlp.targets(labels)
+    # log10 k = 1, 2, 3: mean 2, population sd sqrt(2/3)
+    assert mean[0] == pytest.approx(2.0) and sd[0] == pytest.approx(math.sqrt(2 / 3))
+    assert np.allclose(T[:, 0], np.array([-1.0, 0.0, 1.0]) / math.sqrt(2 / 3))
+    assert mean[1] == pytest.approx(112 / 3)
+    # q constant: zero deviation counts as 1, targets 0
+    assert sd[2] == 1.0 and np.all(T[:, 2] == 0.0)
+
+
+def test_decode_by_hand():
+    # raw = (2.5, 20, 1.2): k = ceil(1.1 * 316.23) = 348, p -> 32, q -> 2
+    assert mlp.decode([0, 0, 0], [2.5, 20, 1.2], [1, 1, 1], 10**6) == (348, 32, 2)
+    # beyond the grid, negative q, capped k
+    assert mlp.decode([0, 0, 0], [2.5, 200, -0.5], [1, 1, 1], 100) == (100, 256, 0)
+    assert mlp.decode([0, 0, 0], [2.5, 500, -0.5], [1, 1, 1], 100) == (100, 384, 0)
+    # de-standardization: raw = (1 + 1, 20 - 12, 1 + 6) = (2, 8, 7): p exactly on the grid
+    k, p, q = mlp.decode([1, -1, 2], [1, 20, 1], [1, 12, 3], 10**6)
+    assert k in (110, 111) and p == 8 and q == 4
+
+
+def test_size_label_by_hand():
+    # s_i = 10^(-i/9): (s_{k+p-1}/s_{k-1})^(4q+2) = 10^(-p (4q+2) / 9) <= 1e-8
+    # needs p (4q+2) >= 72: q=0 p=64 (l=114), q=1 p=16 (l=66), q=2 p=8 (l=58).
+    # n = 10000: costs (2q+2) n^2 l + 11.4 (2q+1) n l^2 + 5000 l^3 are
+    # 3.2e10, 2.93e10, 3.6e10 -> q = 1, p = 16
+    s = 10.0 ** (-np.arange(400) / 9.0)
+    assert mlp.size_label(s, 50, 10000) == (50, 16, 1)
+    # n = 60: l = 66 would be exact (l = n = 60, cost 1.08e9) but q = 2, p = 8
+    # (l = 58, 9.88e8) is cheaper through the small SVD's l^3
+    assert mlp.size_label(s, 50, 60) == (50, 8, 2)
+    # a spectrum reaching only k + 10: converged at its last value (index 59)
+    # for q = 2 (10 * 10 / 9 >= 8), so every p >= 8 qualifies for q >= 2, and
+    # q = 1 with p = 16 cannot be checked beyond index 59 (9 * 6 / 9 < 8):
+    # the cheapest is q = 2, p = 8
+    assert mlp.size_label(s[:60], 50, 10000) == (50, 8, 2)
+    # coverage: the labelling run needed l >= 140 -> p >= 90 -> 128 (q = 0
+    # converges: 128 * 2 / 9 >= 8) beats p = 128 with q >= 1
+    assert mlp.size_label(s, 50, 10000, l_min=140) == (50, 128, 0)
+    # nothing converges and nothing reaches n
+    assert mlp.size_label(np.ones(100), 50, 10000) == (50, -1, -1)
