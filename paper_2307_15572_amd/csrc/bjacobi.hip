@@ -22,6 +22,11 @@ namespace rsvd {
 namespace {
 
 constexpr double kU = 1.1102230246251565e-16;
+// waves per workgroup: all of them load and multiply in the Gram and the
+// apply; the first four (256 threads, one per 2 x 2 block of the 32 x 32
+// rotation problem) run the inner rounds while the others wait at its barriers
+constexpr int kJacWaves = 8;
+constexpr int kJacThreads = 64 * kJacWaves;
 
 // x mod m for 0 <= x < 2 m
 __device__ __forceinline__ int mod_once(int x, int m) { return x >= m ? x - m : x; }
@@ -77,14 +82,14 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
 
   // ---- Gram of the 32 rows (tiles 00, 01, 11), K split over the 4 waves;
   // GB column tiles of a wave in flight together
-  constexpr int GB = 5;
+  constexpr int GB = 3;
   d4 h00 = {0, 0, 0, 0}, h01 = {0, 0, 0, 0}, h11 = {0, 0, 0, 0};
-  for (int ct0 = wave; ct0 < nct; ct0 += 4 * GB) {
+  for (int ct0 = wave; ct0 < nct; ct0 += kJacWaves * GB) {
     double xi[GB][4], xj[GB][4];
 #pragma unroll
     for (int u = 0; u < GB; u++) {
-      const int c0 = 16 * (ct0 + 4 * u) + 4 * g;
-      if (ct0 + 4 * u < nct) {
+      const int c0 = 16 * (ct0 + kJacWaves * u) + 4 * g;
+      if (ct0 + kJacWaves * u < nct) {
 #pragma unroll
         for (int s = 0; s < 4; s++) {
           xi[u][s] = rI[(int64_t)r * Lp + c0 + s];
@@ -94,7 +99,7 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
     }
 #pragma unroll
     for (int u = 0; u < GB; u++) {
-      if (ct0 + 4 * u < nct) {
+      if (ct0 + kJacWaves * u < nct) {
 #pragma unroll
         for (int s = 0; s < 4; s++) {
           h00 = mfma_f64_16x16x4(xi[u][s], xi[u][s], h00);
@@ -115,7 +120,7 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
   __syncthreads();
   for (int e = threadIdx.x; e < 256; e += blockDim.x) {
     double v0 = 0, v1 = 0, v2 = 0;
-    for (int w = 0; w < 4; w++) {
+    for (int w = 0; w < kJacWaves; w++) {
       v0 += red[(w * 3 + 0) * 256 + e];
       v1 += red[(w * 3 + 1) * 256 + e];
       v2 += red[(w * 3 + 2) * 256 + e];
@@ -159,9 +164,14 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
   __syncthreads();
   {
     const int k = threadIdx.x >> 4, mm = threadIdx.x & 15;
+    const bool rounds = threadIdx.x < 256;
     int cur = 0;
     for (int isw = 0; isw < a.inner_sweeps; isw++) {
       for (int round = 0; round < 31; round++) {
+        if (!rounds) {
+          __syncthreads();
+          continue;
+        }
         double (*Hc)[33] = Hb[cur];
         double (*Hn)[33] = Hb[cur ^ 1];
         int pk, qk, pm, qm;
@@ -215,8 +225,8 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
     double* bI = base + (int64_t)16 * I * Lp;
     double* bJ = base + (int64_t)16 * J * Lp;
     // AB column tiles per iteration (their loads in flight together)
-    constexpr int AB = 5;
-    for (int ct = wave; ct < nct; ct += 4 * AB) {
+    constexpr int AB = 3;
+    for (int ct = wave; ct < nct; ct += kJacWaves * AB) {
       double b[AB][8];
 #pragma unroll
       for (int u = 0; u < AB; u++)
@@ -224,12 +234,14 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
         for (int s = 0; s < 8; s++) {
           const int row = 4 * s + g;  // 0..31
           const double* src = row < 16 ? bI : bJ;
-          b[u][s] = ct + 4 * u < nct ? src[(int64_t)(row & 15) * Lp + 16 * (ct + 4 * u) + r] : 0.0;
+          b[u][s] = ct + kJacWaves * u < nct
+                        ? src[(int64_t)(row & 15) * Lp + 16 * (ct + kJacWaves * u) + r]
+                        : 0.0;
         }
 #pragma unroll
       for (int u = 0; u < AB; u++) {
-        if (ct + 4 * u >= nct) break;
-        const int c = 16 * (ct + 4 * u) + r;
+        if (ct + kJacWaves * u >= nct) break;
+        const int c = 16 * (ct + kJacWaves * u) + r;
         d4 o0 = {0, 0, 0, 0}, o1 = {0, 0, 0, 0};
 #pragma unroll
         for (int s = 0; s < 8; s++) {
@@ -248,11 +260,11 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
   return true;
 }
 
-__global__ void __launch_bounds__(256) bjacobi_kernel(JacArgs a) {
+__global__ void __launch_bounds__(kJacThreads) bjacobi_kernel(JacArgs a) {
   __shared__ int s_bar_ok;
   __shared__ double Hb[2][32][33];
   __shared__ double Vb[2][32][33];
-  __shared__ double red[4 * 3 * 256];
+  __shared__ double red[kJacWaves * 3 * 256];
   __shared__ double dsq[32];
   __shared__ int s_any;
   const int nb = a.Lp / 16;  // even
@@ -340,7 +352,8 @@ rsvd_status block_jacobi(int64_t l, const double* R, double* M, double* P, int m
   int ncu = 0, per_cu = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return RSVD_EHIP;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)bjacobi_kernel, 256, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)bjacobi_kernel,
+                                                   kJacThreads, 0) !=
       hipSuccess)
     return RSVD_EHIP;
   int grid = (Lp / 16) / 2;
@@ -349,7 +362,7 @@ rsvd_status block_jacobi(int64_t l, const double* R, double* M, double* P, int m
   int cap = ncu * (per_cu > 0 ? per_cu : 1) / (share > 1 ? 2 * share : 1);
   if (cap < 1) cap = 1;
   if (grid > cap) grid = cap;
-  hipLaunchKernelGGL(bjacobi_kernel, dim3(grid), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(bjacobi_kernel, dim3(grid), dim3(kJacThreads), 0, s, a);
   RSVD_LAUNCH_CHECK();
   return RSVD_OK;
 }

@@ -85,8 +85,10 @@ rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, double* scra
                      bool full_inverse = true);
 // Q = Y R^{-1} (rows x l) by block forward substitution with R upper
 // triangular and Xd holding the inverses of R's 16 x 16 diagonal tiles (as
-// chol_inv writes them, with or without the full inverse); skipped when pred
-// is non-null and *pred == 0. Supported for l <= 320 (trsm_supported).
+// chol_inv writes them, with or without the full inverse), both with leading
+// dimension ldr; skipped when pred is non-null and *pred == 0. Y and Q may be
+// the same panel. Supported for l <= 608 (trsm_supported); wider factors are
+// solved by column blocks (orth).
 bool trsm_supported(int64_t l);
 // G = Y^T Y (l x l, both triangles) of a rows x l panel by slabs of rows on
 // the matrix cores (upper tiles, per-slab partials in part, summed in a fixed
@@ -95,8 +97,8 @@ bool trsm_supported(int64_t l);
 rsvd_status gram(int64_t rows, int64_t l, const double* Y, int64_t ldy, double* G, double* part,
                  size_t part_doubles, const uint32_t* pred, hipStream_t s);
 rsvd_status trsm_upper(int64_t rows, int64_t l, const double* Y, int64_t ldy, const double* R,
-                       const double* Xd, double* Q, int64_t ldq, const uint32_t* pred,
-                       hipStream_t s);
+                       int64_t ldr, const double* Xd, double* Q, int64_t ldq,
+                       const uint32_t* pred, hipStream_t s);
 // Householder QR of the rows x l panel Yorig into Y (= Q) and R, run only
 // when st->qr_householder is set (tau: 2 l doubles of scratch; scratch: l x l
 // doubles for the grid variant of large panels, may be null; share: runs on
@@ -116,9 +118,11 @@ int64_t jacobi_padded(int64_t l);
 // runs on concurrent streams, whose cooperative grids must fit together).
 rsvd_status block_jacobi(int64_t l, const double* R, double* M, double* P, int max_sweeps,
                          int inner_sweeps, DevState* st, hipStream_t s, int share = 1);
-// From converged M, P: s (decreasing), Us (l x kc), W (l x kc).
+// From converged M, P: s (decreasing), Us (l x kc), W (l x kc); scratch:
+// 2 l doubles.
 rsvd_status svd_finish(int64_t l, int64_t kc, const double* M, const double* P, int64_t ld,
-                       double* s, double* Us, double* W, DevState* st, hipStream_t st_);
+                       double* s, double* Us, double* W, double* scratch, DevState* st,
+                       hipStream_t st_);
 rsvd_status select_rank(int64_t l, int64_t p, int64_t kc, int mode, double param,
                         const double* s, DevState* st, hipStream_t hs);
 // Sign rule on the first kc columns of U (m x kc) and V (n x kc, may be null);

@@ -153,14 +153,32 @@ rsvd_status orth(const rsvd_plan_s& pl, const Ws& w, int64_t rows, int64_t l, do
   RSVD_TRY(clear_shift(st, s));
   RSVD_TRY(copy_panel(rows, l, Y, l, Yorig, l, 0, st, s));
   // Q = Y R^{-1}: block forward substitution with the diagonal tiles'
-  // inverses (the factorization then skips the full inverse), or a product
-  // with the full inverse beyond the substitution kernel's width
-  const bool tri = trsm_supported(l);
+  // inverses (the factorization skips the full inverse). Beyond the
+  // substitution kernel's width, by column blocks B of at most that width:
+  //   Q_B = (Y_B - Q_{<B} R_{<B,B}) R_BB^{-1}
+  // (copy, one product with the blocks already solved, substitution in place)
+  const bool tri = true;
   auto apply = [&](const double* src, const double* Rf, const double* Ri, double* dst,
                    const uint32_t* pred) -> rsvd_status {
-    if (tri) return trsm_upper(rows, l, src, l, Rf, Ri, dst, l, pred, s);
-    return dgemm(false, rows, l, l, 1.0, src, l, Ri, l, 0.0, dst, l, part, pl.part_doubles, s, 64,
-                 pred);
+    if (trsm_supported(l)) return trsm_upper(rows, l, src, l, Rf, l, Ri, dst, l, pred, s);
+    int64_t wb = 16;
+    while (trsm_supported(wb + 16)) wb += 16;  // widest supported multiple of 16
+    const int64_t nblk = (l + wb - 1) / wb;
+    wb = ((l + nblk - 1) / nblk + 15) / 16 * 16;  // balanced blocks
+    for (int64_t cb = 0; cb < l; cb += wb) {
+      const int64_t w = l - cb < wb ? l - cb : wb;
+      if (cb == 0) {
+        RSVD_TRY(trsm_upper(rows, w, src, l, Rf, l, Ri, dst, l, pred, s));
+        continue;
+      }
+      // pred is either absent or the shift word (copy_panel's condition 1)
+      RSVD_TRY(copy_panel(rows, w, src + cb, l, dst + cb, l, pred ? 1 : 0, st, s));
+      RSVD_TRY(dgemm(false, rows, w, cb, -1.0, dst, l, Rf + cb, l, 1.0, dst + cb, l, part,
+                     pl.part_doubles, s, 64, pred));
+      RSVD_TRY(trsm_upper(rows, w, dst + cb, l, Rf + cb * l + cb, l, Ri + cb * l + cb, dst + cb, l,
+                          pred, s));
+    }
+    return RSVD_OK;
   };
   // pass 0
   RSVD_TRY(gram(rows, l, Y, l, G, part, pl.part_doubles, nullptr, s));
@@ -171,12 +189,18 @@ rsvd_status orth(const rsvd_plan_s& pl, const Ws& w, int64_t rows, int64_t l, do
   RSVD_TRY(chol_inv(l, G, R2, R2i, Rtmp, rows, 1, full ? 0 : 1, st, s, pl.coop_share, !tri));
   RSVD_TRY(apply(T, R2, R2i, Y, p1));
   if (!full) RSVD_TRY(copy_panel(rows, l, T, l, Y, l, 2, st, s));  // unshifted: Q = T
-  // pass 2 (device-predicated on the shift)
-  RSVD_TRY(gram(rows, l, Y, l, G, part, pl.part_doubles, shifted, s));
-  RSVD_TRY(chol_inv(l, G, R3, R3i, Rtmp, rows, 2, 1, st, s, pl.coop_share, !tri));
-  RSVD_TRY(apply(Y, R3, R3i, T, shifted));
-  RSVD_TRY(copy_panel(rows, l, T, l, Y, l, 1, st, s));
-  if (Rout) {
+  // pass 2 (device-predicated on the shift), for the bases that must be
+  // orthonormal to working accuracy; an intermediate basis after a shifted
+  // pass and one unshifted pass is orthonormal to about u kappa(T)^2 with
+  // kappa(T) <= 1 / sqrt(shift / ||G||) (~1e4 here), which carries its span
+  // to the next product unchanged
+  if (full) {
+    RSVD_TRY(gram(rows, l, Y, l, G, part, pl.part_doubles, shifted, s));
+    RSVD_TRY(chol_inv(l, G, R3, R3i, Rtmp, rows, 2, 1, st, s, pl.coop_share, !tri));
+    RSVD_TRY(apply(Y, R3, R3i, T, shifted));
+    RSVD_TRY(copy_panel(rows, l, T, l, Y, l, 1, st, s));
+  }
+  if (Rout && full) {
     // R = R2 R1, then R3 R when shifted
     RSVD_TRY(dgemm(false, l, l, l, 1.0, R2, l, R1, l, 0.0, Rout, l, part, pl.part_doubles, s));
     RSVD_TRY(dgemm(false, l, l, l, 1.0, R3, l, Rout, l, 0.0, Rtmp, l, part, pl.part_doubles, s, 64, shifted));
@@ -419,9 +443,10 @@ rsvd_status small_svd_and_rank(const rsvd_plan_s& pl, const Ws& w, int64_t l, do
     PhaseScope ph(2, s);
     RSVD_TRY(block_jacobi(l, Rt, w.at<double>(pl.off_M), w.at<double>(pl.off_P),
                           p.max_sweeps > 0 ? p.max_sweeps : 30, 1, st, s, pl.coop_share));
+    // the Householder fallback's tau (2 l doubles) is free again: ordering scratch
     RSVD_TRY(svd_finish(l, kcl, w.at<double>(pl.off_M), w.at<double>(pl.off_P), jacobi_padded(l),
                         w.at<double>(pl.off_sig), w.at<double>(pl.off_Us), w.at<double>(pl.off_W),
-                        st, s));
+                        w.at<double>(pl.off_tau), st, s));
   }
   // the l - p cap protects unconverged trailing values; an exact SVD
   // (l = min(m, n)) has none
@@ -927,6 +952,7 @@ size_t rsvd_small_svd_work_bytes(int64_t l) {
   c.take(sizeof(DevState));
   c.take((size_t)Lp * Lp * sizeof(double));
   c.take((size_t)Lp * Lp * sizeof(double));
+  c.take((size_t)2 * l * sizeof(double));
   return c.at;
 }
 
@@ -942,6 +968,7 @@ rsvd_status rsvd_small_svd(int64_t l, const double* R, double* sv, double* Us, d
   const size_t off_state = c.take(sizeof(DevState));
   const size_t off_M = c.take((size_t)Lp * Lp * sizeof(double));
   const size_t off_P = c.take((size_t)Lp * Lp * sizeof(double));
+  const size_t off_scr = c.take((size_t)2 * l * sizeof(double));
   Ws w{(char*)work};
   DevState* st = w.at<DevState>(off_state);
   double* Mj = w.at<double>(off_M);
@@ -950,7 +977,7 @@ rsvd_status rsvd_small_svd(int64_t l, const double* R, double* sv, double* Us, d
 #define RSVD_TRY(x) do { r = (x); if (r != RSVD_OK) return r; } while (0)
   RSVD_TRY(init_state(st, 0, s));
   RSVD_TRY(block_jacobi(l, R, Mj, Pj, max_sweeps > 0 ? max_sweeps : 30, 1, st, s));
-  RSVD_TRY(svd_finish(l, l, Mj, Pj, Lp, sv, Us, W, st, s));
+  RSVD_TRY(svd_finish(l, l, Mj, Pj, Lp, sv, Us, W, w.at<double>(off_scr), st, s));
   if (sweeps && hipMemcpyAsync(sweeps, &st->sweeps, sizeof(int32_t), hipMemcpyDeviceToDevice, s) != hipSuccess)
     return RSVD_EHIP;
   if (flags && hipMemcpyAsync(flags, &st->flags, sizeof(uint32_t), hipMemcpyDeviceToDevice, s) != hipSuccess)
@@ -1232,7 +1259,7 @@ rsvd_status rsvd_pilot_features(const double* A, int64_t lda, int64_t m, int64_t
     return r;
   if ((r = svd_finish(l, pl.kc, w.at<double>(pl.off_M), w.at<double>(pl.off_P), jacobi_padded(l),
                       w.at<double>(pl.off_sig), w.at<double>(pl.off_Us), w.at<double>(pl.off_W),
-                      st, s)) != RSVD_OK)
+                      w.at<double>(pl.off_tau), st, s)) != RSVD_OK)
     return r;
   return pilot_features((int)l, w.at<double>(pl.off_sig), feat, s);
 }

@@ -1083,11 +1083,12 @@ __global__ void __launch_bounds__(256) householder_grid_kernel(int64_t rows, int
 // LDS, double buffered. Rows past `rows` read as zero and are not stored;
 // columns past l act as identity.
 // ---------------------------------------------------------------------------
-constexpr int kTrsmMaxNB = 20;
+constexpr int kTrsmMaxNB = 20;      // l <= 320: the register budget of the common widths
+constexpr int kTrsmMaxNBWide = 38;  // l <= 608: R's two column blocks fill the LDS
 constexpr int kTrsmWaves = 4;
 
 struct TrsmCtx {
-  int64_t rows, ldy, ldq, row;
+  int64_t rows, ldy, ldq, ldr, row;
   int l, nb, r, g;
   bool row_ok;
   const double* Y;
@@ -1099,8 +1100,8 @@ struct TrsmCtx {
 
 // Column tile J of the substitution (J a constant, so the register arrays
 // are indexed statically).
-template <int J>
-__device__ __forceinline__ void trsm_tile(const TrsmCtx& c, double (&qt)[kTrsmMaxNB][4]) {
+template <int J, int MAXNB>
+__device__ __forceinline__ void trsm_tile(const TrsmCtx& c, double (&qt)[MAXNB][4]) {
   constexpr int kT = 64 * kTrsmWaves;
   constexpr int kU = (256 * (J + 1) + kT - 1) / kT;
   if (J >= c.nb) return;
@@ -1114,7 +1115,7 @@ __device__ __forceinline__ void trsm_tile(const TrsmCtx& c, double (&qt)[kTrsmMa
   for (int u = 0; u < kU; u++) {
     const int e = (int)threadIdx.x + kT * u;
     const int i = e >> 4, cc = 16 * (J + 1) + (e & 15);
-    nxt[u] = (more && e < 256 * (J + 1) && cc < l) ? c.R[(int64_t)i * l + cc] : 0.0;
+    nxt[u] = (more && e < 256 * (J + 1) && cc < l) ? c.R[(int64_t)i * c.ldr + cc] : 0.0;
   }
   d4 acc;
   double xa[4];
@@ -1123,7 +1124,7 @@ __device__ __forceinline__ void trsm_tile(const TrsmCtx& c, double (&qt)[kTrsmMa
     const int cc = 16 * J + g + 4 * t;
     acc[t] = (c.row_ok && cc < l) ? c.Y[c.row * c.ldy + cc] : 0.0;
     const int i = 16 * J + g + 4 * t, cd = 16 * J + r;
-    xa[t] = (i < l && cd < l) ? c.Xd[(int64_t)i * l + cd] : (i == cd ? 1.0 : 0.0);
+    xa[t] = (i < l && cd < l) ? c.Xd[(int64_t)i * c.ldr + cd] : (i == cd ? 1.0 : 0.0);
   }
   if constexpr (J > 0) {
     __syncthreads();  // block J written, block J - 1 no longer read
@@ -1166,15 +1167,17 @@ __device__ __forceinline__ void trsm_tile(const TrsmCtx& c, double (&qt)[kTrsmMa
   }
 }
 
-template <int... Js>
-__device__ __forceinline__ void trsm_tiles(const TrsmCtx& c, double (&qt)[kTrsmMaxNB][4],
+template <int MAXNB, int... Js>
+__device__ __forceinline__ void trsm_tiles(const TrsmCtx& c, double (&qt)[MAXNB][4],
                                            std::integer_sequence<int, Js...>) {
-  (trsm_tile<Js>(c, qt), ...);
+  (trsm_tile<Js, MAXNB>(c, qt), ...);
 }
 
+template <int MAXNB>
 __global__ void __launch_bounds__(64 * kTrsmWaves) trsm_upper_kernel(
     int64_t rows, int l, const double* __restrict__ Y, int64_t ldy, const double* __restrict__ R,
-    const double* __restrict__ Xd, double* __restrict__ Q, int64_t ldq, const uint32_t* pred) {
+    int64_t ldr, const double* __restrict__ Xd, double* __restrict__ Q, int64_t ldq,
+    const uint32_t* pred) {
   extern __shared__ double lds[];
   if (pred != nullptr && *pred == 0) return;
   TrsmCtx c;
@@ -1182,6 +1185,7 @@ __global__ void __launch_bounds__(64 * kTrsmWaves) trsm_upper_kernel(
   c.ldy = ldy;
   c.ldq = ldq;
   c.l = l;
+  c.ldr = ldr;
   c.nb = (l + 15) / 16;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   c.r = lane & 15;
@@ -1193,8 +1197,8 @@ __global__ void __launch_bounds__(64 * kTrsmWaves) trsm_upper_kernel(
   c.Xd = Xd;
   c.Q = Q;
   c.lds = lds;
-  double qt[kTrsmMaxNB][4];
-  trsm_tiles(c, qt, std::make_integer_sequence<int, kTrsmMaxNB>{});
+  double qt[MAXNB][4];
+  trsm_tiles<MAXNB>(c, qt, std::make_integer_sequence<int, MAXNB>{});
 }
 
 // ---------------------------------------------------------------------------
@@ -1365,26 +1369,34 @@ __global__ void __launch_bounds__(256) identity_kernel(int64_t l, double* P) {
 
 // s_i = |row i of M|, sorted decreasingly (ties keep the lower row first);
 // Us[:, i] = row pi(i) of M / s_i, W[:, i] = row pi(i) of P.
-__global__ void __launch_bounds__(kBig) svd_finish_kernel(int l, int kc,
-                                                          const double* __restrict__ M,
-                                                          const double* __restrict__ P, int64_t ld,
-                                                          double* __restrict__ s,
-                                                          double* __restrict__ Us,
-                                                          double* __restrict__ W, DevState* st) {
-  extern __shared__ double lds[];
-  double* nrm = lds;                       // l
-  int* perm = (int*)(lds + l);             // l
-  for (int i = threadIdx.x; i < l; i += blockDim.x) {
-    double a = 0.0;
-    for (int c = 0; c < l; c++) {
-      const double x = M[(int64_t)i * ld + c];
-      a += x * x;
-    }
-    nrm[i] = sqrt(a);
+// Ordering and extraction of the small SVD from converged M (rows mutually
+// orthogonal: row i = s_i u_i^T) and P (rotations), in three launches:
+//   norms  one wave per row of M (coalesced), summed in a fixed lane order
+//   rank   one workgroup ranks the norms by (norm, index), NaN below every
+//          norm, so the positions always form a permutation; s sorted
+//   gather Us[r][i] = M[perm i][r] / s_i and W[r][i] = P[perm i][r] through
+//          32 x 32 LDS tiles (rows of M and P read along r, Us and W written
+//          along i)
+// scratch: 2 l doubles (the norms, then the permutation as integers).
+__global__ void __launch_bounds__(256) svd_norms_kernel(int l, const double* __restrict__ M,
+                                                        int64_t ld, double* __restrict__ nrm) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= l) return;
+  double a = 0.0;
+  for (int c = lane; c < l; c += 64) {
+    const double x = M[(int64_t)row * ld + c];
+    a += x * x;
   }
+  a = wave_sum(a);
+  if (lane == 0) nrm[row] = sqrt(a);
+}
+
+__global__ void __launch_bounds__(kBig) svd_rank_kernel(int l, const double* __restrict__ nrm,
+                                                        int* __restrict__ perm,
+                                                        double* __restrict__ s, DevState* st) {
+  __shared__ int s_zero;
+  if (threadIdx.x == 0) s_zero = 0;
   __syncthreads();
-  // rank by (norm, index) with NaN ordered below every norm, so the
-  // positions always form a permutation of 0..l-1
   for (int i = threadIdx.x; i < l; i += blockDim.x) {
     const double v = isnan(nrm[i]) ? -1.0 : nrm[i];
     int pos = 0;
@@ -1393,25 +1405,42 @@ __global__ void __launch_bounds__(kBig) svd_finish_kernel(int l, int kc,
       pos += (u > v) || (u == v && j < i);
     }
     perm[pos] = i;
+    s[pos] = nrm[i];
+    if (!(nrm[i] > 0.0)) s_zero = 1;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < l; i += blockDim.x) s[i] = nrm[min(max(perm[i], 0), l - 1)];
-  for (int64_t e = threadIdx.x; e < (int64_t)l * kc; e += blockDim.x) {
-    const int r = (int)(e / kc), i = (int)(e % kc);
-    if (i < l) {
+  if (threadIdx.x == 0 && s_zero) atomicOr(&st->flags, (uint32_t)RSVD_FLAG_ZERO_SIGMA);
+}
+
+__global__ void __launch_bounds__(256) svd_gather_kernel(int l, int kc,
+                                                         const double* __restrict__ M,
+                                                         const double* __restrict__ P, int64_t ld,
+                                                         const int* __restrict__ perm,
+                                                         const double* __restrict__ s,
+                                                         double* __restrict__ Us,
+                                                         double* __restrict__ W) {
+  __shared__ double tm[32][33], tp[32][33];
+  const int r0 = blockIdx.x * 32, i0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 8 rows of threads
+  for (int y = ty; y < 32; y += 8) {
+    const int i = i0 + y, r = r0 + tx;
+    double vm = 0.0, vp = 0.0;
+    if (i < kc && i < l && r < l) {
       const int src = min(max(perm[i], 0), l - 1);
-      const double sv = nrm[src];
-      Us[e] = sv > 0.0 ? M[(int64_t)src * ld + r] / sv : 0.0;
-      W[e] = P[(int64_t)src * ld + r];
-    } else {
-      Us[e] = 0.0;
-      W[e] = 0.0;
+      vm = M[(int64_t)src * ld + r];
+      vp = P[(int64_t)src * ld + r];
     }
+    tm[y][tx] = vm;
+    tp[y][tx] = vp;
   }
-  if (threadIdx.x == 0) {
-    bool zero = false;
-    for (int i = 0; i < l; i++) zero |= !(nrm[i] > 0.0);
-    if (zero) atomicOr(&st->flags, (uint32_t)RSVD_FLAG_ZERO_SIGMA);
+  __syncthreads();
+  for (int y = ty; y < 32; y += 8) {
+    const int r = r0 + y, i = i0 + tx;
+    if (r < l && i < kc) {
+      const double sv = i < l ? s[i] : 0.0;
+      Us[(int64_t)r * kc + i] = sv > 0.0 ? tm[tx][y] / sv : 0.0;
+      W[(int64_t)r * kc + i] = tp[tx][y];
+    }
   }
 }
 
@@ -1823,25 +1852,33 @@ rsvd_status gram(int64_t rows, int64_t l, const double* Y, int64_t ldy, double* 
   return RSVD_OK;
 }
 
-bool trsm_supported(int64_t l) { return l >= 1 && (l + 15) / 16 <= kTrsmMaxNB; }
+bool trsm_supported(int64_t l) { return l >= 1 && (l + 15) / 16 <= kTrsmMaxNBWide; }
 
 rsvd_status trsm_upper(int64_t rows, int64_t l, const double* Y, int64_t ldy, const double* R,
-                       const double* Xd, double* Q, int64_t ldq, const uint32_t* pred,
-                       hipStream_t s) {
+                       int64_t ldr, const double* Xd, double* Q, int64_t ldq,
+                       const uint32_t* pred, hipStream_t s) {
   if (rows <= 0 || l <= 0) return RSVD_OK;
-  if (!trsm_supported(l) || ldy < l || ldq < l) return RSVD_EINVAL;
+  if (!trsm_supported(l) || ldy < l || ldq < l || ldr < l) return RSVD_EINVAL;
   static bool attr = false;
   if (!attr) {
     attr = true;
-    (void)hipFuncSetAttribute((const void*)trsm_upper_kernel,
+    (void)hipFuncSetAttribute((const void*)trsm_upper_kernel<kTrsmMaxNB>,
                               hipFuncAttributeMaxDynamicSharedMemorySize,
                               2 * kTrsmMaxNB * 256 * (int)sizeof(double));
+    (void)hipFuncSetAttribute((const void*)trsm_upper_kernel<kTrsmMaxNBWide>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              2 * kTrsmMaxNBWide * 256 * (int)sizeof(double));
   }
   const int nb = (int)((l + 15) / 16);
   const size_t lds = (size_t)2 * nb * 256 * sizeof(double);
   const int64_t per = 16 * kTrsmWaves;
-  hipLaunchKernelGGL(trsm_upper_kernel, dim3((unsigned)((rows + per - 1) / per)),
-                     dim3(64 * kTrsmWaves), lds, s, rows, (int)l, Y, ldy, R, Xd, Q, ldq, pred);
+  const dim3 grid((unsigned)((rows + per - 1) / per));
+  if (nb <= kTrsmMaxNB)
+    hipLaunchKernelGGL(trsm_upper_kernel<kTrsmMaxNB>, grid, dim3(64 * kTrsmWaves), lds, s, rows,
+                       (int)l, Y, ldy, R, ldr, Xd, Q, ldq, pred);
+  else
+    hipLaunchKernelGGL(trsm_upper_kernel<kTrsmMaxNBWide>, grid, dim3(64 * kTrsmWaves), lds, s,
+                       rows, (int)l, Y, ldy, R, ldr, Xd, Q, ldq, pred);
   RSVD_LAUNCH_CHECK();
   return RSVD_OK;
 }
@@ -1904,11 +1941,20 @@ rsvd_status set_identity(int64_t l, double* P, hipStream_t s) {
 }
 
 rsvd_status svd_finish(int64_t l, int64_t kc, const double* M, const double* P, int64_t ld,
-                       double* sv, double* Us, double* W, DevState* st, hipStream_t s) {
-  const size_t shm = (size_t)l * (sizeof(double) + sizeof(int));
-  hipLaunchKernelGGL(svd_finish_kernel, dim3(1), dim3(kBig), shm, s, (int)l, (int)kc, M, P, ld, sv,
-                     Us, W, st);
+                       double* sv, double* Us, double* W, double* scratch, DevState* st,
+                       hipStream_t s) {
+  double* nrm = scratch;
+  int* perm = reinterpret_cast<int*>(scratch + l);
+  hipLaunchKernelGGL(svd_norms_kernel, dim3((unsigned)((l + 3) / 4)), dim3(256), 0, s, (int)l, M,
+                     ld, nrm);
   RSVD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(svd_rank_kernel, dim3(1), dim3(kBig), 0, s, (int)l, nrm, perm, sv, st);
+  RSVD_LAUNCH_CHECK();
+  if (kc > 0) {
+    hipLaunchKernelGGL(svd_gather_kernel, dim3((unsigned)((l + 31) / 32), (unsigned)((kc + 31) / 32)),
+                       dim3(256), 0, s, (int)l, (int)kc, M, P, ld, perm, sv, Us, W);
+    RSVD_LAUNCH_CHECK();
+  }
   return RSVD_OK;
 }
 

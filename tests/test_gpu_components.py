@@ -56,7 +56,11 @@ def test_dgemm_matches_numpy(ta, m, n, k):
                                        (700, 16, 0.1), (900, 17, 0.05), (5000, 271, 1 / 50),
                                        # 273..320: grid Cholesky with diagonal-tile inverses
                                        # only, then the block triangular solve
-                                       (4096, 288, 1 / 40), (6000, 320, 1 / 50)])
+                                       (4096, 288, 1 / 40), (6000, 320, 1 / 50),
+                                       # 321..608: the wide substitution kernel; 609: the
+                                       # full inverse and a product
+                                       (5000, 400, 1 / 80), (4000, 608, 1 / 150),
+                                       (3000, 609, 1 / 150)])
 def test_orth_matches_oracle(m, l, decay):
     import paper_2307_15572_amd as rs
     announce(f"orth m={m} l={l} decay={decay}")
