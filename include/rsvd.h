@@ -574,14 +574,14 @@ rsvd_status rsvd_tune_set(int32_t kind, int32_t arith, int32_t trans, int64_t M,
  * pair on its stream around every launch group of a phase; the events are
  * kept on the host until collected. Not thread-safe: one tracing caller at a
  * time. Phases:
- *   0 streaming products with A in FP64 / in-register FP32 (sketch, power
- *     iterations, projection)
+ *   0 streaming products with A in FP64 (sketch, power iterations, projection)
  *   1 QR of the panels    2 small SVD (Jacobi + ordering)   3 lift + signs
  *   4 residual pass       5 projection P                    6 everything else
  *   7 rounding A into the BF16 planes of the BF16 schedules
  *   8 the BF16 products of those schedules (panel planes, product, partial sums)
+ *   9 the FP32 products of the FP32 schedule (operands rounded in registers)
  */
-#define RSVD_TRACE_PHASES 9
+#define RSVD_TRACE_PHASES 10
 void rsvd_trace_enable(int32_t on);
 /* Synchronize on the recorded events, add their durations per phase into
  * ms[RSVD_TRACE_PHASES] and counts[RSVD_TRACE_PHASES] (host arrays), and

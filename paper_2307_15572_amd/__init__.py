@@ -46,7 +46,7 @@ EXPORTED = (
 )
 MLP_PARAMS, MLP_IN, MLP_OUT, MLP_MAX_BATCH, PILOT_COLS = 5443, 16, 3, 128, 32
 TRACE_PHASES = ("stream_gemm", "qr", "small_svd", "lift_signs", "residual", "omega", "other",
-                "bf16_planes", "bf16_gemm")
+                "bf16_planes", "bf16_gemm", "fp32_gemm")
 
 
 class RsvdError(RuntimeError):

@@ -19,6 +19,8 @@
 // blocks of one row strip and row strips of one K range share that XCD's L2.
 // Split-K writes FP64 partial tiles that a second kernel sums in a fixed
 // order (deterministic; no floating-point atomics).
+#include <type_traits>
+
 #include "common.hpp"
 #include "kernels.hpp"
 #include "tune.hpp"
@@ -53,9 +55,9 @@ __device__ __forceinline__ int acc_row(int g, int it) {
 // One chunk of 16 k values for NT tiles: av[s] = A(row r, k = 4 g + s),
 // Bs holds the chunk's 16 x BN block of B. Each precision uses its own
 // matrix-core instruction; the lane-group-to-k assignment is the same.
-template <int PREC, int NT, int BN>
+template <int PREC, int NT, int BN, typename BT>
 __device__ __forceinline__ void chunk_mma(typename AccType<PREC>::type (&acc)[NT], const double av[4],
-                                          const double* Bs, int g, int r) {
+                                          const BT* Bs, int g, int r) {
   if constexpr (PREC == kPrecF64) {
 #pragma unroll
     for (int s = 0; s < 4; s++) {
@@ -123,6 +125,7 @@ struct GemmArgs {
   int64_t ldref;
   double* rpart;           // residual mode: per-workgroup partial sums [2][items]
   int vec_a, vec_b;        // 16-byte loads allowed (even leading dimension, aligned base)
+  int64_t b_cols;          // FP32 panel (B_F32 kernels): columns readable in each row of B
 };
 
 template <bool TA, int NT, bool RES, int PREC>
@@ -343,39 +346,43 @@ __global__ void __launch_bounds__(kThreads) dgemm_kernel(GemmArgs g) {
 // A stage layout: wave w, half h (k pairs 0-1 / 2-3 of a lane's 4 k values):
 // 64 lanes x 16 B, so the MFMA A fragments of a lane are one 16-byte read.
 // ---------------------------------------------------------------------------
-// copies a wave issues per chunk: 2 for A plus its share of the 2 NT B copies
-template <int NT, int WM, int W>
+// copies a wave issues per chunk: 2 for A plus its share of the NBQ B copies
+template <int NBQ, int WM, int W>
 struct CopiesPerChunk {
-  static constexpr int value = 2 + (2 * NT - W + WM - 1) / WM;
+  static constexpr int value = 2 + (NBQ - W + WM - 1) / WM;
 };
 
-template <int NT, int WM>
+template <int NBQ, int WM>
 __device__ __forceinline__ void wait_own_next(int wave, bool next_pending) {
   if (!next_pending) {
     wait_vmcnt<0>();
     return;
   }
   switch (wave) {
-    case 0: wait_vmcnt<CopiesPerChunk<NT, WM, 0>::value>(); break;
-    case 1: wait_vmcnt<CopiesPerChunk<NT, WM, 1>::value>(); break;
-    case 2: wait_vmcnt<CopiesPerChunk<NT, WM, 2>::value>(); break;
-    case 3: wait_vmcnt<CopiesPerChunk<NT, WM, 3>::value>(); break;
-    case 4: wait_vmcnt<CopiesPerChunk<NT, WM, (WM > 4 ? 4 : 0)>::value>(); break;
-    case 5: wait_vmcnt<CopiesPerChunk<NT, WM, (WM > 5 ? 5 : 0)>::value>(); break;
-    case 6: wait_vmcnt<CopiesPerChunk<NT, WM, (WM > 6 ? 6 : 0)>::value>(); break;
-    default: wait_vmcnt<CopiesPerChunk<NT, WM, (WM > 7 ? 7 : 0)>::value>(); break;
+    case 0: wait_vmcnt<CopiesPerChunk<NBQ, WM, 0>::value>(); break;
+    case 1: wait_vmcnt<CopiesPerChunk<NBQ, WM, 1>::value>(); break;
+    case 2: wait_vmcnt<CopiesPerChunk<NBQ, WM, 2>::value>(); break;
+    case 3: wait_vmcnt<CopiesPerChunk<NBQ, WM, 3>::value>(); break;
+    case 4: wait_vmcnt<CopiesPerChunk<NBQ, WM, (WM > 4 ? 4 : 0)>::value>(); break;
+    case 5: wait_vmcnt<CopiesPerChunk<NBQ, WM, (WM > 5 ? 5 : 0)>::value>(); break;
+    case 6: wait_vmcnt<CopiesPerChunk<NBQ, WM, (WM > 6 ? 6 : 0)>::value>(); break;
+    default: wait_vmcnt<CopiesPerChunk<NBQ, WM, (WM > 7 ? 7 : 0)>::value>(); break;
   }
 }
 
-template <int NT, int WM, bool RES, int PREC>
+template <int NT, int WM, bool RES, int PREC, bool B_F32 = false>
 __global__ void __launch_bounds__(64 * WM) dgemm_nn_dma_kernel(GemmArgs g) {
+  static_assert(!B_F32 || PREC == kPrecF32, "FP32 panels feed the FP32 matrix cores");
+  using BT = typename std::conditional<B_F32, float, double>::type;
   constexpr int BN = NT * 16;
   constexpr int BEL = kBK * BN;
-  constexpr int NBQ = 2 * NT;            // 1 KB copies per B chunk
+  constexpr int EPL = 16 / (int)sizeof(BT);  // elements per lane and 16-byte copy
+  constexpr int CPE = 64 * EPL;             // elements per 1 KB copy
+  constexpr int NBQ = BEL / CPE;            // 1 KB copies per B chunk
   constexpr int AEL = WM * 2 * 128;      // doubles per A stage
-  __shared__ __attribute__((aligned(16))) double B0[BEL];
-  __shared__ __attribute__((aligned(16))) double B1[BEL];
-  __shared__ __attribute__((aligned(16))) double B2[BEL];
+  __shared__ __attribute__((aligned(16))) BT B0[BEL];
+  __shared__ __attribute__((aligned(16))) BT B1[BEL];
+  __shared__ __attribute__((aligned(16))) BT B2[BEL];
   __shared__ __attribute__((aligned(16))) double A0[AEL];
   __shared__ __attribute__((aligned(16))) double A1[AEL];
   __shared__ __attribute__((aligned(16))) double A2[AEL];
@@ -413,29 +420,31 @@ __global__ void __launch_bounds__(64 * WM) dgemm_nn_dma_kernel(GemmArgs g) {
   const int64_t row0 = (int64_t)tm * (16 * WM) + wave * 16;
   const int64_t col0 = (int64_t)tn * BN;
   const double* __restrict__ A = g.A;
-  const double* __restrict__ B = g.B;
+  const BT* __restrict__ B = reinterpret_cast<const BT*>(g.B);
   // source of this lane's A copies: row (clamped), k offset 4 gq + 2 h
   const double* asrc = A + min(row0 + r, g.M - 1) * g.lda + kb + 4 * gq;
 
   // per-lane copy sources, advanced by one chunk after every issue
   constexpr int NQ = (NBQ + WM - 1) / WM;
-  const double* bsrc[NQ];
+  const BT* bsrc[NQ];
+  // last column a copy may start at (columns past N are never stored)
+  const int64_t bmax = (B_F32 ? g.b_cols : g.N) - EPL;
 #pragma unroll
   for (int i = 0; i < NQ; i++) {
     const int q = min(wave + WM * i, NBQ - 1);
-    const int e = q * 128 + 2 * lane;  // element of the chunk this lane copies
+    const int e = q * CPE + EPL * lane;  // element of the chunk this lane copies
     const int kk = e / BN, cc = e % BN;
-    const int64_t col = min(col0 + cc, g.N - 2);  // columns past N are never stored
+    const int64_t col = min(col0 + cc, bmax);
     bsrc[i] = B + (kb + kk) * g.ldb + col;
   }
   const int64_t bstep = (int64_t)kBK * g.ldb;
-  auto issue = [&](double* As, double* Bs) {
+  auto issue = [&](double* As, BT* Bs) {
 #pragma unroll
     for (int h = 0; h < 2; h++) copy_to_lds16(asrc + 2 * h, As + (wave * 2 + h) * 128);
     asrc += kBK;
 #pragma unroll
     for (int i = 0; i < NQ; i++) {
-      if (wave + WM * i < NBQ) copy_to_lds16(bsrc[i], Bs + (wave + WM * i) * 128);
+      if (wave + WM * i < NBQ) copy_to_lds16(bsrc[i], Bs + (wave + WM * i) * CPE);
       bsrc[i] += bstep;
     }
   };
@@ -447,15 +456,15 @@ __global__ void __launch_bounds__(64 * WM) dgemm_nn_dma_kernel(GemmArgs g) {
 
   // one chunk; the copies of chunk c + 2 are issued first (their LDS stage
   // was released by the barrier)
-  auto compute = [&](const double* As, const double* Bs, double* As2, double* Bs2, bool do_issue) {
+  auto compute = [&](const double* As, const BT* Bs, double* As2, BT* Bs2, bool do_issue) {
     if (do_issue) issue(As2, Bs2);
     const double2 a01 = *reinterpret_cast<const double2*>(As + (wave * 2 + 0) * 128 + 2 * lane);
     const double2 a23 = *reinterpret_cast<const double2*>(As + (wave * 2 + 1) * 128 + 2 * lane);
     const double av[4] = {a01.x, a01.y, a23.x, a23.y};
     chunk_mma<PREC, NT, BN>(acc, av, Bs, gq, r);
   };
-  auto step = [&](int c, double* As, double* Bs, double* As2, double* Bs2) {
-    wait_own_next<NT, WM>(wave, c + 1 < nk);
+  auto step = [&](int c, double* As, BT* Bs, double* As2, BT* Bs2) {
+    wait_own_next<NBQ, WM>(wave, c + 1 < nk);
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");  // no LDS access moves across the barrier
     compute(As, Bs, As2, Bs2, c + 2 < nk);
@@ -488,7 +497,7 @@ __global__ void __launch_bounds__(64 * WM) dgemm_nn_dma_kernel(GemmArgs g) {
     sd = wave_sum(sd);
     sa = wave_sum(sa);
     __syncthreads();
-    double* red = B0;  // the stages are no longer in use
+    double* red = reinterpret_cast<double*>(B0);  // the stages are no longer in use
     if (lane == 0) {
       red[wave] = sd;
       red[WM + wave] = sa;
@@ -578,6 +587,30 @@ hipError_t launch_dma(int nt, dim3 grid, hipStream_t st, const GemmArgs& a) {
 }
 
 template <int WM>
+hipError_t launch_dma_bf32(int nt, dim3 grid, hipStream_t st, const GemmArgs& a) {
+  switch (nt) {
+#define RSVD_FCASE(X) case X: hipLaunchKernelGGL((dgemm_nn_dma_kernel<X, WM, false, kPrecF32, true>), grid, dim3(64 * WM), 0, st, a); break;
+    RSVD_FCASE(1) RSVD_FCASE(2) RSVD_FCASE(3) RSVD_FCASE(4) RSVD_FCASE(5) RSVD_FCASE(6)
+    RSVD_FCASE(7) RSVD_FCASE(8) RSVD_FCASE(9) RSVD_FCASE(10) RSVD_FCASE(11) RSVD_FCASE(12)
+    RSVD_FCASE(13) RSVD_FCASE(14) RSVD_FCASE(15) RSVD_FCASE(16) RSVD_FCASE(17)
+#undef RSVD_FCASE
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+// Xf (rows x ldf, FP32) = X (rows x cols, FP64) rounded to nearest, columns
+// cols .. ldf - 1 zero.
+__global__ void __launch_bounds__(256) f32_panel_kernel(int64_t rows, int64_t cols,
+                                                        const double* __restrict__ X, int64_t ldx,
+                                                        float* __restrict__ Xf, int64_t ldf) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * ldf) return;
+  const int64_t r = idx / ldf, c = idx % ldf;
+  Xf[idx] = c < cols ? (float)X[r * ldx + c] : 0.0f;
+}
+
+template <int WM>
 hipError_t launch_dma_prec(int prec, int nt, dim3 grid, hipStream_t st, const GemmArgs& a) {
   if (prec == kPrecF32) return launch_dma<WM, false, kPrecF32>(nt, grid, st, a);
   if (prec == kPrecBF16) return launch_dma<WM, false, kPrecBF16>(nt, grid, st, a);
@@ -621,10 +654,22 @@ GemmShape dgemm_shape(int64_t M, int64_t N, int64_t K, int max_splits) {
   return s;
 }
 
+int64_t f32_panel_ld(int64_t cols) { return (cols + 3) / 4 * 4; }
+
+rsvd_status f32_panel(int64_t rows, int64_t cols, const double* X, int64_t ldx, float* Xf,
+                      hipStream_t s) {
+  const int64_t ldf = f32_panel_ld(cols);
+  if (rows * ldf == 0) return RSVD_OK;
+  hipLaunchKernelGGL(f32_panel_kernel, dim3((unsigned)((rows * ldf + 255) / 256)), dim3(256), 0, s,
+                     rows, cols, X, ldx, Xf, ldf);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
 rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                   int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                   double* part, size_t part_doubles, hipStream_t st, int max_splits,
-                  const uint32_t* pred, int prec) {
+                  const uint32_t* pred, int prec, const float* Bf, int64_t ldbf) {
   if (M <= 0 || N <= 0) return RSVD_OK;
   if (K <= 0) {
     // C = beta * C
@@ -639,6 +684,9 @@ rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const 
   const bool vec_a = (lda % 2 == 0) && ((uintptr_t)A % 16 == 0);
   const bool vec_b = (ldb % 2 == 0) && ((uintptr_t)B % 16 == 0);
   const bool dma_ok = !ta && dgemm_dma_eligible(K, N, A, lda, B, ldb);
+  // the FP32 panel of B instead of B itself (FP32 schedule, streaming kernel)
+  const bool bf32 = dma_ok && Bf != nullptr && prec == kPrecF32 && ldbf >= N && ldbf % 4 == 0 &&
+                    ((uintptr_t)Bf % 16 == 0);
   const TuneKey tkey{dma_ok ? kTuneDma : kTuneGeneric, prec, ta ? 1 : 0, M, N, K};
   if (pred == nullptr && tune_recording()) {
     // candidates: waves (LDS-DMA kernel) x split counts whose partials fit
@@ -651,7 +699,7 @@ rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const 
     }
     tune_record(tkey, std::move(cands), [=](hipStream_t s2) {
       return dgemm(ta, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, part_doubles, s2,
-                   max_splits, pred, prec);
+                   max_splits, pred, prec, Bf, ldbf);
     });
   }
   TuneCfg tcfg;
@@ -678,6 +726,7 @@ rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const 
   a.pred = pred; a.Aref = nullptr; a.ldref = 0; a.rpart = nullptr;
   a.vec_a = vec_a;
   a.vec_b = vec_b;
+  a.b_cols = 0;
   const int64_t total = (int64_t)s.tiles_m * s.tiles_n * s.splits;
   dim3 grid((unsigned)total);
   hipError_t e;
@@ -709,7 +758,15 @@ rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const 
     d.part = S > 1 ? part : nullptr;
     s.splits = S;
     const dim3 g2((unsigned)(T * S));
-    e = wm == 8 ? launch_dma_prec<8>(prec, s.nt, g2, st, d) : launch_dma_prec<4>(prec, s.nt, g2, st, d);
+    if (bf32) {
+      d.B = reinterpret_cast<const double*>(Bf);
+      d.ldb = ldbf;
+      d.b_cols = ldbf;
+      e = wm == 8 ? launch_dma_bf32<8>(s.nt, g2, st, d) : launch_dma_bf32<4>(s.nt, g2, st, d);
+    } else {
+      e = wm == 8 ? launch_dma_prec<8>(prec, s.nt, g2, st, d)
+                  : launch_dma_prec<4>(prec, s.nt, g2, st, d);
+    }
   } else {
     e = ta ? launch_nt_prec<true>(prec, s.nt, grid, st, a)
            : launch_nt_prec<false>(prec, s.nt, grid, st, a);
@@ -783,7 +840,7 @@ rsvd_status resid(int64_t M, int64_t N, int64_t K, const double* US, int64_t ldu
     a.part = nullptr;
     a.tiles_m = (int)((M + 16 * wm - 1) / (16 * wm)); a.tiles_n = tiles_n; a.splits = 1;
     a.pred = nullptr; a.Aref = A; a.ldref = lda; a.rpart = partial;
-    a.vec_a = 1; a.vec_b = 1;
+    a.vec_a = 1; a.vec_b = 1; a.b_cols = 0;
     const int64_t total = (int64_t)a.tiles_m * a.tiles_n;
     if ((size_t)2 * total > resid_partials(M, N)) return RSVD_EINVAL;
     hipError_t e = wm == 4 ? launch_dma<4, true, kPrecF64>(nt, dim3((unsigned)total), s, a)

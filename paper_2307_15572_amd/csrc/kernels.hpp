@@ -18,10 +18,18 @@ void dgemm_set_dma(bool on, int waves = 4);
 // given, streams through the LDS-DMA kernel
 bool dgemm_dma_eligible(int64_t K, int64_t N, const double* A, int64_t lda, const double* B,
                         int64_t ldb);
+// Bf (FP32 schedule only): the FP32 panel of B (ldbf floats per row, 16-byte
+// aligned, ldbf a multiple of 4) that the streaming kernel reads instead of B
+// where it applies; B must still be given.
 rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                   int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                   double* part, size_t part_doubles, hipStream_t st, int max_splits = 64,
-                  const uint32_t* pred = nullptr, int prec = kPrecF64);
+                  const uint32_t* pred = nullptr, int prec = kPrecF64, const float* Bf = nullptr,
+                  int64_t ldbf = 0);
+// FP32 panel Xf (rows x f32_panel_ld(cols)) of X, rounded to nearest, zero padded
+int64_t f32_panel_ld(int64_t cols);
+rsvd_status f32_panel(int64_t rows, int64_t cols, const double* X, int64_t ldx, float* Xf,
+                      hipStream_t s);
 // ||A - US * Vt||_F^2 and ||A||_F^2 accumulated into st->resid2 / st->fro2
 // (US: M x K, Vt: K x N, A: M x N). partial: >= resid_partials(M, N) doubles.
 size_t resid_partials(int64_t M, int64_t N);

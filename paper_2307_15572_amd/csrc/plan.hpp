@@ -43,6 +43,8 @@ struct rsvd_plan_s {
   rsvd::Bf16Shape sh_n, sh_t;
   size_t off_Ah = 0, off_Al = 0, off_Ath = 0, off_Atl = 0, off_XTh = 0, off_XTl = 0;
   size_t off_fpart = 0, fpart_floats = 0;
+  // FP32 schedule: the FP32 panel of each low-precision product's operand
+  size_t off_Xf = 0;
   size_t part_doubles = 0;
   size_t total = 0;
 };

@@ -393,6 +393,8 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* worksp
     pl->fpart_floats = fpart;
     if (fpart) pl->off_fpart = c.take(fpart * sizeof(float));
   }
+  if (!adaptive && n_low > 0 && p.precision == RSVD_PREC_MIXED_FP32)
+    pl->off_Xf = c.take((size_t)mx * f32_panel_ld(l) * sizeof(float));
   if (adaptive) {
     pl->off_Wb = c.take((size_t)m * blk * D);
     pl->off_Zb = c.take((size_t)n * blk * D);
@@ -699,7 +701,7 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
                          int64_t inner) -> rsvd_status {
     const int prec = product < n_early - p.trailing_hp ? lowp : kPrecF64;
     product++;
-    PhaseScope ph(pl.bf16 && prec != kPrecF64 ? 8 : 0, s);
+    PhaseScope ph(pl.bf16 && prec != kPrecF64 ? 8 : (prec == kPrecF32 ? 9 : 0), s);
     if (pl.bf16 && prec != kPrecF64) {
       // X (inner x l) -> XT planes, then the product from the planes
       const Bf16Shape sh = bf16_tuned_shape(rows_out, l, inner, pl.bf16_split);
@@ -721,6 +723,14 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
                        pl.part_doubles, s, 64, nullptr, prec));
         return transpose(l, rows_out, Ct, rows_out, out, l, s);
       }
+    }
+    if (prec == kPrecF32 && !trans && pl.off_Xf) {
+      // the panel rounded to FP32 once: the streaming kernel stages half the
+      // bytes of it and feeds the matrix cores without conversions
+      float* Xf = w.at<float>(pl.off_Xf);
+      RSVD_TRY(f32_panel(inner, l, X, ldx, Xf, s));
+      return dgemm(false, rows_out, l, inner, 1.0, A, lda, X, ldx, 0.0, out, l, part,
+                   pl.part_doubles, s, 64, nullptr, prec, Xf, f32_panel_ld(l));
     }
     return dgemm(trans, rows_out, l, inner, 1.0, A, lda, X, ldx, 0.0, out, l, part,
                  pl.part_doubles, s, 64, nullptr, prec);
