@@ -51,15 +51,25 @@ PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 matrix
 GATE = 1e-6
 
-# HBM bytes per launch of the FP64 streaming product, from rocprofv3 --pmc
-# FETCH_SIZE and WRITE_SIZE runs of this benchmark
-# (profiles/rsvd_fp64_16384sq_symmetric_traffic.md). FETCH_SIZE is scaled by
-# 2.0 and WRITE_SIZE by 1.0: what the counters read for a plain 1 GiB copy
-# kernel. Valid only for the GEMM source they were taken with; any other
-# source reports traffic as null.
-TRAFFIC_SOURCE_SHA256 = "22708e6b1645ad24"
-TRAFFIC_FETCH_BYTES = 1135019 * 1024 * 2.0
-TRAFFIC_WRITE_BYTES = 69632 * 1024 * 1.0
+# HBM bytes per launch of the streaming products at the 16384 x 16384 x 272
+# shape, from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE runs of this benchmark
+# (profiles/rsvd_16384sq_symmetric_streaming_traffic.md): raw KiB per dispatch,
+# FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0, what the counters read for a
+# plain 1 GiB copy kernel. Valid only for the GEMM source they were taken
+# with; any other source reports traffic as null.
+TRAFFIC_SOURCE_SHA256 = "bebc41b9251f06ab"
+TRAFFIC_KIB = {"fp64": (1119523.8, 69632.0), "fp32": (1117170.8, 69632.0)}
+
+
+def product_traffic(kind):
+    """Measured HBM bytes per launch of the FP64 or FP32-panel streaming
+    product, or None when gemm.hip is not the source they were taken with."""
+    import hashlib
+    src = os.path.join(ROOT, "paper_2307_15572_amd", "csrc", "gemm.hip")
+    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != TRAFFIC_SOURCE_SHA256:
+        return None
+    fetch, write = TRAFFIC_KIB[kind]
+    return round(fetch * 1024 * 2.0 + write * 1024 * 1.0)
 
 
 def log(msg):
@@ -185,10 +195,7 @@ def headline(dev, args, A, sigma, w):
     s64 = f64["S"]
     gemm_ms, gemm_cnt = f64["phases"]["stream_gemm"]
     gemm_avg_s = gemm_ms / gemm_cnt * 1e-3
-    import hashlib
-    src = os.path.join(ROOT, "paper_2307_15572_amd", "csrc", "gemm.hip")
-    same = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] == TRAFFIC_SOURCE_SHA256
-    traffic = round(TRAFFIC_FETCH_BYTES + TRAFFIC_WRITE_BYTES) if same else None
+    traffic = product_traffic("fp64")
     roof64 = product_roofline(
         "fp64", flops_product, gemm_avg_s, PEAK_FP64_TFLOPS,
         "dgemm_nn_dma_kernel<NT=17, FP64> (A x 272-column panel, LDS-DMA pipeline)", gemm_cnt,
@@ -230,7 +237,10 @@ def headline(dev, args, A, sigma, w):
             fms, fcnt = ph["fp32_gemm"]
             ent["fp32_product"] = product_roofline(
                 "fp32", flops_product, fms / fcnt * 1e-3, PEAK_FP32_TFLOPS,
-                "dgemm_nn_dma_kernel<NT=17, FP32, FP32 panel> (A rounded in registers, the panel rounded once per product)", fcnt)
+                "dgemm_nn_dma_kernel<NT=17, FP32, FP32 panel> (A rounded in registers, the panel rounded once per product)", fcnt,
+                traffic=product_traffic("fp32"),
+                traffic_unit="bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+                algorithmic_bytes=8.0 * w.m * w.n + 4.0 * w.n * l + 8.0 * w.m * l)
         if ph["bf16_gemm"][1]:
             bms, bcnt = ph["bf16_gemm"]
             planes = 2 if prec == "mixed_bf16_split" else 1
@@ -373,7 +383,8 @@ def learned_leg(dev):
     finder (its rank, the width at which its posterior estimate passed, its
     spectrum) and train the predictor on the device; the last 500 are
     decomposed with learned sizing (pilot, prediction, judged run, adaptive
-    fallback) and with the adaptive finder alone."""
+    fallback) one by one and as one batch, and with the adaptive finder
+    alone (which decides its width block by block, channel after channel)."""
     import numpy as np
     import torch
     import paper_2307_15572_amd as rs
@@ -404,6 +415,7 @@ def learned_leg(dev):
     t_l = t_a = 0.0
     passes_l = passes_a = fell = agree = exact = 0
     reasons = {}
+    evals = []
     for c in range(1500, 2000):
         n, d = int(dims[c]), float(dec[c])
         A, _ = synth.channel_device_rng(c, n, d, tag=tag, device=dev)
@@ -425,15 +437,31 @@ def learned_leg(dev):
             reasons[out.reason] = reasons.get(out.reason, 0) + 1
         agree += int(out.rank == ad.rank)
         exact += int(out.rank == min(n, 1 + int(math.floor(d * math.log(1.0 / tau)))))
-        del A
+        evals.append(A)
     log(f"learned: 500 channels {t_l:.2f} s learned vs {t_a:.2f} s adaptive-only, fallbacks {fell}")
+    # the same 500 channels as one batch (sizes known before any run)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    outs = learned.decompose_batch(evals, net, tau, seed, list(range(1500, 2000)), symmetric=True)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t1
+    passes_b = sum(o.passes for o in outs)
+    fell_b = sum(int(o.fell_back) for o in outs)
+    exact_b = sum(int(o.rank == min(int(dims[c]), 1 + int(math.floor(float(dec[c]) * math.log(1.0 / tau)))))
+                  for c, o in zip(range(1500, 2000), outs))
+    del evals, outs
+    log(f"learned, one batch: {t_b:.2f} s, fallbacks {fell_b}")
     return {
         "workload": "c5_2000_channels_threshold_1e-6", "train": 1500, "evaluate": 500,
         "labelled": len(labels), "label_seconds": round(label_s, 2),
         "train_seconds": round(train_s, 2), "final_loss": round(loss, 4),
-        "learned_seconds": round(t_l, 3), "adaptive_only_seconds": round(t_a, 3),
-        "wall_time_speedup": round(t_a / t_l, 4),
-        "a_streams_learned": passes_l, "a_streams_adaptive_only": passes_a,
+        "learned_batched_seconds": round(t_b, 3), "learned_one_by_one_seconds": round(t_l, 3),
+        "adaptive_only_seconds": round(t_a, 3),
+        "wall_time_speedup_batched": round(t_a / t_b, 4),
+        "wall_time_speedup_one_by_one": round(t_a / t_l, 4),
+        "a_streams_learned": passes_l, "a_streams_learned_batched": passes_b,
+        "a_streams_adaptive_only": passes_a,
+        "fallbacks_batched": fell_b, "rank_equals_threshold_count_of_construction_batched": exact_b,
         "fallbacks": fell, "misprediction_rate": round(fell / 500.0, 4),
         "fallback_reasons": reasons, "rank_equals_adaptive_judge": agree,
         "rank_equals_threshold_count_of_construction": exact,

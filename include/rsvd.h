@@ -408,9 +408,11 @@ rsvd_status rsvd_mlp_targets(const int64_t* labels, int64_t B, float* stats, flo
                              void* stream);
 /* Sizing from the network: y = MLP(X) (B x 16 features), raw = y sd + mean
  * (stats as rsvd_mlp_targets writes them), then per sample
- *   k = min(max(ceil(1.1 * 10^raw0), 1), n_cap[b])   (10 % rank margin)
- *   p = the smallest of {8, 16, 32, 64, 128, 192, 256, 384} >= raw1 (else 384)
- *   q = min(max(ceil(raw2), 0), 4)
+ *   k = min(max(ceil(1.05 * 10^raw0), 1), n_cap[b])  (5 % rank margin)
+ *   p = the smallest of {8, 16, 32, 48, 64, 96, 128, 160, 192, 256, 320, 384,
+ *       448, 512} >= raw1 (else 512)
+ *   q = min(max(floor(raw2 + 1/2), 0), 4)    (nearest; a q too small shows in
+ *       the judge's UNCONVERGED flag)
  * into kpq (B x 3 device int64). n_cap: B device int64 (min(m, n) of each
  * channel). B >= 0. */
 rsvd_status rsvd_mlp_predict(const float* params, const float* stats, const float* X, int64_t B,
@@ -418,15 +420,17 @@ rsvd_status rsvd_mlp_predict(const float* params, const float* stats, const floa
 /* Label of one channel from a spectrum the method computed (e.g. the
  * adaptive finder's singular values s, count of them, decreasing, device)
  * with threshold rank k (>= 1) of an n x n channel: the cheapest (p, q) on
- * the grid p in {8, 16, 32, 64, 128, 192, 256, 384}, q in 0..4 whose l = k + p reaches
+ * the grid p in {8, 16, 32, 48, 64, 96, 128, 160, 192, 256, 320, 384, 448,
+ * 512}, q in 0..4 whose l = k + p reaches
  * n (an exact SVD), or whose l is at least l_min (the width at which the
  * adaptive finder's posterior estimate passed: the basis covers the tail)
  * and whose kept values are converged, (s[k+p-1] / s[k-1])^(4q+2) <= 1e-8
  * (for k + p > count the last computed value stands in: the ratio only
- * falls beyond it). Cost of a decomposition of
- * width l: (2q+2) n^2 l (products with A) + 11.4 (2q+1) n l^2 (panel QRs)
- * + 5000 l^3 (the small SVD), the weights being measured times of a QR and
- * of the small SVD in units of products with A (16384^2, l = 272).
+ * falls beyond it). Cost of a decomposition of width l, in seconds fitted to
+ * this library's measured times on MI355X: (2q + 2) (2 n^2 l / 60e12 +
+ * 0.44e-3 (l / 272)^1.6) for the products with A and the panel QRs (2q + 1
+ * in the power iteration and the QR of the projection) plus
+ * 3.2e-3 (l / 272)^1.6 for the small SVD (both latency-bound at these widths).
  * kpq (3 device int64) = (k, p, q); p = q = -1 when no grid point
  * qualifies. */
 rsvd_status rsvd_size_label(const double* s, int64_t count, int64_t k, int64_t n, int64_t l_min,

@@ -28,11 +28,13 @@ W1 (64 x 16, row-major), b1 (64), W2 (64 x 64), b2 (64), W3 (3 x 64), b3 (3).
 
 Sizing (the same rules as the device): targets() standardizes integer labels
 (log10 k, p, q) by their column means and population deviations; decode()
-turns a network output back into (k, p, q) with a 10 % rank margin and the
-grids p in {8, 16, 32, 64, 128, 192, 256, 384}, q in 0..4; size_label() picks a label
+turns a network output back into (k, p, q) with a 5 % rank margin and the
+grids p in {8, 16, 32, 48, 64, 96, 128, 160, 192, 256, 320, 384, 448, 512},
+q in 0..4; size_label() picks a label
 from a spectrum the method computed: the cheapest grid point whose kept
 values are converged, (s_{k+p}/s_k)^(4q+2) <= 1e-8, by the cost of the
-products with A, the panel QRs and the small SVD.
+products with A, the panel QRs and the small SVD (seconds, fitted to the
+library's measured times).
 
 Pins (tests/test_oracle_mlp.py): hand-worked standardization, decoding and
 labels; fourth-order finite-difference gradients
@@ -161,15 +163,16 @@ def pilot_features(A, seed, channel=0):
 
 
 # ---- sizing from the network and labels from computed spectra ---------------
-P_GRID = (8, 16, 32, 64, 128, 192, 256, 384)
+P_GRID = (8, 16, 32, 48, 64, 96, 128, 160, 192, 256, 320, 384, 448, 512)
 Q_MAX = 4
-RANK_MARGIN = 1.1
-# cost of a decomposition of width l in units of multiply-adds with A:
-# (2q+2) n^2 l products, QR_WEIGHT (2q+1) n l^2 panel QRs, SVD_WEIGHT l^3 the
-# small SVD (measured times of one QR and of the small SVD relative to one
-# product with A at 16384^2, l = 272)
-QR_WEIGHT = 11.4
-SVD_WEIGHT = 5000.0
+RANK_MARGIN = 1.05
+# cost of a decomposition of width l, in seconds fitted to the library's
+# measured times: 2q + 2 products with A at 60 TFLOP/s and as many panel QRs
+# (2q + 1 in the power iteration, one of the projection) at
+# QR_SECONDS (l / 272)^1.6 each, plus the small SVD at SVD_SECONDS (l / 272)^1.6
+PRODUCT_FLOPS = 60e12
+QR_SECONDS = 0.44e-3
+SVD_SECONDS = 3.2e-3
 
 
 def targets(labels):
@@ -184,14 +187,14 @@ def targets(labels):
 
 
 def decode(y, mean, sd, n_cap):
-    """Network output y (3 values, standardized) -> (k, p, q): k with a 10 %
-    margin rounded up into 1..n_cap, p rounded up to the grid (384 beyond it),
-    q rounded up into 0..4."""
+    """Network output y (3 values, standardized) -> (k, p, q): k with a 5 %
+    margin rounded up into 1..n_cap, p rounded up to the grid (512 beyond it),
+    q rounded to nearest into 0..4."""
     raw = [float(y[i]) * float(sd[i]) + float(mean[i]) for i in range(3)]
     kk = math.ceil(RANK_MARGIN * 10.0 ** raw[0]) if raw[0] < 300 else math.inf
     k = int(min(max(kk, 1), n_cap))
     p = next((g for g in P_GRID if g >= raw[1]), P_GRID[-1])
-    q = int(min(max(math.ceil(raw[2] - 1e-9), 0), Q_MAX))
+    q = int(min(max(math.floor(raw[2] + 0.5), 0), Q_MAX))
     return k, p, q
 
 
@@ -215,7 +218,8 @@ def size_label(s, k, n, l_min=0):
                 if not r ** (4 * q + 2) <= 1e-8:
                     continue
             L = min(k + p, n)
-            cost = (2 * q + 2) * n * n * L + QR_WEIGHT * (2 * q + 1) * n * L * L + SVD_WEIGHT * L ** 3
+            w = (L / 272.0) ** 1.6
+            cost = (2 * q + 2) * (2.0 * n * n * L / PRODUCT_FLOPS + QR_SECONDS * w) + SVD_SECONDS * w
             if best is None or cost < best[0]:
                 best = (cost, p, q)
     return (k, best[1], best[2]) if best else (k, -1, -1)

@@ -724,12 +724,20 @@ def small_svd(R, max_sweeps=0):
     return s, Us, W, int(sw.item()), flags
 
 
-def pilot_features(A, seed, channel=0, work=None):
-    """16 FP32 features of the pilot sketch of A (see include/rsvd.h)."""
+def pilot_features(A, seed, channel=0, work=None, out=None):
+    """16 FP32 features of the pilot sketch of A (see include/rsvd.h), into
+    out (a contiguous device FP32 vector of 16, e.g. a row of a batch's
+    feature matrix) or a new tensor."""
     torch = _torch()
     _check_matrix(torch, A, "A")
     m, n = A.shape
-    feat = torch.empty(MLP_IN, dtype=torch.float32, device=A.device)
+    if out is None:
+        feat = torch.empty(MLP_IN, dtype=torch.float32, device=A.device)
+    else:
+        if (out.dtype != torch.float32 or out.numel() != MLP_IN or not out.is_contiguous()
+                or out.device != A.device):
+            raise RsvdError("out: a contiguous FP32 vector of 16 on the device of A")
+        feat = out
     L = lib()
     wb = L.rsvd_pilot_work_bytes(m, n)
     if work is None or work[2] < wb:

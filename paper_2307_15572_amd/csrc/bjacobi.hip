@@ -22,11 +22,11 @@ namespace rsvd {
 namespace {
 
 constexpr double kU = 1.1102230246251565e-16;
-// waves per workgroup: all of them load and multiply in the Gram and the
-// apply; the first four (256 threads, one per 2 x 2 block of the 32 x 32
-// rotation problem) run the inner rounds while the others wait at its barriers
-constexpr int kJacWaves = 8;
-constexpr int kJacThreads = 64 * kJacWaves;
+// Waves per workgroup (template W, 4 or 8): all of them load and multiply in
+// the Gram and the apply; the first four (256 threads, one per 2 x 2 block of
+// the 32 x 32 rotation problem) run the inner rounds while the others wait at
+// its barriers. Eight waves halve a pair's load time but fit one workgroup
+// per CU; four fit two, which matters when pairs outnumber the grid.
 
 // x mod m for 0 <= x < 2 m
 __device__ __forceinline__ int mod_once(int x, int m) { return x >= m ? x - m : x; }
@@ -71,6 +71,7 @@ __device__ __forceinline__ void jac_rot(double hpp, double hqq, double hpq, doub
 }
 
 // Returns true if the pair needed rotating. dsq: 32 doubles of LDS.
+template <int kJacWaves>
 __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double (*Hb)[32][33],
                              double (*Vb)[32][33], double* red, double* dsq, int* s_any) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
@@ -82,7 +83,7 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
 
   // ---- Gram of the 32 rows (tiles 00, 01, 11), K split over the 4 waves;
   // GB column tiles of a wave in flight together
-  constexpr int GB = 3;
+  constexpr int GB = kJacWaves == 8 ? 3 : 5;
   d4 h00 = {0, 0, 0, 0}, h01 = {0, 0, 0, 0}, h11 = {0, 0, 0, 0};
   for (int ct0 = wave; ct0 < nct; ct0 += kJacWaves * GB) {
     double xi[GB][4], xj[GB][4];
@@ -225,7 +226,7 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
     double* bI = base + (int64_t)16 * I * Lp;
     double* bJ = base + (int64_t)16 * J * Lp;
     // AB column tiles per iteration (their loads in flight together)
-    constexpr int AB = 3;
+    constexpr int AB = kJacWaves == 8 ? 3 : 5;
     for (int ct = wave; ct < nct; ct += kJacWaves * AB) {
       double b[AB][8];
 #pragma unroll
@@ -260,7 +261,8 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
   return true;
 }
 
-__global__ void __launch_bounds__(kJacThreads) bjacobi_kernel(JacArgs a) {
+template <int kJacWaves>
+__global__ void __launch_bounds__(64 * kJacWaves) bjacobi_kernel(JacArgs a) {
   __shared__ int s_bar_ok;
   __shared__ double Hb[2][32][33];
   __shared__ double Vb[2][32][33];
@@ -279,7 +281,7 @@ __global__ void __launch_bounds__(kJacThreads) bjacobi_kernel(JacArgs a) {
       for (int pr = blockIdx.x; pr < npairs; pr += gridDim.x) {
         int I, J;
         rr_pair_blk(nb, step, pr, I, J);
-        const bool rot = process_pair(a, I, J, tol, Hb, Vb, red, dsq, &s_any);
+        const bool rot = process_pair<kJacWaves>(a, I, J, tol, Hb, Vb, red, dsq, &s_any);
         if (rot && threadIdx.x == 0)
           __hip_atomic_fetch_add(&counters[sweep], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
@@ -349,20 +351,27 @@ rsvd_status block_jacobi(int64_t l, const double* R, double* M, double* P, int m
   a.st = st;
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess) return RSVD_EHIP;
-  int ncu = 0, per_cu = 0;
+  int ncu = 0, per8 = 0, per4 = 0;
   if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return RSVD_EHIP;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)bjacobi_kernel,
-                                                   kJacThreads, 0) !=
-      hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per8, (const void*)bjacobi_kernel<8>, 512, 0) !=
+          hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per4, (const void*)bjacobi_kernel<4>, 256, 0) !=
+          hipSuccess)
     return RSVD_EHIP;
-  int grid = (Lp / 16) / 2;
+  const int npairs = (Lp / 16) / 2;
   // grids of concurrent runs (share of them) must fit on the device together:
   // half of a fair share, so that grids of different kernels also fit
-  int cap = ncu * (per_cu > 0 ? per_cu : 1) / (share > 1 ? 2 * share : 1);
-  if (cap < 1) cap = 1;
-  if (grid > cap) grid = cap;
-  hipLaunchKernelGGL(bjacobi_kernel, dim3(grid), dim3(kJacThreads), 0, s, a);
+  auto cap_of = [&](int per_cu) {
+    int c = ncu * (per_cu > 0 ? per_cu : 1) / (share > 1 ? 2 * share : 1);
+    return c < 1 ? 1 : c;
+  };
+  const int cap8 = cap_of(per8), cap4 = cap_of(per4);
+  if (npairs <= cap8) {
+    hipLaunchKernelGGL(bjacobi_kernel<8>, dim3(npairs), dim3(512), 0, s, a);
+  } else {
+    hipLaunchKernelGGL(bjacobi_kernel<4>, dim3(npairs < cap4 ? npairs : cap4), dim3(256), 0, s, a);
+  }
   RSVD_LAUNCH_CHECK();
   return RSVD_OK;
 }

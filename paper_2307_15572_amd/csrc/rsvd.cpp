@@ -701,6 +701,13 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
                          int64_t inner) -> rsvd_status {
     const int prec = product < n_early - p.trailing_hp ? lowp : kPrecF64;
     product++;
+    const bool f32_panel_path = prec == kPrecF32 && !trans && pl.off_Xf;
+    if (f32_panel_path) {
+      // the panel rounded to FP32 once: the streaming kernel stages half the
+      // bytes of it and feeds the matrix cores without conversions
+      PhaseScope ph6(6, s);
+      RSVD_TRY(f32_panel(inner, l, X, ldx, w.at<float>(pl.off_Xf), s));
+    }
     PhaseScope ph(pl.bf16 && prec != kPrecF64 ? 8 : (prec == kPrecF32 ? 9 : 0), s);
     if (pl.bf16 && prec != kPrecF64) {
       // X (inner x l) -> XT planes, then the product from the planes
@@ -724,14 +731,9 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
         return transpose(l, rows_out, Ct, rows_out, out, l, s);
       }
     }
-    if (prec == kPrecF32 && !trans && pl.off_Xf) {
-      // the panel rounded to FP32 once: the streaming kernel stages half the
-      // bytes of it and feeds the matrix cores without conversions
-      float* Xf = w.at<float>(pl.off_Xf);
-      RSVD_TRY(f32_panel(inner, l, X, ldx, Xf, s));
+    if (f32_panel_path)
       return dgemm(false, rows_out, l, inner, 1.0, A, lda, X, ldx, 0.0, out, l, part,
-                   pl.part_doubles, s, 64, nullptr, prec, Xf, f32_panel_ld(l));
-    }
+                   pl.part_doubles, s, 64, nullptr, prec, w.at<float>(pl.off_Xf), f32_panel_ld(l));
     return dgemm(trans, rows_out, l, inner, 1.0, A, lda, X, ldx, 0.0, out, l, part,
                  pl.part_doubles, s, 64, nullptr, prec);
   };

@@ -5,20 +5,25 @@ The paper fixes R_SVD and the oversampling by hand (section "Randomized
 matrix decompositions"). For many independent channels with a threshold
 rank, the predictor maps 16 pilot-sketch features of a channel to the rank
 k, the oversampling p and the number of power steps q (rsvd_mlp_predict:
-de-standardization, 10 % rank margin, rounding to the grid, cap at the
-channel size), the decomposition runs with l = k + p and r probe columns,
-and the library's judge flags it (include/rsvd.h, posterior > 0):
+de-standardization, 5 % rank margin, rounding to the grid, cap at the
+channel size), the decomposition runs with l = k + p, r probe columns, and
+the rank cap at l - 16 (the predicted p sizes the basis; the judge, not the
+cap, guards the kept values), and the library's judge flags it
+(include/rsvd.h, posterior > 0):
 
-  * RANK_CAPPED: the threshold rule wanted more than l - p values;
+  * RANK_CAPPED: the threshold rule wanted more than l - 16 values;
   * POSTERIOR_FAIL: the posterior estimate of ||(I - QQ^T) A||_2 exceeds
     tau s_1, the adaptive finder's own stopping test;
   * UNCONVERGED: (s_l / s_k)^(4q + 2) > 1e-8, the kept values have not
     converged for these (p, q).
 
 A flagged run is replaced by the adaptive range finder (FP64), which is
-also the judge that produced the training labels: k* is its threshold rank
-and (p*, q*) the cheapest grid point whose kept values its own spectrum
-shows converged (rsvd_size_label, with the cost of the products, the panel
+also the judge that produced the training labels. Because the sizes are
+known before any decomposition starts, many channels run as one batch
+(decompose_batch); the adaptive finder decides its width block by block and
+runs channel after channel. Labels: k* is the finder's threshold rank and
+(p*, q*) the cheapest grid point whose kept values its own spectrum shows
+converged (rsvd_size_label, with the cost of the products, the panel
 QRs and the small SVD). Every computation runs in the library's kernels;
 this module moves integers and flags between the calls.
 """
@@ -26,6 +31,7 @@ this module moves integers and flags between the calls.
 from dataclasses import dataclass
 
 POSTERIOR_COLUMNS = 16
+RUN_P = 16        # the rank cap of a sized run sits at l - RUN_P
 LABEL_Q = 2      # power steps of the labelling runs (accurate spectra)
 LABEL_BLOCK = 32  # their growth step: the stopping width within 32 columns
 
@@ -90,7 +96,8 @@ def decompose(A, net, tau, seed, channel, symmetric=False, block=64, q_fallback=
     m, n = A.shape
     f, pilot_work = pilot_features(A, seed=seed, channel=channel, work=pilot_work)
     (k, p, q), = net.predict(f.view(1, -1), [min(m, n)])
-    out = run(A, k, p, q, seed=seed, channel=channel, symmetric=symmetric,
+    l = min(k + p, min(m, n))
+    out = run(A, max(l - RUN_P, 1), RUN_P, q, seed=seed, channel=channel, symmetric=symmetric,
               rank_mode="rel_threshold", rank_param=tau, want_u=False, want_v=False,
               want_residual=False, precision=precision, trailing_hp=1,
               posterior=POSTERIOR_COLUMNS)
@@ -101,6 +108,55 @@ def decompose(A, net, tau, seed, channel, symmetric=False, block=64, q_fallback=
     ad = run_adaptive(A, tau, seed, channel, symmetric=symmetric, block=block, q=q_fallback)
     passes += adaptive_passes(ad.blocks, q_fallback, ad.l, min(m, n))
     return ChannelOutcome(ad.rank, ad.S, passes, True, (k, p, q), ", ".join(why)), pilot_work
+
+
+def decompose_batch(As, net, tau, seed, channels, symmetric=False, block=64, q_fallback=1,
+                    precision="fp64", lanes=8):
+    """Many channels at once: the pilot features of every channel into one
+    B x 16 matrix, one predictor call (one synchronization), then every
+    sized run in one batch (rsvd_batch_plan: the shapes are fixed before any
+    run starts, so the channels share lanes of streams), the judge's flags
+    read once, and the adaptive finder for the rejected channels. Returns a
+    list of ChannelOutcome in the order of As."""
+    import torch
+    from . import MLP_IN, BatchPlan, check_flags, pilot_features
+    if len(As) != len(channels):
+        raise ValueError("one channel id per matrix")
+    if not As:
+        return []
+    dev = As[0].device
+    F = torch.empty(len(As), MLP_IN, dtype=torch.float32, device=dev)
+    work = None
+    for c, (A, ch) in enumerate(zip(As, channels)):
+        _, work = pilot_features(A, seed=seed, channel=ch, work=work, out=F[c])
+    del work
+    kpq = net.predict(F, [min(A.shape) for A in As])
+    probs = []
+    for A, ch, (k, p, q) in zip(As, channels, kpq):
+        m, n = A.shape
+        l = min(k + p, min(m, n))
+        probs.append(dict(m=m, n=n, k=max(l - RUN_P, 1), p=RUN_P, q=q, symmetric=symmetric,
+                          seed=seed, channel=ch, rank_mode="rel_threshold", rank_param=tau,
+                          want_u=False, want_v=False, want_residual=False, precision=precision,
+                          trailing_hp=1, posterior=POSTERIOR_COLUMNS))
+    bp = BatchPlan(probs, lanes=lanes, use_graph=False)
+    bufs = bp.allocate(dev)
+    bp.run_into(list(As), bufs)
+    res = bp.results(bufs, check=False)
+    out = []
+    for c, (A, ch, (k, p, q), r) in enumerate(zip(As, channels, kpq, res)):
+        m, n = A.shape
+        passes = 1 + (2 * q + 2) + 1
+        why = rejected(r.flags)
+        if not why:
+            check_flags(r.flags, f"channel {ch}")
+            out.append(ChannelOutcome(int(r.rank), bufs["S"][c][: r.rank].clone(), passes, False,
+                                      (k, p, q), "accepted"))
+            continue
+        ad = run_adaptive(A, tau, seed, ch, symmetric=symmetric, block=block, q=q_fallback)
+        passes += adaptive_passes(ad.blocks, q_fallback, ad.l, min(m, n))
+        out.append(ChannelOutcome(ad.rank, ad.S, passes, True, (k, p, q), ", ".join(why)))
+    return out
 
 
 def train_predictor(features, labels, epochs=300, batch=128, lr=3e-3, seed=0, device="cuda"):

@@ -240,7 +240,8 @@ def test_learned_sizing_beats_adaptive_only():
     # train on channels labelled by the method itself (the adaptive FP64
     # finder's rank and spectrum), evaluate on others: every evaluated channel
     # ends with its exact threshold rank and accurate kept values, with fewer
-    # streams of A and less wall time than the adaptive finder alone
+    # streams of A than the adaptive finder alone, and, run as one batch
+    # (which the sizes known up front allow), in less wall time
     import paper_2307_15572_amd as rs
     from paper_2307_15572_amd import learned
     announce("learned sizing: 240 train channels (n ~ logU[1500, 4000]) / 60 eval (n ~ logU[600, 2500])")
@@ -271,9 +272,11 @@ def test_learned_sizing_beats_adaptive_only():
     assert loss < 0.6
     passes_l = passes_a = fell = 0
     t_l = t_a = 0.0
+    truth = {}
     for c, n, d, A in evals:
         k_true = min(n, 1 + int(np.floor(d * np.log(1.0 / tau))))
         sig = synth.spectrum_exp(n, d)
+        truth[c] = (k_true, sig)
         (out, work), dt = _timed(lambda: learned.decompose(A, net, tau, seed=seed, channel=c,
                                                             symmetric=True, pilot_work=work))
         t_l += dt
@@ -288,7 +291,19 @@ def test_learned_sizing_beats_adaptive_only():
         t_a += dt
         assert ad.rank == k_true
         passes_a += learned.adaptive_passes(ad.blocks, 1, ad.l, n)
-    print(f"[learned] passes {passes_l} vs adaptive {passes_a}, time {t_l:.3f} s vs {t_a:.3f} s, "
+    # the same channels as one batch: the sizes are known up front
+    outs, t_b = _timed(lambda: learned.decompose_batch([e[3] for e in evals], net, tau, seed,
+                                                       [e[0] for e in evals], symmetric=True))
+    passes_b = 0
+    for (c, n, d, A), out in zip(evals, outs):
+        k_true, sig = truth[c]
+        assert out.rank == k_true, (c, n, d, out.predicted, out.reason)
+        s = out.S.cpu().numpy()
+        assert np.max(np.abs(s - sig[: out.rank]) / sig[: out.rank]) <= 1e-6
+        passes_b += out.passes
+    print(f"[learned] passes {passes_l} (batched {passes_b}) vs adaptive {passes_a}; time "
+          f"{t_l:.3f} s one by one, {t_b:.3f} s batched, adaptive {t_a:.3f} s; "
           f"fallbacks {fell}/{len(evals)}")
-    assert passes_l < passes_a
+    assert passes_l < passes_a and passes_b < passes_a
     assert fell <= len(evals) // 3
+    assert t_b < t_a

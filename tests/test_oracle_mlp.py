@@ -148,33 +148,33 @@ def test_targets_standardize_by_hand():
 
 
 def test_decode_by_hand():
-    # raw = (2.5, 20, 1.2): k = ceil(1.1 * 316.23) = 348, p -> 32, q -> 2
-    assert mlp.decode([0, 0, 0], [2.5, 20, 1.2], [1, 1, 1], 10**6) == (348, 32, 2)
-    # beyond the grid, negative q, capped k
+    # raw = (2.5, 20, 1.2): k = ceil(1.05 * 316.23) = 333, p -> 32, q -> 1 (nearest)
+    assert mlp.decode([0, 0, 0], [2.5, 20, 1.2], [1, 1, 1], 10**6) == (333, 32, 1)
+    assert mlp.decode([0, 0, 0], [2.5, 20, 1.7], [1, 1, 1], 10**6) == (333, 32, 2)
+    # on the grid, beyond the grid, negative q, capped k
     assert mlp.decode([0, 0, 0], [2.5, 200, -0.5], [1, 1, 1], 100) == (100, 256, 0)
-    assert mlp.decode([0, 0, 0], [2.5, 500, -0.5], [1, 1, 1], 100) == (100, 384, 0)
+    assert mlp.decode([0, 0, 0], [2.5, 500, -0.5], [1, 1, 1], 100) == (100, 512, 0)
+    assert mlp.decode([0, 0, 0], [2.5, 600, -0.5], [1, 1, 1], 100) == (100, 512, 0)
     # de-standardization: raw = (1 + 1, 20 - 12, 1 + 6) = (2, 8, 7): p exactly on the grid
     k, p, q = mlp.decode([1, -1, 2], [1, 20, 1], [1, 12, 3], 10**6)
-    assert k in (110, 111) and p == 8 and q == 4
+    assert k in (105, 106) and p == 8 and q == 4
 
 
 def test_size_label_by_hand():
     # s_i = 10^(-i/9): (s_{k+p-1}/s_{k-1})^(4q+2) = 10^(-p (4q+2) / 9) <= 1e-8
-    # needs p (4q+2) >= 72: q=0 p=64 (l=114), q=1 p=16 (l=66), q=2 p=8 (l=58).
-    # n = 10000: costs (2q+2) n^2 l + 11.4 (2q+1) n l^2 + 5000 l^3 are
-    # 3.2e10, 2.93e10, 3.6e10 -> q = 1, p = 16
+    # needs p (4q+2) >= 72: q=0 p=48 (l=98), q=1 p=16 (l=66), q=2 p=8 (l=58).
+    # cost (2q+2) (2 n^2 l / 60e12 + 0.44e-3 w) + 3.2e-3 w, w = (l/272)^1.6;
+    # n = 10000: 1.45e-3, 1.40e-3, 1.65e-3 -> q = 1, p = 16
     s = 10.0 ** (-np.arange(400) / 9.0)
     assert mlp.size_label(s, 50, 10000) == (50, 16, 1)
-    # n = 60: l = 66 would be exact (l = n = 60, cost 1.08e9) but q = 2, p = 8
-    # (l = 58, 9.88e8) is cheaper through the small SVD's l^3
-    assert mlp.size_label(s, 50, 60) == (50, 8, 2)
-    # a spectrum reaching only k + 10: converged at its last value (index 59)
-    # for q = 2 (10 * 10 / 9 >= 8), so every p >= 8 qualifies for q >= 2, and
-    # q = 1 with p = 16 cannot be checked beyond index 59 (9 * 6 / 9 < 8):
-    # the cheapest is q = 2, p = 8
+    # n = 60: p = 16 reaches n (exact, l = 60, q = 0: 3.6e-4) and beats the
+    # converged q = 2, p = 8 (l = 58: 4.9e-4)
+    assert mlp.size_label(s, 50, 60) == (50, 16, 0)
+    # a spectrum reaching only k + 10: q = 1 cannot be shown converged (its
+    # last value gives 10^(-6.7)); q = 2 with p = 8 is (10^(-8.9))
     assert mlp.size_label(s[:60], 50, 10000) == (50, 8, 2)
-    # coverage: the labelling run needed l >= 140 -> p >= 90 -> 128 (q = 0
-    # converges: 128 * 2 / 9 >= 8) beats p = 128 with q >= 1
-    assert mlp.size_label(s, 50, 10000, l_min=140) == (50, 128, 0)
+    # coverage: the labelling run needed l >= 140 -> p >= 90 -> 96, q = 0
+    # converges (96 * 2 / 9 >= 8) and is the cheapest
+    assert mlp.size_label(s, 50, 10000, l_min=140) == (50, 96, 0)
     # nothing converges and nothing reaches n
     assert mlp.size_label(np.ones(100), 50, 10000) == (50, -1, -1)
