@@ -220,8 +220,10 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
   }
   double (*Vm)[33] = V;
 
-  // ---- apply: rows <- V^T rows for M and P; each wave owns whole column tiles
-  for (int mat = 0; mat < 2; mat++) {
+  // ---- apply: rows <- V^T rows for M and P (P absent: values only); each
+  // wave owns whole column tiles
+  const int nmat = a.P ? 2 : 1;
+  for (int mat = 0; mat < nmat; mat++) {
     double* base = mat == 0 ? a.M : a.P;
     double* bI = base + (int64_t)16 * I * Lp;
     double* bJ = base + (int64_t)16 * J * Lp;
@@ -309,8 +311,8 @@ __global__ void __launch_bounds__(64 * kJacWaves) bjacobi_kernel(JacArgs a) {
   }
 }
 
-// M (Lp x Lp) <- R (l x l) zero padded; P <- identity on the leading l x l;
-// sweep counters and the grid barrier cleared.
+// M (Lp x Lp) <- R (l x l) zero padded; P (if present) <- identity on the
+// leading l x l; sweep counters and the grid barrier cleared.
 __global__ void __launch_bounds__(256) jac_init_kernel(int l, int Lp, const double* __restrict__ R,
                                                        double* __restrict__ M, double* __restrict__ P,
                                                        DevState* st) {
@@ -322,7 +324,7 @@ __global__ void __launch_bounds__(256) jac_init_kernel(int l, int Lp, const doub
   if (idx >= (int64_t)Lp * Lp) return;
   const int i = (int)(idx / Lp), c = (int)(idx % Lp);
   M[idx] = (i < l && c < l) ? R[(int64_t)i * l + c] : 0.0;
-  P[idx] = (i == c && i < l) ? 1.0 : 0.0;
+  if (P) P[idx] = (i == c && i < l) ? 1.0 : 0.0;
 }
 
 }  // namespace

@@ -120,14 +120,15 @@ rsvd_status copy_panel(int64_t rows, int64_t cols, const double* src, int64_t ld
                        int64_t ldd, int cond_shifted, DevState* st, hipStream_t s);
 // Block one-sided Jacobi (bjacobi.hip): M, P are Lp x Lp (Lp = jacobi_padded(l))
 // workspace buffers; M <- R zero padded, P <- I, then the rows of M are
-// orthogonalized and the rotations accumulated in P.
+// orthogonalized and the rotations accumulated in P (P null: not
+// accumulated, for runs that want the values only).
 int64_t jacobi_padded(int64_t l);
 // share > 1: at most 1/share of the device's co-resident workgroups (for
 // runs on concurrent streams, whose cooperative grids must fit together).
 rsvd_status block_jacobi(int64_t l, const double* R, double* M, double* P, int max_sweeps,
                          int inner_sweeps, DevState* st, hipStream_t s, int share = 1);
 // From converged M, P: s (decreasing), Us (l x kc), W (l x kc); scratch:
-// 2 l doubles.
+// 2 l doubles. kc = 0: the values only (P may then be null).
 rsvd_status svd_finish(int64_t l, int64_t kc, const double* M, const double* P, int64_t ld,
                        double* s, double* Us, double* W, double* scratch, DevState* st,
                        hipStream_t st_);

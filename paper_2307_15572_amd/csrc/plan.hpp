@@ -23,6 +23,10 @@ struct rsvd_plan_s {
   size_t off_Yorig = 0, off_tau = 0;
   // symmetric form: the l x l core B = Q^T A Q (then Q_B of its QR)
   int form = 0;
+  // singular vectors (or the residual, which needs them) requested: without
+  // them the small SVD does not accumulate its right rotations and the lift,
+  // the sign rule and the vector products are skipped
+  bool vectors = true;
   size_t off_Bs = 0;
   // a-posteriori judge: r probe columns (P_r, A P_r deflated, Q^T A P_r)
   int post_r = 0;

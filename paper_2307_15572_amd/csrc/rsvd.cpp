@@ -290,6 +290,7 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* worksp
   pl->adaptive = adaptive;
   pl->blk = blk;
   pl->form = p.form;
+  pl->vectors = p.want_u || p.want_v || p.want_residual;
   pl->post_r = p.posterior;
   const int64_t m = p.m, n = p.n, kc = pl->kc;
   const int64_t mx = m > n ? m : n;
@@ -443,10 +444,12 @@ rsvd_status small_svd_and_rank(const rsvd_plan_s& pl, const Ws& w, int64_t l, do
   }
   {
     PhaseScope ph(2, s);
-    RSVD_TRY(block_jacobi(l, Rt, w.at<double>(pl.off_M), w.at<double>(pl.off_P),
-                          p.max_sweeps > 0 ? p.max_sweeps : 30, 1, st, s, pl.coop_share));
+    // values only: no right rotations (P) and no vectors gathered
+    double* P = pl.vectors ? w.at<double>(pl.off_P) : nullptr;
+    RSVD_TRY(block_jacobi(l, Rt, w.at<double>(pl.off_M), P, p.max_sweeps > 0 ? p.max_sweeps : 30,
+                          1, st, s, pl.coop_share));
     // the Householder fallback's tau (2 l doubles) is free again: ordering scratch
-    RSVD_TRY(svd_finish(l, kcl, w.at<double>(pl.off_M), w.at<double>(pl.off_P), jacobi_padded(l),
+    RSVD_TRY(svd_finish(l, pl.vectors ? kcl : 0, w.at<double>(pl.off_M), P, jacobi_padded(l),
                         w.at<double>(pl.off_sig), w.at<double>(pl.off_Us), w.at<double>(pl.off_W),
                         w.at<double>(pl.off_tau), st, s));
   }
@@ -468,7 +471,7 @@ rsvd_status lift_and_finish(const rsvd_plan_s& pl, const Ws& w, const double* A,
   DevState* st = w.at<DevState>(pl.off_state);
   double* part = w.at<double>(pl.off_part);
   const double* sig = w.at<double>(pl.off_sig);
-  {
+  if (pl.vectors) {
     PhaseScope ph(3, s);
     RSVD_TRY(dgemm(false, m, kcl, l, 1.0, Q, ldq, w.at<double>(pl.off_Us), kcl, 0.0, o.U, o.ldu,
                    part, pl.part_doubles, s));
@@ -783,7 +786,7 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
     const int64_t kcl = pl.kc < l ? pl.kc : l;
     double* Wv = w.at<double>(pl.off_W);
     double* Rtmp = w.at<double>(pl.off_Rtmp);
-    {
+    if (pl.vectors) {
       PhaseScope ph(3, s);
       RSVD_TRY(dgemm(false, l, kcl, l, 1.0, Bs, l, Wv, kcl, 0.0, Rtmp, kcl, part, pl.part_doubles,
                      s));

@@ -121,6 +121,31 @@ def test_threshold_percent_frobtail_rules():
     assert out.rank == ref.rank
 
 
+@pytest.mark.parametrize("form", ["svd", "symmetric"])
+def test_values_only_equals_full_run(form):
+    # without vectors or residual the small SVD skips its right rotations and
+    # the lift is skipped: the values, the rank and the flags are unchanged
+    # (the rows of the Jacobi matrix never depend on the rotations kept
+    # beside them), bit for bit
+    import paper_2307_15572_amd as rs
+    n, d = 1400, 25.0
+    A = to_dev(synth.symmetric(n, synth.spectrum_exp(n, d), tag=502))
+    announce(f"values-only run vs full run, {form} form")
+    kw = dict(seed=12, symmetric=True, rank_mode="rel_threshold", rank_param=1e-6, form=form)
+    full = rs.run(A, 400, 48, 2, **kw)
+    vals = rs.run(A, 400, 48, 2, want_u=False, want_v=False, want_residual=False, **kw)
+    assert vals.rank == full.rank and vals.flags == full.flags
+    assert vals.sweeps == full.sweeps
+    assert np.array_equal(vals.S.cpu().numpy(), full.S.cpu().numpy())
+    ref = oracle_rsvd(synth.symmetric(n, synth.spectrum_exp(n, d), tag=502), 400, 48, 2, seed=12,
+                      symmetric=True, rank_mode="rel_threshold", rank_param=1e-6,
+                      want_residual=False) if form == "svd" else None
+    if ref is not None:
+        assert vals.rank == ref.rank
+        ok, worst = sigma_gate(vals.S.cpu().numpy(), ref.s)
+        assert ok, worst
+
+
 def test_oversampled_past_the_fp64_floor():
     # a steep spectrum sketched with much more than its numerical rank
     # (sigma_l / sigma_1 ~ 1e-14, q = 0): the unshifted Cholesky QR breaks
