@@ -266,13 +266,23 @@ const char* rsvd_strerror(rsvd_status s);
  *  - the channels of one lane run one after another in one workspace slice
  *    sized for the largest of them; the lanes run concurrently and join the
  *    caller's stream at the end;
+ *  - channels that want neither vectors nor the residual (values only) stop
+ *    after the QR of their projection; once the lanes have joined, one
+ *    launch runs the Jacobi sweeps of all of them (channels in lockstep
+ *    rounds, widest first, their pairs dealt over the whole device, one
+ *    rotation counter per channel and sweep deciding its convergence), and
+ *    the values, rank rule, judge and result record of each follow on the
+ *    caller's stream. Their Jacobi matrices and states stay in the
+ *    workspace between the phases (the workspace grows by about 8 Lp^2
+ *    bytes per such channel, Lp = l rounded up to an even multiple of 16);
  *  - with use_graph != 0 the whole fork / run / join sequence is captured
  *    into a hipGraph on the first call and replayed by later calls with the
  *    same pointers and leading dimensions (a call with other pointers
  *    captures again). If the runtime refuses the capture, the batch runs
  *    eagerly from then on (rsvd_batch_info reports it).
  * Each channel computes exactly what rsvd_run computes for its problem
- * (bitwise: the same kernels on the same data).
+ * (bitwise: the same kernels on the same data; the grouped sweeps apply each
+ * channel's pair steps with the single run's pair kernel in its order).
  */
 typedef struct rsvd_batch_s* rsvd_batch_t;
 

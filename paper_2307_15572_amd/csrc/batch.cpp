@@ -25,6 +25,13 @@ struct rsvd_batch_s {
   std::vector<std::vector<int64_t>> items;  // channels of each lane, in run order
   std::vector<size_t> lane_off, lane_bytes;
   size_t total = 0;
+  // values-only channels: small SVDs grouped into one launch (jacobi_batch)
+  std::vector<int64_t> deferred;          // channel ids, in table order
+  std::vector<rsvd::JacChan> table;       // their Jacobi matrices and states
+  std::vector<size_t> def_sig, def_scr;   // per deferred channel: values, ordering scratch
+  size_t off_bar = 0;                     // grid barrier of the grouped launch
+  int64_t first_round_pairs = 0;
+  rsvd::JacChan* dtable = nullptr;        // device copy of the table
   // device objects, created at the first run
   int device = -1;
   std::vector<hipStream_t> streams;
@@ -50,6 +57,8 @@ void release(rsvd_batch_s* b) {
   for (hipStream_t s : b->streams)
     if (s) (void)hipStreamDestroy(s);
   for (rsvd_plan_t p : b->plans) rsvd_destroy(p);
+  if (b->dtable) (void)hipFree(b->dtable);
+  b->dtable = nullptr;
   b->exec = nullptr;
   b->fork = nullptr;
   b->joins.clear();
@@ -71,6 +80,13 @@ rsvd_status ensure_device_objects(rsvd_batch_s* b) {
       return RSVD_EHIP;
   }
   if (hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess) return RSVD_EHIP;
+  if (!b->table.empty()) {
+    // the table holds workspace offsets, so one upload serves every run
+    const size_t bytes = b->table.size() * sizeof(rsvd::JacChan);
+    if (hipMalloc((void**)&b->dtable, bytes) != hipSuccess) return RSVD_EHIP;
+    if (hipMemcpy(b->dtable, b->table.data(), bytes, hipMemcpyHostToDevice) != hipSuccess)
+      return RSVD_EHIP;
+  }
   b->device = dev;
   return RSVD_OK;
 }
@@ -97,9 +113,22 @@ rsvd_status check_channel(const rsvd_plan_s& pl, const BatchArgs& a, int64_t c) 
   return RSVD_OK;
 }
 
+// Point the deferred channels' plans at their slots of this workspace (or
+// clear them: work == nullptr).
+void set_deferral(rsvd_batch_s* b, char* work) {
+  for (size_t i = 0; i < b->deferred.size(); i++) {
+    rsvd_plan_s& pl = *b->plans[b->deferred[i]];
+    pl.defer_M = work ? reinterpret_cast<double*>(work + b->table[i].M_off) : nullptr;
+    pl.defer_st = work ? reinterpret_cast<rsvd::DevState*>(work + b->table[i].st_off) : nullptr;
+  }
+}
+
 // Fork from `origin`, run every lane's channels (enqueued interleaved so all
-// lanes start early), join back into `origin`.
+// lanes start early), join back into `origin`. Values-only channels stop
+// before their small SVD; after the join their sweeps run in one grouped
+// launch and their results are finished on `origin`.
 rsvd_status enqueue_all(rsvd_batch_s* b, const BatchArgs& a, hipStream_t origin) {
+  set_deferral(b, a.work);
   if (hipEventRecord(b->fork, origin) != hipSuccess) return RSVD_EHIP;
   for (int i = 0; i < b->lanes; i++)
     if (b->streams[i] != origin && hipStreamWaitEvent(b->streams[i], b->fork, 0) != hipSuccess)
@@ -116,13 +145,26 @@ rsvd_status enqueue_all(rsvd_batch_s* b, const BatchArgs& a, hipStream_t origin)
                                pl.p.want_v ? a.V[c] : nullptr, pl.p.want_v ? a.ldv[c] : 0,
                                a.res + c, a.work + b->lane_off[i], b->lane_bytes[i],
                                (void*)b->streams[i]);
-      if (r != RSVD_OK) return r;
+      if (r != RSVD_OK && r != kStatusDeferred) return r;
     }
   }
   for (int i = 0; i < b->lanes; i++) {
     if (b->streams[i] == origin) continue;
     if (hipEventRecord(b->joins[i], b->streams[i]) != hipSuccess) return RSVD_EHIP;
     if (hipStreamWaitEvent(origin, b->joins[i], 0) != hipSuccess) return RSVD_EHIP;
+  }
+  if (b->deferred.empty()) return RSVD_OK;
+  rsvd_status r = rsvd::jacobi_batch(b->dtable, (int)b->deferred.size(), b->first_round_pairs,
+                                     a.work, reinterpret_cast<rsvd::GridBar*>(a.work + b->off_bar),
+                                     origin);
+  if (r != RSVD_OK) return r;
+  for (size_t i = 0; i < b->deferred.size(); i++) {
+    const int64_t c = b->deferred[i];
+    r = finish_deferred(*b->plans[c], reinterpret_cast<double*>(a.work + b->table[i].M_off),
+                        reinterpret_cast<rsvd::DevState*>(a.work + b->table[i].st_off),
+                        reinterpret_cast<double*>(a.work + b->def_sig[i]),
+                        reinterpret_cast<double*>(a.work + b->def_scr[i]), a.S[c], a.res + c, origin);
+    if (r != RSVD_OK) return r;
   }
   return RSVD_OK;
 }
@@ -227,6 +269,40 @@ rsvd_status rsvd_batch_plan(const rsvd_problem* probs, int64_t count, int32_t la
     b->lane_bytes[i] = need;
     at += round256(need);
   }
+  // values-only channels (no vectors, no residual): the small SVDs of all of
+  // them in one grouped launch, widest first; each keeps its Jacobi matrix,
+  // state, values and ordering scratch in the workspace between the phases
+  if (count > 1) {
+    std::vector<int64_t> dorder = order;  // widest Jacobi matrix first
+    std::stable_sort(dorder.begin(), dorder.end(),
+                     [&](int64_t x, int64_t y) { return b->plans[x]->l > b->plans[y]->l; });
+    for (int64_t c : dorder) {
+      const rsvd_plan_s& pl = *b->plans[c];
+      if (pl.vectors || pl.adaptive) continue;
+      if (b->deferred.size() >= rsvd::jacobi_batch_max_channels()) break;
+      const int64_t l = pl.l, Lp = rsvd::jacobi_padded(l);
+      rsvd::JacChan ch{};
+      ch.M_off = (int64_t)at;
+      at += round256((size_t)Lp * Lp * sizeof(double));
+      ch.st_off = (int64_t)at;
+      at += round256(sizeof(rsvd::DevState));
+      ch.l = (int)l;
+      ch.Lp = (int)Lp;
+      const int ms = pl.p.max_sweeps > 0 ? pl.p.max_sweeps : 30;
+      ch.max_sweeps = ms > 64 ? 64 : ms;
+      b->def_sig.push_back(at);
+      at += round256((size_t)l * sizeof(double));
+      b->def_scr.push_back(at);
+      at += round256((size_t)2 * l * sizeof(double));
+      b->table.push_back(ch);
+      b->deferred.push_back(c);
+      b->first_round_pairs += Lp / 32;
+    }
+    if (!b->deferred.empty()) {
+      b->off_bar = at;
+      at += round256(sizeof(rsvd::GridBar));
+    }
+  }
   b->total = at;
   *out = b;
   if (workspace_bytes) *workspace_bytes = b->total;
@@ -288,7 +364,9 @@ rsvd_status rsvd_batch_tune(rsvd_batch_t plan, const double* const* A, const int
     if (r != RSVD_OK) return r;
   }
   // channel by channel on the caller's stream, each in its lane's workspace;
-  // shapes already in the table are not timed again
+  // shapes already in the table are not timed again (whole runs: nothing is
+  // deferred to the grouped launch here)
+  set_deferral(b, nullptr);
   int tuned = 0;
   rsvd_status r = RSVD_OK;
   for (int64_t c = 0; c < b->count && r == RSVD_OK; c++) {

@@ -319,12 +319,108 @@ __global__ void __launch_bounds__(256) jac_init_kernel(int l, int Lp, const doub
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (blockIdx.x == 0) {
     if (threadIdx.x < 64) st->rot_count[threadIdx.x] = 0u;
+    if (threadIdx.x == 0) st->sweeps = -1;  // set when the sweeps end
     grid_barrier_reset(&st->bar);
   }
   if (idx >= (int64_t)Lp * Lp) return;
   const int i = (int)(idx / Lp), c = (int)(idx % Lp);
   M[idx] = (i < l && c < l) ? R[(int64_t)i * l + c] : 0.0;
   if (P) P[idx] = (i == c && i < l) ? 1.0 : 0.0;
+}
+
+// ---------------------------------------------------------------------------
+// The small SVDs of many independent channels in one launch. Every channel
+// sweeps with its own tournament (nb_c - 1 steps of nb_c / 2 pairs), and all
+// channels advance in lockstep global rounds: in round r channel c runs
+// step r mod (nb_c - 1) of its sweep r / (nb_c - 1), unless it has finished.
+// The pairs of all active channels form one task list, dealt to the
+// workgroups round-robin (the channel table is ordered by cost, longest
+// first), and one grid barrier separates the rounds. Per channel, the
+// rotation counter of each sweep (its phase counter) decides at the sweep's
+// end, identically in every workgroup, whether it has converged; workgroup 0
+// then records its sweep count and flags. process_pair is the single-run
+// kernel's pair step, so each channel's rows see exactly the rotations of
+// its single run. A channel left unfinished (barrier timed out) keeps
+// sweeps = -1 for the caller to flag.
+constexpr int kBatchJacMaxChannels = 4096;
+
+template <int kJacWaves>
+__global__ void __launch_bounds__(64 * kJacWaves)
+    bjacobi_batch_kernel(const JacChan* __restrict__ ch, int nch, char* __restrict__ work,
+                         GridBar* bar) {
+  __shared__ int s_bar_ok;
+  __shared__ double Hb[2][32][33];
+  __shared__ double Vb[2][32][33];
+  __shared__ double red[kJacWaves * 3 * 256];
+  __shared__ double dsq[32];
+  __shared__ int s_any;
+  __shared__ uint32_t done[kBatchJacMaxChannels / 32];
+  for (int i = threadIdx.x; i < kBatchJacMaxChannels / 32; i += blockDim.x) done[i] = 0u;
+  __syncthreads();
+  int remaining = nch;
+  for (int r = 0; remaining > 0; r++) {
+    // sweep ends: channels whose previous round closed a sweep
+    for (int c = 0; c < nch; c++) {
+      if (done[c >> 5] & (1u << (c & 31))) continue;
+      const int steps = ch[c].Lp / 16 - 1;
+      if (r == 0 || r % steps != 0) continue;
+      const int sw = r / steps;  // sweeps completed
+      DevState* st = reinterpret_cast<DevState*>(work + ch[c].st_off);
+      const uint32_t cnt =
+          __hip_atomic_load(&st->rot_count[sw - 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      const bool conv = cnt == 0u;
+      if (conv || sw >= ch[c].max_sweeps) {
+        __syncthreads();
+        if (threadIdx.x == 0) done[c >> 5] |= 1u << (c & 31);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+          st->sweeps = sw;
+          if (!conv)
+            __hip_atomic_fetch_or(&st->flags, (uint32_t)RSVD_FLAG_JACOBI_MAXSWEEP,
+                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        remaining--;
+      }
+    }
+    if (remaining == 0) break;
+    // this round's tasks: pair pr of every active channel, dealt round-robin
+    int64_t base = 0;
+    for (int c = 0; c < nch; c++) {
+      if (done[c >> 5] & (1u << (c & 31))) continue;
+      const int Lp = ch[c].Lp, nb = Lp / 16, npairs = nb / 2, steps = nb - 1;
+      const int step = r % steps, sw = r / steps;
+      int64_t t0 = base + (((int64_t)blockIdx.x - base) % gridDim.x + gridDim.x) % gridDim.x;
+      for (int64_t t = t0; t < base + npairs; t += gridDim.x) {
+        const int pr = (int)(t - base);
+        int I, J;
+        rr_pair_blk(nb, step, pr, I, J);
+        JacArgs a;
+        a.l = ch[c].l;
+        a.Lp = Lp;
+        a.max_sweeps = ch[c].max_sweeps;
+        a.inner_sweeps = 1;
+        a.M = reinterpret_cast<double*>(work + ch[c].M_off);
+        a.P = nullptr;
+        a.st = reinterpret_cast<DevState*>(work + ch[c].st_off);
+        const double tol = (double)a.l * kU;
+        const bool rot = process_pair<kJacWaves>(a, I, J, tol, Hb, Vb, red, dsq, &s_any);
+        if (rot && threadIdx.x == 0)
+          __hip_atomic_fetch_add(&a.st->rot_count[sw], 1u, __ATOMIC_RELAXED,
+                                 __HIP_MEMORY_SCOPE_AGENT);
+      }
+      base += npairs;
+    }
+    if (!grid_barrier(bar, &s_bar_ok)) return;
+  }
+}
+
+__global__ void jac_batch_reset_kernel(GridBar* bar) { grid_barrier_reset(bar); }
+
+// sweeps < 0: the batched sweeps never finished this channel
+__global__ void jac_check_done_kernel(DevState* st) {
+  if (threadIdx.x == 0 && st->sweeps < 0)
+    __hip_atomic_fetch_or(&st->flags, (uint32_t)RSVD_FLAG_SYNC_TIMEOUT, __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace
@@ -334,6 +430,44 @@ int64_t jacobi_padded(int64_t l) {
   if (nb & 1) nb++;
   if (nb < 2) nb = 2;
   return nb * 16;
+}
+
+rsvd_status jacobi_prepare(int64_t l, const double* R, double* M, DevState* st, hipStream_t s) {
+  const int Lp = (int)jacobi_padded(l);
+  const int64_t tot = (int64_t)Lp * Lp;
+  hipLaunchKernelGGL(jac_init_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, (int)l,
+                     Lp, R, M, (double*)nullptr, st);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+size_t jacobi_batch_max_channels() { return kBatchJacMaxChannels; }
+
+rsvd_status jacobi_batch(const JacChan* table, int nch, int64_t first_round_pairs, char* work,
+                         GridBar* bar, hipStream_t s) {
+  if (nch < 1) return RSVD_OK;
+  if (nch > kBatchJacMaxChannels) return RSVD_EINVAL;
+  int dev = 0, ncu = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)bjacobi_batch_kernel<8>, 512,
+                                                   0) != hipSuccess)
+    return RSVD_EHIP;
+  const int64_t cap = (int64_t)ncu * (per > 0 ? per : 1);
+  int64_t grid = first_round_pairs < cap ? first_round_pairs : cap;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(jac_batch_reset_kernel, dim3(1), dim3(256), 0, s, bar);
+  RSVD_LAUNCH_CHECK();
+  hipLaunchKernelGGL(bjacobi_batch_kernel<8>, dim3((unsigned)grid), dim3(512), 0, s, table, nch,
+                     work, bar);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
+}
+
+rsvd_status jacobi_check_done(DevState* st, hipStream_t s) {
+  hipLaunchKernelGGL(jac_check_done_kernel, dim3(1), dim3(64), 0, s, st);
+  RSVD_LAUNCH_CHECK();
+  return RSVD_OK;
 }
 
 rsvd_status block_jacobi(int64_t l, const double* R, double* M, double* P, int max_sweeps,

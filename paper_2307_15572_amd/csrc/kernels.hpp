@@ -123,6 +123,25 @@ rsvd_status copy_panel(int64_t rows, int64_t cols, const double* src, int64_t ld
 // orthogonalized and the rotations accumulated in P (P null: not
 // accumulated, for runs that want the values only).
 int64_t jacobi_padded(int64_t l);
+// Batched small SVDs (values only): one channel of the table, byte offsets
+// into the batch workspace of its Jacobi matrix (Lp x Lp, prepared by
+// jacobi_prepare) and of its device state.
+struct JacChan {
+  int64_t M_off, st_off;
+  int l, Lp, max_sweeps, pad;
+};
+// M <- R zero padded (Lp x Lp), the state's sweep counters cleared and its
+// sweep count unset (no rotations kept)
+rsvd_status jacobi_prepare(int64_t l, const double* R, double* M, DevState* st, hipStream_t s);
+size_t jacobi_batch_max_channels();
+// the sweeps of every channel of the (device) table in one launch, all
+// channels in lockstep rounds separated by the grid barrier bar (in device
+// memory, reset here); first_round_pairs: the pairs of all channels in the
+// first round (the grid is at most that and what the device holds at once)
+rsvd_status jacobi_batch(const JacChan* table, int nch, int64_t first_round_pairs, char* work,
+                         GridBar* bar, hipStream_t s);
+// a channel whose batched sweeps never finished is flagged SYNC_TIMEOUT
+rsvd_status jacobi_check_done(DevState* st, hipStream_t s);
 // share > 1: at most 1/share of the device's co-resident workgroups (for
 // runs on concurrent streams, whose cooperative grids must fit together).
 rsvd_status block_jacobi(int64_t l, const double* R, double* M, double* P, int max_sweeps,

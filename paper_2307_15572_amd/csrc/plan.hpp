@@ -28,6 +28,13 @@ struct rsvd_plan_s {
   // the sign rule and the vector products are skipped
   bool vectors = true;
   size_t off_Bs = 0;
+  // grouped small SVD (a batch's values-only channels): with defer_M set, a
+  // run stops after the QR of its projection, leaving the padded Jacobi
+  // matrix in defer_M and its device state in defer_st and returning
+  // kStatusDeferred; the batch runs the sweeps of all such channels in one
+  // launch (jacobi_batch) and then finish_deferred
+  double* defer_M = nullptr;
+  rsvd::DevState* defer_st = nullptr;
   // a-posteriori judge: r probe columns (P_r, A P_r deflated, Q^T A P_r)
   int post_r = 0;
   size_t off_Op = 0, off_Wp = 0, off_Cp = 0;
@@ -52,3 +59,13 @@ struct rsvd_plan_s {
   size_t part_doubles = 0;
   size_t total = 0;
 };
+
+// internal status of a run that deferred its small SVD to the batch (never
+// returned through the C ABI; within the range of the enumeration's values)
+constexpr rsvd_status kStatusDeferred = static_cast<rsvd_status>(7);
+
+// The rest of a deferred run once its sweeps are done: ordering of the
+// values (svd_finish on M), rank rule, values to S, the judge and the result
+// record, all on st; sig: l doubles, scratch: 2 l doubles.
+rsvd_status finish_deferred(const rsvd_plan_s& pl, double* M, rsvd::DevState* st, double* sig,
+                            double* scratch, double* S, rsvd_result* res_dev, hipStream_t s);

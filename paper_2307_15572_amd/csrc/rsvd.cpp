@@ -442,6 +442,14 @@ rsvd_status small_svd_and_rank(const rsvd_plan_s& pl, const Ws& w, int64_t l, do
     PhaseScope ph(1, s);
     RSVD_TRY(orth(pl, w, rows < 0 ? p.n : rows, l, Zc, Rt, s, true));
   }
+  if (pl.defer_M) {
+    // grouped small SVD: the Jacobi matrix and the state go to the batch
+    RSVD_TRY(jacobi_prepare(l, Rt, pl.defer_M, st, s));
+    if (hipMemcpyAsync(pl.defer_st, st, sizeof(DevState), hipMemcpyDeviceToDevice, s) !=
+        hipSuccess)
+      return RSVD_EHIP;
+    return kStatusDeferred;
+  }
   {
     PhaseScope ph(2, s);
     // values only: no right rotations (P) and no vectors gathered
@@ -497,6 +505,29 @@ rsvd_status lift_and_finish(const rsvd_plan_s& pl, const Ws& w, const double* A,
   }
   return finalize(m, n, l, p.want_residual, err_est, blocks, st, res_dev, s);
 }
+
+}  // namespace
+
+rsvd_status finish_deferred(const rsvd_plan_s& pl, double* M, DevState* st, double* sig,
+                            double* scratch, double* S, rsvd_result* res_dev, hipStream_t s) {
+  const rsvd_problem& p = pl.p;
+  const int64_t m = p.m, n = p.n, l = pl.l;
+  const int64_t kcl = pl.kc < l ? pl.kc : l;
+  RSVD_TRY(jacobi_check_done(st, s));
+  RSVD_TRY(svd_finish(l, 0, M, nullptr, jacobi_padded(l), sig, nullptr, nullptr, scratch, st, s));
+  const int64_t p_cap = l == (m < n ? m : n) ? 0 : p.oversample;
+  RSVD_TRY(select_rank(l, p_cap, kcl, pl.mode, pl.param, sig, st, s));
+  if (hipMemcpyAsync(S, sig, (size_t)kcl * sizeof(double), hipMemcpyDeviceToDevice, s) !=
+      hipSuccess)
+    return RSVD_EHIP;
+  if (pl.post_r) {
+    RSVD_TRY(judge(l, m < n ? m : n, p.power_iters, pl.mode, pl.param, sig, st, s));
+    return finalize(m, n, l, 0, __builtin_nan(""), 0, st, res_dev, s, true);
+  }
+  return finalize(m, n, l, 0, __builtin_nan(""), 0, st, res_dev, s);
+}
+
+namespace {
 
 // The adaptive range finder (header: "Adaptive range finder").
 rsvd_status run_adaptive(const rsvd_plan_s& pl, const Ws& w, const double* A, int64_t lda,

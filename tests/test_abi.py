@@ -149,6 +149,31 @@ def test_batch_plan_lpt_and_workspace():
     assert bp.workspace_bytes == want
 
 
+def test_batch_plan_grouped_small_svd_workspace():
+    # values-only channels keep their padded Jacobi matrix (Lp x Lp), state,
+    # values and ordering scratch in the batch workspace between the phases
+    sizes = [300, 90, 500, 120]
+    kw = dict(want_u=False, want_v=False, want_residual=False)
+    vals = rs.BatchPlan(_batch_problems(sizes, **kw), lanes=2, use_graph=False)
+    lanes = vals.lanes_of()
+    single = [rs.Plan(n, n, min(20, n - 4), 4, 1, **kw).workspace_bytes for n in sizes]
+    lane_part = sum(-(-max(s for s, ln in zip(single, lanes) if ln == i) // 256) * 256
+                    for i in range(2))
+    pad = [-(-min(24, n) // 32) * 32 for n in sizes]  # jacobi_padded: even tile count
+    least = sum(-(-(L * L * 8) // 256) * 256 for L in pad)
+    extra = vals.workspace_bytes - lane_part
+    assert least <= extra <= least + 8192 * (len(sizes) + 1)
+    # with vectors nothing is grouped: the lane slices only
+    vecs = rs.BatchPlan(_batch_problems(sizes), lanes=2, use_graph=False)
+    single = [rs.Plan(n, n, min(20, n - 4), 4, 1).workspace_bytes for n in sizes]
+    assert vecs.workspace_bytes == sum(
+        -(-max(s for s, ln in zip(single, vecs.lanes_of()) if ln == i) // 256) * 256
+        for i in range(2))
+    # a single channel runs whole (nothing to group)
+    one = rs.BatchPlan(_batch_problems([300], **kw))
+    assert one.workspace_bytes == -(-rs.Plan(300, 300, 20, 4, 1, **kw).workspace_bytes // 256) * 256
+
+
 def test_batch_plan_validation():
     with pytest.raises(rs.RsvdError, match="invalid"):
         rs.BatchPlan([])

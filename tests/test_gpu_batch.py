@@ -111,3 +111,52 @@ def test_batch_mixed_precision_and_threshold_rule():
     bp.run_into(dev, bufs)
     res = bp.results(bufs)
     _check_against_single(bp, bufs, dev, probs, res)
+
+
+def test_grouped_small_svd_values_only_channels():
+    # values-only channels stop before their small SVD; one launch sweeps all
+    # of them (lockstep rounds, per-channel sweep counters) and each channel
+    # is finished afterwards. Every channel must equal its single run bitwise
+    # (values, rank, flags, sweep count), beside two channels that want
+    # vectors and run whole; graph replays with eager work between them
+    import torch
+    import paper_2307_15572_amd as rs
+    announce("batch of 14 channels: 12 values-only (grouped small SVD) + 2 with vectors")
+    mats, probs = _channels(14, 150, 1500, tag=604)
+    for c, pr in enumerate(probs):
+        pr.update(rank_mode="rel_threshold", rank_param=1e-6, k=min(pr["m"] - 40, 3 * pr["k"]),
+                  p=16, q=2)
+        if c not in (2, 9):
+            pr.update(want_u=False, want_v=False, want_residual=False)
+        if c == 4:
+            pr.update(posterior=16)
+        if c == 5:
+            pr.update(form="symmetric")
+        if c == 6:
+            pr.update(precision="mixed_fp32", trailing_hp=1)
+    dev = [to_dev(A) for A in mats]
+    bp = rs.BatchPlan(probs, lanes=4, use_graph=True)
+    bufs = bp.allocate("cuda:0")
+    singles = [_single(A, pr) for A, pr in zip(dev, probs)]
+    for rep in range(2):
+        for c in range(len(probs)):
+            bufs["S"][c].fill_(-1.0)
+        bp.run_into(dev, bufs)
+        res = bp.results(bufs)
+        x = torch.randn(256, 256, dtype=torch.float64, device="cuda:0")
+        (x @ x).sum().item()
+        for c, one in enumerate(singles):
+            r = res[c]
+            assert (r.rank, r.flags, r.sweeps) == (one.rank, one.flags, one.sweeps), (rep, c)
+            k = one.rank
+            assert np.array_equal(bufs["S"][c][:k].cpu().numpy(), one.S.cpu().numpy()), (rep, c)
+            if c in (2, 9):
+                assert np.array_equal(bufs["U"][c][:, :k].cpu().numpy(), one.U.cpu().numpy())
+                assert np.array_equal(bufs["V"][c][:, :k].cpu().numpy(), one.V.cpu().numpy())
+    for c in (0, 7):
+        pr = probs[c]
+        ref = oracle_rsvd(mats[c], pr["k"], pr["p"], pr["q"], seed=7, channel=c, symmetric=True,
+                          rank_mode="rel_threshold", rank_param=1e-6, want_residual=False)
+        assert res[c].rank == ref.rank
+        ok, worst = sigma_gate(bufs["S"][c][: res[c].rank].cpu().numpy(), ref.s)
+        assert ok, (c, worst)
