@@ -266,15 +266,16 @@ const char* rsvd_strerror(rsvd_status s);
  *  - the channels of one lane run one after another in one workspace slice
  *    sized for the largest of them; the lanes run concurrently and join the
  *    caller's stream at the end;
- *  - channels that want neither vectors nor the residual (values only) stop
- *    after the QR of their projection; once the lanes have joined, one
- *    launch runs the Jacobi sweeps of all of them (channels in lockstep
- *    rounds, widest first, their pairs dealt over the whole device, one
- *    rotation counter per channel and sweep deciding its convergence), and
- *    the values, rank rule, judge and result record of each follow on the
- *    caller's stream. Their Jacobi matrices and states stay in the
- *    workspace between the phases (the workspace grows by about 8 Lp^2
- *    bytes per such channel, Lp = l rounded up to an even multiple of 16);
+ *  - with count > 1 every channel stops after the QR of its projection;
+ *    once the lanes have joined, one launch runs the Jacobi sweeps of all
+ *    of them (channels in lockstep rounds, widest first, their pairs dealt
+ *    over the whole device, one rotation counter per channel and sweep
+ *    deciding its convergence), then each channel is finished: values-only
+ *    channels (no vectors, no residual) on the caller's stream from compact
+ *    slots (about 8 Lp^2 bytes each, Lp = l rounded up to an even multiple
+ *    of 16), the others on their lanes in a workspace slice of their own
+ *    (lift, signs, residual). Channels with vectors beyond 64 GiB of such
+ *    slices run whole in their lane's slice;
  *  - with use_graph != 0 the whole fork / run / join sequence is captured
  *    into a hipGraph on the first call and replayed by later calls with the
  *    same pointers and leading dimensions (a call with other pointers

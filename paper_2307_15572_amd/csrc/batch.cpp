@@ -25,10 +25,14 @@ struct rsvd_batch_s {
   std::vector<std::vector<int64_t>> items;  // channels of each lane, in run order
   std::vector<size_t> lane_off, lane_bytes;
   size_t total = 0;
-  // values-only channels: small SVDs grouped into one launch (jacobi_batch)
+  // small SVDs grouped into one launch (jacobi_batch): values-only channels
+  // keep their Jacobi matrix and state in compact slots; channels that want
+  // vectors run in a workspace slice of their own and are resumed there
   std::vector<int64_t> deferred;          // channel ids, in table order
   std::vector<rsvd::JacChan> table;       // their Jacobi matrices and states
   std::vector<size_t> def_sig, def_scr;   // per deferred channel: values, ordering scratch
+  std::vector<int> kind;                  // per channel: 0 whole, 1 compact, 2 own slice
+  std::vector<size_t> own_off, own_bytes; // per channel: its own slice (kind 2)
   size_t off_bar = 0;                     // grid barrier of the grouped launch
   int64_t first_round_pairs = 0;
   rsvd::JacChan* dtable = nullptr;        // device copy of the table
@@ -46,6 +50,10 @@ struct rsvd_batch_s {
 namespace {
 
 size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Workspace of the own slices of channels that want vectors and have their
+// small SVD grouped; channels beyond it run whole in their lane's slice.
+constexpr size_t kOwnSliceBudget = (size_t)64 << 30;
 
 void release(rsvd_batch_s* b) {
   for (hipStream_t s : b->streams)
@@ -117,10 +125,42 @@ rsvd_status check_channel(const rsvd_plan_s& pl, const BatchArgs& a, int64_t c) 
 // clear them: work == nullptr).
 void set_deferral(rsvd_batch_s* b, char* work) {
   for (size_t i = 0; i < b->deferred.size(); i++) {
-    rsvd_plan_s& pl = *b->plans[b->deferred[i]];
-    pl.defer_M = work ? reinterpret_cast<double*>(work + b->table[i].M_off) : nullptr;
-    pl.defer_st = work ? reinterpret_cast<rsvd::DevState*>(work + b->table[i].st_off) : nullptr;
+    const int64_t c = b->deferred[i];
+    rsvd_plan_s& pl = *b->plans[c];
+    const bool compact = b->kind[c] == 1;
+    pl.defer_M = work && compact ? reinterpret_cast<double*>(work + b->table[i].M_off) : nullptr;
+    pl.defer_st =
+        work && compact ? reinterpret_cast<rsvd::DevState*>(work + b->table[i].st_off) : nullptr;
+    pl.defer_inplace = work && !compact;
   }
+}
+
+// Workspace of channel c's run: its own slice, or its lane's.
+char* chan_work(const rsvd_batch_s* b, char* work, int64_t c, size_t* bytes) {
+  if (b->kind[c] == 2) {
+    *bytes = b->own_bytes[c];
+    return work + b->own_off[c];
+  }
+  const int i = b->lane_of[c];
+  *bytes = b->lane_bytes[i];
+  return work + b->lane_off[i];
+}
+
+rsvd_status fork(rsvd_batch_s* b, hipStream_t origin) {
+  if (hipEventRecord(b->fork, origin) != hipSuccess) return RSVD_EHIP;
+  for (int i = 0; i < b->lanes; i++)
+    if (b->streams[i] != origin && hipStreamWaitEvent(b->streams[i], b->fork, 0) != hipSuccess)
+      return RSVD_EHIP;
+  return RSVD_OK;
+}
+
+rsvd_status join(rsvd_batch_s* b, hipStream_t origin) {
+  for (int i = 0; i < b->lanes; i++) {
+    if (b->streams[i] == origin) continue;
+    if (hipEventRecord(b->joins[i], b->streams[i]) != hipSuccess) return RSVD_EHIP;
+    if (hipStreamWaitEvent(origin, b->joins[i], 0) != hipSuccess) return RSVD_EHIP;
+  }
+  return RSVD_OK;
 }
 
 // Fork from `origin`, run every lane's channels (enqueued interleaved so all
@@ -129,10 +169,8 @@ void set_deferral(rsvd_batch_s* b, char* work) {
 // launch and their results are finished on `origin`.
 rsvd_status enqueue_all(rsvd_batch_s* b, const BatchArgs& a, hipStream_t origin) {
   set_deferral(b, a.work);
-  if (hipEventRecord(b->fork, origin) != hipSuccess) return RSVD_EHIP;
-  for (int i = 0; i < b->lanes; i++)
-    if (b->streams[i] != origin && hipStreamWaitEvent(b->streams[i], b->fork, 0) != hipSuccess)
-      return RSVD_EHIP;
+  rsvd_status r = fork(b, origin);
+  if (r != RSVD_OK) return r;
   size_t longest = 0;
   for (const auto& it : b->items) longest = std::max(longest, it.size());
   for (size_t pos = 0; pos < longest; pos++) {
@@ -140,33 +178,50 @@ rsvd_status enqueue_all(rsvd_batch_s* b, const BatchArgs& a, hipStream_t origin)
       if (pos >= b->items[i].size()) continue;
       const int64_t c = b->items[i][pos];
       const rsvd_plan_s& pl = *b->plans[c];
-      rsvd_status r = rsvd_run(b->plans[c], a.A[c], a.lda[c], nullptr, 0, a.S[c],
-                               pl.p.want_u ? a.U[c] : nullptr, pl.p.want_u ? a.ldu[c] : 0,
-                               pl.p.want_v ? a.V[c] : nullptr, pl.p.want_v ? a.ldv[c] : 0,
-                               a.res + c, a.work + b->lane_off[i], b->lane_bytes[i],
-                               (void*)b->streams[i]);
+      size_t bytes = 0;
+      char* w = chan_work(b, a.work, c, &bytes);
+      r = rsvd_run(b->plans[c], a.A[c], a.lda[c], nullptr, 0, a.S[c],
+                   pl.p.want_u ? a.U[c] : nullptr, pl.p.want_u ? a.ldu[c] : 0,
+                   pl.p.want_v ? a.V[c] : nullptr, pl.p.want_v ? a.ldv[c] : 0, a.res + c, w, bytes,
+                   (void*)b->streams[i]);
       if (r != RSVD_OK && r != kStatusDeferred) return r;
     }
   }
-  for (int i = 0; i < b->lanes; i++) {
-    if (b->streams[i] == origin) continue;
-    if (hipEventRecord(b->joins[i], b->streams[i]) != hipSuccess) return RSVD_EHIP;
-    if (hipStreamWaitEvent(origin, b->joins[i], 0) != hipSuccess) return RSVD_EHIP;
-  }
+  if ((r = join(b, origin)) != RSVD_OK) return r;
   if (b->deferred.empty()) return RSVD_OK;
-  rsvd_status r = rsvd::jacobi_batch(b->dtable, (int)b->deferred.size(), b->first_round_pairs,
-                                     a.work, reinterpret_cast<rsvd::GridBar*>(a.work + b->off_bar),
-                                     origin);
+  // the sweeps of every deferred channel in one launch
+  r = rsvd::jacobi_batch(b->dtable, (int)b->deferred.size(), b->first_round_pairs, a.work,
+                         reinterpret_cast<rsvd::GridBar*>(a.work + b->off_bar), origin);
   if (r != RSVD_OK) return r;
+  // values-only channels: finished on the caller's stream
   for (size_t i = 0; i < b->deferred.size(); i++) {
     const int64_t c = b->deferred[i];
+    if (b->kind[c] != 1) continue;
     r = finish_deferred(*b->plans[c], reinterpret_cast<double*>(a.work + b->table[i].M_off),
                         reinterpret_cast<rsvd::DevState*>(a.work + b->table[i].st_off),
                         reinterpret_cast<double*>(a.work + b->def_sig[i]),
                         reinterpret_cast<double*>(a.work + b->def_scr[i]), a.S[c], a.res + c, origin);
     if (r != RSVD_OK) return r;
   }
-  return RSVD_OK;
+  // channels with vectors: resumed in their own slices on their lanes
+  bool any = false;
+  for (int64_t c : b->deferred) any = any || b->kind[c] == 2;
+  if (!any) return RSVD_OK;
+  if ((r = fork(b, origin)) != RSVD_OK) return r;
+  for (size_t pos = 0; pos < longest; pos++) {
+    for (int i = 0; i < b->lanes; i++) {
+      if (pos >= b->items[i].size()) continue;
+      const int64_t c = b->items[i][pos];
+      if (b->kind[c] != 2) continue;
+      const rsvd_plan_s& pl = *b->plans[c];
+      r = resume_deferred(pl, a.A[c], a.lda[c], a.S[c], pl.p.want_u ? a.U[c] : nullptr,
+                          pl.p.want_u ? a.ldu[c] : 0, pl.p.want_v ? a.V[c] : nullptr,
+                          pl.p.want_v ? a.ldv[c] : 0, a.res + c, a.work + b->own_off[c],
+                          b->streams[i]);
+      if (r != RSVD_OK) return r;
+    }
+  }
+  return join(b, origin);
 }
 
 std::vector<uintptr_t> make_key(const rsvd_batch_s* b, const BatchArgs& a) {
@@ -259,49 +314,81 @@ rsvd_status rsvd_batch_plan(const rsvd_problem* probs, int64_t count, int32_t la
     b->lane_of[c] = best;
     load[best] += cost[c];
   }
+  // grouped small SVD: values-only channels in compact slots (kind 1), the
+  // others in slices of their own within a budget (kind 2), widest first;
+  // a single channel runs whole
+  b->kind.assign((size_t)count, 0);
+  b->own_off.assign((size_t)count, 0);
+  b->own_bytes.assign((size_t)count, 0);
+  std::vector<int64_t> dorder = order;
+  std::stable_sort(dorder.begin(), dorder.end(),
+                   [&](int64_t x, int64_t y) { return b->plans[x]->l > b->plans[y]->l; });
+  if (count > 1) {
+    size_t own_total = 0;
+    for (int64_t c : dorder) {
+      const rsvd_plan_s& pl = *b->plans[c];
+      if (pl.adaptive) continue;
+      if (b->deferred.size() >= rsvd::jacobi_batch_max_channels()) break;
+      if (!pl.vectors) {
+        b->kind[c] = 1;
+      } else if (own_total + round256(ws[c]) <= kOwnSliceBudget) {
+        b->kind[c] = 2;
+        own_total += round256(ws[c]);
+      } else {
+        continue;
+      }
+      b->deferred.push_back(c);
+    }
+  }
+  // lane slices: for the channels that run in them (whole or compact)
   b->lane_off.assign((size_t)L, 0);
   b->lane_bytes.assign((size_t)L, 0);
   size_t at = 0;
   for (int i = 0; i < L; i++) {
     size_t need = 0;
-    for (int64_t c : b->items[i]) need = std::max(need, ws[c]);
+    for (int64_t c : b->items[i])
+      if (b->kind[c] != 2) need = std::max(need, ws[c]);
     b->lane_off[i] = at;
     b->lane_bytes[i] = need;
     at += round256(need);
   }
-  // values-only channels (no vectors, no residual): the small SVDs of all of
-  // them in one grouped launch, widest first; each keeps its Jacobi matrix,
-  // state, values and ordering scratch in the workspace between the phases
-  if (count > 1) {
-    std::vector<int64_t> dorder = order;  // widest Jacobi matrix first
-    std::stable_sort(dorder.begin(), dorder.end(),
-                     [&](int64_t x, int64_t y) { return b->plans[x]->l > b->plans[y]->l; });
-    for (int64_t c : dorder) {
-      const rsvd_plan_s& pl = *b->plans[c];
-      if (pl.vectors || pl.adaptive) continue;
-      if (b->deferred.size() >= rsvd::jacobi_batch_max_channels()) break;
-      const int64_t l = pl.l, Lp = rsvd::jacobi_padded(l);
-      rsvd::JacChan ch{};
+  for (int64_t c : b->deferred) {
+    if (b->kind[c] != 2) continue;
+    b->own_off[c] = at;
+    b->own_bytes[c] = ws[c];
+    at += round256(ws[c]);
+  }
+  for (int64_t c : b->deferred) {
+    const rsvd_plan_s& pl = *b->plans[c];
+    const int64_t l = pl.l, Lp = rsvd::jacobi_padded(l);
+    rsvd::JacChan ch{};
+    ch.l = (int)l;
+    ch.Lp = (int)Lp;
+    const int ms = pl.p.max_sweeps > 0 ? pl.p.max_sweeps : 30;
+    ch.max_sweeps = ms > 64 ? 64 : ms;
+    if (b->kind[c] == 1) {
       ch.M_off = (int64_t)at;
       at += round256((size_t)Lp * Lp * sizeof(double));
       ch.st_off = (int64_t)at;
       at += round256(sizeof(rsvd::DevState));
-      ch.l = (int)l;
-      ch.Lp = (int)Lp;
-      const int ms = pl.p.max_sweeps > 0 ? pl.p.max_sweeps : 30;
-      ch.max_sweeps = ms > 64 ? 64 : ms;
+      ch.P_off = -1;
       b->def_sig.push_back(at);
       at += round256((size_t)l * sizeof(double));
       b->def_scr.push_back(at);
       at += round256((size_t)2 * l * sizeof(double));
-      b->table.push_back(ch);
-      b->deferred.push_back(c);
-      b->first_round_pairs += Lp / 32;
+    } else {
+      ch.M_off = (int64_t)(b->own_off[c] + pl.off_M);
+      ch.st_off = (int64_t)(b->own_off[c] + pl.off_state);
+      ch.P_off = (int64_t)(b->own_off[c] + pl.off_P);
+      b->def_sig.push_back(0);
+      b->def_scr.push_back(0);
     }
-    if (!b->deferred.empty()) {
-      b->off_bar = at;
-      at += round256(sizeof(rsvd::GridBar));
-    }
+    b->table.push_back(ch);
+    b->first_round_pairs += Lp / 32;
+  }
+  if (!b->deferred.empty()) {
+    b->off_bar = at;
+    at += round256(sizeof(rsvd::GridBar));
   }
   b->total = at;
   *out = b;
@@ -363,7 +450,7 @@ rsvd_status rsvd_batch_tune(rsvd_batch_t plan, const double* const* A, const int
     const rsvd_status r = check_channel(*b->plans[c], a, c);
     if (r != RSVD_OK) return r;
   }
-  // channel by channel on the caller's stream, each in its lane's workspace;
+  // channel by channel on the caller's stream, each in its run's workspace;
   // shapes already in the table are not timed again (whole runs: nothing is
   // deferred to the grouped launch here)
   set_deferral(b, nullptr);
@@ -371,11 +458,12 @@ rsvd_status rsvd_batch_tune(rsvd_batch_t plan, const double* const* A, const int
   rsvd_status r = RSVD_OK;
   for (int64_t c = 0; c < b->count && r == RSVD_OK; c++) {
     const rsvd_plan_s& pl = *b->plans[c];
-    const int i = b->lane_of[c];
+    size_t bytes = 0;
+    char* w = chan_work(b, a.work, c, &bytes);
     const rsvd::TuneRun run{a.A[c], a.lda[c], nullptr, 0, a.S[c],
                             pl.p.want_u ? a.U[c] : nullptr, pl.p.want_u ? a.ldu[c] : 0,
                             pl.p.want_v ? a.V[c] : nullptr, pl.p.want_v ? a.ldv[c] : 0,
-                            a.res + c, a.work + b->lane_off[i], b->lane_bytes[i]};
+                            a.res + c, w, bytes};
     r = rsvd::tune_plan(b->plans[c], run, reps, (hipStream_t)stream, &tuned);
   }
   if (n_tuned) *n_tuned = tuned;

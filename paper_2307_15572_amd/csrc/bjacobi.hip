@@ -400,7 +400,7 @@ __global__ void __launch_bounds__(64 * kJacWaves)
         a.max_sweeps = ch[c].max_sweeps;
         a.inner_sweeps = 1;
         a.M = reinterpret_cast<double*>(work + ch[c].M_off);
-        a.P = nullptr;
+        a.P = ch[c].P_off >= 0 ? reinterpret_cast<double*>(work + ch[c].P_off) : nullptr;
         a.st = reinterpret_cast<DevState*>(work + ch[c].st_off);
         const double tol = (double)a.l * kU;
         const bool rot = process_pair<kJacWaves>(a, I, J, tol, Hb, Vb, red, dsq, &s_any);
@@ -432,11 +432,12 @@ int64_t jacobi_padded(int64_t l) {
   return nb * 16;
 }
 
-rsvd_status jacobi_prepare(int64_t l, const double* R, double* M, DevState* st, hipStream_t s) {
+rsvd_status jacobi_prepare(int64_t l, const double* R, double* M, double* P, DevState* st,
+                           hipStream_t s) {
   const int Lp = (int)jacobi_padded(l);
   const int64_t tot = (int64_t)Lp * Lp;
   hipLaunchKernelGGL(jac_init_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, (int)l,
-                     Lp, R, M, (double*)nullptr, st);
+                     Lp, R, M, P, st);
   RSVD_LAUNCH_CHECK();
   return RSVD_OK;
 }

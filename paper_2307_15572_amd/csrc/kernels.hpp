@@ -123,16 +123,17 @@ rsvd_status copy_panel(int64_t rows, int64_t cols, const double* src, int64_t ld
 // orthogonalized and the rotations accumulated in P (P null: not
 // accumulated, for runs that want the values only).
 int64_t jacobi_padded(int64_t l);
-// Batched small SVDs (values only): one channel of the table, byte offsets
-// into the batch workspace of its Jacobi matrix (Lp x Lp, prepared by
-// jacobi_prepare) and of its device state.
+// Batched small SVDs: one channel of the table, byte offsets into the batch
+// workspace of its Jacobi matrix (Lp x Lp, prepared by jacobi_prepare), of
+// its device state and of its rotations P (or -1).
 struct JacChan {
-  int64_t M_off, st_off;
+  int64_t M_off, st_off, P_off;  // P_off < 0: no rotations kept
   int l, Lp, max_sweeps, pad;
 };
-// M <- R zero padded (Lp x Lp), the state's sweep counters cleared and its
-// sweep count unset (no rotations kept)
-rsvd_status jacobi_prepare(int64_t l, const double* R, double* M, DevState* st, hipStream_t s);
+// M <- R zero padded (Lp x Lp), P <- I when given, the state's sweep
+// counters cleared and its sweep count unset
+rsvd_status jacobi_prepare(int64_t l, const double* R, double* M, double* P, DevState* st,
+                           hipStream_t s);
 size_t jacobi_batch_max_channels();
 // the sweeps of every channel of the (device) table in one launch, all
 // channels in lockstep rounds separated by the grid barrier bar (in device

@@ -35,6 +35,10 @@ struct rsvd_plan_s {
   // launch (jacobi_batch) and then finish_deferred
   double* defer_M = nullptr;
   rsvd::DevState* defer_st = nullptr;
+  // the same for a channel with its own workspace (vectors wanted): the run
+  // stops with the Jacobi matrix (and P) prepared in place and is resumed
+  // by resume_deferred in that workspace after the grouped sweeps
+  bool defer_inplace = false;
   // a-posteriori judge: r probe columns (P_r, A P_r deflated, Q^T A P_r)
   int post_r = 0;
   size_t off_Op = 0, off_Wp = 0, off_Cp = 0;
@@ -67,5 +71,11 @@ constexpr rsvd_status kStatusDeferred = static_cast<rsvd_status>(7);
 // The rest of a deferred run once its sweeps are done: ordering of the
 // values (svd_finish on M), rank rule, values to S, the judge and the result
 // record, all on st; sig: l doubles, scratch: 2 l doubles.
+// The rest of a run deferred in place, in its own workspace, once its sweeps
+// are done: ordering, rank rule, the symmetric form's W, lift, signs,
+// residual and result record (arguments as for rsvd_run).
+rsvd_status resume_deferred(const rsvd_plan_s& pl, const double* A, int64_t lda, double* S,
+                            double* U, int64_t ldu, double* V, int64_t ldv, rsvd_result* res_dev,
+                            void* work, hipStream_t s);
 rsvd_status finish_deferred(const rsvd_plan_s& pl, double* M, rsvd::DevState* st, double* sig,
                             double* scratch, double* S, rsvd_result* res_dev, hipStream_t s);

@@ -428,6 +428,26 @@ struct Outs {
   int64_t ldv;
 };
 
+// The rest of step 2 once the Jacobi sweeps are done: the values ordered
+// decreasingly (with the vectors when wanted), then the rank rule.
+rsvd_status small_svd_tail(const rsvd_plan_s& pl, const Ws& w, int64_t l, hipStream_t s) {
+  const rsvd_problem& p = pl.p;
+  DevState* st = w.at<DevState>(pl.off_state);
+  const int64_t kcl = pl.kc < l ? pl.kc : l;
+  {
+    PhaseScope ph(2, s);
+    double* P = pl.vectors ? w.at<double>(pl.off_P) : nullptr;
+    // the Householder fallback's tau (2 l doubles) is free again: ordering scratch
+    RSVD_TRY(svd_finish(l, pl.vectors ? kcl : 0, w.at<double>(pl.off_M), P, jacobi_padded(l),
+                        w.at<double>(pl.off_sig), w.at<double>(pl.off_Us), w.at<double>(pl.off_W),
+                        w.at<double>(pl.off_tau), st, s));
+  }
+  // the l - p cap protects unconverged trailing values; an exact SVD
+  // (l = min(m, n)) has none
+  const int64_t p_cap = l == (p.m < p.n ? p.m : p.n) ? 0 : p.oversample;
+  return select_rank(l, p_cap, kcl, pl.mode, pl.param, w.at<double>(pl.off_sig), st, s);
+}
+
 // Step 2 on a basis of width l whose transposed projection Y^T = A^T Q
 // (n x l, contiguous) is in Zc: Y^T = Q_B X_B (Zc <- Q_B), SVD of X_B^T by
 // one-sided Jacobi, singular values ordered decreasingly, then the rank rule.
@@ -442,9 +462,16 @@ rsvd_status small_svd_and_rank(const rsvd_plan_s& pl, const Ws& w, int64_t l, do
     PhaseScope ph(1, s);
     RSVD_TRY(orth(pl, w, rows < 0 ? p.n : rows, l, Zc, Rt, s, true));
   }
+  // values only: no right rotations (P) and no vectors gathered
+  double* P = pl.vectors ? w.at<double>(pl.off_P) : nullptr;
+  if (pl.defer_inplace) {
+    // grouped small SVD, the run resumed later in this workspace
+    RSVD_TRY(jacobi_prepare(l, Rt, w.at<double>(pl.off_M), P, st, s));
+    return kStatusDeferred;
+  }
   if (pl.defer_M) {
     // grouped small SVD: the Jacobi matrix and the state go to the batch
-    RSVD_TRY(jacobi_prepare(l, Rt, pl.defer_M, st, s));
+    RSVD_TRY(jacobi_prepare(l, Rt, pl.defer_M, nullptr, st, s));
     if (hipMemcpyAsync(pl.defer_st, st, sizeof(DevState), hipMemcpyDeviceToDevice, s) !=
         hipSuccess)
       return RSVD_EHIP;
@@ -452,19 +479,10 @@ rsvd_status small_svd_and_rank(const rsvd_plan_s& pl, const Ws& w, int64_t l, do
   }
   {
     PhaseScope ph(2, s);
-    // values only: no right rotations (P) and no vectors gathered
-    double* P = pl.vectors ? w.at<double>(pl.off_P) : nullptr;
     RSVD_TRY(block_jacobi(l, Rt, w.at<double>(pl.off_M), P, p.max_sweeps > 0 ? p.max_sweeps : 30,
                           1, st, s, pl.coop_share));
-    // the Householder fallback's tau (2 l doubles) is free again: ordering scratch
-    RSVD_TRY(svd_finish(l, pl.vectors ? kcl : 0, w.at<double>(pl.off_M), P, jacobi_padded(l),
-                        w.at<double>(pl.off_sig), w.at<double>(pl.off_Us), w.at<double>(pl.off_W),
-                        w.at<double>(pl.off_tau), st, s));
   }
-  // the l - p cap protects unconverged trailing values; an exact SVD
-  // (l = min(m, n)) has none
-  const int64_t p_cap = l == (p.m < p.n ? p.m : p.n) ? 0 : p.oversample;
-  return select_rank(l, p_cap, kcl, pl.mode, pl.param, w.at<double>(pl.off_sig), st, s);
+  return small_svd_tail(pl, w, l, s);
 }
 
 // Step 3 and the outputs: L = Q L_Y (Q: m x l, ldq), R = Q_B W (Q_B = Zc),
@@ -506,7 +524,52 @@ rsvd_status lift_and_finish(const rsvd_plan_s& pl, const Ws& w, const double* A,
   return finalize(m, n, l, p.want_residual, err_est, blocks, st, res_dev, s);
 }
 
+// Step 3 of a fixed-width run after its small SVD: for the symmetric form
+// first R_small = Q_b W; then L = Q L_Y, R = Q_B W and the outputs.
+rsvd_status run_tail(const rsvd_plan_s& pl, const Ws& w, const double* A, int64_t lda,
+                     const Outs& o, rsvd_result* res_dev, hipStream_t s) {
+  const int64_t l = pl.l;
+  double* Y = w.at<double>(pl.off_Y);
+  if (pl.form == RSVD_FORM_SYMMETRIC) {
+    const int64_t kcl = pl.kc < l ? pl.kc : l;
+    double* Wv = w.at<double>(pl.off_W);
+    double* Rtmp = w.at<double>(pl.off_Rtmp);
+    if (pl.vectors) {
+      PhaseScope ph(3, s);
+      RSVD_TRY(dgemm(false, l, kcl, l, 1.0, w.at<double>(pl.off_Bs), l, Wv, kcl, 0.0, Rtmp, kcl,
+                     w.at<double>(pl.off_part), pl.part_doubles, s));
+      RSVD_TRY(copy_panel(l, kcl, Rtmp, kcl, Wv, kcl, 0, w.at<DevState>(pl.off_state), s));
+    }
+    return lift_and_finish(pl, w, A, lda, l, Y, l, Y, o, __builtin_nan(""), 0, res_dev, s);
+  }
+  return lift_and_finish(pl, w, A, lda, l, Y, l, w.at<double>(pl.off_Z), o, __builtin_nan(""), 0,
+                         res_dev, s);
+}
+
+// Output buffers of a run: the caller's U / V, or workspace stand-ins.
+Outs make_outs(const rsvd_plan_s& pl, const Ws& w, double* S, double* U, int64_t ldu, double* V,
+               int64_t ldv) {
+  const rsvd_problem& p = pl.p;
+  Outs o;
+  o.S = S;
+  o.U = p.want_u ? U : w.at<double>(pl.off_Ub);
+  o.ldu = p.want_u ? ldu : pl.kc;
+  o.V = p.want_v ? V : w.at<double>(pl.off_Vb);
+  o.ldv = p.want_v ? ldv : pl.kc;
+  return o;
+}
+
 }  // namespace
+
+rsvd_status resume_deferred(const rsvd_plan_s& pl, const double* A, int64_t lda, double* S,
+                            double* U, int64_t ldu, double* V, int64_t ldv, rsvd_result* res_dev,
+                            void* work, hipStream_t s) {
+  Ws w{(char*)work};
+  const Outs o = make_outs(pl, w, S, U, ldu, V, ldv);
+  RSVD_TRY(jacobi_check_done(w.at<DevState>(pl.off_state), s));
+  RSVD_TRY(small_svd_tail(pl, w, pl.l, s));
+  return run_tail(pl, w, A, lda, o, res_dev, s);
+}
 
 rsvd_status finish_deferred(const rsvd_plan_s& pl, double* M, DevState* st, double* sig,
                             double* scratch, double* S, rsvd_result* res_dev, hipStream_t s) {
@@ -681,12 +744,7 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
   if (((uintptr_t)work & 255) != 0) return RSVD_EINVAL;
   hipStream_t s = (hipStream_t)stream;
   Ws w{(char*)work};
-  Outs o;
-  o.S = S;
-  o.U = p.want_u ? U : w.at<double>(pl.off_Ub);
-  o.ldu = p.want_u ? ldu : kc;
-  o.V = p.want_v ? V : w.at<double>(pl.off_Vb);
-  o.ldv = p.want_v ? ldv : kc;
+  const Outs o = make_outs(pl, w, S, U, ldu, V, ldv);
   if (pl.adaptive) return run_adaptive(pl, w, A, lda, o, res_dev, s);
 
   DevState* st = w.at<DevState>(pl.off_state);
@@ -814,22 +872,12 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
       RSVD_TRY(symmetrize(l, Bs, l, s));
     }
     RSVD_TRY(small_svd_and_rank(pl, w, l, Bs, s, l));
-    const int64_t kcl = pl.kc < l ? pl.kc : l;
-    double* Wv = w.at<double>(pl.off_W);
-    double* Rtmp = w.at<double>(pl.off_Rtmp);
-    if (pl.vectors) {
-      PhaseScope ph(3, s);
-      RSVD_TRY(dgemm(false, l, kcl, l, 1.0, Bs, l, Wv, kcl, 0.0, Rtmp, kcl, part, pl.part_doubles,
-                     s));
-      RSVD_TRY(copy_panel(l, kcl, Rtmp, kcl, Wv, kcl, 0, st, s));
-    }
-    return lift_and_finish(pl, w, A, lda, l, Y, l, Y, o, __builtin_nan(""), 0, res_dev, s);
+    return run_tail(pl, w, A, lda, o, res_dev, s);
   }
   // step 2: Y^T = A^T Q = Q_B X_B, small SVD of X_B^T, rank rule
   RSVD_TRY(stream_pass(!p.symmetric, Y, l, Z, n, m));
   RSVD_TRY(small_svd_and_rank(pl, w, l, Z, s));
-  // step 3: L = Q L_Y, R = Q_B W
-  return lift_and_finish(pl, w, A, lda, l, Y, l, Z, o, __builtin_nan(""), 0, res_dev, s);
+  return run_tail(pl, w, A, lda, o, res_dev, s);
 }
 
 #undef RSVD_TRY

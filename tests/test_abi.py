@@ -143,10 +143,11 @@ def test_batch_plan_lpt_and_workspace():
     load = [sum(c for c, ln in zip(cost, lanes) if ln == i) for i in range(3)]
     assert lanes[sizes.index(500)] == 0
     assert max(load) - min(load) <= max(cost)
-    # workspace: one slice per lane, sized for its largest channel
+    # workspace: channels that want vectors run in slices of their own (their
+    # small SVDs are grouped), plus the grouped launch's barrier block
     single = [rs.Plan(n, n, min(20, n - 4), 4, 1).workspace_bytes for n in sizes]
-    want = sum(-(-max(s for s, ln in zip(single, lanes) if ln == i) // 256) * 256 for i in range(3))
-    assert bp.workspace_bytes == want
+    own = sum(-(-w // 256) * 256 for w in single)
+    assert 0 < bp.workspace_bytes - own <= 4096
 
 
 def test_batch_plan_grouped_small_svd_workspace():
@@ -163,12 +164,12 @@ def test_batch_plan_grouped_small_svd_workspace():
     least = sum(-(-(L * L * 8) // 256) * 256 for L in pad)
     extra = vals.workspace_bytes - lane_part
     assert least <= extra <= least + 8192 * (len(sizes) + 1)
-    # with vectors nothing is grouped: the lane slices only
+    # channels that want vectors run in slices of their own (resumed there
+    # after the grouped sweeps): no lane slices, one barrier block
     vecs = rs.BatchPlan(_batch_problems(sizes), lanes=2, use_graph=False)
     single = [rs.Plan(n, n, min(20, n - 4), 4, 1).workspace_bytes for n in sizes]
-    assert vecs.workspace_bytes == sum(
-        -(-max(s for s, ln in zip(single, vecs.lanes_of()) if ln == i) // 256) * 256
-        for i in range(2))
+    own = sum(-(-w // 256) * 256 for w in single)
+    assert 0 < vecs.workspace_bytes - own <= 4096
     # a single channel runs whole (nothing to group)
     one = rs.BatchPlan(_batch_problems([300], **kw))
     assert one.workspace_bytes == -(-rs.Plan(300, 300, 20, 4, 1, **kw).workspace_bytes // 256) * 256
