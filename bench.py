@@ -479,6 +479,7 @@ def batch_leg(dev, net, reps=2):
     import numpy as np
     import torch
     import paper_2307_15572_amd as rs
+    from paper_2307_15572_amd import learned
     import synth
 
     t0 = time.perf_counter()
@@ -503,9 +504,12 @@ def batch_leg(dev, net, reps=2):
                                       ("mixed_fp32_sequential", "mixed_fp32", 1, False)):
         pp = []
         for pr, (k, p, q) in zip(probs, kpq):
+            # the learned path's sizing: l = k + p, rank cap at l - 16
             d = dict(pr)
             d.pop("d")
-            d.update(k=k, p=p, q=q, precision=prec, want_residual=False, posterior=16)
+            l = min(k + p, pr["m"])
+            d.update(k=max(l - learned.RUN_P, 1), p=learned.RUN_P, q=q, precision=prec,
+                     want_residual=False, posterior=learned.POSTERIOR_COLUMNS)
             pp.append(d)
         bp = rs.BatchPlan(pp, lanes=lanes, use_graph=graph)
         bufs = bp.allocate(dev)
@@ -536,8 +540,25 @@ def batch_leg(dev, net, reps=2):
                             "floor_ms": round(floor_s * 1e3, 2),
                             "frac": round(floor_s * 1e3 / ms, 4),
                             "product_tflops_per_s": round(flops / (ms * 1e-3) / 1e12, 3)}}
+        leg["judge_flags"] = {}
+        for c in flagged:
+            why = ", ".join(learned.rejected(res[c].flags))
+            leg["judge_flags"][why] = leg["judge_flags"].get(why, 0) + 1
         if prec == "fp64":
             s64 = S
+            # the rejected channels go to the adaptive finder (FP64), as the
+            # learned path does; timed on their own
+            torch.cuda.synchronize()
+            tt = time.perf_counter()
+            fixed = {c: learned.run_adaptive(mats[c], probs[c]["rank_param"], probs[c]["seed"],
+                                             probs[c]["channel"], symmetric=True)
+                     for c in flagged}
+            torch.cuda.synchronize()
+            leg["fallback_ms"] = round((time.perf_counter() - tt) * 1e3, 2)
+            final = [int(fixed[c].rank) if c in fixed else len(S[c]) for c in range(len(S))]
+            leg["ranks_equal_threshold_count_after_fallback"] = sum(
+                int(min(pr["m"], 1 + int(math.floor(pr["d"] * math.log(1e6)))) == k)
+                for pr, k in zip(probs, final))
         else:
             worst, worst_c, fails = 0.0, -1, 0
             for c, (a, b) in enumerate(zip(S, s64)):

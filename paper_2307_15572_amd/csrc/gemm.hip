@@ -370,8 +370,17 @@ __device__ __forceinline__ void wait_own_next(int wave, bool next_pending) {
   }
 }
 
-template <int NT, int WM, bool RES, int PREC, bool B_F32 = false>
+// TA: op(A) = A^T for A stored K x M row-major (lda >= M): C = A^T B with the
+// big matrix in its stored orientation. A wave's 16 x 16 tile of A^T for a
+// chunk is 16 rows of A (k) by 16 contiguous columns (the wave's 16 output
+// rows), 128 contiguous bytes per row of A: copy j = 64 h + lane brings
+// 16 bytes of row j / 8, columns 2 (j mod 8) .. + 1, and lands at element 2 j
+// of the wave's stage, so the stage holds the tile as [k][m] and a lane's 4
+// k values for its row r are 4 reads 16 doubles apart. Columns beyond M are
+// clamped (their outputs are never stored): M must be even.
+template <int NT, int WM, bool RES, int PREC, bool B_F32 = false, bool TA = false>
 __global__ void __launch_bounds__(64 * WM) dgemm_nn_dma_kernel(GemmArgs g) {
+  static_assert(!(TA && RES), "the residual epilogue reads A in the NN orientation");
   static_assert(!B_F32 || PREC == kPrecF32, "FP32 panels feed the FP32 matrix cores");
   using BT = typename std::conditional<B_F32, float, double>::type;
   constexpr int BN = NT * 16;
@@ -421,8 +430,12 @@ __global__ void __launch_bounds__(64 * WM) dgemm_nn_dma_kernel(GemmArgs g) {
   const int64_t col0 = (int64_t)tn * BN;
   const double* __restrict__ A = g.A;
   const BT* __restrict__ B = reinterpret_cast<const BT*>(g.B);
-  // source of this lane's A copies: row (clamped), k offset 4 gq + 2 h
-  const double* asrc = A + min(row0 + r, g.M - 1) * g.lda + kb + 4 * gq;
+  // source of this lane's A copies: NN: row (clamped), k offset 4 gq + 2 h;
+  // TA: rows kb + 8 h + lane / 8 of A, columns row0 + 2 (lane mod 8) (clamped)
+  const double* asrc = TA ? A + (kb + lane / 8) * g.lda + min(row0 + 2 * (lane & 7), g.M - 2)
+                          : A + min(row0 + r, g.M - 1) * g.lda + kb + 4 * gq;
+  const int64_t astep = TA ? (int64_t)kBK * g.lda : kBK;  // per chunk
+  const int64_t ahalf = TA ? (int64_t)8 * g.lda : 2;      // second copy of a chunk
 
   // per-lane copy sources, advanced by one chunk after every issue
   constexpr int NQ = (NBQ + WM - 1) / WM;
@@ -440,8 +453,8 @@ __global__ void __launch_bounds__(64 * WM) dgemm_nn_dma_kernel(GemmArgs g) {
   const int64_t bstep = (int64_t)kBK * g.ldb;
   auto issue = [&](double* As, BT* Bs) {
 #pragma unroll
-    for (int h = 0; h < 2; h++) copy_to_lds16(asrc + 2 * h, As + (wave * 2 + h) * 128);
-    asrc += kBK;
+    for (int h = 0; h < 2; h++) copy_to_lds16(asrc + ahalf * h, As + (wave * 2 + h) * 128);
+    asrc += astep;
 #pragma unroll
     for (int i = 0; i < NQ; i++) {
       if (wave + WM * i < NBQ) copy_to_lds16(bsrc[i], Bs + (wave + WM * i) * CPE);
@@ -458,9 +471,19 @@ __global__ void __launch_bounds__(64 * WM) dgemm_nn_dma_kernel(GemmArgs g) {
   // was released by the barrier)
   auto compute = [&](const double* As, const BT* Bs, double* As2, BT* Bs2, bool do_issue) {
     if (do_issue) issue(As2, Bs2);
-    const double2 a01 = *reinterpret_cast<const double2*>(As + (wave * 2 + 0) * 128 + 2 * lane);
-    const double2 a23 = *reinterpret_cast<const double2*>(As + (wave * 2 + 1) * 128 + 2 * lane);
-    const double av[4] = {a01.x, a01.y, a23.x, a23.y};
+    double av[4];
+    if constexpr (TA) {
+      const double* at = As + wave * 256 + 64 * gq + r;  // [k][m]: k = 4 gq + s, m = r
+#pragma unroll
+      for (int s4 = 0; s4 < 4; s4++) av[s4] = at[16 * s4];
+    } else {
+      const double2 a01 = *reinterpret_cast<const double2*>(As + (wave * 2 + 0) * 128 + 2 * lane);
+      const double2 a23 = *reinterpret_cast<const double2*>(As + (wave * 2 + 1) * 128 + 2 * lane);
+      av[0] = a01.x;
+      av[1] = a01.y;
+      av[2] = a23.x;
+      av[3] = a23.y;
+    }
     chunk_mma<PREC, NT, BN>(acc, av, Bs, gq, r);
   };
   auto step = [&](int c, double* As, BT* Bs, double* As2, BT* Bs2) {
@@ -573,10 +596,10 @@ hipError_t launch_nt_prec(int prec, int nt, dim3 grid, hipStream_t st, const Gem
   return launch_nt<TA, false, kPrecF64>(nt, grid, st, a);
 }
 
-template <int WM, bool RES, int PREC>
+template <int WM, bool RES, int PREC, bool TA = false>
 hipError_t launch_dma(int nt, dim3 grid, hipStream_t st, const GemmArgs& a) {
   switch (nt) {
-#define RSVD_DCASE(X) case X: hipLaunchKernelGGL((dgemm_nn_dma_kernel<X, WM, RES, PREC>), grid, dim3(64 * WM), 0, st, a); break;
+#define RSVD_DCASE(X) case X: hipLaunchKernelGGL((dgemm_nn_dma_kernel<X, WM, RES, PREC, false, TA>), grid, dim3(64 * WM), 0, st, a); break;
     RSVD_DCASE(1) RSVD_DCASE(2) RSVD_DCASE(3) RSVD_DCASE(4) RSVD_DCASE(5) RSVD_DCASE(6)
     RSVD_DCASE(7) RSVD_DCASE(8) RSVD_DCASE(9) RSVD_DCASE(10) RSVD_DCASE(11) RSVD_DCASE(12)
     RSVD_DCASE(13) RSVD_DCASE(14) RSVD_DCASE(15) RSVD_DCASE(16) RSVD_DCASE(17)
@@ -610,12 +633,12 @@ __global__ void __launch_bounds__(256) f32_panel_kernel(int64_t rows, int64_t co
   Xf[idx] = c < cols ? (float)X[r * ldx + c] : 0.0f;
 }
 
-template <int WM>
+template <int WM, bool TA = false>
 hipError_t launch_dma_prec(int prec, int nt, dim3 grid, hipStream_t st, const GemmArgs& a) {
-  if (prec == kPrecF32) return launch_dma<WM, false, kPrecF32>(nt, grid, st, a);
-  if (prec == kPrecBF16) return launch_dma<WM, false, kPrecBF16>(nt, grid, st, a);
-  if (prec == kPrecBF16S) return launch_dma<WM, false, kPrecBF16S>(nt, grid, st, a);
-  return launch_dma<WM, false, kPrecF64>(nt, grid, st, a);
+  if (prec == kPrecF32) return launch_dma<WM, false, kPrecF32, TA>(nt, grid, st, a);
+  if (prec == kPrecBF16) return launch_dma<WM, false, kPrecBF16, TA>(nt, grid, st, a);
+  if (prec == kPrecBF16S) return launch_dma<WM, false, kPrecBF16S, TA>(nt, grid, st, a);
+  return launch_dma<WM, false, kPrecF64, TA>(nt, grid, st, a);
 }
 
 }  // namespace
@@ -623,6 +646,16 @@ hipError_t launch_dma_prec(int prec, int nt, dim3 grid, hipStream_t st, const Ge
 void dgemm_set_dma(bool on, int waves) {
   g_use_dma = on;
   if (waves == 4 || waves == 8) g_dma_wm = waves;
+}
+
+bool dgemm_dma_eligible_t(int64_t M, int64_t K, int64_t N, const double* A, int64_t lda,
+                          const double* B, int64_t ldb) {
+  // A^T B with A (K x M) in its stored orientation: whole K chunks, even M
+  // and N, 16-byte aligned rows
+  const bool vec_a = (lda % 2 == 0) && ((uintptr_t)A % 16 == 0);
+  const bool vec_b = (ldb % 2 == 0) && ((uintptr_t)B % 16 == 0);
+  return (K % kBK == 0) && K > 0 && M >= 2 && (M % 2 == 0) && (N % 2 == 0) && N >= 2 && vec_a &&
+         vec_b && g_use_dma;
 }
 
 bool dgemm_dma_eligible(int64_t K, int64_t N, const double* A, int64_t lda, const double* B,
@@ -683,9 +716,27 @@ rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const 
   }
   const bool vec_a = (lda % 2 == 0) && ((uintptr_t)A % 16 == 0);
   const bool vec_b = (ldb % 2 == 0) && ((uintptr_t)B % 16 == 0);
-  const bool dma_ok = !ta && dgemm_dma_eligible(K, N, A, lda, B, ldb);
+  const bool dma_ok = ta ? dgemm_dma_eligible_t(M, K, N, A, lda, B, ldb)
+                        : dgemm_dma_eligible(K, N, A, lda, B, ldb);
+  const int64_t ktail = K % kBK;
+  if (!dma_ok && ktail != 0 && K > kBK && Bf == nullptr) {
+    // K not a whole number of chunks: the whole chunks on the streaming
+    // kernel (if it takes them), then the last K mod 16 terms added by the
+    // register-staged kernel
+    const int64_t K0 = K - ktail;
+    const bool main_ok = ta ? dgemm_dma_eligible_t(M, K0, N, A, lda, B, ldb)
+                            : dgemm_dma_eligible(K0, N, A, lda, B, ldb);
+    if (main_ok) {
+      rsvd_status r = dgemm(ta, M, N, K0, alpha, A, lda, B, ldb, beta, C, ldc, part, part_doubles,
+                            st, max_splits, pred, prec);
+      if (r != RSVD_OK) return r;
+      const double* At = ta ? A + K0 * lda : A + K0;
+      return dgemm(ta, M, N, ktail, alpha, At, lda, B + K0 * ldb, ldb, 1.0, C, ldc, part,
+                   part_doubles, st, max_splits, pred, prec);
+    }
+  }
   // the FP32 panel of B instead of B itself (FP32 schedule, streaming kernel)
-  const bool bf32 = dma_ok && Bf != nullptr && prec == kPrecF32 && ldbf >= N && ldbf % 4 == 0 &&
+  const bool bf32 = dma_ok && !ta && Bf != nullptr && prec == kPrecF32 && ldbf >= N && ldbf % 4 == 0 &&
                     ((uintptr_t)Bf % 16 == 0);
   const TuneKey tkey{dma_ok ? kTuneDma : kTuneGeneric, prec, ta ? 1 : 0, M, N, K};
   if (pred == nullptr && tune_recording()) {
@@ -763,6 +814,9 @@ rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const 
       d.ldb = ldbf;
       d.b_cols = ldbf;
       e = wm == 8 ? launch_dma_bf32<8>(s.nt, g2, st, d) : launch_dma_bf32<4>(s.nt, g2, st, d);
+    } else if (ta) {
+      e = wm == 8 ? launch_dma_prec<8, true>(prec, s.nt, g2, st, d)
+                  : launch_dma_prec<4, true>(prec, s.nt, g2, st, d);
     } else {
       e = wm == 8 ? launch_dma_prec<8>(prec, s.nt, g2, st, d)
                   : launch_dma_prec<4>(prec, s.nt, g2, st, d);

@@ -16,6 +16,10 @@ GemmShape dgemm_shape(int64_t M, int64_t N, int64_t K, int max_splits = 64);
 void dgemm_set_dma(bool on, int waves = 4);
 // whether an untransposed product of inner size K with N columns, A and B as
 // given, streams through the LDS-DMA kernel
+// whether A^T B with A (K x M) in its stored orientation streams through the
+// LDS-DMA kernel's transposed variant
+bool dgemm_dma_eligible_t(int64_t M, int64_t K, int64_t N, const double* A, int64_t lda,
+                          const double* B, int64_t ldb);
 bool dgemm_dma_eligible(int64_t K, int64_t N, const double* A, int64_t lda, const double* B,
                         int64_t ldb);
 // Bf (FP32 schedule only): the FP32 panel of B (ldbf floats per row, 16-byte

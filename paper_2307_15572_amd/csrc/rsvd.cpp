@@ -809,6 +809,12 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
                        trans ? pl.ld_at : pl.ld_an, XTh, XTl, out, l, fpart, pl.fpart_floats,
                        pl.bf16_split, s);
     }
+    if (trans && dgemm_dma_eligible_t(rows_out, inner - inner % 16, l, A, lda, X, ldx)) {
+      // A^T X on the streaming kernel's transposed variant (A in its stored
+      // orientation, no transposes of the panels)
+      return dgemm(true, rows_out, l, inner, 1.0, A, lda, X, ldx, 0.0, out, l, part,
+                   pl.part_doubles, s, 64, nullptr, prec);
+    }
     if (trans && rows_out * inner >= kTransStreamMin && l >= 16) {
       // A^T X = (X^T A)^T: the LDS-DMA streaming kernel takes X^T A with A
       // in its stored orientation, between two transposes of the skinny
@@ -1181,7 +1187,11 @@ rsvd_status rsvd_factor_transform(int64_t N, int64_t Nb, int64_t k, const double
   if (R) RSVD_TRY(copy_panel(N, k, R, ldr, X + k, K2, 0, nullptr, s));
   double* Xt = w.at<double>(lay.off_Xt);
   double* Ct = w.at<double>(lay.off_Ct);
-  if (N * Nb >= kTransStreamMin && K2 >= 16 && dgemm_dma_eligible(N, Nb, Xt, N, Ub, ldub)) {
+  if (dgemm_dma_eligible_t(Nb, N - N % 16, K2, Ub, ldub, X, K2)) {
+    // U^T X on the streaming kernel's transposed variant (U in its stored
+    // orientation)
+    RSVD_TRY(dgemm(true, Nb, K2, N, 1.0, Ub, ldub, X, K2, 0.0, O, K2, part, lay.part_doubles, s));
+  } else if (N * Nb >= kTransStreamMin && K2 >= 16 && dgemm_dma_eligible(N, Nb, Xt, N, Ub, ldub)) {
     // U^T X = (X^T U)^T: U streams in its stored orientation through the
     // LDS-DMA kernel between two transposes of the skinny panels
     RSVD_TRY(transpose(N, K2, X, K2, Xt, N, s));

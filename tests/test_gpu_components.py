@@ -29,6 +29,11 @@ GEMM_CASES = [
     (False, 64, 16, 16), (False, 1, 1, 1), (False, 130, 50, 77), (False, 517, 272, 1000),
     (False, 300, 528, 257), (False, 2048, 272, 8192), (False, 64, 300, 20000),
     (True, 50, 50, 512), (True, 272, 272, 16384), (True, 1000, 33, 999), (True, 40, 7, 3),
+    # A^T B on the LDS-DMA kernel with A in its stored orientation: ragged
+    # row tiles (columns of A clamped), the smallest even M, several column
+    # blocks, split K; odd M takes the register-staged kernel
+    (True, 130, 50, 4096), (True, 2, 20, 64), (True, 600, 600, 2048), (True, 3000, 528, 16384),
+    (True, 131, 40, 256),
 ]
 
 
