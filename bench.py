@@ -346,8 +346,8 @@ def tall_leg(dev, reps=2):
         if sc:
             leg["fp64_product"] = product_roofline(
                 "fp64", flops, sm / sc * 1e-3, PEAK_FP64_TFLOPS,
-                "FP64 streaming product (A X on the LDS-DMA kernel; A^T X as (X^T A)^T between "
-                "two panel transposes)", sc // reps)
+                "FP64 streaming product (A X and A^T X on the LDS-DMA kernel, A^T in its "
+                "stored orientation)", sc // reps)
         if prec == "fp64":
             ref = (S, r.residual)
             leg["max_rel_sigma_err_vs_constructed_first256"] = float(
