@@ -473,9 +473,11 @@ def learned_leg(dev):
 def batch_leg(dev, net, reps=2):
     """96 symmetric channels (n_c ~ logU[500, 12000], sigma_i = exp(-i/d_c),
     d_c ~ U[10, 80]), rank by the relative threshold 1e-6, each channel sized
-    from its pilot sketch by the learned predictor, the a-posteriori judge on
-    every channel; FP64 and the FP32 schedule through the batch planner (8
-    lanes, graph replay, tuned tiles), each channel's values against FP64."""
+    from its pilot sketch by the learned predictor (net None: by the
+    constructed spectrum), the a-posteriori judge on every channel and the
+    adaptive finder for the rejected ones; FP64 and the FP32 schedule through
+    the batch planner (8 lanes, graph replay, tuned tiles, grouped small SVDs),
+    each channel's values against FP64."""
     import numpy as np
     import torch
     import paper_2307_15572_amd as rs
@@ -487,16 +489,20 @@ def batch_leg(dev, net, reps=2):
     torch.cuda.synchronize()
     log(f"batch workload: {len(mats)} channels in {time.perf_counter() - t0:.1f} s")
     stream = torch.cuda.current_stream(dev)
-    # sizing: pilot features -> one batched prediction
+    # sizing: pilot features -> one batched prediction; without a predictor
+    # (the learned leg skipped) the constructed spectrum's (k, p, q)
     t0 = time.perf_counter()
-    feats, work = [], None
-    for pr, A in zip(probs, mats):
-        f, work = rs.pilot_features(A, seed=pr["seed"], channel=pr["channel"], work=work)
-        feats.append(f)
-    kpq = net.predict(torch.stack(feats).contiguous(), [pr["m"] for pr in probs])
+    if net is not None:
+        feats, work = [], None
+        for pr, A in zip(probs, mats):
+            f, work = rs.pilot_features(A, seed=pr["seed"], channel=pr["channel"], work=work)
+            feats.append(f)
+        kpq = net.predict(torch.stack(feats).contiguous(), [pr["m"] for pr in probs])
+        del work
+    else:
+        kpq = [(pr["k"], pr["p"], pr["q"]) for pr in probs]
     torch.cuda.synchronize()
     sizing_ms = (time.perf_counter() - t0) * 1e3
-    del work
     legs = {}
     s64 = None
     for name, prec, lanes, graph in (("fp64_8lanes_graph", "fp64", 8, True),
@@ -587,7 +593,8 @@ def batch_leg(dev, net, reps=2):
     torch.cuda.empty_cache()
     return {"workload": "c4_96_channels_threshold_1e-6", "channels": len(probs),
             "sum_n2": int(sum(p["m"] * p["n"] for p in probs)),
-            "sizing": "pilot features -> learned predictor (one batched call)",
+            "sizing": ("pilot features -> learned predictor (one batched call)" if net is not None
+                       else "constructed spectrum: k = threshold rank, p, q by the convergence factor"),
             "sizing_ms": round(sizing_ms, 2), "l_min_median_max": [ls[0], ls[len(ls) // 2], ls[-1]],
             "ranks_equal_threshold_count_of_construction": exact, "legs": legs}
 
@@ -685,6 +692,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the 2000-channel learned sizing leg (and the batch, sized by it)")
     ap.add_argument("--no-paper", action="store_true", help="skip the N = 40050 channel leg")
+    ap.add_argument("--only", choices=("batch", "tall", "paper"), default=None,
+                    help="profiling aid: run only this leg (the batch sized by the constructed "
+                         "spectrum) and print its record instead of the benchmark line")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -698,6 +708,11 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
+    if args.only:
+        leg = {"batch": lambda: batch_leg(dev, None), "tall": lambda: tall_leg(dev),
+               "paper": lambda: paper_leg(dev)}[args.only]()
+        print(json.dumps({"leg": args.only, **leg}), flush=True)
+        return
     log("generating workload")
     t0 = time.perf_counter()
     A_np, sigma, w = synth.c2(n=args.n, device=dev)
@@ -731,7 +746,7 @@ def main():
     if not args.no_learned:
         out["learned"], net = learned_leg(dev)
         torch.cuda.empty_cache()
-    if not args.no_batch and net is not None:
+    if not args.no_batch:
         out["batch"] = batch_leg(dev, net)
     if not args.no_tall:
         torch.cuda.empty_cache()
