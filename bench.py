@@ -57,8 +57,8 @@ GATE = 1e-6
 # FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0, what the counters read for a
 # plain 1 GiB copy kernel. Valid only for the GEMM source they were taken
 # with; any other source reports traffic as null.
-TRAFFIC_SOURCE_SHA256 = "bebc41b9251f06ab"
-TRAFFIC_KIB = {"fp64": (1119523.8, 69632.0), "fp32": (1117170.8, 69632.0)}
+TRAFFIC_SOURCE_SHA256 = "8a31146509f96bc8"
+TRAFFIC_KIB = {"fp64": (1135868.7, 69632.0), "fp32": (1108621.8, 69632.0)}
 
 
 def product_traffic(kind):
