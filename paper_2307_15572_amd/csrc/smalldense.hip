@@ -1791,8 +1791,10 @@ rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, double* scra
   }
   if (!scratch) return RSVD_EINVAL;
   {
-    // one 4-wave workgroup per ~32 tiles of the first trailing update, capped
-    // so the grids of concurrent runs fit on the device together
+    // one 4-wave workgroup per ~48 tiles of the first trailing update, at
+    // most 64 (measured at l = 528 .. 1541: more workgroups cost more in the
+    // two grid barriers per super-step than they save in the updates), and
+    // capped so the grids of concurrent runs fit on the device together
     static int cap_all = 0;
     if (cap_all == 0) {
       int dev = 0, ncu = 0, per_cu = 0;
@@ -1804,11 +1806,11 @@ rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, double* scra
       cap_all = ncu * (per_cu > 0 ? per_cu : 1);
     }
     const int64_t nb = (l + 15) / 16;
-    int grid = (int)((nb * (nb - 1) / 2 + 31) / 32);
+    int grid = (int)((nb * (nb - 1) / 2 + 47) / 48);
     // concurrent runs: half of a fair share, so that grids of different
     // kernels (different per-CU footprints) also fit together
     int cap = cap_all / (share > 1 ? 2 * share : 1);
-    if (cap > 128) cap = 128;
+    if (cap > 64) cap = 64;
     if (grid > cap) grid = cap;
     if (grid < 1) grid = 1;
     hipLaunchKernelGGL(chol_grid_kernel, dim3(grid), dim3(256), 0, s, (int)l, G, R, Rinv, scratch,
