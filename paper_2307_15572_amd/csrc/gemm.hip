@@ -142,7 +142,8 @@ struct GemmArgs {
   int64_t ldref;
   double* rpart;           // residual mode: per-workgroup partial sums [2][items]
   int vec_a, vec_b;        // 16-byte loads allowed (even leading dimension, aligned base)
-  int64_t b_cols;          // FP32 panel (B_F32 kernels): columns readable in each row of B
+  int64_t b_cols;          // columns readable in each row of B (0: N); set for FP32 panels
+                           // and for FP64 copies of B with an even leading dimension
 };
 
 template <bool TA, int NT, bool RES, int PREC>
@@ -458,7 +459,7 @@ __global__ void __launch_bounds__(64 * WM) dgemm_nn_dma_kernel(GemmArgs g) {
   constexpr int NQ = (NBQ + WM - 1) / WM;
   const BT* bsrc[NQ];
   // last column a copy may start at (columns past N are never stored)
-  const int64_t bmax = (B_F32 ? g.b_cols : g.N) - EPL;
+  const int64_t bmax = (g.b_cols ? g.b_cols : g.N) - EPL;
 #pragma unroll
   for (int i = 0; i < NQ; i++) {
     const int q = min(wave + WM * i, NBQ - 1);
@@ -719,7 +720,8 @@ rsvd_status f32_panel(int64_t rows, int64_t cols, const double* X, int64_t ldx, 
 rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                   int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                   double* part, size_t part_doubles, hipStream_t st, int max_splits,
-                  const uint32_t* pred, int prec, const float* Bf, int64_t ldbf) {
+                  const uint32_t* pred, int prec, const float* Bf, int64_t ldbf, const double* Bp,
+                  int64_t ldbp) {
   if (M <= 0 || N <= 0) return RSVD_OK;
   if (K <= 0) {
     // C = beta * C
@@ -733,28 +735,39 @@ rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const 
   }
   const bool vec_a = (lda % 2 == 0) && ((uintptr_t)A % 16 == 0);
   const bool vec_b = (ldb % 2 == 0) && ((uintptr_t)B % 16 == 0);
-  const bool dma_ok = ta ? dgemm_dma_eligible_t(M, K, N, A, lda, B, ldb)
-                        : dgemm_dma_eligible(K, N, A, lda, B, ldb);
+  // the panel the streaming kernel stages for A B: B itself (even N, even
+  // ldb), its FP32 panel (FP32 schedule), or its FP64 copy with an even
+  // leading dimension (odd N or ldb); with the copies it reads whole 16-byte
+  // pairs up to their row ends, and stores only the N columns
+  auto nn_stream = [&](int64_t k, bool* f32, bool* pad) {
+    *f32 = *pad = false;
+    if (ta || !(vec_a && k % kBK == 0 && k > 0 && g_use_dma)) return false;
+    *f32 = Bf != nullptr && prec == kPrecF32 && ldbf >= N && ldbf % 4 == 0 &&
+           ((uintptr_t)Bf % 16 == 0);
+    if (*f32) return true;
+    if (dgemm_dma_eligible(k, N, A, lda, B, ldb)) return true;
+    *pad = Bp != nullptr && ldbp % 2 == 0 && ldbp >= N + (N & 1) && ((uintptr_t)Bp % 16 == 0);
+    return *pad;
+  };
+  bool bf32 = false, bpad = false;
+  const bool dma_ok = ta ? dgemm_dma_eligible_t(M, K, N, A, lda, B, ldb) : nn_stream(K, &bf32, &bpad);
   const int64_t ktail = K % kBK;
-  if (!dma_ok && ktail != 0 && K > kBK && Bf == nullptr) {
+  if (!dma_ok && ktail != 0 && K > kBK) {
     // K not a whole number of chunks: the whole chunks on the streaming
     // kernel (if it takes them), then the last K mod 16 terms added by the
     // register-staged kernel
     const int64_t K0 = K - ktail;
-    const bool main_ok = ta ? dgemm_dma_eligible_t(M, K0, N, A, lda, B, ldb)
-                            : dgemm_dma_eligible(K0, N, A, lda, B, ldb);
+    bool f0 = false, p0 = false;
+    const bool main_ok = ta ? dgemm_dma_eligible_t(M, K0, N, A, lda, B, ldb) : nn_stream(K0, &f0, &p0);
     if (main_ok) {
       rsvd_status r = dgemm(ta, M, N, K0, alpha, A, lda, B, ldb, beta, C, ldc, part, part_doubles,
-                            st, max_splits, pred, prec);
+                            st, max_splits, pred, prec, Bf, ldbf, Bp, ldbp);
       if (r != RSVD_OK) return r;
       const double* At = ta ? A + K0 * lda : A + K0;
       return dgemm(ta, M, N, ktail, alpha, At, lda, B + K0 * ldb, ldb, 1.0, C, ldc, part,
                    part_doubles, st, max_splits, pred, prec);
     }
   }
-  // the FP32 panel of B instead of B itself (FP32 schedule, streaming kernel)
-  const bool bf32 = dma_ok && !ta && Bf != nullptr && prec == kPrecF32 && ldbf >= N && ldbf % 4 == 0 &&
-                    ((uintptr_t)Bf % 16 == 0);
   const TuneKey tkey{dma_ok ? kTuneDma : kTuneGeneric, prec, ta ? 1 : 0, M, N, K};
   if (pred == nullptr && tune_recording()) {
     // candidates: waves (LDS-DMA kernel) x split counts whose partials fit
@@ -767,7 +780,7 @@ rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const 
     }
     tune_record(tkey, std::move(cands), [=](hipStream_t s2) {
       return dgemm(ta, M, N, K, alpha, A, lda, B, ldb, beta, C, ldc, part, part_doubles, s2,
-                   max_splits, pred, prec, Bf, ldbf);
+                   max_splits, pred, prec, Bf, ldbf, Bp, ldbp);
     });
   }
   TuneCfg tcfg;
@@ -826,6 +839,11 @@ rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const 
     d.part = S > 1 ? part : nullptr;
     s.splits = S;
     const dim3 g2((unsigned)(T * S));
+    if (bpad) {
+      d.B = Bp;
+      d.ldb = ldbp;
+      d.b_cols = ldbp;
+    }
     if (bf32) {
       d.B = reinterpret_cast<const double*>(Bf);
       d.ldb = ldbf;

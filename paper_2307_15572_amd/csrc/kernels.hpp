@@ -24,12 +24,15 @@ bool dgemm_dma_eligible(int64_t K, int64_t N, const double* A, int64_t lda, cons
                         int64_t ldb);
 // Bf (FP32 schedule only): the FP32 panel of B (ldbf floats per row, 16-byte
 // aligned, ldbf a multiple of 4) that the streaming kernel reads instead of B
-// where it applies; B must still be given.
+// where it applies; B must still be given. Bp (A B only): a copy of B with an
+// even leading dimension ldbp >= N + (N & 1), 16-byte aligned, that the
+// streaming kernel stages when B itself does not fit it (odd N or ldb); its
+// padding column is read but never reaches C. B must still be given.
 rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const double* A,
                   int64_t lda, const double* B, int64_t ldb, double beta, double* C, int64_t ldc,
                   double* part, size_t part_doubles, hipStream_t st, int max_splits = 64,
                   const uint32_t* pred = nullptr, int prec = kPrecF64, const float* Bf = nullptr,
-                  int64_t ldbf = 0);
+                  int64_t ldbf = 0, const double* Bp = nullptr, int64_t ldbp = 0);
 // FP32 panel Xf (rows x f32_panel_ld(cols)) of X, rounded to nearest, zero padded
 int64_t f32_panel_ld(int64_t cols);
 rsvd_status f32_panel(int64_t rows, int64_t cols, const double* X, int64_t ldx, float* Xf,

@@ -60,6 +60,11 @@ struct rsvd_plan_s {
   size_t off_fpart = 0, fpart_floats = 0;
   // FP32 schedule: the FP32 panel of each low-precision product's operand
   size_t off_Xf = 0;
+  // odd sizes: a copy of A with an even leading dimension (odd n; made at
+  // the start of a run whose A has odd rows) and of each streamed FP64 panel
+  // (odd l), so that the products stream through the LDS-DMA kernel
+  size_t off_Apad = 0, off_Xp = 0;
+  int64_t ld_apad = 0, ld_xp = 0;
   size_t part_doubles = 0;
   size_t total = 0;
 };

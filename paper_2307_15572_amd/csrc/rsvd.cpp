@@ -92,6 +92,9 @@ int64_t percent_rank(double pct, int64_t m, int64_t n) {
 // m n from which a transposed streaming product A^T X runs as (X^T A)^T on the
 // LDS-DMA kernel (below it the two extra transposes and launches do not pay)
 constexpr int64_t kTransStreamMin = (int64_t)1 << 24;
+// matrices from this size on get even-leading-dimension copies of A and of
+// the streamed panels when their sizes are odd
+constexpr int64_t kPadMin = (int64_t)1 << 18;
 constexpr int kTransSplits = 8;
 
 // Split-K scratch needed by the products of one run.
@@ -302,6 +305,18 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* worksp
   pl->off_T = c.take((size_t)mx * l * D);
   pl->off_Yorig = c.take((size_t)mx * l * D);
   pl->off_tau = c.take((size_t)2 * l * D);
+  if (!adaptive && m * n >= kPadMin) {
+    // 16-byte rows for the streaming kernel (copies cost one pass over A per
+    // run, one over the panel per product)
+    if (n & 1) {
+      pl->ld_apad = n + 1;
+      pl->off_Apad = c.take((size_t)m * pl->ld_apad * D);
+    }
+    if (l & 1) {
+      pl->ld_xp = l + 1;
+      pl->off_Xp = c.take((size_t)mx * pl->ld_xp * D);
+    }
+  }
   pl->part_doubles = gemm_part_need(m, n, l);
   if (!p.symmetric && !adaptive && m * n >= kTransStreamMin) {
     // A^T X as (X^T A)^T: its l output rows make few tiles; room for up to
@@ -753,6 +768,14 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
   double* part = w.at<double>(pl.off_part);
   const int64_t mn = m < n ? m : n;
   RSVD_TRY(init_state(st, l == mn ? RSVD_FLAG_FULL_SVD : 0u, s));
+  if (pl.off_Apad && (lda % 2 != 0 || ((uintptr_t)A & 15) != 0)) {
+    // rows of A that the streaming kernel cannot copy whole: the run reads a
+    // copy with an even leading dimension instead
+    double* Ap = w.at<double>(pl.off_Apad);
+    RSVD_TRY(copy_panel(m, n, A, lda, Ap, pl.ld_apad, 0, st, s));
+    A = Ap;
+    lda = pl.ld_apad;
+  }
   if (pl.mode == RSVD_RANK_FROB_TAIL) {
     PhaseScope ph(6, s);
     RSVD_TRY(sumsq(m, n, A, lda, part, st, s));
@@ -832,6 +855,14 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
     if (f32_panel_path)
       return dgemm(false, rows_out, l, inner, 1.0, A, lda, X, ldx, 0.0, out, l, part,
                    pl.part_doubles, s, 64, nullptr, prec, w.at<float>(pl.off_Xf), f32_panel_ld(l));
+    if (!trans && prec == kPrecF64 && pl.off_Xp && (ldx % 2 != 0 || ((uintptr_t)X & 15) != 0)) {
+      // an odd-width panel staged through its copy with an even leading
+      // dimension (the padding column reaches no output)
+      double* Xp = w.at<double>(pl.off_Xp);
+      RSVD_TRY(copy_panel(inner, l, X, ldx, Xp, pl.ld_xp, 0, st, s));
+      return dgemm(false, rows_out, l, inner, 1.0, A, lda, X, ldx, 0.0, out, l, part,
+                   pl.part_doubles, s, 64, nullptr, prec, nullptr, 0, Xp, pl.ld_xp);
+    }
     return dgemm(trans, rows_out, l, inner, 1.0, A, lda, X, ldx, 0.0, out, l, part,
                  pl.part_doubles, s, 64, nullptr, prec);
   };

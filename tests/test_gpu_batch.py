@@ -160,3 +160,49 @@ def test_grouped_small_svd_values_only_channels():
         assert res[c].rank == ref.rank
         ok, worst = sigma_gate(bufs["S"][c][: res[c].rank].cpu().numpy(), ref.s)
         assert ok, (c, worst)
+
+
+def test_wide_and_shifted_channels_graph():
+    # panels wider than 272 (the multi-workgroup Cholesky, here with the
+    # batch's share of the device) and steep spectra (the shifted passes):
+    # every channel equals its single run bitwise (values, vectors, rank,
+    # flags, sweeps), over graph replays with eager work between them
+    import torch
+    import paper_2307_15572_amd as rs
+    announce("batch of 7 channels, l 120..704, graph replays")
+    spec = [(700, 320, 4.0), (1100, 400, 4.0), (1500, 560, 4.0), (2000, 704, 4.0),
+            (900, 200, 4.0), (1300, 480, 40.0), (600, 120, 40.0)]
+    mats, probs = [], []
+    for c, (n, l, r) in enumerate(spec):
+        A, _ = synth.channel(c, n, l / r, tag=605)
+        mats.append(A)
+        probs.append(dict(m=n, n=n, k=l - 16, p=16, q=1, symmetric=True, seed=9, channel=c))
+    probs[1].update(want_u=False, want_v=False, want_residual=False,
+                    rank_mode="rel_threshold", rank_param=1e-6)
+    probs[3].update(precision="mixed_fp32", trailing_hp=1)
+    probs[6].update(want_u=False, want_v=False, want_residual=False)
+    dev = [to_dev(A) for A in mats]
+    singles = [_single(A, pr) for A, pr in zip(dev, probs)]
+    bp = rs.BatchPlan(probs, lanes=4, use_graph=True)
+    bufs = bp.allocate("cuda:0")
+    for rep in range(2):
+        for c in range(len(probs)):
+            bufs["S"][c].fill_(-1.0)
+        bp.run_into(dev, bufs)
+        assert bp.graph_used()
+        res = bp.results(bufs)
+        x = torch.randn(256, 256, dtype=torch.float64, device="cuda:0")
+        (x @ x).sum().item()
+        for c, one in enumerate(singles):
+            r = res[c]
+            assert (r.rank, r.flags, r.sweeps) == (one.rank, one.flags, one.sweeps), (rep, c)
+            k = one.rank
+            assert np.array_equal(bufs["S"][c][:k].cpu().numpy(), one.S.cpu().numpy()), (rep, c)
+            if probs[c].get("want_u", True):
+                assert r.residual == one.residual, (rep, c)
+                assert np.array_equal(bufs["U"][c][:, :k].cpu().numpy(), one.U.cpu().numpy())
+                assert np.array_equal(bufs["V"][c][:, :k].cpu().numpy(), one.V.cpu().numpy())
+    pr = probs[2]
+    ref = oracle_rsvd(mats[2], pr["k"], pr["p"], pr["q"], seed=9, channel=2, symmetric=True)
+    ok, worst = sigma_gate(bufs["S"][2][: res[2].rank].cpu().numpy(), ref.s[: res[2].rank])
+    assert ok, worst

@@ -82,6 +82,30 @@ def test_general_shapes(m, n, k, p, q, decay):
     run_both(A, k, p, q, seed=m * n)
 
 
+@pytest.mark.parametrize("m,n,k,p,q,sym", [
+    (1001, 1001, 41, 8, 2, True),   # odd n and odd l: copies of A and of every panel
+    (1201, 777, 50, 13, 1, False),  # general with odd n and l
+    (1500, 1500, 63, 16, 2, True),  # even n, odd l: the panel copies alone
+])
+def test_odd_sizes_through_even_copies(m, n, k, p, q, sym):
+    # odd leading dimensions: the run streams an even-leading-dimension copy
+    # of A and of each odd-width panel through the LDS-DMA kernel
+    announce(f"pipeline odd sizes {m}x{n} k={k} p={p} q={q} symmetric={sym}")
+    sig = synth.spectrum_pow10(min(m, n), 1 / 40)
+    A = synth.symmetric(n, sig, tag=311 + n) if sym else synth.general(m, n, sig, tag=311 + n)
+    run_both(A, k, p, q, seed=m + n, symmetric=sym)
+
+
+@pytest.mark.parametrize("n,k,p", [(1025, 64, 16), (1500, 63, 16)])
+def test_mixed_fp32_odd_sizes(n, k, p):
+    # FP32 panels of odd width and an odd n (copy of A) in the FP32 schedule
+    announce(f"mixed fp32 symmetric {n} k={k} p={p}")
+    sig = synth.spectrum_pow10(n, 1 / 64)
+    A = synth.symmetric(n, sig, tag=331 + n, noise=1e-9)
+    rel, nrm, out, ref = _mixed_errors(A, k, p, 2, 17, True, "mixed_fp32", 1)
+    assert rel <= 1e-6, rel
+
+
 def test_symmetric_scaled_c2():
     n = 2048
     announce(f"pipeline symmetric {n} (C2 spectrum and noise)")
