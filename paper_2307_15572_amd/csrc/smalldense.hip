@@ -172,79 +172,6 @@ __device__ __forceinline__ void store_tile(const TileCtx& cx, double* W, int I, 
   }
 }
 
-// Upper Cholesky of one 16 x 16 tile held by a wave; returns false on a
-// non-positive or non-finite pivot (unless clamping). Tracks the pivot range
-// over rows below lmax.
-__device__ bool tile_chol(double t[4], bool clamp, double clampv, int row0, int lmax,
-                          double& dmax, double& dmin) {
-  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
-  bool ok = true;
-#pragma unroll
-  for (int j = 0; j < 16; j++) {
-    const int jg = j & 3, jt = j >> 2;
-    double piv = __shfl(t[jt], j + 16 * jg, 64);
-    if (clamp && !(piv > clampv)) piv = clampv;
-    if (!(piv > 0.0) || !isfinite(piv)) {
-      ok = false;
-      piv = 1.0;
-    }
-    // 1 / sqrt(piv) from the estimate and Newton steps (piv is the same in
-    // every lane, so the exact path for tiny pivots is a uniform branch)
-    double inv, rjj;
-    if (piv >= 1e-290) {
-      inv = rsq_nr(piv);
-      rjj = piv * inv;
-    } else {
-      rjj = sqrt(piv);
-      inv = 1.0 / rjj;
-    }
-    if (row0 + j < lmax) {
-      dmax = fmax(dmax, rjj);
-      dmin = fmin(dmin, rjj);
-    }
-    if (g == jg) {
-      if (r > j) t[jt] *= inv;
-      else if (r == j) t[jt] = rjj;
-    }
-    const double colv = __shfl(t[jt], r + 16 * jg, 64);
-#pragma unroll
-    for (int it = 0; it < 4; it++) {
-      const int i = g + 4 * it;
-      const double rowv = __shfl(t[jt], i + 16 * jg, 64);
-      if (i > j && r >= i) t[it] -= rowv * colv;
-    }
-  }
-#pragma unroll
-  for (int it = 0; it < 4; it++)
-    if (g + 4 * it > r) t[it] = 0.0;
-  return ok;
-}
-
-// Inverse of an upper-triangular tile held by a wave (same layout).
-__device__ void tile_inv_upper(const double t[4], double x[4]) {
-  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
-#pragma unroll
-  for (int it = 0; it < 4; it++) x[it] = 0.0;
-#pragma unroll
-  for (int i = 15; i >= 0; i--) {
-    const int ig = i & 3, ii = i >> 2;
-    const double rii = __shfl(t[ii], i + 16 * ig, 64);
-    double part = 0.0;
-#pragma unroll
-    for (int it = 0; it < 4; it++) {
-      const int tr = g + 4 * it;
-      const double rit = __shfl(t[ii], tr + 16 * ig, 64);
-      if (tr > i) part += rit * x[it];
-    }
-    part += __shfl_xor(part, 16, 64);
-    part += __shfl_xor(part, 32, 64);
-    // rii >= 2e-162: the square root of a positive double, or 1 for a
-    // failed pivot, so the reciprocal estimate is in range
-    const double ri = rcp_nr(rii);
-    if (g == ig) x[ii] = (r == i) ? ri : (r > i ? -part * ri : 0.0);
-  }
-}
-
 // Upper Cholesky of one tile held by a wave together with Z = R^{-T} (lower,
 // same layout): the row operations of the factorization (row j scaled by
 // 1 / r_jj, then row i > j less r_ji times row j) are L^{-1} for G = L L^T,
@@ -254,7 +181,9 @@ __device__ void tile_inv_upper(const double t[4], double x[4]) {
 // lane into scalar registers; row j of R and Z goes through the wave's own
 // 32 doubles of LDS (rowbuf), which every lane then reads by broadcast
 // (LDS operations of one wave complete in order, so no barrier is needed).
-// Same pivot handling and return value as tile_chol.
+// Returns false on a non-positive or non-finite pivot (unless clamping:
+// pivots at most clampv are raised to it); tracks the range of the diagonal
+// of R over rows below lmax.
 __device__ bool tile_chol_inv(d4& t, d4& z, double* rowbuf, bool clamp, double clampv, int row0,
                               int lmax, double& dmax, double& dmin) {
   // an opaque lane index: the lane masks below are formed here, not hoisted
@@ -701,40 +630,67 @@ __device__ __forceinline__ void note_pivots(bool ok, double dmax, double dmin, D
 
 // Factor the updated 32 x 32 diagonal block of super-step K held by one wave
 // (t00, t01, t11 in the accumulator layout): R_00, R_01, R_11 to W and the
-// inverses X_00, X_11 to Xg. The accumulator layout of each product is the
-// operand layout the next one needs (item s of lane (r, g) is entry
-// (g + 4 s, r)), so no transposition is required:
-//   R_01 = X_00^T t01;  t11 -= R_01^T R_01;  R_11 = chol(t11).
+// inverses X_00, X_11 to Xg. Each diagonal tile is factored together with
+// Z = R^{-T} (tile_chol_inv: the inverse costs a few FMAs per pivot instead
+// of a second 16-step substitution); Z holds X^T in the accumulator layout,
+// so X is stored transposed and turned into the operand layout of
+//   R_01 = X_00^T t01 (the accumulator layout of x00 is the operand it needs)
+// through the wave's 16 x 17 LDS tile zl (rowbuf: 32 doubles, the factor's
+// row broadcast). Then t11 -= R_01^T R_01 and R_11 = chol(t11).
 struct Tiles3 {
   double t00[4], t01[4], t11[4];
 };
 
-// Not inlined: its unrolled shuffles would otherwise share the register
+// X (entry (g + 4 it, r) of the accumulator layout) from Z = X^T held in
+// the same layout, through the wave's LDS tile.
+__device__ __forceinline__ void tile_transpose(const d4& z, double x[4], double* zl) {
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int it = 0; it < 4; it++) zl[(g + 4 * it) * 17 + r] = z[it];
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int it = 0; it < 4; it++) x[it] = zl[r * 17 + g + 4 * it];
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Store Z = X^T of diagonal tile k as X (entries beyond l are not stored).
+__device__ __forceinline__ void store_tile_t(const TileCtx& cx, double* W, int k, const d4& z) {
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int it = 0; it < 4; it++) {
+    const int i = 16 * k + r, c = 16 * k + g + 4 * it;
+    if (cx.in(i, c)) W[(int64_t)i * cx.l + c] = z[it];
+  }
+}
+
+// Not inlined: its unrolled chains would otherwise share the register
 // budget of the grid kernel's trailing loop (and spill it).
 __device__ __noinline__ void grid_block_factor(TileCtx cx, Tiles3 tb, int K, double* W, double* Xg,
-                                               bool clamp, double clampv, DevState* st) {
-  double* t00 = tb.t00;
-  double* t01 = tb.t01;
-  double* t11 = tb.t11;
+                                               bool clamp, double clampv, DevState* st,
+                                               double* lds) {
+  double* zl = lds;             // 16 x 17
+  double* rowbuf = lds + 272;   // 32
   const int i0 = 2 * K, i1 = 2 * K + 1;
-  double dmax = 0.0, dmin = INFINITY, x00[4], x11[4];
-  bool ok = tile_chol(t00, clamp, clampv, 16 * i0, cx.l, dmax, dmin);
-  tile_inv_upper(t00, x00);
+  double dmax = 0.0, dmin = INFINITY, x00[4];
+  d4 t0 = {tb.t00[0], tb.t00[1], tb.t00[2], tb.t00[3]}, z0;
+  bool ok = tile_chol_inv(t0, z0, rowbuf, clamp, clampv, 16 * i0, cx.l, dmax, dmin);
+  tile_transpose(z0, x00, zl);
   d4 acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-  for (int s4 = 0; s4 < 4; s4++) acc = mfma_f64_16x16x4(x00[s4], t01[s4], acc);
+  for (int s4 = 0; s4 < 4; s4++) acc = mfma_f64_16x16x4(x00[s4], tb.t01[s4], acc);
   double r01[4] = {acc[0], acc[1], acc[2], acc[3]};
-  d4 upd = {t11[0], t11[1], t11[2], t11[3]};
+  d4 upd = {tb.t11[0], tb.t11[1], tb.t11[2], tb.t11[3]};
 #pragma unroll
   for (int s4 = 0; s4 < 4; s4++) upd = mfma_f64_16x16x4(-r01[s4], r01[s4], upd);
-  double u11[4] = {upd[0], upd[1], upd[2], upd[3]};
-  ok = tile_chol(u11, clamp, clampv, 16 * i1, cx.l, dmax, dmin) && ok;
-  tile_inv_upper(u11, x11);
-  store_tile(cx, W, i0, i0, t00);
+  d4 z1;
+  ok = tile_chol_inv(upd, z1, rowbuf, clamp, clampv, 16 * i1, cx.l, dmax, dmin) && ok;
+  const double r00[4] = {t0[0], t0[1], t0[2], t0[3]};
+  const double r11[4] = {upd[0], upd[1], upd[2], upd[3]};
+  store_tile(cx, W, i0, i0, r00);
   store_tile(cx, W, i0, i1, r01);
-  store_tile(cx, W, i1, i1, u11);
-  store_tile(cx, Xg, i0, i0, x00);
-  store_tile(cx, Xg, i1, i1, x11);
+  store_tile(cx, W, i1, i1, r11);
+  store_tile_t(cx, Xg, i0, z0);
+  store_tile_t(cx, Xg, i1, z1);
   note_pivots(ok, dmax, dmin, st);
 }
 
@@ -761,6 +717,7 @@ __global__ void __launch_bounds__(256) chol_grid_kernel(int l, double* __restric
                                                          int pass, int only_if_shifted,
                                                          int full_inverse, DevState* st) {
   __shared__ double red[256 / 64];
+  __shared__ double flds[272 + 32];  // the factor wave's transpose tile and row buffer
   __shared__ int s_ok;
   if (only_if_shifted && st->qr_shifted == 0) return;
   const GridTeam tm{st, &s_ok};
@@ -804,7 +761,7 @@ __global__ void __launch_bounds__(256) chol_grid_kernel(int l, double* __restric
       load_tile(cx, R, 0, 0, tb.t00);
       load_tile(cx, R, 0, 1, tb.t01);
       load_tile(cx, R, 1, 1, tb.t11);
-      grid_block_factor(cx, tb, 0, R, Rinv, clamp, clampv, st);
+      grid_block_factor(cx, tb, 0, R, Rinv, clamp, clampv, st, flds);
     }
     if (!tm.sync()) return;
     bool failed = __hip_atomic_load(&st->chol_fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
@@ -862,7 +819,7 @@ __global__ void __launch_bounds__(256) chol_grid_kernel(int l, double* __restric
 #pragma unroll
             for (int it = 0; it < 4; it++) dst[q][it] = acc[it];
           }
-          grid_block_factor(cx, tb, K + 1, R, Rinv, clamp, clampv, st);
+          grid_block_factor(cx, tb, K + 1, R, Rinv, clamp, clampv, st, flds);
         }
         // every other wave: the remaining tiles, TB at a time so their L2
         // round trips overlap
