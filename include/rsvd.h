@@ -170,6 +170,12 @@ typedef struct rsvd_plan_s* rsvd_plan_t;
  * lanes; rsvd_run calls on one device are meant to be ordered (one stream,
  * or streams joined by events).
  *   workspace_bytes receives the device workspace size rsvd_run needs.
+ *                   For m n >= 2^18 it includes, when n is odd, room for a
+ *                   copy of A with an even leading dimension (made by runs
+ *                   whose lda is odd or whose A is not 16-byte aligned) and,
+ *                   when l is odd, for a copy of the streamed panel with an
+ *                   even leading dimension: the streaming products read
+ *                   16-byte rows.
  * Returns RSVD_EINVAL for m, n < 1, k < 1 (fixed rule), p < 0, q < 0,
  * R% outside (0, 100], tau outside (0, 1), an unknown mode, trailing_hp < 0,
  * or k_cap < the fixed rank, an unknown form, the symmetric form without
