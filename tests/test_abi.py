@@ -175,6 +175,23 @@ def test_batch_plan_grouped_small_svd_workspace():
     assert one.workspace_bytes == -(-rs.Plan(300, 300, 20, 4, 1, **kw).workspace_bytes // 256) * 256
 
 
+def test_plan_workspace_holds_even_copies_for_odd_sizes():
+    # m n >= 2^18: an odd n adds an m x (n + 1) copy of A, an odd l an
+    # max(m, n) x (l + 1) copy of the panel (FP64, 256-byte aligned regions)
+    def ws(m, n, k, p):
+        return rs.Plan(m, n, k, p, 1, want_residual=False).workspace_bytes
+    up = lambda b: -(-b // 256) * 256
+    # odd l alone: 1000 x 1000 with l = 49 against l = 48 (one more column of
+    # every l-sized region besides the copy)
+    base, odd_l = ws(1000, 1000, 32, 16), ws(1000, 1000, 33, 16)
+    assert odd_l - base >= up(1000 * 50 * 8)
+    # odd n: 1000 x 1001 against 1000 x 1000 holds the copy of A
+    assert ws(1000, 1001, 32, 16) - ws(1000, 1000, 32, 16) >= up(1000 * 1002 * 8)
+    # below 2^18 entries no copies
+    small_even, small_odd = ws(500, 500, 32, 16), ws(500, 501, 32, 16)
+    assert small_odd - small_even < 500 * 502 * 8
+
+
 def test_batch_plan_validation():
     with pytest.raises(rs.RsvdError, match="invalid"):
         rs.BatchPlan([])
