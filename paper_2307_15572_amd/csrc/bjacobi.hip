@@ -71,9 +71,14 @@ __device__ __forceinline__ void jac_rot(double hpp, double hqq, double hpq, doub
 }
 
 // Returns true if the pair needed rotating. dsq: 32 doubles of LDS.
+// jl: kJacLds doubles of LDS holding the Gram's partial sums, and after them
+// (the same memory) the double-buffered 32 x 32 H and the rotations V.
+constexpr int kJacLds = 8 * 3 * 256;
 template <int kJacWaves>
-__device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double (*Hb)[32][33],
-                             double (*Vb)[32][33], double* red, double* dsq, int* s_any) {
+__device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double* jl, double* dsq,
+                             int* s_any) {
+  double (*Hb)[32][33] = reinterpret_cast<double (*)[32][33]>(jl);
+  double* red = jl;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
   double (*H)[33] = Hb[0];
   const int Lp = a.Lp;
@@ -81,51 +86,72 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
   const double* rI = a.M + (int64_t)16 * I * Lp;
   const double* rJ = a.M + (int64_t)16 * J * Lp;
 
-  // ---- Gram of the 32 rows (tiles 00, 01, 11), K split over the 4 waves;
-  // GB column tiles of a wave in flight together
-  constexpr int GB = kJacWaves == 8 ? 3 : 5;
-  d4 h00 = {0, 0, 0, 0}, h01 = {0, 0, 0, 0}, h11 = {0, 0, 0, 0};
-  for (int ct0 = wave; ct0 < nct; ct0 += kJacWaves * GB) {
-    double xi[GB][4], xj[GB][4];
+  // ---- Gram of the 32 rows (tiles 00, 01, 11), the column tiles split into
+  // kGramParts partial sums by their index mod kGramParts, whatever the
+  // number of waves (a wave takes parts wave, wave + W, ...): every part is
+  // summed in increasing tile order and the parts in increasing order, so
+  // the Gram is bitwise the same for 4 and 8 waves. GB column tiles of a
+  // part in flight together.
+  constexpr int kGramParts = 8;
+  constexpr int PW = kGramParts / kJacWaves;  // parts per wave
+  constexpr int GB = kJacWaves == 8 ? 3 : 2;
+  d4 h00[PW], h01[PW], h11[PW];
 #pragma unroll
-    for (int u = 0; u < GB; u++) {
-      const int c0 = 16 * (ct0 + kJacWaves * u) + 4 * g;
-      if (ct0 + kJacWaves * u < nct) {
+  for (int pw = 0; pw < PW; pw++) h00[pw] = h01[pw] = h11[pw] = d4{0, 0, 0, 0};
 #pragma unroll
-        for (int s = 0; s < 4; s++) {
-          xi[u][s] = rI[(int64_t)r * Lp + c0 + s];
-          xj[u][s] = rJ[(int64_t)r * Lp + c0 + s];
+  for (int pw = 0; pw < PW; pw++) {
+    const int part = wave + kJacWaves * pw;
+    for (int ct0 = part; ct0 < nct; ct0 += kGramParts * GB) {
+      double xi[GB][4], xj[GB][4];
+#pragma unroll
+      for (int u = 0; u < GB; u++) {
+        const int c0 = 16 * (ct0 + kGramParts * u) + 4 * g;
+        if (ct0 + kGramParts * u < nct) {
+#pragma unroll
+          for (int s = 0; s < 4; s++) {
+            xi[u][s] = rI[(int64_t)r * Lp + c0 + s];
+            xj[u][s] = rJ[(int64_t)r * Lp + c0 + s];
+          }
         }
       }
-    }
 #pragma unroll
-    for (int u = 0; u < GB; u++) {
-      if (ct0 + kJacWaves * u < nct) {
+      for (int u = 0; u < GB; u++) {
+        if (ct0 + kGramParts * u < nct) {
 #pragma unroll
-        for (int s = 0; s < 4; s++) {
-          h00 = mfma_f64_16x16x4(xi[u][s], xi[u][s], h00);
-          h01 = mfma_f64_16x16x4(xi[u][s], xj[u][s], h01);
-          h11 = mfma_f64_16x16x4(xj[u][s], xj[u][s], h11);
+          for (int s = 0; s < 4; s++) {
+            h00[pw] = mfma_f64_16x16x4(xi[u][s], xi[u][s], h00[pw]);
+            h01[pw] = mfma_f64_16x16x4(xi[u][s], xj[u][s], h01[pw]);
+            h11[pw] = mfma_f64_16x16x4(xj[u][s], xj[u][s], h11[pw]);
+          }
         }
       }
     }
   }
 #pragma unroll
-  for (int it = 0; it < 4; it++) {
-    const int e = (g + 4 * it) * 16 + r;
-    red[(wave * 3 + 0) * 256 + e] = h00[it];
-    red[(wave * 3 + 1) * 256 + e] = h01[it];
-    red[(wave * 3 + 2) * 256 + e] = h11[it];
+  for (int pw = 0; pw < PW; pw++) {
+    const int part = wave + kJacWaves * pw;
+#pragma unroll
+    for (int it = 0; it < 4; it++) {
+      const int e = (g + 4 * it) * 16 + r;
+      red[(part * 3 + 0) * 256 + e] = h00[pw][it];
+      red[(part * 3 + 1) * 256 + e] = h01[pw][it];
+      red[(part * 3 + 2) * 256 + e] = h11[pw][it];
+    }
   }
   if (threadIdx.x == 0) *s_any = 0;
   __syncthreads();
-  for (int e = threadIdx.x; e < 256; e += blockDim.x) {
-    double v0 = 0, v1 = 0, v2 = 0;
-    for (int w = 0; w < kJacWaves; w++) {
+  // the parts summed into registers first: H lives in the same memory
+  const int e = threadIdx.x;
+  double v0 = 0, v1 = 0, v2 = 0;
+  if (e < 256) {
+    for (int w = 0; w < kGramParts; w++) {
       v0 += red[(w * 3 + 0) * 256 + e];
       v1 += red[(w * 3 + 1) * 256 + e];
       v2 += red[(w * 3 + 2) * 256 + e];
     }
+  }
+  __syncthreads();
+  if (e < 256) {
     const int i = e / 16, j = e % 16;
     H[i][j] = v0;
     H[i][16 + j] = v1;
@@ -159,7 +185,7 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
   // one buffer and writes the other, since other threads read the diagonal
   // entries of a block its owner rewrites), which leaves one barrier per
   // round. The blocks partition V, so V is updated in place.
-  double (*V)[33] = Vb[0];
+  double (*V)[33] = reinterpret_cast<double (*)[33]>(jl + 2 * 32 * 33);
   for (int e = threadIdx.x; e < 32 * 32; e += blockDim.x)
     V[e / 32][e % 32] = (e / 32 == e % 32) ? 1.0 : 0.0;
   __syncthreads();
@@ -264,11 +290,9 @@ __device__ bool process_pair(const JacArgs& a, int I, int J, double tol, double 
 }
 
 template <int kJacWaves>
-__global__ void __launch_bounds__(64 * kJacWaves) bjacobi_kernel(JacArgs a) {
+__global__ void __launch_bounds__(64 * kJacWaves, kJacWaves == 4 ? 2 : 1) bjacobi_kernel(JacArgs a) {
   __shared__ int s_bar_ok;
-  __shared__ double Hb[2][32][33];
-  __shared__ double Vb[2][32][33];
-  __shared__ double red[kJacWaves * 3 * 256];
+  __shared__ double jl[kJacLds];
   __shared__ double dsq[32];
   __shared__ int s_any;
   const int nb = a.Lp / 16;  // even
@@ -283,7 +307,7 @@ __global__ void __launch_bounds__(64 * kJacWaves) bjacobi_kernel(JacArgs a) {
       for (int pr = blockIdx.x; pr < npairs; pr += gridDim.x) {
         int I, J;
         rr_pair_blk(nb, step, pr, I, J);
-        const bool rot = process_pair<kJacWaves>(a, I, J, tol, Hb, Vb, red, dsq, &s_any);
+        const bool rot = process_pair<kJacWaves>(a, I, J, tol, jl, dsq, &s_any);
         if (rot && threadIdx.x == 0)
           __hip_atomic_fetch_add(&counters[sweep], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       }
@@ -345,13 +369,11 @@ __global__ void __launch_bounds__(256) jac_init_kernel(int l, int Lp, const doub
 constexpr int kBatchJacMaxChannels = 4096;
 
 template <int kJacWaves>
-__global__ void __launch_bounds__(64 * kJacWaves)
+__global__ void __launch_bounds__(64 * kJacWaves, kJacWaves == 4 ? 2 : 1)
     bjacobi_batch_kernel(const JacChan* __restrict__ ch, int nch, char* __restrict__ work,
                          GridBar* bar) {
   __shared__ int s_bar_ok;
-  __shared__ double Hb[2][32][33];
-  __shared__ double Vb[2][32][33];
-  __shared__ double red[kJacWaves * 3 * 256];
+  __shared__ double jl[kJacLds];
   __shared__ double dsq[32];
   __shared__ int s_any;
   __shared__ uint32_t done[kBatchJacMaxChannels / 32];
@@ -403,7 +425,7 @@ __global__ void __launch_bounds__(64 * kJacWaves)
         a.P = ch[c].P_off >= 0 ? reinterpret_cast<double*>(work + ch[c].P_off) : nullptr;
         a.st = reinterpret_cast<DevState*>(work + ch[c].st_off);
         const double tol = (double)a.l * kU;
-        const bool rot = process_pair<kJacWaves>(a, I, J, tol, Hb, Vb, red, dsq, &s_any);
+        const bool rot = process_pair<kJacWaves>(a, I, J, tol, jl, dsq, &s_any);
         if (rot && threadIdx.x == 0)
           __hip_atomic_fetch_add(&a.st->rot_count[sw], 1u, __ATOMIC_RELAXED,
                                  __HIP_MEMORY_SCOPE_AGENT);
@@ -448,19 +470,29 @@ rsvd_status jacobi_batch(const JacChan* table, int nch, int64_t first_round_pair
                          GridBar* bar, hipStream_t s) {
   if (nch < 1) return RSVD_OK;
   if (nch > kBatchJacMaxChannels) return RSVD_EINVAL;
+  // pairs outnumbering the CUs: 4-wave workgroups, two per CU (the pair
+  // step's arithmetic, and so every channel's result, is the same for 4 and
+  // 8 waves); otherwise 8 waves per pair
   int dev = 0, ncu = 0, per = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, (const void*)bjacobi_batch_kernel<8>, 512,
-                                                   0) != hipSuccess)
+      hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return RSVD_EHIP;
+  const bool four = first_round_pairs > ncu;
+  const void* fn = four ? (const void*)bjacobi_batch_kernel<4> : (const void*)bjacobi_batch_kernel<8>;
+  const int threads = four ? 256 : 512;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, fn, threads, 0) != hipSuccess)
     return RSVD_EHIP;
   const int64_t cap = (int64_t)ncu * (per > 0 ? per : 1);
   int64_t grid = first_round_pairs < cap ? first_round_pairs : cap;
   if (grid < 1) grid = 1;
   hipLaunchKernelGGL(jac_batch_reset_kernel, dim3(1), dim3(256), 0, s, bar);
   RSVD_LAUNCH_CHECK();
-  hipLaunchKernelGGL(bjacobi_batch_kernel<8>, dim3((unsigned)grid), dim3(512), 0, s, table, nch,
-                     work, bar);
+  if (four)
+    hipLaunchKernelGGL(bjacobi_batch_kernel<4>, dim3((unsigned)grid), dim3(256), 0, s, table, nch,
+                       work, bar);
+  else
+    hipLaunchKernelGGL(bjacobi_batch_kernel<8>, dim3((unsigned)grid), dim3(512), 0, s, table, nch,
+                       work, bar);
   RSVD_LAUNCH_CHECK();
   return RSVD_OK;
 }

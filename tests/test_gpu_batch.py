@@ -206,3 +206,32 @@ def test_wide_and_shifted_channels_graph():
     ref = oracle_rsvd(mats[2], pr["k"], pr["p"], pr["q"], seed=9, channel=2, symmetric=True)
     ok, worst = sigma_gate(bufs["S"][2][: res[2].rank].cpu().numpy(), ref.s[: res[2].rank])
     assert ok, worst
+
+
+def test_grouped_small_svd_four_wave_launch_equals_single_runs():
+    # more first-round block pairs than CUs: the grouped launch runs 4-wave
+    # workgroups (two per CU) while the single runs use 8 waves per pair; the
+    # Gram of a pair sums the same partials in the same order either way, so
+    # values, ranks, flags and sweep counts agree bitwise
+    import paper_2307_15572_amd as rs
+    announce("batch of 16 values-only channels, l ~ 560: 4-wave grouped small SVDs")
+    mats, probs = [], []
+    for c in range(16):
+        n = 1100 + 37 * c
+        A, _ = synth.channel(c, n, 140.0, tag=606)
+        mats.append(A)
+        probs.append(dict(m=n, n=n, k=540 + c, p=16, q=1, symmetric=True, seed=13, channel=c,
+                          want_u=False, want_v=False, want_residual=False))
+    pairs = sum((-(-(pr["k"] + pr["p"]) // 16) + 1) // 2 * 2 // 2 for pr in probs)
+    assert pairs > 256
+    dev = [to_dev(A) for A in mats]
+    singles = [_single(A, pr) for A, pr in zip(dev, probs)]
+    bp = rs.BatchPlan(probs, lanes=4, use_graph=True)
+    bufs = bp.allocate("cuda:0")
+    bp.run_into(dev, bufs)
+    res = bp.results(bufs)
+    for c, one in enumerate(singles):
+        r = res[c]
+        assert (r.rank, r.flags, r.sweeps) == (one.rank, one.flags, one.sweeps), c
+        k = one.rank
+        assert np.array_equal(bufs["S"][c][:k].cpu().numpy(), one.S.cpu().numpy()), c
