@@ -49,6 +49,7 @@ PEAK_FP64_TFLOPS = 78.6   # MI355X dense FP64 (vector = matrix)
 PEAK_FP32_TFLOPS = 157.3  # MI355X dense FP32 matrix
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 PEAK_BF16_TFLOPS = 2500.0  # MI355X dense BF16 matrix
+PEAK_INT8_TOPS = 5000.0   # MI355X dense INT8 matrix (TOP/s)
 GATE = 1e-6
 
 # HBM bytes per launch of the streaming products at the 16384 x 16384 x 272
@@ -155,8 +156,9 @@ def product_roofline(name, flops, avg_s, peak, kernel, launches, **extra):
 
 # ---- the headline matrix: FP64, every precision schedule, symmetric form -----
 
-SCHEDULES = (("mixed_fp32", 1), ("mixed_fp32", 2), ("mixed_bf16", 1), ("mixed_bf16", 2),
-             ("mixed_bf16_split", 1), ("mixed_bf16_split", 2))
+SCHEDULES = (("mixed_fp32", 1), ("mixed_fp32", 2), ("mixed_fp32_sliced", 1), ("mixed_bf16", 1),
+             ("mixed_bf16", 2), ("mixed_bf16_split", 1), ("mixed_bf16_split", 2))
+SLICE_PRODUCTS = 28  # INT8 slice products of one error-free sliced product (7 slices each side)
 
 
 def headline(dev, args, A, sigma, w):
@@ -241,6 +243,13 @@ def headline(dev, args, A, sigma, w):
                 traffic=product_traffic("fp32"),
                 traffic_unit="bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                 algorithmic_bytes=8.0 * w.m * w.n + 4.0 * w.n * l + 8.0 * w.m * l)
+        if prec == "mixed_fp32_sliced" and ph["stream_gemm"][1]:
+            sms, scnt = ph["stream_gemm"]
+            ent["sliced_product"] = product_roofline(
+                "int8", SLICE_PRODUCTS * flops_product, sms / scnt * 1e-3, PEAK_INT8_TOPS,
+                "sliced_gemm_kernel (28 exact INT8 slice products, FP64 sums; A sliced once per run)",
+                scnt)
+            ent["sliced_product"]["unit"] = "TOP/s"
         if ph["bf16_gemm"][1]:
             bms, bcnt = ph["bf16_gemm"]
             planes = 2 if prec == "mixed_bf16_split" else 1
@@ -280,7 +289,8 @@ def headline(dev, args, A, sigma, w):
         r = runs[best]
         ent = mixed[best]
         head = {"schedule": best, "ms": r["ms"], "value": ent["value"],
-                "dtype": "f32+f64" if best.startswith("mixed_fp32") else "bf16+f64"}
+                "dtype": ("f32+i8" if best.startswith("mixed_fp32_sliced") else
+                          "f32+f64" if best.startswith("mixed_fp32") else "bf16+f64")}
         ph = r["phases"]
         # dominant kernel of the step: the low-precision product if it takes
         # the larger share, else the FP64 product
@@ -292,6 +302,8 @@ def headline(dev, args, A, sigma, w):
             roof = {"bound": "hbm", "achieved": bp["GBs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": bp["frac_hbm"], "kernel": "bf16_stream_kernel (BF16 plane product)",
                     "avg_ms": bp["avg_ms"]}
+        elif "sliced_product" in ent:
+            roof = dict(ent["sliced_product"])
         else:
             sm, sc = ph["stream_gemm"]
             roof = product_roofline("fp64", flops_product, sm / sc * 1e-3, PEAK_FP64_TFLOPS,

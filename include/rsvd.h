@@ -58,9 +58,16 @@ enum {
   RSVD_PREC_FP64 = 0,          /* every product in FP64 (MFMA f64)                  */
   RSVD_PREC_MIXED_FP32 = 1,    /* early passes FP32 MFMA, trailing passes FP64       */
   RSVD_PREC_MIXED_BF16 = 2,    /* early passes BF16 MFMA (FP32 accumulate)           */
-  RSVD_PREC_MIXED_BF16_SPLIT = 3 /* early passes on BF16 matrix cores with each operand
+  RSVD_PREC_MIXED_BF16_SPLIT = 3, /* early passes on BF16 matrix cores with each operand
                                     split x = hi + lo (hi = bf16(x), lo = bf16(x - hi)):
                                     hi*lo + lo*hi + hi*hi, FP32 accumulation          */
+  RSVD_PREC_MIXED_FP32_SLICED = 4 /* early passes as RSVD_PREC_MIXED_FP32; the trailing
+                                    passes and the projection (products A X; A^T X of a
+                                    non-symmetric A stays FP64) as error-free sliced
+                                    products: 7 INT8 slices per entry (one power-of-two
+                                    scale per row of A, per column of the panel), slice
+                                    products exact in INT32 on the integer matrix
+                                    cores, summed in FP64 (rsvd_gemm, mode 4)         */
 };
 
 /* How step 2 projects A (rsvd_problem.form). */
@@ -496,7 +503,19 @@ rsvd_status rsvd_dgemm(int32_t trans_a, int64_t m, int64_t n, int64_t k, double 
  * RSVD_PREC_MIXED_BF16_SPLIT (operands split into BF16 hi + lo, three BF16
  * products, FP32 accumulation). Inputs
  * and output stay FP64 in memory; work as for rsvd_dgemm. These are the
- * early products of the precision schedule of the mixed modes. */
+ * early products of the precision schedule of the mixed modes.
+ * RSVD_PREC_MIXED_FP32_SLICED: the error-free sliced product of that
+ * schedule's FP64-accurate passes (the splitting of Ozaki, Ogita, Oishi and
+ * Rump with 8-bit integer slices): A and B cut into 7 signed 7-bit slices
+ * per entry with one power-of-two scale per row of A and per column of B,
+ * the 28 slice products of weight >= 2^-56 computed exactly (INT32, flushed
+ * to FP64 every 16384 terms of k) and summed in FP64; each entry of C within
+ * about 1e-14 k max_k |a_ik| max_k |b_kj| of the exact product, integer
+ * inputs of at most 7 bits reproduced exactly. Only trans_a = 0, alpha = 1,
+ * beta = 0 (RSVD_EINVAL otherwise); work: at least
+ * rsvd_sliced_gemm_work_bytes(m, n, k) bytes, 256-byte aligned
+ * (RSVD_ENOMEM otherwise). */
+size_t rsvd_sliced_gemm_work_bytes(int64_t m, int64_t n, int64_t k);
 rsvd_status rsvd_gemm(int32_t precision, int32_t trans_a, int64_t m, int64_t n, int64_t k,
                       double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
                       double beta, double* C, int64_t ldc, void* work, size_t work_bytes,

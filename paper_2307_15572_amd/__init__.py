@@ -16,7 +16,8 @@ LIB_PATH = os.path.join(PKG_DIR, "librsvd.so")
 
 RSVD_OK, RSVD_EINVAL, RSVD_ENOMEM, RSVD_EHIP, RSVD_EUNSUPPORTED = range(5)
 RANK_MODES = {"fixed": 0, "percent": 1, "rel_threshold": 2, "frob_tail": 3}
-PRECISIONS = {"fp64": 0, "mixed_fp32": 1, "mixed_bf16": 2, "mixed_bf16_split": 3}
+PRECISIONS = {"fp64": 0, "mixed_fp32": 1, "mixed_bf16": 2, "mixed_bf16_split": 3,
+              "mixed_fp32_sliced": 4}
 FORMS = {"svd": 0, "symmetric": 1}
 FLAG_FULL_SVD = 1 << 0
 FLAG_RANK_CAPPED = 1 << 1
@@ -32,6 +33,7 @@ FLAG_UNCONVERGED = 1 << 9
 EXPORTED = (
     "rsvd_plan", "rsvd_plan_l", "rsvd_run", "rsvd_destroy", "rsvd_strerror",
     "rsvd_gaussian_omega", "rsvd_dgemm_work_bytes", "rsvd_dgemm", "rsvd_gemm",
+    "rsvd_sliced_gemm_work_bytes",
     "rsvd_bf16_gemm_work_bytes", "rsvd_bf16_gemm",
     "rsvd_orth_work_bytes", "rsvd_orth", "rsvd_small_svd_work_bytes", "rsvd_small_svd",
     "rsvd_trace_enable", "rsvd_trace_collect",
@@ -119,6 +121,8 @@ def lib():
     L.rsvd_gaussian_omega.restype = ctypes.c_int
     L.rsvd_dgemm_work_bytes.argtypes = [i64, i64, i64, i32]
     L.rsvd_dgemm_work_bytes.restype = sz
+    L.rsvd_sliced_gemm_work_bytes.argtypes = [i64, i64, i64]
+    L.rsvd_sliced_gemm_work_bytes.restype = sz
     L.rsvd_dgemm.argtypes = [i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, vp, sz, vp]
     L.rsvd_dgemm.restype = ctypes.c_int
     L.rsvd_gemm.argtypes = [i32, i32, i64, i64, i64, dbl, vp, i64, vp, i64, dbl, vp, i64, vp, sz, vp]
@@ -593,7 +597,10 @@ def dgemm(A, B, trans_a=False, alpha=1.0, beta=0.0, C=None, precision="fp64"):
     if C is None:
         C = torch.zeros(m, n, dtype=torch.float64, device=A.device)
     L = lib()
-    wb = L.rsvd_dgemm_work_bytes(m, n, k, int(trans_a))
+    if precision == "mixed_fp32_sliced":
+        wb = L.rsvd_sliced_gemm_work_bytes(m, n, k)
+    else:
+        wb = L.rsvd_dgemm_work_bytes(m, n, k, int(trans_a))
     work = torch.empty(max(wb // 8, 1), dtype=torch.float64, device=A.device)
     _check(L.rsvd_gemm(PRECISIONS[precision], int(trans_a), m, n, k, alpha, _ptr(A), A.stride(0),
                        _ptr(B), B.stride(0), beta, _ptr(C), C.stride(0), _ptr(work), wb,

@@ -16,7 +16,7 @@ OUT = os.path.join(PKG, "librsvd.so")
 BUILD = os.path.join(ROOT, "_build")
 
 SOURCES = ["gemm.hip", "bf16gemm.hip", "omega.hip", "smalldense.hip", "bjacobi.hip", "rsvd.cpp", "batch.cpp", "tune.cpp", "mlp.hip",
-           "noalloc.hip"]
+           "noalloc.hip", "sliced.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

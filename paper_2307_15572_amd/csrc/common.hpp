@@ -54,6 +54,9 @@ __device__ __forceinline__ double bf16_value(short b) {
 // accumulate in FP32. Operands stay FP64 in memory and are rounded (split)
 // when they enter the matrix core.
 enum Prec { kPrecF64 = 0, kPrecF32 = 1, kPrecBF16 = 2, kPrecBF16S = 3 };
+// Schedules only (no kernel template takes it): the error-free sliced
+// product (sliced.hip) in place of an FP64 one.
+constexpr int kPrecSliced = 4;
 
 // ---- LDS-DMA copies ---------------------------------------------------------
 #define RSVD_LDS(p) ((__attribute__((address_space(3))) void*)(p))

@@ -33,6 +33,18 @@ rsvd_status dgemm(bool ta, int64_t M, int64_t N, int64_t K, double alpha, const 
                   double* part, size_t part_doubles, hipStream_t st, int max_splits = 64,
                   const uint32_t* pred = nullptr, int prec = kPrecF64, const float* Bf = nullptr,
                   int64_t ldbf = 0, const double* Bp = nullptr, int64_t ldbp = 0);
+// Error-free sliced product C = A X (sliced.hip): A (M x K, lda) and X
+// (K x N, ldx) FP64, cut into 7 INT8 slices per entry with one power-of-two
+// scale per row of A and per column of X, the slice products exact in INT32
+// on the integer matrix cores, summed in FP64 (about 1e-14 relative to
+// K max_k |a_ik| max_k |x_kj|). work: sliced_work_bytes(M, N, K) bytes,
+// 256-byte aligned. sliced_prepare_a slices A into work once; sliced_gemm
+// then slices X and forms C (ldc >= N) from both; both on stream s.
+size_t sliced_work_bytes(int64_t M, int64_t N, int64_t K);
+rsvd_status sliced_prepare_a(int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                             void* work, hipStream_t s);
+rsvd_status sliced_gemm(int64_t M, int64_t N, int64_t K, const double* X, int64_t ldx, double* C,
+                        int64_t ldc, void* work, hipStream_t s);
 // FP32 panel Xf (rows x f32_panel_ld(cols)) of X, rounded to nearest, zero padded
 int64_t f32_panel_ld(int64_t cols);
 rsvd_status f32_panel(int64_t rows, int64_t cols, const double* X, int64_t ldx, float* Xf,

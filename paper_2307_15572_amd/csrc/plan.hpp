@@ -65,6 +65,9 @@ struct rsvd_plan_s {
   // (odd l), so that the products stream through the LDS-DMA kernel
   size_t off_Apad = 0, off_Xp = 0;
   int64_t ld_apad = 0, ld_xp = 0;
+  // error-free sliced schedule: the slices of A (made once per run) and of
+  // the panel of each sliced product
+  size_t off_sl = 0;
   size_t part_doubles = 0;
   size_t total = 0;
 };

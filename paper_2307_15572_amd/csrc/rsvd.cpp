@@ -236,7 +236,7 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* worksp
   const rsvd_problem& p = *prob;
   if (p.m < 1 || p.n < 1 || p.oversample < 0 || p.power_iters < 0) return RSVD_EINVAL;
   if (p.symmetric && p.m != p.n) return RSVD_EINVAL;
-  if (p.precision < RSVD_PREC_FP64 || p.precision > RSVD_PREC_MIXED_BF16_SPLIT) return RSVD_EINVAL;
+  if (p.precision < RSVD_PREC_FP64 || p.precision > RSVD_PREC_MIXED_FP32_SLICED) return RSVD_EINVAL;
   if (p.trailing_hp < 0) return RSVD_EINVAL;
   if (p.posterior < 0 || p.posterior > 64) return RSVD_EINVAL;
   if (p.posterior != 0 && p.adaptive) return RSVD_EINVAL;
@@ -409,8 +409,11 @@ rsvd_status rsvd_plan(const rsvd_problem* prob, rsvd_plan_t* out, size_t* worksp
     pl->fpart_floats = fpart;
     if (fpart) pl->off_fpart = c.take(fpart * sizeof(float));
   }
-  if (!adaptive && n_low > 0 && p.precision == RSVD_PREC_MIXED_FP32)
+  if (!adaptive && n_low > 0 &&
+      (p.precision == RSVD_PREC_MIXED_FP32 || p.precision == RSVD_PREC_MIXED_FP32_SLICED))
     pl->off_Xf = c.take((size_t)mx * f32_panel_ld(l) * sizeof(float));
+  if (!adaptive && p.precision == RSVD_PREC_MIXED_FP32_SLICED)
+    pl->off_sl = c.take(sliced_work_bytes(m, l, n));
   if (adaptive) {
     pl->off_Wb = c.take((size_t)m * blk * D);
     pl->off_Zb = c.take((size_t)n * blk * D);
@@ -794,10 +797,13 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
   // the last trailing_hp use the low-precision matrix cores in mixed modes;
   // the projection, QR, small SVD and residual are always FP64
   const int n_early = 2 * p.power_iters + 1;
-  const int lowp = p.precision == RSVD_PREC_MIXED_FP32         ? kPrecF32
+  const int lowp = p.precision == RSVD_PREC_MIXED_FP32 ||
+                           p.precision == RSVD_PREC_MIXED_FP32_SLICED
+                       ? kPrecF32
                    : p.precision == RSVD_PREC_MIXED_BF16       ? kPrecBF16
                    : p.precision == RSVD_PREC_MIXED_BF16_SPLIT ? kPrecBF16S
                                                                : kPrecF64;
+  bool a_sliced = false;  // the slices of A, made by the first sliced product
   int product = 0;
   uint16_t* Ah = pl.bf16 ? w.at<uint16_t>(pl.off_Ah) : nullptr;
   uint16_t* Al = pl.bf16_split ? w.at<uint16_t>(pl.off_Al) : nullptr;
@@ -814,8 +820,19 @@ rsvd_status rsvd_run(rsvd_plan_t plan, const double* A, int64_t lda, const doubl
   }
   auto stream_pass = [&](bool trans, const double* X, int64_t ldx, double* out, int64_t rows_out,
                          int64_t inner) -> rsvd_status {
-    const int prec = product < n_early - p.trailing_hp ? lowp : kPrecF64;
+    int prec = product < n_early - p.trailing_hp ? lowp : kPrecF64;
     product++;
+    if (prec == kPrecF64 && pl.off_sl && !trans) {
+      // the FP64-accurate passes of the sliced schedule (A X; A^T X of a
+      // non-symmetric A stays FP64)
+      PhaseScope ph(0, s);
+      void* ws = w.at<char>(pl.off_sl);
+      if (!a_sliced) {
+        RSVD_TRY(sliced_prepare_a(m, l, n, A, lda, ws, s));
+        a_sliced = true;
+      }
+      return sliced_gemm(rows_out, l, inner, X, ldx, out, l, ws, s);
+    }
     const bool f32_panel_path = prec == kPrecF32 && !trans && pl.off_Xf;
     if (f32_panel_path) {
       // the panel rounded to FP32 once: the streaming kernel stages half the
@@ -929,7 +946,7 @@ rsvd_status rsvd_gemm(int32_t precision, int32_t trans_a, int64_t m, int64_t n, 
                       double alpha, const double* A, int64_t lda, const double* B, int64_t ldb,
                       double beta, double* C, int64_t ldc, void* work, size_t work_bytes,
                       void* stream) {
-  if (precision < RSVD_PREC_FP64 || precision > RSVD_PREC_MIXED_BF16_SPLIT) return RSVD_EINVAL;
+  if (precision < RSVD_PREC_FP64 || precision > RSVD_PREC_MIXED_FP32_SLICED) return RSVD_EINVAL;
   if (m < 0 || n < 0 || k < 0) return RSVD_EINVAL;
   if (m == 0 || n == 0) return RSVD_OK;
   if (!C || ldc < n) return RSVD_EINVAL;
@@ -937,12 +954,25 @@ rsvd_status rsvd_gemm(int32_t precision, int32_t trans_a, int64_t m, int64_t n, 
     if (!A || !B || ldb < n) return RSVD_EINVAL;
     if (trans_a ? lda < m : lda < k) return RSVD_EINVAL;
   }
+  if (precision == RSVD_PREC_MIXED_FP32_SLICED) {
+    if (trans_a || alpha != 1.0 || beta != 0.0 || k == 0) return RSVD_EINVAL;
+    if (!work || ((uintptr_t)work & 255) != 0) return RSVD_EINVAL;
+    if (work_bytes < sliced_work_bytes(m, n, k)) return RSVD_ENOMEM;
+    hipStream_t s = (hipStream_t)stream;
+    rsvd_status r = sliced_prepare_a(m, n, k, A, lda, work, s);
+    if (r != RSVD_OK) return r;
+    return sliced_gemm(m, n, k, B, ldb, C, ldc, work, s);
+  }
   const int prec = precision == RSVD_PREC_MIXED_FP32         ? kPrecF32
                    : precision == RSVD_PREC_MIXED_BF16       ? kPrecBF16
                    : precision == RSVD_PREC_MIXED_BF16_SPLIT ? kPrecBF16S
                                                              : kPrecF64;
   return dgemm(trans_a != 0, m, n, k, alpha, A, lda, B, ldb, beta, C, ldc, (double*)work,
                work_bytes / sizeof(double), (hipStream_t)stream, 64, nullptr, prec);
+}
+
+size_t rsvd_sliced_gemm_work_bytes(int64_t m, int64_t n, int64_t k) {
+  return sliced_work_bytes(m, n, k);
 }
 
 namespace {

@@ -279,3 +279,36 @@ def test_bf16_planes_gemm(split, ta, m, n, k):
     exact = opA @ B
     u_in = 2.0 ** -15 if split else 2.0 ** -8
     assert np.all(np.abs(got - exact) <= (2 * u_in + (terms + 2) * u32) * (np.abs(opA) @ np.abs(B)))
+
+
+def test_sliced_product_exact_on_small_integers():
+    # integers of at most 7 bits fit one slice each: the slice product is the
+    # exact product, so C equals A B (exact in FP64 here) bitwise
+    import torch
+    import paper_2307_15572_amd as rs
+    announce("sliced product, integer inputs, 333 x 1001 x 70")
+    g = torch.Generator().manual_seed(21)
+    A = torch.randint(-100, 101, (333, 1001), generator=g).double()
+    B = torch.randint(-100, 101, (1001, 70), generator=g).double()
+    C = rs.dgemm(to_dev(A.numpy()), to_dev(B.numpy()), precision="mixed_fp32_sliced")
+    assert torch.equal(C.cpu(), A @ B)
+
+
+@pytest.mark.parametrize("m,n,k", [(700, 130, 1001), (1024, 272, 4096), (65, 17, 33)])
+def test_sliced_product_error_bound(m, n, k):
+    # random FP64 operands whose rows and columns span many binades: every
+    # entry within 4e-14 k max_k |a_ik| max_k |b_kj| of the exact product
+    # (numpy FP64 products differ from it by far less), and far closer than
+    # an FP32 product would be
+    import paper_2307_15572_amd as rs
+    announce(f"sliced product error bound {m} x {n} x {k}")
+    rng = np.random.default_rng(m + n + k)
+    A = rng.standard_normal((m, k)) * np.exp2(rng.integers(-30, 30, size=(m, 1)))
+    B = rng.standard_normal((k, n)) * np.exp2(rng.integers(-30, 30, size=(1, n)))
+    C = rs.dgemm(to_dev(A), to_dev(B), precision="mixed_fp32_sliced").cpu().numpy()
+    ref = A @ B
+    scale = k * np.abs(A).max(axis=1)[:, None] * np.abs(B).max(axis=0)[None, :]
+    err = np.abs(C - ref) / scale
+    assert err.max() <= 4e-14, err.max()
+    C32 = rs.dgemm(to_dev(A), to_dev(B), precision="mixed_fp32").cpu().numpy()
+    assert err.max() < 1e-5 * (np.abs(C32 - ref) / scale).max()

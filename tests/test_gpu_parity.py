@@ -242,6 +242,30 @@ def test_mixed_fp32_meets_1e6_gate(thp):
     assert abs(out.residual - ref.residual) <= 1e-6 * ref.residual
 
 
+@pytest.mark.parametrize("n", [2048, 1025])
+def test_mixed_fp32_sliced_meets_1e6_gate(n):
+    # FP32 early products, the trailing product and the projection as
+    # error-free sliced products: every kept value within 1e-6 of the FP64
+    # oracle, and within 1e-10 of the schedule with FP64 trailing products
+    # (the same FP32 products before them)
+    import paper_2307_15572_amd as rs
+    announce(f"mixed fp32 + sliced trailing products, symmetric {n}")
+    if n == 2048:
+        A, sigma, w = synth.c2(n=n)
+        k, p, q, seed = 256, 16, 2, 2002
+    else:
+        A = synth.symmetric(n, synth.spectrum_pow10(n, 1 / 64), tag=341, noise=1e-9)
+        k, p, q, seed = 64, 15, 2, 17
+    rel, nrm, out, ref = _mixed_errors(A, k, p, q, seed, True, "mixed_fp32_sliced", 1)
+    assert rel <= 1e-6, rel
+    assert abs(out.residual - ref.residual) <= 1e-6 * ref.residual
+    f64t = rs.run(to_dev(A), k, p, q, seed=seed, symmetric=True, precision="mixed_fp32",
+                  trailing_hp=1)
+    s1, s2 = out.S.cpu().numpy(), f64t.S.cpu().numpy()
+    kk = min(len(s1), len(s2))
+    assert np.max(np.abs(s1[:kk] - s2[:kk]) / s2[:kk]) <= 1e-10
+
+
 def test_mixed_fp32_general_tall():
     announce("mixed fp32 general 3000 x 400")
     sig = synth.spectrum_pow10(400, 1 / 64)
