@@ -22,15 +22,14 @@ namespace {
 
 constexpr int kSlices = 7;
 constexpr int kSliceChunk = 16384;  // K terms per INT32 sum
-constexpr int kSliceKStep = 32;     // K of one v_mfma_i32_16x16x32_i8
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
-// v_mfma_i32_16x16x32_i8 (checked on the device): lane (r, g) supplies
-// A[r][8g .. 8g+7] and B[8g .. 8g+7][r] (8 bytes each, lowest k in the
-// lowest byte) and receives C[4g + i][r] in item i.
-__device__ __forceinline__ v4i mfma_i8_16x16x32(long a, long b, v4i c) {
-  return __builtin_amdgcn_mfma_i32_16x16x32_i8(a, b, c, 0, 0, 0);
+// v_mfma_i32_16x16x64_i8 (checked on the device): lane (r, g) supplies
+// A[r][16g .. 16g+15] and B[16g .. 16g+15][r] (16 bytes each, lowest k in
+// the lowest byte) and receives C[4g + i][r] in item i.
+__device__ __forceinline__ v4i mfma_i8_16x16x64(v4i a, v4i b, v4i c) {
+  return __builtin_amdgcn_mfma_i32_16x16x64_i8(a, b, c, 0, 0, 0);
 }
 
 // The digits of x (|x| < 2^e, e the line's exponent) into kSlices planes.
@@ -77,9 +76,33 @@ __global__ void __launch_bounds__(256) slice_rows_kernel(int64_t M, int64_t K, i
   for (int64_t k = threadIdx.x; k < K; k += blockDim.x) m = fmax(m, fabs(a[k]));
   const int e = line_exponent(block_max(m, red));
   if (threadIdx.x == 0) ea[row] = e;
+  // 1024 entries at a time: digits of coalesced reads into LDS planes, then
+  // 16-byte stores of each plane
+  __shared__ __attribute__((aligned(16))) int8_t dig[kSlices][1024];
   const int64_t plane = M * Kp;
-  for (int64_t k = threadIdx.x; k < Kp; k += blockDim.x)
-    digits(k < K ? a[k] : 0.0, e, AS + row * Kp + k, plane);
+  for (int64_t c0 = 0; c0 < Kp; c0 += 1024) {
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      const int kk = (int)threadIdx.x + 256 * j;
+      const int64_t k = c0 + kk;
+      double r = __builtin_amdgcn_ldexp(k < K ? a[k] : 0.0, -e);  // |r| < 1, exact
+#pragma unroll
+      for (int s = 0; s < kSlices; s++) {
+        r *= 128.0;                  // exact
+        const double d = trunc(r);   // |d| <= 127
+        r -= d;                      // exact
+        dig[s][kk] = (int8_t)(int)d;
+      }
+    }
+    __syncthreads();
+    for (int q = (int)threadIdx.x; q < kSlices * 64; q += 256) {
+      const int s = q / 64, off = 16 * (q % 64);
+      if (c0 + off < Kp)
+        *reinterpret_cast<v4i*>(AS + s * plane + row * Kp + c0 + off) =
+            *reinterpret_cast<const v4i*>(&dig[s][off]);
+    }
+    __syncthreads();
+  }
 }
 
 // One workgroup per column of X (K x N): its exponent and its digits into
@@ -100,93 +123,140 @@ __global__ void __launch_bounds__(256) slice_cols_kernel(int64_t K, int64_t N, i
     digits(k < K ? X[k * ldx + col] : 0.0, e, XS + col * Kp + k, plane);
 }
 
-// C (M x N) from the planes: a workgroup of 4 waves takes 64 rows (16 per
-// wave) by kSlTiles column tiles of 16; each wave keeps one INT32 tile per
-// weight 2^-7(s+t) and column tile, flushes them to FP64 every kSliceChunk
-// terms and scales by 2^(e_i + f_j) at the end. Tiles are ordered so that
-// the column groups of one row block are consecutive and land on the same
-// XCD (their A planes are then shared in its L2).
-constexpr int kSlTiles = 4;
-__global__ void __launch_bounds__(256) sliced_gemm_kernel(int64_t M, int64_t N, int64_t Kp,
-                                                          const int8_t* __restrict__ AS,
-                                                          const int* __restrict__ ea,
-                                                          const int8_t* __restrict__ XS,
-                                                          const int* __restrict__ fx,
-                                                          double* __restrict__ C, int64_t ldc,
-                                                          int tiles_n, int total) {
+// C (M x N) from the planes. A workgroup of 8 waves takes 128 rows (16 per
+// wave) by 64 columns (4 tiles of 16). The panel slices of its columns are
+// staged in LDS, kSlStage values of K at a time (double buffered, 16-byte
+// copies); each wave reads its A slices from global memory, 16 bytes per
+// lane and slice for 64 values of K, and keeps one INT32 tile per weight
+// 2^-7(s+t) and column tile, flushed to FP64 every kSliceChunk terms. Within
+// a block of 64 values of K, lane (r, g) takes k = 16 g .. 16 g + 15 of its
+// row of A and of column r of the panel (one 16x16x64 product): integer
+// sums are exact, so the assignment of k to lanes does not change a bit of
+// the result. Tiles are ordered so that the column groups of one row block
+// are consecutive and land on the same XCD (their A slices are then shared
+// in its L2).
+constexpr int kSlWaves = 8;
+constexpr int kSlRows = 16 * kSlWaves;
+constexpr int kSlCols = 64;
+constexpr int kSlTiles = kSlCols / 16;
+constexpr int kSlStage = 128;                 // values of K per LDS stage
+constexpr int kSlRowB = kSlStage + 16;        // bytes per staged column (padded)
+constexpr int kSlSliceB = kSlCols * kSlRowB;  // bytes per staged slice
+constexpr int kSlStageB = kSlices * kSlSliceB;
+static_assert(kSlCols * (kSlStage / 16) == 64 * kSlWaves, "one 16-byte copy per thread and slice");
+
+typedef v4i v4i32;
+
+__global__ void __launch_bounds__(64 * kSlWaves) sliced_gemm_kernel(
+    int64_t M, int64_t N, int64_t Kp, const int8_t* __restrict__ AS, const int* __restrict__ ea,
+    const int8_t* __restrict__ XS, const int* __restrict__ fx, double* __restrict__ C, int64_t ldc,
+    int tiles_n, int total) {
+  __shared__ __attribute__((aligned(16))) int8_t bst[2][kSlStageB];
   const int full = total & ~7;
-  const int b = blockIdx.x;
-  const int item = b < full ? (b & 7) * (full >> 3) + (b >> 3) : b;
+  const int bid = blockIdx.x;
+  const int item = bid < full ? (bid & 7) * (full >> 3) + (bid >> 3) : bid;
   const int tm = item / tiles_n, tn = item % tiles_n;
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
-  const int64_t row0 = (int64_t)tm * 64 + wave * 16;
-  const int64_t col0 = (int64_t)tn * 16 * kSlTiles;
+  const int64_t row0 = (int64_t)tm * kSlRows + wave * 16;
+  const int64_t col0 = (int64_t)tn * kSlCols;
   const int64_t arow = row0 + r;
   const bool arow_ok = arow < M;
   const int64_t pa = M * Kp, px = N * Kp;
-  const int8_t* abase = AS + (arow_ok ? arow : 0) * Kp + 8 * g;
-  const int8_t* xbase[kSlTiles];
-  bool xok[kSlTiles];
+  const int8_t* abase = AS + (arow_ok ? arow : 0) * Kp + 16 * g;
+  // this thread's staging copy: column tid / 8, K bytes 16 (tid mod 8), every slice
+  const int ccol = threadIdx.x >> 3, ck = 16 * (threadIdx.x & 7);
+  const bool ccol_ok = col0 + ccol < N;
+  const int8_t* cbase = XS + (ccol_ok ? col0 + ccol : 0) * Kp + ck;
+  // staging copies in two groups of slices (0..3 during the first block of
+  // 64 values of K, 4..6 during the second), stored after their block
+  constexpr int kHalf = (kSlices + 1) / 2;
+  v4i32 cregs[kHalf];
+  auto stage_load = [&](int64_t kb, int t0, int t1) {
 #pragma unroll
-  for (int ct = 0; ct < kSlTiles; ct++) {
-    const int64_t col = col0 + 16 * ct + r;
-    xok[ct] = col < N;
-    xbase[ct] = XS + (xok[ct] ? col : 0) * Kp + 8 * g;
-  }
+    for (int t = 0; t < kHalf; t++)
+      if (t0 + t < t1)
+        cregs[t] = ccol_ok ? *reinterpret_cast<const v4i32*>(cbase + (t0 + t) * px + kb)
+                           : v4i32{0, 0, 0, 0};
+  };
+  auto stage_store = [&](int buf, int t0, int t1) {
+#pragma unroll
+    for (int t = 0; t < kHalf; t++)
+      if (t0 + t < t1)
+        *reinterpret_cast<v4i32*>(&bst[buf][(t0 + t) * kSlSliceB + ccol * kSlRowB + ck]) = cregs[t];
+  };
+
   v4i acc[kSlices][kSlTiles];
-  d4 out[kSlTiles];
 #pragma unroll
-  for (int ct = 0; ct < kSlTiles; ct++) {
-    out[ct] = d4{0.0, 0.0, 0.0, 0.0};
+  for (int ct = 0; ct < kSlTiles; ct++)
 #pragma unroll
     for (int d = 0; d < kSlices; d++) acc[d][ct] = v4i{0, 0, 0, 0};
-  }
+  // a chunk's sums, smallest weights first, scaled by 2^(e_i + f_j) (exact)
+  // and added to C (the first chunk stores)
+  bool first = true;
   auto flush = [&]() {
 #pragma unroll
     for (int ct = 0; ct < kSlTiles; ct++) {
-      // smallest weights first
+      const int64_t col = col0 + 16 * ct + r;
+      const int fcol = col < N ? fx[col] : 0;
 #pragma unroll
-      for (int d = kSlices - 1; d >= 0; d--) {
+      for (int i = 0; i < 4; i++) {
+        double v = 0.0;
 #pragma unroll
-        for (int i = 0; i < 4; i++)
-          out[ct][i] += __builtin_amdgcn_ldexp((double)acc[d][ct][i], -7 * (d + 2));
-        acc[d][ct] = v4i{0, 0, 0, 0};
+        for (int d = kSlices - 1; d >= 0; d--)
+          v += __builtin_amdgcn_ldexp((double)acc[d][ct][i], -7 * (d + 2));
+        const int64_t row = row0 + 4 * g + i;
+        if (row < M && col < N) {
+          const double o = __builtin_amdgcn_ldexp(v, ea[row] + fcol);
+          double* dst = C + row * ldc + col;
+          *dst = first ? o : *dst + o;
+        }
       }
+#pragma unroll
+      for (int d = 0; d < kSlices; d++) acc[d][ct] = v4i{0, 0, 0, 0};
     }
+    first = false;
   };
+
+  const int nst = (int)(Kp / kSlStage);
+  stage_load(0, 0, kHalf);
+  stage_store(0, 0, kHalf);
+  stage_load(0, kHalf, kSlices);
+  stage_store(0, kHalf, kSlices);
+  __syncthreads();
   int in_chunk = 0;
-  for (int64_t k0 = 0; k0 < Kp; k0 += kSliceKStep) {
-    long a[kSlices];
+  for (int st = 0; st < nst; st++) {
+    const int buf = st & 1;
+    const bool more = st + 1 < nst;
+    const int64_t knext = (int64_t)(st + 1) * kSlStage;
 #pragma unroll
-    for (int s = 0; s < kSlices; s++)
-      a[s] = arow_ok ? *reinterpret_cast<const long*>(abase + s * pa + k0) : 0l;
+    for (int seg = 0; seg < kSlStage / 64; seg++) {
+      if (more) stage_load(knext, seg == 0 ? 0 : kHalf, seg == 0 ? kHalf : kSlices);
+      const int64_t k = (int64_t)st * kSlStage + seg * 64;
+      v4i32 a[kSlices];
 #pragma unroll
-    for (int t = 0; t < kSlices; t++) {
+      for (int s2 = 0; s2 < kSlices; s2++)
+        a[s2] = arow_ok ? *reinterpret_cast<const v4i32*>(abase + s2 * pa + k) : v4i32{0, 0, 0, 0};
 #pragma unroll
-      for (int ct = 0; ct < kSlTiles; ct++) {
-        const long bv = xok[ct] ? *reinterpret_cast<const long*>(xbase[ct] + t * px + k0) : 0l;
+      for (int t = 0; t < kSlices; t++) {
 #pragma unroll
-        for (int s = 0; s + t < kSlices; s++) acc[s + t][ct] = mfma_i8_16x16x32(a[s], bv, acc[s + t][ct]);
+        for (int ct = 0; ct < kSlTiles; ct++) {
+          const v4i32 bv = *reinterpret_cast<const v4i32*>(
+              &bst[buf][t * kSlSliceB + (16 * ct + r) * kSlRowB + seg * 64 + 16 * g]);
+#pragma unroll
+          for (int s2 = 0; s2 + t < kSlices; s2++)
+            acc[s2 + t][ct] = mfma_i8_16x16x64(a[s2], bv, acc[s2 + t][ct]);
+        }
       }
+      if (more) stage_store(buf ^ 1, seg == 0 ? 0 : kHalf, seg == 0 ? kHalf : kSlices);
     }
-    in_chunk += kSliceKStep;
+    __syncthreads();
+    in_chunk += kSlStage;
     if (in_chunk >= kSliceChunk) {
       flush();
       in_chunk = 0;
     }
   }
-  flush();
-#pragma unroll
-  for (int ct = 0; ct < kSlTiles; ct++) {
-    const int64_t col = col0 + 16 * ct + r;
-    if (col >= N) continue;
-    const int fcol = fx[col];
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-      const int64_t row = row0 + 4 * g + i;
-      if (row < M) C[row * ldc + col] = __builtin_amdgcn_ldexp(out[ct][i], ea[row] + fcol);
-    }
-  }
+  if (in_chunk > 0 || first) flush();
 }
 
 struct SlicedLayout {
@@ -197,7 +267,7 @@ struct SlicedLayout {
 SlicedLayout sliced_layout(int64_t M, int64_t N, int64_t K) {
   auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
   SlicedLayout L;
-  L.Kp = (K + kSliceKStep - 1) / kSliceKStep * kSliceKStep;
+  L.Kp = (K + kSlStage - 1) / kSlStage * kSlStage;
   size_t at = 0;
   L.as = at;
   at += up((size_t)kSlices * M * L.Kp);
@@ -240,10 +310,11 @@ rsvd_status sliced_gemm(int64_t M, int64_t N, int64_t K, const double* X, int64_
   hipLaunchKernelGGL(slice_cols_kernel, dim3((unsigned)N), dim3(256), 0, s, K, N, L.Kp, X, ldx,
                      reinterpret_cast<int8_t*>(w + L.xs), reinterpret_cast<int*>(w + L.fx));
   RSVD_LAUNCH_CHECK();
-  const int tiles_m = (int)((M + 63) / 64);
-  const int tiles_n = (int)((N + 16 * kSlTiles - 1) / (16 * kSlTiles));
+  const int tiles_m = (int)((M + kSlRows - 1) / kSlRows);
+  const int tiles_n = (int)((N + kSlCols - 1) / kSlCols);
   const int total = tiles_m * tiles_n;
-  hipLaunchKernelGGL(sliced_gemm_kernel, dim3((unsigned)total), dim3(256), 0, s, M, N, L.Kp,
+  hipLaunchKernelGGL(sliced_gemm_kernel, dim3((unsigned)total), dim3(64 * kSlWaves), 0, s, M, N,
+                     L.Kp,
                      reinterpret_cast<const int8_t*>(w + L.as),
                      reinterpret_cast<const int*>(w + L.ea),
                      reinterpret_cast<const int8_t*>(w + L.xs),
