@@ -172,15 +172,45 @@ __device__ __forceinline__ void store_tile(const TileCtx& cx, double* W, int I, 
   }
 }
 
+__device__ __forceinline__ double bcast_lane(double v, int src) {
+  const long long bits = __double_as_longlong(v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(bits >> 32), src);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)bits, src);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// Pivot of one Cholesky step: clamped (pivots at most clampv raised to it,
+// when clamping), replaced by 1 with ok cleared when non-positive or
+// non-finite; inv = 1 / sqrt(piv), rjj = sqrt(piv).
+__device__ __forceinline__ void chol_pivot(double piv, bool clamp, double clampv, bool& ok,
+                                           double& inv, double& rjj) {
+  if (clamp && !(piv > clampv)) piv = clampv;
+  if (!(piv > 0.0) || !isfinite(piv)) {
+    ok = false;
+    piv = 1.0;
+  }
+  if (piv >= 1e-290) {
+    inv = rsq_nr(piv);
+    rjj = piv * inv;
+  } else {
+    rjj = sqrt(piv);
+    inv = 1.0 / rjj;
+  }
+}
+
 // Upper Cholesky of one tile held by a wave together with Z = R^{-T} (lower,
 // same layout): the row operations of the factorization (row j scaled by
 // 1 / r_jj, then row i > j less r_ji times row j) are L^{-1} for G = L L^T,
 // L = R^T, so applied to the identity beside G they leave L^{-1} = R^{-T}.
 // Row j of Z is final after step j, so the inverse costs a few more FMAs per
-// step instead of a second 16-step substitution. The pivot is read from its
-// lane into scalar registers; row j of R and Z goes through the wave's own
-// 32 doubles of LDS (rowbuf), which every lane then reads by broadcast
-// (LDS operations of one wave complete in order, so no barrier is needed).
+// step instead of a second 16-step substitution. Row j of R and Z goes
+// through the wave's own 32 doubles of LDS (rowbuf), which every lane then
+// reads by broadcast (LDS operations of one wave complete in order, so no
+// barrier is needed). The next pivot, (j+1, j+1) less the square of the
+// scaled (j, j+1), is formed from two lanes' values read into scalar
+// registers and its inverse square root taken while row j is in flight
+// through LDS; it is the same FMA on the same operands that the row update
+// applies to that entry, so the result does not depend on this order.
 // Returns false on a non-positive or non-finite pivot (unless clamping:
 // pivots at most clampv are raised to it); tracks the range of the diagonal
 // of R over rows below lmax.
@@ -194,33 +224,22 @@ __device__ bool tile_chol_inv(d4& t, d4& z, double* rowbuf, bool clamp, double c
   bool ok = true;
 #pragma unroll
   for (int it = 0; it < 4; it++) z[it] = (g + 4 * it == r) ? 1.0 : 0.0;
+  // entry (i, c) is item i / 4 of lane c + 16 (i % 4)
+  double inv, rjj;
+  chol_pivot(bcast_lane(t[0], 0), clamp, clampv, ok, inv, rjj);
 #pragma unroll
   for (int j = 0; j < 16; j++) {
     const int jg = j & 3, jt = j >> 2;
-    // entry (j, j): item jt of lane j + 16 jg
-    const int src = j + 16 * jg;
-    const double tv = t[jt];
-    const uint64_t bits = ((uint64_t)(uint32_t)__builtin_amdgcn_readlane(
-                               (int)(__double_as_longlong(tv) >> 32), src)
-                           << 32) |
-                          (uint32_t)__builtin_amdgcn_readlane((int)__double_as_longlong(tv), src);
-    double piv = __longlong_as_double((long long)bits);
-    if (clamp && !(piv > clampv)) piv = clampv;
-    if (!(piv > 0.0) || !isfinite(piv)) {
-      ok = false;
-      piv = 1.0;
-    }
-    double inv, rjj;
-    if (piv >= 1e-290) {
-      inv = rsq_nr(piv);
-      rjj = piv * inv;
-    } else {
-      rjj = sqrt(piv);
-      inv = 1.0 / rjj;
-    }
     if (row0 + j < lmax) {
       dmax = fmax(dmax, rjj);
       dmin = fmin(dmin, rjj);
+    }
+    // (j, j+1) and (j+1, j+1) before this step's update
+    double a = 0.0, b = 0.0;
+    if (j < 15) {
+      const int j1 = j + 1;
+      a = bcast_lane(t[jt], j1 + 16 * jg);
+      b = bcast_lane(t[j1 >> 2], j1 + 16 * (j1 & 3));
     }
     if (g == jg) {
       if (r > j) t[jt] *= inv;
@@ -230,12 +249,16 @@ __device__ bool tile_chol_inv(d4& t, d4& z, double* rowbuf, bool clamp, double c
       rowbuf[16 + r] = z[jt];  // z_j,r
     }
     __builtin_amdgcn_wave_barrier();
-    // all six reads in flight together, then a branch-free update
     const double colv = rowbuf[r];
     const double colz = rowbuf[16 + r];
     double rowv[4];
 #pragma unroll
     for (int it = 0; it < 4; it++) rowv[it] = rowbuf[g + 4 * it];  // r_j,i
+    double inv_n = 1.0, rjj_n = 1.0;
+    if (j < 15) {
+      const double as = a * inv;
+      chol_pivot(fma(-as, as, b), clamp, clampv, ok, inv_n, rjj_n);
+    }
 #pragma unroll
     for (int it = 0; it < 4; it++) {
       const int i = g + 4 * it;
@@ -245,6 +268,8 @@ __device__ bool tile_chol_inv(d4& t, d4& z, double* rowbuf, bool clamp, double c
       z[it] = i > j ? zn : z[it];
     }
     __builtin_amdgcn_wave_barrier();
+    inv = inv_n;
+    rjj = rjj_n;
   }
 #pragma unroll
   for (int it = 0; it < 4; it++) {
