@@ -567,7 +567,9 @@ rsvd_status rsvd_small_svd(int64_t l, const double* R, double* s, double* Us, do
  * once (arguments exactly as rsvd_run) while each launch records itself,
  * replays every recorded key not yet in the table once per candidate tiling
  * (FP64 kernel: 4 or 8 waves per workgroup x K-split counts whose partial
- * sums fit the plan's workspace; residual pass: 4 or 8 waves; BF16 plane
+ * sums fit the plan's workspace; residual pass: U diag(s) held in
+ * registers (inner size at most 272) or the streaming kernel with 4 or 8
+ * waves and narrower column tiles; BF16 plane
  * kernel: 16 or 32 rows per wave x one or two times the fewest column
  * groups x K-split counts), timed with HIP events over `reps` (1..100)
  * launches after one warm-up, keeps the fastest, and runs the
@@ -587,8 +589,9 @@ rsvd_status rsvd_small_svd(int64_t l, const double* R, double* s, double* Us, do
  * rsvd_tune_entries copies up to `max` entries of the table (kind[i] =
  * 100 kind + 10 arithmetic + transposed; mnk[3i..3i+2] = M, N, K; cfg[3i..]
  * = the tiling: waves / rows per wave, K splits (residual: column tiles per
- * workgroup, 0 for the widest), column groups) into host arrays (each may be
- * NULL) and returns the number of entries;
+ * workgroup, 0 for the widest), column groups (residual: 1 for U diag(s)
+ * held in registers, 0 for the streaming kernel)) into host arrays (each
+ * may be NULL) and returns the number of entries;
  * rsvd_tune_clear empties the table. rsvd_tune_set pins the tiling of one
  * key (kind 0 FP64 streaming, 1 register-staged, 2 residual, 3 BF16 plane
  * product; arith 0 FP64, 1 FP32, 2 BF16, 3 split BF16; a, b, c as in

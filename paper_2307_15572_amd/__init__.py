@@ -656,7 +656,7 @@ def tune_table():
         if k0 == "bf16_planes":
             ent.update(rows_per_wave=16 * a, splits=b, column_groups=c)
         elif k0 == "residual":
-            ent.update(waves=a, column_tiles=b)
+            ent.update(waves=a, column_tiles=b, registers=c)
         elif k0 == "generic":
             ent.update(splits=b)
         else:
@@ -673,7 +673,7 @@ def tune_clear():
 def tune_set(kind, M, N, K, arith=0, trans=0, **tiling):
     """Pin the tiling of one product key. kind: "fp64_stream", "generic",
     "residual" or "bf16_planes"; tiling keywords as tune_table() reports them
-    (waves, splits, rows_per_wave, column_groups, column_tiles)."""
+    (waves, splits, rows_per_wave, column_groups, column_tiles, registers)."""
     kinds = {v: k for k, v in TUNE_KINDS.items()}
     kd = kinds[kind]
     if kind == "bf16_planes":
@@ -681,7 +681,7 @@ def tune_set(kind, M, N, K, arith=0, trans=0, **tiling):
     elif kind == "generic":
         a, b, c = 0, tiling["splits"], 0
     elif kind == "residual":
-        a, b, c = tiling["waves"], tiling.get("column_tiles", 0), 0
+        a, b, c = tiling["waves"], tiling.get("column_tiles", 0), tiling.get("registers", 0)
     else:
         a, b, c = tiling["waves"], tiling.get("splits", 1), 0
     _check(lib().rsvd_tune_set(kd, int(arith), int(trans), M, N, K, a, b, c), "rsvd_tune_set")

@@ -659,6 +659,153 @@ hipError_t launch_dma_prec(int prec, int nt, dim3 grid, hipStream_t st, const Ge
   return launch_dma<WM, false, kPrecF64, TA>(nt, grid, st, a);
 }
 
+
+// ---------------------------------------------------------------------------
+// Residual pass with U diag(s) held in registers (K <= 272): the squared
+// Frobenius norms of A - US Vt and of A, both summed over one sweep of A.
+// A workgroup of 8 waves takes 128 rows; each wave keeps its 16 rows of US
+// (16 x K, the MFMA A operand: K / 4 doubles per lane) in registers
+// for the whole sweep over its column range, so US is read once per
+// workgroup; Vt goes through LDS in stages of 16 columns (double-buffered,
+// the next stage's loads in flight while the current one is multiplied) and
+// A is read once, each element by the lane that holds the matching entry of
+// the product. The column range of a workgroup is one of `chunks` slices of
+// N; with 8 slices, consecutive workgroups (which the dispatcher deals to
+// the 8 XCDs in turn) take the 8 slices of one row strip, so every XCD
+// sweeps one slice of Vt for all row strips and its L2 serves the strips
+// that run there together.
+// The K index of MFMA step s, lane group g is KQM g + s: each lane's share
+// of a US row is contiguous. The kernel is instantiated for a few even
+// bounds KQM with 4 KQM >= K and always runs KQM straight-line steps (a
+// branch per step would make the compiler wait for every load in flight
+// before each product); indices from K on hold zeros in registers and in
+// LDS. In LDS, row k of a stage sits at 16 k + 16 (k / KQM) doubles: the
+// 16-double gap between lane groups puts the two groups of a half-wave read
+// on disjoint banks.
+// Partial sums per workgroup: rpart[item] (residual), rpart[total + item]
+// (A), summed by sum_partials_into in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int kRrWaves = 8;
+constexpr int kRrRows = 16 * kRrWaves;
+constexpr int kRrMaxK = 272;
+constexpr int kRrCols = 16;  // columns per stage
+
+template <int KQM>
+__global__ void __launch_bounds__(64 * kRrWaves, 1) resid_reg_kernel(
+    int64_t M, int64_t N, int K, const double* __restrict__ US, int64_t ldus,
+    const double* __restrict__ Vt, int64_t ldvt, const double* __restrict__ A, int64_t lda,
+    int chunks, int64_t chunk_cols, double* __restrict__ rpart) {
+  constexpr int kRowsK = 4 * KQM;                              // staged rows of Vt
+  constexpr int kStage = 16 * kRowsK + 4 * 16;                 // doubles per stage
+  constexpr int kLoads = (16 * kRowsK + 64 * kRrWaves - 1) / (64 * kRrWaves);  // per thread
+  __shared__ double bs[2 * kStage];
+  __shared__ double red[2 * kRrWaves];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  const int item = blockIdx.x;
+  const int total = gridDim.x;
+  const int strip = item / chunks, slice = item % chunks;
+  const int64_t row_w = (int64_t)strip * kRrRows + 16 * wave;  // this wave's first row
+  const int64_t c_begin = (int64_t)slice * chunk_cols;
+  const int64_t c_end = c_begin + chunk_cols < N ? c_begin + chunk_cols : N;
+
+  // Every load below reads a clamped, valid address and its value is scaled
+  // by a 0 / 1 mask where the entry lies outside the operand, and the loop
+  // body has no branches: the loads are issued ahead of the products and
+  // the compiler waits for them only where they are used.
+  // this wave's rows of US: lane (r, g) holds US[row_w + r][KQM g + s]
+  double av[KQM];
+  {
+    const int64_t row = row_w + r;
+    const double* src = US + (row < M ? row : M - 1) * ldus;
+    const double mr = row < M ? 1.0 : 0.0;
+#pragma unroll
+    for (int s = 0; s < KQM; s++) {
+      const int k = KQM * g + s;
+      av[s] = src[k < K ? k : K - 1] * (k < K ? mr : 0.0);
+    }
+  }
+
+  // stage loader: value v of this thread is Vt row k = e / 16, column e % 16,
+  // e = threadIdx.x + 512 v (rows from K on load zeros)
+  double nx[kLoads];
+  auto load_stage = [&](int64_t c0) {
+#pragma unroll
+    for (int v = 0; v < kLoads; v++) {
+      const int e = threadIdx.x + 64 * kRrWaves * v;
+      const int k = e >> 4, c = e & 15;
+      nx[v] = Vt[(int64_t)(k < K ? k : K - 1) * ldvt + (c0 + c < c_end ? c0 + c : c_end - 1)];
+    }
+  };
+  auto store_stage = [&](double* dst, int64_t c0) {
+#pragma unroll
+    for (int v = 0; v < kLoads; v++) {
+      const int e = threadIdx.x + 64 * kRrWaves * v;
+      const int k = e >> 4, c = e & 15;
+      if (e < 16 * kRowsK)
+        dst[16 * k + 16 * (k / KQM) + c] = nx[v] * (k < K && c0 + c < c_end ? 1.0 : 0.0);
+    }
+  };
+
+  double sd = 0.0, sa = 0.0;
+  int buf = 0;
+  if (c_begin < c_end) {
+    load_stage(c_begin);
+    store_stage(bs, c_begin);
+  }
+  __syncthreads();
+  const int rd = 16 * KQM * g + 16 * g + r;  // this lane's B operand, step 0
+  for (int64_t c0 = c_begin; c0 < c_end; c0 += kRrCols) {
+    // the next stage (clamped past the end; its values are then unused)
+    load_stage(c0 + kRrCols);
+    // A at the product's entries: rows row_w + g + 4 it, column c0 + r
+    double ar[4];
+#pragma unroll
+    for (int it = 0; it < 4; it++) {
+      const int64_t row = row_w + g + 4 * it, col = c0 + r;
+      ar[it] = A[(row < M ? row : M - 1) * lda + (col < c_end ? col : c_end - 1)];
+    }
+    // keep these loads ahead of the products (the scheduler would otherwise
+    // sink them to their first use and expose their latency)
+    __builtin_amdgcn_sched_barrier(0);
+    const double* b0 = bs + buf * kStage + rd;
+    // two accumulation chains (even and odd steps) in flight on the matrix core
+    d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < KQM; s += 2) {
+      acc0 = mfma_f64_16x16x4(av[s], b0[16 * s], acc0);
+      acc1 = mfma_f64_16x16x4(av[s + 1], b0[16 * s + 16], acc1);
+    }
+    const d4 acc = acc0 + acc1;
+    const double mc = c0 + r < c_end ? 1.0 : 0.0;
+#pragma unroll
+    for (int it = 0; it < 4; it++) {
+      const double m = (row_w + g + 4 * it < M ? 1.0 : 0.0) * mc;
+      const double dv = (ar[it] - acc[it]) * m, av2 = ar[it] * m;
+      sd += dv * dv;
+      sa += av2 * av2;
+    }
+    store_stage(bs + (buf ^ 1) * kStage, c0 + kRrCols);
+    __syncthreads();
+    buf ^= 1;
+  }
+  sd = wave_sum(sd);
+  sa = wave_sum(sa);
+  if (lane == 0) {
+    red[wave] = sd;
+    red[kRrWaves + wave] = sa;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s0 = 0.0, s1 = 0.0;
+    for (int w = 0; w < kRrWaves; w++) {
+      s0 += red[w];
+      s1 += red[kRrWaves + w];
+    }
+    rpart[item] = s0;
+    rpart[total + item] = s1;
+  }
+}
 }  // namespace
 
 void dgemm_set_dma(bool on, int waves) {
@@ -893,6 +1040,51 @@ size_t resid_partials_dma(int64_t M, int64_t N) {
 rsvd_status resid(int64_t M, int64_t N, int64_t K, const double* US, int64_t ldus,
                   const double* Vt, int64_t ldvt, const double* A, int64_t lda, double* partial,
                   DevState* st, hipStream_t s) {
+  // US in registers (K <= 272): 8 column slices (one per XCD) unless N is
+  // narrow; the tuner's candidate c = 1
+  const int64_t rr_strips = (M + kRrRows - 1) / kRrRows;
+  const int64_t rr_stages = (N + kRrCols - 1) / kRrCols;
+  const int rr_chunks = (int)(rr_stages < 8 ? rr_stages : 8);
+  const int64_t rr_total = rr_strips * rr_chunks;
+  const bool rr_ok = K > 0 && K <= kRrMaxK && K % 16 == 0 && M > 0 && N > 0 &&
+                     (size_t)2 * rr_total <= resid_partials(M, N) && rr_total < (int64_t)1 << 31;
+  const TuneKey rkey{kTuneResid, kPrecF64, 0, M, N, K};
+  TuneCfg rcfg;
+  const bool rtuned = !tune_recording() && tune_get(rkey, &rcfg);
+  // untuned: the register kernel once its grid covers the device twice
+  // (fewer, larger workgroups leave CUs idle)
+  if (rr_ok && (rtuned ? rcfg.c == 1 : (tune_recording() || rr_total >= 512))) {
+    if (tune_recording()) {
+      std::vector<TuneCfg> cands = {{8, 0, 1}, {4, 0, 0}, {8, 0, 0}};
+      const GemmShape sh0 = dgemm_shape(M, N, K, 1);
+      for (int nt : kResNarrow) {
+        if (nt < sh0.nt) {
+          cands.push_back({4, nt, 0});
+          cands.push_back({8, nt, 0});
+        }
+      }
+      tune_record(rkey, cands, [=](hipStream_t s2) {
+        return resid(M, N, K, US, ldus, Vt, ldvt, A, lda, partial, st, s2);
+      });
+    }
+    TuneCfg fc;
+    if (tune_get(rkey, &fc) ? fc.c == 1 : rr_total >= 512) {
+      const int64_t chunk_cols = (rr_stages + rr_chunks - 1) / rr_chunks * kRrCols;
+      // the fewest straight-line steps that cover K / 4
+      const int kq = (int)((K + 3) / 4);
+      auto kern = kq <= 16   ? resid_reg_kernel<16>
+                  : kq <= 32 ? resid_reg_kernel<32>
+                  : kq <= 48 ? resid_reg_kernel<48>
+                  : kq <= 64 ? resid_reg_kernel<64>
+                             : resid_reg_kernel<68>;
+      hipLaunchKernelGGL(kern, dim3((unsigned)rr_total), dim3(64 * kRrWaves), 0, s, M, N, (int)K, US,
+                         ldus, Vt, ldvt, A, lda, rr_chunks, chunk_cols, partial);
+      RSVD_LAUNCH_CHECK();
+      rsvd_status r = sum_partials_into(rr_total, partial, &st->resid2, s);
+      if (r != RSVD_OK) return r;
+      return sum_partials_into(rr_total, partial + rr_total, &st->fro2, s);
+    }
+  }
   GemmShape sh = dgemm_shape(M, N, K, 1);
   const bool dma_ok = (K % kBK == 0) && K > 0 && (N % 2 == 0) && N >= 2 && (ldus % 2 == 0) &&
                       (ldvt % 2 == 0) && ((uintptr_t)US % 16 == 0) && ((uintptr_t)Vt % 16 == 0) &&

@@ -531,7 +531,11 @@ rsvd_status lift_and_finish(const rsvd_plan_s& pl, const Ws& w, const double* A,
     PhaseScope ph(4, s);
     double* US = w.at<double>(pl.off_US);
     double* Vt = w.at<double>(pl.off_Vt);
-    const int64_t kcp = (kcl + 15) / 16 * 16;  // padded with zero columns / rows
+    // inner size: the rank, padded to 16 with zero columns / rows (under the
+    // fixed rule the rank is known here: k within [1, kcl]; otherwise up to kcl)
+    int64_t kres = kcl;
+    if (pl.mode == RSVD_RANK_FIXED) kres = pl.k_fixed < 1 ? 1 : (pl.k_fixed < kcl ? pl.k_fixed : kcl);
+    const int64_t kcp = (kres + 15) / 16 * 16;
     RSVD_TRY(resid_prep(m, n, kcl, kcp, o.U, o.ldu, sig, o.V, o.ldv, US, Vt, st, s));
     RSVD_TRY(resid(m, n, kcp, US, kcp, Vt, n, A, lda, w.at<double>(pl.off_rpart), st, s));
   }

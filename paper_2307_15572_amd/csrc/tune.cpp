@@ -223,7 +223,8 @@ rsvd_status rsvd_tune_set(int32_t kind, int32_t arith, int32_t trans, int64_t M,
   // the launch sites validate a tiling against the call's scratch and fall
   // back to their heuristic when it does not fit; here only the ranges
   if ((kind == kTuneDma && (a != 4 && a != 8)) || (kind == kTuneResid && (a != 4 && a != 8)) ||
-      (kind == kTuneBf16 && (a != 1 && a != 2)) || (kind == kTuneResid && b > 17) || b < 0 ||
+      (kind == kTuneBf16 && (a != 1 && a != 2)) || (kind == kTuneResid && (b > 17 || c > 1)) ||
+      b < 0 ||
       b > 64 || c < 0 || c > 1024)
     return RSVD_EINVAL;
   TuneKey k;

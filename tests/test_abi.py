@@ -257,5 +257,10 @@ def test_tune_set_pins_and_rejects_without_device():
         assert {e["kind"]: e for e in rs.tune_table()}["residual"]["waves"] == 4
         with pytest.raises(rs.RsvdError):
             rs.tune_set("bf16_planes", 10, 10, 10, rows_per_wave=48)
+        # residual: the register-resident kernel is c = 1, nothing beyond
+        rs.tune_set("residual", 1000, 272, 256, waves=8, registers=1)
+        assert {(e["kind"], e["K"]): e for e in rs.tune_table()}[("residual", 256)]["registers"] == 1
+        with pytest.raises(rs.RsvdError):
+            rs.tune_set("residual", 1000, 272, 256, waves=8, registers=2)
     finally:
         rs.tune_clear()

@@ -161,21 +161,22 @@ def test_pinned_bf16_tiling(split, rows, splits, groups):
     assert np.abs(got - base).max() <= (terms + 2) * 2.0 ** -23 * mag.max()
 
 
-@pytest.mark.parametrize("waves,column_tiles", [(8, 0), (4, 0), (4, 8), (8, 8), (4, 4), (8, 6), (4, 12)])
-def test_pinned_residual_tiling(waves, column_tiles):
+@pytest.mark.parametrize("waves,column_tiles,registers", [(8, 0, 1), (8, 0, 0), (4, 0, 0), (4, 8, 0),
+                                                         (8, 8, 0), (4, 4, 0), (8, 6, 0), (4, 12, 0)])
+def test_pinned_residual_tiling(waves, column_tiles, registers):
     # every residual tiling the tuner may choose gives the oracle's residual
     # (the tiling changes only the order of the FP64 sums)
     import paper_2307_15572_amd as rs
     m, n, k, p, q = 3000, 2000, 100, 16, 1
-    announce(f"pinned residual tiling waves={waves} column_tiles={column_tiles}")
+    announce(f"pinned residual tiling waves={waves} column_tiles={column_tiles} registers={registers}")
     sig = synth.spectrum_pow10(n, 1 / 50)
     A = synth.general(m, n, sig, tag=811, noise=1e-9)
     ref = oracle_rsvd(A, k, p, q, seed=811)
     kcp = (k + 15) // 16 * 16  # the residual product's inner size: k padded to 16
-    rs.tune_set("residual", m, n, kcp, waves=waves, column_tiles=column_tiles)
+    rs.tune_set("residual", m, n, kcp, waves=waves, column_tiles=column_tiles, registers=registers)
     out = rs.run(to_dev(A), k, p, q, seed=811)
     assert out.rank == ref.rank
     assert abs(out.residual - ref.residual) <= 1e-10 * ref.residual
     tab = rs.tune_table()
     assert tab == [dict(kind="residual", arith=0, trans=0, M=m, N=n, K=kcp, waves=waves,
-                        column_tiles=column_tiles)]
+                        column_tiles=column_tiles, registers=registers)]
