@@ -156,7 +156,8 @@ def product_roofline(name, flops, avg_s, peak, kernel, launches, **extra):
 
 # ---- the headline matrix: FP64, every precision schedule, symmetric form -----
 
-SCHEDULES = (("mixed_fp32", 1), ("mixed_fp32", 2), ("mixed_fp32_sliced", 1), ("mixed_bf16", 1),
+SCHEDULES = (("mixed_fp32", 0), ("mixed_fp32", 1), ("mixed_fp32", 2), ("mixed_fp32_sliced", 1),
+             ("mixed_bf16", 1),
              ("mixed_bf16", 2), ("mixed_bf16_split", 1), ("mixed_bf16_split", 2))
 SLICE_PRODUCTS = 28  # INT8 slice products of one error-free sliced product (7 slices each side)
 

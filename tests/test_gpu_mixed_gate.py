@@ -90,7 +90,7 @@ def _scaled_c3():
 # 1.1e-7 / 2.1e-2, split t2 7.2e-6 / 3.9e-2: the split representation keeps
 # about 16 bits, so its products miss the gate where the spectrum decays
 # slowly (a documented miss, held to 3e-5)
-C2_CASES = [("mixed_fp32", 1, 1e-6, 1e-6), ("mixed_bf16", 1, 1e-6, 1e-2),
+C2_CASES = [("mixed_fp32", 0, 1e-6, 1e-6), ("mixed_fp32", 1, 1e-6, 1e-6), ("mixed_bf16", 1, 1e-6, 1e-2),
             ("mixed_bf16", 2, 1e-6, 1e-2), ("mixed_bf16_split", 1, 1e-6, 2e-5),
             ("mixed_bf16_split", 2, 1e-6, 2e-5)]
 C3_CASES = [("mixed_fp32", 2, 1e-6, 0.1), ("mixed_bf16", 3, 1e-6, 0.1),
