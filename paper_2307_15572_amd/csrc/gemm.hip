@@ -661,44 +661,49 @@ hipError_t launch_dma_prec(int prec, int nt, dim3 grid, hipStream_t st, const Ge
 
 
 // ---------------------------------------------------------------------------
-// Residual pass with U diag(s) held in registers (K <= 272): the squared
+// Residual pass with U diag(s) held in registers (K <= 288): the squared
 // Frobenius norms of A - US Vt and of A, both summed over one sweep of A.
-// A workgroup of 8 waves takes 128 rows; each wave keeps its 16 rows of US
-// (16 x K, the MFMA A operand: K / 4 doubles per lane) in registers
-// for the whole sweep over its column range, so US is read once per
-// workgroup; Vt goes through LDS in stages of 16 columns (double-buffered,
-// the next stage's loads in flight while the current one is multiplied) and
-// A is read once, each element by the lane that holds the matching entry of
-// the product. The column range of a workgroup is one of `chunks` slices of
-// N; with 8 slices, consecutive workgroups (which the dispatcher deals to
-// the 8 XCDs in turn) take the 8 slices of one row strip, so every XCD
-// sweeps one slice of Vt for all row strips and its L2 serves the strips
-// that run there together.
+// A workgroup of 4 waves takes 64 rows, two workgroups per CU (their
+// barriers are independent, so one's products run while the other waits);
+// each wave keeps its 16 rows of US (16 x K, the MFMA A operand: K / 4
+// doubles per lane) in registers for the whole sweep over its column range,
+// so US is read once per workgroup. Vt goes HBM/L2 -> LDS by
+// global_load_lds_dwordx4 in stages of 16 columns (two stages: the next
+// stage's copies in flight while the current one is multiplied; no staging
+// registers), and A is read once, each element by the lane that holds the
+// matching entry of the product. The column range of a workgroup is one of
+// `chunks` slices of N; with 8 slices, consecutive workgroups (which the
+// dispatcher deals to the 8 XCDs in turn) take the 8 slices of one row
+// strip, so every XCD sweeps one slice of Vt for all row strips and its L2
+// serves the strips that run there together.
 // The K index of MFMA step s, lane group g is KQM g + s: each lane's share
-// of a US row is contiguous. The kernel is instantiated for a few even
-// bounds KQM with 4 KQM >= K and always runs KQM straight-line steps (a
-// branch per step would make the compiler wait for every load in flight
-// before each product); indices from K on hold zeros in registers and in
-// LDS. In LDS, row k of a stage sits at 16 k + 16 (k / KQM) doubles: the
-// 16-double gap between lane groups puts the two groups of a half-wave read
-// on disjoint banks.
+// of a US row is contiguous. The kernel is instantiated for a few bounds
+// KQM (multiples of 8) with 4 KQM >= K and always runs KQM straight-line
+// steps (a branch per step would make the compiler wait for every load in
+// flight before each product); US entries from K on are zero in registers,
+// so the Vt rows they meet in LDS (copies of row K - 1) add nothing. In LDS,
+// row k of a stage sits at 16 k + 16 (k / KQM) doubles: the 16-double gap
+// between lane groups puts the two groups of a half-wave read on disjoint
+// banks, and a 1 KB copy (8 rows) never straddles a gap.
+// Needs N even, ldvt even and Vt 16-byte aligned (16-byte copies).
 // Partial sums per workgroup: rpart[item] (residual), rpart[total + item]
 // (A), summed by sum_partials_into in a fixed order.
 // ---------------------------------------------------------------------------
-constexpr int kRrWaves = 8;
+constexpr int kRrWaves = 4;
 constexpr int kRrRows = 16 * kRrWaves;
-constexpr int kRrMaxK = 272;
+constexpr int kRrMaxK = 288;
 constexpr int kRrCols = 16;  // columns per stage
 
 template <int KQM>
-__global__ void __launch_bounds__(64 * kRrWaves, 1) resid_reg_kernel(
+__global__ void __launch_bounds__(64 * kRrWaves, 2) resid_reg_kernel(
     int64_t M, int64_t N, int K, const double* __restrict__ US, int64_t ldus,
     const double* __restrict__ Vt, int64_t ldvt, const double* __restrict__ A, int64_t lda,
     int chunks, int64_t chunk_cols, double* __restrict__ rpart) {
-  constexpr int kRowsK = 4 * KQM;                              // staged rows of Vt
-  constexpr int kStage = 16 * kRowsK + 4 * 16;                 // doubles per stage
-  constexpr int kLoads = (16 * kRowsK + 64 * kRrWaves - 1) / (64 * kRrWaves);  // per thread
-  __shared__ double bs[2 * kStage];
+  static_assert(KQM % 8 == 0, "a copy of 8 rows stays within one lane group");
+  constexpr int kStage = 16 * 4 * KQM + 4 * 16;  // doubles per stage
+  constexpr int kCopies = 4 * KQM / 8;            // 1 KB copies per stage
+  constexpr int kCopiesW = kCopies / kRrWaves;    // per wave
+  __shared__ __attribute__((aligned(16))) double bs[2 * kStage];
   __shared__ double red[2 * kRrWaves];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
@@ -709,10 +714,10 @@ __global__ void __launch_bounds__(64 * kRrWaves, 1) resid_reg_kernel(
   const int64_t c_begin = (int64_t)slice * chunk_cols;
   const int64_t c_end = c_begin + chunk_cols < N ? c_begin + chunk_cols : N;
 
-  // Every load below reads a clamped, valid address and its value is scaled
+  // Loads below read a clamped, valid address and their values are scaled
   // by a 0 / 1 mask where the entry lies outside the operand, and the loop
-  // body has no branches: the loads are issued ahead of the products and
-  // the compiler waits for them only where they are used.
+  // body has no branches around them: they are issued ahead of the products
+  // and the compiler waits for them only where they are used.
   // this wave's rows of US: lane (r, g) holds US[row_w + r][KQM g + s]
   double av[KQM];
   {
@@ -726,38 +731,35 @@ __global__ void __launch_bounds__(64 * kRrWaves, 1) resid_reg_kernel(
     }
   }
 
-  // stage loader: value v of this thread is Vt row k = e / 16, column e % 16,
-  // e = threadIdx.x + 512 v (rows from K on load zeros)
-  double nx[kLoads];
-  auto load_stage = [&](int64_t c0) {
+  // copy i of this wave: rows 8 q .. 8 q + 7 of the stage (q = wave + 4 i),
+  // lane -> row 8 q + lane / 8 (clamped to K - 1), columns 2 (lane mod 8)
+  // and the next (clamped to N - 2)
+  const double* csrc[kCopiesW];
+  int cdst[kCopiesW];
 #pragma unroll
-    for (int v = 0; v < kLoads; v++) {
-      const int e = threadIdx.x + 64 * kRrWaves * v;
-      const int k = e >> 4, c = e & 15;
-      nx[v] = Vt[(int64_t)(k < K ? k : K - 1) * ldvt + (c0 + c < c_end ? c0 + c : c_end - 1)];
-    }
-  };
-  auto store_stage = [&](double* dst, int64_t c0) {
+  for (int i = 0; i < kCopiesW; i++) {
+    const int q = wave + kRrWaves * i;
+    const int k = 8 * q + (lane >> 3);
+    csrc[i] = Vt + (int64_t)(k < K ? k : K - 1) * ldvt + 2 * (lane & 7);
+    cdst[i] = 16 * (8 * q) + 16 * ((8 * q) / KQM);
+  }
+  auto issue = [&](int64_t c0, int b) {
+    const int64_t cc = c0 + 16 <= N ? c0 : N - 16;  // the last stage may be ragged
 #pragma unroll
-    for (int v = 0; v < kLoads; v++) {
-      const int e = threadIdx.x + 64 * kRrWaves * v;
-      const int k = e >> 4, c = e & 15;
-      if (e < 16 * kRowsK)
-        dst[16 * k + 16 * (k / KQM) + c] = nx[v] * (k < K && c0 + c < c_end ? 1.0 : 0.0);
-    }
+    for (int i = 0; i < kCopiesW; i++) copy_to_lds16(csrc[i] + cc, bs + b * kStage + cdst[i]);
   };
 
   double sd = 0.0, sa = 0.0;
   int buf = 0;
-  if (c_begin < c_end) {
-    load_stage(c_begin);
-    store_stage(bs, c_begin);
-  }
-  __syncthreads();
+  if (c_begin < c_end) issue(c_begin, 0);
   const int rd = 16 * KQM * g + 16 * g + r;  // this lane's B operand, step 0
   for (int64_t c0 = c_begin; c0 < c_end; c0 += kRrCols) {
-    // the next stage (clamped past the end; its values are then unused)
-    load_stage(c0 + kRrCols);
+    // this stage's copies landed (this wave's, then everyone's)
+    wait_vmcnt<0>();
+    __syncthreads();
+    asm volatile("" ::: "memory");
+    // the next stage's copies into the other buffer, released by the barrier
+    if (c0 + kRrCols < c_end) issue(c0 + kRrCols, buf ^ 1);
     // A at the product's entries: rows row_w + g + 4 it, column c0 + r
     double ar[4];
 #pragma unroll
@@ -765,16 +767,32 @@ __global__ void __launch_bounds__(64 * kRrWaves, 1) resid_reg_kernel(
       const int64_t row = row_w + g + 4 * it, col = c0 + r;
       ar[it] = A[(row < M ? row : M - 1) * lda + (col < c_end ? col : c_end - 1)];
     }
-    // keep these loads ahead of the products (the scheduler would otherwise
-    // sink them to their first use and expose their latency)
-    __builtin_amdgcn_sched_barrier(0);
-    const double* b0 = bs + buf * kStage + rd;
-    // two accumulation chains (even and odd steps) in flight on the matrix core
+    // the stage starts at column c0, or earlier when the last one was
+    // shifted back to stay inside the rows of Vt: column c0 + r then sits
+    // at position r + shift (lanes past N read any position: masked below)
+    const int shift = (int)(c0 + 16 <= N ? 0 : c0 - (N - 16));
+    const double* b0 = bs + buf * kStage + rd + (r + shift < 16 ? shift : 0);
+    // two accumulation chains (even and odd steps) in flight on the matrix
+    // core; the LDS reads run kPF steps ahead of the products that use them
+    // (left to itself the scheduler issues each read just before its
+    // products and waits for it). Scheduling-group masks: 0x100 LDS reads,
+    // 0x008 matrix ops.
+    double bv[KQM];
+#pragma unroll
+    for (int s = 0; s < KQM; s++) bv[s] = b0[16 * s];
     d4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int s = 0; s < KQM; s += 2) {
-      acc0 = mfma_f64_16x16x4(av[s], b0[16 * s], acc0);
-      acc1 = mfma_f64_16x16x4(av[s + 1], b0[16 * s + 16], acc1);
+      acc0 = mfma_f64_16x16x4(av[s], bv[s], acc0);
+      acc1 = mfma_f64_16x16x4(av[s + 1], bv[s + 1], acc1);
+    }
+    constexpr int kPF = 4;
+#pragma unroll
+    for (int u = 0; u < kPF; u++) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+#pragma unroll
+    for (int u = 0; u < KQM / 2; u++) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+      if (u + kPF < KQM / 2) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
     }
     const d4 acc = acc0 + acc1;
     const double mc = c0 + r < c_end ? 1.0 : 0.0;
@@ -785,10 +803,9 @@ __global__ void __launch_bounds__(64 * kRrWaves, 1) resid_reg_kernel(
       sd += dv * dv;
       sa += av2 * av2;
     }
-    store_stage(bs + (buf ^ 1) * kStage, c0 + kRrCols);
-    __syncthreads();
     buf ^= 1;
   }
+  wait_vmcnt<0>();
   sd = wave_sum(sd);
   sa = wave_sum(sa);
   if (lane == 0) {
@@ -1040,13 +1057,14 @@ size_t resid_partials_dma(int64_t M, int64_t N) {
 rsvd_status resid(int64_t M, int64_t N, int64_t K, const double* US, int64_t ldus,
                   const double* Vt, int64_t ldvt, const double* A, int64_t lda, double* partial,
                   DevState* st, hipStream_t s) {
-  // US in registers (K <= 272): 8 column slices (one per XCD) unless N is
+  // US in registers (K <= 288): 8 column slices (one per XCD) unless N is
   // narrow; the tuner's candidate c = 1
   const int64_t rr_strips = (M + kRrRows - 1) / kRrRows;
   const int64_t rr_stages = (N + kRrCols - 1) / kRrCols;
   const int rr_chunks = (int)(rr_stages < 8 ? rr_stages : 8);
   const int64_t rr_total = rr_strips * rr_chunks;
-  const bool rr_ok = K > 0 && K <= kRrMaxK && K % 16 == 0 && M > 0 && N > 0 &&
+  const bool rr_ok = K > 0 && K <= kRrMaxK && K % 16 == 0 && M > 0 && N >= 16 && N % 2 == 0 &&
+                     ldvt % 2 == 0 && ((uintptr_t)Vt & 15) == 0 &&
                      (size_t)2 * rr_total <= resid_partials(M, N) && rr_total < (int64_t)1 << 31;
   const TuneKey rkey{kTuneResid, kPrecF64, 0, M, N, K};
   TuneCfg rcfg;
@@ -1071,12 +1089,12 @@ rsvd_status resid(int64_t M, int64_t N, int64_t K, const double* US, int64_t ldu
     if (tune_get(rkey, &fc) ? fc.c == 1 : rr_total >= 512) {
       const int64_t chunk_cols = (rr_stages + rr_chunks - 1) / rr_chunks * kRrCols;
       // the fewest straight-line steps that cover K / 4
-      const int kq = (int)((K + 3) / 4);
+      const int kq = (int)(K / 4);
       auto kern = kq <= 16   ? resid_reg_kernel<16>
                   : kq <= 32 ? resid_reg_kernel<32>
                   : kq <= 48 ? resid_reg_kernel<48>
                   : kq <= 64 ? resid_reg_kernel<64>
-                             : resid_reg_kernel<68>;
+                             : resid_reg_kernel<72>;
       hipLaunchKernelGGL(kern, dim3((unsigned)rr_total), dim3(64 * kRrWaves), 0, s, M, N, (int)K, US,
                          ldus, Vt, ldvt, A, lda, rr_chunks, chunk_cols, partial);
       RSVD_LAUNCH_CHECK();
