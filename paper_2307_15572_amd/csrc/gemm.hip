@@ -1046,7 +1046,11 @@ size_t resid_partials(int64_t M, int64_t N) {
   // every DMA candidate: 4 or 8 waves, the default or the narrow column tile
   const int64_t ntiles = (N + 15) / 16;
   const size_t b = (size_t)2 * ((M + 63) / 64) * ((ntiles + kResNarrowNT - 1) / kResNarrowNT);
-  return a > b ? a : b;
+  // the register-resident kernel: row strips x column slices
+  const int64_t stages = (N + kRrCols - 1) / kRrCols;
+  const size_t c = (size_t)2 * ((M + kRrRows - 1) / kRrRows) * (stages < 8 ? stages : 8);
+  const size_t ab = a > b ? a : b;
+  return ab > c ? ab : c;
 }
 
 size_t resid_partials_dma(int64_t M, int64_t N) {

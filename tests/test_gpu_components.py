@@ -330,3 +330,25 @@ def test_residual_pass_matches_numpy(m, n, k):
     out = rs.residual(to_dev(A), to_dev(S), to_dev(U), to_dev(V), k)
     ref = np.linalg.norm(A - (U * S) @ V.T) / np.linalg.norm(A)
     assert abs(out.residual - ref) <= 1e-9 * ref
+
+
+@pytest.mark.parametrize("m,n,k", [(700, 1002, 190), (130, 18, 16), (1000, 4098, 272), (65, 2000, 64)])
+def test_residual_register_kernel_ragged(m, n, k):
+    # the register-resident residual kernel pinned on shapes it would not
+    # take by default: a ragged last 16-column stage (n even, not a multiple
+    # of 16), row strips past m, inner sizes of every instance
+    import paper_2307_15572_amd as rs
+    announce(f"residual register kernel m={m} n={n} k={k}")
+    rng = np.random.default_rng(m + 3 * n + 5 * k)
+    U = np.linalg.qr(rng.standard_normal((m, k)))[0]
+    V = np.linalg.qr(rng.standard_normal((n, k)))[0]
+    S = np.sort(rng.uniform(0.5, 2.0, k))[::-1].copy()
+    A = (U * S) @ V.T + 1e-3 * rng.standard_normal((m, n))
+    kcp = (k + 15) // 16 * 16
+    try:
+        rs.tune_set("residual", m, n, kcp, waves=8, registers=1)
+        out = rs.residual(to_dev(A), to_dev(S), to_dev(U), to_dev(V), k)
+    finally:
+        rs.tune_clear()
+    ref = np.linalg.norm(A - (U * S) @ V.T) / np.linalg.norm(A)
+    assert abs(out.residual - ref) <= 1e-9 * ref
