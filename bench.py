@@ -58,8 +58,8 @@ GATE = 1e-6
 # FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0, what the counters read for a
 # plain 1 GiB copy kernel. Valid only for the GEMM source they were taken
 # with; any other source reports traffic as null.
-TRAFFIC_SOURCE_SHA256 = "cf5b069e7417aba3"
-TRAFFIC_KIB = {"fp64": (1133677.5, 69632.0), "fp32": (1108225.3, 69632.0)}
+TRAFFIC_SOURCE_SHA256 = "d67245b8c367ebaa"
+TRAFFIC_KIB = {"fp64": (1134137.9, 69632.0), "fp32": (1108181.9, 69632.0)}
 
 
 def product_traffic(kind):
