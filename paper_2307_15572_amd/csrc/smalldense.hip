@@ -426,6 +426,39 @@ __global__ void __launch_bounds__(64 * kCholRegWaves) chol_reg_kernel(
   if (only_if_shifted && st->qr_shifted == 0) return;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
+  if (pass > 0) {
+    // a re-orthogonalization pass whose Gram is within eps = 2^-33 of the
+    // identity (G = I + E, |E_ij| <= eps): R = I + X with X the strict upper
+    // triangle of E plus half its diagonal, and R^-1 = I - X, both to first
+    // order; the neglected terms (X^T X, X^2) are at most l eps^2 <= 4e-18
+    // for l <= 272, below the rounding of the exact factorization. Only the
+    // diagonal tiles of R^-1 are formed, as below.
+    double e = 0.0;
+    for (int i = wave; i < l; i += kCholRegWaves)
+      for (int c = lane; c < l; c += 64)
+        e = fmax(e, fabs(G[(int64_t)i * l + c] - (i == c ? 1.0 : 0.0)));
+    e = wave_max(e);
+    if (lane == 0) red[wave] = e;
+    __syncthreads();
+    double emax = 0.0;
+#pragma unroll
+    for (int w = 0; w < kCholRegWaves; w++) emax = fmax(emax, red[w]);
+    if (emax <= 0x1p-33) {
+      for (int i = wave; i < l; i += kCholRegWaves) {
+        for (int c = lane; c < l; c += 64) {
+          const int64_t x = (int64_t)i * l + c;
+          const double v = G[x];
+          R[x] = i < c ? v : (i == c ? 0.5 * (1.0 + v) : 0.0);
+          if (i / 16 == c / 16)
+            Rinv[x] = i < c ? -v : (i == c ? 0.5 * (3.0 - v) : 0.0);
+          else if (i > c)
+            Rinv[x] = 0.0;
+        }
+      }
+      return;
+    }
+    __syncthreads();  // red is reused by the trace sum below
+  }
   TileCtx cx;
   cx.l = l;
   cx.nb = (l + 15) / 16;
