@@ -86,6 +86,27 @@ def test_orth_matches_oracle(m, l, decay):
     assert np.abs(Q - Qref).max() <= 1e3 * kappa * U_EPS + 1e-12
 
 
+@pytest.mark.parametrize("m,l,scale", [(4000, 272, 1.0), (3000, 130, 1e-3), (2000, 17, 1.0)])
+def test_orth_of_orthonormal_panel(m, l, scale):
+    # a panel with orthonormal columns times a diagonal close to one: the
+    # second Cholesky pass sees a Gram within 2^-33 of the identity and takes
+    # the first-order factor; Q, X must still meet the same bounds
+    import paper_2307_15572_amd as rs
+    announce(f"orth of a near-orthonormal panel m={m} l={l} scale={scale}")
+    rng = np.random.default_rng(m + 7 * l)
+    U = synth.haar_columns(m, l, rng)
+    d = 1.0 + 1e-3 * rng.uniform(-1.0, 1.0, l)
+    Y = scale * U * d
+    Q, X, flags = rs.orth(to_dev(Y))
+    Q = Q.cpu().numpy()
+    X = X.cpu().numpy()
+    assert np.abs(Q.T @ Q - np.eye(l)).max() <= 20 * l * U_EPS
+    assert np.abs(Q @ X - Y).max() <= 50 * l * U_EPS * np.abs(Y).max()
+    assert np.all(np.diag(X) > 0) and np.allclose(np.tril(X, -1), 0)
+    # Q is unique (diag(X) > 0): the oracle's Householder Q
+    assert np.abs(Q - oracle_orth(Y)).max() <= 1e-12
+
+
 def test_orth_numerically_rank_deficient():
     # rank-6 product: the shifted three-pass Cholesky QR still returns an
     # orthonormal Q whose span contains the panel (noise directions complete it)
