@@ -227,6 +227,7 @@ struct DevState {
   uint32_t chol_fail;    // multi-workgroup Cholesky: a pivot broke down
   uint32_t prefer_shift; // the last Cholesky QR of this run needed the shift
   double piv_max, piv_min;  // and the range of its pivots
+  double gram_dev;       // max |G - I| of a re-orthogonalization pass's Gram (grid path)
   GridBar bar;           // grid barrier of the multi-workgroup kernels
 };
 

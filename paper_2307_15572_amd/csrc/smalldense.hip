@@ -406,6 +406,62 @@ __device__ bool tiled_inverse(const Team& tm, const TileCtx& cx, const double* W
 // triangular solve of the QR uses); the strictly lower tiles of R and Rinv
 // are cleared. Pivot checks, shift and retries as in chol_grid_kernel.
 // ---------------------------------------------------------------------------
+// max(e, d) for d >= 0 that turns a NaN d into infinity (fmax would drop it)
+__device__ __forceinline__ double dev_max(double e, double d) {
+  return d <= e ? e : (d == d ? d : INFINITY);
+}
+
+// First-order factor of a near-identity Gram on the grid path (the same
+// rule as in chol_reg_kernel): st->gram_dev is cleared (or set to infinity
+// when the pass is skipped), raised to max |G - I| by every workgroup, and
+// read by the writer and by chol_grid_kernel, which returns at once when the
+// first-order factor stands.
+constexpr double kNearIdentity = 0x1p-33;
+
+__global__ void gram_dev_clear_kernel(int only_if_shifted, DevState* st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0)
+    st->gram_dev = (only_if_shifted && st->qr_shifted == 0) ? INFINITY : 0.0;
+}
+
+__global__ void __launch_bounds__(256) gram_dev_kernel(int l, const double* __restrict__ G,
+                                                       DevState* st) {
+  __shared__ double red[4];
+  if (st->gram_dev == INFINITY) return;
+  const int64_t tot = (int64_t)l * l;
+  double e = 0.0;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < tot;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = x / l, c = x - i * l;
+    e = dev_max(e, fabs(G[x] - (i == c ? 1.0 : 0.0)));
+  }
+  e = wave_max(e);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = e;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    e = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    // non-negative doubles order as their bit patterns
+    atomicMax(reinterpret_cast<unsigned long long*>(&st->gram_dev),
+              (unsigned long long)__double_as_longlong(e));
+  }
+}
+
+// R = I + X and R^-1 = I - X (the full upper triangle) when the Gram is
+// within kNearIdentity of the identity; nothing otherwise
+__global__ void __launch_bounds__(256) gram_first_order_kernel(int l, const double* __restrict__ G,
+                                                               double* __restrict__ R,
+                                                               double* __restrict__ Rinv,
+                                                               const DevState* st) {
+  if (!(st->gram_dev <= kNearIdentity)) return;
+  const int64_t tot = (int64_t)l * l;
+  for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < tot;
+       x += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = x / l, c = x - i * l;
+    const double v = G[x];
+    R[x] = i < c ? v : (i == c ? 0.5 * (1.0 + v) : 0.0);
+    Rinv[x] = i < c ? -v : (i == c ? 0.5 * (3.0 - v) : 0.0);
+  }
+}
+
 constexpr int kCholRegMaxNB = 17;
 constexpr int kCholRegWaves = 8;
 constexpr int kCholRegSlots =
@@ -436,14 +492,14 @@ __global__ void __launch_bounds__(64 * kCholRegWaves) chol_reg_kernel(
     double e = 0.0;
     for (int i = wave; i < l; i += kCholRegWaves)
       for (int c = lane; c < l; c += 64)
-        e = fmax(e, fabs(G[(int64_t)i * l + c] - (i == c ? 1.0 : 0.0)));
+        e = dev_max(e, fabs(G[(int64_t)i * l + c] - (i == c ? 1.0 : 0.0)));
     e = wave_max(e);
     if (lane == 0) red[wave] = e;
     __syncthreads();
     double emax = 0.0;
 #pragma unroll
     for (int w = 0; w < kCholRegWaves; w++) emax = fmax(emax, red[w]);
-    if (emax <= 0x1p-33) {
+    if (emax <= kNearIdentity) {
       for (int i = wave; i < l; i += kCholRegWaves) {
         for (int c = lane; c < l; c += 64) {
           const int64_t x = (int64_t)i * l + c;
@@ -778,6 +834,8 @@ __global__ void __launch_bounds__(256) chol_grid_kernel(int l, double* __restric
   __shared__ double flds[272 + 32];  // the factor wave's transpose tile and row buffer
   __shared__ int s_ok;
   if (only_if_shifted && st->qr_shifted == 0) return;
+  // a re-orthogonalization pass already factored to first order
+  if (pass > 0 && st->gram_dev <= kNearIdentity) return;
   const GridTeam tm{st, &s_ok};
   const int gw = tm.id(), TW = tm.size();
   const int lane = threadIdx.x & 63, r = lane & 15, g = lane >> 4;
@@ -1690,6 +1748,7 @@ __global__ void init_state_kernel(DevState* st, uint32_t flags) {
     st->s1lb2 = 0.0;
     st->froY2 = 0.0;
     st->prefer_shift = 0u;
+    st->gram_dev = INFINITY;
   }
   if (blockIdx.x == 0) {
     if (threadIdx.x < 64) st->rot_count[threadIdx.x] = 0;
@@ -1828,6 +1887,15 @@ rsvd_status chol_inv(int64_t l, double* G, double* R, double* Rinv, double* scra
     if (cap > 64) cap = 64;
     if (grid > cap) grid = cap;
     if (grid < 1) grid = 1;
+    if (pass > 0) {
+      // a Gram within 2^-33 of the identity: the first-order factor instead
+      const unsigned gb = (unsigned)((l * l + 4095) / 4096 < 256 ? (l * l + 4095) / 4096 : 256);
+      hipLaunchKernelGGL(gram_dev_clear_kernel, dim3(1), dim3(64), 0, s, only_if_shifted, st);
+      hipLaunchKernelGGL(gram_dev_kernel, dim3(gb), dim3(256), 0, s, (int)l, (const double*)G, st);
+      hipLaunchKernelGGL(gram_first_order_kernel, dim3(gb), dim3(256), 0, s, (int)l,
+                         (const double*)G, R, Rinv, (const DevState*)st);
+      RSVD_LAUNCH_CHECK();
+    }
     hipLaunchKernelGGL(chol_grid_kernel, dim3(grid), dim3(256), 0, s, (int)l, G, R, Rinv, scratch,
                        m, pass, only_if_shifted, full_inverse ? 1 : 0, st);
     RSVD_LAUNCH_CHECK();

@@ -86,11 +86,13 @@ def test_orth_matches_oracle(m, l, decay):
     assert np.abs(Q - Qref).max() <= 1e3 * kappa * U_EPS + 1e-12
 
 
-@pytest.mark.parametrize("m,l,scale", [(4000, 272, 1.0), (3000, 130, 1e-3), (2000, 17, 1.0)])
+@pytest.mark.parametrize("m,l,scale", [(4000, 272, 1.0), (3000, 130, 1e-3), (2000, 17, 1.0),
+                                         (5000, 400, 1.0), (3000, 609, 1e2)])
 def test_orth_of_orthonormal_panel(m, l, scale):
     # a panel with orthonormal columns times a diagonal close to one: the
     # second Cholesky pass sees a Gram within 2^-33 of the identity and takes
-    # the first-order factor; Q, X must still meet the same bounds
+    # the first-order factor (one workgroup up to l = 272, the predicated
+    # grid path beyond); Q, X must still meet the same bounds
     import paper_2307_15572_amd as rs
     announce(f"orth of a near-orthonormal panel m={m} l={l} scale={scale}")
     rng = np.random.default_rng(m + 7 * l)
